@@ -1,0 +1,413 @@
+/*
+ * gs_oracle.c -- CPU oracle for the per-iteration Gaussian-parameter path of
+ * GS-Scale (arXiv 2509.15645).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the CPU
+ * baseline leg of the benchmark load this library.  It shares no code, header
+ * or table with the HIP library; the two meet only through seeded inputs.
+ *
+ * Build: gcc -O2 -ffp-contract=off -fno-fast-math -fopenmp -fPIC -shared
+ * Every float expression below is evaluated one IEEE binary32 (or binary64)
+ * operation at a time, left to right as parenthesised, with no contraction.
+ *
+ * Contents
+ *   orc_exp_gs          exp for the cull (Cody & Waite 1980 reduction + Taylor)
+ *   orc_cull_v1         FP32 frustum/screen cull of one camera (Sec. 2.3 step 1,
+ *                       Sec. 3.4 challenge 1; formula fixed as the 3-sigma EWA box)
+ *   orc_compact         ascending ids of the kept rows (valid_ids, Sec. 4.1)
+ *   orc_adam_dense_f64  dense Adam, Eq. 1 -- the definition the method reaches
+ *   orc_lut_paper_f64   LUTs of the deferred-update figure (param/mom/var LUT)
+ *   orc_deferred_rows_f64  restore + Adam of the figure, FP64 (model O2)
+ *   orc_lut_spec        FP32 LUT of the implementation spec (model O3)
+ *   orc_deferred_rows_f32  the same update with FP32 state, fixed op order (O3)
+ *   orc_restore_rows_f32   restore-only (read-only forwarding, Sec. 4.3.3)
+ *   orc_flush_rows_*    catch-up of skipped zero-gradient steps (Eq. 2-3)
+ */
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+#include <stdlib.h>
+
+/* ------------------------------------------------------------------------ */
+/* exp for the cull: Cody-Waite argument reduction with ln2 split into a
+ * 9-bit head (355/512, so k*LN2_HI is exact for |k| <= 128) and an FP32 tail,
+ * then the degree-7 Taylor polynomial of e^r on |r| <= ln2/2 in Horner form,
+ * then scaling by 2^k.  Only +,-,*, rint and ldexp are used, each exactly
+ * rounded, so any IEEE machine gets the same bits.  NaN propagates (the
+ * clamp uses ordered comparisons). */
+float orc_exp_gs(float x)
+{
+    const float LOG2E = 1.44269504088896341f;
+    const float LN2_HI = 0.693359375f;          /* 355/512 */
+    const float LN2_LO = -2.12194440e-4f;       /* ln2 - 355/512 */
+    if (x < -87.0f) x = -87.0f;
+    if (x > 88.0f) x = 88.0f;
+    float k = rintf(x * LOG2E);
+    float r = (x - k * LN2_HI) - k * LN2_LO;
+    float p = 1.98412698e-4f;                   /* 1/7! */
+    p = p * r + 1.38888889e-3f;                 /* 1/6! */
+    p = p * r + 8.33333333e-3f;                 /* 1/5! */
+    p = p * r + 4.16666667e-2f;                 /* 1/4! */
+    p = p * r + 1.66666667e-1f;                 /* 1/3! */
+    p = p * r + 0.5f;
+    p = p * r + 1.0f;
+    p = p * r + 1.0f;
+    return ldexpf(p, (int)k);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Cull of one Gaussian.  The paper states what culling does -- drop Gaussians
+ * outside the near/far planes, project mean and covariance to the image, drop
+ * 2D Gaussians outside the image -- using only mean, scale and quaternion
+ * (Sec. 2.3 step 1; Sec. 4.1 step 1; Sec. 4.2.1).  It does not print a formula;
+ * this is the EWA screen-space test of 3D Gaussian Splatting: 3-sigma radius of
+ * the projected covariance (with the 0.3 px low-pass dilation) around the
+ * projected centre, tested against the image rectangle.
+ *
+ * cam[20] = R(9, row-major world->camera), t(3), fx, fy, cx, cy, W, H, near, far.
+ * detail (optional, 11 floats): x y z u v a b c det lambda r. */
+static int cull_one(const float *g, const float *cam, float *detail)
+{
+    const float *R = cam, *T = cam + 9;
+    const float fx = cam[12], fy = cam[13], cx = cam[14], cy = cam[15];
+    const float W = cam[16], H = cam[17], zn = cam[18], zf = cam[19];
+
+    /* 1. centre in camera space */
+    float x = ((R[0] * g[0] + R[1] * g[1]) + R[2] * g[2]) + T[0];
+    float y = ((R[3] * g[0] + R[4] * g[1]) + R[5] * g[2]) + T[1];
+    float z = ((R[6] * g[0] + R[7] * g[1]) + R[8] * g[2]) + T[2];
+
+    /* 2. unit quaternion (w,x,y,z) -> rotation */
+    float qw = g[6], qx = g[7], qy = g[8], qz = g[9];
+    float n2 = ((qw * qw + qx * qx) + qy * qy) + qz * qz;
+    float inv = 1.0f / sqrtf(n2);
+    qw = qw * inv; qx = qx * inv; qy = qy * inv; qz = qz * inv;
+    float Q[9];
+    Q[0] = 1.0f - 2.0f * (qy * qy + qz * qz);
+    Q[1] = 2.0f * (qx * qy - qw * qz);
+    Q[2] = 2.0f * (qx * qz + qw * qy);
+    Q[3] = 2.0f * (qx * qy + qw * qz);
+    Q[4] = 1.0f - 2.0f * (qx * qx + qz * qz);
+    Q[5] = 2.0f * (qy * qz - qw * qx);
+    Q[6] = 2.0f * (qx * qz - qw * qy);
+    Q[7] = 2.0f * (qy * qz + qw * qx);
+    Q[8] = 1.0f - 2.0f * (qx * qx + qy * qy);
+
+    /* 3. scales from log-scales */
+    float s0 = orc_exp_gs(g[3]), s1 = orc_exp_gs(g[4]), s2 = orc_exp_gs(g[5]);
+
+    /* 4. world covariance  Sigma = (Q S)(Q S)^T */
+    float M[9];
+    for (int a = 0; a < 3; ++a) {
+        M[3 * a + 0] = Q[3 * a + 0] * s0;
+        M[3 * a + 1] = Q[3 * a + 1] * s1;
+        M[3 * a + 2] = Q[3 * a + 2] * s2;
+    }
+    float S[9];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+            S[3 * a + b] = (M[3 * a + 0] * M[3 * b + 0] + M[3 * a + 1] * M[3 * b + 1])
+                           + M[3 * a + 2] * M[3 * b + 2];
+
+    /* 5. Jacobian of the pinhole projection at the centre, with the
+     *    tangent clamped to 1.3x the half field of view */
+    float rz = 1.0f / z;
+    float limx = 1.3f * ((0.5f * W) / fx);
+    float limy = 1.3f * ((0.5f * H) / fy);
+    float tx = x * rz, ty = y * rz;
+    if (tx < -limx) tx = -limx;
+    if (tx > limx) tx = limx;
+    if (ty < -limy) ty = -limy;
+    if (ty > limy) ty = limy;
+    float J00 = fx * rz, J02 = -(fx * tx) * rz;
+    float J11 = fy * rz, J12 = -(fy * ty) * rz;
+
+    /* 6. 2D covariance  T Sigma T^T  with T = J R */
+    float T0[3], T1[3];
+    for (int j = 0; j < 3; ++j) {
+        T0[j] = J00 * R[j] + J02 * R[6 + j];
+        T1[j] = J11 * R[3 + j] + J12 * R[6 + j];
+    }
+    float U0[3], U1[3];
+    for (int j = 0; j < 3; ++j) {
+        U0[j] = (T0[0] * S[j] + T0[1] * S[3 + j]) + T0[2] * S[6 + j];
+        U1[j] = (T1[0] * S[j] + T1[1] * S[3 + j]) + T1[2] * S[6 + j];
+    }
+    float a = ((U0[0] * T0[0] + U0[1] * T0[1]) + U0[2] * T0[2]) + 0.3f;
+    float b = (U0[0] * T1[0] + U0[1] * T1[1]) + U0[2] * T1[2];
+    float c = ((U1[0] * T1[0] + U1[1] * T1[1]) + U1[2] * T1[2]) + 0.3f;
+
+    /* 7. largest eigenvalue and 3-sigma pixel radius */
+    float det = a * c - b * b;
+    float mid = 0.5f * (a + c);
+    float disc = mid * mid - det;
+    if (!(disc > 0.1f)) disc = 0.1f;
+    float lam = mid + sqrtf(disc);
+    float r = ceilf(3.0f * sqrtf(lam));
+
+    /* 8. projected centre in pixels */
+    float u = (fx * x) * rz + cx;
+    float v = (fy * y) * rz + cy;
+
+    if (detail) {
+        detail[0] = x; detail[1] = y; detail[2] = z; detail[3] = u; detail[4] = v;
+        detail[5] = a; detail[6] = b; detail[7] = c; detail[8] = det; detail[9] = lam;
+        detail[10] = r;
+    }
+    /* 9. conjunction of positive comparisons: any NaN culls */
+    return (z > zn) && (z < zf) && (det > 0.0f) && (u + r > 0.0f) && (u - r < W)
+           && (v + r > 0.0f) && (v - r < H);
+}
+
+void orc_cull_v1(int64_t n, const float *geo, const float *cam, uint8_t *keep, float *detail)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i)
+        keep[i] = (uint8_t)cull_one(geo + 10 * i, cam, detail ? detail + 11 * i : NULL);
+}
+
+/* valid_ids: ids of kept rows in ascending order.  Returns the count. */
+int64_t orc_compact(int64_t n, const uint8_t *keep, uint32_t *ids)
+{
+    int64_t m = 0;
+    for (int64_t i = 0; i < n; ++i)
+        if (keep[i]) ids[m++] = (uint32_t)i;
+    return m;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Dense Adam, Eq. 1, stepped on every row (g = NULL means all-zero grads):
+ *   m = b1 m + (1-b1) g ;  v = b2 v + (1-b2) g^2
+ *   w = w - lr * (m / (1-b1^t)) / (sqrt(v / (1-b2^t)) + eps)                */
+void orc_adam_dense_f64(int64_t n, int dim, double *w, double *m, double *v, const double *g,
+                        const double *lr, double b1, double b2, double eps, int64_t t)
+{
+    const double bc1 = 1.0 - pow(b1, (double)t);
+    const double bc2 = 1.0 - pow(b2, (double)t);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        for (int k = 0; k < dim; ++k) {
+            int64_t e = i * dim + k;
+            double gi = g ? g[e] : 0.0;
+            m[e] = b1 * m[e] + (1.0 - b1) * gi;
+            v[e] = b2 * v[e] + (1.0 - b2) * gi * gi;
+            double mhat = m[e] / bc1;
+            double vhat = v[e] / bc2;
+            w[e] = w[e] - lr[k] * mhat / (sqrt(vhat) + eps);
+        }
+    }
+}
+
+/* Dense Adam where only the listed rows carry a gradient (compact rows
+ * g_rows[j] belong to row ids[j]); every other row steps with g = 0. */
+void orc_adam_dense_sparse_grad_f64(int64_t n, int dim, double *w, double *m, double *v,
+                                    int64_t n_ids, const uint32_t *ids, const float *g_rows,
+                                    const double *lr, double b1, double b2, double eps, int64_t t)
+{
+    double *g = (double *)calloc((size_t)n * dim, sizeof(double));
+    for (int64_t j = 0; j < n_ids; ++j)
+        for (int k = 0; k < dim; ++k)
+            g[(int64_t)ids[j] * dim + k] = (double)g_rows[j * dim + k];
+    orc_adam_dense_f64(n, dim, w, m, v, g, lr, b1, b2, eps, t);
+    free(g);
+}
+
+/* ------------------------------------------------------------------------ */
+/* LUTs of the deferred-update figure, FP64, for update step `step`, with a
+ * unit learning rate (W is linear in lr; callers multiply by the column's lr):
+ *   param_lut[0] = 0
+ *   param_lut[i] = (b1/sqrt(b2)) param_lut[i-1]
+ *                  + b1 / ( sqrt(b2 / (1 - b2^(step-i))) * (1 - b1^(step-i)) )
+ *   mom_lut[i] = b1^(i+1),  var_lut[i] = b2^(i+1)          for i = 0..dmax
+ * Entries exist for d = 0..dmax with dmax <= step-1: a row cannot have been
+ * deferred for step-1 or more steps, and step-i = 0 would divide by zero. */
+void orc_lut_paper_f64(double b1, double b2, int64_t step, int dmax,
+                       double *param_lut, double *mom_lut, double *var_lut)
+{
+    double scale = b1 / sqrt(b2);
+    param_lut[0] = 0.0;
+    for (int i = 1; i <= dmax; ++i)
+        param_lut[i] = scale * param_lut[i - 1]
+                       + b1 / (sqrt(b2 / (1.0 - pow(b2, (double)(step - i)))) * (1.0 - pow(b1, (double)(step - i))));
+    for (int i = 0; i <= dmax; ++i) {
+        mom_lut[i] = pow(b1, (double)(i + 1));
+        var_lut[i] = pow(b2, (double)(i + 1));
+    }
+}
+
+/* Model O2: restore + Adam of the deferred-update figure in FP64, for the
+ * update rows rows[j] with defer counts d[j] and compact gradients g[j][:]
+ * (zero rows for saturated Gaussians).  Per column k with learning rate lr[k]:
+ *   w -= (W[d] lr m) / (sqrt(v) + eps)            restore with the OLD moments
+ *   m' = b1^(d+1) m + (1-b1) g ;  v' = b2^(d+1) v + (1-b2) g g
+ *   w  = w - (lr/(1-b1^t)) m' / (sqrt(v')/sqrt(1-b2^t) + eps)
+ * The last line uses the new variance; the printed listing's use of the old
+ * one would make the step diverge and contradicts the text ("the standard
+ * Adam update is applied"). */
+void orc_deferred_rows_f64(int dim, double *w, double *m, double *v, int64_t n_rows,
+                           const uint32_t *rows, const int64_t *d, const double *g,
+                           const double *lr, double b1, double b2, double eps, int64_t t,
+                           const double *param_lut, const double *mom_lut, const double *var_lut)
+{
+    const double bias_correction = sqrt(1.0 - pow(b2, (double)t));
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < n_rows; ++j) {
+        int64_t id = rows[j];
+        int64_t dj = d[j];
+        double w_scale = param_lut[dj], m_scale = mom_lut[dj], v_scale = var_lut[dj];
+        for (int k = 0; k < dim; ++k) {
+            int64_t e = id * dim + k;
+            double wk = w[e], mk = m[e], vk = v[e], gk = g ? g[j * dim + k] : 0.0;
+            double m_new = m_scale * mk + (1.0 - b1) * gk;
+            double v_new = v_scale * vk + (1.0 - b2) * gk * gk;
+            m[e] = m_new;
+            v[e] = v_new;
+            if (dj > 0) wk -= (w_scale * lr[k] * mk) / (sqrt(vk) + eps);
+            double denom = sqrt(v_new) / bias_correction + eps;
+            double step_size = lr[k] / (1.0 - pow(b1, (double)t));
+            w[e] = wk - step_size * m_new / denom;
+        }
+    }
+}
+
+/* Restore-only in FP64: current value of rows with defer count d (read-only). */
+void orc_restore_rows_f64(int dim, const double *w, const double *m, const double *v,
+                          int64_t n_rows, const uint32_t *rows, const int64_t *d,
+                          const double *lr, double eps, const double *param_lut, double *out)
+{
+    for (int64_t j = 0; j < n_rows; ++j) {
+        int64_t id = rows[j];
+        for (int k = 0; k < dim; ++k) {
+            int64_t e = id * dim + k;
+            double wk = w[e];
+            if (d[j] > 0) wk -= (param_lut[d[j]] * lr[k] * m[e]) / (sqrt(v[e]) + eps);
+            out[j * dim + k] = wk;
+        }
+    }
+}
+
+/* Flush in FP64 after update `t`: rows rows[j] skipped delta[j] >= 1 steps.
+ * Their value after update t is the restore of update t+1 with d = delta
+ * (param_lut of step t+1), and the moments decay by b^delta. */
+void orc_flush_rows_f64(int dim, double *w, double *m, double *v, int64_t n_rows,
+                        const uint32_t *rows, const int64_t *delta, const double *lr,
+                        double b1, double b2, double eps, const double *param_lut_next)
+{
+    for (int64_t j = 0; j < n_rows; ++j) {
+        int64_t id = rows[j];
+        int64_t dl = delta[j];
+        for (int k = 0; k < dim; ++k) {
+            int64_t e = id * dim + k;
+            w[e] -= (param_lut_next[dl] * lr[k] * m[e]) / (sqrt(v[e]) + eps);
+            m[e] *= pow(b1, (double)dl);
+            v[e] *= pow(b2, (double)dl);
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Model O3: the implementation's FP32 arithmetic, written out independently.
+ *
+ * FP32 tables for update step t (computed in FP64, rounded once):
+ *   P1[k] = b1^k, P2[k] = b2^k by repeated multiplication from P[0] = 1
+ *   C[k]  = b1 / ( sqrt(b2 / (1 - P2[k])) * (1 - P1[k]) )              k >= 1
+ *   W[0]  = 0,  W[d] = (b1/sqrt(b2)) W[d-1] + C[t-d]                   d >= 1
+ *   Wf[d] = W[d], Mf[d] = P1[d+1], Vf[d] = P2[d+1],
+ *   ss = 1/(1 - P1[t]),  bc = sqrt(1 - P2[t])                (all as FP32)     */
+void orc_lut_spec(double b1, double b2, int64_t t, int dmax, float *Wf, float *Mf, float *Vf,
+                  float *ss, float *bc)
+{
+    int64_t kmax = t > dmax + 1 ? t : dmax + 1;
+    double *P1 = (double *)malloc(sizeof(double) * (size_t)(kmax + 1));
+    double *P2 = (double *)malloc(sizeof(double) * (size_t)(kmax + 1));
+    P1[0] = 1.0; P2[0] = 1.0;
+    for (int64_t k = 1; k <= kmax; ++k) { P1[k] = P1[k - 1] * b1; P2[k] = P2[k - 1] * b2; }
+    double r = b1 / sqrt(b2);
+    double W = 0.0;
+    Wf[0] = 0.0f;
+    for (int d = 1; d <= dmax; ++d) {
+        int64_t k = t - d;
+        double C = b1 / (sqrt(b2 / (1.0 - P2[k])) * (1.0 - P1[k]));
+        W = r * W + C;
+        Wf[d] = (float)W;
+    }
+    for (int d = 0; d <= dmax; ++d) { Mf[d] = (float)P1[d + 1]; Vf[d] = (float)P2[d + 1]; }
+    *ss = (float)(1.0 / (1.0 - P1[t]));
+    *bc = (float)sqrt(1.0 - P2[t]);
+    free(P1); free(P2);
+}
+
+/* O3 restore of one element: w - ((Wf[d]*lr)*m) / (sqrt(v)+eps), d > 0 only. */
+static float restore32(float w, float m, float v, float wd, float lr, float eps)
+{
+    float wsc = wd * lr;
+    float num = wsc * m;
+    float den = sqrtf(v) + eps;
+    return w - num / den;
+}
+
+/* O3 update of the rows rows[j] (defer count d[j], FP32 compact gradient
+ * g[j][:] or zero when g == NULL), state arrays [n][ld]. */
+void orc_deferred_rows_f32(int dim, float *w, float *m, float *v, int64_t ld, int64_t n_rows,
+                           const uint32_t *rows, const int64_t *d, const float *g, int64_t g_ld,
+                           const float *lr, double b1, double b2, double eps,
+                           const float *Wf, const float *Mf, const float *Vf, float ss, float bc)
+{
+    const float omb1 = (float)(1.0 - b1), omb2 = (float)(1.0 - b2), eps32 = (float)eps;
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < n_rows; ++j) {
+        int64_t id = rows[j];
+        int64_t dj = d[j];
+        for (int k = 0; k < dim; ++k) {
+            int64_t e = id * ld + k;
+            float wk = w[e], mk = m[e], vk = v[e];
+            float gk = g ? g[j * g_ld + k] : 0.0f;
+            if (dj > 0) wk = restore32(wk, mk, vk, Wf[dj], lr[k], eps32);
+            float m1 = Mf[dj] * mk + omb1 * gk;
+            float v1 = Vf[dj] * vk + (omb2 * gk) * gk;
+            float den = sqrtf(v1) / bc + eps32;
+            float st = lr[k] * ss;
+            w[e] = wk - (st * m1) / den;
+            m[e] = m1;
+            v[e] = v1;
+        }
+    }
+}
+
+/* O3 restore-only: out[j][:] = current FP32 value of row rows[j]. */
+void orc_restore_rows_f32(int dim, const float *w, const float *m, const float *v, int64_t ld,
+                          int64_t n_rows, const uint32_t *rows, const int64_t *d,
+                          const float *lr, double eps, const float *Wf, float *out)
+{
+    const float eps32 = (float)eps;
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < n_rows; ++j) {
+        int64_t id = rows[j];
+        for (int k = 0; k < dim; ++k) {
+            int64_t e = id * ld + k;
+            float wk = w[e];
+            if (d[j] > 0) wk = restore32(wk, m[e], v[e], Wf[d[j]], lr[k], eps32);
+            out[j * dim + k] = wk;
+        }
+    }
+}
+
+/* O3 flush: rows skipped delta[j] >= 1 steps; Wf_next is the table of step t+1. */
+void orc_flush_rows_f32(int dim, float *w, float *m, float *v, int64_t ld, int64_t n_rows,
+                        const uint32_t *rows, const int64_t *delta, const float *lr, double eps,
+                        const float *Wf_next, const float *Mf, const float *Vf)
+{
+    const float eps32 = (float)eps;
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < n_rows; ++j) {
+        int64_t id = rows[j];
+        int64_t dl = delta[j];
+        for (int k = 0; k < dim; ++k) {
+            int64_t e = id * ld + k;
+            float mk = m[e], vk = v[e];
+            w[e] = restore32(w[e], mk, vk, Wf_next[dl], lr[k], eps32);
+            m[e] = Mf[dl - 1] * mk;
+            v[e] = Vf[dl - 1] * vk;
+        }
+    }
+}

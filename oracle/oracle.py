@@ -1,0 +1,348 @@
+"""Python driver of the CPU oracle (TEST INFRASTRUCTURE ONLY).
+
+Only the tests, the smoke check and the CPU-baseline leg of the benchmark may
+import this module.  It loads ``liboracle.so`` built from ``gs_oracle.c`` (plain
+C, ``-O2 -ffp-contract=off -fno-fast-math``) and never touches the HIP library.
+
+Models
+  DenseAdamF64     Eq. 1 stepped on every row every step (the definition).
+  DeferredF64      the deferred-update figure in FP64 (model O2): restore with
+                   the paper's LUTs, Adam on update_ids = valid_ids U saturated.
+  DeferredF32      the same algorithm with FP32 state and the implementation's
+                   fixed operation order (model O3); its cull of the *current*
+                   geometry gives the visible sets.
+Every simulation may run on a subset of rows (``keys`` = the rows' Gaussian
+ids): rows are independent given their own visibility, so a row sample is
+exact for the sampled rows.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+import sys
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "gs_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+GEO_DIM, APP_DIM = 10, 49
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so with gcc (no contraction, no fast-math, OpenMP)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC",
+               "-shared", "-std=c11", "-Wall", "-o", tmp, SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, LIB)
+    return LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+            build(force=True)
+        L = C.CDLL(LIB)
+        vp, i64, i32, f64, f32 = C.c_void_p, C.c_int64, C.c_int, C.c_double, C.c_float
+        sig = {
+            "orc_exp_gs": (f32, [f32]),
+            "orc_cull_v1": (None, [i64, vp, vp, vp, vp]),
+            "orc_compact": (i64, [i64, vp, vp]),
+            "orc_adam_dense_f64": (None, [i64, i32, vp, vp, vp, vp, vp, f64, f64, f64, i64]),
+            "orc_adam_dense_sparse_grad_f64": (None, [i64, i32, vp, vp, vp, i64, vp, vp, vp,
+                                                       f64, f64, f64, i64]),
+            "orc_lut_paper_f64": (None, [f64, f64, i64, i32, vp, vp, vp]),
+            "orc_deferred_rows_f64": (None, [i32, vp, vp, vp, i64, vp, vp, vp, vp, f64, f64, f64,
+                                             i64, vp, vp, vp]),
+            "orc_restore_rows_f64": (None, [i32, vp, vp, vp, i64, vp, vp, vp, f64, vp, vp]),
+            "orc_flush_rows_f64": (None, [i32, vp, vp, vp, i64, vp, vp, vp, f64, f64, f64, vp]),
+            "orc_lut_spec": (None, [f64, f64, i64, i32, vp, vp, vp, vp, vp]),
+            "orc_deferred_rows_f32": (None, [i32, vp, vp, vp, i64, i64, vp, vp, vp, i64, vp,
+                                             f64, f64, f64, vp, vp, vp, f32, f32]),
+            "orc_restore_rows_f32": (None, [i32, vp, vp, vp, i64, i64, vp, vp, vp, f64, vp, vp]),
+            "orc_flush_rows_f32": (None, [i32, vp, vp, vp, i64, i64, vp, vp, vp, f64, vp, vp, vp]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _p(a, dtype=None):
+    if a is None:
+        return None
+    if dtype is not None:
+        assert a.dtype == dtype, (a.dtype, dtype)
+    assert a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data
+
+
+# ---------------------------------------------------------------------------
+# cull
+# ---------------------------------------------------------------------------
+def cam_floats(cam) -> np.ndarray:
+    """R(9), t(3), fx, fy, cx, cy, W, H, near, far as float32."""
+    if isinstance(cam, np.ndarray):
+        out = cam.astype(np.float32)
+    else:
+        out = cam.as_floats()
+    assert out.shape == (20,)
+    return np.ascontiguousarray(out)
+
+
+def exp_gs(x: np.ndarray) -> np.ndarray:
+    f = lib().orc_exp_gs
+    x = np.asarray(x, np.float32).ravel()
+    return np.array([f(float(v)) for v in x], np.float32)
+
+
+def cull(geo: np.ndarray, cam, detail: bool = False):
+    """keep mask (bool [n]) of cull_v1 on FP32 geometry [n,10]; optional detail [n,11]."""
+    geo = np.ascontiguousarray(geo, np.float32)
+    n = geo.shape[0]
+    keep = np.zeros(n, np.uint8)
+    det = np.zeros((n, 11), np.float32) if detail else None
+    lib().orc_cull_v1(n, _p(geo), _p(cam_floats(cam)), _p(keep), _p(det))
+    return (keep.astype(bool), det) if detail else keep.astype(bool)
+
+
+def compact(keep: np.ndarray) -> np.ndarray:
+    k = np.ascontiguousarray(keep, np.uint8)
+    ids = np.empty(k.shape[0], np.uint32)
+    m = lib().orc_compact(k.shape[0], _p(k), _p(ids))
+    return ids[:m].copy()
+
+
+# ---------------------------------------------------------------------------
+# LUTs
+# ---------------------------------------------------------------------------
+def lut_paper(b1: float, b2: float, step: int, dmax: int):
+    """param_lut, mom_lut, var_lut (FP64, unit lr) of the deferred-update figure."""
+    p = np.zeros(dmax + 1); mo = np.zeros(dmax + 1); va = np.zeros(dmax + 1)
+    lib().orc_lut_paper_f64(b1, b2, step, dmax, _p(p), _p(mo), _p(va))
+    return p, mo, va
+
+
+def lut_spec(b1: float, b2: float, step: int, dmax: int):
+    """FP32 tables (Wf, Mf, Vf, ss, bc) of the implementation spec for update `step`."""
+    Wf = np.zeros(dmax + 1, np.float32); Mf = np.zeros(dmax + 1, np.float32)
+    Vf = np.zeros(dmax + 1, np.float32)
+    ss = C.c_float(); bc = C.c_float()
+    lib().orc_lut_spec(b1, b2, step, dmax, _p(Wf), _p(Mf), _p(Vf), C.addressof(ss), C.addressof(bc))
+    return Wf, Mf, Vf, np.float32(ss.value), np.float32(bc.value)
+
+
+# ---------------------------------------------------------------------------
+# dense Adam (Eq. 1)
+# ---------------------------------------------------------------------------
+class DenseAdamF64:
+    """FP64 Adam on every row every step; rows without a gradient use g = 0."""
+
+    def __init__(self, geo, app, lr_geo, lr_app, b1=0.9, b2=0.999, eps=1e-15):
+        self.w = [np.array(geo, np.float64), np.array(app, np.float64)]
+        self.m = [np.zeros_like(x) for x in self.w]
+        self.v = [np.zeros_like(x) for x in self.w]
+        self.lr = [np.asarray(lr_geo, np.float64), np.asarray(lr_app, np.float64)]
+        self.b1, self.b2, self.eps = b1, b2, eps
+
+    def step(self, t: int, ids: np.ndarray, g_geo: np.ndarray, g_app: np.ndarray):
+        ids = np.ascontiguousarray(ids, np.uint32)
+        for k, g in enumerate((g_geo, g_app)):
+            g = np.ascontiguousarray(g, np.float32)
+            w, m, v = self.w[k], self.m[k], self.v[k]
+            lib().orc_adam_dense_sparse_grad_f64(w.shape[0], w.shape[1], _p(w), _p(m), _p(v),
+                                                 ids.shape[0], _p(ids), _p(g), _p(self.lr[k]),
+                                                 self.b1, self.b2, self.eps, t)
+
+
+# ---------------------------------------------------------------------------
+# deferred models
+# ---------------------------------------------------------------------------
+class _Deferred:
+    """Common bookkeeping of the deferred-update figure: a per-row counter of
+    deferred steps, update_ids = union(valid_ids, where(counter == MAX)),
+    counters of updated rows reset and all others incremented.  max_defer = 0
+    means no saturation (the counter never forces an update)."""
+
+    def __init__(self, n, max_defer):
+        self.counter = np.zeros(n, np.int64)
+        self.max_defer = int(max_defer)
+
+    def update_set(self, valid):
+        valid = np.asarray(valid, np.int64)
+        if self.max_defer > 0:
+            sat = np.nonzero(self.counter == self.max_defer)[0]
+            sat = np.setdiff1d(sat, valid, assume_unique=True)
+        else:
+            sat = np.zeros(0, np.int64)
+        return valid, sat
+
+    def bump(self, valid, sat):
+        self.counter += 1
+        self.counter[valid] = 0
+        self.counter[sat] = 0
+
+    def dmax(self, t):
+        return min(t - 1, self.max_defer) if self.max_defer > 0 else t - 1
+
+    def last_step(self, t_done: int) -> np.ndarray:
+        """last update step of every row after update t_done (0 = never)."""
+        return (t_done - self.counter).astype(np.int32)
+
+
+class DeferredF64(_Deferred):
+    """Model O2: the paper's deferred algorithm with FP64 state."""
+
+    def __init__(self, geo, app, lr_geo, lr_app, b1=0.9, b2=0.999, eps=1e-15, max_defer=0):
+        super().__init__(geo.shape[0], max_defer)
+        self.w = [np.array(geo, np.float64), np.array(app, np.float64)]
+        self.m = [np.zeros_like(x) for x in self.w]
+        self.v = [np.zeros_like(x) for x in self.w]
+        self.lr = [np.asarray(lr_geo, np.float64), np.asarray(lr_app, np.float64)]
+        self.b1, self.b2, self.eps = b1, b2, eps
+
+    def current(self, t: int, rows=None):
+        """Restored values of rows (default all) before update t: (geo, app)."""
+        rows = np.arange(self.counter.shape[0]) if rows is None else np.asarray(rows)
+        rows32 = np.ascontiguousarray(rows, np.uint32)
+        d = np.ascontiguousarray(self.counter[rows], np.int64)
+        lut, _, _ = lut_paper(self.b1, self.b2, t, max(self.dmax(t), 0))
+        out = []
+        for k in range(2):
+            o = np.zeros((rows.shape[0], self.w[k].shape[1]))
+            lib().orc_restore_rows_f64(self.w[k].shape[1], _p(self.w[k]), _p(self.m[k]), _p(self.v[k]),
+                                       rows.shape[0], _p(rows32), _p(d), _p(self.lr[k]), self.eps,
+                                       _p(lut), _p(o))
+            out.append(o)
+        return out[0], out[1]
+
+    def step(self, t, valid, g_geo, g_app):
+        valid, sat = self.update_set(valid)
+        rows = np.ascontiguousarray(np.concatenate([valid, sat]), np.uint32)
+        d = np.ascontiguousarray(self.counter[rows.astype(np.int64)], np.int64)
+        lut, mom, var = lut_paper(self.b1, self.b2, t, max(self.dmax(t), 0))
+        for k, g in enumerate((g_geo, g_app)):
+            dim = self.w[k].shape[1]
+            gg = np.zeros((rows.shape[0], dim))
+            gg[:valid.shape[0]] = np.asarray(g, np.float64)
+            lib().orc_deferred_rows_f64(dim, _p(self.w[k]), _p(self.m[k]), _p(self.v[k]), rows.shape[0],
+                                        _p(rows), _p(d), _p(gg), _p(self.lr[k]), self.b1, self.b2,
+                                        self.eps, t, _p(lut), _p(mom), _p(var))
+        self.bump(valid, sat)
+        return valid, sat
+
+    def flush(self, t_done: int):
+        rows = np.nonzero(self.counter > 0)[0]
+        if rows.shape[0] == 0:
+            return
+        delta = np.ascontiguousarray(self.counter[rows], np.int64)
+        lut, _, _ = lut_paper(self.b1, self.b2, t_done + 1, int(delta.max()))
+        rows32 = np.ascontiguousarray(rows, np.uint32)
+        for k in range(2):
+            lib().orc_flush_rows_f64(self.w[k].shape[1], _p(self.w[k]), _p(self.m[k]), _p(self.v[k]),
+                                     rows.shape[0], _p(rows32), _p(delta), _p(self.lr[k]),
+                                     self.b1, self.b2, self.eps, _p(lut))
+        self.counter[:] = 0
+
+
+class DeferredF32(_Deferred):
+    """Model O3: deferred algorithm, FP32 state, the implementation's op order."""
+
+    def __init__(self, geo, app, lr_geo, lr_app, b1=0.9, b2=0.999, eps=1e-15, max_defer=0):
+        super().__init__(geo.shape[0], max_defer)
+        self.w = [np.array(geo, np.float32), np.array(app, np.float32)]
+        self.m = [np.zeros_like(x) for x in self.w]
+        self.v = [np.zeros_like(x) for x in self.w]
+        self.lr = [np.asarray(lr_geo, np.float32), np.asarray(lr_app, np.float32)]
+        self.b1, self.b2, self.eps = b1, b2, eps
+
+    def _restore(self, k, t, rows):
+        rows32 = np.ascontiguousarray(rows, np.uint32)
+        d = np.ascontiguousarray(self.counter[np.asarray(rows, np.int64)], np.int64)
+        Wf, _, _, _, _ = lut_spec(self.b1, self.b2, t, max(self.dmax(t), 0))
+        dim = self.w[k].shape[1]
+        out = np.zeros((rows32.shape[0], dim), np.float32)
+        lib().orc_restore_rows_f32(dim, _p(self.w[k]), _p(self.m[k]), _p(self.v[k]), dim,
+                                   rows32.shape[0], _p(rows32), _p(d), _p(self.lr[k]), self.eps,
+                                   _p(Wf), _p(out))
+        return out
+
+    def current(self, t: int, rows=None):
+        """FP32 restored (geo, app) of rows (default all) before update t."""
+        rows = np.arange(self.counter.shape[0]) if rows is None else np.asarray(rows)
+        return self._restore(0, t, rows), self._restore(1, t, rows)
+
+    def current_geo(self, t: int):
+        return self._restore(0, t, np.arange(self.counter.shape[0]))
+
+    def cull_current(self, t: int, cam):
+        """valid_ids (local row indices, ascending) of the current geometry."""
+        return compact(cull(self.current_geo(t), cam))
+
+    def step(self, t, valid, g_geo, g_app):
+        valid, sat = self.update_set(valid)
+        rows = np.ascontiguousarray(np.concatenate([valid, sat]), np.uint32)
+        d = np.ascontiguousarray(self.counter[rows.astype(np.int64)], np.int64)
+        Wf, Mf, Vf, ss, bc = lut_spec(self.b1, self.b2, t, max(self.dmax(t), 0))
+        for k, g in enumerate((g_geo, g_app)):
+            dim = self.w[k].shape[1]
+            gg = np.zeros((rows.shape[0], dim), np.float32)
+            gg[:valid.shape[0]] = g
+            lib().orc_deferred_rows_f32(dim, _p(self.w[k]), _p(self.m[k]), _p(self.v[k]), dim,
+                                        rows.shape[0], _p(rows), _p(d), _p(gg), dim, _p(self.lr[k]),
+                                        self.b1, self.b2, self.eps, _p(Wf), _p(Mf), _p(Vf),
+                                        float(ss), float(bc))
+        self.bump(valid, sat)
+        return valid, sat
+
+    def flush(self, t_done: int):
+        rows = np.nonzero(self.counter > 0)[0]
+        if rows.shape[0] == 0:
+            return
+        delta = np.ascontiguousarray(self.counter[rows], np.int64)
+        # table of step t_done+1 at index delta <= t_done; Mf/Vf do not depend on t
+        Wn, Mf, Vf, _, _ = lut_spec(self.b1, self.b2, t_done + 1, int(delta.max()))
+        rows32 = np.ascontiguousarray(rows, np.uint32)
+        for k in range(2):
+            dim = self.w[k].shape[1]
+            lib().orc_flush_rows_f32(dim, _p(self.w[k]), _p(self.m[k]), _p(self.v[k]), dim,
+                                     rows.shape[0], _p(rows32), _p(delta), _p(self.lr[k]), self.eps,
+                                     _p(Wn), _p(Mf), _p(Vf))
+        self.counter[:] = 0
+
+
+def simulate(models, scene_geo_rows_keys, cams_for_step, grads_for, steps, t0=1):
+    """Drive O3 (and optionally O2 / dense) through `steps` updates.
+
+    models: dict with 'f32' (DeferredF32, required), optional 'f64', 'dense'.
+    scene_geo_rows_keys: Gaussian ids of the simulated rows (for gradients).
+    grads_for(t, keys) -> (g_geo, g_app) FP32 compact gradients.
+    Returns the list of per-step valid (local) id arrays of O3.
+    """
+    keys = np.asarray(scene_geo_rows_keys)
+    history = []
+    for t in range(t0, t0 + steps):
+        o3 = models["f32"]
+        valid = o3.cull_current(t, cams_for_step(t))
+        g_geo, g_app = grads_for(t, keys[valid])
+        o3.step(t, valid, g_geo, g_app)
+        if "f64" in models:
+            models["f64"].step(t, valid, g_geo, g_app)
+        if "dense" in models:
+            models["dense"].step(t, valid, g_geo, g_app)
+        history.append(valid)
+    return history
+
+
+if __name__ == "__main__":
+    print(build(force=True), file=sys.stderr)

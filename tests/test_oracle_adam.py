@@ -1,0 +1,223 @@
+"""Pins of the oracle's optimizer models against the mathematics they follow.
+
+  * dense FP64 Adam (Eq. 1) == torch.optim.Adam in FP64 (independent library);
+  * first step moves w by exactly lr*g/(|g|+eps) (closed form);
+  * the LUT recurrence of the deferred-update figure == the direct sum of Eq. 3;
+  * hand-stepping d zero-gradient dense steps == one restore (Eq. 2-3, eps = 0);
+  * deferred FP64 (O2) == dense FP64 with eps = 0, at MAX = inf and MAX = 15,
+    for the state after any step and after a flush (the method is exact up to
+    rounding apart from the eps factor-out, Sec. 4.3.1 / Sec. 5.5);
+  * with eps = 1e-15 the eps factor-out error stays far below FP32 resolution;
+  * the FP32 model O3 stays within FP32 rounding of O2, and its FP32 LUT
+    within one rounding of the paper's FP64 LUT;
+  * the saturating counter never exceeds MAX and forces exactly the rows that
+    reach it (Sec. 4.3.2, listing's update set).
+"""
+import numpy as np
+import pytest
+import torch
+
+import gs_inputs as gi
+from oracle import oracle as orc
+
+B1, B2 = 0.9, 0.999
+TAU_GEO = np.array([1, 1, 1, .5, .5, .5, .5, .5, .5, .5])
+TAU_APP = np.array([1.0] + [0.1] * 48)
+
+
+def rel_err(w, ref, tau):
+    return np.abs(np.asarray(w, np.float64) - ref) / np.maximum(np.abs(ref), tau)
+
+
+def _scene(n, seed):
+    s = gi.make_scene(n, seed=seed)
+    lg, la = gi.lr_columns()
+    return s, lg, la
+
+
+def _vis_sequence(n, steps, p, seed, first_all=True):
+    rng = np.random.default_rng(seed)
+    out = []
+    for t in range(1, steps + 1):
+        vis = np.ones(n, bool) if (t == 1 and first_all) else rng.random(n) < p
+        out.append(np.nonzero(vis)[0])
+    return out
+
+
+def _gauss_grads(t, ids, seed=0):
+    rng = np.random.default_rng(seed * 100003 + t)
+    return (rng.normal(0, 1e-3, (ids.shape[0], 10)).astype(np.float32),
+            rng.normal(0, 1e-3, (ids.shape[0], 49)).astype(np.float32))
+
+
+def test_dense_adam_matches_torch_adam():
+    n = 300
+    s, lg, la = _scene(n, 0)
+    dense = orc.DenseAdamF64(s.geo, s.app, lg, la, eps=1e-15)
+    groups = [(0, slice(0, 3)), (0, slice(3, 10)), (1, slice(0, 49))]
+    params = [torch.tensor(np.array([s.geo, s.app][g][:, sl], np.float64), requires_grad=True)
+              for g, sl in groups]
+    lrs = [float(lg[0]), float(lg[3]), float(la[0])]
+    opt = torch.optim.Adam([{"params": [p], "lr": lr} for p, lr in zip(params, lrs)],
+                           betas=(B1, B2), eps=1e-15, foreach=False)
+    for t, ids in enumerate(_vis_sequence(n, 25, 0.3, 1), start=1):
+        g_geo, g_app = _gauss_grads(t, ids)
+        dense.step(t, ids, g_geo, g_app)
+        full = [np.zeros((n, 10)), np.zeros((n, 49))]
+        full[0][ids] = g_geo
+        full[1][ids] = g_app
+        for p, (g, sl) in zip(params, groups):
+            p.grad = torch.tensor(full[g][:, sl])
+        opt.step()
+    for p, (g, sl) in zip(params, groups):
+        ref = p.detach().numpy()
+        assert np.max(np.abs(dense.w[g][:, sl] - ref) / np.maximum(np.abs(ref), 1e-3)) < 1e-13
+
+
+def test_first_step_closed_form():
+    n = 200
+    s, lg, la = _scene(n, 1)
+    dense = orc.DenseAdamF64(s.geo, s.app, lg, la, eps=1e-15)
+    ids = np.arange(n)
+    g_geo, g_app = _gauss_grads(1, ids)
+    dense.step(1, ids, g_geo, g_app)
+    for k, (g, lr, w0) in enumerate(((g_geo, lg, s.geo), (g_app, la, s.app))):
+        g = g.astype(np.float64)
+        expect = w0.astype(np.float64) - lr.astype(np.float64) * g / (np.abs(g) + 1e-15)
+        assert np.max(np.abs(dense.w[k] - expect)) < 1e-15
+
+
+@pytest.mark.parametrize("t", [2, 5, 17, 100, 1000])
+def test_lut_recurrence_equals_eq3_sum(t):
+    dmax = min(t - 1, 300)
+    lut, mom, var = orc.lut_paper(B1, B2, t, dmax)
+    for d in range(dmax + 1):
+        direct = 0.0
+        for l in range(d):
+            k = t - d + l
+            direct += (B1 ** (l + 1) / (1 - B1 ** k)) / np.sqrt(B2 ** (l + 1) / (1 - B2 ** k))
+        assert abs(lut[d] - direct) <= 4e-15 * max(abs(direct), 1e-300)
+        assert mom[d] == pytest.approx(B1 ** (d + 1), rel=1e-15)
+        assert var[d] == pytest.approx(B2 ** (d + 1), rel=1e-15)
+
+
+@pytest.mark.parametrize("L,d", [(1, 1), (3, 5), (10, 40), (50, 200)])
+def test_restore_equals_hand_stepping_zero_grads(L, d):
+    """Dense Adam with eps = 0 run L steps with gradients, then d steps with
+    g = 0, equals the restore of Eq. 2-3 from the state after step L."""
+    n = 64
+    s, lg, la = _scene(n, 2)
+    dense = orc.DenseAdamF64(s.geo, s.app, lg, la, eps=0.0)
+    ids = np.arange(n)
+    for t in range(1, L + 1):
+        dense.step(t, ids, *_gauss_grads(t, ids))
+    w_L = [x.copy() for x in dense.w]
+    m_L = [x.copy() for x in dense.m]
+    v_L = [x.copy() for x in dense.v]
+    empty = np.zeros(0, np.int64)
+    for t in range(L + 1, L + d + 1):
+        dense.step(t, empty, np.zeros((0, 10), np.float32), np.zeros((0, 49), np.float32))
+    t = L + d + 1
+    lut, mom, var = orc.lut_paper(B1, B2, t, d)
+    for k, lr in enumerate((lg, la)):
+        restored = w_L[k] - lut[d] * lr.astype(np.float64) * m_L[k] / np.sqrt(v_L[k])
+        assert np.max(np.abs(restored - dense.w[k]) / np.maximum(np.abs(dense.w[k]), 1e-3)) < 1e-13
+        # moments decay by b^d over the d zero steps
+        assert np.allclose(dense.m[k], m_L[k] * B1 ** d, rtol=1e-13, atol=0)
+        assert np.allclose(dense.v[k], v_L[k] * B2 ** d, rtol=1e-13, atol=0)
+
+
+@pytest.mark.parametrize("max_defer", [0, 15])
+def test_deferred_f64_equals_dense_with_eps_zero(max_defer):
+    n, steps = 400, 60
+    s, lg, la = _scene(n, 3)
+    dense = orc.DenseAdamF64(s.geo, s.app, lg, la, eps=0.0)
+    o2 = orc.DeferredF64(s.geo, s.app, lg, la, eps=0.0, max_defer=max_defer)
+    for t, ids in enumerate(_vis_sequence(n, steps, 0.05, 4), start=1):
+        g = _gauss_grads(t, ids, 4)
+        dense.step(t, ids, *g)
+        o2.step(t, ids, *g)
+        if t in (7, 33):
+            cg, ca = o2.current(t + 1)
+            for k, cur in enumerate((cg, ca)):
+                assert np.max(rel_err(cur, dense.w[k], 1e-3)) < 1e-12
+    if max_defer:
+        assert o2.counter.max() <= max_defer
+    o2.flush(steps)
+    for k in range(2):
+        assert np.max(rel_err(o2.w[k], dense.w[k], 1e-3)) < 1e-12
+        # moments: m can cancel (b1^(d+1) m + (1-b1) g), so compare on the group's scale
+        assert np.max(np.abs(o2.m[k] - dense.m[k])) < 1e-12 * np.max(np.abs(dense.m[k]))
+        assert np.max(np.abs(o2.v[k] - dense.v[k]) / np.maximum(np.abs(dense.v[k]), 1e-30)) < 1e-12
+
+
+def test_eps_factor_out_error_is_tiny_at_1e_15():
+    """The only approximation is factoring eps out of the restore (Sec. 4.3.1,
+    Sec. 5.5).  Its error is linear in eps and, at eps = 1e-15, below FP32
+    resolution of the parameters."""
+    n, steps = 400, 60
+    s, lg, la = _scene(n, 5)
+    errs = []
+    for eps in (1e-15, 1e-12):
+        dense = orc.DenseAdamF64(s.geo, s.app, lg, la, eps=eps)
+        o2 = orc.DeferredF64(s.geo, s.app, lg, la, eps=eps)
+        for t, ids in enumerate(_vis_sequence(n, steps, 0.1, 6, first_all=False), start=1):
+            g = gi.step_grads(0, t, ids)
+            dense.step(t, ids, *g)
+            o2.step(t, ids, *g)
+        o2.flush(steps)
+        errs.append(max(np.max(rel_err(o2.w[0], dense.w[0], TAU_GEO)),
+                        np.max(rel_err(o2.w[1], dense.w[1], TAU_APP))))
+    assert errs[0] < 6e-8
+    assert 500 < errs[1] / errs[0] < 2000
+
+
+@pytest.mark.parametrize("t", [2, 17, 100, 1000])
+def test_spec_lut_within_one_rounding_of_paper_lut(t):
+    dmax = t - 1
+    lut, mom, var = orc.lut_paper(B1, B2, t, dmax)
+    Wf, Mf, Vf, ss, bc = orc.lut_spec(B1, B2, t, dmax)
+    for a, b in ((Wf, lut), (Mf, mom), (Vf, var)):
+        ulp = np.spacing(np.abs(b).astype(np.float32)).astype(np.float64)
+        assert np.all(np.abs(a.astype(np.float64) - b) <= ulp)
+    assert abs(float(ss) - 1 / (1 - B1 ** t)) <= np.spacing(np.float32(ss))
+    assert abs(float(bc) - np.sqrt(1 - B2 ** t)) <= np.spacing(np.float32(bc))
+
+
+@pytest.mark.parametrize("max_defer", [0, 15])
+def test_f32_model_within_fp32_rounding_of_f64(max_defer):
+    n, steps = 2000, 20
+    s, lg, la = _scene(n, 7)
+    o2 = orc.DeferredF64(s.geo, s.app, lg, la, max_defer=max_defer)
+    o3 = orc.DeferredF32(s.geo, s.app, lg, la, max_defer=max_defer)
+    dense = orc.DenseAdamF64(s.geo, s.app, lg, la)
+    for t, ids in enumerate(_vis_sequence(n, steps, 0.3, 8, first_all=False), start=1):
+        g = gi.step_grads(0, t, ids)
+        o2.step(t, ids, *g)
+        o3.step(t, ids, *g)
+        dense.step(t, ids, *g)
+        cg3, _ = o3.current(t + 1)
+        cg2, _ = o2.current(t + 1)
+        assert np.max(rel_err(cg3, cg2, TAU_GEO)) < 1e-6
+    assert np.array_equal(o2.counter, o3.counter)
+    o2.flush(steps)
+    o3.flush(steps)
+    for k, tau in ((0, TAU_GEO), (1, TAU_APP)):
+        assert np.max(rel_err(o3.w[k], o2.w[k], tau)) < 1e-6
+        assert np.max(rel_err(o3.w[k], dense.w[k], tau)) < 1e-6
+
+
+def test_saturation_forces_exactly_the_rows_at_max():
+    n, steps, MAX = 300, 50, 15
+    s, lg, la = _scene(n, 9)
+    o2 = orc.DeferredF64(s.geo, s.app, lg, la, max_defer=MAX)
+    forced_total = 0
+    for t, ids in enumerate(_vis_sequence(n, steps, 0.02, 10, first_all=False), start=1):
+        before = o2.counter.copy()
+        valid, sat = o2.step(t, ids, *_gauss_grads(t, ids))
+        expect = np.setdiff1d(np.nonzero(before == MAX)[0], ids)
+        assert np.array_equal(np.sort(sat), expect)
+        assert o2.counter.max() <= MAX
+        forced_total += sat.shape[0]
+    # at a 2% visible rate nearly every row is forced once every 16 steps
+    assert forced_total > 0.8 * n * (steps - MAX) / (MAX + 1)
