@@ -1,0 +1,187 @@
+"""Train-step throughput of the Gaussian-parameter path on one MI355X.
+
+One step = gs_cull (cull + ordered compaction of every Gaussian) ->
+gs_gather (restored visible rows) -> gs_adam_step_deferred (fused scatter +
+deferred Adam), on the 4M-Gaussian aerial workload (1000x1000x100 box, 1600
+nadir/oblique cameras 1152x864 f=1100, one camera per step), FP32 state.
+Synthetic gradients are generated on the device before the timed region (a
+pool of compact gradient buffers, one per step mod pool size) and stand in
+for the renderer's backward pass.
+
+Prints one JSON line: value = Gaussians/s = N / (ms per step), with a
+roofline object for the dominant kernel (HIP events on the launch stream,
+algorithmic bytes per launch) and the CPU oracle timed on a row sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=100)
+    p.add_argument("--warmup", type=int, default=10)
+    p.add_argument("--workload", default="aerial4m", choices=["small", "aerial4m", "aerial18m", "aerial40m"])
+    p.add_argument("--n", type=int, default=None, help="override the Gaussian count")
+    p.add_argument("--layout", default="interleaved", choices=["separate", "interleaved"])
+    p.add_argument("--max-defer", type=int, default=0)
+    p.add_argument("--cull-mode", type=int, default=0)
+    p.add_argument("--tilt", default="20,45", help="oblique tilt range in degrees")
+    p.add_argument("--pool", type=int, default=4)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-sample", type=int, default=1 << 20)
+    p.add_argument("--cpu-steps", type=int, default=6)
+    return p.parse_args()
+
+
+def cpu_baseline(w, sc, sample, steps, lg, la):
+    """The oracle as it stands, on a seeded row sample of the same workload:
+    FP32 cull of the sample's geometry + ids + synthetic grads + dense FP64
+    Adam on every sampled row (Eq. 1), per step.  Gaussians/s = sample / t."""
+    from oracle import oracle as orc
+    import gs_inputs as gi
+    rng = np.random.default_rng(123)
+    rows = np.sort(rng.choice(w.n, min(sample, w.n), replace=False))
+    geo = np.ascontiguousarray(sc.geo[rows])
+    app = np.ascontiguousarray(sc.app[rows])
+    dense = orc.DenseAdamF64(geo, app, lg, la)
+    times = []
+    for t in range(1, steps + 1):
+        t0 = time.perf_counter()
+        keep = orc.cull(dense.w[0].astype(np.float32), w.camera_for_step(t))
+        valid = orc.compact(keep)
+        gg, ga = gi.step_grads(0, t, rows[valid])
+        dense.step(t, valid, gg, ga)
+        times.append(time.perf_counter() - t0)
+    med = float(np.median(times[1:] if len(times) > 1 else times))
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": rows.shape[0] / med, "unit": "Gaussians/s", "cores": cores, "kind": "oracle",
+            "sample": f"{rows.shape[0]} seeded rows of the {w.n}-Gaussian workload, {steps} steps "
+                      f"(median step {med * 1e3:.1f} ms): FP32 cull + ids + synthetic grads + dense FP64 Adam"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is a design note only",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+
+    import gs_inputs as gi
+    from paper_2509_15645_amd import gsdp
+
+    torch.cuda.set_device(0)
+    tilt = tuple(float(x) for x in args.tilt.split(","))
+    w = gi.workload(args.workload, n=args.n, tilt_deg=tilt)
+    t_setup = time.perf_counter()
+    sc = gi.make_scene(w.n, seed=0, box=w.scene_box)
+    lg, la = gi.lr_columns()
+    total_steps = args.warmup + args.steps
+    model = gsdp.Model(sc.geo, sc.app, lg, la, max_steps=total_steps + 1, max_defer=args.max_defer,
+                       cull_mode=args.cull_mode, app_layout=args.layout)
+    n = w.n
+    cap = max(1, n // 4)
+    dev = torch.device("cuda")
+    ids = torch.zeros(cap, dtype=torch.int32, device=dev)
+    count = torch.zeros(1, dtype=torch.int32, device=dev)
+    out_g = torch.zeros((cap, 10), dtype=torch.float32, device=dev)
+    out_a = torch.zeros((cap, 49), dtype=torch.float32, device=dev)
+    full = torch.tensor([cap], dtype=torch.int32, device=dev)
+    pool = []
+    for p in range(args.pool):
+        gg = torch.empty((cap, 10), dtype=torch.float32, device=dev)
+        ga = torch.empty((cap, 49), dtype=torch.float32, device=dev)
+        gsdp.gs_synth_grad(1000 + p, 0, None, full, gg, 0)
+        gsdp.gs_synth_grad(1000 + p, 0, None, full, ga, 10)
+        pool.append((gg, ga))
+    cams = [gsdp.camera_struct(w.camera_for_step(t)) for t in range(1, total_steps + 1)]
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t_setup
+
+    stream = torch.cuda.current_stream()
+
+    def step(t, ev=None):
+        if ev is not None:
+            ev[0].record(stream)
+        gsdp.gs_cull(model, cams[t - 1], t, ids, count, stream=stream)
+        if ev is not None:
+            ev[1].record(stream)
+        gsdp.gs_gather(model, t, ids, count, out_g, out_a, stream=stream)
+        if ev is not None:
+            ev[2].record(stream)
+        gg, ga = pool[t % len(pool)]
+        gsdp.gs_adam_step_deferred(model, t, ids, count, gg, ga, stream=stream)
+        if ev is not None:
+            ev[3].record(stream)
+
+    for t in range(1, args.warmup + 1):
+        step(t)
+    torch.cuda.synchronize()
+    h0 = model.ws_header()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(args.warmup + 1 + k, evs[k])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    h1 = model.ws_header()
+    if h1["error"]:
+        raise RuntimeError(f"cull look-back reported an error flag: {h1}")
+
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    k_ms = np.array([[e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2]), e[2].elapsed_time(e[3])]
+                     for e in evs])
+    cull_ms, gather_ms, adam_ms = k_ms.mean(0)
+    vis_total = h1["vis_accum"] - h0["vis_accum"]
+    rest_total = h1["restored_accum"] - h0["restored_accum"]
+    M = vis_total / args.steps
+    R = rest_total / args.steps
+    f = M / n
+    # algorithmic bytes per launch
+    cull_bytes = 44.0 * n + 80.0 * R + 4.0 * M
+    gather_bytes = M * (4 + 4 + 236 + 472 + 236)       # ids, last, w, restore m/v, outputs
+    adam_bytes = M * (4 + 4 + 4 + 59 * 28)             # ids, last r/w, 7 x 4 B per column
+    kernels = {"cull": (cull_ms, cull_bytes), "gather": (gather_ms, gather_bytes), "adam": (adam_ms, adam_bytes)}
+    dom = max(kernels, key=lambda k: kernels[k][0])
+    dms, dbytes = kernels[dom]
+    achieved = dbytes / (dms * 1e-3) / 1e9
+    out = {
+        "metric": "train-step Gaussians/s (cull+gather+Adam), FP32 state",
+        "value": n / (ms_step * 1e-3),
+        "unit": "Gaussians/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": w.name, "n_gaussians": n, "cameras": len(w.cameras),
+                   "image": f"{w.cameras[0].width}x{w.cameras[0].height}", "oblique_tilt_deg": list(tilt),
+                   "visible_fraction": f, "visible_per_step": M, "restored_per_step": R,
+                   "state": "f32", "app_layout": args.layout, "max_defer": args.max_defer,
+                   "cull_mode": args.cull_mode},
+        "kernels_ms": {"cull": cull_ms, "gather": gather_ms, "adam": adam_ms},
+        "kernels_gbs": {k: v[1] / (v[0] * 1e-3) / 1e9 for k, v in kernels.items()},
+        "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+        "setup_s": setup_s,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, sc, args.cpu_sample, args.cpu_steps, lg, la)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,200 @@
+/*
+ * gsdp.h -- C ABI of the Gaussian-parameter hot path of GS-Scale-style 3D
+ * Gaussian Splatting training (arXiv 2509.15645), for AMD MI355X (gfx950).
+ *
+ * One training step t (1-based Adam step) is:
+ *   gs_cull               frustum/screen cull of every Gaussian's current geometry
+ *                         + ordered compaction into valid_ids            (Sec. 4.1, 4.2.1)
+ *   gs_gather             current (restored) parameters of valid_ids, read-only
+ *                         on the stored state                            (Sec. 4.3.3)
+ *   [caller's renderer forward/backward -> compact gradients]
+ *   gs_scatter_grad       compact -> dense gradient rows (optional)      (Sec. 4.1 step 4)
+ *   gs_adam_step_deferred deferred Adam on update_ids = valid_ids U saturated rows
+ *                                                           (Sec. 4.3, Eq. 2-3)
+ *   gs_adam_flush         catch up every skipped step (checkpoint, eval, densify)
+ *
+ * Conventions shared by every entry point
+ *   - Pointers inside gs_model and all array arguments are DEVICE pointers owned
+ *     by the caller; the library never allocates memory the caller can see.
+ *     `stream` is a hipStream_t (NULL = the null stream).  Calls are
+ *     asynchronous on `stream`, perform no host synchronisation and read
+ *     counts from device memory, so a step can be captured in a hipGraph.
+ *   - Return value: GS_OK (0) or a negative gs_status; nothing is launched
+ *     when an argument check fails.
+ *   - Row-major layouts.  Geometric group G: 10 FP32 columns per Gaussian
+ *     (mean xyz, log-scale xyz, quaternion wxyz).  Appearance group A: `dim`
+ *     columns (49 = opacity + 48 SH coefficients in 3DGS).  Each of w, m, v
+ *     has its own row stride (in elements) so interleaved or padded layouts
+ *     are allowed; G.w must be dense (stride 10) and 16-byte aligned.
+ *   - Step semantics: gs_cull(t) and gs_gather(t) see the parameters before
+ *     update t; gs_adam_step_deferred(t) applies update t; gs_adam_flush(t)
+ *     makes every row current as of after update t.  Successive updates of
+ *     one model use t = 1, 2, 3, ...
+ *   - last_step[i] is the last update step applied to Gaussian i (0 = never);
+ *     its defer count at step t is d = t - 1 - last_step[i] (the paper's
+ *     per-Gaussian counter).  Initialise it to 0 with m = v = 0.
+ */
+#ifndef GSDP_H
+#define GSDP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum gs_status {
+    GS_OK = 0,
+    GS_EINVAL = -1,        /* bad argument: null pointer, size, stride, alignment, step */
+    GS_EHIP = -2,          /* a HIP runtime call or launch failed (text: gs_last_hip_error) */
+    GS_EUNSUPPORTED = -3,  /* a mode/dtype combination that is not implemented */
+    GS_ESPACE = -4         /* workspace or LUT buffer too small for this call */
+} gs_status;
+
+typedef enum gs_dtype { GS_F32 = 0, GS_BF16 = 1, GS_FP8E4M3 = 2 } gs_dtype;
+
+/* Pinhole training camera.  p_cam = R p_world + t; OpenCV axes (x right,
+ * y down, z forward); pixel u = fx x/z + cx, v = fy y/z + cy. */
+typedef struct gs_camera {
+    float R[9];            /* world -> camera rotation, row-major */
+    float t[3];
+    float fx, fy, cx, cy;
+    int32_t width, height;
+    float near_plane, far_plane;
+} gs_camera;
+
+/* One parameter group (G or A) with its Adam moments. */
+typedef struct gs_group {
+    float *w;              /* [n][w_ld] parameters (FP32) */
+    void *m;               /* [n][m_ld] first moment, element type `state` */
+    void *v;               /* [n][v_ld] second moment */
+    int32_t dim;           /* columns: 10 for G, 1..54 for A */
+    int32_t w_ld, m_ld, v_ld;
+    int32_t state;         /* gs_dtype of m and v (GS_F32 in this version) */
+    int32_t pad_;
+    float lr[64];          /* learning rate of each column (dim entries used) */
+} gs_group;
+
+/* The optimisation problem: n Gaussians, both groups, the per-row step
+ * counter and the Adam constants. */
+typedef struct gs_model {
+    int64_t n;
+    gs_group geo;
+    gs_group app;
+    int32_t *last_step;    /* [n] */
+    const void *lut;       /* device tables written by gs_lut_build */
+    int32_t lut_max_steps; /* largest update step the tables cover */
+    int32_t max_defer;     /* 0 = unbounded; K > 0: a row deferred K steps is force-updated
+                              (the paper's saturating counter, MAX = 15) */
+    double beta1, beta2, eps;
+    int32_t cull_mode;     /* 0 = exact restoring cull, 1 = band cull (exact result,
+                              restores only rows near a decision boundary) */
+    int32_t reserved_[3];
+} gs_model;
+
+/* ---------------------------------------------------------------- tables */
+
+/* Bytes of the device tables for updates 1..max_steps (plus the flush table
+ * of step max_steps+1).  max_defer as in gs_model.  The deferred-update LUT
+ * (w_scale of Eq. 3, m_scale/v_scale of Eq. 2, Sec. 4.3.2 pseudocode) is
+ * stored for every step: max_defer = 0 needs (T+1)(T+2)/2 floats for
+ * T = max_steps, max_defer = K needs (T+1)(K+1). */
+int gs_lut_bytes(int32_t max_steps, int32_t max_defer, size_t *bytes);
+
+/* Compute the tables on the host in FP64 (powers by repeated multiplication,
+ * the LUT recurrence of the Sec. 4.3.2 pseudocode with unit learning rate), round them once to
+ * FP32 and copy them to `lut_dev` (a device buffer of at least
+ * gs_lut_bytes bytes).  Synchronous: returns after the copy completed. */
+int gs_lut_build(double beta1, double beta2, int32_t max_steps, int32_t max_defer,
+                 void *lut_dev, size_t bytes);
+
+/* Same tables written to host memory (for inspection and tests). */
+int gs_lut_build_host(double beta1, double beta2, int32_t max_steps, int32_t max_defer,
+                      void *lut_host, size_t bytes);
+
+/* ------------------------------------------------------------- workspace */
+
+/* Bytes of the scratch workspace that gs_cull and gs_adam_step_deferred
+ * share for one model: compaction tile states, work counters and the list of
+ * saturated rows.  The buffer must be zero-filled once before its first use
+ * and then left alone by the caller; one workspace serves one model and one
+ * stream at a time. */
+int gs_workspace_bytes(const gs_model *model, size_t *bytes);
+
+/* ------------------------------------------------------------------ path */
+
+/* Cull (Sec. 2.3 step 1 and Sec. 3.4: drop Gaussians outside the near/far
+ * planes and those whose projected 3-sigma footprint misses the image, from
+ * mean, scale and quaternion only) of every Gaussian's CURRENT geometry before
+ * update `step` -- stored G restored with Eq. 3 for deferred rows -- against
+ * `cam`, then ordered compaction: ids[0..M) = visible Gaussian ids ascending
+ * (valid_ids, Sec. 4.1).  *count_dev = M (device).  If M > capacity only the
+ * first `capacity` ids are written and *count_dev still holds M.  With
+ * max_defer > 0 the saturated invisible rows are listed in the workspace for
+ * gs_adam_step_deferred.  Deterministic: same inputs, same bits. */
+int gs_cull(const gs_model *model, const gs_camera *cam, int64_t step, uint32_t *ids,
+            uint32_t *count_dev, uint32_t capacity, void *ws, size_t ws_bytes, void *stream);
+
+/* Gather: out_geo[i][0..10) and out_app[i][0..dim) = current values of row
+ * ids[i] before update `step`, for i < min(*count_dev, capacity).  Deferred
+ * rows are restored with the w_scale LUT and their stored moments (Eq. 3);
+ * nothing in the model is written (read-only forwarding, Sec. 4.3.3).
+ * out_geo / out_app are dense [capacity][10] / [capacity][dim]; either may
+ * be NULL to skip that group. */
+int gs_gather(const gs_model *model, int64_t step, const uint32_t *ids, const uint32_t *count_dev,
+              uint32_t capacity, float *out_geo, float *out_app, void *stream);
+
+/* Scatter compact gradient rows into dense rows: g_dense[ids[i]][:] =
+ * g_compact[i][:] (accumulate != 0: +=) for i < min(*count_dev, capacity).
+ * ids must be unique (they are, from gs_cull), so no atomics are used.  Used
+ * to sum the gradients of split images before one update (Sec. 4.4). */
+int gs_scatter_grad(const uint32_t *ids, const uint32_t *count_dev, uint32_t capacity, int32_t dim,
+                    const float *g_compact, float *g_dense, int32_t accumulate, void *stream);
+
+/* Deferred Adam update `step` (Sec. 4.3.2 and its pseudocode) on update_ids = the
+ * visible rows ids[0..min(M,capacity)) plus, when max_defer > 0, the
+ * saturated rows the preceding gs_cull listed in `ws`.  Per row with defer
+ * count d and per column: restore w with the stored (old) moments (Eq. 3),
+ * m = b1^(d+1) m + (1-b1) g, v = b2^(d+1) v + (1-b2) g^2 (Eq. 2), then the
+ * standard Adam step with the new moments; last_step = step.
+ * Gradients: compact g_geo [capacity][10] / g_app [capacity][dim] aligned
+ * with ids (the scatter is fused), or, when g_geo/g_app are NULL, dense rows
+ * g_geo_dense[id] / g_app_dense[id] that are read and then cleared to zero.
+ * Saturated rows use g = 0. */
+int gs_adam_step_deferred(const gs_model *model, int64_t step, const uint32_t *ids,
+                          const uint32_t *count_dev, uint32_t capacity, const float *g_geo,
+                          const float *g_app, float *g_geo_dense, float *g_app_dense, void *ws,
+                          size_t ws_bytes, void *stream);
+
+/* Flush after update `step`: every row with last_step < step skipped
+ * delta = step - last_step zero-gradient steps; bring it current (w restored
+ * with the LUT of step+1 at delta, m *= b1^delta, v *= b2^delta, Eq. 2-3) and
+ * set last_step = step.  Required before saving, evaluating or densifying. */
+int gs_adam_flush(const gs_model *model, int64_t step, void *stream);
+
+/* --------------------------------------------------------------- harness */
+
+/* Synthetic gradients for benchmarks and tests (not part of the method):
+ * out[i][c] for i < min(*count_dev, capacity), c < dim, is the SplitMix64
+ * (Steele, Lea & Flood 2014) derived value for key = ids[i] (or i when ids is
+ * NULL) and global column col0 + c: s1 = at(seed, step), s2 = at(s1, key),
+ * h = at(s2, col) with at(s, k) = mix64(s + (k+1)*0x9E3779B97F4A7C15); the
+ * four 16-bit fields of h are summed, centred and scaled to std `sigma`. */
+int gs_synth_grad(uint64_t seed, int64_t step, const uint32_t *ids, const uint32_t *count_dev,
+                  uint32_t capacity, int32_t dim, int32_t col0, double sigma, float *out,
+                  void *stream);
+
+/* Number of compute units of the current device (0 when none). */
+int gs_device_cu_count(void);
+
+/* Human-readable name of a status code. */
+const char *gs_status_string(int status);
+
+/* Text of the last HIP error seen by this thread ("" if none). */
+const char *gs_last_hip_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GSDP_H */

@@ -1,0 +1,66 @@
+// Internal definitions shared by the host and device parts of libgsdp.
+#pragma once
+#include <stdint.h>
+
+namespace gsdp {
+
+// Device tables for the deferred update (all FP32, offsets in floats):
+//   W  : rows t = 1..T+1; row t holds w_scale for d = 0..min(t-1, K) (K = 0: unbounded)
+//   Mf : b1^(d+1),  Vf : b2^(d+1)   for d = 0..Dm
+//   SS : 1/(1-b1^t),  BC : sqrt(1-b2^t)   indexed by t = 0..T+1
+struct LutLayout {
+    int64_t T, K;
+    int64_t nW, nMV;
+    int64_t offM, offV, offSS, offBC, total;
+};
+
+inline LutLayout lut_layout(int64_t T, int64_t K)
+{
+    LutLayout L;
+    L.T = T;
+    L.K = K;
+    const int64_t rows = T + 1;
+    L.nW = K > 0 ? rows * (K + 1) : rows * (rows + 1) / 2;
+    L.nMV = (K > 0 ? K : T) + 1;
+    L.offM = L.nW;
+    L.offV = L.offM + L.nMV;
+    L.offSS = L.offV + L.nMV;
+    L.offBC = L.offSS + (T + 2);
+    L.total = L.offBC + (T + 2);
+    return L;
+}
+
+// Offset of W row t (t >= 1).
+inline int64_t lut_w_row(int64_t t, int64_t K) { return K > 0 ? (t - 1) * (K + 1) : t * (t - 1) / 2; }
+
+// Cull tiles: 256 threads x 4 rows.
+constexpr int kCullBlock = 256;
+constexpr int kCullIpt = 4;
+constexpr int kCullTile = kCullBlock * kCullIpt;
+
+// Workspace layout (bytes): header | tile states [2][tiles] (u64) | saturated ids [n] (u32)
+constexpr int64_t kWsHeader = 256;
+struct WsHeader {
+    uint32_t ticket;     // next cull tile to hand out
+    uint32_t done;       // blocks finished (last one resets the header)
+    uint32_t parity;     // which tile-state buffer the next cull uses
+    uint32_t error;      // bit 0: a look-back wait hit its bound
+    uint32_t sat_total;  // saturated rows listed by the last cull
+    uint32_t restored;   // rows restored by the running cull (diagnostic accumulator)
+    uint32_t restored_last;  // rows restored by the last completed cull
+    uint32_t pad_;
+    unsigned long long vis_accum;       // visible rows summed over all completed culls
+    unsigned long long restored_accum;  // restored rows summed over all completed culls
+};
+
+inline int64_t cull_tiles(int64_t n) { return (n + kCullTile - 1) / kCullTile; }
+inline int64_t ws_bytes_for(int64_t n, int32_t K)
+{
+    int64_t b = kWsHeader + 16 * cull_tiles(n);
+    if (K > 0) b += 4 * n;
+    return (b + 255) / 256 * 256;
+}
+
+int build_lut_host(double b1, double b2, int32_t T, int32_t K, float *out, int64_t nfloats);
+
+}  // namespace gsdp

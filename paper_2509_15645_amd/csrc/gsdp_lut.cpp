@@ -1,0 +1,57 @@
+// Host construction of the deferred-update tables (FP64 math, one FP32 rounding).
+//
+// The paper precomputes three lookup tables per update step (Sec. 4.3.2 and
+// its pseudocode): w_scale of Eq. 3 by the recurrence
+//     W[0] = 0,   W[d] = (b1/sqrt(b2)) W[d-1] + c(t-d),
+//     c(k) = b1 / ( sqrt(b2 / (1 - b2^k)) * (1 - b1^k) )      (unit learning rate)
+// and m_scale = b1^(d+1), v_scale = b2^(d+1) of Eq. 2.  Here the tables for
+// every step of a run are built once: powers come from repeated
+// multiplication (no pow), every operation is one IEEE binary64 operation, and
+// each entry is rounded once to FP32, so the values are fully determined by
+// (b1, b2, t, d).
+#include <cmath>
+#include <vector>
+
+#include "gsdp_internal.h"
+
+namespace gsdp {
+
+int build_lut_host(double b1, double b2, int32_t T, int32_t K, float *out, int64_t nfloats)
+{
+    const LutLayout L = lut_layout(T, K);
+    if (nfloats < L.total) return -1;
+    const int64_t kmax = T + 2 > L.nMV + 1 ? T + 2 : L.nMV + 1;
+    std::vector<double> P1(kmax + 1), P2(kmax + 1), Ck(T + 2, 0.0);
+    P1[0] = 1.0;
+    P2[0] = 1.0;
+    for (int64_t k = 1; k <= kmax; ++k) {
+        P1[k] = P1[k - 1] * b1;
+        P2[k] = P2[k - 1] * b2;
+    }
+    const double r = b1 / std::sqrt(b2);
+    for (int64_t k = 1; k <= T; ++k) Ck[k] = b1 / (std::sqrt(b2 / (1.0 - P2[k])) * (1.0 - P1[k]));
+
+    for (int64_t i = 0; i < L.total; ++i) out[i] = 0.0f;
+    for (int64_t t = 1; t <= T + 1; ++t) {
+        float *row = out + lut_w_row(t, K);
+        int64_t dm = t - 1;
+        if (K > 0 && dm > K) dm = K;
+        double W = 0.0;
+        row[0] = 0.0f;
+        for (int64_t d = 1; d <= dm; ++d) {
+            W = r * W + Ck[t - d];
+            row[d] = (float)W;
+        }
+    }
+    for (int64_t d = 0; d < L.nMV; ++d) {
+        out[L.offM + d] = (float)P1[d + 1];
+        out[L.offV + d] = (float)P2[d + 1];
+    }
+    for (int64_t t = 1; t <= T + 1; ++t) {
+        out[L.offSS + t] = (float)(1.0 / (1.0 - P1[t]));
+        out[L.offBC + t] = (float)std::sqrt(1.0 - P2[t]);
+    }
+    return 0;
+}
+
+}  // namespace gsdp

@@ -1,0 +1,275 @@
+"""Thin ctypes binding of libgsdp (argument marshalling only).
+
+Every step of the path runs in the HIP kernels of ``libgsdp.so``; this module
+only turns torch tensors into device pointers and the current HIP stream into
+a stream handle, and raises when the library reports an error.  If the
+library has not been built the import of this module fails: there is no
+fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libgsdp.so")
+
+GS_OK, GS_EINVAL, GS_EHIP, GS_EUNSUPPORTED, GS_ESPACE = 0, -1, -2, -3, -4
+GS_F32, GS_BF16, GS_FP8E4M3 = 0, 1, 2
+
+# exported C symbols (kept in sync with include/gsdp.h)
+SYMBOLS = ("gs_lut_bytes", "gs_lut_build", "gs_lut_build_host", "gs_workspace_bytes", "gs_cull",
+           "gs_gather", "gs_scatter_grad", "gs_adam_step_deferred", "gs_adam_flush", "gs_synth_grad",
+           "gs_device_cu_count", "gs_status_string", "gs_last_hip_error")
+
+
+class GsCamera(C.Structure):
+    _fields_ = [("R", C.c_float * 9), ("t", C.c_float * 3), ("fx", C.c_float), ("fy", C.c_float),
+                ("cx", C.c_float), ("cy", C.c_float), ("width", C.c_int32), ("height", C.c_int32),
+                ("near_plane", C.c_float), ("far_plane", C.c_float)]
+
+
+class GsGroup(C.Structure):
+    _fields_ = [("w", C.c_void_p), ("m", C.c_void_p), ("v", C.c_void_p), ("dim", C.c_int32),
+                ("w_ld", C.c_int32), ("m_ld", C.c_int32), ("v_ld", C.c_int32), ("state", C.c_int32),
+                ("pad_", C.c_int32), ("lr", C.c_float * 64)]
+
+
+class GsModel(C.Structure):
+    _fields_ = [("n", C.c_int64), ("geo", GsGroup), ("app", GsGroup), ("last_step", C.c_void_p),
+                ("lut", C.c_void_p), ("lut_max_steps", C.c_int32), ("max_defer", C.c_int32),
+                ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double),
+                ("cull_mode", C.c_int32), ("reserved_", C.c_int32 * 3)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() (hipcc, gfx950)")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64, u32, u64, f64, sz = (C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_uint64,
+                                       C.c_double, C.c_size_t)
+    P = C.POINTER
+    sig = {
+        "gs_lut_bytes": (C.c_int, [i32, i32, P(sz)]),
+        "gs_lut_build": (C.c_int, [f64, f64, i32, i32, vp, sz]),
+        "gs_lut_build_host": (C.c_int, [f64, f64, i32, i32, vp, sz]),
+        "gs_workspace_bytes": (C.c_int, [P(GsModel), P(sz)]),
+        "gs_cull": (C.c_int, [P(GsModel), P(GsCamera), i64, vp, vp, u32, vp, sz, vp]),
+        "gs_gather": (C.c_int, [P(GsModel), i64, vp, vp, u32, vp, vp, vp]),
+        "gs_scatter_grad": (C.c_int, [vp, vp, u32, i32, vp, vp, i32, vp]),
+        "gs_adam_step_deferred": (C.c_int, [P(GsModel), i64, vp, vp, u32, vp, vp, vp, vp, vp, sz, vp]),
+        "gs_adam_flush": (C.c_int, [P(GsModel), i64, vp]),
+        "gs_synth_grad": (C.c_int, [u64, i64, vp, vp, u32, i32, i32, f64, vp, vp]),
+        "gs_device_cu_count": (C.c_int, []),
+        "gs_status_string": (C.c_char_p, [C.c_int]),
+        "gs_last_hip_error": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    return L
+
+
+lib = _load()
+
+
+class GsError(RuntimeError):
+    pass
+
+
+def _check(rc: int, what: str):
+    if rc != GS_OK:
+        msg = lib.gs_status_string(rc).decode()
+        if rc == GS_EHIP:
+            msg += ": " + lib.gs_last_hip_error().decode()
+        raise GsError(f"{what}: {msg}")
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def camera_struct(cam) -> GsCamera:
+    """gs_camera from an object with R, t, fx, fy, cx, cy, width, height, near, far."""
+    c = GsCamera()
+    R = np.asarray(cam.R, np.float32).ravel()
+    t = np.asarray(cam.t, np.float32).ravel()
+    for i in range(9):
+        c.R[i] = float(R[i])
+    for i in range(3):
+        c.t[i] = float(t[i])
+    c.fx, c.fy, c.cx, c.cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
+    c.width, c.height = int(cam.width), int(cam.height)
+    c.near_plane, c.far_plane = float(cam.near), float(cam.far)
+    return c
+
+
+# ---------------------------------------------------------------------------
+# tables and workspace
+# ---------------------------------------------------------------------------
+def gs_lut_bytes(max_steps: int, max_defer: int) -> int:
+    b = C.c_size_t()
+    _check(lib.gs_lut_bytes(max_steps, max_defer, C.byref(b)), "gs_lut_bytes")
+    return b.value
+
+
+def gs_lut_build(beta1, beta2, max_steps, max_defer, lut: torch.Tensor):
+    _check(lib.gs_lut_build(beta1, beta2, max_steps, max_defer, _ptr(lut), lut.numel() * lut.element_size()),
+           "gs_lut_build")
+
+
+def gs_lut_build_host(beta1, beta2, max_steps, max_defer) -> np.ndarray:
+    nbytes = gs_lut_bytes(max_steps, max_defer)
+    out = np.zeros(nbytes // 4, np.float32)
+    _check(lib.gs_lut_build_host(beta1, beta2, max_steps, max_defer, out.ctypes.data, nbytes),
+           "gs_lut_build_host")
+    return out
+
+
+def gs_workspace_bytes(model) -> int:
+    b = C.c_size_t()
+    _check(lib.gs_workspace_bytes(C.byref(model.c), C.byref(b)), "gs_workspace_bytes")
+    return b.value
+
+
+# ---------------------------------------------------------------------------
+# model state (device memory owned by torch)
+# ---------------------------------------------------------------------------
+class Model:
+    """Device-resident parameters, Adam moments, per-row last step, tables and
+    workspace of one set of Gaussians, plus the gs_model struct describing them.
+
+    app_layout "separate": w, m, v of A are three [n, dim] tensors.
+               "interleaved": one [n, row] tensor per Gaussian holding w | m | v
+               (row = 3*dim padded to a multiple of 32 floats), so the random
+               row accesses of gather and Adam touch one contiguous span.
+    """
+
+    def __init__(self, geo, app, lr_geo, lr_app, *, beta1=0.9, beta2=0.999, eps=1e-15, max_defer=0,
+                 max_steps=1000, cull_mode=0, app_layout="separate", device=None):
+        device = device or torch.device("cuda")
+        geo = torch.as_tensor(geo, dtype=torch.float32)
+        app = torch.as_tensor(app, dtype=torch.float32)
+        n, adim = geo.shape[0], app.shape[1]
+        assert geo.shape == (n, 10) and app.shape[0] == n
+        self.n, self.adim, self.device = n, adim, device
+        self.geo_w = geo.to(device).contiguous()
+        self.geo_m = torch.zeros((n, 10), dtype=torch.float32, device=device)
+        self.geo_v = torch.zeros((n, 10), dtype=torch.float32, device=device)
+        self.app_layout = app_layout
+        if app_layout == "separate":
+            self.app_w = app.to(device).contiguous()
+            self.app_m = torch.zeros((n, adim), dtype=torch.float32, device=device)
+            self.app_v = torch.zeros((n, adim), dtype=torch.float32, device=device)
+            ld = (adim, adim, adim)
+        elif app_layout == "interleaved":
+            row = (3 * adim + 31) // 32 * 32
+            self.app_state = torch.zeros((n, row), dtype=torch.float32, device=device)
+            self.app_w = self.app_state[:, 0:adim]
+            self.app_m = self.app_state[:, adim:2 * adim]
+            self.app_v = self.app_state[:, 2 * adim:3 * adim]
+            self.app_w.copy_(app.to(device))
+            ld = (row, row, row)
+        else:
+            raise ValueError(app_layout)
+        self.last_step = torch.zeros(n, dtype=torch.int32, device=device)
+        self.max_steps, self.max_defer = int(max_steps), int(max_defer)
+        self.lut = torch.empty(gs_lut_bytes(self.max_steps, self.max_defer) // 4, dtype=torch.float32,
+                               device=device)
+        gs_lut_build(beta1, beta2, self.max_steps, self.max_defer, self.lut)
+        self.lr_geo = np.asarray(lr_geo, np.float32)
+        self.lr_app = np.asarray(lr_app, np.float32)
+
+        c = GsModel()
+        c.n = n
+        for grp, w, m, v, lds, lr, dim in ((c.geo, self.geo_w, self.geo_m, self.geo_v, (10, 10, 10),
+                                            self.lr_geo, 10),
+                                           (c.app, self.app_w, self.app_m, self.app_v, ld, self.lr_app, adim)):
+            grp.w, grp.m, grp.v = w.data_ptr(), m.data_ptr(), v.data_ptr()
+            grp.dim = dim
+            grp.w_ld, grp.m_ld, grp.v_ld = lds
+            grp.state = GS_F32
+            for k in range(dim):
+                grp.lr[k] = float(lr[k])
+        c.last_step = self.last_step.data_ptr()
+        c.lut = self.lut.data_ptr()
+        c.lut_max_steps = self.max_steps
+        c.max_defer = self.max_defer
+        c.beta1, c.beta2, c.eps = float(beta1), float(beta2), float(eps)
+        c.cull_mode = int(cull_mode)
+        self.c = c
+        self.ws = torch.zeros(gs_workspace_bytes(self) // 4, dtype=torch.int32, device=device)
+
+    @property
+    def ws_bytes(self) -> int:
+        return self.ws.numel() * 4
+
+    def ws_header(self) -> dict:
+        h = self.ws[:12].cpu().numpy().view(np.uint32)
+        q = h[8:12].view(np.uint64)
+        return {"ticket": int(h[0]), "done": int(h[1]), "parity": int(h[2]), "error": int(h[3]),
+                "sat_total": int(h[4]), "restored_last": int(h[6]), "vis_accum": int(q[0]),
+                "restored_accum": int(q[1])}
+
+    def state(self):
+        """Host copies: dict of geo/app w, m, v (float32) and last_step."""
+        out = {}
+        for name in ("geo_w", "geo_m", "geo_v", "app_w", "app_m", "app_v"):
+            out[name] = getattr(self, name).contiguous().cpu().numpy()
+        out["last_step"] = self.last_step.cpu().numpy()
+        return out
+
+
+# ---------------------------------------------------------------------------
+# the path (same names as the C ABI)
+# ---------------------------------------------------------------------------
+def gs_cull(model: Model, cam, step: int, ids: torch.Tensor, count: torch.Tensor, capacity=None, stream=None):
+    cap = ids.numel() if capacity is None else int(capacity)
+    camc = cam if isinstance(cam, GsCamera) else camera_struct(cam)
+    _check(lib.gs_cull(C.byref(model.c), C.byref(camc), int(step), _ptr(ids), _ptr(count), cap,
+                       _ptr(model.ws), model.ws_bytes, _stream(stream)), "gs_cull")
+
+
+def gs_gather(model: Model, step: int, ids, count, out_geo, out_app, capacity=None, stream=None):
+    cap = ids.numel() if capacity is None else int(capacity)
+    _check(lib.gs_gather(C.byref(model.c), int(step), _ptr(ids), _ptr(count), cap, _ptr(out_geo),
+                         _ptr(out_app), _stream(stream)), "gs_gather")
+
+
+def gs_scatter_grad(ids, count, g_compact, g_dense, accumulate=False, capacity=None, stream=None):
+    cap = ids.numel() if capacity is None else int(capacity)
+    dim = g_compact.shape[1]
+    _check(lib.gs_scatter_grad(_ptr(ids), _ptr(count), cap, dim, _ptr(g_compact), _ptr(g_dense),
+                               1 if accumulate else 0, _stream(stream)), "gs_scatter_grad")
+
+
+def gs_adam_step_deferred(model: Model, step: int, ids, count, g_geo=None, g_app=None, g_geo_dense=None,
+                          g_app_dense=None, capacity=None, stream=None):
+    cap = ids.numel() if capacity is None else int(capacity)
+    _check(lib.gs_adam_step_deferred(C.byref(model.c), int(step), _ptr(ids), _ptr(count), cap, _ptr(g_geo),
+                                     _ptr(g_app), _ptr(g_geo_dense), _ptr(g_app_dense), _ptr(model.ws),
+                                     model.ws_bytes, _stream(stream)), "gs_adam_step_deferred")
+
+
+def gs_adam_flush(model: Model, step: int, stream=None):
+    _check(lib.gs_adam_flush(C.byref(model.c), int(step), _stream(stream)), "gs_adam_flush")
+
+
+def gs_synth_grad(seed: int, step: int, ids, count, out, col0: int, sigma=1e-3, capacity=None, stream=None):
+    cap = out.shape[0] if capacity is None else int(capacity)
+    _check(lib.gs_synth_grad(int(seed), int(step), _ptr(ids), _ptr(count), cap, out.shape[1], int(col0),
+                             float(sigma), _ptr(out), _stream(stream)), "gs_synth_grad")
+
+
+def gs_device_cu_count() -> int:
+    return int(lib.gs_device_cu_count())

@@ -1,0 +1,92 @@
+"""The C ABI without a GPU: the library loads, exports every declared symbol,
+rejects bad arguments before touching the device, and its host-built tables
+equal the oracle's independently computed FP32 tables bit for bit."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gsdp.h")
+
+
+@pytest.fixture(scope="module")
+def gsdp():
+    from paper_2509_15645_amd import build
+    if not os.path.exists(build.LIB):
+        build.build(force=True)
+    from paper_2509_15645_amd import gsdp as g
+    return g
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gs_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(gsdp):
+    names = declared_functions()
+    assert len(names) >= 12
+    lib = C.CDLL(gsdp.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(gsdp.SYMBOLS) == names
+
+
+def test_struct_layouts(gsdp):
+    assert C.sizeof(gsdp.GsCamera) == 80
+    assert C.sizeof(gsdp.GsGroup) == 3 * 8 + 6 * 4 + 64 * 4
+    assert gsdp.GsModel.lut_max_steps.offset == 8 + 2 * C.sizeof(gsdp.GsGroup) + 16
+
+
+def test_status_strings(gsdp):
+    for code in (0, -1, -2, -3, -4):
+        assert gsdp.lib.gs_status_string(code).decode().startswith("GS_")
+
+
+def test_argument_checks_need_no_device(gsdp):
+    L = gsdp.lib
+    b = C.c_size_t()
+    assert L.gs_lut_bytes(0, 0, C.byref(b)) == gsdp.GS_EINVAL
+    assert L.gs_lut_bytes(10, -1, C.byref(b)) == gsdp.GS_EINVAL
+    assert L.gs_lut_bytes(10, 0, C.byref(b)) == 0 and b.value > 0
+    assert L.gs_cull(None, None, 1, None, None, 0, None, 0, None) == gsdp.GS_EINVAL
+    m = gsdp.GsModel()
+    m.n = 10
+    assert L.gs_cull(C.byref(m), None, 1, None, None, 0, None, 0, None) == gsdp.GS_EINVAL
+    assert L.gs_adam_flush(C.byref(m), 1, None) == gsdp.GS_EINVAL
+    assert L.gs_workspace_bytes(None, C.byref(b)) == gsdp.GS_EINVAL
+    m.max_defer = 0
+    assert L.gs_workspace_bytes(C.byref(m), C.byref(b)) == 0 and b.value >= 256
+    # a host buffer that is too small is reported, not overrun
+    small = np.zeros(4, np.float32)
+    assert L.gs_lut_build_host(0.9, 0.999, 10, 0, small.ctypes.data, 16) == gsdp.GS_ESPACE
+    assert L.gs_lut_build_host(1.5, 0.999, 10, 0, small.ctypes.data, 16) == gsdp.GS_EINVAL
+
+
+@pytest.mark.parametrize("max_defer", [0, 15])
+def test_host_tables_equal_oracle_tables_bitwise(gsdp, max_defer):
+    T = 300
+    lut = gsdp.gs_lut_build_host(0.9, 0.999, T, max_defer)
+    K = max_defer
+    rows = T + 1
+    nW = rows * (K + 1) if K else rows * (rows + 1) // 2
+    nMV = (K if K else T) + 1
+    offM, offV = nW, nW + nMV
+    offSS = offV + nMV
+    offBC = offSS + T + 2
+    assert lut.shape[0] == offBC + T + 2
+    for t in [1, 2, 3, 16, 17, 100, T, T + 1]:
+        row = (t - 1) * (K + 1) if K else t * (t - 1) // 2
+        dmax = min(t - 1, K) if K else t - 1
+        Wf, Mf, Vf, ss, bc = orc.lut_spec(0.9, 0.999, t, dmax)
+        assert np.array_equal(lut[row:row + dmax + 1].view(np.uint32), Wf.view(np.uint32)), t
+        assert np.array_equal(lut[offM:offM + dmax + 1].view(np.uint32), Mf.view(np.uint32))
+        assert np.array_equal(lut[offV:offV + dmax + 1].view(np.uint32), Vf.view(np.uint32))
+        assert lut[offSS + t].view(np.uint32) == np.float32(ss).view(np.uint32)
+        assert lut[offBC + t].view(np.uint32) == np.float32(bc).view(np.uint32)

@@ -1,0 +1,286 @@
+"""GPU parity of the HIP path against the CPU oracle (run with -m gpu).
+
+Cull + compaction: visible-id lists bit-exact against the oracle's FP32 cull
+of the same FP32 current geometry (the oracle's own FP32 state model O3).
+Gather / Adam / flush: bit-exact against O3, and within the FP32 tolerance of
+the dense FP64 Adam definition (error per element |w - w64| / max(|w64|, tau),
+tau = the group's initial scale; bound 1e-6 for the 20-step workload).
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import gs_inputs as gi
+from oracle import oracle as orc
+
+pytestmark = pytest.mark.gpu
+
+TAU_GEO = np.array([1, 1, 1, .5, .5, .5, .5, .5, .5, .5])
+TAU_APP = np.array([1.0] + [0.1] * 48)
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def g():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2509_15645_amd import gsdp
+    return gsdp
+
+
+def u32(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+def bits(a):
+    return np.ascontiguousarray(a, np.float32).view(np.uint32)
+
+
+def run_cull(g, model, cam, t, cap=None, fill=-1):
+    cap = max(model.n, 1) if cap is None else cap
+    ids = torch.full((max(cap, 1),), fill, dtype=torch.int32, device="cuda")
+    count = torch.zeros(1, dtype=torch.int32, device="cuda")
+    g.gs_cull(model, cam, t, ids, count, capacity=cap)
+    torch.cuda.synchronize()
+    m = int(count.item())
+    return ids, count, m
+
+
+def model_for(g, geo, app=None, **kw):
+    n = geo.shape[0]
+    if app is None:
+        app = np.zeros((n, 49), np.float32)
+    lg, la = gi.lr_columns()
+    kw.setdefault("max_steps", 64)
+    return g.Model(geo, app, lg, la, **kw)
+
+
+# ---------------------------------------------------------------- cull
+@pytest.mark.parametrize("n", [0, 1, 5, 1023, 1024, 1025, 3007, 100_000])
+def test_cull_step1_matches_oracle(g, n):
+    say(f"[cull] n={n}")
+    sc = gi.make_scene(n, seed=n % 7)
+    model = model_for(g, sc.geo, sc.app)
+    for cam in gi.orbit_cameras(4, seed=n % 5):
+        ids, count, m = run_cull(g, model, cam, 1)
+        ref = orc.compact(orc.cull(sc.geo, cam))
+        assert m == ref.shape[0]
+        assert np.array_equal(u32(ids[:m]), ref)
+    assert model.ws_header()["error"] == 0
+
+
+def test_cull_aerial_full_scale_step1(g):
+    w = gi.workload("aerial4m")
+    say(f"[cull aerial] n={w.n}")
+    sc = gi.make_scene(w.n, seed=0, box=w.scene_box)
+    model = model_for(g, sc.geo, sc.app)
+    fr = []
+    for t in (1, 2, 3):
+        cam = w.camera_for_step(t)
+        ids, count, m = run_cull(g, model, cam, 1)
+        ref = orc.compact(orc.cull(sc.geo, cam))
+        assert m == ref.shape[0]
+        assert np.array_equal(u32(ids[:m]), ref)
+        fr.append(m / w.n)
+    say(f"[cull aerial] visible fractions {fr}")
+
+
+def _boundary_scene(cam, n, rng):
+    """Gaussians whose centres sit on and around the image border and the
+    near/far planes, plus NaN, Inf and behind-camera rows."""
+    u = rng.choice([-8.0, -3.0, -1.0, -0.5, 0.0, 0.25, 1.0, cam.width - 1.0, cam.width - 0.5, cam.width,
+                    cam.width + 0.5, cam.width + 3.0], n) + rng.normal(0, 0.3, n)
+    v = rng.uniform(-10, cam.height + 10, n)
+    swap = rng.random(n) < 0.5
+    u2 = np.where(swap, rng.uniform(-10, cam.width + 10, n), u)
+    v2 = np.where(swap, rng.choice([-4.0, -1.0, 0.0, cam.height - 0.5, cam.height, cam.height + 2.0], n)
+                  + rng.normal(0, 0.3, n), v)
+    z = rng.choice([cam.near, cam.near * 1.0000001, 1.0, 20.0, 200.0, cam.far * 0.9999999, cam.far], n)
+    z = z * np.where(rng.random(n) < 0.05, -1, 1)
+    xc = (u2 - cam.cx) / cam.fx * z
+    yc = (v2 - cam.cy) / cam.fy * z
+    pc = np.stack([xc, yc, z], 1)
+    world = (pc - cam.t.astype(np.float64)) @ cam.R.astype(np.float64)
+    geo = np.zeros((n, 10), np.float32)
+    geo[:, :3] = world
+    geo[:, 3:6] = rng.normal(-3, 1.5, (n, 3))
+    q = rng.normal(size=(n, 4))
+    geo[:, 6:10] = q / np.linalg.norm(q, axis=1, keepdims=True)
+    bad = rng.choice(n, n // 50, replace=False)
+    geo[bad, rng.integers(0, 10, bad.shape[0])] = rng.choice([np.nan, np.inf, -np.inf], bad.shape[0])
+    geo[rng.choice(n, 5, replace=False), 6:10] = 0.0        # zero quaternion
+    geo[rng.choice(n, 5, replace=False), 3:6] = 200.0       # huge scale (exp clamp)
+    geo[rng.choice(n, 5, replace=False), 3:6] = -200.0      # tiny scale
+    return geo
+
+
+def test_cull_boundary_and_degenerate_rows(g):
+    rng = np.random.default_rng(42)
+    for seed, cam in enumerate(gi.orbit_cameras(3, seed=3)):
+        geo = _boundary_scene(cam, 50_000, rng)
+        model = model_for(g, geo)
+        ids, count, m = run_cull(g, model, cam, 1)
+        keep = orc.cull(geo, cam)
+        ref = orc.compact(keep)
+        say(f"[cull boundary] cam {seed}: M={m} ref={ref.shape[0]}")
+        assert m == ref.shape[0]
+        assert np.array_equal(u32(ids[:m]), ref)
+
+
+def test_cull_capacity_overflow_and_determinism(g):
+    sc = gi.make_scene(30_000, seed=9)
+    model = model_for(g, sc.geo, sc.app)
+    cam = gi.orbit_cameras(1, seed=9)[0]
+    ref = orc.compact(orc.cull(sc.geo, cam))
+    cap = ref.shape[0] // 2
+    ids, count, m = run_cull(g, model, cam, 1, cap=cap + 100, fill=-7)
+    assert m == ref.shape[0]
+    ids2, _, m2 = run_cull(g, model, cam, 1, cap=cap)
+    assert m2 == ref.shape[0]
+    assert np.array_equal(u32(ids2), ref[:cap])
+    # capacity 0 still counts
+    _, _, m0 = run_cull(g, model, cam, 1, cap=0)
+    assert m0 == ref.shape[0]
+    a, _, _ = run_cull(g, model, cam, 1)
+    b, _, _ = run_cull(g, model, cam, 1)
+    assert torch.equal(a, b)
+
+
+# ---------------------------------------------------------------- harness pieces
+def test_synth_grad_matches_host_generator(g):
+    rng = np.random.default_rng(0)
+    ids = np.sort(rng.choice(1 << 22, 5000, replace=False)).astype(np.uint32)
+    dids = torch.from_numpy(ids.view(np.int32)).cuda()
+    count = torch.tensor([ids.shape[0]], dtype=torch.int32, device="cuda")
+    for col0, dim in ((0, 10), (10, 49)):
+        out = torch.zeros((ids.shape[0], dim), dtype=torch.float32, device="cuda")
+        g.gs_synth_grad(7, 3, dids, count, out, col0)
+        ref = gi.hash_grads(7, 3, ids, np.arange(col0, col0 + dim))
+        assert np.array_equal(bits(out.cpu().numpy()), bits(ref))
+
+
+def test_scatter_grad(g):
+    rng = np.random.default_rng(1)
+    n, m, dim = 10_000, 3_000, 49
+    ids = np.sort(rng.choice(n, m, replace=False)).astype(np.int32)
+    gc = rng.normal(size=(m, dim)).astype(np.float32)
+    dids = torch.from_numpy(ids).cuda()
+    count = torch.tensor([m], dtype=torch.int32, device="cuda")
+    dense = torch.zeros((n, dim), dtype=torch.float32, device="cuda")
+    dgc = torch.from_numpy(gc).cuda()
+    g.gs_scatter_grad(dids, count, dgc, dense)
+    ref = np.zeros((n, dim), np.float32)
+    ref[ids] = gc
+    assert np.array_equal(dense.cpu().numpy(), ref)
+    g.gs_scatter_grad(dids, count, dgc, dense, accumulate=True)
+    assert np.array_equal(dense.cpu().numpy(), ref + ref)
+
+
+# ---------------------------------------------------------------- full path
+def _compare_state(model, o3, tag):
+    st = model.state()
+    for k, name in ((0, "geo"), (1, "app")):
+        for part, ref in (("w", o3.w[k]), ("m", o3.m[k]), ("v", o3.v[k])):
+            got = st[f"{name}_{part}"]
+            if not np.array_equal(bits(got), bits(ref)):
+                bad = np.nonzero(bits(got) != bits(ref))
+                raise AssertionError(f"{tag}: {name}_{part} differs at {bad[0][:5]},{bad[1][:5]}")
+
+
+@pytest.mark.parametrize("max_defer,layout,grad_mode", [
+    (0, "separate", "compact"),
+    (15, "separate", "compact"),
+    (0, "interleaved", "dense"),
+    (15, "interleaved", "dense"),
+])
+def test_small_workload_path_vs_oracle(g, max_defer, layout, grad_mode):
+    """100k Gaussians, 10 orbit cameras, 20 steps: every step's visible ids and
+    gathered rows bit-exact vs O3; state bit-exact after steps and after the
+    flush; flushed parameters within 1e-6 of dense FP64 Adam."""
+    w = gi.workload("small")
+    sc = gi.make_scene(w.n, seed=0, box=w.scene_box)
+    lg, la = gi.lr_columns()
+    model = g.Model(sc.geo, sc.app, lg, la, max_steps=32, max_defer=max_defer, app_layout=layout)
+    o3 = orc.DeferredF32(sc.geo, sc.app, lg, la, max_defer=max_defer)
+    dense = orc.DenseAdamF64(sc.geo, sc.app, lg, la)
+    n = w.n
+    out_g = torch.zeros((n, 10), dtype=torch.float32, device="cuda")
+    out_a = torch.zeros((n, 49), dtype=torch.float32, device="cuda")
+    gd_g = torch.zeros((n, 10), dtype=torch.float32, device="cuda")
+    gd_a = torch.zeros((n, 49), dtype=torch.float32, device="cuda")
+    state0 = None
+    for t in range(1, w.steps + 1):
+        cam = w.camera_for_step(t)
+        ids, count, m = run_cull(g, model, cam, t)
+        valid = o3.cull_current(t, cam)
+        assert m == valid.shape[0], f"step {t}"
+        assert np.array_equal(u32(ids[:m]), valid), f"step {t}"
+        if t == 3:
+            state0 = model.state()
+        g.gs_gather(model, t, ids, count, out_g, out_a)
+        torch.cuda.synchronize()
+        cg, ca = o3.current(t, valid)
+        assert np.array_equal(bits(out_g[:m].cpu().numpy()), bits(cg)), f"gather geo step {t}"
+        assert np.array_equal(bits(out_a[:m].cpu().numpy()), bits(ca)), f"gather app step {t}"
+        if t == 3:
+            st = model.state()       # gather is read-only on the stored state
+            for key in st:
+                assert np.array_equal(st[key], state0[key]), key
+        gg, ga = gi.step_grads(0, t, valid)
+        dgg, dga = torch.from_numpy(gg).cuda(), torch.from_numpy(ga).cuda()
+        if grad_mode == "compact":
+            g.gs_adam_step_deferred(model, t, ids, count, dgg, dga)
+        else:
+            g.gs_scatter_grad(ids, count, dgg, gd_g)
+            g.gs_scatter_grad(ids, count, dga, gd_a)
+            g.gs_adam_step_deferred(model, t, ids, count, g_geo_dense=gd_g, g_app_dense=gd_a)
+        o3.step(t, valid, gg, ga)
+        dense.step(t, valid, gg, ga)
+        if t % 5 == 0:
+            _compare_state(model, o3, f"step {t}")
+            assert np.array_equal(model.last_step.cpu().numpy(), o3.last_step(t))
+        say(f"[path K={max_defer} {layout} {grad_mode}] step {t}: M={m}")
+    if grad_mode == "dense":
+        assert not gd_g.any() and not gd_a.any()
+    g.gs_adam_flush(model, w.steps)
+    o3.flush(w.steps)
+    _compare_state(model, o3, "after flush")
+    assert np.all(model.last_step.cpu().numpy() == w.steps)
+    st = model.state()
+    e_geo = np.abs(st["geo_w"] - dense.w[0]) / np.maximum(np.abs(dense.w[0]), TAU_GEO)
+    e_app = np.abs(st["app_w"] - dense.w[1]) / np.maximum(np.abs(dense.w[1]), TAU_APP)
+    say(f"[path] vs dense FP64: geo max {e_geo.max():.3e} mean {e_geo.mean():.3e}; "
+        f"app max {e_app.max():.3e} mean {e_app.mean():.3e}")
+    assert e_geo.max() <= 1e-6 and e_app.max() <= 1e-6
+    assert model.ws_header()["error"] == 0
+
+
+def test_aerial_full_scale_path_vs_oracle(g):
+    """4M Gaussians, aerial cameras, 6 steps with device-generated gradients:
+    full visible-id lists and the full state bit-exact vs O3 on the host."""
+    w = gi.workload("aerial4m")
+    steps = 6
+    sc = gi.make_scene(w.n, seed=0, box=w.scene_box)
+    lg, la = gi.lr_columns()
+    model = g.Model(sc.geo, sc.app, lg, la, max_steps=w.steps)
+    o3 = orc.DeferredF32(sc.geo, sc.app, lg, la)
+    n = w.n
+    cap = n // 4
+    gbuf_g = torch.zeros((cap, 10), dtype=torch.float32, device="cuda")
+    gbuf_a = torch.zeros((cap, 49), dtype=torch.float32, device="cuda")
+    for t in range(1, steps + 1):
+        cam = w.camera_for_step(t)
+        ids, count, m = run_cull(g, model, cam, t, cap=cap)
+        valid = o3.cull_current(t, cam)
+        assert m == valid.shape[0], f"step {t}"
+        assert np.array_equal(u32(ids[:m]), valid), f"step {t}"
+        g.gs_synth_grad(0, t, ids, count, gbuf_g, 0)
+        g.gs_synth_grad(0, t, ids, count, gbuf_a, 10)
+        g.gs_adam_step_deferred(model, t, ids, count, gbuf_g, gbuf_a)
+        o3.step(t, valid, *gi.step_grads(0, t, valid))
+        say(f"[aerial] step {t}: M={m} ({m / n:.4f})")
+    _compare_state(model, o3, f"aerial after {steps} steps")
