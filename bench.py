@@ -37,7 +37,7 @@ def parse():
     p.add_argument("--n", type=int, default=None, help="override the Gaussian count")
     p.add_argument("--layout", default="interleaved", choices=["separate", "interleaved"])
     p.add_argument("--max-defer", type=int, default=0)
-    p.add_argument("--cull-mode", type=int, default=0)
+    p.add_argument("--cull-mode", type=int, default=1)
     p.add_argument("--tilt", default="20,45", help="oblique tilt range in degrees")
     p.add_argument("--pool", type=int, default=4)
     p.add_argument("--no-cpu-baseline", action="store_true")

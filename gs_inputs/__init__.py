@@ -6,7 +6,7 @@ no optimizer math).  Both the CPU oracle and the HIP path consume what it
 produces; neither imports the other.
 
 Workload shapes follow the paper's setting: 59 FP32 parameters per Gaussian
-(Sec. 2.2: mean 3, scale 3, quaternion 4, opacity 1, SH degree 3 = 48), large
+(Sec. 2.3: mean 3, scale 3, quaternion 4, opacity 1, SH degree 3 = 48), large
 aerial scenes rendered at 1152x864 (Table 2, Mill-19), 4M-40M Gaussians
 (Sec. 5.6).  The paper's datasets are not available; these generators stand in
 for them.

@@ -71,7 +71,7 @@ typedef struct gs_group {
     void *v;               /* [n][v_ld] second moment */
     int32_t dim;           /* columns: 10 for G, 1..54 for A */
     int32_t w_ld, m_ld, v_ld;
-    int32_t state;         /* gs_dtype of m and v (GS_F32 in this version) */
+    int32_t state;         /* gs_dtype of m and v: GS_F32 or GS_BF16 (stochastic rounding) */
     int32_t pad_;
     float lr[64];          /* learning rate of each column (dim entries used) */
 } gs_group;
@@ -90,7 +90,11 @@ typedef struct gs_model {
     double beta1, beta2, eps;
     int32_t cull_mode;     /* 0 = exact restoring cull, 1 = band cull (exact result,
                               restores only rows near a decision boundary) */
-    int32_t reserved_[3];
+    int32_t geo_mode;      /* 0 = geometry deferred like the rest (default); 1 = geometric
+                              columns updated by dense Adam on every row every step, the
+                              split of Sec. 4.2.2 step 4 (appearance stays deferred) */
+    uint64_t sr_seed;      /* seed of the stochastic-rounding stream of quantised moments */
+    int32_t reserved_[4];
 } gs_model;
 
 /* ---------------------------------------------------------------- tables */
@@ -124,7 +128,7 @@ int gs_workspace_bytes(const gs_model *model, size_t *bytes);
 
 /* ------------------------------------------------------------------ path */
 
-/* Cull (Sec. 2.3 step 1 and Sec. 3.4: drop Gaussians outside the near/far
+/* Cull (Sec. 2.4 step 1 and Sec. 3.4: drop Gaussians outside the near/far
  * planes and those whose projected 3-sigma footprint misses the image, from
  * mean, scale and quaternion only) of every Gaussian's CURRENT geometry before
  * update `step` -- stored G restored with Eq. 3 for deferred rows -- against
@@ -162,6 +166,9 @@ int gs_scatter_grad(const uint32_t *ids, const uint32_t *count_dev, uint32_t cap
  * with ids (the scatter is fused), or, when g_geo/g_app are NULL, dense rows
  * g_geo_dense[id] / g_app_dense[id] that are read and then cleared to zero.
  * Saturated rows use g = 0. */
+/* (With geo_mode = 1 and compact gradients, the call must follow the gs_cull
+ * of the same step on the same workspace: the dense geometric update finds
+ * each visible row's compact gradient from the cull's keep ballots.) */
 int gs_adam_step_deferred(const gs_model *model, int64_t step, const uint32_t *ids,
                           const uint32_t *count_dev, uint32_t capacity, const float *g_geo,
                           const float *g_app, float *g_geo_dense, float *g_app_dense, void *ws,

@@ -12,14 +12,16 @@
  *
  * Contents
  *   orc_exp_gs          exp for the cull (Cody & Waite 1980 reduction + Taylor)
- *   orc_cull_v1         FP32 frustum/screen cull of one camera (Sec. 2.3 step 1,
+ *   orc_cull_v1         FP32 frustum/screen cull of one camera (Sec. 2.4 step 1,
  *                       Sec. 3.4 challenge 1; formula fixed as the 3-sigma EWA box)
  *   orc_compact         ascending ids of the kept rows (valid_ids, Sec. 4.1)
  *   orc_adam_dense_f64  dense Adam, Eq. 1 -- the definition the method reaches
  *   orc_lut_paper_f64   LUTs of the deferred-update figure (param/mom/var LUT)
  *   orc_deferred_rows_f64  restore + Adam of the figure, FP64 (model O2)
  *   orc_lut_spec        FP32 LUT of the implementation spec (model O3)
- *   orc_deferred_rows_f32  the same update with FP32 state, fixed op order (O3)
+ *   orc_restore_bound   clamp of the restore factor (above the Adam ratio bound)
+ *   orc_deferred_rows_f32  the same update with FP32 math and FP32 (O3) or
+ *                       BF16 stochastically rounded (O4) moments, fixed op order
  *   orc_restore_rows_f32   restore-only (read-only forwarding, Sec. 4.3.3)
  *   orc_flush_rows_*    catch-up of skipped zero-gradient steps (Eq. 2-3)
  */
@@ -59,7 +61,7 @@ float orc_exp_gs(float x)
 /* Cull of one Gaussian.  The paper states what culling does -- drop Gaussians
  * outside the near/far planes, project mean and covariance to the image, drop
  * 2D Gaussians outside the image -- using only mean, scale and quaternion
- * (Sec. 2.3 step 1; Sec. 4.1 step 1; Sec. 4.2.1).  It does not print a formula;
+ * (Sec. 2.4 step 1; Sec. 4.1 step 1; Sec. 4.2.1).  It does not print a formula;
  * this is the EWA screen-space test of 3D Gaussian Splatting: 3-sigma radius of
  * the projected covariance (with the 0.3 px low-pass dilation) around the
  * projected centre, tested against the image rectangle.
@@ -337,21 +339,93 @@ void orc_lut_spec(double b1, double b2, int64_t t, int dmax, float *Wf, float *M
     free(P1); free(P2);
 }
 
-/* O3 restore of one element: w - ((Wf[d]*lr)*m) / (sqrt(v)+eps), d > 0 only. */
-static float restore32(float w, float m, float v, float wd, float lr, float eps)
+/* Bound on the restore factor m/(sqrt(v)+eps).  For Adam moments grown from
+ * zero, Cauchy-Schwarz gives |m|/sqrt(v) <= (1-b1)/sqrt((1-b2)(1-b1^2/b2))
+ * (7.27 for b = 0.9, 0.999); the restore clamps the factor at 1.03 times
+ * that, which leaves every reachable FP32 state untouched and bounds how far
+ * a restore can move a parameter whatever the stored moments are.
+ * +inf (no clamp) when b1^2 >= b2. */
+float orc_restore_bound(double b1, double b2)
 {
-    float wsc = wd * lr;
-    float num = wsc * m;
-    float den = sqrtf(v) + eps;
-    return w - num / den;
+    if (!(b1 * b1 < b2)) return INFINITY;
+    return (float)((1.0 - b1) / sqrt((1.0 - b2) * (1.0 - b1 * b1 / b2)) * 1.03);
 }
 
-/* O3 update of the rows rows[j] (defer count d[j], FP32 compact gradient
- * g[j][:] or zero when g == NULL), state arrays [n][ld]. */
-void orc_deferred_rows_f32(int dim, float *w, float *m, float *v, int64_t ld, int64_t n_rows,
+/* Moment storage: state 0 = FP32, state 1 = BF16 (upper 16 bits of the FP32
+ * pattern).  Stores round stochastically: the 16 random bits are added to the
+ * FP32 pattern before truncation, so x rounds up with probability equal to
+ * the dropped fraction.  Inf stays Inf, NaN stays a quiet NaN. */
+static float mom_load(const void *p, int state, int64_t e)
+{
+    if (state == 0) return ((const float *)p)[e];
+    uint32_t u = (uint32_t)((const uint16_t *)p)[e] << 16;
+    float f;
+    memcpy(&f, &u, 4);
+    return f;
+}
+
+static void mom_store(void *p, int state, int64_t e, float x, uint32_t r16)
+{
+    if (state == 0) {
+        ((float *)p)[e] = x;
+        return;
+    }
+    uint32_t u;
+    memcpy(&u, &x, 4);
+    if ((u & 0x7f800000u) == 0x7f800000u) {
+        uint16_t h = (uint16_t)(u >> 16);
+        if (u & 0x007fffffu) h |= 0x0040u;
+        ((uint16_t *)p)[e] = h;
+        return;
+    }
+    u += r16;
+    ((uint16_t *)p)[e] = (uint16_t)(u >> 16);
+}
+
+/* One BF16 stochastic rounding (exposed for tests). */
+uint16_t orc_bf16_sr(float x, uint32_t r16)
+{
+    uint16_t h;
+    mom_store(&h, 1, 0, x, r16);
+    return h;
+}
+
+/* SplitMix64 (Steele, Lea & Flood 2014): output k of the stream seeded s. */
+static uint64_t mix64(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+static uint64_t sm_at(uint64_t s, uint64_t k) { return mix64(s + (k + 1) * 0x9E3779B97F4A7C15ull); }
+
+/* Random bits of element (step t, row id, global column col): bits 0..15 round m,
+ * bits 16..31 round v. */
+static uint64_t sr_bits(uint64_t seed, int64_t t, int64_t id, int64_t col)
+{
+    return sm_at(sm_at(sm_at(seed, (uint64_t)t), (uint64_t)id), (uint64_t)col);
+}
+
+/* O3 restore of one element (d > 0 only): q = m / (sqrt(v)+eps) clamped to
+ * [-rb, rb], then w - (Wf[d]*lr) * q. */
+static float restore32(float w, float m, float v, float wd, float lr, float eps, float rb)
+{
+    float den = sqrtf(v) + eps;
+    float q = m / den;
+    if (q > rb) q = rb;
+    else if (q < -rb) q = -rb;
+    float wsc = wd * lr;
+    return w - wsc * q;
+}
+
+/* O3/O4 update of the rows rows[j] (defer count d[j], FP32 compact gradient
+ * g[j][:] or zero when g == NULL).  w is [n][ld] FP32; m, v are [n][ld] in the
+ * given storage.  Global column of k is col0 + k (SR random stream). */
+void orc_deferred_rows_f32(int dim, float *w, void *m, void *v, int state, int64_t ld, int64_t n_rows,
                            const uint32_t *rows, const int64_t *d, const float *g, int64_t g_ld,
                            const float *lr, double b1, double b2, double eps,
-                           const float *Wf, const float *Mf, const float *Vf, float ss, float bc)
+                           const float *Wf, const float *Mf, const float *Vf, float ss, float bc, float rb,
+                           uint64_t seed, int64_t t, int col0)
 {
     const float omb1 = (float)(1.0 - b1), omb2 = (float)(1.0 - b2), eps32 = (float)eps;
 #pragma omp parallel for schedule(static)
@@ -360,24 +434,25 @@ void orc_deferred_rows_f32(int dim, float *w, float *m, float *v, int64_t ld, in
         int64_t dj = d[j];
         for (int k = 0; k < dim; ++k) {
             int64_t e = id * ld + k;
-            float wk = w[e], mk = m[e], vk = v[e];
+            float wk = w[e], mk = mom_load(m, state, e), vk = mom_load(v, state, e);
             float gk = g ? g[j * g_ld + k] : 0.0f;
-            if (dj > 0) wk = restore32(wk, mk, vk, Wf[dj], lr[k], eps32);
+            if (dj > 0) wk = restore32(wk, mk, vk, Wf[dj], lr[k], eps32, rb);
             float m1 = Mf[dj] * mk + omb1 * gk;
             float v1 = Vf[dj] * vk + (omb2 * gk) * gk;
             float den = sqrtf(v1) / bc + eps32;
             float st = lr[k] * ss;
             w[e] = wk - (st * m1) / den;
-            m[e] = m1;
-            v[e] = v1;
+            uint64_t r = state ? sr_bits(seed, t, id, col0 + k) : 0;
+            mom_store(m, state, e, m1, (uint32_t)(r & 0xffffu));
+            mom_store(v, state, e, v1, (uint32_t)((r >> 16) & 0xffffu));
         }
     }
 }
 
-/* O3 restore-only: out[j][:] = current FP32 value of row rows[j]. */
-void orc_restore_rows_f32(int dim, const float *w, const float *m, const float *v, int64_t ld,
+/* O3/O4 restore-only: out[j][:] = current FP32 value of row rows[j]. */
+void orc_restore_rows_f32(int dim, const float *w, const void *m, const void *v, int state, int64_t ld,
                           int64_t n_rows, const uint32_t *rows, const int64_t *d,
-                          const float *lr, double eps, const float *Wf, float *out)
+                          const float *lr, double eps, const float *Wf, float rb, float *out)
 {
     const float eps32 = (float)eps;
 #pragma omp parallel for schedule(static)
@@ -386,16 +461,19 @@ void orc_restore_rows_f32(int dim, const float *w, const float *m, const float *
         for (int k = 0; k < dim; ++k) {
             int64_t e = id * ld + k;
             float wk = w[e];
-            if (d[j] > 0) wk = restore32(wk, m[e], v[e], Wf[d[j]], lr[k], eps32);
+            if (d[j] > 0)
+                wk = restore32(wk, mom_load(m, state, e), mom_load(v, state, e), Wf[d[j]], lr[k], eps32, rb);
             out[j * dim + k] = wk;
         }
     }
 }
 
-/* O3 flush: rows skipped delta[j] >= 1 steps; Wf_next is the table of step t+1. */
-void orc_flush_rows_f32(int dim, float *w, float *m, float *v, int64_t ld, int64_t n_rows,
+/* O3/O4 flush after update t: rows skipped delta[j] >= 1 steps; Wf_next is the
+ * table of step t+1.  Quantised moments round with the stream of step t. */
+void orc_flush_rows_f32(int dim, float *w, void *m, void *v, int state, int64_t ld, int64_t n_rows,
                         const uint32_t *rows, const int64_t *delta, const float *lr, double eps,
-                        const float *Wf_next, const float *Mf, const float *Vf)
+                        const float *Wf_next, const float *Mf, const float *Vf, float rb,
+                        uint64_t seed, int64_t t, int col0)
 {
     const float eps32 = (float)eps;
 #pragma omp parallel for schedule(static)
@@ -404,10 +482,11 @@ void orc_flush_rows_f32(int dim, float *w, float *m, float *v, int64_t ld, int64
         int64_t dl = delta[j];
         for (int k = 0; k < dim; ++k) {
             int64_t e = id * ld + k;
-            float mk = m[e], vk = v[e];
-            w[e] = restore32(w[e], mk, vk, Wf_next[dl], lr[k], eps32);
-            m[e] = Mf[dl - 1] * mk;
-            v[e] = Vf[dl - 1] * vk;
+            float mk = mom_load(m, state, e), vk = mom_load(v, state, e);
+            w[e] = restore32(w[e], mk, vk, Wf_next[dl], lr[k], eps32, rb);
+            uint64_t r = state ? sr_bits(seed, t, id, col0 + k) : 0;
+            mom_store(m, state, e, Mf[dl - 1] * mk, (uint32_t)(r & 0xffffu));
+            mom_store(v, state, e, Vf[dl - 1] * vk, (uint32_t)((r >> 16) & 0xffffu));
         }
     }
 }

@@ -65,10 +65,13 @@ def lib():
             "orc_restore_rows_f64": (None, [i32, vp, vp, vp, i64, vp, vp, vp, f64, vp, vp]),
             "orc_flush_rows_f64": (None, [i32, vp, vp, vp, i64, vp, vp, vp, f64, f64, f64, vp]),
             "orc_lut_spec": (None, [f64, f64, i64, i32, vp, vp, vp, vp, vp]),
-            "orc_deferred_rows_f32": (None, [i32, vp, vp, vp, i64, i64, vp, vp, vp, i64, vp,
-                                             f64, f64, f64, vp, vp, vp, f32, f32]),
-            "orc_restore_rows_f32": (None, [i32, vp, vp, vp, i64, i64, vp, vp, vp, f64, vp, vp]),
-            "orc_flush_rows_f32": (None, [i32, vp, vp, vp, i64, i64, vp, vp, vp, f64, vp, vp, vp]),
+            "orc_restore_bound": (f32, [f64, f64]),
+            "orc_bf16_sr": (C.c_uint16, [f32, C.c_uint32]),
+            "orc_deferred_rows_f32": (None, [i32, vp, vp, vp, i32, i64, i64, vp, vp, vp, i64, vp,
+                                             f64, f64, f64, vp, vp, vp, f32, f32, f32, C.c_uint64, i64, i32]),
+            "orc_restore_rows_f32": (None, [i32, vp, vp, vp, i32, i64, i64, vp, vp, vp, f64, vp, f32, vp]),
+            "orc_flush_rows_f32": (None, [i32, vp, vp, vp, i32, i64, i64, vp, vp, vp, f64, vp, vp, vp, f32,
+                                          C.c_uint64, i64, i32]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -255,26 +258,59 @@ class DeferredF64(_Deferred):
         self.counter[:] = 0
 
 
-class DeferredF32(_Deferred):
-    """Model O3: deferred algorithm, FP32 state, the implementation's op order."""
+def restore_bound(b1: float, b2: float) -> np.float32:
+    """Clamp of the restore factor m/(sqrt(v)+eps) (1.03 x the Adam ratio bound)."""
+    return np.float32(lib().orc_restore_bound(b1, b2))
 
-    def __init__(self, geo, app, lr_geo, lr_app, b1=0.9, b2=0.999, eps=1e-15, max_defer=0):
+
+STATES = {"f32": (0, np.float32), "bf16": (1, np.uint16)}
+
+
+class DeferredF32(_Deferred):
+    """Model O3 (state='f32') / O4 (state='bf16'): deferred algorithm with FP32
+    math, moments stored in FP32 or in BF16 with stochastic rounding (random
+    bits from SplitMix64 of (sr_seed, step, row key, global column)), and the
+    implementation's op order.  `keys` are the Gaussian ids of the rows (for
+    the rounding stream); default 0..n-1."""
+
+    def __init__(self, geo, app, lr_geo, lr_app, b1=0.9, b2=0.999, eps=1e-15, max_defer=0,
+                 state="f32", sr_seed=0, keys=None, app_state=None, geo_dense=False):
         super().__init__(geo.shape[0], max_defer)
+        # geo_dense: the geometric group takes a plain Adam step on every row
+        # every step (the split of Sec. 4.2.2); only the appearance is deferred
+        self.geo_dense = bool(geo_dense)
+        states = [state, app_state or state]
+        self.sid = [STATES[x][0] for x in states]
         self.w = [np.array(geo, np.float32), np.array(app, np.float32)]
-        self.m = [np.zeros_like(x) for x in self.w]
-        self.v = [np.zeros_like(x) for x in self.w]
+        self.m = [np.zeros(x.shape, STATES[st][1]) for x, st in zip(self.w, states)]
+        self.v = [np.zeros(x.shape, STATES[st][1]) for x, st in zip(self.w, states)]
         self.lr = [np.asarray(lr_geo, np.float32), np.asarray(lr_app, np.float32)]
         self.b1, self.b2, self.eps = b1, b2, eps
+        self.rb = float(restore_bound(b1, b2))
+        self.sr_seed = int(sr_seed)
+        self.col0 = [0, self.w[0].shape[1]]
+        if keys is not None:
+            assert np.array_equal(np.asarray(keys), np.arange(geo.shape[0])), \
+                "row sampling with quantised state needs keys == row index"
+
+    def moments_f32(self, k):
+        """FP32 view of the stored moments of group k."""
+        if self.sid[k] == 0:
+            return self.m[k], self.v[k]
+        conv = lambda a: (a.astype(np.uint32) << 16).view(np.float32)
+        return conv(self.m[k]), conv(self.v[k])
 
     def _restore(self, k, t, rows):
         rows32 = np.ascontiguousarray(rows, np.uint32)
         d = np.ascontiguousarray(self.counter[np.asarray(rows, np.int64)], np.int64)
+        if k == 0 and self.geo_dense:
+            d = np.zeros_like(d)
         Wf, _, _, _, _ = lut_spec(self.b1, self.b2, t, max(self.dmax(t), 0))
         dim = self.w[k].shape[1]
         out = np.zeros((rows32.shape[0], dim), np.float32)
-        lib().orc_restore_rows_f32(dim, _p(self.w[k]), _p(self.m[k]), _p(self.v[k]), dim,
+        lib().orc_restore_rows_f32(dim, _p(self.w[k]), _p(self.m[k]), _p(self.v[k]), self.sid[k], dim,
                                    rows32.shape[0], _p(rows32), _p(d), _p(self.lr[k]), self.eps,
-                                   _p(Wf), _p(out))
+                                   _p(Wf), self.rb, _p(out))
         return out
 
     def current(self, t: int, rows=None):
@@ -296,12 +332,19 @@ class DeferredF32(_Deferred):
         Wf, Mf, Vf, ss, bc = lut_spec(self.b1, self.b2, t, max(self.dmax(t), 0))
         for k, g in enumerate((g_geo, g_app)):
             dim = self.w[k].shape[1]
-            gg = np.zeros((rows.shape[0], dim), np.float32)
-            gg[:valid.shape[0]] = g
-            lib().orc_deferred_rows_f32(dim, _p(self.w[k]), _p(self.m[k]), _p(self.v[k]), dim,
-                                        rows.shape[0], _p(rows), _p(d), _p(gg), dim, _p(self.lr[k]),
+            if k == 0 and self.geo_dense:
+                krows = np.arange(self.counter.shape[0], dtype=np.uint32)
+                kd = np.zeros(krows.shape[0], np.int64)
+                gg = np.zeros((krows.shape[0], dim), np.float32)
+                gg[valid] = g
+            else:
+                krows, kd = rows, d
+                gg = np.zeros((rows.shape[0], dim), np.float32)
+                gg[:valid.shape[0]] = g
+            lib().orc_deferred_rows_f32(dim, _p(self.w[k]), _p(self.m[k]), _p(self.v[k]), self.sid[k], dim,
+                                        krows.shape[0], _p(krows), _p(kd), _p(gg), dim, _p(self.lr[k]),
                                         self.b1, self.b2, self.eps, _p(Wf), _p(Mf), _p(Vf),
-                                        float(ss), float(bc))
+                                        float(ss), float(bc), self.rb, self.sr_seed, t, self.col0[k])
         self.bump(valid, sat)
         return valid, sat
 
@@ -314,10 +357,12 @@ class DeferredF32(_Deferred):
         Wn, Mf, Vf, _, _ = lut_spec(self.b1, self.b2, t_done + 1, int(delta.max()))
         rows32 = np.ascontiguousarray(rows, np.uint32)
         for k in range(2):
+            if k == 0 and self.geo_dense:
+                continue
             dim = self.w[k].shape[1]
-            lib().orc_flush_rows_f32(dim, _p(self.w[k]), _p(self.m[k]), _p(self.v[k]), dim,
+            lib().orc_flush_rows_f32(dim, _p(self.w[k]), _p(self.m[k]), _p(self.v[k]), self.sid[k], dim,
                                      rows.shape[0], _p(rows32), _p(delta), _p(self.lr[k]), self.eps,
-                                     _p(Wn), _p(Mf), _p(Vf))
+                                     _p(Wn), _p(Mf), _p(Vf), self.rb, self.sr_seed, t_done, self.col0[k])
         self.counter[:] = 0
 
 

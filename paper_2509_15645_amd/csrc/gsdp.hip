@@ -7,7 +7,7 @@
 // written as the exact sequence of IEEE operations that defines the result.
 //
 // Kernels
-//   k_cull      persistent; each block claims 1024-row tiles with a ticket,
+//   k_cull      each block claims 512-row tiles with a ticket,
 //               stages the tile's geometry through LDS with 128-bit loads,
 //               restores deferred rows, culls, and compacts the kept rows in
 //               id order: wave ballot + mbcnt, block scan in LDS, decoupled
@@ -21,7 +21,9 @@
 //   k_synth     synthetic gradients (harness only)
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <vector>
@@ -69,7 +71,7 @@ struct CamK {
 // camera: the 3-sigma EWA footprint (projected covariance + 0.3 px dilation,
 // largest eigenvalue, radius rounded up) around the projected centre must
 // overlap the image, and the centre must lie strictly between near and far
-// (Sec. 2.3 step 1).  All comparisons are positive, so a NaN anywhere culls.
+// (Sec. 2.4 step 1).  All comparisons are positive, so a NaN anywhere culls.
 __device__ __forceinline__ bool cull_v1(const float *g, const CamK &c)
 {
     const float x = ((c.R[0] * g[0] + c.R[1] * g[1]) + c.R[2] * g[2]) + c.T[0];
@@ -151,13 +153,114 @@ __device__ __forceinline__ bool cull_v1(const float *g, const CamK &c)
 }
 
 // Restore of one element deferred d > 0 steps (Eq. 3 with eps factored out):
-// w - ((W[d] lr) m) / (sqrt(v) + eps), with the stored (old) moments.
-__device__ __forceinline__ float restore1(float w, float m, float v, float wd, float lr, float eps)
+// q = m / (sqrt(v) + eps) with the stored (old) moments, clamped to [-rb, rb],
+// then w - (W[d] lr) q.  rb is 1.03x the Cauchy-Schwarz bound of |m|/sqrt(v)
+// for Adam moments grown from zero, so the clamp never acts on a reachable
+// FP32 state; it bounds the restore for any stored moments (quantised ones too).
+__device__ __forceinline__ float restore1(float w, float m, float v, float wd, float lr, float eps, float rb)
 {
-    const float wsc = wd * lr;
-    const float num = wsc * m;
     const float den = sqrtf(v) + eps;
-    return w - num / den;
+    float q = m / den;
+    if (q > rb) q = rb;
+    else if (q < -rb) q = -rb;
+    const float wsc = wd * lr;
+    return w - wsc * q;
+}
+
+// SplitMix64 (Steele, Lea & Flood 2014): output k of the stream seeded s.
+__device__ __forceinline__ u64 mix64(u64 z)
+{
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+__device__ __forceinline__ u64 sm_at(u64 s, u64 i) { return mix64(s + (i + 1ull) * 0x9E3779B97F4A7C15ull); }
+
+// Moment storage.  BF16 keeps the upper 16 bits of the FP32 pattern; stores
+// round stochastically by adding 16 random bits before truncation (Inf kept,
+// NaN quieted).
+template <int ST> __device__ __forceinline__ float mom_load(const void *p, int64_t e);
+template <> __device__ __forceinline__ float mom_load<GS_F32>(const void *p, int64_t e)
+{
+    return static_cast<const float *>(p)[e];
+}
+template <> __device__ __forceinline__ float mom_load<GS_BF16>(const void *p, int64_t e)
+{
+    return __uint_as_float((u32) static_cast<const uint16_t *>(p)[e] << 16);
+}
+template <int ST> __device__ __forceinline__ void mom_store(void *p, int64_t e, float x, u32 r16);
+template <> __device__ __forceinline__ void mom_store<GS_F32>(void *p, int64_t e, float x, u32)
+{
+    static_cast<float *>(p)[e] = x;
+}
+template <> __device__ __forceinline__ void mom_store<GS_BF16>(void *p, int64_t e, float x, u32 r16)
+{
+    const u32 u = __float_as_uint(x);
+    uint16_t h;
+    if ((u & 0x7f800000u) == 0x7f800000u) h = (uint16_t)((u >> 16) | ((u & 0x007fffffu) ? 0x0040u : 0u));
+    else h = (uint16_t)((u + r16) >> 16);
+    static_cast<uint16_t *>(p)[e] = h;
+}
+
+// Per-camera constants of the band classifier (host-computed, rounded up).
+struct BandK {
+    float rs0, rs1, rs2;   // |R_i0| + |R_i1| + |R_i2|, rows of the camera rotation
+    float jf2;             // fx^2 (1 + limx^2) + fy^2 (1 + limy^2): bound of |J|_F^2 z^2
+    float kpos, kscl, kq;  // B * max lr over position / log-scale / quaternion columns
+};
+
+// Conservative classification of one Gaussian whose stored geometry g may be
+// stale by a restore of at most B*W[d]*lr per column (B bounds |m|/sqrt(v) of
+// Adam moments grown from zero: by Cauchy-Schwarz (1-b1)/sqrt((1-b2)(1-b1^2/b2))
+// = 7.27 for b = (0.9, 0.999); B includes a margin for FP32 storage).
+// Returns 0 when every admissible restored geometry is culled by cull_v1,
+// 1 when every one is kept, 2 when undecided (the exact test must run).
+// Bounds, all with generous margins for FP32 rounding of the exact test:
+//   camera-space centre moves by <= |R_i|_1 * position drift;
+//   projected covariance trace <= |J|_F^2 sigma_max^2, |J|_F^2 <= jf2 / z^2 since
+//   |tan| is clamped, and the radius of cull_v1 is <= ceil(3 sqrt(trace + 0.92));
+//   the radius is >= 3 and det > 0 holds when the trace bound is <= 1000.
+__device__ __forceinline__ int classify(const float *g, float wd, const CamK &c, const BandK &b)
+{
+    bool fin = true;
+#pragma unroll
+    for (int j = 0; j < 10; ++j) fin &= __builtin_isfinite(g[j]);
+    if (!fin) return 2;
+    const float dpos = b.kpos * wd, dscl = b.kscl * wd, dq = b.kq * wd;
+    const float mu = fmaxf(fmaxf(fabsf(g[0]), fabsf(g[1])), fabsf(g[2]));
+    const float dp = dpos + 1e-6f * mu;
+    const float x = ((c.R[0] * g[0] + c.R[1] * g[1]) + c.R[2] * g[2]) + c.T[0];
+    const float y = ((c.R[3] * g[0] + c.R[4] * g[1]) + c.R[5] * g[2]) + c.T[1];
+    const float z = ((c.R[6] * g[0] + c.R[7] * g[1]) + c.R[8] * g[2]) + c.T[2];
+    const float sx = fabsf(c.R[0] * g[0]) + fabsf(c.R[1] * g[1]) + fabsf(c.R[2] * g[2]) + fabsf(c.T[0]);
+    const float sy = fabsf(c.R[3] * g[0]) + fabsf(c.R[4] * g[1]) + fabsf(c.R[5] * g[2]) + fabsf(c.T[1]);
+    const float sz = fabsf(c.R[6] * g[0]) + fabsf(c.R[7] * g[1]) + fabsf(c.R[8] * g[2]) + fabsf(c.T[2]);
+    const float ex = b.rs0 * dp + 1e-6f * (sx + b.rs0 * dp) + 1e-6f;
+    const float ey = b.rs1 * dp + 1e-6f * (sy + b.rs1 * dp) + 1e-6f;
+    const float ez = b.rs2 * dp + 1e-6f * (sz + b.rs2 * dp) + 1e-6f;
+    const float zlo = z - ez, zhi = z + ez;
+    if (zhi <= c.zn || zlo >= c.zf) return 0;
+    if (!(zlo > 0.0f)) return 2;
+    const float smax = fmaxf(fmaxf(g[3], g[4]), g[5]) + dscl + 1e-6f * fmaxf(fmaxf(fabsf(g[3]), fabsf(g[4])), fabsf(g[5]));
+    if (!(smax < 80.0f)) return 2;
+    const float sig = __expf(smax) * 1.001f;
+    const float izl = 1.0f / zlo, izh = 1.0f / zhi;
+    const float S = ((b.jf2 * izl) * izl) * (sig * sig);
+    const float lam = 1.001f * S + 0.95f;
+    const float rup = 3.0f * sqrtf(lam) * 1.001f + 1.0f;
+    const float xlo = x - ex, xhi = x + ex, ylo = y - ey, yhi = y + ey;
+    const float qxlo = fminf(xlo * izl, xlo * izh), qxhi = fmaxf(xhi * izl, xhi * izh);
+    const float qylo = fminf(ylo * izl, ylo * izh), qyhi = fmaxf(yhi * izl, yhi * izh);
+    const float eu = 1e-5f * (c.fx * fmaxf(fabsf(qxlo), fabsf(qxhi)) + fabsf(c.cx)) + 1e-3f;
+    const float ev = 1e-5f * (c.fy * fmaxf(fabsf(qylo), fabsf(qyhi)) + fabsf(c.cy)) + 1e-3f;
+    const float ulo = c.fx * qxlo + c.cx - eu, uhi = c.fx * qxhi + c.cx + eu;
+    const float vlo = c.fy * qylo + c.cy - ev, vhi = c.fy * qyhi + c.cy + ev;
+    if (uhi + rup <= 0.0f || ulo - rup >= c.W || vhi + rup <= 0.0f || vlo - rup >= c.H) return 0;
+    const float qn = sqrtf(((g[6] * g[6] + g[7] * g[7]) + g[8] * g[8]) + g[9] * g[9]);
+    if (zlo > c.zn && zhi < c.zf && ulo > -1.5f && uhi < c.W + 1.5f && vlo > -1.5f && vhi < c.H + 1.5f &&
+        lam <= 1000.0f && qn > 2.002f * dq + 1e-6f)
+        return 1;
+    return 2;
 }
 
 __device__ __forceinline__ u32 lane_rank(u64 mask)
@@ -184,8 +287,10 @@ __device__ __forceinline__ u64 pack_vs(u32 vis, u32 sat) { return ((u64)vis << 3
 
 struct CullArgs {
     const float *gw;                 // [n][10]
-    const float *gm, *gv;            // G moments (restore)
+    const void *gm, *gv;             // G moments (restore), storage type gst
     int64_t m_ld, v_ld;
+    int32_t gst, pad2;
+    float rb, pad3;
     const int32_t *last;
     int64_t n;
     int32_t t, K, dmax, pad0;
@@ -193,6 +298,10 @@ struct CullArgs {
     float lr[10];
     float eps;
     CamK cam;
+    BandK band;
+    int32_t mode;                    // 0 exact restoring, 1 band
+    int32_t geo_dense;               // geometry updated densely every step: never restore G
+    u64 *keep_bits;                  // per tile, per (slab, wave) keep ballots (dense-G mode)
     u32 *ids, *count;
     u32 cap, pad1;
     u32 *sat_ids;
@@ -259,16 +368,29 @@ __global__ __launch_bounds__(kCullBlock) void k_cull(CullArgs a)
                 }
                 int d = a.t - 1 - lastv[k];
                 d = d < 0 ? 0 : (d > a.dmax ? a.dmax : d);
-                if (d > 0) {
-                    const int64_t row = row0 + r;
-                    const float *mr = a.gm + row * a.m_ld;
-                    const float *vr = a.gv + row * a.v_ld;
-                    const float wd = a.Wrow[d];
+                // with dense geometry the stored G is always current
+                const float wd = (d > 0 && !a.geo_dense) ? a.Wrow[d] : 0.0f;
+                const int cls = a.mode == 1 ? classify(g, wd, a.cam, a.band) : 2;
+                if (cls == 2) {
+                    if (d > 0 && !a.geo_dense) {
+                        const int64_t row = row0 + r;
+                        if (a.gst == GS_F32) {
 #pragma unroll
-                    for (int j = 0; j < 10; ++j) g[j] = restore1(g[j], mr[j], vr[j], wd, a.lr[j], a.eps);
-                    ++nrest;
+                            for (int j = 0; j < 10; ++j)
+                                g[j] = restore1(g[j], mom_load<GS_F32>(a.gm, row * a.m_ld + j),
+                                                mom_load<GS_F32>(a.gv, row * a.v_ld + j), wd, a.lr[j], a.eps, a.rb);
+                        } else {
+#pragma unroll
+                            for (int j = 0; j < 10; ++j)
+                                g[j] = restore1(g[j], mom_load<GS_BF16>(a.gm, row * a.m_ld + j),
+                                                mom_load<GS_BF16>(a.gv, row * a.v_ld + j), wd, a.lr[j], a.eps, a.rb);
+                        }
+                        ++nrest;
+                    }
+                    keep = cull_v1(g, a.cam);
+                } else {
+                    keep = cls == 1;
                 }
-                keep = cull_v1(g, a.cam);
                 sat = (a.K > 0) && !keep && d == a.K;
             }
             bv[k] = __ballot(keep);
@@ -276,6 +398,7 @@ __global__ __launch_bounds__(kCullBlock) void k_cull(CullArgs a)
             if (lane == 0) {
                 sCntV[k * 4 + wave] = (u32)__popcll(bv[k]);
                 sCntS[k * 4 + wave] = (u32)__popcll(bs[k]);
+                if (a.keep_bits) a.keep_bits[(int64_t)tile * (kCullIpt * 4) + k * 4 + wave] = bv[k];
             }
         }
         if (nrest) atomicAdd(&sRestored, nrest);
@@ -388,13 +511,15 @@ enum RowMode { kGather = 0, kAdam = 1, kFlush = 2 };
 constexpr int kRowUnroll = 4;
 
 struct RowArgs {
-    float *gw, *gm, *gv;
+    float *gw, *aw;
+    void *gm, *gv, *am, *av;
     int64_t gw_ld, gm_ld, gv_ld;
-    float *aw, *am, *av;
     int64_t aw_ld, am_ld, av_ld;
     int32_t adim, t, K, dmax;
     float lr[64];                    // lane-indexed: 0..9 G, 10.. A
-    float eps, omb1, omb2, pad0;
+    float eps, omb1, omb2, rb;       // rb: clamp of the restore factor
+    u64 sr_seed;
+    int32_t geo_dense, pad2;
     int32_t *last;
     int64_t n;
     const float *Wrow, *Mf, *Vf, *SS, *BC;
@@ -406,14 +531,18 @@ struct RowArgs {
     float *out_geo, *out_app;        // gather outputs
 };
 
-template <int MODE>
+// One wavefront per Gaussian row: lane c < 10 owns G column c, lane 10+c owns
+// A column c.  GST / AST are the moment storage types of G and A.
+template <int MODE, int GST, int AST>
 __global__ __launch_bounds__(256) void k_rows(RowArgs a)
 {
     const int lane = threadIdx.x & 63;
     const int64_t wid = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int64_t nw = (int64_t)gridDim.x * 4;
     const bool isG = lane < 10;
-    const bool act = lane < 10 + a.adim;
+    // with dense geometry, G columns are updated elsewhere and never deferred
+    const bool act = lane < 10 + a.adim && !(isG && a.geo_dense && MODE != kGather);
+    const bool grest = !(isG && a.geo_dense);
     const int ca = lane - 10;
     const float lr = a.lr[lane];
 
@@ -432,6 +561,8 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
         bc = a.BC[a.t];
     }
     const float step = lr * ss;
+    const bool quant = (GST != GS_F32) || (AST != GS_F32);
+    const u64 s_step = quant ? sm_at(a.sr_seed, (u64)a.t) : 0ull;
 
     for (int64_t base = wid * kRowUnroll; base < total; base += nw * kRowUnroll) {
         int64_t id[kRowUnroll];
@@ -462,14 +593,18 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
 #pragma unroll
         for (int u = 0; u < kRowUnroll; ++u) {
             w[u] = m[u] = v[u] = g[u] = 0.0f;
-            const bool need = ok[u] && act && (MODE == kAdam || d[u] > 0 || MODE == kGather);
+            const bool need = ok[u] && act && (MODE != kFlush || d[u] > 0);
             if (!need) continue;
             const int64_t r = id[u];
-            float *wp = isG ? a.gw + r * a.gw_ld + lane : a.aw + r * a.aw_ld + ca;
-            w[u] = *wp;
-            if (MODE == kAdam || d[u] > 0) {
-                m[u] = isG ? a.gm[r * a.gm_ld + lane] : a.am[r * a.am_ld + ca];
-                v[u] = isG ? a.gv[r * a.gv_ld + lane] : a.av[r * a.av_ld + ca];
+            w[u] = isG ? a.gw[r * a.gw_ld + lane] : a.aw[r * a.aw_ld + ca];
+            if ((MODE == kAdam || d[u] > 0) && grest) {
+                if (isG) {
+                    m[u] = mom_load<GST>(a.gm, r * a.gm_ld + lane);
+                    v[u] = mom_load<GST>(a.gv, r * a.gv_ld + lane);
+                } else {
+                    m[u] = mom_load<AST>(a.am, r * a.am_ld + ca);
+                    v[u] = mom_load<AST>(a.av, r * a.av_ld + ca);
+                }
             }
             if (MODE == kAdam && base + u < nvis) {
                 if (a.g_geo) g[u] = isG ? a.g_geo[(base + u) * 10 + lane] : a.g_app[(base + u) * a.adim + ca];
@@ -482,7 +617,7 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
             const int64_t r = id[u];
             if (MODE == kGather) {
                 float x = w[u];
-                if (d[u] > 0) x = restore1(x, m[u], v[u], a.Wrow[d[u]], lr, a.eps);
+                if (d[u] > 0 && grest) x = restore1(x, m[u], v[u], a.Wrow[d[u]], lr, a.eps, a.rb);
                 if (act) {
                     if (isG) {
                         if (a.out_geo) a.out_geo[(base + u) * 10 + lane] = x;
@@ -490,51 +625,131 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
                         a.out_app[(base + u) * a.adim + ca] = x;
                     }
                 }
-            } else if (MODE == kAdam) {
-                if (act) {
-                    float x = w[u];
-                    const int dd = d[u];
-                    if (dd > 0) x = restore1(x, m[u], v[u], a.Wrow[dd], lr, a.eps);
-                    const float m1 = a.Mf[dd] * m[u] + a.omb1 * g[u];
-                    const float v1 = a.Vf[dd] * v[u] + (a.omb2 * g[u]) * g[u];
+                continue;
+            }
+            const int dd = d[u];
+            if (MODE == kFlush && dd == 0) continue;
+            if (act) {
+                float x, m1, v1;
+                if (MODE == kAdam) {
+                    x = w[u];
+                    if (dd > 0) x = restore1(x, m[u], v[u], a.Wrow[dd], lr, a.eps, a.rb);
+                    m1 = a.Mf[dd] * m[u] + a.omb1 * g[u];
+                    v1 = a.Vf[dd] * v[u] + (a.omb2 * g[u]) * g[u];
                     const float den = sqrtf(v1) / bc + a.eps;
                     x = x - (step * m1) / den;
-                    if (isG) {
-                        a.gw[r * a.gw_ld + lane] = x;
-                        a.gm[r * a.gm_ld + lane] = m1;
-                        a.gv[r * a.gv_ld + lane] = v1;
-                    } else {
-                        a.aw[r * a.aw_ld + ca] = x;
-                        a.am[r * a.am_ld + ca] = m1;
-                        a.av[r * a.av_ld + ca] = v1;
-                    }
-                    if (!a.g_geo && base + u < nvis) {
-                        if (isG) a.gd_geo[r * 10 + lane] = 0.0f;
-                        else a.gd_app[r * a.adim + ca] = 0.0f;
-                    }
+                } else {
+                    x = restore1(w[u], m[u], v[u], a.Wrow[dd], lr, a.eps, a.rb);
+                    m1 = a.Mf[dd - 1] * m[u];
+                    v1 = a.Vf[dd - 1] * v[u];
                 }
-                if (lane == 0) a.last[r] = a.t;
-            } else {  // flush
-                const int dl = d[u];
-                if (dl > 0) {
-                    if (act) {
-                        const float x = restore1(w[u], m[u], v[u], a.Wrow[dl], lr, a.eps);
-                        const float m1 = a.Mf[dl - 1] * m[u];
-                        const float v1 = a.Vf[dl - 1] * v[u];
-                        if (isG) {
-                            a.gw[r * a.gw_ld + lane] = x;
-                            a.gm[r * a.gm_ld + lane] = m1;
-                            a.gv[r * a.gv_ld + lane] = v1;
-                        } else {
-                            a.aw[r * a.aw_ld + ca] = x;
-                            a.am[r * a.am_ld + ca] = m1;
-                            a.av[r * a.av_ld + ca] = v1;
-                        }
-                    }
-                    if (lane == 0) a.last[r] = a.t;
+                u32 rm = 0, rv = 0;
+                if (quant) {
+                    const u64 h = sm_at(sm_at(s_step, (u64)r), (u64)lane);
+                    rm = (u32)(h & 0xffffull);
+                    rv = (u32)((h >> 16) & 0xffffull);
+                }
+                if (isG) {
+                    a.gw[r * a.gw_ld + lane] = x;
+                    mom_store<GST>(a.gm, r * a.gm_ld + lane, m1, rm);
+                    mom_store<GST>(a.gv, r * a.gv_ld + lane, v1, rv);
+                } else {
+                    a.aw[r * a.aw_ld + ca] = x;
+                    mom_store<AST>(a.am, r * a.am_ld + ca, m1, rm);
+                    mom_store<AST>(a.av, r * a.av_ld + ca, v1, rv);
+                }
+                if (MODE == kAdam && !a.g_geo && base + u < nvis) {
+                    if (isG) a.gd_geo[r * 10 + lane] = 0.0f;
+                    else a.gd_app[r * a.adim + ca] = 0.0f;
                 }
             }
+            if (lane == 0) a.last[r] = a.t;
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// dense geometric Adam (geo_mode = 1): every row's 10 G columns, every step
+// ---------------------------------------------------------------------------
+struct DenseArgs {
+    float *w;
+    void *m, *v;
+    int64_t m_ld, v_ld, n;
+    int32_t t, pad0;
+    float lr[10];
+    float eps, omb1, omb2, b1f, b2f, pad1;
+    const float *SS, *BC;
+    u64 sr_seed;
+    const float *g_geo;              // compact gradients of the cull's visible rows, or NULL
+    const u64 *keep_bits;            // the cull's keep ballots
+    const u64 *st0;                  // tile states [2][tiles]
+    const gsdp::WsHeader *hdr;
+    int64_t tiles;
+    u32 cap, pad2;
+    float *gd_geo;                   // dense [n][10] gradients (read and cleared) when g_geo is NULL
+};
+
+// One block per cull tile (512 rows x 10 columns, element-parallel and
+// coalesced).  The compact index of a visible row is the tile's exclusive
+// prefix (from the cull's look-back states) + the keep bits before it.
+template <int GST>
+__global__ __launch_bounds__(256) void k_dense_geo(DenseArgs a)
+{
+    __shared__ u64 sBits[gsdp::kWordsPerTile];
+    __shared__ u32 sOff[gsdp::kWordsPerTile];
+    __shared__ u32 sExcl;
+    const int tid = threadIdx.x;
+    const int64_t tile = blockIdx.x;
+    const int64_t row0 = tile * kCullTile;
+    const int rows = (int)min((int64_t)kCullTile, a.n - row0);
+    if (a.g_geo) {
+        if (tid < gsdp::kWordsPerTile) sBits[tid] = a.keep_bits[tile * gsdp::kWordsPerTile + tid];
+        if (tid == 0) {
+            const u32 used = (__hip_atomic_load(&a.hdr->parity, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ^ 1u) & 1u;
+            const u64 *st = a.st0 + (size_t)used * a.tiles;
+            sExcl = tile == 0 ? 0u : (u32)((st[tile - 1] >> 31) & 0x7fffffffull);
+        }
+        __syncthreads();
+        if (tid == 0) {
+            u32 o = 0;
+            for (int j = 0; j < gsdp::kWordsPerTile; ++j) {
+                sOff[j] = o;
+                o += (u32)__popcll(sBits[j]);
+            }
+        }
+        __syncthreads();
+    }
+    const float ss = a.SS[a.t], bc = a.BC[a.t];
+    const u64 s_step = GST != GS_F32 ? sm_at(a.sr_seed, (u64)a.t) : 0ull;
+    for (int e = tid; e < rows * 10; e += 256) {
+        const int r = e / 10, c = e - r * 10;
+        const int64_t row = row0 + r;
+        float g = 0.0f;
+        if (a.g_geo) {
+            const int word = (r >> 8) * 4 + ((r & 255) >> 6), bit = r & 63;
+            const u64 bw = sBits[word];
+            if ((bw >> bit) & 1ull) {
+                const u32 rank = sExcl + sOff[word] + (u32)__popcll(bw & ((1ull << bit) - 1ull));
+                if (rank < a.cap) g = a.g_geo[(int64_t)rank * 10 + c];
+            }
+        } else {
+            g = a.gd_geo[row * 10 + c];
+            a.gd_geo[row * 10 + c] = 0.0f;
+        }
+        const float mm = mom_load<GST>(a.m, row * a.m_ld + c), vv = mom_load<GST>(a.v, row * a.v_ld + c);
+        const float m1 = a.b1f * mm + a.omb1 * g;
+        const float v1 = a.b2f * vv + (a.omb2 * g) * g;
+        const float den = sqrtf(v1) / bc + a.eps;
+        const float lr = a.lr[c];
+        a.w[row * 10 + c] = a.w[row * 10 + c] - ((lr * ss) * m1) / den;
+        u32 rm = 0, rv = 0;
+        if (GST != GS_F32) {
+            const u64 h = sm_at(sm_at(s_step, (u64)row), (u64)c);
+            rm = (u32)(h & 0xffffull);
+            rv = (u32)((h >> 16) & 0xffffull);
+        }
+        mom_store<GST>(a.m, row * a.m_ld + c, m1, rm);
+        mom_store<GST>(a.v, row * a.v_ld + c, v1, rv);
     }
 }
 
@@ -555,14 +770,6 @@ __global__ __launch_bounds__(256) void k_scatter(const u32 *ids, const u32 *coun
         *dst = acc ? *dst + val : val;
     }
 }
-
-__device__ __forceinline__ u64 mix64(u64 z)
-{
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    return z ^ (z >> 31);
-}
-__device__ __forceinline__ u64 sm_at(u64 s, u64 i) { return mix64(s + (i + 1ull) * 0x9E3779B97F4A7C15ull); }
 
 __global__ __launch_bounds__(256) void k_synth(u64 seed, u64 step, const u32 *ids, const u32 *count, u32 cap,
                                                int dim, int col0, double scale, float *out)
@@ -614,14 +821,25 @@ int cu_count()
 
 bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
+// Clamp of the restore factor: 1.03 x (1-b1)/sqrt((1-b2)(1-b1^2/b2)) in FP32
+// (+inf when b1^2 >= b2, where Adam moments have no such bound).
+float restore_bound(double b1, double b2)
+{
+    if (!(b1 * b1 < b2)) return INFINITY;
+    return (float)((1.0 - b1) / std::sqrt((1.0 - b2) * (1.0 - b1 * b1 / b2)) * 1.03);
+}
+
+size_t mom_bytes(int state) { return state == GS_F32 ? 4 : 2; }
+
 int check_group(const gs_group &g, int64_t n, bool geo)
 {
     if (geo && g.dim != 10) return GS_EINVAL;
     if (!geo && (g.dim < 1 || g.dim > 54)) return GS_EINVAL;
     if (g.w_ld < g.dim || g.m_ld < g.dim || g.v_ld < g.dim) return GS_EINVAL;
-    if (g.state != GS_F32) return GS_EUNSUPPORTED;
+    if (g.state != GS_F32 && g.state != GS_BF16) return GS_EUNSUPPORTED;
     if (n > 0 && (!g.w || !g.m || !g.v)) return GS_EINVAL;
-    if (!aligned(g.w, 4) || !aligned(g.m, 4) || !aligned(g.v, 4)) return GS_EINVAL;
+    if (!aligned(g.w, 4) || !aligned(g.m, mom_bytes(g.state)) || !aligned(g.v, mom_bytes(g.state)))
+        return GS_EINVAL;
     return GS_OK;
 }
 
@@ -638,6 +856,7 @@ int check_model(const gs_model *m)
     if (!m->lut || m->lut_max_steps < 1 || m->max_defer < 0) return GS_EINVAL;
     if (!(m->beta1 > 0.0 && m->beta1 < 1.0 && m->beta2 > 0.0 && m->beta2 < 1.0 && m->eps >= 0.0)) return GS_EINVAL;
     if (m->cull_mode != 0 && m->cull_mode != 1) return GS_EINVAL;
+    if (m->geo_mode != 0 && m->geo_mode != 1) return GS_EINVAL;
     return GS_OK;
 }
 
@@ -663,14 +882,14 @@ void fill_rows(RowArgs &a, const gs_model *m)
 {
     memset(&a, 0, sizeof a);
     a.gw = m->geo.w;
-    a.gm = static_cast<float *>(m->geo.m);
-    a.gv = static_cast<float *>(m->geo.v);
+    a.gm = m->geo.m;
+    a.gv = m->geo.v;
     a.gw_ld = m->geo.w_ld;
     a.gm_ld = m->geo.m_ld;
     a.gv_ld = m->geo.v_ld;
     a.aw = m->app.w;
-    a.am = static_cast<float *>(m->app.m);
-    a.av = static_cast<float *>(m->app.v);
+    a.am = m->app.m;
+    a.av = m->app.v;
     a.aw_ld = m->app.w_ld;
     a.am_ld = m->app.m_ld;
     a.av_ld = m->app.v_ld;
@@ -681,8 +900,22 @@ void fill_rows(RowArgs &a, const gs_model *m)
     a.eps = (float)m->eps;
     a.omb1 = (float)(1.0 - m->beta1);
     a.omb2 = (float)(1.0 - m->beta2);
+    a.rb = restore_bound(m->beta1, m->beta2);
+    a.sr_seed = m->sr_seed;
+    a.geo_dense = m->geo_mode == 1;
     a.last = m->last_step;
     a.n = m->n;
+}
+
+// Launch k_rows<MODE> for the moment storage types of the model's groups.
+template <int MODE>
+void launch_rows(const gs_model *m, int grid, hipStream_t st, const RowArgs &a)
+{
+    const int g = m->geo.state, p = m->app.state;
+    if (g == GS_F32 && p == GS_F32) hipLaunchKernelGGL((k_rows<MODE, GS_F32, GS_F32>), dim3(grid), dim3(256), 0, st, a);
+    else if (g == GS_F32 && p == GS_BF16) hipLaunchKernelGGL((k_rows<MODE, GS_F32, GS_BF16>), dim3(grid), dim3(256), 0, st, a);
+    else if (g == GS_BF16 && p == GS_F32) hipLaunchKernelGGL((k_rows<MODE, GS_BF16, GS_F32>), dim3(grid), dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((k_rows<MODE, GS_BF16, GS_BF16>), dim3(grid), dim3(256), 0, st, a);
 }
 
 int row_grid(int64_t rows)
@@ -757,7 +990,7 @@ int gs_lut_build(double beta1, double beta2, int32_t max_steps, int32_t max_defe
 int gs_workspace_bytes(const gs_model *model, size_t *bytes)
 {
     if (!model || !bytes || model->n < 0 || model->max_defer < 0) return GS_EINVAL;
-    *bytes = (size_t)gsdp::ws_bytes_for(model->n, model->max_defer);
+    *bytes = (size_t)gsdp::ws_bytes_for(model->n, model->max_defer, model->geo_mode);
     return GS_OK;
 }
 
@@ -770,15 +1003,17 @@ int gs_cull(const gs_model *model, const gs_camera *cam, int64_t step, uint32_t 
     if (step < 1 || step > model->lut_max_steps) return GS_EINVAL;
     if (!(cam->fx > 0.0f && cam->fy > 0.0f) || cam->width <= 0 || cam->height <= 0) return GS_EINVAL;
     if (!aligned(ws, 256)) return GS_EINVAL;
-    if ((int64_t)ws_bytes < gsdp::ws_bytes_for(model->n, model->max_defer)) return GS_ESPACE;
+    if ((int64_t)ws_bytes < gsdp::ws_bytes_for(model->n, model->max_defer, model->geo_mode)) return GS_ESPACE;
 
     CullArgs a;
     memset(&a, 0, sizeof a);
     a.gw = model->geo.w;
-    a.gm = static_cast<const float *>(model->geo.m);
-    a.gv = static_cast<const float *>(model->geo.v);
+    a.gm = model->geo.m;
+    a.gv = model->geo.v;
     a.m_ld = model->geo.m_ld;
     a.v_ld = model->geo.v_ld;
+    a.gst = model->geo.state;
+    a.rb = restore_bound(model->beta1, model->beta2);
     a.last = model->last_step;
     a.n = model->n;
     a.t = (int32_t)step;
@@ -797,6 +1032,27 @@ int gs_cull(const gs_model *model, const gs_camera *cam, int64_t step, uint32_t 
     a.cam.H = (float)cam->height;
     a.cam.zn = cam->near_plane;
     a.cam.zf = cam->far_plane;
+    // band classifier constants; the band cull needs eps > 0 (with eps = 0 a
+    // row with m = v = 0 restores to NaN) and falls back to the exact cull
+    a.mode = (model->cull_mode == 1 && model->eps > 0.0 && std::isfinite(a.rb)) ? 1 : 0;
+    {
+        const double B = (double)a.rb * 1.001;
+        auto mx = [&](int lo, int hi) {
+            double v = 0.0;
+            for (int c = lo; c < hi; ++c) v = std::max(v, (double)std::fabs(model->geo.lr[c]));
+            return (float)(B * v * (1.0 + 1e-6));
+        };
+        a.band.kpos = mx(0, 3);
+        a.band.kscl = mx(3, 6);
+        a.band.kq = mx(6, 10);
+        a.band.rs0 = (float)((std::fabs((double)cam->R[0]) + std::fabs((double)cam->R[1]) + std::fabs((double)cam->R[2])) * (1 + 1e-6));
+        a.band.rs1 = (float)((std::fabs((double)cam->R[3]) + std::fabs((double)cam->R[4]) + std::fabs((double)cam->R[5])) * (1 + 1e-6));
+        a.band.rs2 = (float)((std::fabs((double)cam->R[6]) + std::fabs((double)cam->R[7]) + std::fabs((double)cam->R[8])) * (1 + 1e-6));
+        const float limx = 1.3f * ((0.5f * (float)cam->width) / cam->fx);
+        const float limy = 1.3f * ((0.5f * (float)cam->height) / cam->fy);
+        const double fx = cam->fx, fy = cam->fy;
+        a.band.jf2 = (float)((fx * fx * (1.0 + (double)limx * limx) + fy * fy * (1.0 + (double)limy * limy)) * (1.0 + 1e-4));
+    }
     a.ids = ids;
     a.count = count_dev;
     a.cap = capacity;
@@ -804,20 +1060,16 @@ int gs_cull(const gs_model *model, const gs_camera *cam, int64_t step, uint32_t 
     a.hdr = reinterpret_cast<gsdp::WsHeader *>(wsb);
     a.tiles = gsdp::cull_tiles(model->n);
     a.st = reinterpret_cast<u64 *>(wsb + gsdp::kWsHeader);
-    a.sat_ids = model->max_defer > 0 ? reinterpret_cast<u32 *>(wsb + gsdp::kWsHeader + 16 * a.tiles) : nullptr;
+    a.sat_ids = model->max_defer > 0 ? reinterpret_cast<u32 *>(wsb + gsdp::ws_sat_offset(model->n)) : nullptr;
+    a.geo_dense = model->geo_mode == 1;
+    a.keep_bits = a.geo_dense ? reinterpret_cast<u64 *>(wsb + gsdp::ws_bits_offset(model->n, model->max_defer))
+                              : nullptr;
 
-    // persistent grid: as many blocks as can be resident at once
-    static std::atomic<int> s_cull_occ{0};
-    int occ = s_cull_occ.load(std::memory_order_relaxed);
-    if (occ == 0) {
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_cull, kCullBlock, 0) != hipSuccess || occ < 1)
-            occ = 1;
-        s_cull_occ.store(occ, std::memory_order_relaxed);
-    }
-    const int cu = cu_count();
-    int64_t grid = (int64_t)(cu > 0 ? cu : 256) * occ;
-    if (grid > a.tiles) grid = a.tiles;
+    // one block per tile; blocks take tiles in ticket order, so a block only
+    // ever waits on tiles already claimed by running blocks
+    int64_t grid = a.tiles;
     if (grid < 1) grid = 1;
+    if (grid > 0x7fffffff) return GS_EINVAL;
     hipLaunchKernelGGL(k_cull, dim3((unsigned)grid), dim3(kCullBlock), 0, (hipStream_t)stream, a);
     return launched("gs_cull");
 }
@@ -840,7 +1092,7 @@ int gs_gather(const gs_model *model, int64_t step, const uint32_t *ids, const ui
     a.cap = capacity;
     a.out_geo = out_geo;
     a.out_app = out_app;
-    hipLaunchKernelGGL(k_rows<kGather>, dim3(row_grid(capacity)), dim3(256), 0, (hipStream_t)stream, a);
+    launch_rows<kGather>(model, row_grid(capacity), (hipStream_t)stream, a);
     return launched("gs_gather");
 }
 
@@ -869,9 +1121,10 @@ int gs_adam_step_deferred(const gs_model *model, int64_t step, const uint32_t *i
     const bool compact = g_geo || g_app;
     if (compact && (!g_geo || !g_app)) return GS_EINVAL;
     if (!compact && capacity > 0 && (!g_geo_dense || !g_app_dense)) return GS_EINVAL;
-    if (model->max_defer > 0) {
+    const bool geo_dense = model->geo_mode == 1;
+    if (model->max_defer > 0 || (geo_dense && compact)) {
         if (!ws || !aligned(ws, 256)) return GS_EINVAL;
-        if ((int64_t)ws_bytes < gsdp::ws_bytes_for(model->n, model->max_defer)) return GS_ESPACE;
+        if ((int64_t)ws_bytes < gsdp::ws_bytes_for(model->n, model->max_defer, model->geo_mode)) return GS_ESPACE;
     }
     RowArgs a;
     fill_rows(a, model);
@@ -894,10 +1147,47 @@ int gs_adam_step_deferred(const gs_model *model, int64_t step, const uint32_t *i
     if (model->max_defer > 0) {
         char *wsb = static_cast<char *>(ws);
         a.sat_count = &reinterpret_cast<gsdp::WsHeader *>(wsb)->sat_total;
-        a.sat_ids = reinterpret_cast<const u32 *>(wsb + gsdp::kWsHeader + 16 * gsdp::cull_tiles(model->n));
+        a.sat_ids = reinterpret_cast<const u32 *>(wsb + gsdp::ws_sat_offset(model->n));
         rows += model->n;
     }
-    hipLaunchKernelGGL(k_rows<kAdam>, dim3(row_grid(rows)), dim3(256), 0, (hipStream_t)stream, a);
+    if (geo_dense && model->n > 0) {
+        DenseArgs da;
+        memset(&da, 0, sizeof da);
+        da.w = model->geo.w;
+        da.m = model->geo.m;
+        da.v = model->geo.v;
+        da.m_ld = model->geo.m_ld;
+        da.v_ld = model->geo.v_ld;
+        da.n = model->n;
+        da.t = (int32_t)step;
+        for (int c = 0; c < 10; ++c) da.lr[c] = model->geo.lr[c];
+        da.eps = (float)model->eps;
+        da.omb1 = (float)(1.0 - model->beta1);
+        da.omb2 = (float)(1.0 - model->beta2);
+        // b^(0+1) of the tables, i.e. the FP32 rounding of b (a d = 0 step)
+        da.b1f = (float)model->beta1;
+        da.b2f = (float)model->beta2;
+        da.SS = L.SS;
+        da.BC = L.BC;
+        da.sr_seed = model->sr_seed;
+        da.g_geo = g_geo;
+        da.gd_geo = g_geo_dense;
+        da.cap = capacity;
+        da.tiles = gsdp::cull_tiles(model->n);
+        if (compact) {
+            char *wsb = static_cast<char *>(ws);
+            da.hdr = reinterpret_cast<const gsdp::WsHeader *>(wsb);
+            da.st0 = reinterpret_cast<const u64 *>(wsb + gsdp::kWsHeader);
+            da.keep_bits = reinterpret_cast<const u64 *>(wsb + gsdp::ws_bits_offset(model->n, model->max_defer));
+        }
+        if (model->geo.state == GS_F32)
+            hipLaunchKernelGGL(k_dense_geo<GS_F32>, dim3((unsigned)da.tiles), dim3(256), 0, (hipStream_t)stream, da);
+        else
+            hipLaunchKernelGGL(k_dense_geo<GS_BF16>, dim3((unsigned)da.tiles), dim3(256), 0, (hipStream_t)stream, da);
+        int rc2 = launched("gs_adam_step_deferred (dense geometry)");
+        if (rc2) return rc2;
+    }
+    launch_rows<kAdam>(model, row_grid(rows), (hipStream_t)stream, a);
     return launched("gs_adam_step_deferred");
 }
 
@@ -915,7 +1205,7 @@ int gs_adam_flush(const gs_model *model, int64_t step, void *stream)
     a.Wrow = L.W;
     a.Mf = L.Mf;
     a.Vf = L.Vf;
-    hipLaunchKernelGGL(k_rows<kFlush>, dim3(row_grid(model->n)), dim3(256), 0, (hipStream_t)stream, a);
+    launch_rows<kFlush>(model, row_grid(model->n), (hipStream_t)stream, a);
     return launched("gs_adam_flush");
 }
 

@@ -33,12 +33,13 @@ inline LutLayout lut_layout(int64_t T, int64_t K)
 // Offset of W row t (t >= 1).
 inline int64_t lut_w_row(int64_t t, int64_t K) { return K > 0 ? (t - 1) * (K + 1) : t * (t - 1) / 2; }
 
-// Cull tiles: 256 threads x 4 rows.
+// Cull tiles: 256 threads x 2 rows (512 rows, 20 KB of geometry in LDS).
 constexpr int kCullBlock = 256;
-constexpr int kCullIpt = 4;
+constexpr int kCullIpt = 2;
 constexpr int kCullTile = kCullBlock * kCullIpt;
 
-// Workspace layout (bytes): header | tile states [2][tiles] (u64) | saturated ids [n] (u32)
+// Workspace layout (bytes): header | tile states [2][tiles] (u64) | saturated ids [n] (u32,
+// max_defer > 0) | keep ballots [tiles][8] (u64, dense-geometry mode)
 constexpr int64_t kWsHeader = 256;
 struct WsHeader {
     uint32_t ticket;     // next cull tile to hand out
@@ -54,10 +55,16 @@ struct WsHeader {
 };
 
 inline int64_t cull_tiles(int64_t n) { return (n + kCullTile - 1) / kCullTile; }
-inline int64_t ws_bytes_for(int64_t n, int32_t K)
+constexpr int kWordsPerTile = kCullTile / 64;
+inline int64_t ws_sat_offset(int64_t n) { return kWsHeader + 16 * cull_tiles(n); }
+inline int64_t ws_bits_offset(int64_t n, int32_t K)
 {
-    int64_t b = kWsHeader + 16 * cull_tiles(n);
-    if (K > 0) b += 4 * n;
+    int64_t b = ws_sat_offset(n) + (K > 0 ? 4 * n : 0);
+    return (b + 7) / 8 * 8;
+}
+inline int64_t ws_bytes_for(int64_t n, int32_t K, int32_t geo_dense)
+{
+    int64_t b = ws_bits_offset(n, K) + (geo_dense ? 8 * kWordsPerTile * cull_tiles(n) : 0);
     return (b + 255) / 256 * 256;
 }
 

@@ -42,7 +42,8 @@ class GsModel(C.Structure):
     _fields_ = [("n", C.c_int64), ("geo", GsGroup), ("app", GsGroup), ("last_step", C.c_void_p),
                 ("lut", C.c_void_p), ("lut_max_steps", C.c_int32), ("max_defer", C.c_int32),
                 ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double),
-                ("cull_mode", C.c_int32), ("reserved_", C.c_int32 * 3)]
+                ("cull_mode", C.c_int32), ("geo_mode", C.c_int32), ("sr_seed", C.c_uint64),
+                ("reserved_", C.c_int32 * 4)]
 
 
 def _load():
@@ -149,37 +150,45 @@ class Model:
     """Device-resident parameters, Adam moments, per-row last step, tables and
     workspace of one set of Gaussians, plus the gs_model struct describing them.
 
+    geo_state / app_state: "f32" or "bf16" storage of the Adam moments.
     app_layout "separate": w, m, v of A are three [n, dim] tensors.
-               "interleaved": one [n, row] tensor per Gaussian holding w | m | v
-               (row = 3*dim padded to a multiple of 32 floats), so the random
-               row accesses of gather and Adam touch one contiguous span.
+               "interleaved": one byte row per Gaussian holding w | m | v
+               (padded to a multiple of 64 bytes), so the random row accesses of
+               gather and Adam touch one contiguous span.
     """
 
     def __init__(self, geo, app, lr_geo, lr_app, *, beta1=0.9, beta2=0.999, eps=1e-15, max_defer=0,
-                 max_steps=1000, cull_mode=0, app_layout="separate", device=None):
+                 max_steps=1000, cull_mode=0, app_layout="separate", geo_state="f32", app_state="f32",
+                 sr_seed=0, geo_mode=0, device=None):
         device = device or torch.device("cuda")
         geo = torch.as_tensor(geo, dtype=torch.float32)
         app = torch.as_tensor(app, dtype=torch.float32)
         n, adim = geo.shape[0], app.shape[1]
         assert geo.shape == (n, 10) and app.shape[0] == n
         self.n, self.adim, self.device = n, adim, device
+        sdt = {"f32": (torch.float32, GS_F32, 4), "bf16": (torch.bfloat16, GS_BF16, 2)}
+        gdt, gcode, _ = sdt[geo_state]
+        adt, acode, asz = sdt[app_state]
+        self.geo_state, self.app_state = geo_state, app_state
         self.geo_w = geo.to(device).contiguous()
-        self.geo_m = torch.zeros((n, 10), dtype=torch.float32, device=device)
-        self.geo_v = torch.zeros((n, 10), dtype=torch.float32, device=device)
+        self.geo_m = torch.zeros((n, 10), dtype=gdt, device=device)
+        self.geo_v = torch.zeros((n, 10), dtype=gdt, device=device)
         self.app_layout = app_layout
         if app_layout == "separate":
             self.app_w = app.to(device).contiguous()
-            self.app_m = torch.zeros((n, adim), dtype=torch.float32, device=device)
-            self.app_v = torch.zeros((n, adim), dtype=torch.float32, device=device)
+            self.app_m = torch.zeros((n, adim), dtype=adt, device=device)
+            self.app_v = torch.zeros((n, adim), dtype=adt, device=device)
             ld = (adim, adim, adim)
         elif app_layout == "interleaved":
-            row = (3 * adim + 31) // 32 * 32
-            self.app_state = torch.zeros((n, row), dtype=torch.float32, device=device)
-            self.app_w = self.app_state[:, 0:adim]
-            self.app_m = self.app_state[:, adim:2 * adim]
-            self.app_v = self.app_state[:, 2 * adim:3 * adim]
+            wbytes, mbytes = 4 * adim, asz * adim
+            row = (wbytes + 2 * mbytes + 63) // 64 * 64
+            self.app_state_bytes = torch.zeros((n, row), dtype=torch.uint8, device=device)
+            st = self.app_state_bytes
+            self.app_w = st[:, 0:wbytes].view(torch.float32)
+            self.app_m = st[:, wbytes:wbytes + mbytes].view(adt)
+            self.app_v = st[:, wbytes + mbytes:wbytes + 2 * mbytes].view(adt)
             self.app_w.copy_(app.to(device))
-            ld = (row, row, row)
+            ld = (row // 4, row // asz, row // asz)
         else:
             raise ValueError(app_layout)
         self.last_step = torch.zeros(n, dtype=torch.int32, device=device)
@@ -192,13 +201,13 @@ class Model:
 
         c = GsModel()
         c.n = n
-        for grp, w, m, v, lds, lr, dim in ((c.geo, self.geo_w, self.geo_m, self.geo_v, (10, 10, 10),
-                                            self.lr_geo, 10),
-                                           (c.app, self.app_w, self.app_m, self.app_v, ld, self.lr_app, adim)):
+        for grp, w, m, v, lds, lr, dim, code in (
+                (c.geo, self.geo_w, self.geo_m, self.geo_v, (10, 10, 10), self.lr_geo, 10, gcode),
+                (c.app, self.app_w, self.app_m, self.app_v, ld, self.lr_app, adim, acode)):
             grp.w, grp.m, grp.v = w.data_ptr(), m.data_ptr(), v.data_ptr()
             grp.dim = dim
             grp.w_ld, grp.m_ld, grp.v_ld = lds
-            grp.state = GS_F32
+            grp.state = code
             for k in range(dim):
                 grp.lr[k] = float(lr[k])
         c.last_step = self.last_step.data_ptr()
@@ -207,6 +216,8 @@ class Model:
         c.max_defer = self.max_defer
         c.beta1, c.beta2, c.eps = float(beta1), float(beta2), float(eps)
         c.cull_mode = int(cull_mode)
+        c.sr_seed = int(sr_seed)
+        c.geo_mode = int(geo_mode)
         self.c = c
         self.ws = torch.zeros(gs_workspace_bytes(self) // 4, dtype=torch.int32, device=device)
 
@@ -222,10 +233,14 @@ class Model:
                 "restored_accum": int(q[1])}
 
     def state(self):
-        """Host copies: dict of geo/app w, m, v (float32) and last_step."""
+        """Host copies: geo/app w (float32), m, v (float32 or raw uint16 BF16 bits) and last_step."""
         out = {}
         for name in ("geo_w", "geo_m", "geo_v", "app_w", "app_m", "app_v"):
-            out[name] = getattr(self, name).contiguous().cpu().numpy()
+            t = getattr(self, name).contiguous()
+            if t.dtype == torch.bfloat16:
+                out[name] = t.view(torch.int16).cpu().numpy().view(np.uint16)
+            else:
+                out[name] = t.cpu().numpy()
         out["last_step"] = self.last_step.cpu().numpy()
         return out
 

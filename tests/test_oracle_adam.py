@@ -221,3 +221,47 @@ def test_saturation_forces_exactly_the_rows_at_max():
         forced_total += sat.shape[0]
     # at a 2% visible rate nearly every row is forced once every 16 steps
     assert forced_total > 0.8 * n * (steps - MAX) / (MAX + 1)
+
+
+def test_bf16_stochastic_rounding_is_unbiased_and_brackets():
+    """Averaged over all 2^16 random inputs, BF16 stochastic rounding returns
+    the FP32 value exactly; every result is one of the two BF16 neighbours."""
+    rng = np.random.default_rng(11)
+    f = orc.lib().orc_bf16_sr
+    xs = np.concatenate([rng.normal(0, 1e-3, 20), rng.normal(0, 1e3, 5), [1.0, -2.5, 3e-39, 6.1e-5]])
+    for x in xs.astype(np.float32):
+        outs = np.array([f(float(x), r) for r in range(0, 65536, 1)], np.uint16)
+        vals = (outs.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+        lo = (np.array([x], np.float32).view(np.uint32) & np.uint32(0xffff0000)).view(np.float32)[0]
+        assert set(np.unique(outs)).issubset({int(np.array([lo]).view(np.uint32)[0] >> 16),
+                                              int(np.array([lo]).view(np.uint32)[0] >> 16) + 1})
+        assert vals.mean() == pytest.approx(float(x), rel=1e-12, abs=1e-45)
+    inf = f(float("inf"), 12345)
+    assert inf == 0x7f80
+    assert f(float("nan"), 0) & 0x7f80 == 0x7f80
+
+
+def test_bf16_state_tracks_fp32_state():
+    """O4 (BF16 moments, stochastic rounding) stays within BF16-level error of
+    O3 (FP32 moments) over 30 steps; O3 with the dense-geometry split matches
+    dense FP64 Adam to FP32 rounding."""
+    n, steps = 2000, 30
+    s, lg, la = _scene(n, 12)
+    o3 = orc.DeferredF32(s.geo, s.app, lg, la)
+    o4 = orc.DeferredF32(s.geo, s.app, lg, la, state="bf16", sr_seed=3)
+    od = orc.DeferredF32(s.geo, s.app, lg, la, geo_dense=True)
+    dense = orc.DenseAdamF64(s.geo, s.app, lg, la)
+    for t, ids in enumerate(_vis_sequence(n, steps, 0.3, 13, first_all=False), start=1):
+        g = gi.step_grads(0, t, ids)
+        for mdl in (o3, o4, od, dense):
+            mdl.step(t, ids, *g)
+    for mdl in (o3, o4, od):
+        mdl.flush(steps)
+    for k, tau, lr in ((0, TAU_GEO, lg), (1, TAU_APP, la)):
+        # BF16 bound: within 2% of the largest possible movement lr * steps
+        err4 = np.abs(o4.w[k] - dense.w[k]) / (lr.astype(np.float64) * steps)
+        assert err4.max() < 2e-2
+        assert np.max(rel_err(od.w[k], dense.w[k], tau)) < 1e-6
+    m4, v4 = o4.moments_f32(1)
+    assert np.max(np.abs(m4 - o3.m[1])) < 0.02 * np.max(np.abs(o3.m[1]))
+    assert np.max(np.abs(v4 - o3.v[1]) / np.maximum(o3.v[1], 1e-30)) < 0.05

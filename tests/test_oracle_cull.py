@@ -1,6 +1,6 @@
 """Pins of the oracle's FP32 cull against geometry it does not compute itself.
 
-The cull formula is not printed in the paper (Sec. 2.3 step 1 only says what
+The cull formula is not printed in the paper (Sec. 2.4 step 1 only says what
 is culled); the oracle fixes it as the 3-sigma EWA screen box.  These tests
 pin that arithmetic against:
   * exact tangent-plane extents of the 3-sigma ellipsoid (FP64 closed form,
