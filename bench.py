@@ -38,6 +38,9 @@ def parse():
     p.add_argument("--layout", default="interleaved", choices=["separate", "interleaved"])
     p.add_argument("--max-defer", type=int, default=0)
     p.add_argument("--cull-mode", type=int, default=1)
+    p.add_argument("--state", default="f32", choices=["f32", "bf16"], help="Adam moment storage (both groups)")
+    p.add_argument("--geo-state", default=None, choices=["f32", "bf16"])
+    p.add_argument("--geo-mode", type=int, default=0, help="1 = dense geometric Adam every step")
     p.add_argument("--tilt", default="20,45", help="oblique tilt range in degrees")
     p.add_argument("--pool", type=int, default=4)
     p.add_argument("--no-cpu-baseline", action="store_true")
@@ -90,8 +93,10 @@ def main():
     sc = gi.make_scene(w.n, seed=0, box=w.scene_box)
     lg, la = gi.lr_columns()
     total_steps = args.warmup + args.steps
+    geo_state = args.geo_state or args.state
     model = gsdp.Model(sc.geo, sc.app, lg, la, max_steps=total_steps + 1, max_defer=args.max_defer,
-                       cull_mode=args.cull_mode, app_layout=args.layout)
+                       cull_mode=args.cull_mode, app_layout=args.layout, geo_state=geo_state,
+                       app_state=args.state, geo_mode=args.geo_mode, sr_seed=9)
     n = w.n
     cap = max(1, n // 4)
     dev = torch.device("cuda")
@@ -151,27 +156,32 @@ def main():
     M = vis_total / args.steps
     R = rest_total / args.steps
     f = M / n
-    # algorithmic bytes per launch
-    cull_bytes = 44.0 * n + 80.0 * R + 4.0 * M
-    gather_bytes = M * (4 + 4 + 236 + 472 + 236)       # ids, last, w, restore m/v, outputs
-    adam_bytes = M * (4 + 4 + 4 + 59 * 28)             # ids, last r/w, 7 x 4 B per column
+    # algorithmic bytes per launch (sg / sa: bytes per stored moment of G / A)
+    sg = 4 if geo_state == "f32" else 2
+    sa = 4 if args.state == "f32" else 2
+    gcols = 0 if args.geo_mode else 10                  # G columns handled by the sparse kernels
+    cull_bytes = 44.0 * n + 20.0 * sg * R + 4.0 * M
+    gather_bytes = M * (4 + 4 + 8 * 10 + 2 * sg * gcols + 8 * 49 + 2 * sa * 49)
+    adam_bytes = M * (4 + 4 + 4 + gcols * (12 + 4 * sg) + 49 * (12 + 4 * sa))
+    if args.geo_mode:                                   # dense G Adam over every row
+        adam_bytes += n * 10 * (8 + 4 * sg) + n / 8.0 + M * 40
     kernels = {"cull": (cull_ms, cull_bytes), "gather": (gather_ms, gather_bytes), "adam": (adam_ms, adam_bytes)}
     dom = max(kernels, key=lambda k: kernels[k][0])
     dms, dbytes = kernels[dom]
     achieved = dbytes / (dms * 1e-3) / 1e9
     out = {
-        "metric": "train-step Gaussians/s (cull+gather+Adam), FP32 state",
+        "metric": f"train-step Gaussians/s (cull+gather+Adam), {args.state.upper()} moment state",
         "value": n / (ms_step * 1e-3),
         "unit": "Gaussians/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32", "data": "synthetic",
+        "dtype": "f32" if args.state == "f32" else "f32 math, bf16 moments", "data": "synthetic",
         "config": {"workload": w.name, "n_gaussians": n, "cameras": len(w.cameras),
                    "image": f"{w.cameras[0].width}x{w.cameras[0].height}", "oblique_tilt_deg": list(tilt),
                    "visible_fraction": f, "visible_per_step": M, "restored_per_step": R,
-                   "state": "f32", "app_layout": args.layout, "max_defer": args.max_defer,
-                   "cull_mode": args.cull_mode},
+                   "state": args.state, "geo_state": geo_state, "app_layout": args.layout,
+                   "max_defer": args.max_defer, "cull_mode": args.cull_mode, "geo_mode": args.geo_mode},
         "kernels_ms": {"cull": cull_ms, "gather": gather_ms, "adam": adam_ms},
         "kernels_gbs": {k: v[1] / (v[0] * 1e-3) / 1e9 for k, v in kernels.items()},
         "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -71,8 +71,12 @@ typedef struct gs_group {
     void *v;               /* [n][v_ld] second moment */
     int32_t dim;           /* columns: 10 for G, 1..54 for A */
     int32_t w_ld, m_ld, v_ld;
-    int32_t state;         /* gs_dtype of m and v: GS_F32 or GS_BF16 (stochastic rounding) */
+    int32_t state;         /* gs_dtype of m and v: GS_F32, GS_BF16 (stochastic rounding) or
+                              GS_FP8E4M3 (E4M3 codes, sqrt(v) stored, one FP32 power-of-two
+                              scale per 128 rows, stochastic rounding) */
     int32_t pad_;
+    float *m_scale;        /* FP8 only: [ceil(n/128)] block scales of m, zero-initialised */
+    float *v_scale;        /* FP8 only: [ceil(n/128)] block scales of sqrt(v), zero-initialised */
     float lr[64];          /* learning rate of each column (dim entries used) */
 } gs_group;
 

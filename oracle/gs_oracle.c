@@ -418,6 +418,20 @@ static float restore32(float w, float m, float v, float wd, float lr, float eps,
     return w - wsc * q;
 }
 
+/* Adam step of one element: (st*m1) / (sqrt(v1)/bc + eps), with the step
+ * clamped to st*bc*rb.  For moments grown from zero |m1|/sqrt(v1) <= 7.27 < rb,
+ * so the clamp never acts on an FP32 state; it bounds the step when quantised
+ * moments lose the second moment to underflow. */
+static float adam_step32(float m1, float v1, float st, float bc, float eps, float rb)
+{
+    float den = sqrtf(v1) / bc + eps;
+    float upd = (st * m1) / den;
+    float lim = (st * bc) * rb;
+    if (upd > lim) upd = lim;
+    else if (upd < -lim) upd = -lim;
+    return upd;
+}
+
 /* O3/O4 update of the rows rows[j] (defer count d[j], FP32 compact gradient
  * g[j][:] or zero when g == NULL).  w is [n][ld] FP32; m, v are [n][ld] in the
  * given storage.  Global column of k is col0 + k (SR random stream). */
@@ -439,9 +453,8 @@ void orc_deferred_rows_f32(int dim, float *w, void *m, void *v, int state, int64
             if (dj > 0) wk = restore32(wk, mk, vk, Wf[dj], lr[k], eps32, rb);
             float m1 = Mf[dj] * mk + omb1 * gk;
             float v1 = Vf[dj] * vk + (omb2 * gk) * gk;
-            float den = sqrtf(v1) / bc + eps32;
             float st = lr[k] * ss;
-            w[e] = wk - (st * m1) / den;
+            w[e] = wk - adam_step32(m1, v1, st, bc, eps32, rb);
             uint64_t r = state ? sr_bits(seed, t, id, col0 + k) : 0;
             mom_store(m, state, e, m1, (uint32_t)(r & 0xffffu));
             mom_store(v, state, e, v1, (uint32_t)((r >> 16) & 0xffffu));
@@ -487,6 +500,181 @@ void orc_flush_rows_f32(int dim, float *w, void *m, void *v, int state, int64_t 
             uint64_t r = state ? sr_bits(seed, t, id, col0 + k) : 0;
             mom_store(m, state, e, Mf[dl - 1] * mk, (uint32_t)(r & 0xffffu));
             mom_store(v, state, e, Vf[dl - 1] * vk, (uint32_t)((r >> 16) & 0xffffu));
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Model O4 with FP8 moments: OCP E4M3FN codes (bias 7, largest finite 448, no
+ * Inf, NaN = S.1111.111) times one FP32 power-of-two scale per block of 128
+ * rows, per group and per moment.  A scale of 0 marks a block that has never
+ * held a nonzero moment. */
+#define FP8_BLOCK 128
+
+static float e4m3_decode(uint8_t b)
+{
+    int e = (b >> 3) & 0xf, m = b & 7;
+    if (e == 15 && m == 7) return NAN;
+    float a = e == 0 ? ldexpf((float)m, -9) : ldexpf((float)(8 + m), e - 10);
+    return (b & 0x80) ? -a : a;
+}
+
+/* Stochastic rounding of y to E4M3 with 16 random bits: magnitudes above 448
+ * saturate; within a binade of quantum q the value k*q + f*q rounds up with
+ * probability f (f*65536 > r16). */
+uint8_t orc_e4m3_sr(float y, uint32_t r16)
+{
+    if (isnan(y)) return 0x7f;
+    uint8_t sign = signbit(y) ? 0x80 : 0;
+    float a = fabsf(y);
+    if (a > 448.0f) a = 448.0f;
+    int e;
+    if (a < 0.015625f) {
+        e = -6;                          /* subnormal range: quantum 2^-9 */
+    } else {
+        uint32_t u;
+        memcpy(&u, &a, 4);
+        e = (int)((u >> 23) & 0xff) - 127;
+    }
+    float quantum = ldexpf(1.0f, e - 3);
+    float yq = a / quantum;
+    float k = floorf(yq);
+    float f = yq - k;
+    if (f * 65536.0f > (float)r16) k = k + 1.0f;
+    float val = k * quantum;
+    if (val == 0.0f) return sign;
+    if (val < 0.015625f) return (uint8_t)(sign | (uint8_t)(val / ldexpf(1.0f, -9)));
+    uint32_t u;
+    memcpy(&u, &val, 4);
+    int ev = (int)((u >> 23) & 0xff) - 127;
+    int mant = (int)(val / ldexpf(1.0f, ev) * 8.0f) - 8;
+    return (uint8_t)(sign | (uint8_t)((ev + 7) << 3) | (uint8_t)mant);
+}
+
+/* Smallest power of two p with amax / p <= 448 (amax / 448 rounded once). */
+float orc_fp8_scale_for(float amax)
+{
+    if (!(amax > 0.0f) || !(amax < INFINITY)) return 0.0f;
+    float r = amax / 448.0f;
+    int e;
+    float fr = frexpf(r, &e);            /* r = fr * 2^e, fr in [0.5, 1) */
+    return fr == 0.5f ? ldexpf(1.0f, e - 1) : ldexpf(1.0f, e);
+}
+
+static float fp8_load(const uint8_t *q, const float *s, int64_t row, int64_t e)
+{
+    return e4m3_decode(q[e]) * s[row / FP8_BLOCK];
+}
+
+/* The second moment is stored as its square root (halving its dynamic range
+ * in the 4-bit exponent); v = (code * scale)^2. */
+static float fp8_load_v(const uint8_t *q, const float *s, int64_t row, int64_t e)
+{
+    float r = e4m3_decode(q[e]) * s[row / FP8_BLOCK];
+    return r * r;
+}
+
+/* One update step of the rows rows[j] of a group with FP8 moments:
+ *  1. new moments of every update row in FP32, per-block max |m'|, |v'|;
+ *  2. every block whose max no longer fits (|x| > 448 s) gets the new scale
+ *     and all its rows are re-encoded (random column col0+k+64);
+ *  3. the update proper from the re-encoded moments: restore, Adam step,
+ *     moments encoded with the final scales (random column col0+k). */
+void orc_deferred_rows_fp8(int dim, float *w, uint8_t *mq, uint8_t *vq, float *ms, float *vs, int64_t ld,
+                           int64_t n, int64_t n_rows, const uint32_t *rows, const int64_t *d, const float *g,
+                           int64_t g_ld, const float *lr, double b1, double b2, double eps, const float *Wf,
+                           const float *Mf, const float *Vf, float ss, float bc, float rb, uint64_t seed,
+                           int64_t t, int col0)
+{
+    const float omb1 = (float)(1.0 - b1), omb2 = (float)(1.0 - b2), eps32 = (float)eps;
+    const int64_t nb = (n + FP8_BLOCK - 1) / FP8_BLOCK;
+    float *amax_m = (float *)calloc((size_t)nb, sizeof(float));
+    float *amax_v = (float *)calloc((size_t)nb, sizeof(float));
+    for (int64_t j = 0; j < n_rows; ++j) {
+        int64_t id = rows[j], dj = d[j], b = id / FP8_BLOCK;
+        for (int k = 0; k < dim; ++k) {
+            int64_t e = id * ld + k;
+            float gk = g ? g[j * g_ld + k] : 0.0f;
+            float m1 = Mf[dj] * fp8_load(mq, ms, id, e) + omb1 * gk;
+            float v1 = Vf[dj] * fp8_load_v(vq, vs, id, e) + (omb2 * gk) * gk;
+            float r1 = sqrtf(v1);
+            if (fabsf(m1) > 448.0f * ms[b] && fabsf(m1) > amax_m[b]) amax_m[b] = fabsf(m1);
+            if (r1 > 448.0f * vs[b] && r1 > amax_v[b]) amax_v[b] = r1;
+        }
+    }
+    for (int64_t b = 0; b < nb; ++b) {
+        for (int mv = 0; mv < 2; ++mv) {
+            float amax = mv ? amax_v[b] : amax_m[b];
+            float *sc = mv ? vs : ms;
+            uint8_t *q = mv ? vq : mq;
+            if (!(amax > 0.0f)) continue;
+            float snew = orc_fp8_scale_for(amax);
+            if (!(snew > sc[b])) continue;
+            for (int64_t id = b * FP8_BLOCK; id < (b + 1) * FP8_BLOCK && id < n; ++id)
+                for (int k = 0; k < dim; ++k) {
+                    int64_t e = id * ld + k;
+                    float x = e4m3_decode(q[e]) * sc[b];
+                    uint64_t r = sr_bits(seed, t, id, col0 + k + 64);
+                    q[e] = orc_e4m3_sr(x / snew, (uint32_t)((mv ? r >> 16 : r) & 0xffffu));
+                }
+            sc[b] = snew;
+        }
+    }
+    free(amax_m);
+    free(amax_v);
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < n_rows; ++j) {
+        int64_t id = rows[j], dj = d[j], b = id / FP8_BLOCK;
+        for (int k = 0; k < dim; ++k) {
+            int64_t e = id * ld + k;
+            float wk = w[e], mk = fp8_load(mq, ms, id, e), vk = fp8_load_v(vq, vs, id, e);
+            float gk = g ? g[j * g_ld + k] : 0.0f;
+            if (dj > 0) wk = restore32(wk, mk, vk, Wf[dj], lr[k], eps32, rb);
+            float m1 = Mf[dj] * mk + omb1 * gk;
+            float v1 = Vf[dj] * vk + (omb2 * gk) * gk;
+            float st = lr[k] * ss;
+            w[e] = wk - adam_step32(m1, v1, st, bc, eps32, rb);
+            uint64_t r = sr_bits(seed, t, id, col0 + k);
+            mq[e] = ms[b] > 0.0f ? orc_e4m3_sr(m1 / ms[b], (uint32_t)(r & 0xffffu)) : 0;
+            vq[e] = vs[b] > 0.0f ? orc_e4m3_sr(sqrtf(v1) / vs[b], (uint32_t)((r >> 16) & 0xffffu)) : 0;
+        }
+    }
+}
+
+void orc_restore_rows_fp8(int dim, const float *w, const uint8_t *mq, const uint8_t *vq, const float *ms,
+                          const float *vs, int64_t ld, int64_t n_rows, const uint32_t *rows, const int64_t *d,
+                          const float *lr, double eps, const float *Wf, float rb, float *out)
+{
+    const float eps32 = (float)eps;
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < n_rows; ++j) {
+        int64_t id = rows[j];
+        for (int k = 0; k < dim; ++k) {
+            int64_t e = id * ld + k;
+            float wk = w[e];
+            if (d[j] > 0)
+                wk = restore32(wk, fp8_load(mq, ms, id, e), fp8_load_v(vq, vs, id, e), Wf[d[j]], lr[k], eps32, rb);
+            out[j * dim + k] = wk;
+        }
+    }
+}
+
+void orc_flush_rows_fp8(int dim, float *w, uint8_t *mq, uint8_t *vq, const float *ms, const float *vs,
+                        int64_t ld, int64_t n_rows, const uint32_t *rows, const int64_t *delta, const float *lr,
+                        double eps, const float *Wf_next, const float *Mf, const float *Vf, float rb, uint64_t seed,
+                        int64_t t, int col0)
+{
+    const float eps32 = (float)eps;
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < n_rows; ++j) {
+        int64_t id = rows[j], dl = delta[j], b = id / FP8_BLOCK;
+        for (int k = 0; k < dim; ++k) {
+            int64_t e = id * ld + k;
+            float mk = fp8_load(mq, ms, id, e), vk = fp8_load_v(vq, vs, id, e);
+            w[e] = restore32(w[e], mk, vk, Wf_next[dl], lr[k], eps32, rb);
+            uint64_t r = sr_bits(seed, t, id, col0 + k);
+            mq[e] = ms[b] > 0.0f ? orc_e4m3_sr(Mf[dl - 1] * mk / ms[b], (uint32_t)(r & 0xffffu)) : 0;
+            vq[e] = vs[b] > 0.0f ? orc_e4m3_sr(sqrtf(Vf[dl - 1] * vk) / vs[b], (uint32_t)((r >> 16) & 0xffffu)) : 0;
         }
     }
 }

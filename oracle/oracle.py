@@ -67,6 +67,13 @@ def lib():
             "orc_lut_spec": (None, [f64, f64, i64, i32, vp, vp, vp, vp, vp]),
             "orc_restore_bound": (f32, [f64, f64]),
             "orc_bf16_sr": (C.c_uint16, [f32, C.c_uint32]),
+            "orc_e4m3_sr": (C.c_uint8, [f32, C.c_uint32]),
+            "orc_fp8_scale_for": (f32, [f32]),
+            "orc_deferred_rows_fp8": (None, [i32, vp, vp, vp, vp, vp, i64, i64, i64, vp, vp, vp, i64, vp,
+                                             f64, f64, f64, vp, vp, vp, f32, f32, f32, C.c_uint64, i64, i32]),
+            "orc_restore_rows_fp8": (None, [i32, vp, vp, vp, vp, vp, i64, i64, vp, vp, vp, f64, vp, f32, vp]),
+            "orc_flush_rows_fp8": (None, [i32, vp, vp, vp, vp, vp, i64, i64, vp, vp, vp, f64, vp, vp, vp, f32,
+                                          C.c_uint64, i64, i32]),
             "orc_deferred_rows_f32": (None, [i32, vp, vp, vp, i32, i64, i64, vp, vp, vp, i64, vp,
                                              f64, f64, f64, vp, vp, vp, f32, f32, f32, C.c_uint64, i64, i32]),
             "orc_restore_rows_f32": (None, [i32, vp, vp, vp, i32, i64, i64, vp, vp, vp, f64, vp, f32, vp]),
@@ -263,7 +270,17 @@ def restore_bound(b1: float, b2: float) -> np.float32:
     return np.float32(lib().orc_restore_bound(b1, b2))
 
 
-STATES = {"f32": (0, np.float32), "bf16": (1, np.uint16)}
+STATES = {"f32": (0, np.float32), "bf16": (1, np.uint16), "fp8": (2, np.uint8)}
+FP8_BLOCK = 128
+
+
+def e4m3_decode(codes: np.ndarray) -> np.ndarray:
+    """FP32 values of E4M3FN codes (bias 7, max 448, NaN = S.1111.111)."""
+    c = np.asarray(codes, np.uint8).astype(np.int32)
+    e, m = (c >> 3) & 15, c & 7
+    a = np.where(e == 0, m * 2.0 ** -9, (8 + m) * 2.0 ** (e - 10.0))
+    a = np.where((e == 15) & (m == 7), np.nan, a)
+    return np.where(c & 0x80, -a, a).astype(np.float32)
 
 
 class DeferredF32(_Deferred):
@@ -284,6 +301,9 @@ class DeferredF32(_Deferred):
         self.w = [np.array(geo, np.float32), np.array(app, np.float32)]
         self.m = [np.zeros(x.shape, STATES[st][1]) for x, st in zip(self.w, states)]
         self.v = [np.zeros(x.shape, STATES[st][1]) for x, st in zip(self.w, states)]
+        nb = (geo.shape[0] + FP8_BLOCK - 1) // FP8_BLOCK
+        self.ms = [np.zeros(nb, np.float32), np.zeros(nb, np.float32)]
+        self.vs = [np.zeros(nb, np.float32), np.zeros(nb, np.float32)]
         self.lr = [np.asarray(lr_geo, np.float32), np.asarray(lr_app, np.float32)]
         self.b1, self.b2, self.eps = b1, b2, eps
         self.rb = float(restore_bound(b1, b2))
@@ -297,6 +317,11 @@ class DeferredF32(_Deferred):
         """FP32 view of the stored moments of group k."""
         if self.sid[k] == 0:
             return self.m[k], self.v[k]
+        if self.sid[k] == 2:
+            blk = np.arange(self.m[k].shape[0]) // FP8_BLOCK
+            # the second moment is stored as its square root
+            return (e4m3_decode(self.m[k]) * self.ms[k][blk][:, None],
+                    (e4m3_decode(self.v[k]) * self.vs[k][blk][:, None]) ** 2)
         conv = lambda a: (a.astype(np.uint32) << 16).view(np.float32)
         return conv(self.m[k]), conv(self.v[k])
 
@@ -308,6 +333,11 @@ class DeferredF32(_Deferred):
         Wf, _, _, _, _ = lut_spec(self.b1, self.b2, t, max(self.dmax(t), 0))
         dim = self.w[k].shape[1]
         out = np.zeros((rows32.shape[0], dim), np.float32)
+        if self.sid[k] == 2:
+            lib().orc_restore_rows_fp8(dim, _p(self.w[k]), _p(self.m[k]), _p(self.v[k]), _p(self.ms[k]),
+                                       _p(self.vs[k]), dim, rows32.shape[0], _p(rows32), _p(d), _p(self.lr[k]),
+                                       self.eps, _p(Wf), self.rb, _p(out))
+            return out
         lib().orc_restore_rows_f32(dim, _p(self.w[k]), _p(self.m[k]), _p(self.v[k]), self.sid[k], dim,
                                    rows32.shape[0], _p(rows32), _p(d), _p(self.lr[k]), self.eps,
                                    _p(Wf), self.rb, _p(out))
@@ -341,6 +371,13 @@ class DeferredF32(_Deferred):
                 krows, kd = rows, d
                 gg = np.zeros((rows.shape[0], dim), np.float32)
                 gg[:valid.shape[0]] = g
+            if self.sid[k] == 2:
+                lib().orc_deferred_rows_fp8(dim, _p(self.w[k]), _p(self.m[k]), _p(self.v[k]), _p(self.ms[k]),
+                                            _p(self.vs[k]), dim, self.w[k].shape[0], krows.shape[0], _p(krows),
+                                            _p(kd), _p(gg), dim, _p(self.lr[k]), self.b1, self.b2, self.eps,
+                                            _p(Wf), _p(Mf), _p(Vf), float(ss), float(bc), self.rb,
+                                            self.sr_seed, t, self.col0[k])
+                continue
             lib().orc_deferred_rows_f32(dim, _p(self.w[k]), _p(self.m[k]), _p(self.v[k]), self.sid[k], dim,
                                         krows.shape[0], _p(krows), _p(kd), _p(gg), dim, _p(self.lr[k]),
                                         self.b1, self.b2, self.eps, _p(Wf), _p(Mf), _p(Vf),
@@ -360,6 +397,12 @@ class DeferredF32(_Deferred):
             if k == 0 and self.geo_dense:
                 continue
             dim = self.w[k].shape[1]
+            if self.sid[k] == 2:
+                lib().orc_flush_rows_fp8(dim, _p(self.w[k]), _p(self.m[k]), _p(self.v[k]), _p(self.ms[k]),
+                                         _p(self.vs[k]), dim, rows.shape[0], _p(rows32), _p(delta),
+                                         _p(self.lr[k]), self.eps, _p(Wn), _p(Mf), _p(Vf), self.rb,
+                                         self.sr_seed, t_done, self.col0[k])
+                continue
             lib().orc_flush_rows_f32(dim, _p(self.w[k]), _p(self.m[k]), _p(self.v[k]), self.sid[k], dim,
                                      rows.shape[0], _p(rows32), _p(delta), _p(self.lr[k]), self.eps,
                                      _p(Wn), _p(Mf), _p(Vf), self.rb, self.sr_seed, t_done, self.col0[k])

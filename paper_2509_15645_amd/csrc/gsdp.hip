@@ -176,30 +176,114 @@ __device__ __forceinline__ u64 mix64(u64 z)
 }
 __device__ __forceinline__ u64 sm_at(u64 s, u64 i) { return mix64(s + (i + 1ull) * 0x9E3779B97F4A7C15ull); }
 
-// Moment storage.  BF16 keeps the upper 16 bits of the FP32 pattern; stores
-// round stochastically by adding 16 random bits before truncation (Inf kept,
-// NaN quieted).
-template <int ST> __device__ __forceinline__ float mom_load(const void *p, int64_t e);
-template <> __device__ __forceinline__ float mom_load<GS_F32>(const void *p, int64_t e)
+// Moment storage.
+//   F32 : plain FP32.
+//   BF16: the upper 16 bits of the FP32 pattern; stores round stochastically by
+//         adding 16 random bits before truncation (Inf kept, NaN quieted).
+//   FP8 : OCP E4M3FN codes times one FP32 power-of-two scale per block of 128
+//         rows (per group, per moment); the second moment is stored as its
+//         square root.  Stores round stochastically (see e4m3_sr).
+constexpr int kFp8Block = 128;
+
+struct MomRef {
+    void *p;            // [n][ld] elements
+    const float *s;     // FP8 block scales (FP8 only)
+    int64_t ld;
+};
+
+__device__ __forceinline__ float e4m3_dec(u32 b)
 {
-    return static_cast<const float *>(p)[e];
+    const int e = (int)((b >> 3) & 0xfu), m = (int)(b & 7u);
+    if (e == 15 && m == 7) return __uint_as_float(0x7fc00000u);
+    const float a = e == 0 ? ldexpf((float)m, -9) : ldexpf((float)(8 + m), e - 10);
+    return (b & 0x80u) ? -a : a;
 }
-template <> __device__ __forceinline__ float mom_load<GS_BF16>(const void *p, int64_t e)
+
+// Stochastic rounding of y to E4M3 (saturating at 448): in a binade of
+// quantum q, y = k q + f q rounds up when f * 65536 > r16.
+__device__ __forceinline__ u32 e4m3_sr(float y, u32 r16)
 {
-    return __uint_as_float((u32) static_cast<const uint16_t *>(p)[e] << 16);
+    if (__builtin_isnan(y)) return 0x7fu;
+    const u32 sign = (__float_as_uint(y) >> 31) << 7;
+    float a = fabsf(y);
+    if (a > 448.0f) a = 448.0f;
+    const int e = a < 0.015625f ? -6 : (int)((__float_as_uint(a) >> 23) & 0xffu) - 127;
+    const float quantum = ldexpf(1.0f, e - 3);
+    const float yq = a / quantum;
+    float k = floorf(yq);
+    const float f = yq - k;
+    if (f * 65536.0f > (float)r16) k = k + 1.0f;
+    const float val = k * quantum;
+    if (val == 0.0f) return sign;
+    if (val < 0.015625f) return sign | (u32)(val / ldexpf(1.0f, -9));
+    const int ev = (int)((__float_as_uint(val) >> 23) & 0xffu) - 127;
+    const int mant = (int)(val / ldexpf(1.0f, ev) * 8.0f) - 8;
+    return sign | ((u32)(ev + 7) << 3) | (u32)mant;
 }
-template <int ST> __device__ __forceinline__ void mom_store(void *p, int64_t e, float x, u32 r16);
-template <> __device__ __forceinline__ void mom_store<GS_F32>(void *p, int64_t e, float x, u32)
+
+// Smallest power of two p with amax / p <= 448 (0 for amax <= 0 or non-finite).
+__device__ __forceinline__ float fp8_scale_for(float amax)
 {
-    static_cast<float *>(p)[e] = x;
+    if (!(amax > 0.0f) || !(amax < __builtin_huge_valf())) return 0.0f;
+    const float r = amax / 448.0f;
+    int e;
+    const float fr = frexpf(r, &e);
+    return fr == 0.5f ? ldexpf(1.0f, e - 1) : ldexpf(1.0f, e);
 }
-template <> __device__ __forceinline__ void mom_store<GS_BF16>(void *p, int64_t e, float x, u32 r16)
+
+template <int ST> __device__ __forceinline__ float mom_load(const MomRef &q, int64_t row, int64_t col, bool is_v);
+template <> __device__ __forceinline__ float mom_load<GS_F32>(const MomRef &q, int64_t row, int64_t col, bool)
+{
+    return static_cast<const float *>(q.p)[row * q.ld + col];
+}
+template <> __device__ __forceinline__ float mom_load<GS_BF16>(const MomRef &q, int64_t row, int64_t col, bool)
+{
+    return __uint_as_float((u32) static_cast<const uint16_t *>(q.p)[row * q.ld + col] << 16);
+}
+template <> __device__ __forceinline__ float mom_load<GS_FP8E4M3>(const MomRef &q, int64_t row, int64_t col,
+                                                                  bool is_v)
+{
+    const float x = e4m3_dec(static_cast<const uint8_t *>(q.p)[row * q.ld + col]) * q.s[row / kFp8Block];
+    return is_v ? x * x : x;
+}
+
+template <int ST>
+__device__ __forceinline__ void mom_store(const MomRef &q, int64_t row, int64_t col, float x, u32 r16, bool is_v);
+template <>
+__device__ __forceinline__ void mom_store<GS_F32>(const MomRef &q, int64_t row, int64_t col, float x, u32, bool)
+{
+    static_cast<float *>(q.p)[row * q.ld + col] = x;
+}
+template <>
+__device__ __forceinline__ void mom_store<GS_BF16>(const MomRef &q, int64_t row, int64_t col, float x, u32 r16, bool)
 {
     const u32 u = __float_as_uint(x);
     uint16_t h;
     if ((u & 0x7f800000u) == 0x7f800000u) h = (uint16_t)((u >> 16) | ((u & 0x007fffffu) ? 0x0040u : 0u));
     else h = (uint16_t)((u + r16) >> 16);
-    static_cast<uint16_t *>(p)[e] = h;
+    static_cast<uint16_t *>(q.p)[row * q.ld + col] = h;
+}
+template <>
+__device__ __forceinline__ void mom_store<GS_FP8E4M3>(const MomRef &q, int64_t row, int64_t col, float x, u32 r16,
+                                                      bool is_v)
+{
+    const float sc = q.s[row / kFp8Block];
+    const float y = is_v ? sqrtf(x) : x;
+    static_cast<uint8_t *>(q.p)[row * q.ld + col] = sc > 0.0f ? (uint8_t)e4m3_sr(y / sc, r16) : (uint8_t)0;
+}
+
+// Adam step of one element, (st m1) / (sqrt(v1)/bc + eps), clamped to
+// st bc rb: moments grown from zero keep |m1|/sqrt(v1) below 7.27 < rb, so the
+// clamp never acts on an FP32 state; it bounds the step when quantised
+// moments lose the second moment to underflow.
+__device__ __forceinline__ float adam_step(float m1, float v1, float st, float bc, float eps, float rb)
+{
+    const float den = sqrtf(v1) / bc + eps;
+    float upd = (st * m1) / den;
+    const float lim = (st * bc) * rb;
+    if (upd > lim) upd = lim;
+    else if (upd < -lim) upd = -lim;
+    return upd;
 }
 
 // Per-camera constants of the band classifier (host-computed, rounded up).
@@ -287,8 +371,7 @@ __device__ __forceinline__ u64 pack_vs(u32 vis, u32 sat) { return ((u64)vis << 3
 
 struct CullArgs {
     const float *gw;                 // [n][10]
-    const void *gm, *gv;             // G moments (restore), storage type gst
-    int64_t m_ld, v_ld;
+    MomRef gm, gv;                   // G moments (restore), storage type gst
     int32_t gst, pad2;
     float rb, pad3;
     const int32_t *last;
@@ -374,17 +457,28 @@ __global__ __launch_bounds__(kCullBlock) void k_cull(CullArgs a)
                 if (cls == 2) {
                     if (d > 0 && !a.geo_dense) {
                         const int64_t row = row0 + r;
+                        float mv[10], vv[10];
                         if (a.gst == GS_F32) {
 #pragma unroll
-                            for (int j = 0; j < 10; ++j)
-                                g[j] = restore1(g[j], mom_load<GS_F32>(a.gm, row * a.m_ld + j),
-                                                mom_load<GS_F32>(a.gv, row * a.v_ld + j), wd, a.lr[j], a.eps, a.rb);
+                            for (int j = 0; j < 10; ++j) {
+                                mv[j] = mom_load<GS_F32>(a.gm, row, j, false);
+                                vv[j] = mom_load<GS_F32>(a.gv, row, j, true);
+                            }
+                        } else if (a.gst == GS_BF16) {
+#pragma unroll
+                            for (int j = 0; j < 10; ++j) {
+                                mv[j] = mom_load<GS_BF16>(a.gm, row, j, false);
+                                vv[j] = mom_load<GS_BF16>(a.gv, row, j, true);
+                            }
                         } else {
 #pragma unroll
-                            for (int j = 0; j < 10; ++j)
-                                g[j] = restore1(g[j], mom_load<GS_BF16>(a.gm, row * a.m_ld + j),
-                                                mom_load<GS_BF16>(a.gv, row * a.v_ld + j), wd, a.lr[j], a.eps, a.rb);
+                            for (int j = 0; j < 10; ++j) {
+                                mv[j] = mom_load<GS_FP8E4M3>(a.gm, row, j, false);
+                                vv[j] = mom_load<GS_FP8E4M3>(a.gv, row, j, true);
+                            }
                         }
+#pragma unroll
+                        for (int j = 0; j < 10; ++j) g[j] = restore1(g[j], mv[j], vv[j], wd, a.lr[j], a.eps, a.rb);
                         ++nrest;
                     }
                     keep = cull_v1(g, a.cam);
@@ -507,17 +601,16 @@ __global__ __launch_bounds__(kCullBlock) void k_cull(CullArgs a)
 // ---------------------------------------------------------------------------
 // row kernels: gather / adam / flush
 // ---------------------------------------------------------------------------
-enum RowMode { kGather = 0, kAdam = 1, kFlush = 2 };
+enum RowMode { kGather = 0, kAdam = 1, kFlush = 2, kAdamMax = 3 };
 constexpr int kRowUnroll = 4;
 
 struct RowArgs {
     float *gw, *aw;
-    void *gm, *gv, *am, *av;
-    int64_t gw_ld, gm_ld, gv_ld;
-    int64_t aw_ld, am_ld, av_ld;
+    int64_t gw_ld, aw_ld;
+    MomRef gm, gv, am, av;
     int32_t adim, t, K, dmax;
     float lr[64];                    // lane-indexed: 0..9 G, 10.. A
-    float eps, omb1, omb2, rb;       // rb: clamp of the restore factor
+    float eps, omb1, omb2, rb;       // rb: clamp of the restore factor and of the Adam step
     u64 sr_seed;
     int32_t geo_dense, pad2;
     int32_t *last;
@@ -529,10 +622,16 @@ struct RowArgs {
     const float *g_geo, *g_app;      // compact gradients
     float *gd_geo, *gd_app;          // dense gradients (read and cleared)
     float *out_geo, *out_app;        // gather outputs
+    u32 *fp8max[4];                  // per-block max |m'|, sqrt(v') that outgrew the scale (G m, G v, A m, A v)
 };
 
 // One wavefront per Gaussian row: lane c < 10 owns G column c, lane 10+c owns
 // A column c.  GST / AST are the moment storage types of G and A.
+//   kGather   current values into compact buffers (read-only)
+//   kAdam     restore + Adam step + stores, last_step = t
+//   kFlush    catch-up of deferred rows
+//   kAdamMax  first pass for FP8 moments: new moments only, recording per
+//             block the largest magnitude that no longer fits the block scale
 template <int MODE, int GST, int AST>
 __global__ __launch_bounds__(256) void k_rows(RowArgs a)
 {
@@ -544,7 +643,10 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
     const bool act = lane < 10 + a.adim && !(isG && a.geo_dense && MODE != kGather);
     const bool grest = !(isG && a.geo_dense);
     const int ca = lane - 10;
+    const int col = isG ? lane : ca;
     const float lr = a.lr[lane];
+    const MomRef &qm = isG ? a.gm : a.am;
+    const MomRef &qv = isG ? a.gv : a.av;
 
     int64_t nvis, total;
     if (MODE == kFlush) {
@@ -553,7 +655,7 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
     } else {
         const u32 c = *a.count;
         nvis = c < a.cap ? c : a.cap;
-        total = nvis + ((MODE == kAdam && a.sat_count) ? (int64_t)*a.sat_count : 0);
+        total = nvis + (((MODE == kAdam || MODE == kAdamMax) && a.sat_count) ? (int64_t)*a.sat_count : 0);
     }
     float ss = 0.0f, bc = 1.0f;
     if (MODE == kAdam) {
@@ -596,17 +698,17 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
             const bool need = ok[u] && act && (MODE != kFlush || d[u] > 0);
             if (!need) continue;
             const int64_t r = id[u];
-            w[u] = isG ? a.gw[r * a.gw_ld + lane] : a.aw[r * a.aw_ld + ca];
-            if ((MODE == kAdam || d[u] > 0) && grest) {
+            if (MODE != kAdamMax) w[u] = isG ? a.gw[r * a.gw_ld + lane] : a.aw[r * a.aw_ld + ca];
+            if ((MODE == kAdam || MODE == kAdamMax || d[u] > 0) && grest) {
                 if (isG) {
-                    m[u] = mom_load<GST>(a.gm, r * a.gm_ld + lane);
-                    v[u] = mom_load<GST>(a.gv, r * a.gv_ld + lane);
+                    m[u] = mom_load<GST>(qm, r, col, false);
+                    v[u] = mom_load<GST>(qv, r, col, true);
                 } else {
-                    m[u] = mom_load<AST>(a.am, r * a.am_ld + ca);
-                    v[u] = mom_load<AST>(a.av, r * a.av_ld + ca);
+                    m[u] = mom_load<AST>(qm, r, col, false);
+                    v[u] = mom_load<AST>(qv, r, col, true);
                 }
             }
-            if (MODE == kAdam && base + u < nvis) {
+            if ((MODE == kAdam || MODE == kAdamMax) && base + u < nvis) {
                 if (a.g_geo) g[u] = isG ? a.g_geo[(base + u) * 10 + lane] : a.g_app[(base + u) * a.adim + ca];
                 else g[u] = isG ? a.gd_geo[r * 10 + lane] : a.gd_app[r * a.adim + ca];
             }
@@ -628,6 +730,19 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
                 continue;
             }
             const int dd = d[u];
+            if (MODE == kAdamMax) {
+                const bool fp8 = isG ? GST == GS_FP8E4M3 : AST == GS_FP8E4M3;
+                if (act && fp8) {
+                    const float m1 = a.Mf[dd] * m[u] + a.omb1 * g[u];
+                    const float v1 = a.Vf[dd] * v[u] + (a.omb2 * g[u]) * g[u];
+                    const float r1 = sqrtf(v1);
+                    const int64_t b = r / kFp8Block;
+                    const float am = fabsf(m1);
+                    if (am > 448.0f * qm.s[b]) atomicMax(&a.fp8max[isG ? 0 : 2][b], __float_as_uint(am));
+                    if (r1 > 448.0f * qv.s[b]) atomicMax(&a.fp8max[isG ? 1 : 3][b], __float_as_uint(r1));
+                }
+                continue;
+            }
             if (MODE == kFlush && dd == 0) continue;
             if (act) {
                 float x, m1, v1;
@@ -636,8 +751,7 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
                     if (dd > 0) x = restore1(x, m[u], v[u], a.Wrow[dd], lr, a.eps, a.rb);
                     m1 = a.Mf[dd] * m[u] + a.omb1 * g[u];
                     v1 = a.Vf[dd] * v[u] + (a.omb2 * g[u]) * g[u];
-                    const float den = sqrtf(v1) / bc + a.eps;
-                    x = x - (step * m1) / den;
+                    x = x - adam_step(m1, v1, step, bc, a.eps, a.rb);
                 } else {
                     x = restore1(w[u], m[u], v[u], a.Wrow[dd], lr, a.eps, a.rb);
                     m1 = a.Mf[dd - 1] * m[u];
@@ -651,12 +765,12 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
                 }
                 if (isG) {
                     a.gw[r * a.gw_ld + lane] = x;
-                    mom_store<GST>(a.gm, r * a.gm_ld + lane, m1, rm);
-                    mom_store<GST>(a.gv, r * a.gv_ld + lane, v1, rv);
+                    mom_store<GST>(qm, r, col, m1, rm, false);
+                    mom_store<GST>(qv, r, col, v1, rv, true);
                 } else {
                     a.aw[r * a.aw_ld + ca] = x;
-                    mom_store<AST>(a.am, r * a.am_ld + ca, m1, rm);
-                    mom_store<AST>(a.av, r * a.av_ld + ca, v1, rv);
+                    mom_store<AST>(qm, r, col, m1, rm, false);
+                    mom_store<AST>(qv, r, col, v1, rv, true);
                 }
                 if (MODE == kAdam && !a.g_geo && base + u < nvis) {
                     if (isG) a.gd_geo[r * 10 + lane] = 0.0f;
@@ -668,16 +782,67 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
     }
 }
 
+// FP8 scale growth between the two Adam passes: every 128-row block whose
+// recorded max outgrew its scale gets the smallest power-of-two scale that
+// fits, and all its rows are re-encoded (random column = column + 64); the
+// recorded max is cleared.  One wavefront per block and moment.
+struct RescaleArgs {
+    uint8_t *q[4];                   // G m, G v, A m, A v codes
+    float *s[4];                     // their block scales
+    int64_t ld[4];
+    int32_t dim[4], col0[4];
+    u32 *maxb[4];
+    int32_t fp8[4];                  // which of the four are FP8
+    int64_t n, nb;
+    u64 sr_seed;
+    int32_t t, pad0;
+};
+
+__global__ __launch_bounds__(256) void k_fp8_rescale(RescaleArgs a)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t wid = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t nw = (int64_t)gridDim.x * 4;
+    const u64 s_step = sm_at(a.sr_seed, (u64)a.t);
+    for (int64_t task = wid; task < 4 * a.nb; task += nw) {
+        const int which = (int)(task / a.nb);
+        const int64_t b = task - (int64_t)which * a.nb;
+        if (!a.fp8[which]) continue;
+        const u32 mb = a.maxb[which][b];
+        if (mb == 0) continue;
+        const float amax = __uint_as_float(mb);
+        const float sold = a.s[which][b];
+        const float snew = fp8_scale_for(amax);
+        if (snew > sold) {
+            const int dim = a.dim[which];
+            const int64_t r0 = b * kFp8Block;
+            const int64_t r1 = min(r0 + kFp8Block, a.n);
+            const bool is_v = which & 1;
+            for (int64_t r = r0; r < r1; ++r) {
+                for (int c = lane; c < dim; c += 64) {
+                    uint8_t *qp = a.q[which] + r * a.ld[which] + c;
+                    const float x = e4m3_dec(*qp) * sold;
+                    const u64 h = sm_at(sm_at(s_step, (u64)r), (u64)(a.col0[which] + c + 64));
+                    const u32 rr = (u32)((is_v ? h >> 16 : h) & 0xffffull);
+                    *qp = (uint8_t)e4m3_sr(x / snew, rr);
+                }
+            }
+            if (lane == 0) a.s[which][b] = snew;
+        }
+        if (lane == 0) a.maxb[which][b] = 0u;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // dense geometric Adam (geo_mode = 1): every row's 10 G columns, every step
 // ---------------------------------------------------------------------------
 struct DenseArgs {
     float *w;
-    void *m, *v;
-    int64_t m_ld, v_ld, n;
+    MomRef m, v;
+    int64_t n;
     int32_t t, pad0;
     float lr[10];
-    float eps, omb1, omb2, b1f, b2f, pad1;
+    float eps, omb1, omb2, b1f, b2f, rb;
     const float *SS, *BC;
     u64 sr_seed;
     const float *g_geo;              // compact gradients of the cull's visible rows, or NULL
@@ -736,20 +901,19 @@ __global__ __launch_bounds__(256) void k_dense_geo(DenseArgs a)
             g = a.gd_geo[row * 10 + c];
             a.gd_geo[row * 10 + c] = 0.0f;
         }
-        const float mm = mom_load<GST>(a.m, row * a.m_ld + c), vv = mom_load<GST>(a.v, row * a.v_ld + c);
+        const float mm = mom_load<GST>(a.m, row, c, false), vv = mom_load<GST>(a.v, row, c, true);
         const float m1 = a.b1f * mm + a.omb1 * g;
         const float v1 = a.b2f * vv + (a.omb2 * g) * g;
-        const float den = sqrtf(v1) / bc + a.eps;
         const float lr = a.lr[c];
-        a.w[row * 10 + c] = a.w[row * 10 + c] - ((lr * ss) * m1) / den;
+        a.w[row * 10 + c] = a.w[row * 10 + c] - adam_step(m1, v1, lr * ss, bc, a.eps, a.rb);
         u32 rm = 0, rv = 0;
         if (GST != GS_F32) {
             const u64 h = sm_at(sm_at(s_step, (u64)row), (u64)c);
             rm = (u32)(h & 0xffffull);
             rv = (u32)((h >> 16) & 0xffffull);
         }
-        mom_store<GST>(a.m, row * a.m_ld + c, m1, rm);
-        mom_store<GST>(a.v, row * a.v_ld + c, v1, rv);
+        mom_store<GST>(a.m, row, c, m1, rm, false);
+        mom_store<GST>(a.v, row, c, v1, rv, true);
     }
 }
 
@@ -829,15 +993,18 @@ float restore_bound(double b1, double b2)
     return (float)((1.0 - b1) / std::sqrt((1.0 - b2) * (1.0 - b1 * b1 / b2)) * 1.03);
 }
 
-size_t mom_bytes(int state) { return state == GS_F32 ? 4 : 2; }
+size_t mom_bytes(int state) { return state == GS_F32 ? 4 : (state == GS_BF16 ? 2 : 1); }
+
+bool has_fp8(const gs_model *m) { return m->geo.state == GS_FP8E4M3 || m->app.state == GS_FP8E4M3; }
 
 int check_group(const gs_group &g, int64_t n, bool geo)
 {
     if (geo && g.dim != 10) return GS_EINVAL;
     if (!geo && (g.dim < 1 || g.dim > 54)) return GS_EINVAL;
     if (g.w_ld < g.dim || g.m_ld < g.dim || g.v_ld < g.dim) return GS_EINVAL;
-    if (g.state != GS_F32 && g.state != GS_BF16) return GS_EUNSUPPORTED;
+    if (g.state != GS_F32 && g.state != GS_BF16 && g.state != GS_FP8E4M3) return GS_EUNSUPPORTED;
     if (n > 0 && (!g.w || !g.m || !g.v)) return GS_EINVAL;
+    if (n > 0 && g.state == GS_FP8E4M3 && (!g.m_scale || !g.v_scale)) return GS_EINVAL;
     if (!aligned(g.w, 4) || !aligned(g.m, mom_bytes(g.state)) || !aligned(g.v, mom_bytes(g.state)))
         return GS_EINVAL;
     return GS_OK;
@@ -857,6 +1024,7 @@ int check_model(const gs_model *m)
     if (!(m->beta1 > 0.0 && m->beta1 < 1.0 && m->beta2 > 0.0 && m->beta2 < 1.0 && m->eps >= 0.0)) return GS_EINVAL;
     if (m->cull_mode != 0 && m->cull_mode != 1) return GS_EINVAL;
     if (m->geo_mode != 0 && m->geo_mode != 1) return GS_EINVAL;
+    if (m->geo_mode == 1 && m->geo.state == GS_FP8E4M3) return GS_EUNSUPPORTED;
     return GS_OK;
 }
 
@@ -882,17 +1050,13 @@ void fill_rows(RowArgs &a, const gs_model *m)
 {
     memset(&a, 0, sizeof a);
     a.gw = m->geo.w;
-    a.gm = m->geo.m;
-    a.gv = m->geo.v;
     a.gw_ld = m->geo.w_ld;
-    a.gm_ld = m->geo.m_ld;
-    a.gv_ld = m->geo.v_ld;
+    a.gm = {m->geo.m, m->geo.m_scale, m->geo.m_ld};
+    a.gv = {m->geo.v, m->geo.v_scale, m->geo.v_ld};
     a.aw = m->app.w;
-    a.am = m->app.m;
-    a.av = m->app.v;
     a.aw_ld = m->app.w_ld;
-    a.am_ld = m->app.m_ld;
-    a.av_ld = m->app.v_ld;
+    a.am = {m->app.m, m->app.m_scale, m->app.m_ld};
+    a.av = {m->app.v, m->app.v_scale, m->app.v_ld};
     a.adim = m->app.dim;
     a.K = m->max_defer;
     for (int c = 0; c < 10; ++c) a.lr[c] = m->geo.lr[c];
@@ -908,14 +1072,21 @@ void fill_rows(RowArgs &a, const gs_model *m)
 }
 
 // Launch k_rows<MODE> for the moment storage types of the model's groups.
+template <int MODE, int G>
+void launch_rows_a(int ast, int grid, hipStream_t st, const RowArgs &a)
+{
+    if (ast == GS_F32) hipLaunchKernelGGL((k_rows<MODE, G, GS_F32>), dim3(grid), dim3(256), 0, st, a);
+    else if (ast == GS_BF16) hipLaunchKernelGGL((k_rows<MODE, G, GS_BF16>), dim3(grid), dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((k_rows<MODE, G, GS_FP8E4M3>), dim3(grid), dim3(256), 0, st, a);
+}
+
 template <int MODE>
 void launch_rows(const gs_model *m, int grid, hipStream_t st, const RowArgs &a)
 {
     const int g = m->geo.state, p = m->app.state;
-    if (g == GS_F32 && p == GS_F32) hipLaunchKernelGGL((k_rows<MODE, GS_F32, GS_F32>), dim3(grid), dim3(256), 0, st, a);
-    else if (g == GS_F32 && p == GS_BF16) hipLaunchKernelGGL((k_rows<MODE, GS_F32, GS_BF16>), dim3(grid), dim3(256), 0, st, a);
-    else if (g == GS_BF16 && p == GS_F32) hipLaunchKernelGGL((k_rows<MODE, GS_BF16, GS_F32>), dim3(grid), dim3(256), 0, st, a);
-    else hipLaunchKernelGGL((k_rows<MODE, GS_BF16, GS_BF16>), dim3(grid), dim3(256), 0, st, a);
+    if (g == GS_F32) launch_rows_a<MODE, GS_F32>(p, grid, st, a);
+    else if (g == GS_BF16) launch_rows_a<MODE, GS_BF16>(p, grid, st, a);
+    else launch_rows_a<MODE, GS_FP8E4M3>(p, grid, st, a);
 }
 
 int row_grid(int64_t rows)
@@ -990,7 +1161,7 @@ int gs_lut_build(double beta1, double beta2, int32_t max_steps, int32_t max_defe
 int gs_workspace_bytes(const gs_model *model, size_t *bytes)
 {
     if (!model || !bytes || model->n < 0 || model->max_defer < 0) return GS_EINVAL;
-    *bytes = (size_t)gsdp::ws_bytes_for(model->n, model->max_defer, model->geo_mode);
+    *bytes = (size_t)gsdp::ws_bytes_for(model->n, model->max_defer, model->geo_mode, has_fp8(model));
     return GS_OK;
 }
 
@@ -1003,15 +1174,13 @@ int gs_cull(const gs_model *model, const gs_camera *cam, int64_t step, uint32_t 
     if (step < 1 || step > model->lut_max_steps) return GS_EINVAL;
     if (!(cam->fx > 0.0f && cam->fy > 0.0f) || cam->width <= 0 || cam->height <= 0) return GS_EINVAL;
     if (!aligned(ws, 256)) return GS_EINVAL;
-    if ((int64_t)ws_bytes < gsdp::ws_bytes_for(model->n, model->max_defer, model->geo_mode)) return GS_ESPACE;
+    if ((int64_t)ws_bytes < gsdp::ws_bytes_for(model->n, model->max_defer, model->geo_mode, has_fp8(model))) return GS_ESPACE;
 
     CullArgs a;
     memset(&a, 0, sizeof a);
     a.gw = model->geo.w;
-    a.gm = model->geo.m;
-    a.gv = model->geo.v;
-    a.m_ld = model->geo.m_ld;
-    a.v_ld = model->geo.v_ld;
+    a.gm = {model->geo.m, model->geo.m_scale, model->geo.m_ld};
+    a.gv = {model->geo.v, model->geo.v_scale, model->geo.v_ld};
     a.gst = model->geo.state;
     a.rb = restore_bound(model->beta1, model->beta2);
     a.last = model->last_step;
@@ -1122,9 +1291,9 @@ int gs_adam_step_deferred(const gs_model *model, int64_t step, const uint32_t *i
     if (compact && (!g_geo || !g_app)) return GS_EINVAL;
     if (!compact && capacity > 0 && (!g_geo_dense || !g_app_dense)) return GS_EINVAL;
     const bool geo_dense = model->geo_mode == 1;
-    if (model->max_defer > 0 || (geo_dense && compact)) {
+    if (model->max_defer > 0 || (geo_dense && compact) || has_fp8(model)) {
         if (!ws || !aligned(ws, 256)) return GS_EINVAL;
-        if ((int64_t)ws_bytes < gsdp::ws_bytes_for(model->n, model->max_defer, model->geo_mode)) return GS_ESPACE;
+        if ((int64_t)ws_bytes < gsdp::ws_bytes_for(model->n, model->max_defer, model->geo_mode, has_fp8(model))) return GS_ESPACE;
     }
     RowArgs a;
     fill_rows(a, model);
@@ -1154,11 +1323,10 @@ int gs_adam_step_deferred(const gs_model *model, int64_t step, const uint32_t *i
         DenseArgs da;
         memset(&da, 0, sizeof da);
         da.w = model->geo.w;
-        da.m = model->geo.m;
-        da.v = model->geo.v;
-        da.m_ld = model->geo.m_ld;
-        da.v_ld = model->geo.v_ld;
+        da.m = {model->geo.m, model->geo.m_scale, model->geo.m_ld};
+        da.v = {model->geo.v, model->geo.v_scale, model->geo.v_ld};
         da.n = model->n;
+        da.rb = restore_bound(model->beta1, model->beta2);
         da.t = (int32_t)step;
         for (int c = 0; c < 10; ++c) da.lr[c] = model->geo.lr[c];
         da.eps = (float)model->eps;
@@ -1186,6 +1354,38 @@ int gs_adam_step_deferred(const gs_model *model, int64_t step, const uint32_t *i
             hipLaunchKernelGGL(k_dense_geo<GS_BF16>, dim3((unsigned)da.tiles), dim3(256), 0, (hipStream_t)stream, da);
         int rc2 = launched("gs_adam_step_deferred (dense geometry)");
         if (rc2) return rc2;
+    }
+    if (has_fp8(model)) {
+        // pass 1: per-block max of the new moments that outgrow their scale
+        char *wsb = static_cast<char *>(ws);
+        const int64_t nb = gsdp::fp8_blocks(model->n);
+        u32 *mx = reinterpret_cast<u32 *>(wsb + gsdp::ws_fp8_offset(model->n, model->max_defer, model->geo_mode));
+        for (int k = 0; k < 4; ++k) a.fp8max[k] = mx + k * nb;
+        launch_rows<kAdamMax>(model, row_grid(rows), (hipStream_t)stream, a);
+        int rc1 = launched("gs_adam_step_deferred (fp8 max pass)");
+        if (rc1) return rc1;
+        // pass 2: grow scales and re-encode those blocks
+        RescaleArgs ra;
+        memset(&ra, 0, sizeof ra);
+        const gs_group *grp[2] = {&model->geo, &model->app};
+        for (int k = 0; k < 4; ++k) {
+            const gs_group &gg = *grp[k / 2];
+            const bool isv = k & 1;
+            ra.q[k] = static_cast<uint8_t *>(isv ? gg.v : gg.m);
+            ra.s[k] = isv ? gg.v_scale : gg.m_scale;
+            ra.ld[k] = isv ? gg.v_ld : gg.m_ld;
+            ra.dim[k] = gg.dim;
+            ra.col0[k] = k < 2 ? 0 : 10;
+            ra.maxb[k] = a.fp8max[k];
+            ra.fp8[k] = gg.state == GS_FP8E4M3;
+        }
+        ra.n = model->n;
+        ra.nb = nb;
+        ra.sr_seed = model->sr_seed;
+        ra.t = (int32_t)step;
+        hipLaunchKernelGGL(k_fp8_rescale, dim3(row_grid(4 * nb * kRowUnroll)), dim3(256), 0, (hipStream_t)stream, ra);
+        rc1 = launched("gs_adam_step_deferred (fp8 rescale)");
+        if (rc1) return rc1;
     }
     launch_rows<kAdam>(model, row_grid(rows), (hipStream_t)stream, a);
     return launched("gs_adam_step_deferred");

@@ -62,9 +62,15 @@ inline int64_t ws_bits_offset(int64_t n, int32_t K)
     int64_t b = ws_sat_offset(n) + (K > 0 ? 4 * n : 0);
     return (b + 7) / 8 * 8;
 }
-inline int64_t ws_bytes_for(int64_t n, int32_t K, int32_t geo_dense)
+inline int64_t fp8_blocks(int64_t n) { return (n + 127) / 128; }
+inline int64_t ws_fp8_offset(int64_t n, int32_t K, int32_t geo_dense)
 {
-    int64_t b = ws_bits_offset(n, K) + (geo_dense ? 8 * kWordsPerTile * cull_tiles(n) : 0);
+    return ws_bits_offset(n, K) + (geo_dense ? 8 * kWordsPerTile * cull_tiles(n) : 0);
+}
+// fp8: per-block max arrays for G m, G v, A m, A v (u32 each)
+inline int64_t ws_bytes_for(int64_t n, int32_t K, int32_t geo_dense, int32_t fp8)
+{
+    int64_t b = ws_fp8_offset(n, K, geo_dense) + (fp8 ? 16 * fp8_blocks(n) : 0);
     return (b + 255) / 256 * 256;
 }
 

@@ -35,7 +35,8 @@ class GsCamera(C.Structure):
 class GsGroup(C.Structure):
     _fields_ = [("w", C.c_void_p), ("m", C.c_void_p), ("v", C.c_void_p), ("dim", C.c_int32),
                 ("w_ld", C.c_int32), ("m_ld", C.c_int32), ("v_ld", C.c_int32), ("state", C.c_int32),
-                ("pad_", C.c_int32), ("lr", C.c_float * 64)]
+                ("pad_", C.c_int32), ("m_scale", C.c_void_p), ("v_scale", C.c_void_p),
+                ("lr", C.c_float * 64)]
 
 
 class GsModel(C.Structure):
@@ -166,7 +167,8 @@ class Model:
         n, adim = geo.shape[0], app.shape[1]
         assert geo.shape == (n, 10) and app.shape[0] == n
         self.n, self.adim, self.device = n, adim, device
-        sdt = {"f32": (torch.float32, GS_F32, 4), "bf16": (torch.bfloat16, GS_BF16, 2)}
+        sdt = {"f32": (torch.float32, GS_F32, 4), "bf16": (torch.bfloat16, GS_BF16, 2),
+               "fp8": (torch.uint8, GS_FP8E4M3, 1)}
         gdt, gcode, _ = sdt[geo_state]
         adt, acode, asz = sdt[app_state]
         self.geo_state, self.app_state = geo_state, app_state
@@ -191,6 +193,10 @@ class Model:
             ld = (row // 4, row // asz, row // asz)
         else:
             raise ValueError(app_layout)
+        nb = (n + 127) // 128
+        zs = lambda code: torch.zeros(nb, dtype=torch.float32, device=device) if code == GS_FP8E4M3 else None
+        self.geo_ms, self.geo_vs = zs(gcode), zs(gcode)
+        self.app_ms, self.app_vs = zs(acode), zs(acode)
         self.last_step = torch.zeros(n, dtype=torch.int32, device=device)
         self.max_steps, self.max_defer = int(max_steps), int(max_defer)
         self.lut = torch.empty(gs_lut_bytes(self.max_steps, self.max_defer) // 4, dtype=torch.float32,
@@ -201,10 +207,14 @@ class Model:
 
         c = GsModel()
         c.n = n
-        for grp, w, m, v, lds, lr, dim, code in (
-                (c.geo, self.geo_w, self.geo_m, self.geo_v, (10, 10, 10), self.lr_geo, 10, gcode),
-                (c.app, self.app_w, self.app_m, self.app_v, ld, self.lr_app, adim, acode)):
+        for grp, w, m, v, lds, lr, dim, code, ms, vs in (
+                (c.geo, self.geo_w, self.geo_m, self.geo_v, (10, 10, 10), self.lr_geo, 10, gcode,
+                 self.geo_ms, self.geo_vs),
+                (c.app, self.app_w, self.app_m, self.app_v, ld, self.lr_app, adim, acode,
+                 self.app_ms, self.app_vs)):
             grp.w, grp.m, grp.v = w.data_ptr(), m.data_ptr(), v.data_ptr()
+            grp.m_scale = ms.data_ptr() if ms is not None else None
+            grp.v_scale = vs.data_ptr() if vs is not None else None
             grp.dim = dim
             grp.w_ld, grp.m_ld, grp.v_ld = lds
             grp.state = code
@@ -242,6 +252,10 @@ class Model:
             else:
                 out[name] = t.cpu().numpy()
         out["last_step"] = self.last_step.cpu().numpy()
+        for name in ("geo_ms", "geo_vs", "app_ms", "app_vs"):
+            t = getattr(self, name)
+            if t is not None:
+                out[name] = t.cpu().numpy()
         return out
 
 

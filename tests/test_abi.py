@@ -40,7 +40,7 @@ def test_every_declared_symbol_is_exported(gsdp):
 
 def test_struct_layouts(gsdp):
     assert C.sizeof(gsdp.GsCamera) == 80
-    assert C.sizeof(gsdp.GsGroup) == 3 * 8 + 6 * 4 + 64 * 4
+    assert C.sizeof(gsdp.GsGroup) == 3 * 8 + 6 * 4 + 2 * 8 + 64 * 4
     assert gsdp.GsModel.lut_max_steps.offset == 8 + 2 * C.sizeof(gsdp.GsGroup) + 16
 
 

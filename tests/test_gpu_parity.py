@@ -189,6 +189,9 @@ def _compare_state(model, o3, tag):
             if not np.array_equal(bits(got), bits(ref)):
                 bad = np.nonzero(bits(got) != bits(ref))
                 raise AssertionError(f"{tag}: {name}_{part} differs at {bad[0][:5]},{bad[1][:5]}")
+        for part, ref in (("ms", o3.ms[k]), ("vs", o3.vs[k])):
+            if f"{name}_{part}" in st:
+                assert np.array_equal(bits(st[f"{name}_{part}"]), bits(ref)), f"{tag}: {name}_{part}"
 
 
 @pytest.mark.parametrize("max_defer,layout,grad_mode,cull_mode,states,geo_mode", [
@@ -202,6 +205,9 @@ def _compare_state(model, o3, tag):
     (0, "separate", "compact", 0, ("bf16", "f32"), 0),
     (0, "interleaved", "compact", 1, ("f32", "f32"), 1),
     (15, "separate", "dense", 0, ("bf16", "bf16"), 1),
+    (0, "interleaved", "compact", 1, ("fp8", "fp8"), 0),
+    (15, "separate", "compact", 1, ("f32", "fp8"), 0),
+    (0, "separate", "dense", 0, ("bf16", "fp8"), 0),
 ])
 def test_small_workload_path_vs_oracle(g, max_defer, layout, grad_mode, cull_mode, states, geo_mode):
     """100k Gaussians, 10 orbit cameras, 20 steps: every step's visible ids and
@@ -269,11 +275,15 @@ def test_small_workload_path_vs_oracle(g, max_defer, layout, grad_mode, cull_mod
     if not quant:
         assert e_geo.max() <= 1e-6 and e_app.max() <= 1e-6
     else:
-        # quantised moments: within 2% of the largest possible movement lr * steps
+        # quantised moments, relative to the largest possible movement lr * steps:
+        # BF16 max 2e-2; FP8 max 0.15 and mean 2e-2
         for k, (got, lr) in enumerate(((st["geo_w"], lg), (st["app_w"], la))):
             err = np.abs(got - dense.w[k]) / (lr.astype(np.float64) * w.steps)
             say(f"[path {states}] group {k}: |w - w64| / (lr T) max {err.max():.3e} mean {err.mean():.3e}")
-            assert err.max() <= 2e-2
+            if states[k] == "fp8":
+                assert err.max() <= 0.15 and err.mean() <= 2e-2
+            elif states[k] == "bf16":
+                assert err.max() <= 2e-2
     assert model.ws_header()["error"] == 0
 
 

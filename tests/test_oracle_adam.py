@@ -265,3 +265,61 @@ def test_bf16_state_tracks_fp32_state():
     m4, v4 = o4.moments_f32(1)
     assert np.max(np.abs(m4 - o3.m[1])) < 0.02 * np.max(np.abs(o3.m[1]))
     assert np.max(np.abs(v4 - o3.v[1]) / np.maximum(o3.v[1], 1e-30)) < 0.05
+
+
+def test_e4m3_codes_follow_the_ocp_definition():
+    """E4M3FN: bias 7, 3 mantissa bits, subnormals m*2^-9, max 448, NaN S.1111.111."""
+    dec = orc.e4m3_decode(np.arange(256, dtype=np.uint8))
+    assert dec[0x38] == 1.0 and dec[0x40] == 2.0 and dec[0x7E] == 448.0 and dec[0xFE] == -448.0
+    assert dec[0x08] == 2.0 ** -6 and dec[0x01] == 2.0 ** -9 and dec[0x07] == 7 * 2.0 ** -9
+    assert np.isnan(dec[0x7F]) and np.isnan(dec[0xFF])
+    finite = np.sort(np.unique(dec[np.isfinite(dec)]))
+    assert finite.shape[0] == 253 and finite.max() == 448.0     # +-0 share a value
+    f = orc.lib().orc_e4m3_sr
+    for c in range(256):
+        if np.isfinite(dec[c]) and c != 0x80:
+            assert f(float(dec[c]), 0) == c and f(float(dec[c]), 65535) == c
+    assert f(1e6, 0) == 0x7E and f(-1e6, 0) == 0xFE                 # saturation
+    assert f(float("nan"), 0) == 0x7F
+
+
+def test_e4m3_stochastic_rounding_is_unbiased_and_brackets():
+    rng = np.random.default_rng(5)
+    f = orc.lib().orc_e4m3_sr
+    ys = np.concatenate([rng.uniform(-440, 440, 8), rng.uniform(-1e-2, 1e-2, 6), [3e-3, 0.3, 17.0]])
+    for y in ys.astype(np.float32):
+        outs = np.array([f(float(y), r) for r in range(65536)], np.uint8)
+        vals = orc.e4m3_decode(outs).astype(np.float64)
+        assert np.unique(vals).shape[0] <= 2
+        lo, hi = vals.min(), vals.max()
+        assert lo <= y <= hi
+        assert vals.mean() == pytest.approx(float(y), abs=(hi - lo) * 2.0 ** -15 + 1e-30)
+
+
+def test_fp8_scale_rule():
+    f = orc.lib().orc_fp8_scale_for
+    for amax in [1e-9, 3e-4, 0.7, 448.0, 449.0, 1e5]:
+        s = f(amax)
+        assert s > 0 and np.log2(s) == np.round(np.log2(s))
+        assert amax / s <= 448.0 * (1 + 1e-6) and amax / (s / 2) > 448.0 * (1 - 1e-6)
+    assert f(0.0) == 0.0 and f(float("inf")) == 0.0
+
+
+def test_fp8_state_tracks_dense_and_keeps_codes_in_range():
+    n, steps = 1500, 30
+    s, lg, la = _scene(n, 21)
+    o8 = orc.DeferredF32(s.geo, s.app, lg, la, state="fp8", sr_seed=4, max_defer=15)
+    dense = orc.DenseAdamF64(s.geo, s.app, lg, la)
+    for t, ids in enumerate(_vis_sequence(n, steps, 0.3, 22, first_all=False), start=1):
+        g = gi.step_grads(0, t, ids)
+        o8.step(t, ids, *g)
+        dense.step(t, ids, *g)
+        for k in range(2):
+            mm, vv = o8.moments_f32(k)
+            blk = np.arange(n) // orc.FP8_BLOCK
+            assert np.all(np.abs(mm) <= 448.0 * o8.ms[k][blk][:, None])
+            assert np.all(vv >= 0) and np.all(np.sqrt(vv) <= 448.0 * o8.vs[k][blk][:, None])
+    o8.flush(steps)
+    for k, lr in ((0, lg), (1, la)):
+        err = np.abs(o8.w[k] - dense.w[k]) / (lr.astype(np.float64) * steps)
+        assert err.max() < 0.15 and err.mean() < 2e-2, (err.max(), err.mean())
