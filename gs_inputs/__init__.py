@@ -253,3 +253,15 @@ def workload(name: str, n: int | None = None, seed: int = 0, tilt_deg=(20.0, 45.
     cams = aerial_cameras(ncam, side / 2, side / 2, seed, tilt_deg=tilt_deg)
     order = np.random.default_rng(seed + 3_000_017).permutation(ncam)
     return Workload(name, n, steps, box, cams, order, seed)
+
+
+def batched_scene_sizes(n_scenes: int = 16, lo: float = 5e5, hi: float = 8e6, seed: int = 0) -> list[int]:
+    """Scene sizes log-uniform in [lo, hi] (seeded)."""
+    rng = np.random.default_rng(seed + 4_000_037)
+    return [int(round(math.exp(rng.uniform(math.log(lo), math.log(hi))))) for _ in range(n_scenes)]
+
+
+def aerial_box_for(n: int, n_ref: int = 4_000_000, side_ref: float = 1000.0, height: float = 100.0):
+    """Aerial box with the 4M-Gaussian workload's density: side 1000 * sqrt(n / 4M)."""
+    half = side_ref * math.sqrt(n / n_ref) / 2
+    return ((-half, half), (-half, half), (0.0, height)), half

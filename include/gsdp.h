@@ -98,7 +98,8 @@ typedef struct gs_model {
                               columns updated by dense Adam on every row every step, the
                               split of Sec. 4.2.2 step 4 (appearance stays deferred) */
     uint64_t sr_seed;      /* seed of the stochastic-rounding stream of quantised moments */
-    int32_t reserved_[4];
+    const int32_t *step_dev; /* device step counter used by calls with step == 0 */
+    int32_t reserved_[2];
 } gs_model;
 
 /* ---------------------------------------------------------------- tables */
@@ -178,11 +179,72 @@ int gs_adam_step_deferred(const gs_model *model, int64_t step, const uint32_t *i
                           const float *g_app, float *g_geo_dense, float *g_app_dense, void *ws,
                           size_t ws_bytes, void *stream);
 
+/* Graph replay: every entry point that takes `step` also accepts step == 0,
+ * meaning "read the step from *model->step_dev when the kernels run" (clamped
+ * to [1, lut_max_steps]), so a captured step can be replayed.  This call adds
+ * one to *step_dev on `stream`. */
+int gs_step_advance(int32_t *step_dev, void *stream);
+
 /* Flush after update `step`: every row with last_step < step skipped
  * delta = step - last_step zero-gradient steps; bring it current (w restored
  * with the LUT of step+1 at delta, m *= b1^delta, v *= b2^delta, Eq. 2-3) and
  * set last_step = step.  Required before saving, evaluating or densifying. */
 int gs_adam_flush(const gs_model *model, int64_t step, void *stream);
+
+/* ------------------------------------------------------------ batched form */
+
+/* Many scenes, many cameras per step, in one launch: the scenes are row
+ * ranges of one model [scene_row0[s], scene_row0[s+1]), each starting at a
+ * multiple of 1024 rows (pad with rows of NaN geometry, which never become
+ * visible).  Camera slot c of scene s at update t is record
+ * cams[((t-1) % n_sets) * n_scenes * C + s * C + c] (records from
+ * gs_camera_pack, uploaded by the caller).  Outputs of gs_cull_multi:
+ *   union_ids[0..U)  rows visible to at least one camera of their scene,
+ *                    ascending (U = *union_count; gather and update these);
+ *   cam_pos[c*cap_cam + i]  union positions of the rows camera slot c sees,
+ *                    ascending over all scenes (cam_count[c] entries);
+ *   scene_start[s*(1+C) + j]  first entry of scene s in the union list (j = 0)
+ *                    and in each camera list (j = 1 + c).
+ * Deterministic; counts beyond a capacity are reported, not written.  Only
+ * max_defer = 0 and geo_mode = 0 models are supported. */
+typedef struct gs_multi {
+    int32_t n_scenes, cams_per_scene, n_sets, variant;   /* variant: see gs_cull_multi_autotune */
+    const int64_t *scene_row0;   /* device [n_scenes + 1] */
+    const void *cams;            /* device camera records */
+    uint32_t *union_ids, *union_count;
+    uint32_t *cam_pos, *cam_count;
+    uint32_t cap_union, cap_cam;
+    uint32_t *scene_start;       /* device [n_scenes][1 + cams_per_scene] */
+} gs_multi;
+
+/* Size of one camera record, and packing of `count` cameras for `model`
+ * (camera matrices plus the rounded-up constants of the band classifier). */
+int gs_camera_pack_bytes(size_t *bytes);
+int gs_camera_pack(const gs_model *model, const gs_camera *cams, int32_t count, void *out_host);
+
+/* Workspace of gs_cull_multi (zero-filled once; 4.2 bytes per Gaussian). */
+int gs_multi_workspace_bytes(const gs_model *model, size_t *bytes);
+
+/* Batched cull + ordered compaction of every (scene, camera) pair (Sec. 2.4
+ * step 1 per camera; the union is the paper's valid_ids of a multi-image
+ * batch).  Each tile of geometry is read once and tested against all cameras
+ * of its scene. */
+int gs_cull_multi(const gs_model *model, const gs_multi *desc, int64_t step, void *ws, size_t ws_bytes,
+                  void *stream);
+
+/* Times every (block size, rows per thread) variant of gs_cull_multi on the
+ * given inputs (synchronising `stream`), stores the fastest in desc->variant
+ * and, when times_ms is not NULL, each variant's mean time. */
+int gs_cull_multi_autotune(const gs_model *model, gs_multi *desc, int64_t step, void *ws, size_t ws_bytes,
+                           void *stream, float *times_ms, int32_t *n_variants);
+
+/* Deterministic gradient sum of a batch: out[p] = sum over camera slots c, in
+ * slot order, of g_cam[c*cap_cam + i] for the entry i of list c with
+ * cam_pos = p.  g_cam rows are [10 + adim] floats (G columns then A); the
+ * result is split into out_geo [cap_union][10] and out_app [cap_union][adim],
+ * ready for gs_adam_step_deferred with ids = union_ids. */
+int gs_grad_sum_multi(const gs_multi *desc, int32_t adim, const float *g_cam, float *out_geo, float *out_app,
+                      void *stream);
 
 /* --------------------------------------------------------------- harness */
 

@@ -434,3 +434,44 @@ def simulate(models, scene_geo_rows_keys, cams_for_step, grads_for, steps, t0=1)
 
 if __name__ == "__main__":
     print(build(force=True), file=sys.stderr)
+
+
+# ---------------------------------------------------------------------------
+# batched form: several scenes (row ranges), several cameras per scene
+# ---------------------------------------------------------------------------
+def cull_multi(geo_current: np.ndarray, scene_row0, cams_per_scene):
+    """Union and per-camera lists of a batch, from the FP32 cull of each row
+    of scene s against each camera of scene s.
+    Returns (union_ids ascending, [cam_pos[c]] union positions ascending,
+    scene_start [S, 1+C])."""
+    n = geo_current.shape[0]
+    row0 = np.asarray(scene_row0, np.int64)
+    S = row0.shape[0] - 1
+    Cc = len(cams_per_scene[0])
+    masks = np.zeros(n, np.uint64)
+    for s in range(S):
+        a, b = int(row0[s]), int(row0[s + 1])
+        for c, cam in enumerate(cams_per_scene[s]):
+            keep = cull(geo_current[a:b], cam)
+            masks[a:b] |= keep.astype(np.uint64) << np.uint64(c)
+    union = np.nonzero(masks)[0]
+    pos_of = np.full(n, -1, np.int64)
+    pos_of[union] = np.arange(union.shape[0])
+    cam_rows = [np.nonzero((masks >> np.uint64(c)) & np.uint64(1))[0] for c in range(Cc)]
+    cam_pos = [pos_of[r] for r in cam_rows]
+    start = np.zeros((S, 1 + Cc), np.int64)
+    for s in range(S):
+        start[s, 0] = np.searchsorted(union, row0[s])
+        for c in range(Cc):
+            start[s, 1 + c] = np.searchsorted(cam_rows[c], row0[s])
+    return union, cam_pos, start
+
+
+def grad_sum_multi(cam_pos, g_cam, n_union: int) -> np.ndarray:
+    """out[p] = sum over cameras c in order of the gradient of the entry of
+    camera c at union position p (FP32 additions starting from 0)."""
+    D = g_cam[0].shape[1]
+    out = np.zeros((n_union, D), np.float32)
+    for c, pos in enumerate(cam_pos):
+        out[pos] = out[pos] + np.asarray(g_cam[c], np.float32)
+    return out

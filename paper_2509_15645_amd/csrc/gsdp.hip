@@ -294,25 +294,44 @@ struct BandK {
 };
 
 // Conservative classification of one Gaussian whose stored geometry g may be
-// stale by a restore of at most B*W[d]*lr per column (B bounds |m|/sqrt(v) of
-// Adam moments grown from zero: by Cauchy-Schwarz (1-b1)/sqrt((1-b2)(1-b1^2/b2))
-// = 7.27 for b = (0.9, 0.999); B includes a margin for FP32 storage).
-// Returns 0 when every admissible restored geometry is culled by cull_v1,
-// 1 when every one is kept, 2 when undecided (the exact test must run).
+// stale by a restore of at most B*W[d]*lr per column.  B is the clamp of the
+// restore factor (1.03x the Cauchy-Schwarz bound (1-b1)/sqrt((1-b2)(1-b1^2/b2))
+// of |m|/sqrt(v) for Adam moments grown from zero, 7.27 for b = (0.9, 0.999)).
+// classify_cam returns 0 when every admissible restored geometry is culled by
+// cull_v1, 1 when every one is kept, 2 when undecided (run the exact test).
 // Bounds, all with generous margins for FP32 rounding of the exact test:
 //   camera-space centre moves by <= |R_i|_1 * position drift;
 //   projected covariance trace <= |J|_F^2 sigma_max^2, |J|_F^2 <= jf2 / z^2 since
 //   |tan| is clamped, and the radius of cull_v1 is <= ceil(3 sqrt(trace + 0.92));
 //   the radius is >= 3 and det > 0 holds when the trace bound is <= 1000.
-__device__ __forceinline__ int classify(const float *g, float wd, const CamK &c, const BandK &b)
+// classify_pre holds the camera-independent part of one row.
+struct RowPre {
+    float dp;       // position drift bound incl. rounding of the restore
+    float sig2;     // bound of sigma_max^2 after the restore
+    int ok;         // 0: undecidable (non-finite, huge scale); bit 1: quaternion stays away from 0
+};
+
+__device__ __forceinline__ RowPre classify_pre(const float *g, float wd, const BandK &b)
 {
+    RowPre p;
     bool fin = true;
 #pragma unroll
     for (int j = 0; j < 10; ++j) fin &= __builtin_isfinite(g[j]);
-    if (!fin) return 2;
     const float dpos = b.kpos * wd, dscl = b.kscl * wd, dq = b.kq * wd;
     const float mu = fmaxf(fmaxf(fabsf(g[0]), fabsf(g[1])), fabsf(g[2]));
-    const float dp = dpos + 1e-6f * mu;
+    p.dp = dpos + 1e-6f * mu;
+    const float smax = fmaxf(fmaxf(g[3], g[4]), g[5]) + dscl + 1e-6f * fmaxf(fmaxf(fabsf(g[3]), fabsf(g[4])), fabsf(g[5]));
+    const float sig = __expf(fminf(smax, 80.0f)) * 1.001f;
+    p.sig2 = sig * sig;
+    const float qn = sqrtf(((g[6] * g[6] + g[7] * g[7]) + g[8] * g[8]) + g[9] * g[9]);
+    p.ok = (fin && smax < 80.0f) ? (qn > 2.002f * dq + 1e-6f ? 3 : 1) : 0;
+    return p;
+}
+
+__device__ __forceinline__ int classify_cam(const float *g, const RowPre &p, const CamK &c, const BandK &b)
+{
+    if (!p.ok) return 2;
+    const float dp = p.dp;
     const float x = ((c.R[0] * g[0] + c.R[1] * g[1]) + c.R[2] * g[2]) + c.T[0];
     const float y = ((c.R[3] * g[0] + c.R[4] * g[1]) + c.R[5] * g[2]) + c.T[1];
     const float z = ((c.R[6] * g[0] + c.R[7] * g[1]) + c.R[8] * g[2]) + c.T[2];
@@ -325,11 +344,8 @@ __device__ __forceinline__ int classify(const float *g, float wd, const CamK &c,
     const float zlo = z - ez, zhi = z + ez;
     if (zhi <= c.zn || zlo >= c.zf) return 0;
     if (!(zlo > 0.0f)) return 2;
-    const float smax = fmaxf(fmaxf(g[3], g[4]), g[5]) + dscl + 1e-6f * fmaxf(fmaxf(fabsf(g[3]), fabsf(g[4])), fabsf(g[5]));
-    if (!(smax < 80.0f)) return 2;
-    const float sig = __expf(smax) * 1.001f;
     const float izl = 1.0f / zlo, izh = 1.0f / zhi;
-    const float S = ((b.jf2 * izl) * izl) * (sig * sig);
+    const float S = ((b.jf2 * izl) * izl) * p.sig2;
     const float lam = 1.001f * S + 0.95f;
     const float rup = 3.0f * sqrtf(lam) * 1.001f + 1.0f;
     const float xlo = x - ex, xhi = x + ex, ylo = y - ey, yhi = y + ey;
@@ -340,11 +356,15 @@ __device__ __forceinline__ int classify(const float *g, float wd, const CamK &c,
     const float ulo = c.fx * qxlo + c.cx - eu, uhi = c.fx * qxhi + c.cx + eu;
     const float vlo = c.fy * qylo + c.cy - ev, vhi = c.fy * qyhi + c.cy + ev;
     if (uhi + rup <= 0.0f || ulo - rup >= c.W || vhi + rup <= 0.0f || vlo - rup >= c.H) return 0;
-    const float qn = sqrtf(((g[6] * g[6] + g[7] * g[7]) + g[8] * g[8]) + g[9] * g[9]);
-    if (zlo > c.zn && zhi < c.zf && ulo > -1.5f && uhi < c.W + 1.5f && vlo > -1.5f && vhi < c.H + 1.5f &&
-        lam <= 1000.0f && qn > 2.002f * dq + 1e-6f)
+    if ((p.ok & 2) && zlo > c.zn && zhi < c.zf && ulo > -1.5f && uhi < c.W + 1.5f && vlo > -1.5f &&
+        vhi < c.H + 1.5f && lam <= 1000.0f)
         return 1;
     return 2;
+}
+
+__device__ __forceinline__ int classify(const float *g, float wd, const CamK &c, const BandK &b)
+{
+    return classify_cam(g, classify_pre(g, wd, b), c, b);
 }
 
 __device__ __forceinline__ u32 lane_rank(u64 mask)
@@ -357,6 +377,30 @@ __device__ __forceinline__ u64 wave_sum_u64(u64 x)
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o);
     return x;
+}
+
+// Step of a launch: the kernel argument, or (graph replay) the value at
+// t_dev clamped to [1, T]; returns the table row of step t (+1 for a flush)
+// and the largest defer count that row holds.
+struct StepK {
+    int32_t t, T, K, pad;
+    const int32_t *t_dev;
+    const float *lut;                // table base (W rows start at 0)
+};
+
+__device__ __forceinline__ int resolve_step(const StepK &s, int extra, const float **wrow, int *dmax)
+{
+    int t = s.t;
+    if (s.t_dev) {
+        t = *s.t_dev;
+        t = t < 1 ? 1 : (t > s.T ? s.T : t);
+    }
+    const int64_t tr = (int64_t)t + extra;
+    *wrow = s.lut + (s.K > 0 ? (tr - 1) * (s.K + 1) : tr * (tr - 1) / 2);
+    int64_t dm = tr - 1;
+    if (s.K > 0 && dm > s.K) dm = s.K;
+    *dmax = (int)dm;
+    return t;
 }
 
 // ---------------------------------------------------------------------------
@@ -376,8 +420,7 @@ struct CullArgs {
     float rb, pad3;
     const int32_t *last;
     int64_t n;
-    int32_t t, K, dmax, pad0;
-    const float *Wrow;               // LUT row of step t
+    StepK step;
     float lr[10];
     float eps;
     CamK cam;
@@ -403,6 +446,10 @@ __global__ __launch_bounds__(kCullBlock) void k_cull(CullArgs a)
     float *sG = reinterpret_cast<float *>(sG4);
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const float *Wrow;
+    int dmax;
+    const int t = resolve_step(a.step, 0, &Wrow, &dmax);
+    const int K = a.step.K;
     if (tid == 0) {
         sParity = __hip_atomic_load(&a.hdr->parity, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         sRestored = 0;
@@ -449,10 +496,10 @@ __global__ __launch_bounds__(kCullBlock) void k_cull(CullArgs a)
                     g[2 * j] = q.x;
                     g[2 * j + 1] = q.y;
                 }
-                int d = a.t - 1 - lastv[k];
-                d = d < 0 ? 0 : (d > a.dmax ? a.dmax : d);
+                int d = t - 1 - lastv[k];
+                d = d < 0 ? 0 : (d > dmax ? dmax : d);
                 // with dense geometry the stored G is always current
-                const float wd = (d > 0 && !a.geo_dense) ? a.Wrow[d] : 0.0f;
+                const float wd = (d > 0 && !a.geo_dense) ? Wrow[d] : 0.0f;
                 const int cls = a.mode == 1 ? classify(g, wd, a.cam, a.band) : 2;
                 if (cls == 2) {
                     if (d > 0 && !a.geo_dense) {
@@ -485,7 +532,7 @@ __global__ __launch_bounds__(kCullBlock) void k_cull(CullArgs a)
                 } else {
                     keep = cls == 1;
                 }
-                sat = (a.K > 0) && !keep && d == a.K;
+                sat = (K > 0) && !keep && d == K;
             }
             bv[k] = __ballot(keep);
             bs[k] = __ballot(sat);
@@ -608,14 +655,15 @@ struct RowArgs {
     float *gw, *aw;
     int64_t gw_ld, aw_ld;
     MomRef gm, gv, am, av;
-    int32_t adim, t, K, dmax;
+    int32_t adim, pad3;
+    StepK step;
     float lr[64];                    // lane-indexed: 0..9 G, 10.. A
     float eps, omb1, omb2, rb;       // rb: clamp of the restore factor and of the Adam step
     u64 sr_seed;
     int32_t geo_dense, pad2;
     int32_t *last;
     int64_t n;
-    const float *Wrow, *Mf, *Vf, *SS, *BC;
+    const float *Mf, *Vf, *SS, *BC;
     const u32 *ids, *count;
     u32 cap, pad1;
     const u32 *sat_ids, *sat_count;
@@ -647,6 +695,9 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
     const float lr = a.lr[lane];
     const MomRef &qm = isG ? a.gm : a.am;
     const MomRef &qv = isG ? a.gv : a.av;
+    const float *Wrow;
+    int dmax;
+    const int t = resolve_step(a.step, MODE == kFlush ? 1 : 0, &Wrow, &dmax);
 
     int64_t nvis, total;
     if (MODE == kFlush) {
@@ -659,12 +710,12 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
     }
     float ss = 0.0f, bc = 1.0f;
     if (MODE == kAdam) {
-        ss = a.SS[a.t];
-        bc = a.BC[a.t];
+        ss = a.SS[t];
+        bc = a.BC[t];
     }
     const float step = lr * ss;
     const bool quant = (GST != GS_F32) || (AST != GS_F32);
-    const u64 s_step = quant ? sm_at(a.sr_seed, (u64)a.t) : 0ull;
+    const u64 s_step = quant ? sm_at(a.sr_seed, (u64)t) : 0ull;
 
     for (int64_t base = wid * kRowUnroll; base < total; base += nw * kRowUnroll) {
         int64_t id[kRowUnroll];
@@ -686,8 +737,8 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
             int dd = 0;
             if (ok[u]) {
                 const int last = a.last[id[u]];
-                dd = (MODE == kFlush) ? a.t - last : a.t - 1 - last;
-                dd = dd < 0 ? 0 : (dd > a.dmax ? a.dmax : dd);
+                dd = (MODE == kFlush) ? t - last : t - 1 - last;
+                dd = dd < 0 ? 0 : (dd > dmax ? dmax : dd);
             }
             d[u] = dd;
         }
@@ -719,7 +770,7 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
             const int64_t r = id[u];
             if (MODE == kGather) {
                 float x = w[u];
-                if (d[u] > 0 && grest) x = restore1(x, m[u], v[u], a.Wrow[d[u]], lr, a.eps, a.rb);
+                if (d[u] > 0 && grest) x = restore1(x, m[u], v[u], Wrow[d[u]], lr, a.eps, a.rb);
                 if (act) {
                     if (isG) {
                         if (a.out_geo) a.out_geo[(base + u) * 10 + lane] = x;
@@ -748,12 +799,12 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
                 float x, m1, v1;
                 if (MODE == kAdam) {
                     x = w[u];
-                    if (dd > 0) x = restore1(x, m[u], v[u], a.Wrow[dd], lr, a.eps, a.rb);
+                    if (dd > 0) x = restore1(x, m[u], v[u], Wrow[dd], lr, a.eps, a.rb);
                     m1 = a.Mf[dd] * m[u] + a.omb1 * g[u];
                     v1 = a.Vf[dd] * v[u] + (a.omb2 * g[u]) * g[u];
                     x = x - adam_step(m1, v1, step, bc, a.eps, a.rb);
                 } else {
-                    x = restore1(w[u], m[u], v[u], a.Wrow[dd], lr, a.eps, a.rb);
+                    x = restore1(w[u], m[u], v[u], Wrow[dd], lr, a.eps, a.rb);
                     m1 = a.Mf[dd - 1] * m[u];
                     v1 = a.Vf[dd - 1] * v[u];
                 }
@@ -777,7 +828,7 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
                     else a.gd_app[r * a.adim + ca] = 0.0f;
                 }
             }
-            if (lane == 0) a.last[r] = a.t;
+            if (lane == 0) a.last[r] = t;
         }
     }
 }
@@ -795,7 +846,7 @@ struct RescaleArgs {
     int32_t fp8[4];                  // which of the four are FP8
     int64_t n, nb;
     u64 sr_seed;
-    int32_t t, pad0;
+    StepK step;
 };
 
 __global__ __launch_bounds__(256) void k_fp8_rescale(RescaleArgs a)
@@ -803,7 +854,10 @@ __global__ __launch_bounds__(256) void k_fp8_rescale(RescaleArgs a)
     const int lane = threadIdx.x & 63;
     const int64_t wid = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int64_t nw = (int64_t)gridDim.x * 4;
-    const u64 s_step = sm_at(a.sr_seed, (u64)a.t);
+    const float *Wrow;
+    int dmax;
+    const int t = resolve_step(a.step, 0, &Wrow, &dmax);
+    const u64 s_step = sm_at(a.sr_seed, (u64)t);
     for (int64_t task = wid; task < 4 * a.nb; task += nw) {
         const int which = (int)(task / a.nb);
         const int64_t b = task - (int64_t)which * a.nb;
@@ -840,7 +894,7 @@ struct DenseArgs {
     float *w;
     MomRef m, v;
     int64_t n;
-    int32_t t, pad0;
+    StepK step;
     float lr[10];
     float eps, omb1, omb2, b1f, b2f, rb;
     const float *SS, *BC;
@@ -884,8 +938,11 @@ __global__ __launch_bounds__(256) void k_dense_geo(DenseArgs a)
         }
         __syncthreads();
     }
-    const float ss = a.SS[a.t], bc = a.BC[a.t];
-    const u64 s_step = GST != GS_F32 ? sm_at(a.sr_seed, (u64)a.t) : 0ull;
+    const float *Wrow;
+    int dmax;
+    const int t = resolve_step(a.step, 0, &Wrow, &dmax);
+    const float ss = a.SS[t], bc = a.BC[t];
+    const u64 s_step = GST != GS_F32 ? sm_at(a.sr_seed, (u64)t) : 0ull;
     for (int e = tid; e < rows * 10; e += 256) {
         const int r = e / 10, c = e - r * 10;
         const int64_t row = row0 + r;
@@ -1039,6 +1096,26 @@ LutPtrs lut_ptrs(const gs_model *m, int64_t t)
     return {base + gsdp::lut_w_row(t, m->max_defer), base + L.offM, base + L.offV, base + L.offSS, base + L.offBC};
 }
 
+// step >= 1: that step; step == 0: the step is read from *step_dev when the
+// kernels run (graph replay), clamped to [1, lut_max_steps]
+bool step_ok(const gs_model *m, int64_t step)
+{
+    if (step == 0) return m->step_dev != nullptr;
+    return step >= 1 && step <= m->lut_max_steps;
+}
+
+StepK step_k(const gs_model *m, int64_t step)
+{
+    StepK k;
+    memset(&k, 0, sizeof k);
+    k.t = (int32_t)step;
+    k.T = m->lut_max_steps;
+    k.K = m->max_defer;
+    k.t_dev = step == 0 ? m->step_dev : nullptr;
+    k.lut = static_cast<const float *>(m->lut);
+    return k;
+}
+
 int dmax_for(const gs_model *m, int64_t t_row)
 {
     int64_t dm = t_row - 1;
@@ -1058,7 +1135,6 @@ void fill_rows(RowArgs &a, const gs_model *m)
     a.am = {m->app.m, m->app.m_scale, m->app.m_ld};
     a.av = {m->app.v, m->app.v_scale, m->app.v_ld};
     a.adim = m->app.dim;
-    a.K = m->max_defer;
     for (int c = 0; c < 10; ++c) a.lr[c] = m->geo.lr[c];
     for (int c = 0; c < m->app.dim; ++c) a.lr[10 + c] = m->app.lr[c];
     a.eps = (float)m->eps;
@@ -1069,6 +1145,41 @@ void fill_rows(RowArgs &a, const gs_model *m)
     a.geo_dense = m->geo_mode == 1;
     a.last = m->last_step;
     a.n = m->n;
+}
+
+// Camera constants of cull_v1 and of the band classifier (bounds rounded up).
+void pack_camera(const gs_model *model, const gs_camera *cam, CamK &k, BandK &b)
+{
+    for (int i = 0; i < 9; ++i) k.R[i] = cam->R[i];
+    for (int i = 0; i < 3; ++i) k.T[i] = cam->t[i];
+    k.fx = cam->fx;
+    k.fy = cam->fy;
+    k.cx = cam->cx;
+    k.cy = cam->cy;
+    k.W = (float)cam->width;
+    k.H = (float)cam->height;
+    k.zn = cam->near_plane;
+    k.zf = cam->far_plane;
+    const double B = (double)restore_bound(model->beta1, model->beta2) * 1.001;
+    auto mx = [&](int lo, int hi) {
+        double v = 0.0;
+        for (int c = lo; c < hi; ++c) v = std::max(v, (double)std::fabs(model->geo.lr[c]));
+        return (float)(B * v * (1.0 + 1e-6));
+    };
+    b.kpos = mx(0, 3);
+    b.kscl = mx(3, 6);
+    b.kq = mx(6, 10);
+    auto rs = [&](int r) {
+        return (float)((std::fabs((double)cam->R[3 * r]) + std::fabs((double)cam->R[3 * r + 1]) +
+                        std::fabs((double)cam->R[3 * r + 2])) * (1 + 1e-6));
+    };
+    b.rs0 = rs(0);
+    b.rs1 = rs(1);
+    b.rs2 = rs(2);
+    const float limx = 1.3f * ((0.5f * (float)cam->width) / cam->fx);
+    const float limy = 1.3f * ((0.5f * (float)cam->height) / cam->fy);
+    const double fx = cam->fx, fy = cam->fy;
+    b.jf2 = (float)((fx * fx * (1.0 + (double)limx * limx) + fy * fy * (1.0 + (double)limy * limy)) * (1.0 + 1e-4));
 }
 
 // Launch k_rows<MODE> for the moment storage types of the model's groups.
@@ -1097,6 +1208,416 @@ int row_grid(int64_t rows)
     if (want > cap) want = cap;
     if (want < 1) want = 1;
     return (int)want;
+}
+
+// ---------------------------------------------------------------------------
+// batched form: many scenes x many cameras in one pass
+// ---------------------------------------------------------------------------
+// The scenes are row ranges of one model (each starting at a multiple of
+// kMultiAlign rows).  One tile of one scene is loaded once and culled against
+// all C <= 32 cameras of that scene.  One global ordered compaction produces
+//   union_ids : rows visible to at least one camera of their scene (ascending)
+//   cam_pos[c]: for camera slot c, the union positions of the rows it sees
+//               (ascending, all scenes back to back; scene_start gives each
+//               scene's first entry in every list)
+// with a decoupled look-back whose payload is 33 counters.
+constexpr int kMaxCams = 32;
+constexpr int kNCnt = kMaxCams + 1;
+constexpr int kMultiAlign = 1024;
+constexpr int kMultiMinTile = 128;
+
+struct CamPack {                     // one camera with its band-classifier constants
+    CamK cam;
+    BandK band;
+    float pad[5];
+};
+
+struct MultiArgs {
+    const float *gw;
+    MomRef gm, gv;
+    int32_t gst, mode;
+    float rb, eps;
+    const int32_t *last;
+    int64_t n;
+    StepK step;
+    float lr[10];
+    int32_t S, C, n_sets, pad0;
+    const int64_t *scene_row0;       // [S+1]
+    const CamPack *cams;             // [n_sets][S][C]
+    u32 *union_ids, *union_count;
+    u32 *cam_pos, *cam_count;
+    u32 cap_union, cap_cam;
+    u32 *scene_start;                // [S][1+C]
+    gsdp::WsHeader *hdr;
+    u32 *flags;                      // [2][stride]
+    u32 *vals;                       // [2][stride][2][kNCnt]: aggregate, inclusive
+    int64_t tiles;                   // tiles of this launch
+    int64_t stride;                  // tiles of the smallest tile size (buffer halves)
+};
+
+template <int BLOCK, int IPT>
+__global__ __launch_bounds__(BLOCK) void k_cull_multi(MultiArgs a)
+{
+    constexpr int NW = BLOCK / 64;
+    constexpr int TR = BLOCK * IPT;
+    constexpr int NSLAB = IPT * NW;
+    __shared__ float4 sG4[TR * 10 / 4];
+    __shared__ u32 sCnt[NSLAB][kNCnt];
+    __shared__ u32 sOff[NSLAB][kNCnt];
+    __shared__ u32 sAgg[kNCnt], sExcl[kNCnt];
+    __shared__ u32 sTile, sParity, sScene;
+    float *sG = reinterpret_cast<float *>(sG4);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const float *Wrow;
+    int dmax;
+    const int t = resolve_step(a.step, 0, &Wrow, &dmax);
+    const int C = a.C;
+    if (tid == 0) sParity = __hip_atomic_load(&a.hdr->parity, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 1u;
+    __syncthreads();
+    const u32 parity = sParity;
+    u32 *flags = a.flags + (size_t)parity * a.stride;
+    u32 *flags_other = a.flags + (size_t)(parity ^ 1u) * a.stride;
+    u32 *vals = a.vals + (size_t)parity * a.stride * 2 * kNCnt;
+    const int set = (t - 1) % a.n_sets;
+
+    for (;;) {
+        if (tid == 0) sTile = atomicAdd(&a.hdr->ticket, 1u);
+        __syncthreads();
+        const u32 tile = sTile;
+        if ((int64_t)tile >= a.tiles) break;
+        const int64_t row0 = (int64_t)tile * TR;
+        const int rows = (int)min((int64_t)TR, a.n - row0);
+        if (tid == 0) {
+            int sc = 0;
+            while (sc + 1 < a.S && a.scene_row0[sc + 1] <= row0) ++sc;
+            sScene = (u32)sc;
+        }
+        const int nf = rows * 10, nf4 = nf >> 2;
+        const float *src = a.gw + row0 * 10;
+        const float4 *src4 = reinterpret_cast<const float4 *>(src);
+        for (int j = tid; j < nf4; j += BLOCK) sG4[j] = src4[j];
+        for (int j = nf4 * 4 + tid; j < nf; j += BLOCK) sG[j] = src[j];
+        int lastv[IPT];
+#pragma unroll
+        for (int k = 0; k < IPT; ++k) {
+            const int r = k * BLOCK + tid;
+            lastv[k] = r < rows ? a.last[row0 + r] : 0;
+        }
+        __syncthreads();
+        const int scene = (int)sScene;
+        const bool in_scene = row0 < a.scene_row0[scene + 1];
+        const CamPack *cams = a.cams + ((int64_t)set * a.S + scene) * C;
+
+        u32 mask[IPT];
+#pragma unroll
+        for (int k = 0; k < IPT; ++k) {
+            const int r = k * BLOCK + tid;
+            u32 mk = 0;
+            if (r < rows && in_scene) {
+                float g[10];
+                const float2 *p2 = reinterpret_cast<const float2 *>(sG + r * 10);
+#pragma unroll
+                for (int j = 0; j < 5; ++j) {
+                    const float2 q = p2[j];
+                    g[2 * j] = q.x;
+                    g[2 * j + 1] = q.y;
+                }
+                int d = t - 1 - lastv[k];
+                d = d < 0 ? 0 : (d > dmax ? dmax : d);
+                const float wd = d > 0 ? Wrow[d] : 0.0f;
+                u32 undecided = 0;
+                const RowPre pre = classify_pre(g, wd, cams[0].band);
+                for (int c = 0; c < C; ++c) {
+                    const int cls = a.mode == 1 ? classify_cam(g, pre, cams[c].cam, cams[c].band) : 2;
+                    if (cls == 1) mk |= 1u << c;
+                    else if (cls == 2) undecided |= 1u << c;
+                }
+                if (undecided) {
+                    if (d > 0) {
+                        const int64_t row = row0 + r;
+                        float mv[10], vv[10];
+                        if (a.gst == GS_F32) {
+                            for (int j = 0; j < 10; ++j) {
+                                mv[j] = mom_load<GS_F32>(a.gm, row, j, false);
+                                vv[j] = mom_load<GS_F32>(a.gv, row, j, true);
+                            }
+                        } else if (a.gst == GS_BF16) {
+                            for (int j = 0; j < 10; ++j) {
+                                mv[j] = mom_load<GS_BF16>(a.gm, row, j, false);
+                                vv[j] = mom_load<GS_BF16>(a.gv, row, j, true);
+                            }
+                        } else {
+                            for (int j = 0; j < 10; ++j) {
+                                mv[j] = mom_load<GS_FP8E4M3>(a.gm, row, j, false);
+                                vv[j] = mom_load<GS_FP8E4M3>(a.gv, row, j, true);
+                            }
+                        }
+                        for (int j = 0; j < 10; ++j) g[j] = restore1(g[j], mv[j], vv[j], wd, a.lr[j], a.eps, a.rb);
+                    }
+                    for (int c = 0; c < C; ++c)
+                        if (((undecided >> c) & 1u) && cull_v1(g, cams[c].cam)) mk |= 1u << c;
+                }
+            }
+            mask[k] = mk;
+            const int slab = k * NW + wave;
+            const u64 ub = __ballot(mk != 0u);
+            if (lane == 0) sCnt[slab][0] = (u32)__popcll(ub);
+            for (int c = 0; c < C; ++c) {
+                const u64 cb = __ballot((mk >> c) & 1u);
+                if (lane == 0) sCnt[slab][1 + c] = (u32)__popcll(cb);
+            }
+        }
+        __syncthreads();
+        if (tid < 1 + C) {
+            u32 o = 0;
+            for (int sl = 0; sl < NSLAB; ++sl) {
+                sOff[sl][tid] = o;
+                o += sCnt[sl][tid];
+            }
+            sAgg[tid] = o;
+        }
+        __syncthreads();
+
+        // decoupled look-back over 1 + C counters (wave 0; lane j owns counter j)
+        if (wave == 0) {
+            const int ncnt = 1 + C;
+            const u32 agg = lane < ncnt ? sAgg[lane] : 0u;
+            u32 excl = 0;
+            if (tile > 0) {
+                if (lane < ncnt) vals[((size_t)tile * 2 + 0) * kNCnt + lane] = agg;
+                __threadfence();
+                if (lane == 0) __hip_atomic_store(&flags[tile], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                int64_t base = (int64_t)tile - 1;
+                for (;;) {
+                    const int64_t idx = base - lane;
+                    u32 f = 2u;
+                    if (idx >= 0) {
+                        u32 spins = 0;
+                        f = __hip_atomic_load(&flags[idx], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+                        while (f == 0u && spins < kSpinLimit) {
+                            __builtin_amdgcn_s_sleep(1);
+                            f = __hip_atomic_load(&flags[idx], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+                            ++spins;
+                        }
+                        if (f == 0u) {
+                            atomicOr(&a.hdr->error, 1u);
+                            f = 3u;  // treated as an inclusive zero
+                        }
+                    }
+                    const u64 incm = __ballot(f >= 2u);
+                    const int stop = incm ? __builtin_ctzll(incm) : 63;
+                    for (int j = 0; j < ncnt; ++j) {
+                        u32 x = 0;
+                        if (idx >= 0 && lane <= stop && f != 3u)
+                            x = vals[((size_t)idx * 2 + (f == 2u ? 1 : 0)) * kNCnt + j];
+                        u64 sum = wave_sum_u64((u64)x);
+                        if (lane == j) excl += (u32)sum;
+                    }
+                    if (incm) break;
+                    base -= 64;
+                }
+            }
+            if (lane < ncnt) {
+                vals[((size_t)tile * 2 + 1) * kNCnt + lane] = excl + agg;
+                sExcl[lane] = excl;
+            }
+            __threadfence();
+            if (lane == 0) __hip_atomic_store(&flags[tile], 2u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            // the next call uses the other half, whatever its tile size: clear all of it
+            for (int64_t j = tile + lane * a.tiles; j < a.stride; j += 64 * a.tiles) flags_other[j] = 0u;
+            if (lane < ncnt) {
+                if (row0 == a.scene_row0[scene]) a.scene_start[(int64_t)scene * (1 + C) + lane] = excl;
+                if ((int64_t)tile == a.tiles - 1) {
+                    if (lane == 0) *a.union_count = excl + agg;
+                    else a.cam_count[lane - 1] = excl + agg;
+                }
+            }
+        }
+        __syncthreads();
+
+        const u32 eu = sExcl[0];
+#pragma unroll
+        for (int k = 0; k < IPT; ++k) {
+            const u32 mk = mask[k];
+            const int slab = k * NW + wave;
+            const u64 ub = __ballot(mk != 0u);
+            const u32 p = eu + sOff[slab][0] + lane_rank(ub);
+            if (mk && p < a.cap_union) a.union_ids[p] = (u32)(row0 + k * BLOCK + tid);
+            for (int c = 0; c < C; ++c) {
+                const bool on = (mk >> c) & 1u;
+                const u64 cb = __ballot(on);
+                if (on) {
+                    const u32 q = sExcl[1 + c] + sOff[slab][1 + c] + lane_rank(cb);
+                    if (q < a.cap_cam) a.cam_pos[(size_t)c * a.cap_cam + q] = p;
+                }
+            }
+        }
+    }
+
+    __syncthreads();
+    if (tid == 0) {
+        __threadfence();
+        const u32 prev = atomicAdd(&a.hdr->done, 1u);
+        if (prev == gridDim.x - 1) {
+            __threadfence();
+            if (a.tiles == 0) {
+                *a.union_count = 0;
+                for (int c = 0; c < C; ++c) a.cam_count[c] = 0;
+            }
+            a.hdr->ticket = 0;
+            a.hdr->done = 0;
+            a.hdr->parity = parity ^ 1u;
+        }
+    }
+}
+
+// Deterministic sum of the per-camera gradients onto the union rows:
+// out[p] = (...((0 + g_c0) + g_c1) + ...) over the camera slots that see p, in
+// slot order.  cam_pos[c] is ascending, so the entries of a block of union
+// positions form one contiguous range per camera (binary search).
+struct GradSumArgs {
+    const u32 *cam_pos, *cam_count, *union_count;
+    u32 cap_cam, cap_union;
+    int32_t C, adim;
+    const float *g_cam;              // [C][cap_cam][10 + adim]
+    float *out_geo, *out_app;        // [cap_union][10], [cap_union][adim]
+};
+
+constexpr int kSumRows = 32;
+
+__device__ __forceinline__ u32 lower_bound_u32(const u32 *a, u32 n, u32 key)
+{
+    u32 lo = 0, hi = n;
+    while (lo < hi) {
+        const u32 mid = (lo + hi) >> 1;
+        if (a[mid] < key) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(256) void k_grad_sum(GradSumArgs a)
+{
+    __shared__ float acc[kSumRows][64];
+    __shared__ u32 sLo[kMaxCams], sHi[kMaxCams];
+    const int tid = threadIdx.x;
+    const int D = 10 + a.adim;
+    const u32 U = min(*a.union_count, a.cap_union);
+    for (u32 p0 = blockIdx.x * kSumRows; p0 < U; p0 += gridDim.x * kSumRows) {
+        for (int e = tid; e < kSumRows * 64; e += 256) acc[e / 64][e % 64] = 0.0f;
+        if (tid < a.C) {
+            const u32 nc = min(a.cam_count[tid], a.cap_cam);
+            const u32 *lst = a.cam_pos + (size_t)tid * a.cap_cam;
+            sLo[tid] = lower_bound_u32(lst, nc, p0);
+            sHi[tid] = lower_bound_u32(lst, nc, p0 + kSumRows);
+        }
+        __syncthreads();
+        for (int c = 0; c < a.C; ++c) {
+            const u32 lo = sLo[c], cnt = sHi[c] - lo;
+            const u32 *lst = a.cam_pos + (size_t)c * a.cap_cam;
+            const float *gc = a.g_cam + (size_t)c * a.cap_cam * D;
+            for (u32 e = tid; e < cnt * (u32)D; e += 256) {
+                const u32 i = lo + e / D, col = e % D;
+                acc[lst[i] - p0][col] += gc[(size_t)i * D + col];
+            }
+            __syncthreads();
+        }
+        const u32 np = min((u32)kSumRows, U - p0);
+        for (u32 e = tid; e < np * (u32)D; e += 256) {
+            const u32 r = e / D, col = e % D;
+            if (col < 10) a.out_geo[(size_t)(p0 + r) * 10 + col] = acc[r][col];
+            else a.out_app[(size_t)(p0 + r) * a.adim + (col - 10)] = acc[r][col];
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_step_advance(int32_t *t) { *t += 1; }
+
+}  // namespace
+
+namespace {
+
+// autotuned variants of the batched cull: (block size, rows per thread)
+constexpr int kMultiVariants = 6;
+constexpr int kMultiBlock[kMultiVariants] = {128, 128, 128, 256, 256, 256};
+constexpr int kMultiIpt[kMultiVariants] = {1, 2, 4, 1, 2, 4};
+
+int64_t multi_ws_bytes(int64_t n)
+{
+    const int64_t tiles = (n + kMultiMinTile - 1) / kMultiMinTile;
+    return gsdp::kWsHeader + 8 * tiles + 2 * tiles * 2 * kNCnt * 4;
+}
+
+int multi_args(const gs_model *model, const gs_multi *d, int64_t step, void *ws, size_t ws_bytes, MultiArgs &a)
+{
+    int rc = check_model(model);
+    if (rc) return rc;
+    if (!d || !step_ok(model, step)) return GS_EINVAL;
+    if (model->max_defer != 0 || model->geo_mode != 0) return GS_EUNSUPPORTED;
+    if (d->n_scenes < 1 || d->cams_per_scene < 1 || d->cams_per_scene > kMaxCams || d->n_sets < 1) return GS_EINVAL;
+    if (d->variant < 0 || d->variant >= kMultiVariants) return GS_EINVAL;
+    if (!d->scene_row0 || !d->cams || !d->union_ids || !d->union_count || !d->cam_pos || !d->cam_count ||
+        !d->scene_start)
+        return GS_EINVAL;
+    if (!ws || !aligned(ws, 256) || (int64_t)ws_bytes < multi_ws_bytes(model->n)) return GS_ESPACE;
+    memset(&a, 0, sizeof a);
+    a.gw = model->geo.w;
+    a.gm = {model->geo.m, model->geo.m_scale, model->geo.m_ld};
+    a.gv = {model->geo.v, model->geo.v_scale, model->geo.v_ld};
+    a.gst = model->geo.state;
+    a.rb = restore_bound(model->beta1, model->beta2);
+    a.mode = (model->cull_mode == 1 && model->eps > 0.0 && std::isfinite(a.rb)) ? 1 : 0;
+    a.eps = (float)model->eps;
+    a.last = model->last_step;
+    a.n = model->n;
+    a.step = step_k(model, step);
+    for (int c = 0; c < 10; ++c) a.lr[c] = model->geo.lr[c];
+    a.S = d->n_scenes;
+    a.C = d->cams_per_scene;
+    a.n_sets = d->n_sets;
+    a.scene_row0 = d->scene_row0;
+    a.cams = static_cast<const CamPack *>(d->cams);
+    a.union_ids = d->union_ids;
+    a.union_count = d->union_count;
+    a.cam_pos = d->cam_pos;
+    a.cam_count = d->cam_count;
+    a.cap_union = d->cap_union;
+    a.cap_cam = d->cap_cam;
+    a.scene_start = d->scene_start;
+    char *wsb = static_cast<char *>(ws);
+    a.hdr = reinterpret_cast<gsdp::WsHeader *>(wsb);
+    const int64_t max_tiles = (model->n + kMultiMinTile - 1) / kMultiMinTile;
+    a.flags = reinterpret_cast<u32 *>(wsb + gsdp::kWsHeader);
+    a.vals = reinterpret_cast<u32 *>(wsb + gsdp::kWsHeader + 8 * max_tiles);
+    a.tiles = max_tiles;  // replaced per variant in launch_multi
+    return GS_OK;
+}
+
+// The state buffers are laid out for the smallest tile; a variant with
+// larger tiles uses the first n/TR entries of each half.
+template <int BLOCK, int IPT>
+void launch_multi_t(MultiArgs a, int64_t n, int64_t max_tiles, hipStream_t st)
+{
+    constexpr int TR = BLOCK * IPT;
+    a.tiles = (n + TR - 1) / TR;
+    a.stride = max_tiles;
+    const int64_t grid = a.tiles < 1 ? 1 : a.tiles;
+    hipLaunchKernelGGL((k_cull_multi<BLOCK, IPT>), dim3((unsigned)grid), dim3(BLOCK), 0, st, a);
+}
+
+int launch_multi(int variant, const MultiArgs &a, int64_t n, hipStream_t st)
+{
+    const int64_t max_tiles = (n + kMultiMinTile - 1) / kMultiMinTile;
+    switch (variant) {
+    case 0: launch_multi_t<128, 1>(a, n, max_tiles, st); break;
+    case 1: launch_multi_t<128, 2>(a, n, max_tiles, st); break;
+    case 2: launch_multi_t<128, 4>(a, n, max_tiles, st); break;
+    case 3: launch_multi_t<256, 1>(a, n, max_tiles, st); break;
+    case 4: launch_multi_t<256, 2>(a, n, max_tiles, st); break;
+    default: launch_multi_t<256, 4>(a, n, max_tiles, st); break;
+    }
+    return launched("gs_cull_multi");
 }
 
 }  // namespace
@@ -1171,7 +1692,7 @@ int gs_cull(const gs_model *model, const gs_camera *cam, int64_t step, uint32_t 
     int rc = check_model(model);
     if (rc) return rc;
     if (!cam || !count_dev || !ws || (capacity > 0 && !ids)) return GS_EINVAL;
-    if (step < 1 || step > model->lut_max_steps) return GS_EINVAL;
+    if (!step_ok(model, step)) return GS_EINVAL;
     if (!(cam->fx > 0.0f && cam->fy > 0.0f) || cam->width <= 0 || cam->height <= 0) return GS_EINVAL;
     if (!aligned(ws, 256)) return GS_EINVAL;
     if ((int64_t)ws_bytes < gsdp::ws_bytes_for(model->n, model->max_defer, model->geo_mode, has_fp8(model))) return GS_ESPACE;
@@ -1185,43 +1706,13 @@ int gs_cull(const gs_model *model, const gs_camera *cam, int64_t step, uint32_t 
     a.rb = restore_bound(model->beta1, model->beta2);
     a.last = model->last_step;
     a.n = model->n;
-    a.t = (int32_t)step;
-    a.K = model->max_defer;
-    a.dmax = dmax_for(model, step);
-    a.Wrow = lut_ptrs(model, step).W;
+    a.step = step_k(model, step);
     for (int c = 0; c < 10; ++c) a.lr[c] = model->geo.lr[c];
     a.eps = (float)model->eps;
-    for (int i = 0; i < 9; ++i) a.cam.R[i] = cam->R[i];
-    for (int i = 0; i < 3; ++i) a.cam.T[i] = cam->t[i];
-    a.cam.fx = cam->fx;
-    a.cam.fy = cam->fy;
-    a.cam.cx = cam->cx;
-    a.cam.cy = cam->cy;
-    a.cam.W = (float)cam->width;
-    a.cam.H = (float)cam->height;
-    a.cam.zn = cam->near_plane;
-    a.cam.zf = cam->far_plane;
-    // band classifier constants; the band cull needs eps > 0 (with eps = 0 a
-    // row with m = v = 0 restores to NaN) and falls back to the exact cull
+    // the band cull needs eps > 0 (with eps = 0 a row with m = v = 0 restores
+    // to NaN) and a finite restore bound; otherwise the exact cull runs
     a.mode = (model->cull_mode == 1 && model->eps > 0.0 && std::isfinite(a.rb)) ? 1 : 0;
-    {
-        const double B = (double)a.rb * 1.001;
-        auto mx = [&](int lo, int hi) {
-            double v = 0.0;
-            for (int c = lo; c < hi; ++c) v = std::max(v, (double)std::fabs(model->geo.lr[c]));
-            return (float)(B * v * (1.0 + 1e-6));
-        };
-        a.band.kpos = mx(0, 3);
-        a.band.kscl = mx(3, 6);
-        a.band.kq = mx(6, 10);
-        a.band.rs0 = (float)((std::fabs((double)cam->R[0]) + std::fabs((double)cam->R[1]) + std::fabs((double)cam->R[2])) * (1 + 1e-6));
-        a.band.rs1 = (float)((std::fabs((double)cam->R[3]) + std::fabs((double)cam->R[4]) + std::fabs((double)cam->R[5])) * (1 + 1e-6));
-        a.band.rs2 = (float)((std::fabs((double)cam->R[6]) + std::fabs((double)cam->R[7]) + std::fabs((double)cam->R[8])) * (1 + 1e-6));
-        const float limx = 1.3f * ((0.5f * (float)cam->width) / cam->fx);
-        const float limy = 1.3f * ((0.5f * (float)cam->height) / cam->fy);
-        const double fx = cam->fx, fy = cam->fy;
-        a.band.jf2 = (float)((fx * fx * (1.0 + (double)limx * limx) + fy * fy * (1.0 + (double)limy * limy)) * (1.0 + 1e-4));
-    }
+    pack_camera(model, cam, a.cam, a.band);
     a.ids = ids;
     a.count = count_dev;
     a.cap = capacity;
@@ -1249,13 +1740,11 @@ int gs_gather(const gs_model *model, int64_t step, const uint32_t *ids, const ui
     int rc = check_model(model);
     if (rc) return rc;
     if (!count_dev || (capacity > 0 && !ids)) return GS_EINVAL;
-    if (step < 1 || step > model->lut_max_steps) return GS_EINVAL;
+    if (!step_ok(model, step)) return GS_EINVAL;
     if (capacity == 0 || (!out_geo && !out_app)) return GS_OK;
     RowArgs a;
     fill_rows(a, model);
-    a.t = (int32_t)step;
-    a.dmax = dmax_for(model, step);
-    a.Wrow = lut_ptrs(model, step).W;
+    a.step = step_k(model, step);
     a.ids = ids;
     a.count = count_dev;
     a.cap = capacity;
@@ -1286,7 +1775,7 @@ int gs_adam_step_deferred(const gs_model *model, int64_t step, const uint32_t *i
     int rc = check_model(model);
     if (rc) return rc;
     if (!count_dev || (capacity > 0 && !ids)) return GS_EINVAL;
-    if (step < 1 || step > model->lut_max_steps) return GS_EINVAL;
+    if (!step_ok(model, step)) return GS_EINVAL;
     const bool compact = g_geo || g_app;
     if (compact && (!g_geo || !g_app)) return GS_EINVAL;
     if (!compact && capacity > 0 && (!g_geo_dense || !g_app_dense)) return GS_EINVAL;
@@ -1297,10 +1786,8 @@ int gs_adam_step_deferred(const gs_model *model, int64_t step, const uint32_t *i
     }
     RowArgs a;
     fill_rows(a, model);
-    a.t = (int32_t)step;
-    a.dmax = dmax_for(model, step);
+    a.step = step_k(model, step);
     const LutPtrs L = lut_ptrs(model, step);
-    a.Wrow = L.W;
     a.Mf = L.Mf;
     a.Vf = L.Vf;
     a.SS = L.SS;
@@ -1327,7 +1814,7 @@ int gs_adam_step_deferred(const gs_model *model, int64_t step, const uint32_t *i
         da.v = {model->geo.v, model->geo.v_scale, model->geo.v_ld};
         da.n = model->n;
         da.rb = restore_bound(model->beta1, model->beta2);
-        da.t = (int32_t)step;
+        da.step = step_k(model, step);
         for (int c = 0; c < 10; ++c) da.lr[c] = model->geo.lr[c];
         da.eps = (float)model->eps;
         da.omb1 = (float)(1.0 - model->beta1);
@@ -1382,7 +1869,7 @@ int gs_adam_step_deferred(const gs_model *model, int64_t step, const uint32_t *i
         ra.n = model->n;
         ra.nb = nb;
         ra.sr_seed = model->sr_seed;
-        ra.t = (int32_t)step;
+        ra.step = step_k(model, step);
         hipLaunchKernelGGL(k_fp8_rescale, dim3(row_grid(4 * nb * kRowUnroll)), dim3(256), 0, (hipStream_t)stream, ra);
         rc1 = launched("gs_adam_step_deferred (fp8 rescale)");
         if (rc1) return rc1;
@@ -1395,14 +1882,12 @@ int gs_adam_flush(const gs_model *model, int64_t step, void *stream)
 {
     int rc = check_model(model);
     if (rc) return rc;
-    if (step < 1 || step > model->lut_max_steps) return GS_EINVAL;
+    if (!step_ok(model, step)) return GS_EINVAL;
     if (model->n == 0) return GS_OK;
     RowArgs a;
     fill_rows(a, model);
-    a.t = (int32_t)step;
-    a.dmax = dmax_for(model, step + 1);
+    a.step = step_k(model, step);
     const LutPtrs L = lut_ptrs(model, step + 1);
-    a.Wrow = L.W;
     a.Mf = L.Mf;
     a.Vf = L.Vf;
     launch_rows<kFlush>(model, row_grid(model->n), (hipStream_t)stream, a);
@@ -1423,6 +1908,111 @@ int gs_synth_grad(uint64_t seed, int64_t step, const uint32_t *ids, const uint32
     hipLaunchKernelGGL(k_synth, dim3(grid), dim3(256), 0, (hipStream_t)stream, (u64)seed, (u64)step, ids, count_dev,
                        capacity, dim, col0, scale, out);
     return launched("gs_synth_grad");
+}
+
+int gs_camera_pack_bytes(size_t *bytes)
+{
+    if (!bytes) return GS_EINVAL;
+    *bytes = sizeof(CamPack);
+    return GS_OK;
+}
+
+int gs_camera_pack(const gs_model *model, const gs_camera *cams, int32_t count, void *out_host)
+{
+    if (!model || !cams || !out_host || count < 0) return GS_EINVAL;
+    CamPack *out = static_cast<CamPack *>(out_host);
+    for (int i = 0; i < count; ++i) {
+        if (!(cams[i].fx > 0.0f && cams[i].fy > 0.0f) || cams[i].width <= 0 || cams[i].height <= 0) return GS_EINVAL;
+        memset(&out[i], 0, sizeof(CamPack));
+        pack_camera(model, &cams[i], out[i].cam, out[i].band);
+    }
+    return GS_OK;
+}
+
+int gs_multi_workspace_bytes(const gs_model *model, size_t *bytes)
+{
+    if (!model || !bytes || model->n < 0) return GS_EINVAL;
+    *bytes = (size_t)multi_ws_bytes(model->n);
+    return GS_OK;
+}
+
+int gs_cull_multi(const gs_model *model, const gs_multi *desc, int64_t step, void *ws, size_t ws_bytes, void *stream)
+{
+    MultiArgs a;
+    int rc = multi_args(model, desc, step, ws, ws_bytes, a);
+    if (rc) return rc;
+    return launch_multi(desc->variant, a, model->n, (hipStream_t)stream);
+}
+
+int gs_cull_multi_autotune(const gs_model *model, gs_multi *desc, int64_t step, void *ws, size_t ws_bytes,
+                           void *stream, float *times_ms, int32_t *n_variants)
+{
+    MultiArgs a;
+    int rc = multi_args(model, desc, step, ws, ws_bytes, a);
+    if (rc) return rc;
+    if (n_variants) *n_variants = kMultiVariants;
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return hip_fail(hipGetLastError(), "autotune events");
+    int best = 0;
+    float best_ms = 1e30f;
+    for (int v = 0; v < kMultiVariants; ++v) {
+        rc = launch_multi(v, a, model->n, st);  // warm-up
+        if (rc) break;
+        hipEventRecord(e0, st);
+        for (int r = 0; r < 3; ++r) launch_multi(v, a, model->n, st);
+        hipEventRecord(e1, st);
+        hipError_t he = hipEventSynchronize(e1);
+        if (he != hipSuccess) {
+            rc = hip_fail(he, "autotune");
+            break;
+        }
+        float ms = 0.0f;
+        hipEventElapsedTime(&ms, e0, e1);
+        ms /= 3.0f;
+        if (times_ms) times_ms[v] = ms;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = v;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (rc) return rc;
+    desc->variant = best;
+    return GS_OK;
+}
+
+int gs_grad_sum_multi(const gs_multi *desc, int32_t adim, const float *g_cam, float *out_geo, float *out_app,
+                      void *stream)
+{
+    if (!desc || !g_cam || !out_geo || !out_app || adim < 1 || adim > 54) return GS_EINVAL;
+    if (desc->cams_per_scene < 1 || desc->cams_per_scene > kMaxCams) return GS_EINVAL;
+    if (!desc->cam_pos || !desc->cam_count || !desc->union_count) return GS_EINVAL;
+    GradSumArgs a;
+    a.cam_pos = desc->cam_pos;
+    a.cam_count = desc->cam_count;
+    a.union_count = desc->union_count;
+    a.cap_cam = desc->cap_cam;
+    a.cap_union = desc->cap_union;
+    a.C = desc->cams_per_scene;
+    a.adim = adim;
+    a.g_cam = g_cam;
+    a.out_geo = out_geo;
+    a.out_app = out_app;
+    const int cu = cu_count();
+    int64_t want = ((int64_t)desc->cap_union + kSumRows - 1) / kSumRows;
+    int64_t cap = (int64_t)(cu > 0 ? cu : 256) * 8;
+    int grid = (int)(want < cap ? (want < 1 ? 1 : want) : cap);
+    hipLaunchKernelGGL(k_grad_sum, dim3(grid), dim3(256), 0, (hipStream_t)stream, a);
+    return launched("gs_grad_sum_multi");
+}
+
+int gs_step_advance(int32_t *step_dev, void *stream)
+{
+    if (!step_dev) return GS_EINVAL;
+    hipLaunchKernelGGL(k_step_advance, dim3(1), dim3(1), 0, (hipStream_t)stream, step_dev);
+    return launched("gs_step_advance");
 }
 
 }  // extern "C"

@@ -23,7 +23,9 @@ GS_F32, GS_BF16, GS_FP8E4M3 = 0, 1, 2
 # exported C symbols (kept in sync with include/gsdp.h)
 SYMBOLS = ("gs_lut_bytes", "gs_lut_build", "gs_lut_build_host", "gs_workspace_bytes", "gs_cull",
            "gs_gather", "gs_scatter_grad", "gs_adam_step_deferred", "gs_adam_flush", "gs_synth_grad",
-           "gs_device_cu_count", "gs_status_string", "gs_last_hip_error")
+           "gs_device_cu_count", "gs_status_string", "gs_last_hip_error", "gs_step_advance",
+           "gs_camera_pack_bytes", "gs_camera_pack", "gs_multi_workspace_bytes", "gs_cull_multi",
+           "gs_cull_multi_autotune", "gs_grad_sum_multi")
 
 
 class GsCamera(C.Structure):
@@ -44,7 +46,15 @@ class GsModel(C.Structure):
                 ("lut", C.c_void_p), ("lut_max_steps", C.c_int32), ("max_defer", C.c_int32),
                 ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double),
                 ("cull_mode", C.c_int32), ("geo_mode", C.c_int32), ("sr_seed", C.c_uint64),
-                ("reserved_", C.c_int32 * 4)]
+                ("step_dev", C.c_void_p), ("reserved_", C.c_int32 * 2)]
+
+
+class GsMulti(C.Structure):
+    _fields_ = [("n_scenes", C.c_int32), ("cams_per_scene", C.c_int32), ("n_sets", C.c_int32),
+                ("variant", C.c_int32), ("scene_row0", C.c_void_p), ("cams", C.c_void_p),
+                ("union_ids", C.c_void_p), ("union_count", C.c_void_p), ("cam_pos", C.c_void_p),
+                ("cam_count", C.c_void_p), ("cap_union", C.c_uint32), ("cap_cam", C.c_uint32),
+                ("scene_start", C.c_void_p)]
 
 
 def _load():
@@ -66,6 +76,13 @@ def _load():
         "gs_adam_flush": (C.c_int, [P(GsModel), i64, vp]),
         "gs_synth_grad": (C.c_int, [u64, i64, vp, vp, u32, i32, i32, f64, vp, vp]),
         "gs_device_cu_count": (C.c_int, []),
+        "gs_step_advance": (C.c_int, [vp, vp]),
+        "gs_camera_pack_bytes": (C.c_int, [P(sz)]),
+        "gs_camera_pack": (C.c_int, [P(GsModel), vp, i32, vp]),
+        "gs_multi_workspace_bytes": (C.c_int, [P(GsModel), P(sz)]),
+        "gs_cull_multi": (C.c_int, [P(GsModel), P(GsMulti), i64, vp, sz, vp]),
+        "gs_cull_multi_autotune": (C.c_int, [P(GsModel), P(GsMulti), i64, vp, sz, vp, vp, P(i32)]),
+        "gs_grad_sum_multi": (C.c_int, [P(GsMulti), i32, vp, vp, vp, vp]),
         "gs_status_string": (C.c_char_p, [C.c_int]),
         "gs_last_hip_error": (C.c_char_p, []),
     }
@@ -228,6 +245,9 @@ class Model:
         c.cull_mode = int(cull_mode)
         c.sr_seed = int(sr_seed)
         c.geo_mode = int(geo_mode)
+        # device step counter for graph replay (calls with step == 0 read it)
+        self.step_dev = torch.zeros(1, dtype=torch.int32, device=device)
+        c.step_dev = self.step_dev.data_ptr()
         self.c = c
         self.ws = torch.zeros(gs_workspace_bytes(self) // 4, dtype=torch.int32, device=device)
 
@@ -300,5 +320,94 @@ def gs_synth_grad(seed: int, step: int, ids, count, out, col0: int, sigma=1e-3, 
                              float(sigma), _ptr(out), _stream(stream)), "gs_synth_grad")
 
 
+def gs_step_advance(step_dev, stream=None):
+    _check(lib.gs_step_advance(_ptr(step_dev), _stream(stream)), "gs_step_advance")
+
+
 def gs_device_cu_count() -> int:
     return int(lib.gs_device_cu_count())
+
+
+# ---------------------------------------------------------------------------
+# batched form
+# ---------------------------------------------------------------------------
+MULTI_ALIGN = 1024
+
+
+class Multi:
+    """Device buffers of the batched cull of one model whose scenes are row
+    ranges [scene_row0[s], scene_row0[s+1]) (multiples of 1024).
+    camera_sets[k][s][c] is camera slot c of scene s in set k; update t uses
+    set (t-1) % len(camera_sets)."""
+
+    def __init__(self, model: Model, scene_row0, camera_sets, cap_union=None, cap_cam=None, variant=0):
+        dev = model.device
+        row0 = np.asarray(scene_row0, np.int64)
+        assert np.all(row0[:-1] % MULTI_ALIGN == 0) and row0[-1] == model.n
+        S = row0.shape[0] - 1
+        n_sets = len(camera_sets)
+        Cc = len(camera_sets[0][0])
+        self.S, self.C, self.n_sets = S, Cc, n_sets
+        self.cap_union = int(cap_union or model.n)
+        self.cap_cam = int(cap_cam or model.n)
+        self.scene_row0 = torch.from_numpy(row0).to(dev)
+        rb = C.c_size_t()
+        _check(lib.gs_camera_pack_bytes(C.byref(rb)), "gs_camera_pack_bytes")
+        recs = np.zeros(n_sets * S * Cc * rb.value, np.uint8)
+        flat = (GsCamera * (n_sets * S * Cc))()
+        i = 0
+        for k in range(n_sets):
+            for sc in range(S):
+                assert len(camera_sets[k][sc]) == Cc
+                for cam in camera_sets[k][sc]:
+                    flat[i] = camera_struct(cam)
+                    i += 1
+        _check(lib.gs_camera_pack(C.byref(model.c), flat, i, recs.ctypes.data), "gs_camera_pack")
+        self.cams = torch.from_numpy(recs).to(dev)
+        self.union_ids = torch.zeros(max(self.cap_union, 1), dtype=torch.int32, device=dev)
+        self.union_count = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.cam_pos = torch.zeros((Cc, max(self.cap_cam, 1)), dtype=torch.int32, device=dev)
+        self.cam_count = torch.zeros(Cc, dtype=torch.int32, device=dev)
+        self.scene_start = torch.zeros((S, 1 + Cc), dtype=torch.int32, device=dev)
+        wb = C.c_size_t()
+        _check(lib.gs_multi_workspace_bytes(C.byref(model.c), C.byref(wb)), "gs_multi_workspace_bytes")
+        self.ws = torch.zeros((wb.value + 3) // 4, dtype=torch.int32, device=dev)
+        d = GsMulti()
+        d.n_scenes, d.cams_per_scene, d.n_sets, d.variant = S, Cc, n_sets, int(variant)
+        d.scene_row0 = self.scene_row0.data_ptr()
+        d.cams = self.cams.data_ptr()
+        d.union_ids = self.union_ids.data_ptr()
+        d.union_count = self.union_count.data_ptr()
+        d.cam_pos = self.cam_pos.data_ptr()
+        d.cam_count = self.cam_count.data_ptr()
+        d.cap_union, d.cap_cam = self.cap_union, self.cap_cam
+        d.scene_start = self.scene_start.data_ptr()
+        self.c = d
+
+    def lists(self):
+        """Host copies: union ids, per-camera position lists, scene starts."""
+        u = int(self.union_count.item())
+        cc = self.cam_count.cpu().numpy()
+        ids = self.union_ids[:min(u, self.cap_union)].cpu().numpy().view(np.uint32)
+        pos = self.cam_pos.cpu().numpy().view(np.uint32)
+        cams = [pos[c, :min(int(cc[c]), self.cap_cam)].copy() for c in range(self.C)]
+        return u, ids, [int(x) for x in cc], cams, self.scene_start.cpu().numpy().view(np.uint32)
+
+
+def gs_cull_multi(model: Model, multi: Multi, step: int, stream=None):
+    _check(lib.gs_cull_multi(C.byref(model.c), C.byref(multi.c), int(step), _ptr(multi.ws), multi.ws.numel() * 4,
+                             _stream(stream)), "gs_cull_multi")
+
+
+def gs_cull_multi_autotune(model: Model, multi: Multi, step: int, stream=None):
+    times = (C.c_float * 16)()
+    nv = C.c_int32()
+    _check(lib.gs_cull_multi_autotune(C.byref(model.c), C.byref(multi.c), int(step), _ptr(multi.ws),
+                                      multi.ws.numel() * 4, _stream(stream), times, C.byref(nv)),
+           "gs_cull_multi_autotune")
+    return [times[i] for i in range(nv.value)]
+
+
+def gs_grad_sum_multi(multi: Multi, adim: int, g_cam, out_geo, out_app, stream=None):
+    _check(lib.gs_grad_sum_multi(C.byref(multi.c), int(adim), _ptr(g_cam), _ptr(out_geo), _ptr(out_app),
+                                 _stream(stream)), "gs_grad_sum_multi")

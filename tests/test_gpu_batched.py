@@ -1,0 +1,163 @@
+"""GPU parity of the batched form (many scenes x many cameras per launch),
+the autotuned variants and hipGraph replay with a device step counter."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import gs_inputs as gi
+from oracle import oracle as orc
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def g():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2509_15645_amd import gsdp
+    return gsdp
+
+
+def bits(a):
+    return np.ascontiguousarray(a, np.float32).view(np.uint32)
+
+
+def _batch(sizes, cams_per_scene, n_sets, seed=0):
+    """Scenes of uneven size concatenated on 1024-row boundaries (padding rows
+    have NaN positions and are never visible)."""
+    geos, apps, row0 = [], [], [0]
+    sets = [[] for _ in range(n_sets)]
+    for s, n in enumerate(sizes):
+        sc = gi.make_scene(n, seed=seed + s)
+        pad = (-n) % 1024
+        g = np.concatenate([sc.geo, np.full((pad, 10), np.nan, np.float32)])
+        g[n:, 6] = 1.0
+        geos.append(g)
+        apps.append(np.concatenate([sc.app, np.zeros((pad, 49), np.float32)]))
+        row0.append(row0[-1] + n + pad)
+        cams = gi.orbit_cameras(cams_per_scene * n_sets, seed=seed + 100 * s)
+        for k in range(n_sets):
+            sets[k].append(cams[k * cams_per_scene:(k + 1) * cams_per_scene])
+    return np.concatenate(geos), np.concatenate(apps), np.array(row0), sets
+
+
+def _compare_lists(multi, ref, tag):
+    u, ids, cc, cams, ss = multi.lists()
+    union, cam_pos, start = ref
+    assert u == union.shape[0], tag
+    assert np.array_equal(ids, union.astype(np.uint32)), tag
+    for c in range(len(cam_pos)):
+        assert cc[c] == cam_pos[c].shape[0], (tag, c)
+        assert np.array_equal(cams[c], cam_pos[c].astype(np.uint32)), (tag, c)
+    assert np.array_equal(ss.astype(np.int64), start), tag
+    return u, cc
+
+
+def test_batched_scenes_cameras_vs_oracle(g):
+    sizes, C, n_sets, steps = [30_000, 100_000, 7_000, 60_000], 8, 2, 3
+    geo, app, row0, sets = _batch(sizes, C, n_sets)
+    lg, la = gi.lr_columns()
+    model = g.Model(geo, app, lg, la, max_steps=16, cull_mode=1, app_state="bf16", sr_seed=5)
+    o4 = orc.DeferredF32(geo, app, lg, la, app_state="bf16", sr_seed=5)
+    multi = g.Multi(model, row0, sets)
+    D = 59
+    g_cam_dev = torch.zeros((C, multi.cap_cam, D), dtype=torch.float32, device="cuda")
+    out_g = torch.zeros((multi.cap_union, 10), dtype=torch.float32, device="cuda")
+    out_a = torch.zeros((multi.cap_union, 49), dtype=torch.float32, device="cuda")
+    rng = np.random.default_rng(7)
+    for t in range(1, steps + 1):
+        g.gs_cull_multi(model, multi, t)
+        torch.cuda.synchronize()
+        ref = orc.cull_multi(o4.current_geo(t), row0, sets[(t - 1) % n_sets])
+        u, cc = _compare_lists(multi, ref, f"step {t}")
+        g_cam = [rng.normal(0, 1e-3, (cc[c], D)).astype(np.float32) for c in range(C)]
+        g_cam_dev.zero_()
+        for c in range(C):
+            g_cam_dev[c, :cc[c]] = torch.from_numpy(g_cam[c]).cuda()
+        g.gs_grad_sum_multi(multi, 49, g_cam_dev, out_g, out_a)
+        gsum = orc.grad_sum_multi(ref[1], g_cam, u)
+        torch.cuda.synchronize()
+        assert np.array_equal(bits(out_g[:u].cpu().numpy()), bits(gsum[:, :10])), t
+        assert np.array_equal(bits(out_a[:u].cpu().numpy()), bits(gsum[:, 10:])), t
+        g.gs_adam_step_deferred(model, t, multi.union_ids, multi.union_count, out_g, out_a,
+                                capacity=multi.cap_union)
+        o4.step(t, ref[0], gsum[:, :10], gsum[:, 10:])
+        say(f"[batched] step {t}: union {u} per-camera {cc}")
+    st = model.state()
+    for k, name in ((0, "geo"), (1, "app")):
+        for part, refv in (("w", o4.w[k]), ("m", o4.m[k]), ("v", o4.v[k])):
+            got = st[f"{name}_{part}"]
+            assert np.array_equal(bits(got), bits(refv)), f"{name}_{part}"
+
+
+def test_batched_variants_agree_and_autotune(g):
+    sizes, C = [50_000, 20_000, 80_000], 16
+    geo, app, row0, sets = _batch(sizes, C, 1, seed=3)
+    lg, la = gi.lr_columns()
+    model = g.Model(geo, app, lg, la, max_steps=8, cull_mode=1)
+    multi = g.Multi(model, row0, sets)
+    ref = orc.cull_multi(geo, row0, sets[0])
+    for v in range(6):
+        multi.c.variant = v
+        g.gs_cull_multi(model, multi, 1)
+        torch.cuda.synchronize()
+        _compare_lists(multi, ref, f"variant {v}")
+    times = g.gs_cull_multi_autotune(model, multi, 1)
+    say(f"[autotune] times ms {['%.3f' % x for x in times]} -> variant {multi.c.variant}")
+    assert len(times) == 6 and 0 <= multi.c.variant < 6
+    assert times[multi.c.variant] == min(times)
+    g.gs_cull_multi(model, multi, 1)
+    torch.cuda.synchronize()
+    _compare_lists(multi, ref, "after autotune")
+    assert model.ws_header()["error"] == 0
+
+
+def _graph_step(g, model, multi, g_cam_dev, out_g, out_a):
+    g.gs_cull_multi(model, multi, 0)
+    g.gs_grad_sum_multi(multi, 49, g_cam_dev, out_g, out_a)
+    g.gs_adam_step_deferred(model, 0, multi.union_ids, multi.union_count, out_g, out_a, capacity=multi.cap_union)
+    g.gs_step_advance(model.step_dev)
+
+
+def test_batched_step_graph_replay_matches_eager(g):
+    """One batched step captured in a hipGraph with the step read from device
+    memory, replayed 4 times: every replay equals the eager step."""
+    sizes, C, n_sets = [20_000, 40_000], 4, 2
+    geo, app, row0, sets = _batch(sizes, C, n_sets, seed=9)
+    lg, la = gi.lr_columns()
+    mk = lambda: g.Model(geo, app, lg, la, max_steps=16, cull_mode=1, app_state="bf16", sr_seed=2)
+    eager, graphed = mk(), mk()
+    me, mg = g.Multi(eager, row0, sets), g.Multi(graphed, row0, sets)
+    D = 59
+    bufs = {}
+    for name, mu in (("e", me), ("g", mg)):
+        gc = torch.from_numpy(np.random.default_rng(1).normal(0, 1e-3, (C, mu.cap_cam, D)).astype(np.float32)).cuda()
+        bufs[name] = (gc, torch.zeros((mu.cap_union, 10), device="cuda"), torch.zeros((mu.cap_union, 49), device="cuda"))
+    graphed.step_dev.fill_(1)
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        pass
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        _graph_step(g, graphed, mg, *bufs["g"])
+    torch.cuda.synchronize()
+    for t in range(1, 5):
+        ge, oge, oae = bufs["e"]
+        g.gs_cull_multi(eager, me, t)
+        g.gs_grad_sum_multi(me, 49, ge, oge, oae)
+        g.gs_adam_step_deferred(eager, t, me.union_ids, me.union_count, oge, oae, capacity=me.cap_union)
+        graph.replay()
+        torch.cuda.synchronize()
+        assert int(graphed.step_dev.item()) == t + 1
+        a, b = eager.state(), graphed.state()
+        for key in a:
+            assert np.array_equal(a[key], b[key]), (t, key)
+        ue, ug = me.lists(), mg.lists()
+        assert ue[0] == ug[0] and np.array_equal(ue[1], ug[1])
+        say(f"[graph] replay {t}: union {ue[0]} identical to eager")

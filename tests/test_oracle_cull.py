@@ -224,3 +224,34 @@ def test_compaction_brute_force():
         ids = orc.compact(keep)
         assert ids.dtype == np.uint32
         assert ids.tolist() == [i for i in range(n) if keep[i]]
+
+
+def test_batched_lists_brute_force():
+    """Union / per-camera lists of a batch agree with per-camera culls row by
+    row, and the gradient sum adds each row's camera gradients in slot order."""
+    rng = np.random.default_rng(4)
+    sizes = [700, 1500, 300]
+    geo = np.concatenate([gi.make_scene(n, seed=i).geo for i, n in enumerate(sizes)])
+    row0 = np.concatenate([[0], np.cumsum(sizes)])
+    cams = [gi.orbit_cameras(3, seed=10 + s) for s in range(3)]
+    union, cam_pos, start = orc.cull_multi(geo, row0, cams)
+    vis = np.zeros((geo.shape[0], 3), bool)
+    for s in range(3):
+        for c in range(3):
+            vis[row0[s]:row0[s + 1], c] = orc.cull(geo[row0[s]:row0[s + 1]], cams[s][c])
+    assert np.array_equal(union, np.nonzero(vis.any(1))[0])
+    for c in range(3):
+        assert np.array_equal(union[cam_pos[c]], np.nonzero(vis[:, c])[0])
+        for s in range(3):
+            assert start[s, 1 + c] == vis[:row0[s], c].sum()
+    for s in range(3):
+        assert start[s, 0] == vis[:row0[s]].any(1).sum()
+    g_cam = [rng.normal(size=(cp.shape[0], 5)).astype(np.float32) for cp in cam_pos]
+    out = orc.grad_sum_multi(cam_pos, g_cam, union.shape[0])
+    for p in rng.choice(union.shape[0], 50, replace=False):
+        acc = np.zeros(5, np.float32)
+        for c in range(3):
+            hit = np.nonzero(cam_pos[c] == p)[0]
+            if hit.size:
+                acc = acc + g_cam[c][hit[0]]
+        assert np.array_equal(out[p], acc)
