@@ -38,12 +38,16 @@ def parse():
     p.add_argument("--scenes", type=int, default=16, help="batched16: number of scenes")
     p.add_argument("--cams", type=int, default=32, help="batched16: cameras per scene per step")
     p.add_argument("--scale", type=float, default=1.0, help="batched16: multiply every scene size")
+    p.add_argument("--copy-probe", type=int, default=0,
+                   help="only copy this many MiB device-to-device 5 times (calibrates HBM byte counters)")
     p.add_argument("--n", type=int, default=None, help="override the Gaussian count")
-    p.add_argument("--layout", default="interleaved", choices=["separate", "interleaved"])
+    p.add_argument("--layout", default="interleaved", choices=["separate", "interleaved", "fused"])
     p.add_argument("--max-defer", type=int, default=0)
     p.add_argument("--cull-mode", type=int, default=1)
-    p.add_argument("--state", default="f32", choices=["f32", "bf16"], help="Adam moment storage (both groups)")
-    p.add_argument("--geo-state", default=None, choices=["f32", "bf16"])
+    p.add_argument("--state", default="f32", choices=["f32", "bf16", "fp8"], help="Adam moment storage (both groups)")
+    p.add_argument("--geo-state", default=None, choices=["f32", "bf16", "fp8"])
+    p.add_argument("--graph", action="store_true",
+                   help="also time the step captured in a hipGraph (camera table + device step counter)")
     p.add_argument("--geo-mode", type=int, default=0, help="1 = dense geometric Adam every step")
     p.add_argument("--tilt", default="20,45", help="oblique tilt range in degrees")
     p.add_argument("--pool", type=int, default=4)
@@ -221,6 +225,16 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is a design note only",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.copy_probe:
+        import torch
+        n = args.copy_probe * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_mib": args.copy_probe, "launches": 5}))
+        return
     if args.workload == "batched16":
         run_batched(args)
         return
@@ -237,7 +251,7 @@ def main():
     lg, la = gi.lr_columns()
     total_steps = args.warmup + args.steps
     geo_state = args.geo_state or args.state
-    model = gsdp.Model(sc.geo, sc.app, lg, la, max_steps=total_steps + 1, max_defer=args.max_defer,
+    model = gsdp.Model(sc.geo, sc.app, lg, la, max_steps=2 * total_steps + 8, max_defer=args.max_defer,
                        cull_mode=args.cull_mode, app_layout=args.layout, geo_state=geo_state,
                        app_state=args.state, geo_mode=args.geo_mode, sr_seed=9)
     n = w.n
@@ -289,8 +303,37 @@ def main():
     h1 = model.ws_header()
     if h1["error"]:
         raise RuntimeError(f"cull look-back reported an error flag: {h1}")
-
     ms_step = (t1 - t0) * 1e3 / args.steps
+
+    graph_ms = None
+    if args.graph:
+        # the same step as one hipGraph: the single-camera cull runs as the batched
+        # cull with one scene and one camera per set (set k = the camera of step k+1)
+        ntab = total_steps + args.steps + 2
+        cam_sets = [[[w.camera_for_step(k + 1)]] for k in range(ntab)]
+        multi = gsdp.Multi(model, [0, n], cam_sets, cap_union=cap, cap_cam=1)
+        gg, ga = pool[0]
+        t_next = args.warmup + args.steps + 1
+        model.step_dev.fill_(t_next)
+
+        def gstep():
+            gsdp.gs_cull_multi(model, multi, 0)
+            gsdp.gs_gather(model, 0, multi.union_ids, multi.union_count, out_g, out_a, capacity=cap)
+            gsdp.gs_adam_step_deferred(model, 0, multi.union_ids, multi.union_count, gg, ga, capacity=cap)
+            gsdp.gs_step_advance(model.step_dev)
+
+        gstep()
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            gstep()
+        torch.cuda.synchronize()
+        reps = min(args.steps, ntab - (t_next + 1) - 1)
+        g0 = time.perf_counter()
+        for _ in range(reps):
+            graph.replay()
+        torch.cuda.synchronize()
+        graph_ms = (time.perf_counter() - g0) * 1e3 / reps
     k_ms = np.array([[e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2]), e[2].elapsed_time(e[3])]
                      for e in evs])
     cull_ms, gather_ms, adam_ms = k_ms.mean(0)
@@ -300,8 +343,8 @@ def main():
     R = rest_total / args.steps
     f = M / n
     # algorithmic bytes per launch (sg / sa: bytes per stored moment of G / A)
-    sg = 4 if geo_state == "f32" else 2
-    sa = 4 if args.state == "f32" else 2
+    msz = {"f32": 4, "bf16": 2, "fp8": 1}
+    sg, sa = msz[geo_state], msz[args.state]
     gcols = 0 if args.geo_mode else 10                  # G columns handled by the sparse kernels
     cull_bytes = 44.0 * n + 20.0 * sg * R + 4.0 * M
     gather_bytes = M * (4 + 4 + 8 * 10 + 2 * sg * gcols + 8 * 49 + 2 * sa * 49)
@@ -326,6 +369,7 @@ def main():
                    "state": args.state, "geo_state": geo_state, "app_layout": args.layout,
                    "max_defer": args.max_defer, "cull_mode": args.cull_mode, "geo_mode": args.geo_mode},
         "kernels_ms": {"cull": cull_ms, "gather": gather_ms, "adam": adam_ms},
+        "graph_ms_per_step": graph_ms,
         "kernels_gbs": {k: v[1] / (v[0] * 1e-3) / 1e9 for k, v in kernels.items()},
         "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None},

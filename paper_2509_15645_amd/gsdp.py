@@ -189,11 +189,34 @@ class Model:
         gdt, gcode, _ = sdt[geo_state]
         adt, acode, asz = sdt[app_state]
         self.geo_state, self.app_state = geo_state, app_state
+        _, _, gsz = sdt[geo_state]
         self.geo_w = geo.to(device).contiguous()
-        self.geo_m = torch.zeros((n, 10), dtype=gdt, device=device)
-        self.geo_v = torch.zeros((n, 10), dtype=gdt, device=device)
         self.app_layout = app_layout
-        if app_layout == "separate":
+        gld = (10, 10, 10)
+        if app_layout != "fused":
+            self.geo_m = torch.zeros((n, 10), dtype=gdt, device=device)
+            self.geo_v = torch.zeros((n, 10), dtype=gdt, device=device)
+        if app_layout == "fused":
+            # one byte row per Gaussian: A w | A m | A v | G m | G v, padded to 64 bytes,
+            # so a visible row's state is a single contiguous span
+            wbytes, mbytes, gbytes = 4 * adim, asz * adim, gsz * 10
+            o_am, o_av = wbytes, wbytes + mbytes
+            o_gm = wbytes + 2 * mbytes
+            o_gm = (o_gm + gsz - 1) // gsz * gsz
+            o_gv = o_gm + gbytes
+            row = (o_gv + gbytes + 63) // 64 * 64
+            assert row % 4 == 0 and row % asz == 0 and row % gsz == 0
+            self.app_state_bytes = torch.zeros((n, row), dtype=torch.uint8, device=device)
+            st = self.app_state_bytes
+            self.app_w = st[:, 0:wbytes].view(torch.float32)
+            self.app_m = st[:, o_am:o_am + mbytes].view(adt)
+            self.app_v = st[:, o_av:o_av + mbytes].view(adt)
+            self.geo_m = st[:, o_gm:o_gm + gbytes].view(gdt)
+            self.geo_v = st[:, o_gv:o_gv + gbytes].view(gdt)
+            self.app_w.copy_(app.to(device))
+            ld = (row // 4, row // asz, row // asz)
+            gld = (10, row // gsz, row // gsz)
+        elif app_layout == "separate":
             self.app_w = app.to(device).contiguous()
             self.app_m = torch.zeros((n, adim), dtype=adt, device=device)
             self.app_v = torch.zeros((n, adim), dtype=adt, device=device)
@@ -225,7 +248,7 @@ class Model:
         c = GsModel()
         c.n = n
         for grp, w, m, v, lds, lr, dim, code, ms, vs in (
-                (c.geo, self.geo_w, self.geo_m, self.geo_v, (10, 10, 10), self.lr_geo, 10, gcode,
+                (c.geo, self.geo_w, self.geo_m, self.geo_v, gld, self.lr_geo, 10, gcode,
                  self.geo_ms, self.geo_vs),
                 (c.app, self.app_w, self.app_m, self.app_v, ld, self.lr_app, adim, acode,
                  self.app_ms, self.app_vs)):

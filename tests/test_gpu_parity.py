@@ -208,6 +208,8 @@ def _compare_state(model, o3, tag):
     (0, "interleaved", "compact", 1, ("fp8", "fp8"), 0),
     (15, "separate", "compact", 1, ("f32", "fp8"), 0),
     (0, "separate", "dense", 0, ("bf16", "fp8"), 0),
+    (0, "fused", "compact", 1, ("f32", "f32"), 0),
+    (15, "fused", "compact", 1, ("bf16", "fp8"), 0),
 ])
 def test_small_workload_path_vs_oracle(g, max_defer, layout, grad_mode, cull_mode, states, geo_mode):
     """100k Gaussians, 10 orbit cameras, 20 steps: every step's visible ids and
