@@ -246,6 +246,21 @@ int gs_cull_multi_autotune(const gs_model *model, gs_multi *desc, int64_t step, 
 int gs_grad_sum_multi(const gs_multi *desc, int32_t adim, const float *g_cam, float *out_geo, float *out_app,
                       void *stream);
 
+/* Balance-aware image split (Sec. 4.4), a planning call (synchronises
+ * `stream`): if more than mem_limit * n Gaussians are visible in `cam`, find
+ * a split column x so that the crops [0, x) and [x, W) (same intrinsics, the
+ * right crop's principal point shifted by -x) see similar counts: start at
+ * the midpoint and move x toward the less populated side with a 5-step
+ * binary search, culling both sides each time.  *split_x = 0 means no split.
+ * counts (optional, 3 entries): visible in the whole image, in the left and
+ * in the right crop at the chosen x.  desc must describe one scene, two
+ * cameras and one set; its camera records are overwritten and its capacities
+ * are ignored (only counts are produced).  Train a split image as a batch of
+ * the two crops: gs_cull_multi gives the union and the per-crop lists,
+ * gs_grad_sum_multi sums the crops' gradients, one gs_adam_step_deferred. */
+int gs_plan_image_split(const gs_model *model, const gs_camera *cam, int64_t step, double mem_limit, gs_multi *desc,
+                        void *ws, size_t ws_bytes, void *stream, int32_t *split_x, uint32_t *counts);
+
 /* --------------------------------------------------------------- harness */
 
 /* Synthetic gradients for benchmarks and tests (not part of the method):

@@ -2008,6 +2008,85 @@ int gs_grad_sum_multi(const gs_multi *desc, int32_t adim, const float *g_cam, fl
     return launched("gs_grad_sum_multi");
 }
 
+int gs_plan_image_split(const gs_model *model, const gs_camera *cam, int64_t step, double mem_limit, gs_multi *desc,
+                        void *ws, size_t ws_bytes, void *stream, int32_t *split_x, uint32_t *counts)
+{
+    if (!model || !cam || !desc || !split_x || !(mem_limit > 0.0)) return GS_EINVAL;
+    if (desc->n_scenes != 1 || desc->cams_per_scene != 2 || desc->n_sets != 1 || !desc->cams) return GS_EINVAL;
+    if (step == 0) return GS_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    const uint32_t cap_u = desc->cap_union, cap_c = desc->cap_cam;
+    desc->cap_union = 0;  // counts only
+    desc->cap_cam = 0;
+    CamPack rec[2];
+    int rc = GS_OK;
+    auto count_split = [&](int x, uint32_t out[3]) -> int {
+        gs_camera h[2] = {*cam, *cam};
+        h[0].width = x;                       // left crop [0, x)
+        h[1].width = cam->width - x;          // right crop [x, W): principal point shifts
+        h[1].cx = cam->cx - (float)x;
+        memset(rec, 0, sizeof rec);
+        for (int i = 0; i < 2; ++i) pack_camera(model, &h[i], rec[i].cam, rec[i].band);
+        hipError_t e = hipMemcpyAsync(const_cast<void *>(desc->cams), rec, sizeof rec, hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) return hip_fail(e, "gs_plan_image_split: camera upload");
+        int r = gs_cull_multi(model, desc, step, ws, ws_bytes, stream);
+        if (r) return r;
+        uint32_t cc[2], uc = 0;
+        e = hipMemcpyAsync(cc, desc->cam_count, sizeof cc, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(&uc, desc->union_count, sizeof uc, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return hip_fail(e, "gs_plan_image_split: count readback");
+        out[0] = uc;
+        out[1] = cc[0];
+        out[2] = cc[1];
+        return GS_OK;
+    };
+    // active count of the whole image: both halves empty except the full frame
+    uint32_t full[3];
+    {
+        gs_camera h[2] = {*cam, *cam};
+        memset(rec, 0, sizeof rec);
+        for (int i = 0; i < 2; ++i) pack_camera(model, &h[i], rec[i].cam, rec[i].band);
+        hipError_t e = hipMemcpyAsync(const_cast<void *>(desc->cams), rec, sizeof rec, hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) rc = hip_fail(e, "gs_plan_image_split: camera upload");
+        if (!rc) rc = gs_cull_multi(model, desc, step, ws, ws_bytes, stream);
+        if (!rc) {
+            e = hipMemcpyAsync(&full[0], desc->union_count, sizeof(uint32_t), hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+            if (e != hipSuccess) rc = hip_fail(e, "gs_plan_image_split: count readback");
+        }
+    }
+    if (!rc) {
+        if (counts) counts[0] = full[0];
+        if ((double)full[0] <= mem_limit * (double)model->n || cam->width < 2) {
+            *split_x = 0;  // no split needed
+        } else {
+            // start at the midpoint and move the split toward the less populated
+            // side, halving the step, five times (Sec. 4.4)
+            int lo = 1, hi = cam->width - 1, x = cam->width / 2;
+            uint32_t c3[3] = {0, 0, 0};
+            for (int it = 0; it < 5 && !rc; ++it) {
+                rc = count_split(x, c3);
+                if (rc) break;
+                if (c3[1] > c3[2]) hi = x;
+                else lo = x;
+                x = (lo + hi) / 2;
+            }
+            if (!rc) rc = count_split(x, c3);
+            if (!rc) {
+                *split_x = x;
+                if (counts) {
+                    counts[1] = c3[1];
+                    counts[2] = c3[2];
+                }
+            }
+        }
+    }
+    desc->cap_union = cap_u;
+    desc->cap_cam = cap_c;
+    return rc;
+}
+
 int gs_step_advance(int32_t *step_dev, void *stream)
 {
     if (!step_dev) return GS_EINVAL;

@@ -25,7 +25,7 @@ SYMBOLS = ("gs_lut_bytes", "gs_lut_build", "gs_lut_build_host", "gs_workspace_by
            "gs_gather", "gs_scatter_grad", "gs_adam_step_deferred", "gs_adam_flush", "gs_synth_grad",
            "gs_device_cu_count", "gs_status_string", "gs_last_hip_error", "gs_step_advance",
            "gs_camera_pack_bytes", "gs_camera_pack", "gs_multi_workspace_bytes", "gs_cull_multi",
-           "gs_cull_multi_autotune", "gs_grad_sum_multi")
+           "gs_cull_multi_autotune", "gs_grad_sum_multi", "gs_plan_image_split")
 
 
 class GsCamera(C.Structure):
@@ -83,6 +83,7 @@ def _load():
         "gs_cull_multi": (C.c_int, [P(GsModel), P(GsMulti), i64, vp, sz, vp]),
         "gs_cull_multi_autotune": (C.c_int, [P(GsModel), P(GsMulti), i64, vp, sz, vp, vp, P(i32)]),
         "gs_grad_sum_multi": (C.c_int, [P(GsMulti), i32, vp, vp, vp, vp]),
+        "gs_plan_image_split": (C.c_int, [P(GsModel), P(GsCamera), i64, f64, P(GsMulti), vp, sz, vp, P(i32), vp]),
         "gs_status_string": (C.c_char_p, [C.c_int]),
         "gs_last_hip_error": (C.c_char_p, []),
     }
@@ -434,3 +435,14 @@ def gs_cull_multi_autotune(model: Model, multi: Multi, step: int, stream=None):
 def gs_grad_sum_multi(multi: Multi, adim: int, g_cam, out_geo, out_app, stream=None):
     _check(lib.gs_grad_sum_multi(C.byref(multi.c), int(adim), _ptr(g_cam), _ptr(out_geo), _ptr(out_app),
                                  _stream(stream)), "gs_grad_sum_multi")
+
+
+def gs_plan_image_split(model: Model, cam, step: int, mem_limit: float, stream=None):
+    """(split_x, (visible_full, visible_left, visible_right)); split_x = 0: no split."""
+    multi = Multi(model, [0, model.n], [[[cam, cam]]], cap_union=0, cap_cam=0)
+    x = C.c_int32()
+    counts = (C.c_uint32 * 3)()
+    _check(lib.gs_plan_image_split(C.byref(model.c), C.byref(camera_struct(cam)), int(step), float(mem_limit),
+                                   C.byref(multi.c), _ptr(multi.ws), multi.ws.numel() * 4, _stream(stream),
+                                   C.byref(x), counts), "gs_plan_image_split")
+    return x.value, (counts[0], counts[1], counts[2])

@@ -161,3 +161,44 @@ def test_batched_step_graph_replay_matches_eager(g):
         ue, ug = me.lists(), mg.lists()
         assert ue[0] == ug[0] and np.array_equal(ue[1], ug[1])
         say(f"[graph] replay {t}: union {ue[0]} identical to eager")
+
+
+def _crop(cam, x0, x1):
+    return gi.Camera(cam.R, cam.t, cam.fx, cam.fy, cam.cx - x0, cam.cy, x1 - x0, cam.height, cam.near, cam.far)
+
+
+def test_image_split_planner_matches_oracle_search(g):
+    """Balance-aware image split (Sec. 4.4): 5-step binary search from the
+    midpoint toward the less populated side, counts from both crops."""
+    sc = gi.make_scene(100_000, seed=21)
+    lg, la = gi.lr_columns()
+    model = g.Model(sc.geo, sc.app, lg, la, max_steps=8, cull_mode=1)
+    for cam in gi.orbit_cameras(3, seed=22):
+        x, counts = g.gs_plan_image_split(model, cam, 1, 0.3)
+        full = int(orc.cull(sc.geo, cam).sum())
+        assert counts[0] == full
+        if full <= 0.3 * sc.n:
+            assert x == 0
+            continue
+        lo, hi, xx = 1, cam.width - 1, cam.width // 2
+        for _ in range(5):
+            nl = int(orc.cull(sc.geo, _crop(cam, 0, xx)).sum())
+            nr = int(orc.cull(sc.geo, _crop(cam, xx, cam.width)).sum())
+            if nl > nr:
+                hi = xx
+            else:
+                lo = xx
+            xx = (lo + hi) // 2
+        nl = int(orc.cull(sc.geo, _crop(cam, 0, xx)).sum())
+        nr = int(orc.cull(sc.geo, _crop(cam, xx, cam.width)).sum())
+        say(f"[split] full {full} -> x={x} left {counts[1]} right {counts[2]}")
+        assert x == xx and counts[1] == nl and counts[2] == nr
+        assert abs(nl - nr) < 0.35 * (nl + nr)
+        # the split image trains as a batch of the two crops
+        multi = g.Multi(model, [0, model.n], [[[_crop(cam, 0, x), _crop(cam, x, cam.width)]]])
+        g.gs_cull_multi(model, multi, 1)
+        torch.cuda.synchronize()
+        ref = orc.cull_multi(sc.geo, [0, model.n], [[_crop(cam, 0, x), _crop(cam, x, cam.width)]])
+        _compare_lists(multi, ref, "split batch")
+    x, _ = g.gs_plan_image_split(model, gi.orbit_cameras(1, seed=22)[0], 1, 0.99)
+    assert x == 0
