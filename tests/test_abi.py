@@ -90,3 +90,45 @@ def test_host_tables_equal_oracle_tables_bitwise(gsdp, max_defer):
         assert np.array_equal(lut[offV:offV + dmax + 1].view(np.uint32), Vf.view(np.uint32))
         assert lut[offSS + t].view(np.uint32) == np.float32(ss).view(np.uint32)
         assert lut[offBC + t].view(np.uint32) == np.float32(bc).view(np.uint32)
+
+
+def test_batched_entry_points_check_arguments(gsdp):
+    L = gsdp.lib
+    b = C.c_size_t()
+    assert L.gs_camera_pack_bytes(C.byref(b)) == 0 and b.value == 128
+    m = gsdp.GsModel()
+    m.n = 5000
+    assert L.gs_multi_workspace_bytes(C.byref(m), C.byref(b)) == 0
+    assert b.value >= 256 + 8 * (5000 // 128)
+    assert L.gs_cull_multi(None, None, 1, None, 0, None) == gsdp.GS_EINVAL
+    assert L.gs_grad_sum_multi(None, 49, None, None, None, None) == gsdp.GS_EINVAL
+    d = gsdp.GsMulti()
+    d.cams_per_scene = 40                       # more than 32 camera slots
+    buf = np.zeros(16, np.float32)
+    assert L.gs_grad_sum_multi(C.byref(d), 49, buf.ctypes.data, buf.ctypes.data, buf.ctypes.data,
+                               None) == gsdp.GS_EINVAL
+    assert L.gs_step_advance(None, None) == gsdp.GS_EINVAL
+    assert L.gs_plan_image_split(None, None, 1, 0.3, None, None, 0, None, None, None) == gsdp.GS_EINVAL
+    cams = (gsdp.GsCamera * 2)()
+    out = np.zeros(256, np.uint8)
+    # fx = 0 is rejected before anything is written
+    assert L.gs_camera_pack(C.byref(m), cams, 2, out.ctypes.data) == gsdp.GS_EINVAL
+
+
+def test_camera_pack_layout(gsdp):
+    """Packed camera records hold the camera and rounded-up band constants."""
+    import gs_inputs as gi
+    m = gsdp.GsModel()
+    m.n = 10
+    m.beta1, m.beta2 = 0.9, 0.999
+    for k in range(10):
+        m.geo.lr[k] = 1.6e-4 if k < 3 else 5e-3
+    cam = gi.orbit_cameras(1, seed=3)[0]
+    rec = np.zeros(32, np.float32)
+    assert gsdp.lib.gs_camera_pack(C.byref(m), C.byref(gsdp.camera_struct(cam)), 1, rec.ctypes.data) == 0
+    assert np.array_equal(rec[:9], cam.R.ravel()) and np.array_equal(rec[9:12], cam.t)
+    assert rec[12] == cam.fx and rec[16] == cam.width and rec[17] == cam.height
+    rows = np.abs(cam.R.astype(np.float64)).sum(1)
+    assert np.all(rec[20:23] >= rows) and np.all(rec[20:23] <= rows * (1 + 1e-5))
+    rb = 1.03 * 0.1 / np.sqrt(0.001 * (1 - 0.81 / 0.999))
+    assert rec[24] >= rb * 1.6e-4 and rec[25] >= rb * 5e-3 and rec[26] >= rb * 5e-3
