@@ -122,6 +122,16 @@ int gs_lut_build(double beta1, double beta2, int32_t max_steps, int32_t max_defe
 int gs_lut_build_host(double beta1, double beta2, int32_t max_steps, int32_t max_defer,
                       void *lut_host, size_t bytes);
 
+/* Tables for a learning-rate schedule: at update t every column's rate is
+ * lr * lr_scale[t] (lr_scale: host array of max_steps + 2 finite values >= 0,
+ * index t).  The pseudocode's LUT term (lr b1)/(...) of the skipped step k
+ * then carries that step's rate, lr_scale[k] c(k), and the step size is
+ * lr_scale[t] / (1 - b1^t).  A constant 1 gives gs_lut_build's tables. */
+int gs_lut_build_schedule(double beta1, double beta2, int32_t max_steps, int32_t max_defer,
+                          const double *lr_scale, void *lut_dev, size_t bytes);
+int gs_lut_build_schedule_host(double beta1, double beta2, int32_t max_steps, int32_t max_defer,
+                               const double *lr_scale, void *lut_host, size_t bytes);
+
 /* ------------------------------------------------------------- workspace */
 
 /* Bytes of the scratch workspace that gs_cull and gs_adam_step_deferred

@@ -223,14 +223,17 @@ void orc_adam_dense_sparse_grad_f64(int64_t n, int dim, double *w, double *m, do
  *   mom_lut[i] = b1^(i+1),  var_lut[i] = b2^(i+1)          for i = 0..dmax
  * Entries exist for d = 0..dmax with dmax <= step-1: a row cannot have been
  * deferred for step-1 or more steps, and step-i = 0 would divide by zero. */
-void orc_lut_paper_f64(double b1, double b2, int64_t step, int dmax,
+/* sched (optional): learning-rate multiplier of each step; the listing's
+ * (lr*b1) term of the skipped step step-i then uses that step's rate. */
+void orc_lut_paper_f64(double b1, double b2, int64_t step, int dmax, const double *sched,
                        double *param_lut, double *mom_lut, double *var_lut)
 {
     double scale = b1 / sqrt(b2);
     param_lut[0] = 0.0;
     for (int i = 1; i <= dmax; ++i)
         param_lut[i] = scale * param_lut[i - 1]
-                       + b1 / (sqrt(b2 / (1.0 - pow(b2, (double)(step - i)))) * (1.0 - pow(b1, (double)(step - i))));
+                       + ((sched ? sched[step - i] : 1.0) * b1)
+                             / (sqrt(b2 / (1.0 - pow(b2, (double)(step - i)))) * (1.0 - pow(b1, (double)(step - i))));
     for (int i = 0; i <= dmax; ++i) {
         mom_lut[i] = pow(b1, (double)(i + 1));
         var_lut[i] = pow(b2, (double)(i + 1));
@@ -248,7 +251,7 @@ void orc_lut_paper_f64(double b1, double b2, int64_t step, int dmax,
  * Adam update is applied"). */
 void orc_deferred_rows_f64(int dim, double *w, double *m, double *v, int64_t n_rows,
                            const uint32_t *rows, const int64_t *d, const double *g,
-                           const double *lr, double b1, double b2, double eps, int64_t t,
+                           const double *lr, double b1, double b2, double eps, int64_t t, double lr_scale_t,
                            const double *param_lut, const double *mom_lut, const double *var_lut)
 {
     const double bias_correction = sqrt(1.0 - pow(b2, (double)t));
@@ -266,7 +269,7 @@ void orc_deferred_rows_f64(int dim, double *w, double *m, double *v, int64_t n_r
             v[e] = v_new;
             if (dj > 0) wk -= (w_scale * lr[k] * mk) / (sqrt(vk) + eps);
             double denom = sqrt(v_new) / bias_correction + eps;
-            double step_size = lr[k] / (1.0 - pow(b1, (double)t));
+            double step_size = (lr[k] * lr_scale_t) / (1.0 - pow(b1, (double)t));
             w[e] = wk - step_size * m_new / denom;
         }
     }
@@ -316,8 +319,8 @@ void orc_flush_rows_f64(int dim, double *w, double *m, double *v, int64_t n_rows
  *   W[0]  = 0,  W[d] = (b1/sqrt(b2)) W[d-1] + C[t-d]                   d >= 1
  *   Wf[d] = W[d], Mf[d] = P1[d+1], Vf[d] = P2[d+1],
  *   ss = 1/(1 - P1[t]),  bc = sqrt(1 - P2[t])                (all as FP32)     */
-void orc_lut_spec(double b1, double b2, int64_t t, int dmax, float *Wf, float *Mf, float *Vf,
-                  float *ss, float *bc)
+void orc_lut_spec(double b1, double b2, int64_t t, int dmax, const double *sched, float *Wf, float *Mf,
+                  float *Vf, float *ss, float *bc)
 {
     int64_t kmax = t > dmax + 1 ? t : dmax + 1;
     double *P1 = (double *)malloc(sizeof(double) * (size_t)(kmax + 1));
@@ -330,11 +333,12 @@ void orc_lut_spec(double b1, double b2, int64_t t, int dmax, float *Wf, float *M
     for (int d = 1; d <= dmax; ++d) {
         int64_t k = t - d;
         double C = b1 / (sqrt(b2 / (1.0 - P2[k])) * (1.0 - P1[k]));
+        if (sched) C = sched[k] * C;
         W = r * W + C;
         Wf[d] = (float)W;
     }
     for (int d = 0; d <= dmax; ++d) { Mf[d] = (float)P1[d + 1]; Vf[d] = (float)P2[d + 1]; }
-    *ss = (float)(1.0 / (1.0 - P1[t]));
+    *ss = sched ? (float)(sched[t] / (1.0 - P1[t])) : (float)(1.0 / (1.0 - P1[t]));
     *bc = (float)sqrt(1.0 - P2[t]);
     free(P1); free(P2);
 }

@@ -59,12 +59,12 @@ def lib():
             "orc_adam_dense_f64": (None, [i64, i32, vp, vp, vp, vp, vp, f64, f64, f64, i64]),
             "orc_adam_dense_sparse_grad_f64": (None, [i64, i32, vp, vp, vp, i64, vp, vp, vp,
                                                        f64, f64, f64, i64]),
-            "orc_lut_paper_f64": (None, [f64, f64, i64, i32, vp, vp, vp]),
+            "orc_lut_paper_f64": (None, [f64, f64, i64, i32, vp, vp, vp, vp]),
             "orc_deferred_rows_f64": (None, [i32, vp, vp, vp, i64, vp, vp, vp, vp, f64, f64, f64,
-                                             i64, vp, vp, vp]),
+                                             i64, f64, vp, vp, vp]),
             "orc_restore_rows_f64": (None, [i32, vp, vp, vp, i64, vp, vp, vp, f64, vp, vp]),
             "orc_flush_rows_f64": (None, [i32, vp, vp, vp, i64, vp, vp, vp, f64, f64, f64, vp]),
-            "orc_lut_spec": (None, [f64, f64, i64, i32, vp, vp, vp, vp, vp]),
+            "orc_lut_spec": (None, [f64, f64, i64, i32, vp, vp, vp, vp, vp, vp]),
             "orc_restore_bound": (f32, [f64, f64]),
             "orc_bf16_sr": (C.c_uint16, [f32, C.c_uint32]),
             "orc_e4m3_sr": (C.c_uint8, [f32, C.c_uint32]),
@@ -136,19 +136,26 @@ def compact(keep: np.ndarray) -> np.ndarray:
 # ---------------------------------------------------------------------------
 # LUTs
 # ---------------------------------------------------------------------------
-def lut_paper(b1: float, b2: float, step: int, dmax: int):
-    """param_lut, mom_lut, var_lut (FP64, unit lr) of the deferred-update figure."""
+def _sched(sched):
+    return None if sched is None else np.ascontiguousarray(sched, np.float64)
+
+
+def lut_paper(b1: float, b2: float, step: int, dmax: int, sched=None):
+    """param_lut, mom_lut, var_lut (FP64, unit lr) of the deferred-update figure;
+    sched: optional per-step learning-rate multiplier (index = step)."""
     p = np.zeros(dmax + 1); mo = np.zeros(dmax + 1); va = np.zeros(dmax + 1)
-    lib().orc_lut_paper_f64(b1, b2, step, dmax, _p(p), _p(mo), _p(va))
+    sc = _sched(sched)
+    lib().orc_lut_paper_f64(b1, b2, step, dmax, _p(sc), _p(p), _p(mo), _p(va))
     return p, mo, va
 
 
-def lut_spec(b1: float, b2: float, step: int, dmax: int):
+def lut_spec(b1: float, b2: float, step: int, dmax: int, sched=None):
     """FP32 tables (Wf, Mf, Vf, ss, bc) of the implementation spec for update `step`."""
     Wf = np.zeros(dmax + 1, np.float32); Mf = np.zeros(dmax + 1, np.float32)
     Vf = np.zeros(dmax + 1, np.float32)
     ss = C.c_float(); bc = C.c_float()
-    lib().orc_lut_spec(b1, b2, step, dmax, _p(Wf), _p(Mf), _p(Vf), C.addressof(ss), C.addressof(bc))
+    sc = _sched(sched)
+    lib().orc_lut_spec(b1, b2, step, dmax, _p(sc), _p(Wf), _p(Mf), _p(Vf), C.addressof(ss), C.addressof(bc))
     return Wf, Mf, Vf, np.float32(ss.value), np.float32(bc.value)
 
 
@@ -158,20 +165,23 @@ def lut_spec(b1: float, b2: float, step: int, dmax: int):
 class DenseAdamF64:
     """FP64 Adam on every row every step; rows without a gradient use g = 0."""
 
-    def __init__(self, geo, app, lr_geo, lr_app, b1=0.9, b2=0.999, eps=1e-15):
+    def __init__(self, geo, app, lr_geo, lr_app, b1=0.9, b2=0.999, eps=1e-15, sched=None):
         self.w = [np.array(geo, np.float64), np.array(app, np.float64)]
         self.m = [np.zeros_like(x) for x in self.w]
         self.v = [np.zeros_like(x) for x in self.w]
         self.lr = [np.asarray(lr_geo, np.float64), np.asarray(lr_app, np.float64)]
         self.b1, self.b2, self.eps = b1, b2, eps
+        self.sched = _sched(sched)
 
     def step(self, t: int, ids: np.ndarray, g_geo: np.ndarray, g_app: np.ndarray):
         ids = np.ascontiguousarray(ids, np.uint32)
+        s = 1.0 if self.sched is None else float(self.sched[t])
         for k, g in enumerate((g_geo, g_app)):
             g = np.ascontiguousarray(g, np.float32)
             w, m, v = self.w[k], self.m[k], self.v[k]
+            lr = np.ascontiguousarray(self.lr[k] * s)
             lib().orc_adam_dense_sparse_grad_f64(w.shape[0], w.shape[1], _p(w), _p(m), _p(v),
-                                                 ids.shape[0], _p(ids), _p(g), _p(self.lr[k]),
+                                                 ids.shape[0], _p(ids), _p(g), _p(lr),
                                                  self.b1, self.b2, self.eps, t)
 
 
@@ -213,20 +223,21 @@ class _Deferred:
 class DeferredF64(_Deferred):
     """Model O2: the paper's deferred algorithm with FP64 state."""
 
-    def __init__(self, geo, app, lr_geo, lr_app, b1=0.9, b2=0.999, eps=1e-15, max_defer=0):
+    def __init__(self, geo, app, lr_geo, lr_app, b1=0.9, b2=0.999, eps=1e-15, max_defer=0, sched=None):
         super().__init__(geo.shape[0], max_defer)
         self.w = [np.array(geo, np.float64), np.array(app, np.float64)]
         self.m = [np.zeros_like(x) for x in self.w]
         self.v = [np.zeros_like(x) for x in self.w]
         self.lr = [np.asarray(lr_geo, np.float64), np.asarray(lr_app, np.float64)]
         self.b1, self.b2, self.eps = b1, b2, eps
+        self.sched = _sched(sched)
 
     def current(self, t: int, rows=None):
         """Restored values of rows (default all) before update t: (geo, app)."""
         rows = np.arange(self.counter.shape[0]) if rows is None else np.asarray(rows)
         rows32 = np.ascontiguousarray(rows, np.uint32)
         d = np.ascontiguousarray(self.counter[rows], np.int64)
-        lut, _, _ = lut_paper(self.b1, self.b2, t, max(self.dmax(t), 0))
+        lut, _, _ = lut_paper(self.b1, self.b2, t, max(self.dmax(t), 0), self.sched)
         out = []
         for k in range(2):
             o = np.zeros((rows.shape[0], self.w[k].shape[1]))
@@ -240,14 +251,15 @@ class DeferredF64(_Deferred):
         valid, sat = self.update_set(valid)
         rows = np.ascontiguousarray(np.concatenate([valid, sat]), np.uint32)
         d = np.ascontiguousarray(self.counter[rows.astype(np.int64)], np.int64)
-        lut, mom, var = lut_paper(self.b1, self.b2, t, max(self.dmax(t), 0))
+        lut, mom, var = lut_paper(self.b1, self.b2, t, max(self.dmax(t), 0), self.sched)
+        s_t = 1.0 if self.sched is None else float(self.sched[t])
         for k, g in enumerate((g_geo, g_app)):
             dim = self.w[k].shape[1]
             gg = np.zeros((rows.shape[0], dim))
             gg[:valid.shape[0]] = np.asarray(g, np.float64)
             lib().orc_deferred_rows_f64(dim, _p(self.w[k]), _p(self.m[k]), _p(self.v[k]), rows.shape[0],
                                         _p(rows), _p(d), _p(gg), _p(self.lr[k]), self.b1, self.b2,
-                                        self.eps, t, _p(lut), _p(mom), _p(var))
+                                        self.eps, t, s_t, _p(lut), _p(mom), _p(var))
         self.bump(valid, sat)
         return valid, sat
 
@@ -256,7 +268,7 @@ class DeferredF64(_Deferred):
         if rows.shape[0] == 0:
             return
         delta = np.ascontiguousarray(self.counter[rows], np.int64)
-        lut, _, _ = lut_paper(self.b1, self.b2, t_done + 1, int(delta.max()))
+        lut, _, _ = lut_paper(self.b1, self.b2, t_done + 1, int(delta.max()), self.sched)
         rows32 = np.ascontiguousarray(rows, np.uint32)
         for k in range(2):
             lib().orc_flush_rows_f64(self.w[k].shape[1], _p(self.w[k]), _p(self.m[k]), _p(self.v[k]),
@@ -291,8 +303,9 @@ class DeferredF32(_Deferred):
     the rounding stream); default 0..n-1."""
 
     def __init__(self, geo, app, lr_geo, lr_app, b1=0.9, b2=0.999, eps=1e-15, max_defer=0,
-                 state="f32", sr_seed=0, keys=None, app_state=None, geo_dense=False):
+                 state="f32", sr_seed=0, keys=None, app_state=None, geo_dense=False, sched=None):
         super().__init__(geo.shape[0], max_defer)
+        self.sched = _sched(sched)
         # geo_dense: the geometric group takes a plain Adam step on every row
         # every step (the split of Sec. 4.2.2); only the appearance is deferred
         self.geo_dense = bool(geo_dense)
@@ -330,7 +343,7 @@ class DeferredF32(_Deferred):
         d = np.ascontiguousarray(self.counter[np.asarray(rows, np.int64)], np.int64)
         if k == 0 and self.geo_dense:
             d = np.zeros_like(d)
-        Wf, _, _, _, _ = lut_spec(self.b1, self.b2, t, max(self.dmax(t), 0))
+        Wf, _, _, _, _ = lut_spec(self.b1, self.b2, t, max(self.dmax(t), 0), self.sched)
         dim = self.w[k].shape[1]
         out = np.zeros((rows32.shape[0], dim), np.float32)
         if self.sid[k] == 2:
@@ -359,7 +372,7 @@ class DeferredF32(_Deferred):
         valid, sat = self.update_set(valid)
         rows = np.ascontiguousarray(np.concatenate([valid, sat]), np.uint32)
         d = np.ascontiguousarray(self.counter[rows.astype(np.int64)], np.int64)
-        Wf, Mf, Vf, ss, bc = lut_spec(self.b1, self.b2, t, max(self.dmax(t), 0))
+        Wf, Mf, Vf, ss, bc = lut_spec(self.b1, self.b2, t, max(self.dmax(t), 0), self.sched)
         for k, g in enumerate((g_geo, g_app)):
             dim = self.w[k].shape[1]
             if k == 0 and self.geo_dense:
@@ -391,7 +404,7 @@ class DeferredF32(_Deferred):
             return
         delta = np.ascontiguousarray(self.counter[rows], np.int64)
         # table of step t_done+1 at index delta <= t_done; Mf/Vf do not depend on t
-        Wn, Mf, Vf, _, _ = lut_spec(self.b1, self.b2, t_done + 1, int(delta.max()))
+        Wn, Mf, Vf, _, _ = lut_spec(self.b1, self.b2, t_done + 1, int(delta.max()), self.sched)
         rows32 = np.ascontiguousarray(rows, np.uint32)
         for k in range(2):
             if k == 0 and self.geo_dense:

@@ -1650,8 +1650,8 @@ int gs_lut_bytes(int32_t max_steps, int32_t max_defer, size_t *bytes)
     return GS_OK;
 }
 
-int gs_lut_build_host(double beta1, double beta2, int32_t max_steps, int32_t max_defer, void *lut_host,
-                      size_t bytes)
+int gs_lut_build_schedule_host(double beta1, double beta2, int32_t max_steps, int32_t max_defer, const double *lr_scale,
+                               void *lut_host, size_t bytes)
 {
     size_t need = 0;
     int rc = gs_lut_bytes(max_steps, max_defer, &need);
@@ -1659,13 +1659,23 @@ int gs_lut_build_host(double beta1, double beta2, int32_t max_steps, int32_t max
     if (!lut_host) return GS_EINVAL;
     if (!(beta1 > 0.0 && beta1 < 1.0 && beta2 > 0.0 && beta2 < 1.0)) return GS_EINVAL;
     if (bytes < need) return GS_ESPACE;
-    return gsdp::build_lut_host(beta1, beta2, max_steps, max_defer, static_cast<float *>(lut_host),
+    if (lr_scale)
+        for (int64_t t = 0; t <= (int64_t)max_steps + 1; ++t)
+            if (!(lr_scale[t] >= 0.0) || !std::isfinite(lr_scale[t])) return GS_EINVAL;
+    return gsdp::build_lut_host(beta1, beta2, max_steps, max_defer, lr_scale, static_cast<float *>(lut_host),
                                 (int64_t)(bytes / sizeof(float))) == 0
                ? GS_OK
                : GS_ESPACE;
 }
 
-int gs_lut_build(double beta1, double beta2, int32_t max_steps, int32_t max_defer, void *lut_dev, size_t bytes)
+int gs_lut_build_host(double beta1, double beta2, int32_t max_steps, int32_t max_defer, void *lut_host,
+                      size_t bytes)
+{
+    return gs_lut_build_schedule_host(beta1, beta2, max_steps, max_defer, nullptr, lut_host, bytes);
+}
+
+int gs_lut_build_schedule(double beta1, double beta2, int32_t max_steps, int32_t max_defer, const double *lr_scale,
+                          void *lut_dev, size_t bytes)
 {
     size_t need = 0;
     int rc = gs_lut_bytes(max_steps, max_defer, &need);
@@ -1673,10 +1683,15 @@ int gs_lut_build(double beta1, double beta2, int32_t max_steps, int32_t max_defe
     if (!lut_dev) return GS_EINVAL;
     if (bytes < need) return GS_ESPACE;
     std::vector<float> host(need / sizeof(float));
-    rc = gs_lut_build_host(beta1, beta2, max_steps, max_defer, host.data(), need);
+    rc = gs_lut_build_schedule_host(beta1, beta2, max_steps, max_defer, lr_scale, host.data(), need);
     if (rc) return rc;
     hipError_t e = hipMemcpy(lut_dev, host.data(), need, hipMemcpyHostToDevice);
     return e == hipSuccess ? GS_OK : hip_fail(e, "gs_lut_build: hipMemcpy");
+}
+
+int gs_lut_build(double beta1, double beta2, int32_t max_steps, int32_t max_defer, void *lut_dev, size_t bytes)
+{
+    return gs_lut_build_schedule(beta1, beta2, max_steps, max_defer, nullptr, lut_dev, bytes);
 }
 
 int gs_workspace_bytes(const gs_model *model, size_t *bytes)

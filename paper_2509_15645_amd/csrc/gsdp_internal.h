@@ -74,6 +74,6 @@ inline int64_t ws_bytes_for(int64_t n, int32_t K, int32_t geo_dense, int32_t fp8
     return (b + 255) / 256 * 256;
 }
 
-int build_lut_host(double b1, double b2, int32_t T, int32_t K, float *out, int64_t nfloats);
+int build_lut_host(double b1, double b2, int32_t T, int32_t K, const double *sched, float *out, int64_t nfloats);
 
 }  // namespace gsdp

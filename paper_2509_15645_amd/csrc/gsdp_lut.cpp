@@ -8,7 +8,9 @@
 // every step of a run are built once: powers come from repeated
 // multiplication (no pow), every operation is one IEEE binary64 operation, and
 // each entry is rounded once to FP32, so the values are fully determined by
-// (b1, b2, t, d).
+// (b1, b2, t, d).  An optional learning-rate schedule s[t] (a multiplier of
+// every column's rate at update t) enters as s[k] c(k) for the skipped step k
+// and as s[t] / (1 - b1^t) in the step size.
 #include <cmath>
 #include <vector>
 
@@ -16,7 +18,7 @@
 
 namespace gsdp {
 
-int build_lut_host(double b1, double b2, int32_t T, int32_t K, float *out, int64_t nfloats)
+int build_lut_host(double b1, double b2, int32_t T, int32_t K, const double *sched, float *out, int64_t nfloats)
 {
     const LutLayout L = lut_layout(T, K);
     if (nfloats < L.total) return -1;
@@ -29,7 +31,11 @@ int build_lut_host(double b1, double b2, int32_t T, int32_t K, float *out, int64
         P2[k] = P2[k - 1] * b2;
     }
     const double r = b1 / std::sqrt(b2);
-    for (int64_t k = 1; k <= T; ++k) Ck[k] = b1 / (std::sqrt(b2 / (1.0 - P2[k])) * (1.0 - P1[k]));
+    for (int64_t k = 1; k <= T; ++k) {
+        Ck[k] = b1 / (std::sqrt(b2 / (1.0 - P2[k])) * (1.0 - P1[k]));
+        // a learning-rate schedule scales the skipped step k by its own rate
+        if (sched) Ck[k] = sched[k] * Ck[k];
+    }
 
     for (int64_t i = 0; i < L.total; ++i) out[i] = 0.0f;
     for (int64_t t = 1; t <= T + 1; ++t) {
@@ -48,7 +54,7 @@ int build_lut_host(double b1, double b2, int32_t T, int32_t K, float *out, int64
         out[L.offV + d] = (float)P2[d + 1];
     }
     for (int64_t t = 1; t <= T + 1; ++t) {
-        out[L.offSS + t] = (float)(1.0 / (1.0 - P1[t]));
+        out[L.offSS + t] = sched ? (float)(sched[t] / (1.0 - P1[t])) : (float)(1.0 / (1.0 - P1[t]));
         out[L.offBC + t] = (float)std::sqrt(1.0 - P2[t]);
     }
     return 0;

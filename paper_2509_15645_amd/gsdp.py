@@ -21,7 +21,8 @@ GS_OK, GS_EINVAL, GS_EHIP, GS_EUNSUPPORTED, GS_ESPACE = 0, -1, -2, -3, -4
 GS_F32, GS_BF16, GS_FP8E4M3 = 0, 1, 2
 
 # exported C symbols (kept in sync with include/gsdp.h)
-SYMBOLS = ("gs_lut_bytes", "gs_lut_build", "gs_lut_build_host", "gs_workspace_bytes", "gs_cull",
+SYMBOLS = ("gs_lut_bytes", "gs_lut_build", "gs_lut_build_host", "gs_lut_build_schedule",
+           "gs_lut_build_schedule_host", "gs_workspace_bytes", "gs_cull",
            "gs_gather", "gs_scatter_grad", "gs_adam_step_deferred", "gs_adam_flush", "gs_synth_grad",
            "gs_device_cu_count", "gs_status_string", "gs_last_hip_error", "gs_step_advance",
            "gs_camera_pack_bytes", "gs_camera_pack", "gs_multi_workspace_bytes", "gs_cull_multi",
@@ -68,6 +69,8 @@ def _load():
         "gs_lut_bytes": (C.c_int, [i32, i32, P(sz)]),
         "gs_lut_build": (C.c_int, [f64, f64, i32, i32, vp, sz]),
         "gs_lut_build_host": (C.c_int, [f64, f64, i32, i32, vp, sz]),
+        "gs_lut_build_schedule": (C.c_int, [f64, f64, i32, i32, vp, vp, sz]),
+        "gs_lut_build_schedule_host": (C.c_int, [f64, f64, i32, i32, vp, vp, sz]),
         "gs_workspace_bytes": (C.c_int, [P(GsModel), P(sz)]),
         "gs_cull": (C.c_int, [P(GsModel), P(GsCamera), i64, vp, vp, u32, vp, sz, vp]),
         "gs_gather": (C.c_int, [P(GsModel), i64, vp, vp, u32, vp, vp, vp]),
@@ -148,12 +151,21 @@ def gs_lut_build(beta1, beta2, max_steps, max_defer, lut: torch.Tensor):
            "gs_lut_build")
 
 
-def gs_lut_build_host(beta1, beta2, max_steps, max_defer) -> np.ndarray:
+def gs_lut_build_host(beta1, beta2, max_steps, max_defer, lr_scale=None) -> np.ndarray:
     nbytes = gs_lut_bytes(max_steps, max_defer)
     out = np.zeros(nbytes // 4, np.float32)
-    _check(lib.gs_lut_build_host(beta1, beta2, max_steps, max_defer, out.ctypes.data, nbytes),
+    sc = None if lr_scale is None else np.ascontiguousarray(lr_scale, np.float64)
+    _check(lib.gs_lut_build_schedule_host(beta1, beta2, max_steps, max_defer,
+                                          None if sc is None else sc.ctypes.data, out.ctypes.data, nbytes),
            "gs_lut_build_host")
     return out
+
+
+def gs_lut_build_schedule(beta1, beta2, max_steps, max_defer, lr_scale, lut: torch.Tensor):
+    sc = np.ascontiguousarray(lr_scale, np.float64)
+    assert sc.shape[0] >= max_steps + 2
+    _check(lib.gs_lut_build_schedule(beta1, beta2, max_steps, max_defer, sc.ctypes.data, _ptr(lut),
+                                     lut.numel() * lut.element_size()), "gs_lut_build_schedule")
 
 
 def gs_workspace_bytes(model) -> int:
@@ -178,7 +190,7 @@ class Model:
 
     def __init__(self, geo, app, lr_geo, lr_app, *, beta1=0.9, beta2=0.999, eps=1e-15, max_defer=0,
                  max_steps=1000, cull_mode=0, app_layout="separate", geo_state="f32", app_state="f32",
-                 sr_seed=0, geo_mode=0, device=None):
+                 sr_seed=0, geo_mode=0, lr_scale=None, device=None):
         device = device or torch.device("cuda")
         geo = torch.as_tensor(geo, dtype=torch.float32)
         app = torch.as_tensor(app, dtype=torch.float32)
@@ -242,7 +254,10 @@ class Model:
         self.max_steps, self.max_defer = int(max_steps), int(max_defer)
         self.lut = torch.empty(gs_lut_bytes(self.max_steps, self.max_defer) // 4, dtype=torch.float32,
                                device=device)
-        gs_lut_build(beta1, beta2, self.max_steps, self.max_defer, self.lut)
+        if lr_scale is None:
+            gs_lut_build(beta1, beta2, self.max_steps, self.max_defer, self.lut)
+        else:
+            gs_lut_build_schedule(beta1, beta2, self.max_steps, self.max_defer, lr_scale, self.lut)
         self.lr_geo = np.asarray(lr_geo, np.float32)
         self.lr_app = np.asarray(lr_app, np.float32)
 

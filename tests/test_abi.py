@@ -132,3 +132,22 @@ def test_camera_pack_layout(gsdp):
     assert np.all(rec[20:23] >= rows) and np.all(rec[20:23] <= rows * (1 + 1e-5))
     rb = 1.03 * 0.1 / np.sqrt(0.001 * (1 - 0.81 / 0.999))
     assert rec[24] >= rb * 1.6e-4 and rec[25] >= rb * 5e-3 and rec[26] >= rb * 5e-3
+
+
+@pytest.mark.parametrize("max_defer", [0, 15])
+def test_host_schedule_tables_equal_oracle_tables_bitwise(gsdp, max_defer):
+    T = 120
+    rng = np.random.default_rng(5)
+    sc = 0.01 ** (np.arange(T + 2) / (T + 1)) * rng.uniform(0.5, 2.0, T + 2)
+    lut = gsdp.gs_lut_build_host(0.9, 0.999, T, max_defer, lr_scale=sc)
+    K = max_defer
+    rows = T + 1
+    nW = rows * (K + 1) if K else rows * (rows + 1) // 2
+    nMV = (K if K else T) + 1
+    offSS = nW + 2 * nMV
+    for t in [1, 2, 17, 60, T, T + 1]:
+        row = (t - 1) * (K + 1) if K else t * (t - 1) // 2
+        dmax = min(t - 1, K) if K else t - 1
+        Wf, _, _, ss, _ = orc.lut_spec(0.9, 0.999, t, dmax, sc)
+        assert np.array_equal(lut[row:row + dmax + 1].view(np.uint32), Wf.view(np.uint32)), t
+        assert lut[offSS + t].view(np.uint32) == np.float32(ss).view(np.uint32)

@@ -194,37 +194,44 @@ def _compare_state(model, o3, tag):
                 assert np.array_equal(bits(st[f"{name}_{part}"]), bits(ref)), f"{tag}: {name}_{part}"
 
 
-@pytest.mark.parametrize("max_defer,layout,grad_mode,cull_mode,states,geo_mode", [
-    (0, "separate", "compact", 0, ("f32", "f32"), 0),
-    (15, "separate", "compact", 1, ("f32", "f32"), 0),
-    (0, "interleaved", "dense", 1, ("f32", "f32"), 0),
-    (15, "interleaved", "dense", 0, ("f32", "f32"), 0),
-    (0, "interleaved", "compact", 1, ("f32", "f32"), 0),
-    (0, "interleaved", "compact", 1, ("bf16", "bf16"), 0),
-    (15, "separate", "dense", 1, ("f32", "bf16"), 0),
-    (0, "separate", "compact", 0, ("bf16", "f32"), 0),
-    (0, "interleaved", "compact", 1, ("f32", "f32"), 1),
-    (15, "separate", "dense", 0, ("bf16", "bf16"), 1),
-    (0, "interleaved", "compact", 1, ("fp8", "fp8"), 0),
-    (15, "separate", "compact", 1, ("f32", "fp8"), 0),
-    (0, "separate", "dense", 0, ("bf16", "fp8"), 0),
-    (0, "fused", "compact", 1, ("f32", "f32"), 0),
-    (15, "fused", "compact", 1, ("bf16", "fp8"), 0),
+@pytest.mark.parametrize("max_defer,layout,grad_mode,cull_mode,states,geo_mode,sched", [
+    (0, "separate", "compact", 0, ("f32", "f32"), 0, False),
+    (15, "separate", "compact", 1, ("f32", "f32"), 0, False),
+    (0, "interleaved", "dense", 1, ("f32", "f32"), 0, False),
+    (15, "interleaved", "dense", 0, ("f32", "f32"), 0, False),
+    (0, "interleaved", "compact", 1, ("f32", "f32"), 0, False),
+    (0, "interleaved", "compact", 1, ("bf16", "bf16"), 0, False),
+    (15, "separate", "dense", 1, ("f32", "bf16"), 0, False),
+    (0, "separate", "compact", 0, ("bf16", "f32"), 0, False),
+    (0, "interleaved", "compact", 1, ("f32", "f32"), 1, False),
+    (15, "separate", "dense", 0, ("bf16", "bf16"), 1, False),
+    (0, "interleaved", "compact", 1, ("fp8", "fp8"), 0, False),
+    (15, "separate", "compact", 1, ("f32", "fp8"), 0, False),
+    (0, "separate", "dense", 0, ("bf16", "fp8"), 0, False),
+    (0, "fused", "compact", 1, ("f32", "f32"), 0, False),
+    (15, "fused", "compact", 1, ("bf16", "fp8"), 0, False),
+    (15, "interleaved", "compact", 1, ("f32", "f32"), 0, True),
+    (0, "separate", "dense", 0, ("f32", "f32"), 1, True),
 ])
-def test_small_workload_path_vs_oracle(g, max_defer, layout, grad_mode, cull_mode, states, geo_mode):
+def test_small_workload_path_vs_oracle(g, max_defer, layout, grad_mode, cull_mode, states, geo_mode, sched):
     """100k Gaussians, 10 orbit cameras, 20 steps: every step's visible ids and
     gathered rows bit-exact vs O3; state bit-exact after steps and after the
-    flush; flushed parameters within 1e-6 of dense FP64 Adam."""
+    flush; flushed parameters within 1e-6 of dense FP64 Adam.  `sched` runs a
+    per-step learning-rate multiplier (decay with noise)."""
     w = gi.workload("small")
     sc = gi.make_scene(w.n, seed=0, box=w.scene_box)
     lg, la = gi.lr_columns()
+    lr_scale = None
+    if sched:
+        rng = np.random.default_rng(9)
+        lr_scale = 0.01 ** (np.arange(34) / 33.0) * rng.uniform(0.5, 2.0, 34)
     model = g.Model(sc.geo, sc.app, lg, la, max_steps=32, max_defer=max_defer, app_layout=layout,
                     cull_mode=cull_mode, geo_state=states[0], app_state=states[1], sr_seed=77,
-                    geo_mode=geo_mode)
+                    geo_mode=geo_mode, lr_scale=lr_scale)
     o3 = orc.DeferredF32(sc.geo, sc.app, lg, la, max_defer=max_defer, state=states[0], app_state=states[1],
-                         sr_seed=77, geo_dense=bool(geo_mode))
+                         sr_seed=77, geo_dense=bool(geo_mode), sched=lr_scale)
     quant = states != ("f32", "f32")
-    dense = orc.DenseAdamF64(sc.geo, sc.app, lg, la)
+    dense = orc.DenseAdamF64(sc.geo, sc.app, lg, la, sched=lr_scale)
     n = w.n
     out_g = torch.zeros((n, 10), dtype=torch.float32, device="cuda")
     out_a = torch.zeros((n, 49), dtype=torch.float32, device="cuda")

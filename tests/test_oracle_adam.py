@@ -323,3 +323,64 @@ def test_fp8_state_tracks_dense_and_keeps_codes_in_range():
     for k, lr in ((0, lg), (1, la)):
         err = np.abs(o8.w[k] - dense.w[k]) / (lr.astype(np.float64) * steps)
         assert err.max() < 0.15 and err.mean() < 2e-2, (err.max(), err.mean())
+
+
+def _schedule(steps, seed):
+    """A learning-rate multiplier per step: exponential decay with noise, the
+    shape of the position-rate schedule of 3DGS training, kept adversarial."""
+    rng = np.random.default_rng(seed)
+    t = np.arange(steps + 2, dtype=np.float64)
+    return 0.01 ** (t / (steps + 1)) * rng.uniform(0.5, 2.0, steps + 2)
+
+
+@pytest.mark.parametrize("max_defer", [0, 15])
+def test_deferred_f64_with_schedule_equals_dense(max_defer):
+    """With a per-step rate the skipped step k contributes s[k] c(k) and the
+    method stays exact at eps = 0 (each term of Eq. 3 carries its own rate)."""
+    n, steps = 400, 60
+    s, lg, la = _scene(n, 13)
+    sc = _schedule(steps, 14)
+    dense = orc.DenseAdamF64(s.geo, s.app, lg, la, eps=0.0, sched=sc)
+    o2 = orc.DeferredF64(s.geo, s.app, lg, la, eps=0.0, max_defer=max_defer, sched=sc)
+    plain = orc.DenseAdamF64(s.geo, s.app, lg, la, eps=0.0)
+    for t, ids in enumerate(_vis_sequence(n, steps, 0.05, 15), start=1):
+        g = _gauss_grads(t, ids, 16)
+        dense.step(t, ids, *g)
+        o2.step(t, ids, *g)
+        plain.step(t, ids, *g)
+    o2.flush(steps)
+    for k in range(2):
+        assert np.max(rel_err(o2.w[k], dense.w[k], 1e-3)) < 1e-12
+    # the schedule really changes the trajectory (a dropped s[k] would fail above)
+    assert np.max(rel_err(plain.w[0], dense.w[0], 1e-3)) > 1e-5
+
+
+def test_spec_lut_with_schedule_within_one_rounding_of_paper_lut():
+    sc = _schedule(200, 3)
+    for t in (2, 50, 201):
+        lut, _, _ = orc.lut_paper(B1, B2, t, t - 1, sc)
+        Wf, _, _, ss, _ = orc.lut_spec(B1, B2, t, t - 1, sc)
+        ulp = np.spacing(np.abs(lut).astype(np.float32)).astype(np.float64)
+        assert np.all(np.abs(Wf.astype(np.float64) - lut) <= ulp)
+        assert abs(float(ss) - sc[t] / (1 - B1 ** t)) <= np.spacing(np.float32(ss))
+    # a constant schedule of 1 gives the unscheduled tables bit for bit
+    one = np.ones(202)
+    a = orc.lut_spec(B1, B2, 100, 99, one)
+    b = orc.lut_spec(B1, B2, 100, 99)
+    assert all(np.array_equal(np.asarray(x).view(np.uint32), np.asarray(y).view(np.uint32))
+               for x, y in zip(a, b))
+
+
+def test_f32_model_with_schedule_within_fp32_rounding_of_dense():
+    n, steps = 2000, 20
+    s, lg, la = _scene(n, 17)
+    sc = _schedule(steps, 18)
+    o3 = orc.DeferredF32(s.geo, s.app, lg, la, max_defer=15, sched=sc)
+    dense = orc.DenseAdamF64(s.geo, s.app, lg, la, sched=sc)
+    for t, ids in enumerate(_vis_sequence(n, steps, 0.3, 19, first_all=False), start=1):
+        g = gi.step_grads(0, t, ids)
+        o3.step(t, ids, *g)
+        dense.step(t, ids, *g)
+    o3.flush(steps)
+    for k, tau in ((0, TAU_GEO), (1, TAU_APP)):
+        assert np.max(rel_err(o3.w[k], dense.w[k], tau)) < 1e-6
