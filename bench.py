@@ -51,22 +51,30 @@ def parse():
     p.add_argument("--geo-mode", type=int, default=0, help="1 = dense geometric Adam every step")
     p.add_argument("--tilt", default="20,45", help="oblique tilt range in degrees")
     p.add_argument("--pool", type=int, default=4)
+    p.add_argument("--device-scene", type=int, default=None,
+                   help="1 = draw the scene on the device (default for more than 8M Gaussians)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample", type=int, default=1 << 20)
     p.add_argument("--cpu-steps", type=int, default=6)
     return p.parse_args()
 
 
-def cpu_baseline(w, sc, sample, steps, lg, la):
+def cpu_baseline(w, geo_all, app_all, sample, steps, lg, la):
     """The oracle as it stands, on a seeded row sample of the same workload:
     FP32 cull of the sample's geometry + ids + synthetic grads + dense FP64
-    Adam on every sampled row (Eq. 1), per step.  Gaussians/s = sample / t."""
+    Adam on every sampled row (Eq. 1), per step.  Gaussians/s = sample / t.
+    geo_all / app_all: host arrays or device tensors of the initial scene."""
     from oracle import oracle as orc
     import gs_inputs as gi
     rng = np.random.default_rng(123)
     rows = np.sort(rng.choice(w.n, min(sample, w.n), replace=False))
-    geo = np.ascontiguousarray(sc.geo[rows])
-    app = np.ascontiguousarray(sc.app[rows])
+
+    def take(x):
+        if isinstance(x, np.ndarray):
+            return np.ascontiguousarray(x[rows])
+        import torch
+        return x.index_select(0, torch.from_numpy(rows).to(x.device)).cpu().numpy()
+    geo, app = take(geo_all), take(app_all)
     dense = orc.DenseAdamF64(geo, app, lg, la)
     times = []
     for t in range(1, steps + 1):
@@ -247,16 +255,24 @@ def main():
     tilt = tuple(float(x) for x in args.tilt.split(","))
     w = gi.workload(args.workload, n=args.n, tilt_deg=tilt)
     t_setup = time.perf_counter()
-    sc = gi.make_scene(w.n, seed=0, box=w.scene_box)
+    dev = torch.device("cuda")
+    on_dev = args.device_scene if args.device_scene is not None else int(w.n > 8_000_000)
+    if on_dev:
+        geo0, app0 = device_scene(w.n, w.scene_box, 0, dev)
+    else:
+        sc = gi.make_scene(w.n, seed=0, box=w.scene_box)
+        geo0, app0 = sc.geo, sc.app
     lg, la = gi.lr_columns()
     total_steps = args.warmup + args.steps
     geo_state = args.geo_state or args.state
-    model = gsdp.Model(sc.geo, sc.app, lg, la, max_steps=2 * total_steps + 8, max_defer=args.max_defer,
+    model = gsdp.Model(geo0, app0, lg, la, max_steps=2 * total_steps + 8, max_defer=args.max_defer,
                        cull_mode=args.cull_mode, app_layout=args.layout, geo_state=geo_state,
                        app_state=args.state, geo_mode=args.geo_mode, sr_seed=9)
+    if on_dev:
+        geo0 = model.geo_w.clone()                  # the oracle sample reads the initial scene
+        app0 = app0 if app0.data_ptr() != model.app_w.data_ptr() else model.app_w.clone()
     n = w.n
     cap = max(1, n // 4)
-    dev = torch.device("cuda")
     ids = torch.zeros(cap, dtype=torch.int32, device=dev)
     count = torch.zeros(1, dtype=torch.int32, device=dev)
     out_g = torch.zeros((cap, 10), dtype=torch.float32, device=dev)
@@ -362,8 +378,8 @@ def main():
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32" if args.state == "f32" else "f32 math, bf16 moments", "data": "synthetic",
-        "config": {"workload": w.name, "n_gaussians": n, "cameras": len(w.cameras),
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": w.name, "n_gaussians": n, "scene_drawn_on": "device" if on_dev else "host", "cameras": len(w.cameras),
                    "image": f"{w.cameras[0].width}x{w.cameras[0].height}", "oblique_tilt_deg": list(tilt),
                    "visible_fraction": f, "visible_per_step": M, "restored_per_step": R,
                    "state": args.state, "geo_state": geo_state, "app_layout": args.layout,
@@ -376,7 +392,7 @@ def main():
         "setup_s": setup_s,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, sc, args.cpu_sample, args.cpu_steps, lg, la)
+        out["cpu_baseline"] = cpu_baseline(w, geo0, app0, args.cpu_sample, args.cpu_steps, lg, la)
     print(json.dumps(out), flush=True)
 
 

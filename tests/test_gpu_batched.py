@@ -157,7 +157,8 @@ def test_batched_step_graph_replay_matches_eager(g):
         assert int(graphed.step_dev.item()) == t + 1
         a, b = eager.state(), graphed.state()
         for key in a:
-            assert np.array_equal(a[key], b[key]), (t, key)
+            # compare bit patterns: padding rows hold NaN geometry
+            assert a[key].tobytes() == b[key].tobytes(), (t, key)
         ue, ug = me.lists(), mg.lists()
         assert ue[0] == ug[0] and np.array_equal(ue[1], ug[1])
         say(f"[graph] replay {t}: union {ue[0]} identical to eager")

@@ -254,7 +254,7 @@ def test_small_workload_path_vs_oracle(g, max_defer, layout, grad_mode, cull_mod
         if t == 3:
             st = model.state()       # gather is read-only on the stored state
             for key in st:
-                assert np.array_equal(st[key], state0[key]), key
+                assert st[key].tobytes() == state0[key].tobytes(), key
         gg, ga = gi.step_grads(0, t, valid)
         dgg, dga = torch.from_numpy(gg).cuda(), torch.from_numpy(ga).cuda()
         if grad_mode == "compact":
@@ -285,12 +285,19 @@ def test_small_workload_path_vs_oracle(g, max_defer, layout, grad_mode, cull_mod
         assert e_geo.max() <= 1e-6 and e_app.max() <= 1e-6
     else:
         # quantised moments, relative to the largest possible movement lr * steps:
-        # BF16 max 2e-2; FP8 max 0.15 and mean 2e-2
+        # BF16 max 2e-2; FP8 max 0.3 and mean 2e-2.  Derivation: one stochastic
+        # rounding moves a stored value by less than one ulp, 2^-7 (BF16) or 2^-3
+        # (E4M3 normals) relative, so one step's m/sqrt(v) is off by at most
+        # (1 + 2^-7)/(1 - 2^-8) - 1 = 1.2% (BF16, v stored) or
+        # (1 + 2^-3)/(1 - 2^-3) - 1 = 28.6% (E4M3, sqrt(v) stored); with
+        # |m_hat/sqrt(v_hat)| <= 1 per step (moments of i.i.d. gradients; 7.27 is
+        # the hard limit), T steps move w by at most that
+        # fraction of lr T.  The mean is far below the max (unbiased rounding).
         for k, (got, lr) in enumerate(((st["geo_w"], lg), (st["app_w"], la))):
             err = np.abs(got - dense.w[k]) / (lr.astype(np.float64) * w.steps)
             say(f"[path {states}] group {k}: |w - w64| / (lr T) max {err.max():.3e} mean {err.mean():.3e}")
             if states[k] == "fp8":
-                assert err.max() <= 0.15 and err.mean() <= 2e-2
+                assert err.max() <= 0.3 and err.mean() <= 2e-2
             elif states[k] == "bf16":
                 assert err.max() <= 2e-2
     assert model.ws_header()["error"] == 0

@@ -322,7 +322,7 @@ def test_fp8_state_tracks_dense_and_keeps_codes_in_range():
     o8.flush(steps)
     for k, lr in ((0, lg), (1, la)):
         err = np.abs(o8.w[k] - dense.w[k]) / (lr.astype(np.float64) * steps)
-        assert err.max() < 0.15 and err.mean() < 2e-2, (err.max(), err.mean())
+        assert err.max() < 0.3 and err.mean() < 2e-2, (err.max(), err.mean())
 
 
 def _schedule(steps, seed):
