@@ -149,7 +149,7 @@ def run_batched(args):
     model = gsdp.Model(geo, app, lg, la, max_steps=total_steps + 4, cull_mode=args.cull_mode,
                        app_layout=args.layout, geo_state=args.geo_state or "f32", app_state="bf16", sr_seed=9)
     del geo, app
-    cap_cam = max(1, int(N * 0.035))
+    cap_cam = max(1, int(N * 0.08))      # one camera slot over all scenes sees up to ~5% of the rows
     multi = gsdp.Multi(model, row0, sets, cap_union=N, cap_cam=cap_cam)
     D = 59
     g_cam = torch.empty((C, cap_cam, D), dtype=torch.float32, device=dev)

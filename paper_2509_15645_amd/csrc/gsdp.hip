@@ -557,25 +557,28 @@ __global__ __launch_bounds__(kCullBlock) void k_cull(CullArgs a)
         }
         __syncthreads();
 
-        // decoupled look-back by wave 0
+        // decoupled look-back by wave 0.  A tile's whole state (flag, visible and
+        // saturated counts) is one 64-bit word, so relaxed agent-scope atomics
+        // suffice: no other memory is published through it, and acquire/release
+        // would cost a writeback or invalidate of the whole L2 per access.
         if (wave == 0) {
             const u64 agg = sAgg;
             u64 excl = 0;
             if (tile == 0) {
-                if (lane == 0) __hip_atomic_store(&st[0], kFlagInc | agg, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                if (lane == 0) __hip_atomic_store(&st[0], kFlagInc | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             } else {
                 if (lane == 0)
-                    __hip_atomic_store(&st[tile], kFlagAgg | agg, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_store(&st[tile], kFlagAgg | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 int64_t base = (int64_t)tile - 1;
                 for (;;) {
                     const int64_t idx = base - lane;
                     u64 s = kFlagInc;
                     if (idx >= 0) {
                         u32 spins = 0;
-                        s = __hip_atomic_load(&st[idx], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+                        s = __hip_atomic_load(&st[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                         while ((s >> 62) == 0 && spins < kSpinLimit) {
                             __builtin_amdgcn_s_sleep(1);
-                            s = __hip_atomic_load(&st[idx], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+                            s = __hip_atomic_load(&st[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                             ++spins;
                         }
                         if ((s >> 62) == 0) {
@@ -594,7 +597,7 @@ __global__ __launch_bounds__(kCullBlock) void k_cull(CullArgs a)
                     base -= 64;
                 }
                 if (lane == 0)
-                    __hip_atomic_store(&st[tile], kFlagInc | (excl + agg), __ATOMIC_RELEASE,
+                    __hip_atomic_store(&st[tile], kFlagInc | (excl + agg), __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
             }
             if (lane == 0) {
@@ -625,21 +628,21 @@ __global__ __launch_bounds__(kCullBlock) void k_cull(CullArgs a)
 
     __syncthreads();
     if (tid == 0) {
-        if (sRestored) atomicAdd(&a.hdr->restored, sRestored);
-        __threadfence();
-        const u32 prev = atomicAdd(&a.hdr->done, 1u);
-        if (prev == gridDim.x - 1) {
-            __threadfence();
+        // one atomic carries "block done" and its restored rows; the block that
+        // sees every other block done holds the full count and resets the header
+        // (all other blocks have already taken their last ticket)
+        const u64 prev = __hip_atomic_fetch_add(&a.hdr->done_rest, (1ull << 40) | (u64)sRestored,
+                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((prev >> 40) == gridDim.x - 1) {
             if (a.tiles == 0) {
                 *a.count = 0;
                 a.hdr->sat_total = 0;
             }
-            const u32 rest = __hip_atomic_load(&a.hdr->restored, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const u32 rest = (u32)(prev & ((1ull << 40) - 1)) + sRestored;
             a.hdr->restored_last = rest;
             a.hdr->restored_accum += rest;
-            a.hdr->restored = 0;
+            a.hdr->done_rest = 0;
             a.hdr->ticket = 0;
-            a.hdr->done = 0;
             a.hdr->parity = parity ^ 1u;
         }
     }
@@ -1249,11 +1252,12 @@ struct MultiArgs {
     u32 cap_union, cap_cam;
     u32 *scene_start;                // [S][1+C]
     gsdp::WsHeader *hdr;
-    u32 *flags;                      // [2][stride]
-    u32 *vals;                       // [2][stride][2][kNCnt]: aggregate, inclusive
+    u64 *st;                         // [2][stride][kNCnt] flag (2 bits) | count, one word per counter
     int64_t tiles;                   // tiles of this launch
     int64_t stride;                  // tiles of the smallest tile size (buffer halves)
 };
+
+constexpr int kLookChunk = 8;        // counters whose predecessor words are loaded together
 
 template <int BLOCK, int IPT>
 __global__ __launch_bounds__(BLOCK) void k_cull_multi(MultiArgs a)
@@ -1275,9 +1279,8 @@ __global__ __launch_bounds__(BLOCK) void k_cull_multi(MultiArgs a)
     if (tid == 0) sParity = __hip_atomic_load(&a.hdr->parity, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 1u;
     __syncthreads();
     const u32 parity = sParity;
-    u32 *flags = a.flags + (size_t)parity * a.stride;
-    u32 *flags_other = a.flags + (size_t)(parity ^ 1u) * a.stride;
-    u32 *vals = a.vals + (size_t)parity * a.stride * 2 * kNCnt;
+    u64 *st = a.st + (size_t)parity * a.stride * kNCnt;
+    u64 *st_other = a.st + (size_t)(parity ^ 1u) * a.stride * kNCnt;
     const int set = (t - 1) % a.n_sets;
 
     for (;;) {
@@ -1378,53 +1381,71 @@ __global__ __launch_bounds__(BLOCK) void k_cull_multi(MultiArgs a)
         }
         __syncthreads();
 
-        // decoupled look-back over 1 + C counters (wave 0; lane j owns counter j)
+        // decoupled look-back over 1 + C counters by wave 0.  Every (tile,
+        // counter) pair has its own 64-bit word holding flag and count, so each
+        // word is self-validating and relaxed agent-scope atomics suffice (no
+        // payload is published behind a flag; acquire/release would write back
+        // or invalidate the whole L2).  Lanes walk 64 predecessors at a time;
+        // each counter stops at its nearest inclusive word.  Lane j ends up
+        // holding the exclusive prefix of counter j.
         if (wave == 0) {
             const int ncnt = 1 + C;
+            u64 *mine = st + (size_t)tile * kNCnt;
             const u32 agg = lane < ncnt ? sAgg[lane] : 0u;
+            if (lane < ncnt)
+                __hip_atomic_store(&mine[lane], (tile == 0 ? kFlagInc : kFlagAgg) | (u64)agg, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
             u32 excl = 0;
             if (tile > 0) {
-                if (lane < ncnt) vals[((size_t)tile * 2 + 0) * kNCnt + lane] = agg;
-                __threadfence();
-                if (lane == 0) __hip_atomic_store(&flags[tile], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                u64 pending = (ncnt >= 64) ? ~0ull : ((1ull << ncnt) - 1ull);
                 int64_t base = (int64_t)tile - 1;
-                for (;;) {
+                while (pending) {
                     const int64_t idx = base - lane;
-                    u32 f = 2u;
-                    if (idx >= 0) {
-                        u32 spins = 0;
-                        f = __hip_atomic_load(&flags[idx], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-                        while (f == 0u && spins < kSpinLimit) {
-                            __builtin_amdgcn_s_sleep(1);
-                            f = __hip_atomic_load(&flags[idx], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-                            ++spins;
+                    u64 still = pending;
+                    for (int j0 = 0; j0 < ncnt; j0 += kLookChunk) {
+                        u64 w[kLookChunk];
+#pragma unroll
+                        for (int q = 0; q < kLookChunk; ++q) {
+                            const int j = j0 + q;
+                            w[q] = kFlagInc;  // before the first tile: inclusive zero
+                            if (j < ncnt && ((pending >> j) & 1ull) && idx >= 0)
+                                w[q] = __hip_atomic_load(&st[(size_t)idx * kNCnt + j], __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT);
                         }
-                        if (f == 0u) {
-                            atomicOr(&a.hdr->error, 1u);
-                            f = 3u;  // treated as an inclusive zero
+#pragma unroll
+                        for (int q = 0; q < kLookChunk; ++q) {
+                            const int j = j0 + q;
+                            if (j >= ncnt || !((pending >> j) & 1ull)) continue;
+                            u64 x = w[q];
+                            u32 spins = 0;
+                            while ((x >> 62) == 0 && spins < kSpinLimit) {
+                                __builtin_amdgcn_s_sleep(1);
+                                x = __hip_atomic_load(&st[(size_t)idx * kNCnt + j], __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+                                ++spins;
+                            }
+                            if ((x >> 62) == 0) {
+                                atomicOr(&a.hdr->error, 1u);
+                                x = kFlagInc;  // treated as an inclusive zero
+                            }
+                            const u64 incm = __ballot((x >> 62) == 2);
+                            const int stop = incm ? __builtin_ctzll(incm) : 63;
+                            const u64 sum = wave_sum_u64(lane <= stop ? (x & kValMask) : 0ull);
+                            if (lane == j) excl += (u32)sum;
+                            if (incm) still &= ~(1ull << j);
                         }
                     }
-                    const u64 incm = __ballot(f >= 2u);
-                    const int stop = incm ? __builtin_ctzll(incm) : 63;
-                    for (int j = 0; j < ncnt; ++j) {
-                        u32 x = 0;
-                        if (idx >= 0 && lane <= stop && f != 3u)
-                            x = vals[((size_t)idx * 2 + (f == 2u ? 1 : 0)) * kNCnt + j];
-                        u64 sum = wave_sum_u64((u64)x);
-                        if (lane == j) excl += (u32)sum;
-                    }
-                    if (incm) break;
+                    pending = still;
                     base -= 64;
                 }
+                if (lane < ncnt)
+                    __hip_atomic_store(&mine[lane], kFlagInc | (u64)(excl + agg), __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
             }
-            if (lane < ncnt) {
-                vals[((size_t)tile * 2 + 1) * kNCnt + lane] = excl + agg;
-                sExcl[lane] = excl;
-            }
-            __threadfence();
-            if (lane == 0) __hip_atomic_store(&flags[tile], 2u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            if (lane < ncnt) sExcl[lane] = excl;
             // the next call uses the other half, whatever its tile size: clear all of it
-            for (int64_t j = tile + lane * a.tiles; j < a.stride; j += 64 * a.tiles) flags_other[j] = 0u;
+            const int64_t words = a.stride * kNCnt;
+            for (int64_t j = (int64_t)tile * 64 + lane; j < words; j += 64 * a.tiles) st_other[j] = 0ull;
             if (lane < ncnt) {
                 if (row0 == a.scene_row0[scene]) a.scene_start[(int64_t)scene * (1 + C) + lane] = excl;
                 if ((int64_t)tile == a.tiles - 1) {
@@ -1456,16 +1477,17 @@ __global__ __launch_bounds__(BLOCK) void k_cull_multi(MultiArgs a)
 
     __syncthreads();
     if (tid == 0) {
-        __threadfence();
-        const u32 prev = atomicAdd(&a.hdr->done, 1u);
-        if (prev == gridDim.x - 1) {
-            __threadfence();
+        // the last block to finish resets the header (every other block has
+        // already taken its last ticket)
+        const u64 prev = __hip_atomic_fetch_add(&a.hdr->done_rest, 1ull << 40, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+        if ((prev >> 40) == gridDim.x - 1) {
             if (a.tiles == 0) {
                 *a.union_count = 0;
                 for (int c = 0; c < C; ++c) a.cam_count[c] = 0;
             }
+            a.hdr->done_rest = 0;
             a.hdr->ticket = 0;
-            a.hdr->done = 0;
             a.hdr->parity = parity ^ 1u;
         }
     }
@@ -1546,7 +1568,7 @@ constexpr int kMultiIpt[kMultiVariants] = {1, 2, 4, 1, 2, 4};
 int64_t multi_ws_bytes(int64_t n)
 {
     const int64_t tiles = (n + kMultiMinTile - 1) / kMultiMinTile;
-    return gsdp::kWsHeader + 8 * tiles + 2 * tiles * 2 * kNCnt * 4;
+    return gsdp::kWsHeader + 2 * tiles * kNCnt * 8;
 }
 
 int multi_args(const gs_model *model, const gs_multi *d, int64_t step, void *ws, size_t ws_bytes, MultiArgs &a)
@@ -1588,8 +1610,7 @@ int multi_args(const gs_model *model, const gs_multi *d, int64_t step, void *ws,
     char *wsb = static_cast<char *>(ws);
     a.hdr = reinterpret_cast<gsdp::WsHeader *>(wsb);
     const int64_t max_tiles = (model->n + kMultiMinTile - 1) / kMultiMinTile;
-    a.flags = reinterpret_cast<u32 *>(wsb + gsdp::kWsHeader);
-    a.vals = reinterpret_cast<u32 *>(wsb + gsdp::kWsHeader + 8 * max_tiles);
+    a.st = reinterpret_cast<u64 *>(wsb + gsdp::kWsHeader);
     a.tiles = max_tiles;  // replaced per variant in launch_multi
     return GS_OK;
 }

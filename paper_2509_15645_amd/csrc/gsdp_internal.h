@@ -43,16 +43,18 @@ constexpr int kCullTile = kCullBlock * kCullIpt;
 constexpr int64_t kWsHeader = 256;
 struct WsHeader {
     uint32_t ticket;     // next cull tile to hand out
-    uint32_t done;       // blocks finished (last one resets the header)
     uint32_t parity;     // which tile-state buffer the next cull uses
     uint32_t error;      // bit 0: a look-back wait hit its bound
     uint32_t sat_total;  // saturated rows listed by the last cull
-    uint32_t restored;   // rows restored by the running cull (diagnostic accumulator)
+    // blocks finished (bits 40..63) and rows restored (bits 0..39) by the running
+    // cull, in one word so a single atomic orders them; the last block resets it
+    unsigned long long done_rest;
     uint32_t restored_last;  // rows restored by the last completed cull
     uint32_t pad_;
     unsigned long long vis_accum;       // visible rows summed over all completed culls
     unsigned long long restored_accum;  // restored rows summed over all completed culls
 };
+static_assert(sizeof(WsHeader) == 48, "workspace header layout");
 
 inline int64_t cull_tiles(int64_t n) { return (n + kCullTile - 1) / kCullTile; }
 constexpr int kWordsPerTile = kCullTile / 64;

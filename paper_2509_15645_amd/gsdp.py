@@ -297,8 +297,9 @@ class Model:
     def ws_header(self) -> dict:
         h = self.ws[:12].cpu().numpy().view(np.uint32)
         q = h[8:12].view(np.uint64)
-        return {"ticket": int(h[0]), "done": int(h[1]), "parity": int(h[2]), "error": int(h[3]),
-                "sat_total": int(h[4]), "restored_last": int(h[6]), "vis_accum": int(q[0]),
+        dr = int(h[4]) | (int(h[5]) << 32)
+        return {"ticket": int(h[0]), "done": dr >> 40, "parity": int(h[1]), "error": int(h[2]),
+                "sat_total": int(h[3]), "restored_last": int(h[6]), "vis_accum": int(q[0]),
                 "restored_accum": int(q[1])}
 
     def state(self):
