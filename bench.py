@@ -91,6 +91,37 @@ def cpu_baseline(w, geo_all, app_all, sample, steps, lg, la):
                       f"(median step {med * 1e3:.1f} ms): FP32 cull + ids + synthetic grads + dense FP64 Adam"}
 
 
+KERNEL_SYMBOL = {"cull": "k_cull", "gather": "k_rows<0", "adam": "k_rows<1", "cull_multi": "k_cull_multi",
+                 "grad_sum": "k_grad_sum", "adam_bf16": "k_rows<1"}
+
+
+def source_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("gsdp.hip", "gsdp_internal.h", "gsdp_lut.cpp"):
+        with open(os.path.join(ROOT, "paper_2509_15645_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, config_key):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE per dispatch, scaled by the plain-copy
+    calibration), or None when no summary matches this configuration or the
+    kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    digest, cur, found = source_digest(), None, {}
+    for line in open(path):
+        f = line.split()
+        if len(f) >= 2 and f[0] == "source_digest":
+            cur = f[1]
+        elif len(f) >= 4 and f[0] == "bytes_per_launch" and cur == digest and f[1] == config_key:
+            found[f[2]] = float(f[3])
+    return found.get(KERNEL_SYMBOL.get(kernel, kernel))
+
+
 def device_scene(n, box, seed, dev):
     """Seeded synthetic scene drawn on the device (same distributions as
     gs_inputs.make_scene, torch's generator instead of numpy's)."""
@@ -225,6 +256,12 @@ def run_batched(args):
         "setup_s": setup_s,
     }
     print(json.dumps(out), flush=True)
+
+
+def config_key(args, workload):
+    """Names the launch configuration a counter summary was taken with."""
+    return (f"{workload}/{args.state}/{args.geo_state or args.state}/{args.layout}/cull{args.cull_mode}"
+            f"/geo{args.geo_mode}/K{args.max_defer}/tilt{args.tilt.replace(',', '-')}")
 
 
 def main():
@@ -388,7 +425,8 @@ def main():
         "graph_ms_per_step": graph_ms,
         "kernels_gbs": {k: v[1] / (v[0] * 1e-3) / 1e9 for k, v in kernels.items()},
         "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom, config_key(args, w.name)),
+                     "algorithmic_bytes": dbytes},
         "setup_s": setup_s,
     }
     if not args.no_cpu_baseline:

@@ -135,10 +135,11 @@ int gs_lut_build_schedule_host(double beta1, double beta2, int32_t max_steps, in
 /* ------------------------------------------------------------- workspace */
 
 /* Bytes of the scratch workspace that gs_cull and gs_adam_step_deferred
- * share for one model: compaction tile states, work counters and the list of
- * saturated rows.  The buffer must be zero-filled once before its first use
- * and then left alone by the caller; one workspace serves one model and one
- * stream at a time. */
+ * share for one model: per-tile keep ballots, counts and prefixes of the
+ * compaction, the list of saturated rows and diagnostic counters (about 0.2
+ * bytes per Gaussian, plus 4.1 with max_defer > 0).  Zero-fill it once so the
+ * diagnostic counters start at zero; the caller must not write it afterwards.
+ * One workspace serves one model and one stream at a time. */
 int gs_workspace_bytes(const gs_model *model, size_t *bytes);
 
 /* ------------------------------------------------------------------ path */
@@ -232,7 +233,8 @@ typedef struct gs_multi {
 int gs_camera_pack_bytes(size_t *bytes);
 int gs_camera_pack(const gs_model *model, const gs_camera *cams, int32_t count, void *out_host);
 
-/* Workspace of gs_cull_multi (zero-filled once; 4.2 bytes per Gaussian). */
+/* Workspace of gs_cull_multi: per-row camera bits and per-tile counts and
+ * prefixes (about 6.1 bytes per Gaussian; needs no initialisation). */
 int gs_multi_workspace_bytes(const gs_model *model, size_t *bytes);
 
 /* Batched cull + ordered compaction of every (scene, camera) pair (Sec. 2.4

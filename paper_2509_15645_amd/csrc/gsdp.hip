@@ -404,15 +404,15 @@ __device__ __forceinline__ int resolve_step(const StepK &s, int extra, const flo
 }
 
 // ---------------------------------------------------------------------------
-// cull + ordered compaction
+// cull + ordered compaction, in three launches without inter-block waits:
+//   k_cull       one block per 512-row tile: cull every row, store the keep
+//                (and saturated) ballots and the tile's counts
+//   k_tile_scan  one block: exclusive prefix of the tile counts, totals
+//   k_tile_ids   one wavefront per tile: ids from ballots + tile prefix
+// No same-address atomics and no spin-waits: on this multi-die part a
+// device-scope atomic on one word serialises across all dies, which costs
+// more than the two extra launches.
 // ---------------------------------------------------------------------------
-constexpr u64 kFlagAgg = 1ull << 62;
-constexpr u64 kFlagInc = 2ull << 62;
-constexpr u64 kValMask = (1ull << 62) - 1;
-constexpr u32 kSpinLimit = 1u << 24;
-
-__device__ __forceinline__ u64 pack_vs(u32 vis, u32 sat) { return ((u64)vis << 31) | (u64)sat; }
-
 struct CullArgs {
     const float *gw;                 // [n][10]
     MomRef gm, gv;                   // G moments (restore), storage type gst
@@ -427,12 +427,11 @@ struct CullArgs {
     BandK band;
     int32_t mode;                    // 0 exact restoring, 1 band
     int32_t geo_dense;               // geometry updated densely every step: never restore G
-    u64 *keep_bits;                  // per tile, per (slab, wave) keep ballots (dense-G mode)
-    u32 *ids, *count;
-    u32 cap, pad1;
-    u32 *sat_ids;
-    gsdp::WsHeader *hdr;
-    u64 *st;                         // tile states [2][tiles]
+    int32_t K;                       // max_defer
+    int32_t pad4;
+    u64 *keep_bits;                  // [tiles][8] keep ballots of the tile's 64-row slabs
+    u64 *sat_bits;                   // [tiles][8] saturated ballots (K > 0)
+    u32 *tile_cnt;                   // [tiles][4] visible, saturated, restored, 0
     int64_t tiles;
 };
 
@@ -440,210 +439,235 @@ __global__ __launch_bounds__(kCullBlock) void k_cull(CullArgs a)
 {
     __shared__ float4 sG4[kCullTile * 10 / 4];
     __shared__ u32 sCntV[kCullIpt * 4], sCntS[kCullIpt * 4];
-    __shared__ u32 sOffV[kCullIpt * 4], sOffS[kCullIpt * 4];
-    __shared__ u32 sTile, sParity, sRestored;
-    __shared__ u64 sAgg, sExcl;
+    __shared__ u32 sRestored;
     float *sG = reinterpret_cast<float *>(sG4);
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t tile = blockIdx.x;
     const float *Wrow;
     int dmax;
     const int t = resolve_step(a.step, 0, &Wrow, &dmax);
-    const int K = a.step.K;
-    if (tid == 0) {
-        sParity = __hip_atomic_load(&a.hdr->parity, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        sRestored = 0;
+    const int K = a.K;
+    if (tid == 0) sRestored = 0;
+    const int64_t row0 = tile * kCullTile;
+    const int rows = (int)min((int64_t)kCullTile, a.n - row0);
+
+    // stage the tile's geometry (rows x 40 B, contiguous) through LDS
+    const int nf = rows * 10, nf4 = nf >> 2;
+    const float *src = a.gw + row0 * 10;
+    const float4 *src4 = reinterpret_cast<const float4 *>(src);
+    for (int j = tid; j < nf4; j += kCullBlock) sG4[j] = src4[j];
+    for (int j = nf4 * 4 + tid; j < nf; j += kCullBlock) sG[j] = src[j];
+    int lastv[kCullIpt];
+#pragma unroll
+    for (int k = 0; k < kCullIpt; ++k) {
+        const int r = k * kCullBlock + tid;
+        lastv[k] = r < rows ? a.last[row0 + r] : 0;
     }
     __syncthreads();
-    const u32 parity = sParity & 1u;
-    u64 *st = a.st + (size_t)parity * a.tiles;
-    u64 *st_other = a.st + (size_t)(parity ^ 1u) * a.tiles;
 
-    for (;;) {
-        if (tid == 0) sTile = atomicAdd(&a.hdr->ticket, 1u);
-        __syncthreads();
-        const u32 tile = sTile;
-        if ((int64_t)tile >= a.tiles) break;
-        const int64_t row0 = (int64_t)tile * kCullTile;
-        const int rows = (int)min((int64_t)kCullTile, a.n - row0);
-
-        // stage the tile's geometry (rows x 40 B, contiguous) through LDS
-        const int nf = rows * 10, nf4 = nf >> 2;
-        const float *src = a.gw + row0 * 10;
-        const float4 *src4 = reinterpret_cast<const float4 *>(src);
-        for (int j = tid; j < nf4; j += kCullBlock) sG4[j] = src4[j];
-        for (int j = nf4 * 4 + tid; j < nf; j += kCullBlock) sG[j] = src[j];
-        int lastv[kCullIpt];
+    u32 nrest = 0;
 #pragma unroll
-        for (int k = 0; k < kCullIpt; ++k) {
-            const int r = k * kCullBlock + tid;
-            lastv[k] = r < rows ? a.last[row0 + r] : 0;
-        }
-        __syncthreads();
-
-        u64 bv[kCullIpt], bs[kCullIpt];
-        u32 nrest = 0;
+    for (int k = 0; k < kCullIpt; ++k) {
+        const int r = k * kCullBlock + tid;
+        bool keep = false, sat = false;
+        if (r < rows) {
+            float g[10];
+            const float2 *p2 = reinterpret_cast<const float2 *>(sG + r * 10);
 #pragma unroll
-        for (int k = 0; k < kCullIpt; ++k) {
-            const int r = k * kCullBlock + tid;
-            bool keep = false, sat = false;
-            if (r < rows) {
-                float g[10];
-                const float2 *p2 = reinterpret_cast<const float2 *>(sG + r * 10);
+            for (int j = 0; j < 5; ++j) {
+                const float2 q = p2[j];
+                g[2 * j] = q.x;
+                g[2 * j + 1] = q.y;
+            }
+            int d = t - 1 - lastv[k];
+            d = d < 0 ? 0 : (d > dmax ? dmax : d);
+            // with dense geometry the stored G is always current
+            const float wd = (d > 0 && !a.geo_dense) ? Wrow[d] : 0.0f;
+            const int cls = a.mode == 1 ? classify(g, wd, a.cam, a.band) : 2;
+            if (cls == 2) {
+                if (d > 0 && !a.geo_dense) {
+                    const int64_t row = row0 + r;
+                    float mv[10], vv[10];
+                    if (a.gst == GS_F32) {
 #pragma unroll
-                for (int j = 0; j < 5; ++j) {
-                    const float2 q = p2[j];
-                    g[2 * j] = q.x;
-                    g[2 * j + 1] = q.y;
-                }
-                int d = t - 1 - lastv[k];
-                d = d < 0 ? 0 : (d > dmax ? dmax : d);
-                // with dense geometry the stored G is always current
-                const float wd = (d > 0 && !a.geo_dense) ? Wrow[d] : 0.0f;
-                const int cls = a.mode == 1 ? classify(g, wd, a.cam, a.band) : 2;
-                if (cls == 2) {
-                    if (d > 0 && !a.geo_dense) {
-                        const int64_t row = row0 + r;
-                        float mv[10], vv[10];
-                        if (a.gst == GS_F32) {
-#pragma unroll
-                            for (int j = 0; j < 10; ++j) {
-                                mv[j] = mom_load<GS_F32>(a.gm, row, j, false);
-                                vv[j] = mom_load<GS_F32>(a.gv, row, j, true);
-                            }
-                        } else if (a.gst == GS_BF16) {
-#pragma unroll
-                            for (int j = 0; j < 10; ++j) {
-                                mv[j] = mom_load<GS_BF16>(a.gm, row, j, false);
-                                vv[j] = mom_load<GS_BF16>(a.gv, row, j, true);
-                            }
-                        } else {
-#pragma unroll
-                            for (int j = 0; j < 10; ++j) {
-                                mv[j] = mom_load<GS_FP8E4M3>(a.gm, row, j, false);
-                                vv[j] = mom_load<GS_FP8E4M3>(a.gv, row, j, true);
-                            }
+                        for (int j = 0; j < 10; ++j) {
+                            mv[j] = mom_load<GS_F32>(a.gm, row, j, false);
+                            vv[j] = mom_load<GS_F32>(a.gv, row, j, true);
                         }
+                    } else if (a.gst == GS_BF16) {
 #pragma unroll
-                        for (int j = 0; j < 10; ++j) g[j] = restore1(g[j], mv[j], vv[j], wd, a.lr[j], a.eps, a.rb);
-                        ++nrest;
+                        for (int j = 0; j < 10; ++j) {
+                            mv[j] = mom_load<GS_BF16>(a.gm, row, j, false);
+                            vv[j] = mom_load<GS_BF16>(a.gv, row, j, true);
+                        }
+                    } else {
+#pragma unroll
+                        for (int j = 0; j < 10; ++j) {
+                            mv[j] = mom_load<GS_FP8E4M3>(a.gm, row, j, false);
+                            vv[j] = mom_load<GS_FP8E4M3>(a.gv, row, j, true);
+                        }
                     }
-                    keep = cull_v1(g, a.cam);
-                } else {
-                    keep = cls == 1;
+#pragma unroll
+                    for (int j = 0; j < 10; ++j) g[j] = restore1(g[j], mv[j], vv[j], wd, a.lr[j], a.eps, a.rb);
+                    ++nrest;
                 }
-                sat = (K > 0) && !keep && d == K;
-            }
-            bv[k] = __ballot(keep);
-            bs[k] = __ballot(sat);
-            if (lane == 0) {
-                sCntV[k * 4 + wave] = (u32)__popcll(bv[k]);
-                sCntS[k * 4 + wave] = (u32)__popcll(bs[k]);
-                if (a.keep_bits) a.keep_bits[(int64_t)tile * (kCullIpt * 4) + k * 4 + wave] = bv[k];
-            }
-        }
-        if (nrest) atomicAdd(&sRestored, nrest);
-        __syncthreads();
-
-        if (tid == 0) {
-            u32 sv = 0, ss = 0;
-            for (int e = 0; e < kCullIpt * 4; ++e) {
-                sOffV[e] = sv;
-                sv += sCntV[e];
-                sOffS[e] = ss;
-                ss += sCntS[e];
-            }
-            sAgg = pack_vs(sv, ss);
-        }
-        __syncthreads();
-
-        // decoupled look-back by wave 0.  A tile's whole state (flag, visible and
-        // saturated counts) is one 64-bit word, so relaxed agent-scope atomics
-        // suffice: no other memory is published through it, and acquire/release
-        // would cost a writeback or invalidate of the whole L2 per access.
-        if (wave == 0) {
-            const u64 agg = sAgg;
-            u64 excl = 0;
-            if (tile == 0) {
-                if (lane == 0) __hip_atomic_store(&st[0], kFlagInc | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                keep = cull_v1(g, a.cam);
             } else {
-                if (lane == 0)
-                    __hip_atomic_store(&st[tile], kFlagAgg | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                int64_t base = (int64_t)tile - 1;
-                for (;;) {
-                    const int64_t idx = base - lane;
-                    u64 s = kFlagInc;
-                    if (idx >= 0) {
-                        u32 spins = 0;
-                        s = __hip_atomic_load(&st[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        while ((s >> 62) == 0 && spins < kSpinLimit) {
-                            __builtin_amdgcn_s_sleep(1);
-                            s = __hip_atomic_load(&st[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                            ++spins;
-                        }
-                        if ((s >> 62) == 0) {
-                            atomicOr(&a.hdr->error, 1u);
-                            s = kFlagInc;
-                        }
-                    }
-                    const u64 incm = __ballot((s >> 62) == 2);
-                    const u64 val = s & kValMask;
-                    if (incm) {
-                        const int stop = __builtin_ctzll(incm);
-                        excl += wave_sum_u64(lane <= stop ? val : 0ull);
-                        break;
-                    }
-                    excl += wave_sum_u64(val);
-                    base -= 64;
-                }
-                if (lane == 0)
-                    __hip_atomic_store(&st[tile], kFlagInc | (excl + agg), __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
+                keep = cls == 1;
             }
-            if (lane == 0) {
-                sExcl = excl;
-                if ((int64_t)tile == a.tiles - 1) {
-                    const u64 inc = excl + agg;
-                    *a.count = (u32)(inc >> 31);
-                    a.hdr->sat_total = (u32)(inc & 0x7fffffffu);
-                    a.hdr->vis_accum += inc >> 31;
-                }
-                st_other[tile] = 0;  // the next call uses the other buffer
-            }
+            sat = (K > 0) && !keep && d == K;
         }
-        __syncthreads();
-
-        const u64 ex = sExcl;
-        const u32 pv = (u32)(ex >> 31), ps = (u32)(ex & 0x7fffffffu);
-#pragma unroll
-        for (int k = 0; k < kCullIpt; ++k) {
-            const u32 row = (u32)(row0 + k * kCullBlock + tid);
-            if ((bv[k] >> lane) & 1ull) {
-                const u32 pos = pv + sOffV[k * 4 + wave] + lane_rank(bv[k]);
-                if (pos < a.cap) a.ids[pos] = row;
-            }
-            if ((bs[k] >> lane) & 1ull) a.sat_ids[ps + sOffS[k * 4 + wave] + lane_rank(bs[k])] = row;
+        const u64 bv = __ballot(keep);
+        const u64 bs = __ballot(sat);
+        if (lane == 0) {
+            const int slab = k * 4 + wave;   // rows row0 + slab*64 .. +63
+            sCntV[slab] = (u32)__popcll(bv);
+            sCntS[slab] = (u32)__popcll(bs);
+            a.keep_bits[tile * gsdp::kWordsPerTile + slab] = bv;
+            if (K > 0) a.sat_bits[tile * gsdp::kWordsPerTile + slab] = bs;
         }
     }
-
+    if (nrest) atomicAdd(&sRestored, nrest);
     __syncthreads();
     if (tid == 0) {
-        // one atomic carries "block done" and its restored rows; the block that
-        // sees every other block done holds the full count and resets the header
-        // (all other blocks have already taken their last ticket)
-        const u64 prev = __hip_atomic_fetch_add(&a.hdr->done_rest, (1ull << 40) | (u64)sRestored,
-                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if ((prev >> 40) == gridDim.x - 1) {
-            if (a.tiles == 0) {
-                *a.count = 0;
-                a.hdr->sat_total = 0;
+        u32 sv = 0, ss = 0;
+        for (int e = 0; e < kCullIpt * 4; ++e) {
+            sv += sCntV[e];
+            ss += sCntS[e];
+        }
+        uint4 c;
+        c.x = sv;
+        c.y = ss;
+        c.z = sRestored;
+        c.w = 0;
+        reinterpret_cast<uint4 *>(a.tile_cnt)[tile] = c;
+    }
+}
+
+// Exclusive prefix of (visible, saturated) over tiles by one block: each
+// thread owns a contiguous run of tiles.  Writes tile_off[tile] = (visible,
+// saturated) before the tile, the totals (count, header) and the diagnostics.
+struct ScanArgs {
+    const u32 *tile_cnt;             // [tiles][4]
+    u32 *tile_off;                   // [tiles][2]
+    int64_t tiles;
+    u32 *count;                      // visible total (device, the caller's count)
+    gsdp::WsHeader *hdr;
+};
+
+constexpr int kScanThreads = 1024;
+
+__device__ __forceinline__ u64 block_excl_scan_u64(u64 x, u64 *sWave, u64 *total)
+{
+    // inclusive scan within the wave, then over the 16 wave totals
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    u64 inc = x;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const u64 y = (u64)__shfl_up((long long)inc, o);
+        if (lane >= o) inc += y;
+    }
+    if (lane == 63) sWave[wave] = inc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        u64 run = 0;
+        for (int w = 0; w < kScanThreads / 64; ++w) {
+            const u64 v = sWave[w];
+            sWave[w] = run;
+            run += v;
+        }
+        sWave[kScanThreads / 64] = run;
+    }
+    __syncthreads();
+    *total = sWave[kScanThreads / 64];
+    return sWave[wave] + inc - x;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_tile_scan(ScanArgs a)
+{
+    __shared__ u64 sWave[kScanThreads / 64 + 1];
+    __shared__ u64 sRest[kScanThreads / 64 + 1];
+    const int tid = threadIdx.x;
+    const int64_t per = (a.tiles + kScanThreads - 1) / kScanThreads;
+    const int64_t t0 = min((int64_t)tid * per, a.tiles), t1 = min(t0 + per, a.tiles);
+    const uint4 *cnt = reinterpret_cast<const uint4 *>(a.tile_cnt);
+    constexpr int kIlp = 8;          // independent loads in flight per thread
+    u64 vs = 0, rest = 0;
+    for (int64_t i0 = t0; i0 < t1; i0 += kIlp) {
+        uint4 c[kIlp];
+#pragma unroll
+        for (int q = 0; q < kIlp; ++q) c[q] = i0 + q < t1 ? cnt[i0 + q] : make_uint4(0, 0, 0, 0);
+#pragma unroll
+        for (int q = 0; q < kIlp; ++q) {
+            vs += ((u64)c[q].x << 32) | (u64)c[q].y;
+            rest += c[q].z;
+        }
+    }
+    u64 tot = 0, rtot = 0;
+    u64 run = block_excl_scan_u64(vs, sWave, &tot);
+    block_excl_scan_u64(rest, sRest, &rtot);
+    uint2 *off = reinterpret_cast<uint2 *>(a.tile_off);
+    for (int64_t i0 = t0; i0 < t1; i0 += kIlp) {
+        uint4 c[kIlp];
+#pragma unroll
+        for (int q = 0; q < kIlp; ++q) c[q] = i0 + q < t1 ? cnt[i0 + q] : make_uint4(0, 0, 0, 0);
+#pragma unroll
+        for (int q = 0; q < kIlp; ++q) {
+            if (i0 + q < t1) off[i0 + q] = make_uint2((u32)(run >> 32), (u32)run);
+            run += ((u64)c[q].x << 32) | (u64)c[q].y;
+        }
+    }
+    if (tid == 0) {
+        const u32 vis = (u32)(tot >> 32);
+        *a.count = vis;
+        a.hdr->vis_total = vis;
+        a.hdr->sat_total = (u32)tot;
+        a.hdr->restored_last = (u32)rtot;
+        a.hdr->vis_accum += vis;
+        a.hdr->restored_accum += rtot;
+    }
+}
+
+// One wavefront per tile: visible (and saturated) ids in ascending order from
+// the tile's ballots and exclusive prefix.
+struct IdsArgs {
+    const u64 *keep_bits, *sat_bits;
+    const u32 *tile_off;
+    int64_t tiles, n;
+    u32 *ids;
+    u32 cap, pad;
+    u32 *sat_ids;
+};
+
+__global__ __launch_bounds__(256) void k_tile_ids(IdsArgs a)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t wid = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t nw = (int64_t)gridDim.x * 4;
+    const u64 lt = (1ull << lane) - 1ull;
+    for (int64_t tile = wid; tile < a.tiles; tile += nw) {
+        const int64_t row0 = tile * kCullTile;
+        const uint2 o = reinterpret_cast<const uint2 *>(a.tile_off)[tile];
+        u64 kw = 0, sw = 0;
+        if (lane < gsdp::kWordsPerTile) {
+            kw = a.keep_bits[tile * gsdp::kWordsPerTile + lane];
+            if (a.sat_ids) sw = a.sat_bits[tile * gsdp::kWordsPerTile + lane];
+        }
+        u32 pv = o.x, ps = o.y;
+#pragma unroll
+        for (int sl = 0; sl < gsdp::kWordsPerTile; ++sl) {
+            const u64 bv = (u64)__shfl((long long)kw, sl);
+            if ((bv >> lane) & 1ull) {
+                const u32 pos = pv + (u32)__popcll(bv & lt);
+                if (pos < a.cap) a.ids[pos] = (u32)(row0 + sl * 64 + lane);
             }
-            const u32 rest = (u32)(prev & ((1ull << 40) - 1)) + sRestored;
-            a.hdr->restored_last = rest;
-            a.hdr->restored_accum += rest;
-            a.hdr->done_rest = 0;
-            a.hdr->ticket = 0;
-            a.hdr->parity = parity ^ 1u;
+            pv += (u32)__popcll(bv);
+            if (a.sat_ids) {
+                const u64 bs = (u64)__shfl((long long)sw, sl);
+                if ((bs >> lane) & 1ull) a.sat_ids[ps + (u32)__popcll(bs & lt)] = (u32)(row0 + sl * 64 + lane);
+                ps += (u32)__popcll(bs);
+            }
         }
     }
 }
@@ -854,6 +878,7 @@ struct RescaleArgs {
 
 __global__ __launch_bounds__(256) void k_fp8_rescale(RescaleArgs a)
 {
+    constexpr int kIlp = 8;
     const int lane = threadIdx.x & 63;
     const int64_t wid = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int64_t nw = (int64_t)gridDim.x * 4;
@@ -861,32 +886,62 @@ __global__ __launch_bounds__(256) void k_fp8_rescale(RescaleArgs a)
     int dmax;
     const int t = resolve_step(a.step, 0, &Wrow, &dmax);
     const u64 s_step = sm_at(a.sr_seed, (u64)t);
-    for (int64_t task = wid; task < 4 * a.nb; task += nw) {
-        const int which = (int)(task / a.nb);
-        const int64_t b = task - (int64_t)which * a.nb;
-        if (!a.fp8[which]) continue;
-        const u32 mb = a.maxb[which][b];
-        if (mb == 0) continue;
-        const float amax = __uint_as_float(mb);
-        const float sold = a.s[which][b];
-        const float snew = fp8_scale_for(amax);
-        if (snew > sold) {
-            const int dim = a.dim[which];
-            const int64_t r0 = b * kFp8Block;
-            const int64_t r1 = min(r0 + kFp8Block, a.n);
-            const bool is_v = which & 1;
-            for (int64_t r = r0; r < r1; ++r) {
-                for (int c = lane; c < dim; c += 64) {
-                    uint8_t *qp = a.q[which] + r * a.ld[which] + c;
-                    const float x = e4m3_dec(*qp) * sold;
-                    const u64 h = sm_at(sm_at(s_step, (u64)r), (u64)(a.col0[which] + c + 64));
+    const int64_t ntask = 4 * a.nb;
+    // lane-parallel scan: each wave checks 64 (moment, block) tasks with one
+    // load and then re-encodes the blocks that grew, whole wave per block
+    for (int64_t g0 = wid * 64; g0 < ntask; g0 += nw * 64) {
+        const int64_t task = g0 + lane;
+        int which = 0;
+        int64_t b = 0;
+        u32 mb = 0;
+        if (task < ntask) {
+            which = (int)(task / a.nb);
+            b = task - (int64_t)which * a.nb;
+            if (a.fp8[which]) mb = a.maxb[which][b];
+        }
+        u64 todo = __ballot(mb != 0u);
+        if (mb != 0u) a.maxb[which][b] = 0u;
+        while (todo) {
+            const int src = __builtin_ctzll(todo);
+            todo &= todo - 1;
+            const int wq = __shfl(which, src);
+            const int64_t bq = (int64_t)__shfl((long long)b, src);
+            const float amax = __uint_as_float((u32)__shfl((int)mb, src));
+            const float sold = a.s[wq][bq];
+            const float snew = fp8_scale_for(amax);
+            if (!(snew > sold)) continue;
+            const int dim = a.dim[wq];
+            const int64_t r0 = bq * kFp8Block;
+            const int64_t nrow = min((int64_t)kFp8Block, a.n - r0);
+            const int64_t nel = nrow * dim;
+            const bool is_v = wq & 1;
+            uint8_t *q = a.q[wq];
+            const int64_t ld = a.ld[wq];
+            // flattened (row, column) elements, kIlp loads in flight per lane
+            for (int64_t e0 = 0; e0 < nel; e0 += 64 * kIlp) {
+                uint8_t code[kIlp];
+                int64_t off[kIlp], row[kIlp];
+                int col[kIlp];
+#pragma unroll
+                for (int k = 0; k < kIlp; ++k) {
+                    const int64_t e = e0 + k * 64 + lane;
+                    const int64_t rr = e / dim;
+                    row[k] = r0 + rr;
+                    col[k] = (int)(e - rr * dim);
+                    off[k] = e < nel ? row[k] * ld + col[k] : -1;
+                    code[k] = off[k] >= 0 ? q[off[k]] : (uint8_t)0;
+                }
+#pragma unroll
+                for (int k = 0; k < kIlp; ++k) {
+                    if (off[k] < 0) continue;
+                    const float x = e4m3_dec(code[k]) * sold;
+                    const u64 h = sm_at(sm_at(s_step, (u64)row[k]), (u64)(a.col0[wq] + col[k] + 64));
                     const u32 rr = (u32)((is_v ? h >> 16 : h) & 0xffffull);
-                    *qp = (uint8_t)e4m3_sr(x / snew, rr);
+                    q[off[k]] = (uint8_t)e4m3_sr(x / snew, rr);
                 }
             }
-            if (lane == 0) a.s[which][b] = snew;
+            if (lane == 0) a.s[wq][bq] = snew;
         }
-        if (lane == 0) a.maxb[which][b] = 0u;
     }
 }
 
@@ -904,8 +959,7 @@ struct DenseArgs {
     u64 sr_seed;
     const float *g_geo;              // compact gradients of the cull's visible rows, or NULL
     const u64 *keep_bits;            // the cull's keep ballots
-    const u64 *st0;                  // tile states [2][tiles]
-    const gsdp::WsHeader *hdr;
+    const u32 *tile_off;             // the cull's tile prefixes [tiles][2]
     int64_t tiles;
     u32 cap, pad2;
     float *gd_geo;                   // dense [n][10] gradients (read and cleared) when g_geo is NULL
@@ -913,7 +967,7 @@ struct DenseArgs {
 
 // One block per cull tile (512 rows x 10 columns, element-parallel and
 // coalesced).  The compact index of a visible row is the tile's exclusive
-// prefix (from the cull's look-back states) + the keep bits before it.
+// prefix (from the cull's tile scan) + the keep bits before it.
 template <int GST>
 __global__ __launch_bounds__(256) void k_dense_geo(DenseArgs a)
 {
@@ -926,11 +980,7 @@ __global__ __launch_bounds__(256) void k_dense_geo(DenseArgs a)
     const int rows = (int)min((int64_t)kCullTile, a.n - row0);
     if (a.g_geo) {
         if (tid < gsdp::kWordsPerTile) sBits[tid] = a.keep_bits[tile * gsdp::kWordsPerTile + tid];
-        if (tid == 0) {
-            const u32 used = (__hip_atomic_load(&a.hdr->parity, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ^ 1u) & 1u;
-            const u64 *st = a.st0 + (size_t)used * a.tiles;
-            sExcl = tile == 0 ? 0u : (u32)((st[tile - 1] >> 31) & 0x7fffffffull);
-        }
+        if (tid == 0) sExcl = a.tile_off[2 * tile];
         __syncthreads();
         if (tid == 0) {
             u32 o = 0;
@@ -1251,14 +1301,18 @@ struct MultiArgs {
     u32 *cam_pos, *cam_count;
     u32 cap_union, cap_cam;
     u32 *scene_start;                // [S][1+C]
-    gsdp::WsHeader *hdr;
-    u64 *st;                         // [2][stride][kNCnt] flag (2 bits) | count, one word per counter
+    u32 *cnt;                        // [kNCnt][stride] per-tile counts (union, camera slots)
+    u32 *off;                        // [kNCnt][stride] exclusive prefixes over tiles
+    u32 *mask;                       // [n] camera bits of every row
     int64_t tiles;                   // tiles of this launch
-    int64_t stride;                  // tiles of the smallest tile size (buffer halves)
+    int64_t stride;                  // tiles of the smallest tile size
+    int32_t tile_rows, pad5;         // rows per tile of this launch
 };
 
-constexpr int kLookChunk = 8;        // counters whose predecessor words are loaded together
-
+// Batched cull in three launches (as the single-camera cull): k_cull_multi
+// writes every row's camera bits and the tile's counts, k_multi_scan takes
+// the exclusive prefixes over tiles for every counter, k_multi_ids writes the
+// union ids and the per-camera union positions.
 template <int BLOCK, int IPT>
 __global__ __launch_bounds__(BLOCK) void k_cull_multi(MultiArgs a)
 {
@@ -1267,228 +1321,203 @@ __global__ __launch_bounds__(BLOCK) void k_cull_multi(MultiArgs a)
     constexpr int NSLAB = IPT * NW;
     __shared__ float4 sG4[TR * 10 / 4];
     __shared__ u32 sCnt[NSLAB][kNCnt];
-    __shared__ u32 sOff[NSLAB][kNCnt];
-    __shared__ u32 sAgg[kNCnt], sExcl[kNCnt];
-    __shared__ u32 sTile, sParity, sScene;
+    __shared__ u32 sScene;
     float *sG = reinterpret_cast<float *>(sG4);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const float *Wrow;
     int dmax;
     const int t = resolve_step(a.step, 0, &Wrow, &dmax);
     const int C = a.C;
-    if (tid == 0) sParity = __hip_atomic_load(&a.hdr->parity, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 1u;
-    __syncthreads();
-    const u32 parity = sParity;
-    u64 *st = a.st + (size_t)parity * a.stride * kNCnt;
-    u64 *st_other = a.st + (size_t)(parity ^ 1u) * a.stride * kNCnt;
     const int set = (t - 1) % a.n_sets;
+    const int64_t tile = blockIdx.x;
+    const int64_t row0 = tile * TR;
+    const int rows = (int)min((int64_t)TR, a.n - row0);
+    if (tid == 0) {
+        int sc = 0;
+        while (sc + 1 < a.S && a.scene_row0[sc + 1] <= row0) ++sc;
+        sScene = (u32)sc;
+    }
+    const int nf = rows * 10, nf4 = nf >> 2;
+    const float *src = a.gw + row0 * 10;
+    const float4 *src4 = reinterpret_cast<const float4 *>(src);
+    for (int j = tid; j < nf4; j += BLOCK) sG4[j] = src4[j];
+    for (int j = nf4 * 4 + tid; j < nf; j += BLOCK) sG[j] = src[j];
+    int lastv[IPT];
+#pragma unroll
+    for (int k = 0; k < IPT; ++k) {
+        const int r = k * BLOCK + tid;
+        lastv[k] = r < rows ? a.last[row0 + r] : 0;
+    }
+    __syncthreads();
+    const int scene = (int)sScene;
+    const bool in_scene = row0 < a.scene_row0[scene + 1];
+    const CamPack *cams = a.cams + ((int64_t)set * a.S + scene) * C;
 
-    for (;;) {
-        if (tid == 0) sTile = atomicAdd(&a.hdr->ticket, 1u);
-        __syncthreads();
-        const u32 tile = sTile;
-        if ((int64_t)tile >= a.tiles) break;
-        const int64_t row0 = (int64_t)tile * TR;
-        const int rows = (int)min((int64_t)TR, a.n - row0);
-        if (tid == 0) {
-            int sc = 0;
-            while (sc + 1 < a.S && a.scene_row0[sc + 1] <= row0) ++sc;
-            sScene = (u32)sc;
-        }
-        const int nf = rows * 10, nf4 = nf >> 2;
-        const float *src = a.gw + row0 * 10;
-        const float4 *src4 = reinterpret_cast<const float4 *>(src);
-        for (int j = tid; j < nf4; j += BLOCK) sG4[j] = src4[j];
-        for (int j = nf4 * 4 + tid; j < nf; j += BLOCK) sG[j] = src[j];
-        int lastv[IPT];
 #pragma unroll
-        for (int k = 0; k < IPT; ++k) {
-            const int r = k * BLOCK + tid;
-            lastv[k] = r < rows ? a.last[row0 + r] : 0;
-        }
-        __syncthreads();
-        const int scene = (int)sScene;
-        const bool in_scene = row0 < a.scene_row0[scene + 1];
-        const CamPack *cams = a.cams + ((int64_t)set * a.S + scene) * C;
-
-        u32 mask[IPT];
+    for (int k = 0; k < IPT; ++k) {
+        const int r = k * BLOCK + tid;
+        u32 mk = 0;
+        if (r < rows && in_scene) {
+            float g[10];
+            const float2 *p2 = reinterpret_cast<const float2 *>(sG + r * 10);
 #pragma unroll
-        for (int k = 0; k < IPT; ++k) {
-            const int r = k * BLOCK + tid;
-            u32 mk = 0;
-            if (r < rows && in_scene) {
-                float g[10];
-                const float2 *p2 = reinterpret_cast<const float2 *>(sG + r * 10);
-#pragma unroll
-                for (int j = 0; j < 5; ++j) {
-                    const float2 q = p2[j];
-                    g[2 * j] = q.x;
-                    g[2 * j + 1] = q.y;
-                }
-                int d = t - 1 - lastv[k];
-                d = d < 0 ? 0 : (d > dmax ? dmax : d);
-                const float wd = d > 0 ? Wrow[d] : 0.0f;
-                u32 undecided = 0;
-                const RowPre pre = classify_pre(g, wd, cams[0].band);
-                for (int c = 0; c < C; ++c) {
-                    const int cls = a.mode == 1 ? classify_cam(g, pre, cams[c].cam, cams[c].band) : 2;
-                    if (cls == 1) mk |= 1u << c;
-                    else if (cls == 2) undecided |= 1u << c;
-                }
-                if (undecided) {
-                    if (d > 0) {
-                        const int64_t row = row0 + r;
-                        float mv[10], vv[10];
-                        if (a.gst == GS_F32) {
-                            for (int j = 0; j < 10; ++j) {
-                                mv[j] = mom_load<GS_F32>(a.gm, row, j, false);
-                                vv[j] = mom_load<GS_F32>(a.gv, row, j, true);
-                            }
-                        } else if (a.gst == GS_BF16) {
-                            for (int j = 0; j < 10; ++j) {
-                                mv[j] = mom_load<GS_BF16>(a.gm, row, j, false);
-                                vv[j] = mom_load<GS_BF16>(a.gv, row, j, true);
-                            }
-                        } else {
-                            for (int j = 0; j < 10; ++j) {
-                                mv[j] = mom_load<GS_FP8E4M3>(a.gm, row, j, false);
-                                vv[j] = mom_load<GS_FP8E4M3>(a.gv, row, j, true);
-                            }
-                        }
-                        for (int j = 0; j < 10; ++j) g[j] = restore1(g[j], mv[j], vv[j], wd, a.lr[j], a.eps, a.rb);
-                    }
-                    for (int c = 0; c < C; ++c)
-                        if (((undecided >> c) & 1u) && cull_v1(g, cams[c].cam)) mk |= 1u << c;
-                }
+            for (int j = 0; j < 5; ++j) {
+                const float2 q = p2[j];
+                g[2 * j] = q.x;
+                g[2 * j + 1] = q.y;
             }
-            mask[k] = mk;
-            const int slab = k * NW + wave;
-            const u64 ub = __ballot(mk != 0u);
-            if (lane == 0) sCnt[slab][0] = (u32)__popcll(ub);
+            int d = t - 1 - lastv[k];
+            d = d < 0 ? 0 : (d > dmax ? dmax : d);
+            const float wd = d > 0 ? Wrow[d] : 0.0f;
+            u32 undecided = 0;
+            const RowPre pre = classify_pre(g, wd, cams[0].band);
             for (int c = 0; c < C; ++c) {
-                const u64 cb = __ballot((mk >> c) & 1u);
-                if (lane == 0) sCnt[slab][1 + c] = (u32)__popcll(cb);
+                const int cls = a.mode == 1 ? classify_cam(g, pre, cams[c].cam, cams[c].band) : 2;
+                if (cls == 1) mk |= 1u << c;
+                else if (cls == 2) undecided |= 1u << c;
             }
-        }
-        __syncthreads();
-        if (tid < 1 + C) {
-            u32 o = 0;
-            for (int sl = 0; sl < NSLAB; ++sl) {
-                sOff[sl][tid] = o;
-                o += sCnt[sl][tid];
-            }
-            sAgg[tid] = o;
-        }
-        __syncthreads();
-
-        // decoupled look-back over 1 + C counters by wave 0.  Every (tile,
-        // counter) pair has its own 64-bit word holding flag and count, so each
-        // word is self-validating and relaxed agent-scope atomics suffice (no
-        // payload is published behind a flag; acquire/release would write back
-        // or invalidate the whole L2).  Lanes walk 64 predecessors at a time;
-        // each counter stops at its nearest inclusive word.  Lane j ends up
-        // holding the exclusive prefix of counter j.
-        if (wave == 0) {
-            const int ncnt = 1 + C;
-            u64 *mine = st + (size_t)tile * kNCnt;
-            const u32 agg = lane < ncnt ? sAgg[lane] : 0u;
-            if (lane < ncnt)
-                __hip_atomic_store(&mine[lane], (tile == 0 ? kFlagInc : kFlagAgg) | (u64)agg, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-            u32 excl = 0;
-            if (tile > 0) {
-                u64 pending = (ncnt >= 64) ? ~0ull : ((1ull << ncnt) - 1ull);
-                int64_t base = (int64_t)tile - 1;
-                while (pending) {
-                    const int64_t idx = base - lane;
-                    u64 still = pending;
-                    for (int j0 = 0; j0 < ncnt; j0 += kLookChunk) {
-                        u64 w[kLookChunk];
-#pragma unroll
-                        for (int q = 0; q < kLookChunk; ++q) {
-                            const int j = j0 + q;
-                            w[q] = kFlagInc;  // before the first tile: inclusive zero
-                            if (j < ncnt && ((pending >> j) & 1ull) && idx >= 0)
-                                w[q] = __hip_atomic_load(&st[(size_t)idx * kNCnt + j], __ATOMIC_RELAXED,
-                                                         __HIP_MEMORY_SCOPE_AGENT);
+            if (undecided) {
+                if (d > 0) {
+                    const int64_t row = row0 + r;
+                    float mv[10], vv[10];
+                    if (a.gst == GS_F32) {
+                        for (int j = 0; j < 10; ++j) {
+                            mv[j] = mom_load<GS_F32>(a.gm, row, j, false);
+                            vv[j] = mom_load<GS_F32>(a.gv, row, j, true);
                         }
-#pragma unroll
-                        for (int q = 0; q < kLookChunk; ++q) {
-                            const int j = j0 + q;
-                            if (j >= ncnt || !((pending >> j) & 1ull)) continue;
-                            u64 x = w[q];
-                            u32 spins = 0;
-                            while ((x >> 62) == 0 && spins < kSpinLimit) {
-                                __builtin_amdgcn_s_sleep(1);
-                                x = __hip_atomic_load(&st[(size_t)idx * kNCnt + j], __ATOMIC_RELAXED,
-                                                      __HIP_MEMORY_SCOPE_AGENT);
-                                ++spins;
-                            }
-                            if ((x >> 62) == 0) {
-                                atomicOr(&a.hdr->error, 1u);
-                                x = kFlagInc;  // treated as an inclusive zero
-                            }
-                            const u64 incm = __ballot((x >> 62) == 2);
-                            const int stop = incm ? __builtin_ctzll(incm) : 63;
-                            const u64 sum = wave_sum_u64(lane <= stop ? (x & kValMask) : 0ull);
-                            if (lane == j) excl += (u32)sum;
-                            if (incm) still &= ~(1ull << j);
+                    } else if (a.gst == GS_BF16) {
+                        for (int j = 0; j < 10; ++j) {
+                            mv[j] = mom_load<GS_BF16>(a.gm, row, j, false);
+                            vv[j] = mom_load<GS_BF16>(a.gv, row, j, true);
+                        }
+                    } else {
+                        for (int j = 0; j < 10; ++j) {
+                            mv[j] = mom_load<GS_FP8E4M3>(a.gm, row, j, false);
+                            vv[j] = mom_load<GS_FP8E4M3>(a.gv, row, j, true);
                         }
                     }
-                    pending = still;
-                    base -= 64;
+                    for (int j = 0; j < 10; ++j) g[j] = restore1(g[j], mv[j], vv[j], wd, a.lr[j], a.eps, a.rb);
                 }
-                if (lane < ncnt)
-                    __hip_atomic_store(&mine[lane], kFlagInc | (u64)(excl + agg), __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-            }
-            if (lane < ncnt) sExcl[lane] = excl;
-            // the next call uses the other half, whatever its tile size: clear all of it
-            const int64_t words = a.stride * kNCnt;
-            for (int64_t j = (int64_t)tile * 64 + lane; j < words; j += 64 * a.tiles) st_other[j] = 0ull;
-            if (lane < ncnt) {
-                if (row0 == a.scene_row0[scene]) a.scene_start[(int64_t)scene * (1 + C) + lane] = excl;
-                if ((int64_t)tile == a.tiles - 1) {
-                    if (lane == 0) *a.union_count = excl + agg;
-                    else a.cam_count[lane - 1] = excl + agg;
-                }
+                for (int c = 0; c < C; ++c)
+                    if (((undecided >> c) & 1u) && cull_v1(g, cams[c].cam)) mk |= 1u << c;
             }
         }
-        __syncthreads();
-
-        const u32 eu = sExcl[0];
-#pragma unroll
-        for (int k = 0; k < IPT; ++k) {
-            const u32 mk = mask[k];
-            const int slab = k * NW + wave;
-            const u64 ub = __ballot(mk != 0u);
-            const u32 p = eu + sOff[slab][0] + lane_rank(ub);
-            if (mk && p < a.cap_union) a.union_ids[p] = (u32)(row0 + k * BLOCK + tid);
-            for (int c = 0; c < C; ++c) {
-                const bool on = (mk >> c) & 1u;
-                const u64 cb = __ballot(on);
-                if (on) {
-                    const u32 q = sExcl[1 + c] + sOff[slab][1 + c] + lane_rank(cb);
-                    if (q < a.cap_cam) a.cam_pos[(size_t)c * a.cap_cam + q] = p;
-                }
-            }
+        if (r < rows) a.mask[row0 + r] = mk;
+        const int slab = k * NW + wave;
+        const u64 ub = __ballot(mk != 0u);
+        if (lane == 0) sCnt[slab][0] = (u32)__popcll(ub);
+        for (int c = 0; c < C; ++c) {
+            const u64 cb = __ballot((mk >> c) & 1u);
+            if (lane == 0) sCnt[slab][1 + c] = (u32)__popcll(cb);
         }
     }
-
     __syncthreads();
-    if (tid == 0) {
-        // the last block to finish resets the header (every other block has
-        // already taken its last ticket)
-        const u64 prev = __hip_atomic_fetch_add(&a.hdr->done_rest, 1ull << 40, __ATOMIC_RELAXED,
-                                                __HIP_MEMORY_SCOPE_AGENT);
-        if ((prev >> 40) == gridDim.x - 1) {
-            if (a.tiles == 0) {
-                *a.union_count = 0;
-                for (int c = 0; c < C; ++c) a.cam_count[c] = 0;
+    if (tid < 1 + C) {
+        u32 o = 0;
+        for (int sl = 0; sl < NSLAB; ++sl) o += sCnt[sl][tid];
+        a.cnt[(int64_t)tid * a.stride + tile] = o;
+    }
+}
+
+// Exclusive prefixes over tiles of every counter (one block), totals and the
+// scene starts.
+__global__ __launch_bounds__(kScanThreads) void k_multi_scan(MultiArgs a)
+{
+    __shared__ u64 sWave[kScanThreads / 64 + 1];
+    const int tid = threadIdx.x;
+    const int64_t per = (a.tiles + kScanThreads - 1) / kScanThreads;
+    const int64_t t0 = min((int64_t)tid * per, a.tiles), t1 = min(t0 + per, a.tiles);
+    const int C = a.C;
+    for (int j = 0; j < 1 + C; ++j) {
+        const u32 *cj = a.cnt + (int64_t)j * a.stride;
+        u32 *oj = a.off + (int64_t)j * a.stride;
+        constexpr int kIlp = 8;
+        u64 sum = 0;
+        for (int64_t i0 = t0; i0 < t1; i0 += kIlp) {
+            u32 c[kIlp];
+#pragma unroll
+            for (int q = 0; q < kIlp; ++q) c[q] = i0 + q < t1 ? cj[i0 + q] : 0u;
+#pragma unroll
+            for (int q = 0; q < kIlp; ++q) sum += c[q];
+        }
+        u64 tot = 0;
+        u64 run = block_excl_scan_u64(sum, sWave, &tot);
+        for (int64_t i0 = t0; i0 < t1; i0 += kIlp) {
+            u32 c[kIlp];
+#pragma unroll
+            for (int q = 0; q < kIlp; ++q) c[q] = i0 + q < t1 ? cj[i0 + q] : 0u;
+#pragma unroll
+            for (int q = 0; q < kIlp; ++q) {
+                if (i0 + q < t1) oj[i0 + q] = (u32)run;
+                run += c[q];
             }
-            a.hdr->done_rest = 0;
-            a.hdr->ticket = 0;
-            a.hdr->parity = parity ^ 1u;
+        }
+        if (tid == 0) {
+            if (j == 0) *a.union_count = (u32)tot;
+            else a.cam_count[j - 1] = (u32)tot;
+        }
+        __syncthreads();   // sWave is reused by the next counter
+    }
+}
+
+template <int BLOCK, int IPT>
+__global__ __launch_bounds__(BLOCK) void k_multi_ids(MultiArgs a)
+{
+    constexpr int NW = BLOCK / 64;
+    constexpr int TR = BLOCK * IPT;
+    constexpr int NSLAB = IPT * NW;
+    __shared__ u32 sCnt[NSLAB][kNCnt];
+    __shared__ u32 sOff[NSLAB][kNCnt];
+    __shared__ u32 sScene;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int C = a.C;
+    const int64_t tile = blockIdx.x;
+    const int64_t row0 = tile * TR;
+    const int rows = (int)min((int64_t)TR, a.n - row0);
+    if (tid == 0) {
+        int sc = 0;
+        while (sc + 1 < a.S && a.scene_row0[sc + 1] <= row0) ++sc;
+        sScene = (u32)sc;
+    }
+    u32 mask[IPT];
+#pragma unroll
+    for (int k = 0; k < IPT; ++k) {
+        const int r = k * BLOCK + tid;
+        const u32 mk = r < rows ? a.mask[row0 + r] : 0u;
+        mask[k] = mk;
+        const int slab = k * NW + wave;
+        const u64 ub = __ballot(mk != 0u);
+        if (lane == 0) sCnt[slab][0] = (u32)__popcll(ub);
+        for (int c = 0; c < C; ++c) {
+            const u64 cb = __ballot((mk >> c) & 1u);
+            if (lane == 0) sCnt[slab][1 + c] = (u32)__popcll(cb);
+        }
+    }
+    __syncthreads();
+    if (tid < 1 + C) {
+        u32 o = a.off[(int64_t)tid * a.stride + tile];
+        const int scene = (int)sScene;
+        if (row0 == a.scene_row0[scene]) a.scene_start[(int64_t)scene * (1 + C) + tid] = o;
+        for (int sl = 0; sl < NSLAB; ++sl) {
+            sOff[sl][tid] = o;
+            o += sCnt[sl][tid];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < IPT; ++k) {
+        const u32 mk = mask[k];
+        const int slab = k * NW + wave;
+        const u64 ub = __ballot(mk != 0u);
+        const u32 p = sOff[slab][0] + lane_rank(ub);
+        if (mk && p < a.cap_union) a.union_ids[p] = (u32)(row0 + k * BLOCK + tid);
+        for (int c = 0; c < C; ++c) {
+            const bool on = (mk >> c) & 1u;
+            const u64 cb = __ballot(on);
+            if (on) {
+                const u32 q = sOff[slab][1 + c] + lane_rank(cb);
+                if (q < a.cap_cam) a.cam_pos[(size_t)c * a.cap_cam + q] = p;
+            }
         }
     }
 }
@@ -1568,7 +1597,7 @@ constexpr int kMultiIpt[kMultiVariants] = {1, 2, 4, 1, 2, 4};
 int64_t multi_ws_bytes(int64_t n)
 {
     const int64_t tiles = (n + kMultiMinTile - 1) / kMultiMinTile;
-    return gsdp::kWsHeader + 2 * tiles * kNCnt * 8;
+    return gsdp::kWsHeader + 2 * tiles * kNCnt * 4 + 4 * ((n + 1) / 2 * 2);
 }
 
 int multi_args(const gs_model *model, const gs_multi *d, int64_t step, void *ws, size_t ws_bytes, MultiArgs &a)
@@ -1608,9 +1637,10 @@ int multi_args(const gs_model *model, const gs_multi *d, int64_t step, void *ws,
     a.cap_cam = d->cap_cam;
     a.scene_start = d->scene_start;
     char *wsb = static_cast<char *>(ws);
-    a.hdr = reinterpret_cast<gsdp::WsHeader *>(wsb);
     const int64_t max_tiles = (model->n + kMultiMinTile - 1) / kMultiMinTile;
-    a.st = reinterpret_cast<u64 *>(wsb + gsdp::kWsHeader);
+    a.cnt = reinterpret_cast<u32 *>(wsb + gsdp::kWsHeader);
+    a.off = a.cnt + max_tiles * kNCnt;
+    a.mask = a.off + max_tiles * kNCnt;
     a.tiles = max_tiles;  // replaced per variant in launch_multi
     return GS_OK;
 }
@@ -1623,8 +1653,10 @@ void launch_multi_t(MultiArgs a, int64_t n, int64_t max_tiles, hipStream_t st)
     constexpr int TR = BLOCK * IPT;
     a.tiles = (n + TR - 1) / TR;
     a.stride = max_tiles;
-    const int64_t grid = a.tiles < 1 ? 1 : a.tiles;
-    hipLaunchKernelGGL((k_cull_multi<BLOCK, IPT>), dim3((unsigned)grid), dim3(BLOCK), 0, st, a);
+    a.tile_rows = TR;
+    if (a.tiles > 0) hipLaunchKernelGGL((k_cull_multi<BLOCK, IPT>), dim3((unsigned)a.tiles), dim3(BLOCK), 0, st, a);
+    hipLaunchKernelGGL(k_multi_scan, dim3(1), dim3(kScanThreads), 0, st, a);
+    if (a.tiles > 0) hipLaunchKernelGGL((k_multi_ids<BLOCK, IPT>), dim3((unsigned)a.tiles), dim3(BLOCK), 0, st, a);
 }
 
 int launch_multi(int variant, const MultiArgs &a, int64_t n, hipStream_t st)
@@ -1718,7 +1750,7 @@ int gs_lut_build(double beta1, double beta2, int32_t max_steps, int32_t max_defe
 int gs_workspace_bytes(const gs_model *model, size_t *bytes)
 {
     if (!model || !bytes || model->n < 0 || model->max_defer < 0) return GS_EINVAL;
-    *bytes = (size_t)gsdp::ws_bytes_for(model->n, model->max_defer, model->geo_mode, has_fp8(model));
+    *bytes = (size_t)gsdp::ws_bytes_for(model->n, model->max_defer, has_fp8(model));
     return GS_OK;
 }
 
@@ -1731,7 +1763,7 @@ int gs_cull(const gs_model *model, const gs_camera *cam, int64_t step, uint32_t 
     if (!step_ok(model, step)) return GS_EINVAL;
     if (!(cam->fx > 0.0f && cam->fy > 0.0f) || cam->width <= 0 || cam->height <= 0) return GS_EINVAL;
     if (!aligned(ws, 256)) return GS_EINVAL;
-    if ((int64_t)ws_bytes < gsdp::ws_bytes_for(model->n, model->max_defer, model->geo_mode, has_fp8(model))) return GS_ESPACE;
+    if ((int64_t)ws_bytes < gsdp::ws_bytes_for(model->n, model->max_defer, has_fp8(model))) return GS_ESPACE;
 
     CullArgs a;
     memset(&a, 0, sizeof a);
@@ -1749,24 +1781,42 @@ int gs_cull(const gs_model *model, const gs_camera *cam, int64_t step, uint32_t 
     // to NaN) and a finite restore bound; otherwise the exact cull runs
     a.mode = (model->cull_mode == 1 && model->eps > 0.0 && std::isfinite(a.rb)) ? 1 : 0;
     pack_camera(model, cam, a.cam, a.band);
-    a.ids = ids;
-    a.count = count_dev;
-    a.cap = capacity;
-    char *wsb = static_cast<char *>(ws);
-    a.hdr = reinterpret_cast<gsdp::WsHeader *>(wsb);
-    a.tiles = gsdp::cull_tiles(model->n);
-    a.st = reinterpret_cast<u64 *>(wsb + gsdp::kWsHeader);
-    a.sat_ids = model->max_defer > 0 ? reinterpret_cast<u32 *>(wsb + gsdp::ws_sat_offset(model->n)) : nullptr;
     a.geo_dense = model->geo_mode == 1;
-    a.keep_bits = a.geo_dense ? reinterpret_cast<u64 *>(wsb + gsdp::ws_bits_offset(model->n, model->max_defer))
-                              : nullptr;
-
-    // one block per tile; blocks take tiles in ticket order, so a block only
-    // ever waits on tiles already claimed by running blocks
-    int64_t grid = a.tiles;
-    if (grid < 1) grid = 1;
-    if (grid > 0x7fffffff) return GS_EINVAL;
-    hipLaunchKernelGGL(k_cull, dim3((unsigned)grid), dim3(kCullBlock), 0, (hipStream_t)stream, a);
+    a.K = model->max_defer;
+    char *wsb = static_cast<char *>(ws);
+    const int64_t n = model->n;
+    a.tiles = gsdp::cull_tiles(n);
+    a.tile_cnt = reinterpret_cast<u32 *>(wsb + gsdp::ws_cnt_offset(n));
+    a.keep_bits = reinterpret_cast<u64 *>(wsb + gsdp::ws_keep_offset(n));
+    a.sat_bits = model->max_defer > 0 ? reinterpret_cast<u64 *>(wsb + gsdp::ws_satbits_offset(n)) : nullptr;
+    if (a.tiles > 0x7fffffff) return GS_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    if (a.tiles > 0) {
+        hipLaunchKernelGGL(k_cull, dim3((unsigned)a.tiles), dim3(kCullBlock), 0, st, a);
+        int rc1 = launched("gs_cull (tiles)");
+        if (rc1) return rc1;
+    }
+    ScanArgs sa;
+    sa.tile_cnt = a.tile_cnt;
+    sa.tile_off = reinterpret_cast<u32 *>(wsb + gsdp::ws_off_offset(n));
+    sa.tiles = a.tiles;
+    sa.count = count_dev;
+    sa.hdr = reinterpret_cast<gsdp::WsHeader *>(wsb);
+    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(kScanThreads), 0, st, sa);
+    int rc2 = launched("gs_cull (scan)");
+    if (rc2 || a.tiles == 0) return rc2;
+    IdsArgs ia;
+    ia.keep_bits = a.keep_bits;
+    ia.sat_bits = a.sat_bits;
+    ia.tile_off = sa.tile_off;
+    ia.tiles = a.tiles;
+    ia.n = n;
+    ia.ids = ids;
+    ia.cap = capacity;
+    ia.pad = 0;
+    ia.sat_ids = model->max_defer > 0 ? reinterpret_cast<u32 *>(wsb + gsdp::ws_sat_offset(n, model->max_defer))
+                                      : nullptr;
+    hipLaunchKernelGGL(k_tile_ids, dim3(row_grid(a.tiles * kRowUnroll)), dim3(256), 0, st, ia);
     return launched("gs_cull");
 }
 
@@ -1818,7 +1868,7 @@ int gs_adam_step_deferred(const gs_model *model, int64_t step, const uint32_t *i
     const bool geo_dense = model->geo_mode == 1;
     if (model->max_defer > 0 || (geo_dense && compact) || has_fp8(model)) {
         if (!ws || !aligned(ws, 256)) return GS_EINVAL;
-        if ((int64_t)ws_bytes < gsdp::ws_bytes_for(model->n, model->max_defer, model->geo_mode, has_fp8(model))) return GS_ESPACE;
+        if ((int64_t)ws_bytes < gsdp::ws_bytes_for(model->n, model->max_defer, has_fp8(model))) return GS_ESPACE;
     }
     RowArgs a;
     fill_rows(a, model);
@@ -1839,7 +1889,7 @@ int gs_adam_step_deferred(const gs_model *model, int64_t step, const uint32_t *i
     if (model->max_defer > 0) {
         char *wsb = static_cast<char *>(ws);
         a.sat_count = &reinterpret_cast<gsdp::WsHeader *>(wsb)->sat_total;
-        a.sat_ids = reinterpret_cast<const u32 *>(wsb + gsdp::ws_sat_offset(model->n));
+        a.sat_ids = reinterpret_cast<const u32 *>(wsb + gsdp::ws_sat_offset(model->n, model->max_defer));
         rows += model->n;
     }
     if (geo_dense && model->n > 0) {
@@ -1867,9 +1917,8 @@ int gs_adam_step_deferred(const gs_model *model, int64_t step, const uint32_t *i
         da.tiles = gsdp::cull_tiles(model->n);
         if (compact) {
             char *wsb = static_cast<char *>(ws);
-            da.hdr = reinterpret_cast<const gsdp::WsHeader *>(wsb);
-            da.st0 = reinterpret_cast<const u64 *>(wsb + gsdp::kWsHeader);
-            da.keep_bits = reinterpret_cast<const u64 *>(wsb + gsdp::ws_bits_offset(model->n, model->max_defer));
+            da.tile_off = reinterpret_cast<const u32 *>(wsb + gsdp::ws_off_offset(model->n));
+            da.keep_bits = reinterpret_cast<const u64 *>(wsb + gsdp::ws_keep_offset(model->n));
         }
         if (model->geo.state == GS_F32)
             hipLaunchKernelGGL(k_dense_geo<GS_F32>, dim3((unsigned)da.tiles), dim3(256), 0, (hipStream_t)stream, da);
@@ -1882,7 +1931,7 @@ int gs_adam_step_deferred(const gs_model *model, int64_t step, const uint32_t *i
         // pass 1: per-block max of the new moments that outgrow their scale
         char *wsb = static_cast<char *>(ws);
         const int64_t nb = gsdp::fp8_blocks(model->n);
-        u32 *mx = reinterpret_cast<u32 *>(wsb + gsdp::ws_fp8_offset(model->n, model->max_defer, model->geo_mode));
+        u32 *mx = reinterpret_cast<u32 *>(wsb + gsdp::ws_fp8_offset(model->n, model->max_defer));
         for (int k = 0; k < 4; ++k) a.fp8max[k] = mx + k * nb;
         launch_rows<kAdamMax>(model, row_grid(rows), (hipStream_t)stream, a);
         int rc1 = launched("gs_adam_step_deferred (fp8 max pass)");
@@ -1906,7 +1955,8 @@ int gs_adam_step_deferred(const gs_model *model, int64_t step, const uint32_t *i
         ra.nb = nb;
         ra.sr_seed = model->sr_seed;
         ra.step = step_k(model, step);
-        hipLaunchKernelGGL(k_fp8_rescale, dim3(row_grid(4 * nb * kRowUnroll)), dim3(256), 0, (hipStream_t)stream, ra);
+        hipLaunchKernelGGL(k_fp8_rescale, dim3(row_grid(4 * nb * kRowUnroll / 64 + 1)), dim3(256), 0,
+                           (hipStream_t)stream, ra);
         rc1 = launched("gs_adam_step_deferred (fp8 rescale)");
         if (rc1) return rc1;
     }

@@ -38,41 +38,40 @@ constexpr int kCullBlock = 256;
 constexpr int kCullIpt = 2;
 constexpr int kCullTile = kCullBlock * kCullIpt;
 
-// Workspace layout (bytes): header | tile states [2][tiles] (u64) | saturated ids [n] (u32,
-// max_defer > 0) | keep ballots [tiles][8] (u64, dense-geometry mode)
+// Workspace layout (bytes): header | tile counts [tiles][4] (u32) | tile prefixes
+// [tiles][2] (u32) | keep ballots [tiles][8] (u64) | saturated ballots [tiles][8]
+// (u64, max_defer > 0) | saturated ids [n] (u32, max_defer > 0) | FP8 block maxima
 constexpr int64_t kWsHeader = 256;
 struct WsHeader {
-    uint32_t ticket;     // next cull tile to hand out
-    uint32_t parity;     // which tile-state buffer the next cull uses
-    uint32_t error;      // bit 0: a look-back wait hit its bound
-    uint32_t sat_total;  // saturated rows listed by the last cull
-    // blocks finished (bits 40..63) and rows restored (bits 0..39) by the running
-    // cull, in one word so a single atomic orders them; the last block resets it
-    unsigned long long done_rest;
-    uint32_t restored_last;  // rows restored by the last completed cull
-    uint32_t pad_;
-    unsigned long long vis_accum;       // visible rows summed over all completed culls
-    unsigned long long restored_accum;  // restored rows summed over all completed culls
+    uint32_t vis_total;      // visible rows of the last cull
+    uint32_t sat_total;      // saturated rows listed by the last cull
+    uint32_t restored_last;  // rows restored by the last cull
+    uint32_t error;          // reserved, 0
+    unsigned long long vis_accum;       // visible rows summed over all culls
+    unsigned long long restored_accum;  // restored rows summed over all culls
 };
-static_assert(sizeof(WsHeader) == 48, "workspace header layout");
+static_assert(sizeof(WsHeader) == 32, "workspace header layout");
 
 inline int64_t cull_tiles(int64_t n) { return (n + kCullTile - 1) / kCullTile; }
 constexpr int kWordsPerTile = kCullTile / 64;
-inline int64_t ws_sat_offset(int64_t n) { return kWsHeader + 16 * cull_tiles(n); }
-inline int64_t ws_bits_offset(int64_t n, int32_t K)
+inline int64_t ws_cnt_offset(int64_t) { return kWsHeader; }
+inline int64_t ws_off_offset(int64_t n) { return kWsHeader + 16 * cull_tiles(n); }
+inline int64_t ws_keep_offset(int64_t n) { return ws_off_offset(n) + 8 * cull_tiles(n); }
+inline int64_t ws_satbits_offset(int64_t n) { return ws_keep_offset(n) + 8 * kWordsPerTile * cull_tiles(n); }
+inline int64_t ws_sat_offset(int64_t n, int32_t K)
 {
-    int64_t b = ws_sat_offset(n) + (K > 0 ? 4 * n : 0);
-    return (b + 7) / 8 * 8;
+    return ws_satbits_offset(n) + (K > 0 ? 8 * kWordsPerTile * cull_tiles(n) : 0);
 }
 inline int64_t fp8_blocks(int64_t n) { return (n + 127) / 128; }
-inline int64_t ws_fp8_offset(int64_t n, int32_t K, int32_t geo_dense)
+inline int64_t ws_fp8_offset(int64_t n, int32_t K)
 {
-    return ws_bits_offset(n, K) + (geo_dense ? 8 * kWordsPerTile * cull_tiles(n) : 0);
+    const int64_t b = ws_sat_offset(n, K) + (K > 0 ? 4 * n : 0);
+    return (b + 7) / 8 * 8;
 }
 // fp8: per-block max arrays for G m, G v, A m, A v (u32 each)
-inline int64_t ws_bytes_for(int64_t n, int32_t K, int32_t geo_dense, int32_t fp8)
+inline int64_t ws_bytes_for(int64_t n, int32_t K, int32_t fp8)
 {
-    int64_t b = ws_fp8_offset(n, K, geo_dense) + (fp8 ? 16 * fp8_blocks(n) : 0);
+    const int64_t b = ws_fp8_offset(n, K) + (fp8 ? 16 * fp8_blocks(n) : 0);
     return (b + 255) / 256 * 256;
 }
 

@@ -295,12 +295,10 @@ class Model:
         return self.ws.numel() * 4
 
     def ws_header(self) -> dict:
-        h = self.ws[:12].cpu().numpy().view(np.uint32)
-        q = h[8:12].view(np.uint64)
-        dr = int(h[4]) | (int(h[5]) << 32)
-        return {"ticket": int(h[0]), "done": dr >> 40, "parity": int(h[1]), "error": int(h[2]),
-                "sat_total": int(h[3]), "restored_last": int(h[6]), "vis_accum": int(q[0]),
-                "restored_accum": int(q[1])}
+        h = self.ws[:8].cpu().numpy().view(np.uint32)
+        q = h[4:8].view(np.uint64)
+        return {"vis_total": int(h[0]), "sat_total": int(h[1]), "restored_last": int(h[2]), "error": int(h[3]),
+                "vis_accum": int(q[0]), "restored_accum": int(q[1])}
 
     def state(self):
         """Host copies: geo/app w (float32), m, v (float32 or raw uint16 BF16 bits) and last_step."""
