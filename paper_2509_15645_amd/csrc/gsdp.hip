@@ -431,7 +431,8 @@ struct CullArgs {
     int32_t pad4;
     u64 *keep_bits;                  // [tiles][8] keep ballots of the tile's 64-row slabs
     u64 *sat_bits;                   // [tiles][8] saturated ballots (K > 0)
-    u32 *tile_cnt;                   // [tiles][4] visible, saturated, restored, 0
+    u64 *tile_vs;                    // [tiles] visible << 32 | saturated
+    u32 *tile_rest;                  // [tiles] restored rows
     int64_t tiles;
 };
 
@@ -536,27 +537,27 @@ __global__ __launch_bounds__(kCullBlock) void k_cull(CullArgs a)
             sv += sCntV[e];
             ss += sCntS[e];
         }
-        uint4 c;
-        c.x = sv;
-        c.y = ss;
-        c.z = sRestored;
-        c.w = 0;
-        reinterpret_cast<uint4 *>(a.tile_cnt)[tile] = c;
+        a.tile_vs[tile] = ((u64)sv << 32) | (u64)ss;
+        a.tile_rest[tile] = sRestored;
     }
 }
 
-// Exclusive prefix of (visible, saturated) over tiles by one block: each
-// thread owns a contiguous run of tiles.  Writes tile_off[tile] = (visible,
-// saturated) before the tile, the totals (count, header) and the diagnostics.
+// Exclusive prefix of (visible, saturated) over tiles by one block.  Tiles
+// go through LDS in chunks of kScanChunk: coalesced loads into LDS, then each
+// thread scans a contiguous run of 8 from LDS, a block scan of the 1024 run
+// sums, and coalesced stores of the prefixes; a carry links the chunks.
 struct ScanArgs {
-    const u32 *tile_cnt;             // [tiles][4]
-    u32 *tile_off;                   // [tiles][2]
+    const u64 *tile_vs;              // [tiles] visible << 32 | saturated
+    const u32 *tile_rest;            // [tiles]
+    u64 *tile_off;                   // [tiles] exclusive prefix, same packing
     int64_t tiles;
     u32 *count;                      // visible total (device, the caller's count)
     gsdp::WsHeader *hdr;
 };
 
 constexpr int kScanThreads = 1024;
+constexpr int kScanPer = 7;           // 56 KB of LDS per chunk
+constexpr int kScanChunk = kScanThreads * kScanPer;
 
 __device__ __forceinline__ u64 block_excl_scan_u64(u64 x, u64 *sWave, u64 *total)
 {
@@ -581,48 +582,55 @@ __device__ __forceinline__ u64 block_excl_scan_u64(u64 x, u64 *sWave, u64 *total
     }
     __syncthreads();
     *total = sWave[kScanThreads / 64];
-    return sWave[wave] + inc - x;
+    const u64 r = sWave[wave] + inc - x;
+    __syncthreads();                 // sWave may be reused by the caller's next scan
+    return r;
 }
 
 __global__ __launch_bounds__(kScanThreads) void k_tile_scan(ScanArgs a)
 {
+    __shared__ u64 sV[kScanChunk];
     __shared__ u64 sWave[kScanThreads / 64 + 1];
-    __shared__ u64 sRest[kScanThreads / 64 + 1];
     const int tid = threadIdx.x;
-    const int64_t per = (a.tiles + kScanThreads - 1) / kScanThreads;
-    const int64_t t0 = min((int64_t)tid * per, a.tiles), t1 = min(t0 + per, a.tiles);
-    const uint4 *cnt = reinterpret_cast<const uint4 *>(a.tile_cnt);
-    constexpr int kIlp = 8;          // independent loads in flight per thread
-    u64 vs = 0, rest = 0;
-    for (int64_t i0 = t0; i0 < t1; i0 += kIlp) {
-        uint4 c[kIlp];
+    u64 carry = 0, rest = 0;
+    for (int64_t c0 = 0; c0 < a.tiles; c0 += kScanChunk) {
+        const int64_t nc = min((int64_t)kScanChunk, a.tiles - c0);
 #pragma unroll
-        for (int q = 0; q < kIlp; ++q) c[q] = i0 + q < t1 ? cnt[i0 + q] : make_uint4(0, 0, 0, 0);
-#pragma unroll
-        for (int q = 0; q < kIlp; ++q) {
-            vs += ((u64)c[q].x << 32) | (u64)c[q].y;
-            rest += c[q].z;
+        for (int q = 0; q < kScanPer; ++q) {
+            const int64_t i = (int64_t)q * kScanThreads + tid;
+            sV[i] = i < nc ? a.tile_vs[c0 + i] : 0ull;
+            if (i < nc) rest += a.tile_rest[c0 + i];
         }
-    }
-    u64 tot = 0, rtot = 0;
-    u64 run = block_excl_scan_u64(vs, sWave, &tot);
-    block_excl_scan_u64(rest, sRest, &rtot);
-    uint2 *off = reinterpret_cast<uint2 *>(a.tile_off);
-    for (int64_t i0 = t0; i0 < t1; i0 += kIlp) {
-        uint4 c[kIlp];
+        __syncthreads();
+        u64 v[kScanPer], sum = 0;
 #pragma unroll
-        for (int q = 0; q < kIlp; ++q) c[q] = i0 + q < t1 ? cnt[i0 + q] : make_uint4(0, 0, 0, 0);
-#pragma unroll
-        for (int q = 0; q < kIlp; ++q) {
-            if (i0 + q < t1) off[i0 + q] = make_uint2((u32)(run >> 32), (u32)run);
-            run += ((u64)c[q].x << 32) | (u64)c[q].y;
+        for (int q = 0; q < kScanPer; ++q) {
+            v[q] = sV[tid * kScanPer + q];
+            sum += v[q];
         }
+        u64 tot = 0;
+        u64 run = carry + block_excl_scan_u64(sum, sWave, &tot);
+#pragma unroll
+        for (int q = 0; q < kScanPer; ++q) {
+            sV[tid * kScanPer + q] = run;
+            run += v[q];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kScanPer; ++q) {
+            const int64_t i = (int64_t)q * kScanThreads + tid;
+            if (i < nc) a.tile_off[c0 + i] = sV[i];
+        }
+        carry += tot;
+        __syncthreads();             // sV is refilled by the next chunk
     }
+    u64 rtot = 0;
+    block_excl_scan_u64(rest, sWave, &rtot);
     if (tid == 0) {
-        const u32 vis = (u32)(tot >> 32);
+        const u32 vis = (u32)(carry >> 32);
         *a.count = vis;
         a.hdr->vis_total = vis;
-        a.hdr->sat_total = (u32)tot;
+        a.hdr->sat_total = (u32)carry;
         a.hdr->restored_last = (u32)rtot;
         a.hdr->vis_accum += vis;
         a.hdr->restored_accum += rtot;
@@ -633,7 +641,7 @@ __global__ __launch_bounds__(kScanThreads) void k_tile_scan(ScanArgs a)
 // the tile's ballots and exclusive prefix.
 struct IdsArgs {
     const u64 *keep_bits, *sat_bits;
-    const u32 *tile_off;
+    const u64 *tile_off;             // visible << 32 | saturated before the tile
     int64_t tiles, n;
     u32 *ids;
     u32 cap, pad;
@@ -648,13 +656,13 @@ __global__ __launch_bounds__(256) void k_tile_ids(IdsArgs a)
     const u64 lt = (1ull << lane) - 1ull;
     for (int64_t tile = wid; tile < a.tiles; tile += nw) {
         const int64_t row0 = tile * kCullTile;
-        const uint2 o = reinterpret_cast<const uint2 *>(a.tile_off)[tile];
+        const u64 o = a.tile_off[tile];
         u64 kw = 0, sw = 0;
         if (lane < gsdp::kWordsPerTile) {
             kw = a.keep_bits[tile * gsdp::kWordsPerTile + lane];
             if (a.sat_ids) sw = a.sat_bits[tile * gsdp::kWordsPerTile + lane];
         }
-        u32 pv = o.x, ps = o.y;
+        u32 pv = (u32)(o >> 32), ps = (u32)o;
 #pragma unroll
         for (int sl = 0; sl < gsdp::kWordsPerTile; ++sl) {
             const u64 bv = (u64)__shfl((long long)kw, sl);
@@ -959,7 +967,7 @@ struct DenseArgs {
     u64 sr_seed;
     const float *g_geo;              // compact gradients of the cull's visible rows, or NULL
     const u64 *keep_bits;            // the cull's keep ballots
-    const u32 *tile_off;             // the cull's tile prefixes [tiles][2]
+    const u64 *tile_off;             // the cull's tile prefixes (visible << 32 | saturated)
     int64_t tiles;
     u32 cap, pad2;
     float *gd_geo;                   // dense [n][10] gradients (read and cleared) when g_geo is NULL
@@ -980,7 +988,7 @@ __global__ __launch_bounds__(256) void k_dense_geo(DenseArgs a)
     const int rows = (int)min((int64_t)kCullTile, a.n - row0);
     if (a.g_geo) {
         if (tid < gsdp::kWordsPerTile) sBits[tid] = a.keep_bits[tile * gsdp::kWordsPerTile + tid];
-        if (tid == 0) sExcl = a.tile_off[2 * tile];
+        if (tid == 0) sExcl = (u32)(a.tile_off[tile] >> 32);
         __syncthreads();
         if (tid == 0) {
             u32 o = 0;
@@ -1786,7 +1794,8 @@ int gs_cull(const gs_model *model, const gs_camera *cam, int64_t step, uint32_t 
     char *wsb = static_cast<char *>(ws);
     const int64_t n = model->n;
     a.tiles = gsdp::cull_tiles(n);
-    a.tile_cnt = reinterpret_cast<u32 *>(wsb + gsdp::ws_cnt_offset(n));
+    a.tile_vs = reinterpret_cast<u64 *>(wsb + gsdp::ws_cnt_offset(n));
+    a.tile_rest = reinterpret_cast<u32 *>(wsb + gsdp::ws_cnt_offset(n) + 8 * a.tiles);
     a.keep_bits = reinterpret_cast<u64 *>(wsb + gsdp::ws_keep_offset(n));
     a.sat_bits = model->max_defer > 0 ? reinterpret_cast<u64 *>(wsb + gsdp::ws_satbits_offset(n)) : nullptr;
     if (a.tiles > 0x7fffffff) return GS_EINVAL;
@@ -1797,8 +1806,9 @@ int gs_cull(const gs_model *model, const gs_camera *cam, int64_t step, uint32_t 
         if (rc1) return rc1;
     }
     ScanArgs sa;
-    sa.tile_cnt = a.tile_cnt;
-    sa.tile_off = reinterpret_cast<u32 *>(wsb + gsdp::ws_off_offset(n));
+    sa.tile_vs = a.tile_vs;
+    sa.tile_rest = a.tile_rest;
+    sa.tile_off = reinterpret_cast<u64 *>(wsb + gsdp::ws_off_offset(n));
     sa.tiles = a.tiles;
     sa.count = count_dev;
     sa.hdr = reinterpret_cast<gsdp::WsHeader *>(wsb);
@@ -1917,7 +1927,7 @@ int gs_adam_step_deferred(const gs_model *model, int64_t step, const uint32_t *i
         da.tiles = gsdp::cull_tiles(model->n);
         if (compact) {
             char *wsb = static_cast<char *>(ws);
-            da.tile_off = reinterpret_cast<const u32 *>(wsb + gsdp::ws_off_offset(model->n));
+            da.tile_off = reinterpret_cast<const u64 *>(wsb + gsdp::ws_off_offset(model->n));
             da.keep_bits = reinterpret_cast<const u64 *>(wsb + gsdp::ws_keep_offset(model->n));
         }
         if (model->geo.state == GS_F32)
