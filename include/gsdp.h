@@ -99,8 +99,18 @@ typedef struct gs_model {
                               split of Sec. 4.2.2 step 4 (appearance stays deferred) */
     uint64_t sr_seed;      /* seed of the stochastic-rounding stream of quantised moments */
     const int32_t *step_dev; /* device step counter used by calls with step == 0 */
-    int32_t reserved_[2];
+    int32_t optimizer;     /* GS_OPT_ADAM (default) or GS_OPT_SGD_MOMENTUM */
+    int32_t reserved_;
 } gs_model;
+
+/* Optimizers.  GS_OPT_SGD_MOMENTUM is the momentum-optimizer extension the
+ * paper names in Sec. 4.3: buf = beta1 buf + g, w -= lr buf (no dampening, no
+ * Nesterov; beta1 is the momentum, beta2/eps and the v buffers are unused).
+ * With zero gradients the buffer decays geometrically, so the deferred
+ * catch-up is exact.  It needs tables from gs_lut_build_sgd_momentum, FP32 or
+ * BF16 state, cull_mode 0 and geo_mode 0, and is not available in the batched
+ * form. */
+enum { GS_OPT_ADAM = 0, GS_OPT_SGD_MOMENTUM = 2 };
 
 /* ---------------------------------------------------------------- tables */
 
@@ -117,6 +127,15 @@ int gs_lut_bytes(int32_t max_steps, int32_t max_defer, size_t *bytes);
  * gs_lut_bytes bytes).  Synchronous: returns after the copy completed. */
 int gs_lut_build(double beta1, double beta2, int32_t max_steps, int32_t max_defer,
                  void *lut_dev, size_t bytes);
+
+/* Tables of deferred SGD with momentum (same layout and size as the Adam
+ * tables): W[t][d] = sum_{i=1..d} s[t-i] mu^(d+1-i) by the recurrence
+ * W[d] = mu (W[d-1] + s[t-d]); the first-moment table holds mu^(d+1), the step
+ * table s[t] (lr_scale may be NULL: s = 1), the others 1.  FP64, rounded once. */
+int gs_lut_build_sgd_momentum(double momentum, int32_t max_steps, int32_t max_defer, const double *lr_scale,
+                              void *lut_dev, size_t bytes);
+int gs_lut_build_sgd_momentum_host(double momentum, int32_t max_steps, int32_t max_defer, const double *lr_scale,
+                                   void *lut_host, size_t bytes);
 
 /* Same tables written to host memory (for inspection and tests). */
 int gs_lut_build_host(double beta1, double beta2, int32_t max_steps, int32_t max_defer,

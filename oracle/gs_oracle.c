@@ -682,3 +682,150 @@ void orc_flush_rows_fp8(int dim, float *w, uint8_t *mq, uint8_t *vq, const float
         }
     }
 }
+
+/* ------------------------------------------------------------------------ */
+/* SGD with momentum, the momentum-optimizer extension named in Sec. 4.3
+ * (heavy ball, no dampening, no Nesterov: buf = mu buf + g; w -= lr s_t buf,
+ * with s_t an optional per-step rate multiplier).  With g = 0 for d skipped
+ * steps the buffer decays as mu^j, so the skipped steps move w by
+ * lr buf Ws[d], Ws[d] = sum_{i=1..d} s_{t-i} mu^(d+1-i); this is exact (no eps
+ * term to factor out, unlike Adam's Eq. 3). */
+
+/* Dense definition: every row steps every update, g = 0 unless listed. */
+void orc_sgdm_dense_sparse_grad_f64(int64_t n, int dim, double *w, double *m, int64_t n_ids,
+                                    const uint32_t *ids, const float *g, const double *lr, double mu,
+                                    double s_t)
+{
+    double *gd = (double *)calloc((size_t)n * dim, sizeof(double));
+    for (int64_t j = 0; j < n_ids; ++j)
+        for (int k = 0; k < dim; ++k) gd[(int64_t)ids[j] * dim + k] = (double)g[j * dim + k];
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i)
+        for (int k = 0; k < dim; ++k) {
+            int64_t e = i * dim + k;
+            m[e] = mu * m[e] + gd[e];
+            w[e] = w[e] - (lr[k] * s_t) * m[e];
+        }
+    free(gd);
+}
+
+/* Tables of update t in FP64: Ws[d] by the recurrence Ws[d] = mu (Ws[d-1] +
+ * s_{t-d}), Mf[d] = mu^(d+1) by repeated multiplication. */
+void orc_lut_sgdm_f64(double mu, int64_t t, int dmax, const double *sched, double *Ws, double *Mf)
+{
+    Ws[0] = 0.0;
+    for (int d = 1; d <= dmax; ++d) Ws[d] = mu * (Ws[d - 1] + (sched ? sched[t - d] : 1.0));
+    double p = 1.0;
+    for (int d = 0; d <= dmax; ++d) {
+        p = p * mu;
+        Mf[d] = p;
+    }
+}
+
+/* The same tables rounded once to FP32, and the step multiplier s_t. */
+void orc_lut_sgdm_spec(double mu, int64_t t, int dmax, const double *sched, float *Wf, float *Mf, float *ss)
+{
+    double *W = (double *)malloc(sizeof(double) * (size_t)(dmax + 1));
+    double *M = (double *)malloc(sizeof(double) * (size_t)(dmax + 1));
+    orc_lut_sgdm_f64(mu, t, dmax, sched, W, M);
+    for (int d = 0; d <= dmax; ++d) {
+        Wf[d] = (float)W[d];
+        Mf[d] = (float)M[d];
+    }
+    *ss = sched ? (float)sched[t] : 1.0f;
+    free(W);
+    free(M);
+}
+
+/* Deferred update in FP64, the paper's order: catch up the d skipped steps,
+ * then take step t with the row's gradient. */
+void orc_sgdm_deferred_rows_f64(int dim, double *w, double *m, int64_t n_rows, const uint32_t *rows,
+                                const int64_t *d, const double *g, const double *lr, double s_t,
+                                const double *Ws, const double *Mf)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < n_rows; ++j) {
+        int64_t id = rows[j];
+        for (int k = 0; k < dim; ++k) {
+            int64_t e = id * dim + k;
+            double wk = w[e] - (lr[k] * Ws[d[j]]) * m[e];
+            double m1 = Mf[d[j]] * m[e] + g[j * dim + k];
+            w[e] = wk - (lr[k] * s_t) * m1;
+            m[e] = m1;
+        }
+    }
+}
+
+/* FP64 flush: delta skipped steps with the tables of update t+1. */
+void orc_sgdm_flush_rows_f64(int dim, double *w, double *m, int64_t n_rows, const uint32_t *rows,
+                             const int64_t *delta, const double *lr, const double *Ws_next, double mu)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < n_rows; ++j) {
+        int64_t id = rows[j];
+        for (int k = 0; k < dim; ++k) {
+            int64_t e = id * dim + k;
+            w[e] = w[e] - (lr[k] * Ws_next[delta[j]]) * m[e];
+            m[e] = m[e] * pow(mu, (double)delta[j]);
+        }
+    }
+}
+
+/* FP32 model with the spec's operation order: restore w - (Wf[d] lr) buf;
+ * buf1 = Mf[d] buf + g; w - (lr ss) buf1.  buf is stored FP32 or BF16 (stochastic
+ * rounding with bits 0..15 of the element's random word). */
+void orc_sgdm_rows_f32(int dim, float *w, void *m, int state, int64_t ld, int64_t n_rows, const uint32_t *rows,
+                       const int64_t *d, const float *g, int64_t g_ld, const float *lr, const float *Wf,
+                       const float *Mf, float ss, uint64_t seed, int64_t t, int col0)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < n_rows; ++j) {
+        int64_t id = rows[j];
+        int64_t dj = d[j];
+        for (int k = 0; k < dim; ++k) {
+            int64_t e = id * ld + k;
+            float wk = w[e], mk = mom_load(m, state, e);
+            float gk = g ? g[j * g_ld + k] : 0.0f;
+            if (dj > 0) wk = wk - (Wf[dj] * lr[k]) * mk;
+            float m1 = Mf[dj] * mk + gk;
+            w[e] = wk - (lr[k] * ss) * m1;
+            uint64_t r = state ? sr_bits(seed, t, id, col0 + k) : 0;
+            mom_store(m, state, e, m1, (uint32_t)(r & 0xffffu));
+        }
+    }
+}
+
+/* FP32 restore-only (gather and the cull's current geometry). */
+void orc_sgdm_restore_rows_f32(int dim, const float *w, const void *m, int state, int64_t ld, int64_t n_rows,
+                               const uint32_t *rows, const int64_t *d, const float *lr, const float *Wf, float *out)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < n_rows; ++j) {
+        int64_t id = rows[j];
+        for (int k = 0; k < dim; ++k) {
+            int64_t e = id * ld + k;
+            float wk = w[e];
+            if (d[j] > 0) wk = wk - (Wf[d[j]] * lr[k]) * mom_load(m, state, e);
+            out[j * dim + k] = wk;
+        }
+    }
+}
+
+/* FP32 flush after update t (tables of t+1). */
+void orc_sgdm_flush_rows_f32(int dim, float *w, void *m, int state, int64_t ld, int64_t n_rows,
+                             const uint32_t *rows, const int64_t *delta, const float *lr, const float *Wf_next,
+                             const float *Mf, uint64_t seed, int64_t t, int col0)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < n_rows; ++j) {
+        int64_t id = rows[j];
+        int64_t dl = delta[j];
+        for (int k = 0; k < dim; ++k) {
+            int64_t e = id * ld + k;
+            float mk = mom_load(m, state, e);
+            w[e] = w[e] - (Wf_next[dl] * lr[k]) * mk;
+            uint64_t r = state ? sr_bits(seed, t, id, col0 + k) : 0;
+            mom_store(m, state, e, Mf[dl - 1] * mk, (uint32_t)(r & 0xffffu));
+        }
+    }
+}

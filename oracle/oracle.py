@@ -79,6 +79,16 @@ def lib():
             "orc_restore_rows_f32": (None, [i32, vp, vp, vp, i32, i64, i64, vp, vp, vp, f64, vp, f32, vp]),
             "orc_flush_rows_f32": (None, [i32, vp, vp, vp, i32, i64, i64, vp, vp, vp, f64, vp, vp, vp, f32,
                                           C.c_uint64, i64, i32]),
+            "orc_sgdm_dense_sparse_grad_f64": (None, [i64, i32, vp, vp, i64, vp, vp, vp, f64, f64]),
+            "orc_lut_sgdm_f64": (None, [f64, i64, i32, vp, vp, vp]),
+            "orc_lut_sgdm_spec": (None, [f64, i64, i32, vp, vp, vp, vp]),
+            "orc_sgdm_deferred_rows_f64": (None, [i32, vp, vp, i64, vp, vp, vp, vp, f64, vp, vp]),
+            "orc_sgdm_flush_rows_f64": (None, [i32, vp, vp, i64, vp, vp, vp, vp, f64]),
+            "orc_sgdm_rows_f32": (None, [i32, vp, vp, i32, i64, i64, vp, vp, vp, i64, vp, vp, vp, f32,
+                                         C.c_uint64, i64, i32]),
+            "orc_sgdm_restore_rows_f32": (None, [i32, vp, vp, i32, i64, i64, vp, vp, vp, vp, vp]),
+            "orc_sgdm_flush_rows_f32": (None, [i32, vp, vp, i32, i64, i64, vp, vp, vp, vp, vp, C.c_uint64,
+                                               i64, i32]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -419,6 +429,149 @@ class DeferredF32(_Deferred):
             lib().orc_flush_rows_f32(dim, _p(self.w[k]), _p(self.m[k]), _p(self.v[k]), self.sid[k], dim,
                                      rows.shape[0], _p(rows32), _p(delta), _p(self.lr[k]), self.eps,
                                      _p(Wn), _p(Mf), _p(Vf), self.rb, self.sr_seed, t_done, self.col0[k])
+        self.counter[:] = 0
+
+
+# ---------------------------------------------------------------------------
+# SGD with momentum (the momentum-optimizer extension of Sec. 4.3)
+# ---------------------------------------------------------------------------
+def lut_sgdm(mu: float, t: int, dmax: int, sched=None):
+    """FP64 (Ws, Mf) of update t: Ws[d] = sum_{i=1..d} s_{t-i} mu^(d+1-i), Mf[d] = mu^(d+1)."""
+    W = np.zeros(dmax + 1); M = np.zeros(dmax + 1)
+    lib().orc_lut_sgdm_f64(mu, t, dmax, _p(_sched(sched)), _p(W), _p(M))
+    return W, M
+
+
+def lut_sgdm_spec(mu: float, t: int, dmax: int, sched=None):
+    """The same tables rounded once to FP32, and the step multiplier s_t."""
+    Wf = np.zeros(dmax + 1, np.float32); Mf = np.zeros(dmax + 1, np.float32)
+    ss = C.c_float()
+    lib().orc_lut_sgdm_spec(mu, t, dmax, _p(_sched(sched)), _p(Wf), _p(Mf), C.addressof(ss))
+    return Wf, Mf, np.float32(ss.value)
+
+
+class DenseSGDMF64:
+    """FP64 SGD with momentum on every row every step (g = 0 without a gradient)."""
+
+    def __init__(self, geo, app, lr_geo, lr_app, mu=0.9, sched=None):
+        self.w = [np.array(geo, np.float64), np.array(app, np.float64)]
+        self.m = [np.zeros_like(x) for x in self.w]
+        self.lr = [np.asarray(lr_geo, np.float64), np.asarray(lr_app, np.float64)]
+        self.mu = mu
+        self.sched = _sched(sched)
+
+    def step(self, t, ids, g_geo, g_app):
+        ids = np.ascontiguousarray(ids, np.uint32)
+        s = 1.0 if self.sched is None else float(self.sched[t])
+        for k, g in enumerate((g_geo, g_app)):
+            g = np.ascontiguousarray(g, np.float32)
+            lib().orc_sgdm_dense_sparse_grad_f64(self.w[k].shape[0], self.w[k].shape[1], _p(self.w[k]),
+                                                 _p(self.m[k]), ids.shape[0], _p(ids), _p(g),
+                                                 _p(self.lr[k]), self.mu, s)
+
+
+class DeferredSGDMF64(_Deferred):
+    """Deferred SGD with momentum in FP64, catch-up then step (paper order)."""
+
+    def __init__(self, geo, app, lr_geo, lr_app, mu=0.9, max_defer=0, sched=None):
+        super().__init__(geo.shape[0], max_defer)
+        self.w = [np.array(geo, np.float64), np.array(app, np.float64)]
+        self.m = [np.zeros_like(x) for x in self.w]
+        self.lr = [np.asarray(lr_geo, np.float64), np.asarray(lr_app, np.float64)]
+        self.mu = mu
+        self.sched = _sched(sched)
+
+    def step(self, t, valid, g_geo, g_app):
+        valid, sat = self.update_set(valid)
+        rows = np.ascontiguousarray(np.concatenate([valid, sat]), np.uint32)
+        d = np.ascontiguousarray(self.counter[rows.astype(np.int64)], np.int64)
+        W, M = lut_sgdm(self.mu, t, max(self.dmax(t), 0), self.sched)
+        s_t = 1.0 if self.sched is None else float(self.sched[t])
+        for k, g in enumerate((g_geo, g_app)):
+            dim = self.w[k].shape[1]
+            gg = np.zeros((rows.shape[0], dim))
+            gg[:valid.shape[0]] = np.asarray(g, np.float64)
+            lib().orc_sgdm_deferred_rows_f64(dim, _p(self.w[k]), _p(self.m[k]), rows.shape[0], _p(rows), _p(d),
+                                             _p(gg), _p(self.lr[k]), s_t, _p(W), _p(M))
+        self.bump(valid, sat)
+        return valid, sat
+
+    def flush(self, t_done):
+        rows = np.nonzero(self.counter > 0)[0]
+        if rows.shape[0] == 0:
+            return
+        delta = np.ascontiguousarray(self.counter[rows], np.int64)
+        W, _ = lut_sgdm(self.mu, t_done + 1, int(delta.max()), self.sched)
+        rows32 = np.ascontiguousarray(rows, np.uint32)
+        for k in range(2):
+            lib().orc_sgdm_flush_rows_f64(self.w[k].shape[1], _p(self.w[k]), _p(self.m[k]), rows.shape[0],
+                                          _p(rows32), _p(delta), _p(self.lr[k]), _p(W), self.mu)
+        self.counter[:] = 0
+
+
+class DeferredSGDMF32(_Deferred):
+    """Deferred SGD with momentum with FP32 math and the implementation's op
+    order; the momentum buffer stored FP32 or BF16 (stochastic rounding with
+    the same random stream as the Adam models)."""
+
+    def __init__(self, geo, app, lr_geo, lr_app, mu=0.9, max_defer=0, state="f32", app_state=None,
+                 sr_seed=0, sched=None):
+        super().__init__(geo.shape[0], max_defer)
+        states = [state, app_state or state]
+        assert all(x in ("f32", "bf16") for x in states)
+        self.sid = [STATES[x][0] for x in states]
+        self.w = [np.array(geo, np.float32), np.array(app, np.float32)]
+        self.m = [np.zeros(x.shape, STATES[st][1]) for x, st in zip(self.w, states)]
+        self.lr = [np.asarray(lr_geo, np.float32), np.asarray(lr_app, np.float32)]
+        self.mu = mu
+        self.sched = _sched(sched)
+        self.sr_seed = int(sr_seed)
+        self.col0 = [0, self.w[0].shape[1]]
+
+    def _restore(self, k, t, rows):
+        rows32 = np.ascontiguousarray(rows, np.uint32)
+        d = np.ascontiguousarray(self.counter[np.asarray(rows, np.int64)], np.int64)
+        Wf, _, _ = lut_sgdm_spec(self.mu, t, max(self.dmax(t), 0), self.sched)
+        dim = self.w[k].shape[1]
+        out = np.zeros((rows32.shape[0], dim), np.float32)
+        lib().orc_sgdm_restore_rows_f32(dim, _p(self.w[k]), _p(self.m[k]), self.sid[k], dim, rows32.shape[0],
+                                        _p(rows32), _p(d), _p(self.lr[k]), _p(Wf), _p(out))
+        return out
+
+    def current(self, t, rows=None):
+        rows = np.arange(self.counter.shape[0]) if rows is None else np.asarray(rows)
+        return self._restore(0, t, rows), self._restore(1, t, rows)
+
+    def cull_current(self, t, cam):
+        return compact(cull(self._restore(0, t, np.arange(self.counter.shape[0])), cam))
+
+    def step(self, t, valid, g_geo, g_app):
+        valid, sat = self.update_set(valid)
+        rows = np.ascontiguousarray(np.concatenate([valid, sat]), np.uint32)
+        d = np.ascontiguousarray(self.counter[rows.astype(np.int64)], np.int64)
+        Wf, Mf, ss = lut_sgdm_spec(self.mu, t, max(self.dmax(t), 0), self.sched)
+        for k, g in enumerate((g_geo, g_app)):
+            dim = self.w[k].shape[1]
+            gg = np.zeros((rows.shape[0], dim), np.float32)
+            gg[:valid.shape[0]] = g
+            lib().orc_sgdm_rows_f32(dim, _p(self.w[k]), _p(self.m[k]), self.sid[k], dim, rows.shape[0], _p(rows),
+                                    _p(d), _p(gg), dim, _p(self.lr[k]), _p(Wf), _p(Mf), float(ss), self.sr_seed,
+                                    t, self.col0[k])
+        self.bump(valid, sat)
+        return valid, sat
+
+    def flush(self, t_done):
+        rows = np.nonzero(self.counter > 0)[0]
+        if rows.shape[0] == 0:
+            return
+        delta = np.ascontiguousarray(self.counter[rows], np.int64)
+        Wn, Mf, _ = lut_sgdm_spec(self.mu, t_done + 1, int(delta.max()), self.sched)
+        rows32 = np.ascontiguousarray(rows, np.uint32)
+        for k in range(2):
+            dim = self.w[k].shape[1]
+            lib().orc_sgdm_flush_rows_f32(dim, _p(self.w[k]), _p(self.m[k]), self.sid[k], dim, rows.shape[0],
+                                          _p(rows32), _p(delta), _p(self.lr[k]), _p(Wn), _p(Mf), self.sr_seed,
+                                          t_done, self.col0[k])
         self.counter[:] = 0
 
 

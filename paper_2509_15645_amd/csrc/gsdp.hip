@@ -428,7 +428,7 @@ struct CullArgs {
     int32_t mode;                    // 0 exact restoring, 1 band
     int32_t geo_dense;               // geometry updated densely every step: never restore G
     int32_t K;                       // max_defer
-    int32_t pad4;
+    int32_t sgd;                     // SGD with momentum: restore w - (W lr) buf
     u64 *keep_bits;                  // [tiles][8] keep ballots of the tile's 64-row slabs
     u64 *sat_bits;                   // [tiles][8] saturated ballots (K > 0)
     u64 *tile_vs;                    // [tiles] visible << 32 | saturated
@@ -490,27 +490,38 @@ __global__ __launch_bounds__(kCullBlock) void k_cull(CullArgs a)
                 if (d > 0 && !a.geo_dense) {
                     const int64_t row = row0 + r;
                     float mv[10], vv[10];
-                    if (a.gst == GS_F32) {
+                    if (a.sgd) {
+                        // SGD with momentum (FP32 or BF16 buffer): w - (W lr) buf
+                        if (a.gst == GS_F32) {
 #pragma unroll
-                        for (int j = 0; j < 10; ++j) {
-                            mv[j] = mom_load<GS_F32>(a.gm, row, j, false);
-                            vv[j] = mom_load<GS_F32>(a.gv, row, j, true);
-                        }
-                    } else if (a.gst == GS_BF16) {
+                            for (int j = 0; j < 10; ++j) g[j] = g[j] - (wd * a.lr[j]) * mom_load<GS_F32>(a.gm, row, j, false);
+                        } else {
 #pragma unroll
-                        for (int j = 0; j < 10; ++j) {
-                            mv[j] = mom_load<GS_BF16>(a.gm, row, j, false);
-                            vv[j] = mom_load<GS_BF16>(a.gv, row, j, true);
+                            for (int j = 0; j < 10; ++j) g[j] = g[j] - (wd * a.lr[j]) * mom_load<GS_BF16>(a.gm, row, j, false);
                         }
                     } else {
+                        if (a.gst == GS_F32) {
 #pragma unroll
-                        for (int j = 0; j < 10; ++j) {
-                            mv[j] = mom_load<GS_FP8E4M3>(a.gm, row, j, false);
-                            vv[j] = mom_load<GS_FP8E4M3>(a.gv, row, j, true);
+                            for (int j = 0; j < 10; ++j) {
+                                mv[j] = mom_load<GS_F32>(a.gm, row, j, false);
+                                vv[j] = mom_load<GS_F32>(a.gv, row, j, true);
+                            }
+                        } else if (a.gst == GS_BF16) {
+#pragma unroll
+                            for (int j = 0; j < 10; ++j) {
+                                mv[j] = mom_load<GS_BF16>(a.gm, row, j, false);
+                                vv[j] = mom_load<GS_BF16>(a.gv, row, j, true);
+                            }
+                        } else {
+#pragma unroll
+                            for (int j = 0; j < 10; ++j) {
+                                mv[j] = mom_load<GS_FP8E4M3>(a.gm, row, j, false);
+                                vv[j] = mom_load<GS_FP8E4M3>(a.gv, row, j, true);
+                            }
                         }
-                    }
 #pragma unroll
-                    for (int j = 0; j < 10; ++j) g[j] = restore1(g[j], mv[j], vv[j], wd, a.lr[j], a.eps, a.rb);
+                        for (int j = 0; j < 10; ++j) g[j] = restore1(g[j], mv[j], vv[j], wd, a.lr[j], a.eps, a.rb);
+                    }
                     ++nrest;
                 }
                 keep = cull_v1(g, a.cam);
@@ -695,7 +706,8 @@ struct RowArgs {
     float lr[64];                    // lane-indexed: 0..9 G, 10.. A
     float eps, omb1, omb2, rb;       // rb: clamp of the restore factor and of the Adam step
     u64 sr_seed;
-    int32_t geo_dense, pad2;
+    int32_t geo_dense;
+    int32_t sgd;                     // SGD with momentum: buffer in m, no v
     int32_t *last;
     int64_t n;
     const float *Mf, *Vf, *SS, *BC;
@@ -725,6 +737,7 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
     // with dense geometry, G columns are updated elsewhere and never deferred
     const bool act = lane < 10 + a.adim && !(isG && a.geo_dense && MODE != kGather);
     const bool grest = !(isG && a.geo_dense);
+    const bool sgd = a.sgd != 0;
     const int ca = lane - 10;
     const int col = isG ? lane : ca;
     const float lr = a.lr[lane];
@@ -788,10 +801,10 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
             if ((MODE == kAdam || MODE == kAdamMax || d[u] > 0) && grest) {
                 if (isG) {
                     m[u] = mom_load<GST>(qm, r, col, false);
-                    v[u] = mom_load<GST>(qv, r, col, true);
+                    if (!sgd) v[u] = mom_load<GST>(qv, r, col, true);
                 } else {
                     m[u] = mom_load<AST>(qm, r, col, false);
-                    v[u] = mom_load<AST>(qv, r, col, true);
+                    if (!sgd) v[u] = mom_load<AST>(qv, r, col, true);
                 }
             }
             if ((MODE == kAdam || MODE == kAdamMax) && base + u < nvis) {
@@ -805,7 +818,8 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
             const int64_t r = id[u];
             if (MODE == kGather) {
                 float x = w[u];
-                if (d[u] > 0 && grest) x = restore1(x, m[u], v[u], Wrow[d[u]], lr, a.eps, a.rb);
+                if (d[u] > 0 && grest)
+                    x = sgd ? x - (Wrow[d[u]] * lr) * m[u] : restore1(x, m[u], v[u], Wrow[d[u]], lr, a.eps, a.rb);
                 if (act) {
                     if (isG) {
                         if (a.out_geo) a.out_geo[(base + u) * 10 + lane] = x;
@@ -832,12 +846,23 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
             if (MODE == kFlush && dd == 0) continue;
             if (act) {
                 float x, m1, v1;
-                if (MODE == kAdam) {
+                if (MODE == kAdam && sgd) {
+                    // SGD with momentum: catch up, buf = mu^(d+1) buf + g, w -= (lr s_t) buf
+                    x = w[u];
+                    if (dd > 0) x = x - (Wrow[dd] * lr) * m[u];
+                    m1 = a.Mf[dd] * m[u] + g[u];
+                    v1 = 0.0f;
+                    x = x - step * m1;
+                } else if (MODE == kAdam) {
                     x = w[u];
                     if (dd > 0) x = restore1(x, m[u], v[u], Wrow[dd], lr, a.eps, a.rb);
                     m1 = a.Mf[dd] * m[u] + a.omb1 * g[u];
                     v1 = a.Vf[dd] * v[u] + (a.omb2 * g[u]) * g[u];
                     x = x - adam_step(m1, v1, step, bc, a.eps, a.rb);
+                } else if (sgd) {
+                    x = w[u] - (Wrow[dd] * lr) * m[u];
+                    m1 = a.Mf[dd - 1] * m[u];
+                    v1 = 0.0f;
                 } else {
                     x = restore1(w[u], m[u], v[u], Wrow[dd], lr, a.eps, a.rb);
                     m1 = a.Mf[dd - 1] * m[u];
@@ -852,11 +877,11 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
                 if (isG) {
                     a.gw[r * a.gw_ld + lane] = x;
                     mom_store<GST>(qm, r, col, m1, rm, false);
-                    mom_store<GST>(qv, r, col, v1, rv, true);
+                    if (!sgd) mom_store<GST>(qv, r, col, v1, rv, true);
                 } else {
                     a.aw[r * a.aw_ld + ca] = x;
                     mom_store<AST>(qm, r, col, m1, rm, false);
-                    mom_store<AST>(qv, r, col, v1, rv, true);
+                    if (!sgd) mom_store<AST>(qv, r, col, v1, rv, true);
                 }
                 if (MODE == kAdam && !a.g_geo && base + u < nvis) {
                     if (isG) a.gd_geo[r * 10 + lane] = 0.0f;
@@ -1143,6 +1168,10 @@ int check_model(const gs_model *m)
     if (m->cull_mode != 0 && m->cull_mode != 1) return GS_EINVAL;
     if (m->geo_mode != 0 && m->geo_mode != 1) return GS_EINVAL;
     if (m->geo_mode == 1 && m->geo.state == GS_FP8E4M3) return GS_EUNSUPPORTED;
+    if (m->optimizer != GS_OPT_ADAM && m->optimizer != GS_OPT_SGD_MOMENTUM) return GS_EINVAL;
+    if (m->optimizer == GS_OPT_SGD_MOMENTUM &&
+        (m->geo_mode != 0 || m->geo.state == GS_FP8E4M3 || m->app.state == GS_FP8E4M3))
+        return GS_EUNSUPPORTED;
     return GS_OK;
 }
 
@@ -1204,6 +1233,7 @@ void fill_rows(RowArgs &a, const gs_model *m)
     a.rb = restore_bound(m->beta1, m->beta2);
     a.sr_seed = m->sr_seed;
     a.geo_dense = m->geo_mode == 1;
+    a.sgd = m->optimizer == GS_OPT_SGD_MOMENTUM;
     a.last = m->last_step;
     a.n = m->n;
 }
@@ -1613,7 +1643,7 @@ int multi_args(const gs_model *model, const gs_multi *d, int64_t step, void *ws,
     int rc = check_model(model);
     if (rc) return rc;
     if (!d || !step_ok(model, step)) return GS_EINVAL;
-    if (model->max_defer != 0 || model->geo_mode != 0) return GS_EUNSUPPORTED;
+    if (model->max_defer != 0 || model->geo_mode != 0 || model->optimizer != GS_OPT_ADAM) return GS_EUNSUPPORTED;
     if (d->n_scenes < 1 || d->cams_per_scene < 1 || d->cams_per_scene > kMaxCams || d->n_sets < 1) return GS_EINVAL;
     if (d->variant < 0 || d->variant >= kMultiVariants) return GS_EINVAL;
     if (!d->scene_row0 || !d->cams || !d->union_ids || !d->union_count || !d->cam_pos || !d->cam_count ||
@@ -1755,6 +1785,39 @@ int gs_lut_build(double beta1, double beta2, int32_t max_steps, int32_t max_defe
     return gs_lut_build_schedule(beta1, beta2, max_steps, max_defer, nullptr, lut_dev, bytes);
 }
 
+int gs_lut_build_sgd_momentum_host(double momentum, int32_t max_steps, int32_t max_defer, const double *lr_scale,
+                                   void *lut_host, size_t bytes)
+{
+    size_t need = 0;
+    int rc = gs_lut_bytes(max_steps, max_defer, &need);
+    if (rc) return rc;
+    if (!lut_host) return GS_EINVAL;
+    if (!(momentum > 0.0 && momentum < 1.0)) return GS_EINVAL;
+    if (bytes < need) return GS_ESPACE;
+    if (lr_scale)
+        for (int64_t t = 0; t <= (int64_t)max_steps + 1; ++t)
+            if (!(lr_scale[t] >= 0.0) || !std::isfinite(lr_scale[t])) return GS_EINVAL;
+    return gsdp::build_lut_sgdm_host(momentum, max_steps, max_defer, lr_scale, static_cast<float *>(lut_host),
+                                     (int64_t)(bytes / sizeof(float))) == 0
+               ? GS_OK
+               : GS_ESPACE;
+}
+
+int gs_lut_build_sgd_momentum(double momentum, int32_t max_steps, int32_t max_defer, const double *lr_scale,
+                              void *lut_dev, size_t bytes)
+{
+    size_t need = 0;
+    int rc = gs_lut_bytes(max_steps, max_defer, &need);
+    if (rc) return rc;
+    if (!lut_dev) return GS_EINVAL;
+    if (bytes < need) return GS_ESPACE;
+    std::vector<float> host(need / sizeof(float));
+    rc = gs_lut_build_sgd_momentum_host(momentum, max_steps, max_defer, lr_scale, host.data(), need);
+    if (rc) return rc;
+    hipError_t e = hipMemcpy(lut_dev, host.data(), need, hipMemcpyHostToDevice);
+    return e == hipSuccess ? GS_OK : hip_fail(e, "gs_lut_build_sgd_momentum: hipMemcpy");
+}
+
 int gs_workspace_bytes(const gs_model *model, size_t *bytes)
 {
     if (!model || !bytes || model->n < 0 || model->max_defer < 0) return GS_EINVAL;
@@ -1788,6 +1851,9 @@ int gs_cull(const gs_model *model, const gs_camera *cam, int64_t step, uint32_t 
     // the band cull needs eps > 0 (with eps = 0 a row with m = v = 0 restores
     // to NaN) and a finite restore bound; otherwise the exact cull runs
     a.mode = (model->cull_mode == 1 && model->eps > 0.0 && std::isfinite(a.rb)) ? 1 : 0;
+    // the band bound rests on |m|/sqrt(v) <= rb, which a momentum buffer lacks
+    a.sgd = model->optimizer == GS_OPT_SGD_MOMENTUM;
+    if (a.sgd) a.mode = 0;
     pack_camera(model, cam, a.cam, a.band);
     a.geo_dense = model->geo_mode == 1;
     a.K = model->max_defer;

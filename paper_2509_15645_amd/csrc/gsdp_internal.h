@@ -76,5 +76,6 @@ inline int64_t ws_bytes_for(int64_t n, int32_t K, int32_t fp8)
 }
 
 int build_lut_host(double b1, double b2, int32_t T, int32_t K, const double *sched, float *out, int64_t nfloats);
+int build_lut_sgdm_host(double mu, int32_t T, int32_t K, const double *sched, float *out, int64_t nfloats);
 
 }  // namespace gsdp

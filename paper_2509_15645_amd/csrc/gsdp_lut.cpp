@@ -60,4 +60,37 @@ int build_lut_host(double b1, double b2, int32_t T, int32_t K, const double *sch
     return 0;
 }
 
+// SGD with momentum mu: with zero gradients the buffer decays as mu^j, so the
+// skipped steps move w by lr buf W[d], W[d] = sum_{i=1..d} s[t-i] mu^(d+1-i),
+// built as W[d] = mu (W[d-1] + s[t-d]); the first-moment table holds
+// mu^(d+1), the step table s[t]; the second-moment and bias tables are 1.
+int build_lut_sgdm_host(double mu, int32_t T, int32_t K, const double *sched, float *out, int64_t nfloats)
+{
+    const LutLayout L = lut_layout(T, K);
+    if (nfloats < L.total) return -1;
+    for (int64_t i = 0; i < L.total; ++i) out[i] = 0.0f;
+    for (int64_t t = 1; t <= T + 1; ++t) {
+        float *row = out + lut_w_row(t, K);
+        int64_t dm = t - 1;
+        if (K > 0 && dm > K) dm = K;
+        double W = 0.0;
+        row[0] = 0.0f;
+        for (int64_t d = 1; d <= dm; ++d) {
+            W = mu * (W + (sched ? sched[t - d] : 1.0));
+            row[d] = (float)W;
+        }
+    }
+    double p = 1.0;
+    for (int64_t d = 0; d < L.nMV; ++d) {
+        p = p * mu;
+        out[L.offM + d] = (float)p;
+        out[L.offV + d] = 1.0f;
+    }
+    for (int64_t t = 1; t <= T + 1; ++t) {
+        out[L.offSS + t] = sched ? (float)sched[t] : 1.0f;
+        out[L.offBC + t] = 1.0f;
+    }
+    return 0;
+}
+
 }  // namespace gsdp

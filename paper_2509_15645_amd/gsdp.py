@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(PKG, "libgsdp.so")
 
 GS_OK, GS_EINVAL, GS_EHIP, GS_EUNSUPPORTED, GS_ESPACE = 0, -1, -2, -3, -4
 GS_F32, GS_BF16, GS_FP8E4M3 = 0, 1, 2
+GS_OPT_ADAM, GS_OPT_SGD_MOMENTUM = 0, 2
 
 # exported C symbols (kept in sync with include/gsdp.h)
 SYMBOLS = ("gs_lut_bytes", "gs_lut_build", "gs_lut_build_host", "gs_lut_build_schedule",
@@ -26,7 +27,8 @@ SYMBOLS = ("gs_lut_bytes", "gs_lut_build", "gs_lut_build_host", "gs_lut_build_sc
            "gs_gather", "gs_scatter_grad", "gs_adam_step_deferred", "gs_adam_flush", "gs_synth_grad",
            "gs_device_cu_count", "gs_status_string", "gs_last_hip_error", "gs_step_advance",
            "gs_camera_pack_bytes", "gs_camera_pack", "gs_multi_workspace_bytes", "gs_cull_multi",
-           "gs_cull_multi_autotune", "gs_grad_sum_multi", "gs_plan_image_split")
+           "gs_cull_multi_autotune", "gs_grad_sum_multi", "gs_plan_image_split", "gs_lut_build_sgd_momentum",
+           "gs_lut_build_sgd_momentum_host")
 
 
 class GsCamera(C.Structure):
@@ -47,7 +49,7 @@ class GsModel(C.Structure):
                 ("lut", C.c_void_p), ("lut_max_steps", C.c_int32), ("max_defer", C.c_int32),
                 ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double),
                 ("cull_mode", C.c_int32), ("geo_mode", C.c_int32), ("sr_seed", C.c_uint64),
-                ("step_dev", C.c_void_p), ("reserved_", C.c_int32 * 2)]
+                ("step_dev", C.c_void_p), ("optimizer", C.c_int32), ("reserved_", C.c_int32)]
 
 
 class GsMulti(C.Structure):
@@ -71,6 +73,8 @@ def _load():
         "gs_lut_build_host": (C.c_int, [f64, f64, i32, i32, vp, sz]),
         "gs_lut_build_schedule": (C.c_int, [f64, f64, i32, i32, vp, vp, sz]),
         "gs_lut_build_schedule_host": (C.c_int, [f64, f64, i32, i32, vp, vp, sz]),
+        "gs_lut_build_sgd_momentum": (C.c_int, [f64, i32, i32, vp, vp, sz]),
+        "gs_lut_build_sgd_momentum_host": (C.c_int, [f64, i32, i32, vp, vp, sz]),
         "gs_workspace_bytes": (C.c_int, [P(GsModel), P(sz)]),
         "gs_cull": (C.c_int, [P(GsModel), P(GsCamera), i64, vp, vp, u32, vp, sz, vp]),
         "gs_gather": (C.c_int, [P(GsModel), i64, vp, vp, u32, vp, vp, vp]),
@@ -168,6 +172,23 @@ def gs_lut_build_schedule(beta1, beta2, max_steps, max_defer, lr_scale, lut: tor
                                      lut.numel() * lut.element_size()), "gs_lut_build_schedule")
 
 
+def gs_lut_build_sgd_momentum(momentum, max_steps, max_defer, lr_scale, lut: torch.Tensor):
+    sc = None if lr_scale is None else np.ascontiguousarray(lr_scale, np.float64)
+    assert sc is None or sc.shape[0] >= max_steps + 2
+    _check(lib.gs_lut_build_sgd_momentum(momentum, max_steps, max_defer, None if sc is None else sc.ctypes.data,
+                                         _ptr(lut), lut.numel() * lut.element_size()), "gs_lut_build_sgd_momentum")
+
+
+def gs_lut_build_sgd_momentum_host(momentum, max_steps, max_defer, lr_scale=None) -> np.ndarray:
+    nbytes = gs_lut_bytes(max_steps, max_defer)
+    out = np.zeros(nbytes // 4, np.float32)
+    sc = None if lr_scale is None else np.ascontiguousarray(lr_scale, np.float64)
+    _check(lib.gs_lut_build_sgd_momentum_host(momentum, max_steps, max_defer,
+                                              None if sc is None else sc.ctypes.data, out.ctypes.data, nbytes),
+           "gs_lut_build_sgd_momentum_host")
+    return out
+
+
 def gs_workspace_bytes(model) -> int:
     b = C.c_size_t()
     _check(lib.gs_workspace_bytes(C.byref(model.c), C.byref(b)), "gs_workspace_bytes")
@@ -190,7 +211,7 @@ class Model:
 
     def __init__(self, geo, app, lr_geo, lr_app, *, beta1=0.9, beta2=0.999, eps=1e-15, max_defer=0,
                  max_steps=1000, cull_mode=0, app_layout="separate", geo_state="f32", app_state="f32",
-                 sr_seed=0, geo_mode=0, lr_scale=None, device=None):
+                 sr_seed=0, geo_mode=0, lr_scale=None, optimizer="adam", device=None):
         device = device or torch.device("cuda")
         geo = torch.as_tensor(geo, dtype=torch.float32)
         app = torch.as_tensor(app, dtype=torch.float32)
@@ -254,7 +275,13 @@ class Model:
         self.max_steps, self.max_defer = int(max_steps), int(max_defer)
         self.lut = torch.empty(gs_lut_bytes(self.max_steps, self.max_defer) // 4, dtype=torch.float32,
                                device=device)
-        if lr_scale is None:
+        self.optimizer = optimizer
+        if optimizer == "sgd_momentum":
+            # beta1 is the momentum; the v buffers are allocated but unused
+            gs_lut_build_sgd_momentum(beta1, self.max_steps, self.max_defer, lr_scale, self.lut)
+        elif optimizer != "adam":
+            raise ValueError(optimizer)
+        elif lr_scale is None:
             gs_lut_build(beta1, beta2, self.max_steps, self.max_defer, self.lut)
         else:
             gs_lut_build_schedule(beta1, beta2, self.max_steps, self.max_defer, lr_scale, self.lut)
@@ -284,6 +311,7 @@ class Model:
         c.cull_mode = int(cull_mode)
         c.sr_seed = int(sr_seed)
         c.geo_mode = int(geo_mode)
+        c.optimizer = GS_OPT_SGD_MOMENTUM if optimizer == "sgd_momentum" else GS_OPT_ADAM
         # device step counter for graph replay (calls with step == 0 read it)
         self.step_dev = torch.zeros(1, dtype=torch.int32, device=device)
         c.step_dev = self.step_dev.data_ptr()

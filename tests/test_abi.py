@@ -151,3 +151,27 @@ def test_host_schedule_tables_equal_oracle_tables_bitwise(gsdp, max_defer):
         Wf, _, _, ss, _ = orc.lut_spec(0.9, 0.999, t, dmax, sc)
         assert np.array_equal(lut[row:row + dmax + 1].view(np.uint32), Wf.view(np.uint32)), t
         assert lut[offSS + t].view(np.uint32) == np.float32(ss).view(np.uint32)
+
+
+@pytest.mark.parametrize("max_defer,sched", [(0, False), (15, True)])
+def test_host_sgd_momentum_tables_equal_oracle_bitwise(gsdp, max_defer, sched):
+    T, mu = 90, 0.9
+    sc = None
+    if sched:
+        rng = np.random.default_rng(8)
+        sc = 0.01 ** (np.arange(T + 2) / (T + 1)) * rng.uniform(0.5, 2.0, T + 2)
+    lut = gsdp.gs_lut_build_sgd_momentum_host(mu, T, max_defer, lr_scale=sc)
+    K = max_defer
+    rows = T + 1
+    nW = rows * (K + 1) if K else rows * (rows + 1) // 2
+    nMV = (K if K else T) + 1
+    offM, offSS = nW, nW + 2 * nMV
+    for t in [1, 2, 16, 17, 50, T, T + 1]:
+        row = (t - 1) * (K + 1) if K else t * (t - 1) // 2
+        dmax = min(t - 1, K) if K else t - 1
+        Wf, Mf, ss = orc.lut_sgdm_spec(mu, t, dmax, sc)
+        assert np.array_equal(lut[row:row + dmax + 1].view(np.uint32), Wf.view(np.uint32)), t
+        assert np.array_equal(lut[offM:offM + dmax + 1].view(np.uint32), Mf.view(np.uint32))
+        assert lut[offSS + t].view(np.uint32) == np.float32(ss).view(np.uint32)
+    small = np.zeros(4, np.float32)
+    assert gsdp.lib.gs_lut_build_sgd_momentum_host(1.0, 10, 0, None, small.ctypes.data, 16) == gsdp.GS_EINVAL

@@ -303,6 +303,68 @@ def test_small_workload_path_vs_oracle(g, max_defer, layout, grad_mode, cull_mod
     assert model.ws_header()["error"] == 0
 
 
+@pytest.mark.parametrize("max_defer,layout,states,sched", [
+    (0, "interleaved", ("f32", "f32"), False),
+    (15, "separate", ("f32", "f32"), True),
+    (0, "fused", ("bf16", "bf16"), True),
+])
+def test_small_workload_sgd_momentum_vs_oracle(g, max_defer, layout, states, sched):
+    """Deferred SGD with momentum (the momentum-optimizer extension): ids,
+    gathered rows and stored state bit-exact vs the FP32 oracle model every
+    step and after the flush; FP32 state within 1e-6 of dense FP64 SGD."""
+    w = gi.workload("small")
+    sc = gi.make_scene(w.n, seed=0, box=w.scene_box)
+    lg, la = gi.lr_columns()
+    lr_scale = None
+    if sched:
+        rng = np.random.default_rng(4)
+        lr_scale = 0.01 ** (np.arange(34) / 33.0) * rng.uniform(0.5, 2.0, 34)
+    mu = 0.9
+    model = g.Model(sc.geo, sc.app, lg, la, beta1=mu, max_steps=32, max_defer=max_defer, app_layout=layout,
+                    cull_mode=1, geo_state=states[0], app_state=states[1], sr_seed=5, lr_scale=lr_scale,
+                    optimizer="sgd_momentum")
+    o3 = orc.DeferredSGDMF32(sc.geo, sc.app, lg, la, mu=mu, max_defer=max_defer, state=states[0],
+                             app_state=states[1], sr_seed=5, sched=lr_scale)
+    dense = orc.DenseSGDMF64(sc.geo, sc.app, lg, la, mu=mu, sched=lr_scale)
+    n = w.n
+    out_g = torch.zeros((n, 10), dtype=torch.float32, device="cuda")
+    out_a = torch.zeros((n, 49), dtype=torch.float32, device="cuda")
+
+    def compare(tag):
+        st = model.state()
+        for k, name in ((0, "geo"), (1, "app")):
+            for part, ref in (("w", o3.w[k]), ("m", o3.m[k])):
+                assert np.array_equal(bits(st[f"{name}_{part}"]), bits(ref)), f"{tag}: {name}_{part}"
+
+    for t in range(1, w.steps + 1):
+        cam = w.camera_for_step(t)
+        ids, count, m = run_cull(g, model, cam, t)
+        valid = o3.cull_current(t, cam)
+        assert m == valid.shape[0] and np.array_equal(u32(ids[:m]), valid), f"step {t}"
+        g.gs_gather(model, t, ids, count, out_g, out_a)
+        torch.cuda.synchronize()
+        cg, ca = o3.current(t, valid)
+        assert np.array_equal(bits(out_g[:m].cpu().numpy()), bits(cg)), f"gather geo step {t}"
+        assert np.array_equal(bits(out_a[:m].cpu().numpy()), bits(ca)), f"gather app step {t}"
+        gg, ga = gi.step_grads(0, t, valid)
+        g.gs_adam_step_deferred(model, t, ids, count, torch.from_numpy(gg).cuda(), torch.from_numpy(ga).cuda())
+        o3.step(t, valid, gg, ga)
+        dense.step(t, valid, gg, ga)
+        if t % 5 == 0:
+            compare(f"step {t}")
+            assert np.array_equal(model.last_step.cpu().numpy(), o3.last_step(t))
+        say(f"[sgd-momentum K={max_defer} {layout} {states}] step {t}: M={m}")
+    g.gs_adam_flush(model, w.steps)
+    o3.flush(w.steps)
+    compare("after flush")
+    if states == ("f32", "f32"):
+        st = model.state()
+        e_geo = np.abs(st["geo_w"] - dense.w[0]) / np.maximum(np.abs(dense.w[0]), TAU_GEO)
+        e_app = np.abs(st["app_w"] - dense.w[1]) / np.maximum(np.abs(dense.w[1]), TAU_APP)
+        say(f"[sgd-momentum] vs dense FP64: geo max {e_geo.max():.3e}; app max {e_app.max():.3e}")
+        assert e_geo.max() <= 1e-6 and e_app.max() <= 1e-6
+
+
 @pytest.mark.parametrize("seed", [0, 1, 2])
 def test_band_cull_adversarial_deferred_rows(g, seed):
     """Stale geometry near the image border and the near plane, deferred up
