@@ -829,3 +829,205 @@ void orc_sgdm_flush_rows_f32(int dim, float *w, void *m, int state, int64_t ld, 
         }
     }
 }
+
+/* ------------------------------------------------------------------------ */
+/* AdamW (decoupled weight decay; the other optimizer Sec. 4.3 names), in the
+ * common form where step k first scales w by q_k = 1 - lr s_k lambda and then
+ * applies the Adam update.  With g = 0 for d skipped steps the catch-up is
+ *   w_cur = P_d w - lr (m / (sqrt(v) + eps)) Wl[d]
+ *   P_d   = prod_{i=1..d} q_{t-i}
+ *   Wl[d] = sum_{i=1..d} (prod_{j=1..i-1} q_{t-j}) r^(d-i) s_{t-i} c(t-i)
+ * (r = b1/sqrt(b2), c(k) the unit-rate coefficient of Eq. 3), i.e. Eq. 3 with
+ * every skipped update also shrunk by the decays that follow it.  Built by
+ *   Wl[d] = r Wl[d-1] + P_{d-1} s_{t-d} c(t-d),   P_d = P_{d-1} q_{t-d}.
+ * The tables depend on the column's rate through q. */
+
+/* Dense definition (rates lr[] already include the step's multiplier). */
+void orc_adamw_dense_sparse_grad_f64(int64_t n, int dim, double *w, double *m, double *v, int64_t n_ids,
+                                     const uint32_t *ids, const float *g_rows, const double *lr, double b1,
+                                     double b2, double eps, double lam, int64_t t)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i)
+        for (int k = 0; k < dim; ++k) w[i * dim + k] = w[i * dim + k] * (1.0 - lr[k] * lam);
+    orc_adam_dense_sparse_grad_f64(n, dim, w, m, v, n_ids, ids, g_rows, lr, b1, b2, eps, t);
+}
+
+/* FP64 tables of update t for one column rate lr (paper form: pow for c). */
+void orc_lut_adamw_f64(double b1, double b2, double lam, double lr, int64_t t, int dmax, const double *sched,
+                       double *Wl, double *P)
+{
+    const double r = b1 / sqrt(b2);
+    Wl[0] = 0.0;
+    P[0] = 1.0;
+    for (int d = 1; d <= dmax; ++d) {
+        int64_t k = t - d;
+        double s = sched ? sched[k] : 1.0;
+        double c = b1 / (sqrt(b2 / (1.0 - pow(b2, (double)k))) * (1.0 - pow(b1, (double)k)));
+        Wl[d] = r * Wl[d - 1] + P[d - 1] * (s * c);
+        P[d] = P[d - 1] * (1.0 - lr * s * lam);
+    }
+}
+
+/* The same tables with repeated-multiplication powers, rounded once to FP32,
+ * and the decay factor of step t. */
+void orc_lut_adamw_spec(double b1, double b2, double lam, double lr, int64_t t, int dmax, const double *sched,
+                        float *Wf, float *Pf, float *qt)
+{
+    double P1 = 1.0, P2 = 1.0;
+    double *C = (double *)calloc((size_t)t + 1, sizeof(double));
+    for (int64_t k = 1; k <= t; ++k) {
+        P1 = P1 * b1;
+        P2 = P2 * b2;
+        C[k] = b1 / (sqrt(b2 / (1.0 - P2)) * (1.0 - P1));
+        if (sched) C[k] = sched[k] * C[k];
+    }
+    const double r = b1 / sqrt(b2);
+    double W = 0.0, P = 1.0;
+    Wf[0] = 0.0f;
+    Pf[0] = 1.0f;
+    for (int d = 1; d <= dmax; ++d) {
+        int64_t k = t - d;
+        W = r * W + P * C[k];
+        P = P * (1.0 - lr * (sched ? sched[k] : 1.0) * lam);
+        Wf[d] = (float)W;
+        Pf[d] = (float)P;
+    }
+    *qt = (float)(1.0 - lr * (sched ? sched[t] : 1.0) * lam);
+    free(C);
+}
+
+/* FP64 deferred rows (paper order).  Wl, P: per column tables [dim][ldt]. */
+void orc_adamw_deferred_rows_f64(int dim, double *w, double *m, double *v, int64_t n_rows, const uint32_t *rows,
+                                 const int64_t *d, const double *g, const double *lr, double b1, double b2,
+                                 double eps, int64_t t, double s_t, double lam, const double *Wl, const double *P,
+                                 int64_t ldt, const double *mom_lut, const double *var_lut)
+{
+    const double bias_correction = sqrt(1.0 - pow(b2, (double)t));
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < n_rows; ++j) {
+        int64_t id = rows[j];
+        int64_t dj = d[j];
+        for (int k = 0; k < dim; ++k) {
+            int64_t e = id * dim + k;
+            double wk = w[e], mk = m[e], vk = v[e], gk = g ? g[j * dim + k] : 0.0;
+            if (dj > 0) wk = P[k * ldt + dj] * wk - (Wl[k * ldt + dj] * lr[k] * mk) / (sqrt(vk) + eps);
+            double m_new = mom_lut[dj] * mk + (1.0 - b1) * gk;
+            double v_new = var_lut[dj] * vk + (1.0 - b2) * gk * gk;
+            double lr_t = lr[k] * s_t;
+            double step_size = lr_t / (1.0 - pow(b1, (double)t));
+            wk = wk * (1.0 - lr_t * lam);
+            w[e] = wk - step_size * m_new / (sqrt(v_new) / bias_correction + eps);
+            m[e] = m_new;
+            v[e] = v_new;
+        }
+    }
+}
+
+/* FP64 restore (read-only) and flush (tables of t+1, moments decay by b^delta). */
+void orc_adamw_restore_rows_f64(int dim, const double *w, const double *m, const double *v, int64_t n_rows,
+                                const uint32_t *rows, const int64_t *d, const double *lr, double eps,
+                                const double *Wl, const double *P, int64_t ldt, double *out)
+{
+    for (int64_t j = 0; j < n_rows; ++j)
+        for (int k = 0; k < dim; ++k) {
+            int64_t e = (int64_t)rows[j] * dim + k;
+            double wk = w[e];
+            if (d[j] > 0) wk = P[k * ldt + d[j]] * wk - (Wl[k * ldt + d[j]] * lr[k] * m[e]) / (sqrt(v[e]) + eps);
+            out[j * dim + k] = wk;
+        }
+}
+
+void orc_adamw_flush_rows_f64(int dim, double *w, double *m, double *v, int64_t n_rows, const uint32_t *rows,
+                              const int64_t *delta, const double *lr, double b1, double b2, double eps,
+                              const double *Wl_next, const double *P_next, int64_t ldt)
+{
+    for (int64_t j = 0; j < n_rows; ++j)
+        for (int k = 0; k < dim; ++k) {
+            int64_t e = (int64_t)rows[j] * dim + k, dl = delta[j];
+            w[e] = P_next[k * ldt + dl] * w[e] - (Wl_next[k * ldt + dl] * lr[k] * m[e]) / (sqrt(v[e]) + eps);
+            m[e] *= pow(b1, (double)dl);
+            v[e] *= pow(b2, (double)dl);
+        }
+}
+
+/* FP32 model, the spec's order: restore (Pf w) - (Wf lr) q with q the clamped
+ * m/(sqrt(v)+eps); step qf w - adam_step.  Tables per column [dim][ldt]. */
+static float restore32_w(float w, float m, float v, float wd, float pd, float lr, float eps, float rb)
+{
+    float den = sqrtf(v) + eps;
+    float q = m / den;
+    if (q > rb) q = rb;
+    else if (q < -rb) q = -rb;
+    float a = pd * w;
+    float b = (wd * lr) * q;
+    return a - b;
+}
+
+void orc_adamw_rows_f32(int dim, float *w, void *m, void *v, int state, int64_t ld, int64_t n_rows,
+                        const uint32_t *rows, const int64_t *d, const float *g, int64_t g_ld, const float *lr,
+                        double b1, double b2, double eps, const float *Wf, const float *Pf, int64_t ldt,
+                        const float *qf, const float *Mf, const float *Vf, float ss, float bc, float rb,
+                        uint64_t seed, int64_t t, int col0)
+{
+    const float omb1 = (float)(1.0 - b1), omb2 = (float)(1.0 - b2), eps32 = (float)eps;
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < n_rows; ++j) {
+        int64_t id = rows[j];
+        int64_t dj = d[j];
+        for (int k = 0; k < dim; ++k) {
+            int64_t e = id * ld + k;
+            float wk = w[e], mk = mom_load(m, state, e), vk = mom_load(v, state, e);
+            float gk = g ? g[j * g_ld + k] : 0.0f;
+            if (dj > 0) wk = restore32_w(wk, mk, vk, Wf[k * ldt + dj], Pf[k * ldt + dj], lr[k], eps32, rb);
+            float m1 = Mf[dj] * mk + omb1 * gk;
+            float v1 = Vf[dj] * vk + (omb2 * gk) * gk;
+            float st = lr[k] * ss;
+            float wq = qf[k] * wk;
+            w[e] = wq - adam_step32(m1, v1, st, bc, eps32, rb);
+            uint64_t r = state ? sr_bits(seed, t, id, col0 + k) : 0;
+            mom_store(m, state, e, m1, (uint32_t)(r & 0xffffu));
+            mom_store(v, state, e, v1, (uint32_t)((r >> 16) & 0xffffu));
+        }
+    }
+}
+
+void orc_adamw_restore_rows_f32(int dim, const float *w, const void *m, const void *v, int state, int64_t ld,
+                                int64_t n_rows, const uint32_t *rows, const int64_t *d, const float *lr, double eps,
+                                const float *Wf, const float *Pf, int64_t ldt, float rb, float *out)
+{
+    const float eps32 = (float)eps;
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < n_rows; ++j) {
+        int64_t id = rows[j];
+        for (int k = 0; k < dim; ++k) {
+            int64_t e = id * ld + k;
+            float wk = w[e];
+            if (d[j] > 0)
+                wk = restore32_w(wk, mom_load(m, state, e), mom_load(v, state, e), Wf[k * ldt + d[j]],
+                                 Pf[k * ldt + d[j]], lr[k], eps32, rb);
+            out[j * dim + k] = wk;
+        }
+    }
+}
+
+void orc_adamw_flush_rows_f32(int dim, float *w, void *m, void *v, int state, int64_t ld, int64_t n_rows,
+                              const uint32_t *rows, const int64_t *delta, const float *lr, double eps,
+                              const float *Wf_next, const float *Pf_next, int64_t ldt, const float *Mf,
+                              const float *Vf, float rb, uint64_t seed, int64_t t, int col0)
+{
+    const float eps32 = (float)eps;
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < n_rows; ++j) {
+        int64_t id = rows[j];
+        int64_t dl = delta[j];
+        for (int k = 0; k < dim; ++k) {
+            int64_t e = id * ld + k;
+            float mk = mom_load(m, state, e), vk = mom_load(v, state, e);
+            w[e] = restore32_w(w[e], mk, vk, Wf_next[k * ldt + dl], Pf_next[k * ldt + dl], lr[k], eps32, rb);
+            uint64_t r = state ? sr_bits(seed, t, id, col0 + k) : 0;
+            mom_store(m, state, e, Mf[dl - 1] * mk, (uint32_t)(r & 0xffffu));
+            mom_store(v, state, e, Vf[dl - 1] * vk, (uint32_t)((r >> 16) & 0xffffu));
+        }
+    }
+}

@@ -89,6 +89,20 @@ def lib():
             "orc_sgdm_restore_rows_f32": (None, [i32, vp, vp, i32, i64, i64, vp, vp, vp, vp, vp]),
             "orc_sgdm_flush_rows_f32": (None, [i32, vp, vp, i32, i64, i64, vp, vp, vp, vp, vp, C.c_uint64,
                                                i64, i32]),
+            "orc_adamw_dense_sparse_grad_f64": (None, [i64, i32, vp, vp, vp, i64, vp, vp, vp, f64, f64, f64, f64,
+                                                        i64]),
+            "orc_lut_adamw_f64": (None, [f64, f64, f64, f64, i64, i32, vp, vp, vp]),
+            "orc_lut_adamw_spec": (None, [f64, f64, f64, f64, i64, i32, vp, vp, vp, vp]),
+            "orc_adamw_deferred_rows_f64": (None, [i32, vp, vp, vp, i64, vp, vp, vp, vp, f64, f64, f64, i64, f64,
+                                                   f64, vp, vp, i64, vp, vp]),
+            "orc_adamw_restore_rows_f64": (None, [i32, vp, vp, vp, i64, vp, vp, vp, f64, vp, vp, i64, vp]),
+            "orc_adamw_flush_rows_f64": (None, [i32, vp, vp, vp, i64, vp, vp, vp, f64, f64, f64, vp, vp, i64]),
+            "orc_adamw_rows_f32": (None, [i32, vp, vp, vp, i32, i64, i64, vp, vp, vp, i64, vp, f64, f64, f64,
+                                          vp, vp, i64, vp, vp, vp, f32, f32, f32, C.c_uint64, i64, i32]),
+            "orc_adamw_restore_rows_f32": (None, [i32, vp, vp, vp, i32, i64, i64, vp, vp, vp, f64, vp, vp, i64,
+                                                  f32, vp]),
+            "orc_adamw_flush_rows_f32": (None, [i32, vp, vp, vp, i32, i64, i64, vp, vp, vp, f64, vp, vp, i64, vp,
+                                                vp, f32, C.c_uint64, i64, i32]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -572,6 +586,183 @@ class DeferredSGDMF32(_Deferred):
             lib().orc_sgdm_flush_rows_f32(dim, _p(self.w[k]), _p(self.m[k]), self.sid[k], dim, rows.shape[0],
                                           _p(rows32), _p(delta), _p(self.lr[k]), _p(Wn), _p(Mf), self.sr_seed,
                                           t_done, self.col0[k])
+        self.counter[:] = 0
+
+
+# ---------------------------------------------------------------------------
+# AdamW (decoupled weight decay, the other optimizer named in Sec. 4.3)
+# ---------------------------------------------------------------------------
+def lut_adamw(b1, b2, lam, lr, t, dmax, sched=None):
+    """FP64 (Wl, P) of update t for one column rate (paper form)."""
+    W = np.zeros(dmax + 1); P = np.zeros(dmax + 1)
+    lib().orc_lut_adamw_f64(b1, b2, lam, float(lr), t, dmax, _p(_sched(sched)), _p(W), _p(P))
+    return W, P
+
+
+def lut_adamw_spec(b1, b2, lam, lr, t, dmax, sched=None):
+    """FP32 (Wf, Pf, q_t) of update t for one FP32 column rate."""
+    Wf = np.zeros(dmax + 1, np.float32); Pf = np.zeros(dmax + 1, np.float32)
+    q = C.c_float()
+    lib().orc_lut_adamw_spec(b1, b2, lam, float(lr), t, dmax, _p(_sched(sched)), _p(Wf), _p(Pf), C.addressof(q))
+    return Wf, Pf, np.float32(q.value)
+
+
+def _col_tables(fn, lr, *args):
+    """Per-column tables [dim, dmax+1] (one table per distinct rate)."""
+    cache, W, P, Q = {}, [], [], []
+    for r in np.asarray(lr).tolist():
+        if r not in cache:
+            cache[r] = fn(*args[:3], r, *args[3:])
+        w_, p_, *q_ = cache[r]
+        W.append(w_); P.append(p_); Q.append(q_[0] if q_ else 0.0)
+    return np.ascontiguousarray(np.stack(W)), np.ascontiguousarray(np.stack(P)), np.asarray(Q, np.float32)
+
+
+class DenseAdamWF64:
+    """FP64 AdamW on every row every step: w *= 1 - lr_t lambda, then Adam."""
+
+    def __init__(self, geo, app, lr_geo, lr_app, b1=0.9, b2=0.999, eps=1e-15, weight_decay=0.01, sched=None):
+        self.w = [np.array(geo, np.float64), np.array(app, np.float64)]
+        self.m = [np.zeros_like(x) for x in self.w]
+        self.v = [np.zeros_like(x) for x in self.w]
+        self.lr = [np.asarray(lr_geo, np.float64), np.asarray(lr_app, np.float64)]
+        self.b1, self.b2, self.eps, self.lam = b1, b2, eps, weight_decay
+        self.sched = _sched(sched)
+
+    def step(self, t, ids, g_geo, g_app):
+        ids = np.ascontiguousarray(ids, np.uint32)
+        s = 1.0 if self.sched is None else float(self.sched[t])
+        for k, g in enumerate((g_geo, g_app)):
+            g = np.ascontiguousarray(g, np.float32)
+            lr = np.ascontiguousarray(self.lr[k] * s)
+            lib().orc_adamw_dense_sparse_grad_f64(self.w[k].shape[0], self.w[k].shape[1], _p(self.w[k]),
+                                                  _p(self.m[k]), _p(self.v[k]), ids.shape[0], _p(ids), _p(g),
+                                                  _p(lr), self.b1, self.b2, self.eps, self.lam, t)
+
+
+class DeferredAdamWF64(_Deferred):
+    """Deferred AdamW in FP64 (paper order, paper-form tables)."""
+
+    def __init__(self, geo, app, lr_geo, lr_app, b1=0.9, b2=0.999, eps=1e-15, weight_decay=0.01, max_defer=0,
+                 sched=None):
+        super().__init__(geo.shape[0], max_defer)
+        self.w = [np.array(geo, np.float64), np.array(app, np.float64)]
+        self.m = [np.zeros_like(x) for x in self.w]
+        self.v = [np.zeros_like(x) for x in self.w]
+        self.lr = [np.asarray(lr_geo, np.float64), np.asarray(lr_app, np.float64)]
+        self.b1, self.b2, self.eps, self.lam = b1, b2, eps, weight_decay
+        self.sched = _sched(sched)
+
+    def _tabs(self, k, t, dmax):
+        return _col_tables(lut_adamw, self.lr[k], self.b1, self.b2, self.lam, t, dmax, self.sched)
+
+    def step(self, t, valid, g_geo, g_app):
+        valid, sat = self.update_set(valid)
+        rows = np.ascontiguousarray(np.concatenate([valid, sat]), np.uint32)
+        d = np.ascontiguousarray(self.counter[rows.astype(np.int64)], np.int64)
+        dmax = max(self.dmax(t), 0)
+        _, mom, var = lut_paper(self.b1, self.b2, t, dmax, self.sched)
+        s_t = 1.0 if self.sched is None else float(self.sched[t])
+        for k, g in enumerate((g_geo, g_app)):
+            dim = self.w[k].shape[1]
+            W, P, _ = self._tabs(k, t, dmax)
+            gg = np.zeros((rows.shape[0], dim))
+            gg[:valid.shape[0]] = np.asarray(g, np.float64)
+            lib().orc_adamw_deferred_rows_f64(dim, _p(self.w[k]), _p(self.m[k]), _p(self.v[k]), rows.shape[0],
+                                              _p(rows), _p(d), _p(gg), _p(self.lr[k]), self.b1, self.b2, self.eps,
+                                              t, s_t, self.lam, _p(W), _p(P), dmax + 1, _p(mom), _p(var))
+        self.bump(valid, sat)
+        return valid, sat
+
+    def flush(self, t_done):
+        rows = np.nonzero(self.counter > 0)[0]
+        if rows.shape[0] == 0:
+            return
+        delta = np.ascontiguousarray(self.counter[rows], np.int64)
+        dm = int(delta.max())
+        rows32 = np.ascontiguousarray(rows, np.uint32)
+        for k in range(2):
+            W, P, _ = self._tabs(k, t_done + 1, dm)
+            lib().orc_adamw_flush_rows_f64(self.w[k].shape[1], _p(self.w[k]), _p(self.m[k]), _p(self.v[k]),
+                                           rows.shape[0], _p(rows32), _p(delta), _p(self.lr[k]), self.b1, self.b2,
+                                           self.eps, _p(W), _p(P), dm + 1)
+        self.counter[:] = 0
+
+
+class DeferredAdamWF32(_Deferred):
+    """Deferred AdamW with FP32 math in the implementation's op order;
+    moments FP32 or BF16 (stochastic rounding as the Adam models)."""
+
+    def __init__(self, geo, app, lr_geo, lr_app, b1=0.9, b2=0.999, eps=1e-15, weight_decay=0.01, max_defer=0,
+                 state="f32", app_state=None, sr_seed=0, sched=None):
+        super().__init__(geo.shape[0], max_defer)
+        states = [state, app_state or state]
+        assert all(x in ("f32", "bf16") for x in states)
+        self.sid = [STATES[x][0] for x in states]
+        self.w = [np.array(geo, np.float32), np.array(app, np.float32)]
+        self.m = [np.zeros(x.shape, STATES[st][1]) for x, st in zip(self.w, states)]
+        self.v = [np.zeros(x.shape, STATES[st][1]) for x, st in zip(self.w, states)]
+        self.lr = [np.asarray(lr_geo, np.float32), np.asarray(lr_app, np.float32)]
+        self.b1, self.b2, self.eps, self.lam = b1, b2, eps, weight_decay
+        self.rb = float(restore_bound(b1, b2))
+        self.sched = _sched(sched)
+        self.sr_seed = int(sr_seed)
+        self.col0 = [0, self.w[0].shape[1]]
+
+    def _tabs(self, k, t, dmax):
+        return _col_tables(lut_adamw_spec, self.lr[k], self.b1, self.b2, self.lam, t, dmax, self.sched)
+
+    def _restore(self, k, t, rows):
+        rows32 = np.ascontiguousarray(rows, np.uint32)
+        d = np.ascontiguousarray(self.counter[np.asarray(rows, np.int64)], np.int64)
+        dmax = max(self.dmax(t), 0)
+        W, P, _ = self._tabs(k, t, dmax)
+        dim = self.w[k].shape[1]
+        out = np.zeros((rows32.shape[0], dim), np.float32)
+        lib().orc_adamw_restore_rows_f32(dim, _p(self.w[k]), _p(self.m[k]), _p(self.v[k]), self.sid[k], dim,
+                                         rows32.shape[0], _p(rows32), _p(d), _p(self.lr[k]), self.eps, _p(W), _p(P),
+                                         dmax + 1, self.rb, _p(out))
+        return out
+
+    def current(self, t, rows=None):
+        rows = np.arange(self.counter.shape[0]) if rows is None else np.asarray(rows)
+        return self._restore(0, t, rows), self._restore(1, t, rows)
+
+    def cull_current(self, t, cam):
+        return compact(cull(self._restore(0, t, np.arange(self.counter.shape[0])), cam))
+
+    def step(self, t, valid, g_geo, g_app):
+        valid, sat = self.update_set(valid)
+        rows = np.ascontiguousarray(np.concatenate([valid, sat]), np.uint32)
+        d = np.ascontiguousarray(self.counter[rows.astype(np.int64)], np.int64)
+        dmax = max(self.dmax(t), 0)
+        _, Mf, Vf, ss, bc = lut_spec(self.b1, self.b2, t, dmax, self.sched)
+        for k, g in enumerate((g_geo, g_app)):
+            dim = self.w[k].shape[1]
+            W, P, Q = self._tabs(k, t, dmax)
+            gg = np.zeros((rows.shape[0], dim), np.float32)
+            gg[:valid.shape[0]] = g
+            lib().orc_adamw_rows_f32(dim, _p(self.w[k]), _p(self.m[k]), _p(self.v[k]), self.sid[k], dim,
+                                     rows.shape[0], _p(rows), _p(d), _p(gg), dim, _p(self.lr[k]), self.b1, self.b2,
+                                     self.eps, _p(W), _p(P), dmax + 1, _p(Q), _p(Mf), _p(Vf), float(ss), float(bc),
+                                     self.rb, self.sr_seed, t, self.col0[k])
+        self.bump(valid, sat)
+        return valid, sat
+
+    def flush(self, t_done):
+        rows = np.nonzero(self.counter > 0)[0]
+        if rows.shape[0] == 0:
+            return
+        delta = np.ascontiguousarray(self.counter[rows], np.int64)
+        dm = int(delta.max())
+        _, Mf, Vf, _, _ = lut_spec(self.b1, self.b2, t_done + 1, dm, self.sched)
+        rows32 = np.ascontiguousarray(rows, np.uint32)
+        for k in range(2):
+            dim = self.w[k].shape[1]
+            W, P, _ = self._tabs(k, t_done + 1, dm)
+            lib().orc_adamw_flush_rows_f32(dim, _p(self.w[k]), _p(self.m[k]), _p(self.v[k]), self.sid[k], dim,
+                                           rows.shape[0], _p(rows32), _p(delta), _p(self.lr[k]), self.eps, _p(W),
+                                           _p(P), dm + 1, _p(Mf), _p(Vf), self.rb, self.sr_seed, t_done, self.col0[k])
         self.counter[:] = 0
 
 
