@@ -99,7 +99,7 @@ typedef struct gs_model {
                               split of Sec. 4.2.2 step 4 (appearance stays deferred) */
     uint64_t sr_seed;      /* seed of the stochastic-rounding stream of quantised moments */
     const int32_t *step_dev; /* device step counter used by calls with step == 0 */
-    int32_t optimizer;     /* GS_OPT_ADAM (default) or GS_OPT_SGD_MOMENTUM */
+    int32_t optimizer;     /* GS_OPT_ADAM (default), GS_OPT_ADAMW or GS_OPT_SGD_MOMENTUM */
     int32_t reserved_;
 } gs_model;
 
@@ -110,7 +110,15 @@ typedef struct gs_model {
  * catch-up is exact.  It needs tables from gs_lut_build_sgd_momentum, FP32 or
  * BF16 state, cull_mode 0 and geo_mode 0, and is not available in the batched
  * form. */
-enum { GS_OPT_ADAM = 0, GS_OPT_SGD_MOMENTUM = 2 };
+enum { GS_OPT_ADAM = 0, GS_OPT_ADAMW = 1, GS_OPT_SGD_MOMENTUM = 2 };
+
+/* GS_OPT_ADAMW is Adam with decoupled weight decay (the other optimizer of
+ * Sec. 4.3): each update first scales w by 1 - lr lambda (lr the column's
+ * rate times the step's multiplier), then applies the Adam update.  Skipped
+ * updates are caught up exactly like Eq. 3 with every deferred term also
+ * shrunk by the later decays; the tables (gs_lut_build_adamw) hold one set
+ * per distinct column rate, at most 8 distinct rates.  FP32 or BF16 state,
+ * cull_mode 0, geo_mode 0; not available in the batched form. */
 
 /* ---------------------------------------------------------------- tables */
 
@@ -136,6 +144,19 @@ int gs_lut_build_sgd_momentum(double momentum, int32_t max_steps, int32_t max_de
                               void *lut_dev, size_t bytes);
 int gs_lut_build_sgd_momentum_host(double momentum, int32_t max_steps, int32_t max_defer, const double *lr_scale,
                                    void *lut_host, size_t bytes);
+
+/* AdamW tables for `model` (its betas, column rates, lut_max_steps and
+ * max_defer) with weight decay lambda >= 0 and an optional rate schedule
+ * (as gs_lut_build_schedule).  The Adam tables come first, then per decay
+ * class c -- the distinct column rates in order of first appearance, G columns
+ * before A columns -- the decayed restore rows, the decay products (both laid
+ * out like W) and the step decays 1 - lr s[t] lambda.  gs_lut_bytes_adamw
+ * gives the size; model->lut is not read. */
+int gs_lut_bytes_adamw(const gs_model *model, size_t *bytes);
+int gs_lut_build_adamw(const gs_model *model, double weight_decay, const double *lr_scale, void *lut_dev,
+                       size_t bytes);
+int gs_lut_build_adamw_host(const gs_model *model, double weight_decay, const double *lr_scale, void *lut_host,
+                            size_t bytes);
 
 /* Same tables written to host memory (for inspection and tests). */
 int gs_lut_build_host(double beta1, double beta2, int32_t max_steps, int32_t max_defer,

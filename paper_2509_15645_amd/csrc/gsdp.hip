@@ -167,6 +167,20 @@ __device__ __forceinline__ float restore1(float w, float m, float v, float wd, f
     return w - wsc * q;
 }
 
+// AdamW restore of one element (d > 0): (P[d] w) - (Wl[d] lr) q with q the
+// clamped m/(sqrt(v)+eps): Eq. 3 with every skipped update shrunk by the
+// decoupled weight decays that follow it.
+__device__ __forceinline__ float restore_w(float w, float m, float v, float wd, float pd, float lr, float eps, float rb)
+{
+    const float den = sqrtf(v) + eps;
+    float q = m / den;
+    if (q > rb) q = rb;
+    else if (q < -rb) q = -rb;
+    const float a = pd * w;
+    const float b = (wd * lr) * q;
+    return a - b;
+}
+
 // SplitMix64 (Steele, Lea & Flood 2014): output k of the stream seeded s.
 __device__ __forceinline__ u64 mix64(u64 z)
 {
@@ -429,6 +443,10 @@ struct CullArgs {
     int32_t geo_dense;               // geometry updated densely every step: never restore G
     int32_t K;                       // max_defer
     int32_t sgd;                     // SGD with momentum: restore w - (W lr) buf
+    int32_t adamw, pad7;             // AdamW: decayed restore with the column's class tables
+    const float *aw_base;
+    int64_t aw_per, aw_nW;
+    uint8_t cls[16];                 // rate class of G columns 0..9
     u64 *keep_bits;                  // [tiles][8] keep ballots of the tile's 64-row slabs
     u64 *sat_bits;                   // [tiles][8] saturated ballots (K > 0)
     u64 *tile_vs;                    // [tiles] visible << 32 | saturated
@@ -519,8 +537,18 @@ __global__ __launch_bounds__(kCullBlock) void k_cull(CullArgs a)
                                 vv[j] = mom_load<GS_FP8E4M3>(a.gv, row, j, true);
                             }
                         }
+                        if (a.adamw) {
+                            const int64_t ro = (Wrow - a.step.lut) + d;
 #pragma unroll
-                        for (int j = 0; j < 10; ++j) g[j] = restore1(g[j], mv[j], vv[j], wd, a.lr[j], a.eps, a.rb);
+                            for (int j = 0; j < 10; ++j) {
+                                const float *cb = a.aw_base + (int64_t)a.cls[j] * a.aw_per + ro;
+                                g[j] = restore_w(g[j], mv[j], vv[j], cb[0], cb[a.aw_nW], a.lr[j], a.eps, a.rb);
+                            }
+                        } else {
+#pragma unroll
+                            for (int j = 0; j < 10; ++j)
+                                g[j] = restore1(g[j], mv[j], vv[j], wd, a.lr[j], a.eps, a.rb);
+                        }
                     }
                     ++nrest;
                 }
@@ -708,6 +736,10 @@ struct RowArgs {
     u64 sr_seed;
     int32_t geo_dense;
     int32_t sgd;                     // SGD with momentum: buffer in m, no v
+    int32_t adamw, pad6;             // AdamW: decayed tables of the lane's rate class
+    const float *aw_base;            // first class's tables
+    int64_t aw_per, aw_nW;           // floats per class, floats of one W layout
+    uint8_t cls[64];                 // rate class of each lane
     int32_t *last;
     int64_t n;
     const float *Mf, *Vf, *SS, *BC;
@@ -738,6 +770,7 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
     const bool act = lane < 10 + a.adim && !(isG && a.geo_dense && MODE != kGather);
     const bool grest = !(isG && a.geo_dense);
     const bool sgd = a.sgd != 0;
+    const bool adamw = a.adamw != 0;
     const int ca = lane - 10;
     const int col = isG ? lane : ca;
     const float lr = a.lr[lane];
@@ -746,6 +779,16 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
     const float *Wrow;
     int dmax;
     const int t = resolve_step(a.step, MODE == kFlush ? 1 : 0, &Wrow, &dmax);
+    // AdamW: this lane's rate class tables, same row offset as Wrow
+    const float *WlRow = Wrow, *PRow = Wrow;
+    float qdec = 1.0f;
+    if (adamw) {
+        const float *cb = a.aw_base + (int64_t)a.cls[lane] * a.aw_per;
+        const int64_t ro = Wrow - a.step.lut;
+        WlRow = cb + ro;
+        PRow = cb + a.aw_nW + ro;
+        qdec = cb[2 * a.aw_nW + t];
+    }
 
     int64_t nvis, total;
     if (MODE == kFlush) {
@@ -818,8 +861,11 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
             const int64_t r = id[u];
             if (MODE == kGather) {
                 float x = w[u];
-                if (d[u] > 0 && grest)
-                    x = sgd ? x - (Wrow[d[u]] * lr) * m[u] : restore1(x, m[u], v[u], Wrow[d[u]], lr, a.eps, a.rb);
+                if (d[u] > 0 && grest) {
+                    if (sgd) x = x - (Wrow[d[u]] * lr) * m[u];
+                    else if (adamw) x = restore_w(x, m[u], v[u], WlRow[d[u]], PRow[d[u]], lr, a.eps, a.rb);
+                    else x = restore1(x, m[u], v[u], Wrow[d[u]], lr, a.eps, a.rb);
+                }
                 if (act) {
                     if (isG) {
                         if (a.out_geo) a.out_geo[(base + u) * 10 + lane] = x;
@@ -853,12 +899,24 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
                     m1 = a.Mf[dd] * m[u] + g[u];
                     v1 = 0.0f;
                     x = x - step * m1;
+                } else if (MODE == kAdam && adamw) {
+                    // AdamW: decayed catch-up, Adam moments, w = q_t w - step
+                    x = w[u];
+                    if (dd > 0) x = restore_w(x, m[u], v[u], WlRow[dd], PRow[dd], lr, a.eps, a.rb);
+                    m1 = a.Mf[dd] * m[u] + a.omb1 * g[u];
+                    v1 = a.Vf[dd] * v[u] + (a.omb2 * g[u]) * g[u];
+                    const float xq = qdec * x;
+                    x = xq - adam_step(m1, v1, step, bc, a.eps, a.rb);
                 } else if (MODE == kAdam) {
                     x = w[u];
                     if (dd > 0) x = restore1(x, m[u], v[u], Wrow[dd], lr, a.eps, a.rb);
                     m1 = a.Mf[dd] * m[u] + a.omb1 * g[u];
                     v1 = a.Vf[dd] * v[u] + (a.omb2 * g[u]) * g[u];
                     x = x - adam_step(m1, v1, step, bc, a.eps, a.rb);
+                } else if (adamw) {
+                    x = restore_w(w[u], m[u], v[u], WlRow[dd], PRow[dd], lr, a.eps, a.rb);
+                    m1 = a.Mf[dd - 1] * m[u];
+                    v1 = a.Vf[dd - 1] * v[u];
                 } else if (sgd) {
                     x = w[u] - (Wrow[dd] * lr) * m[u];
                     m1 = a.Mf[dd - 1] * m[u];
@@ -1153,6 +1211,8 @@ int check_group(const gs_group &g, int64_t n, bool geo)
     return GS_OK;
 }
 
+int decay_classes(const gs_model *m, float *rates, uint8_t *cls);
+
 int check_model(const gs_model *m)
 {
     if (!m) return GS_EINVAL;
@@ -1168,10 +1228,15 @@ int check_model(const gs_model *m)
     if (m->cull_mode != 0 && m->cull_mode != 1) return GS_EINVAL;
     if (m->geo_mode != 0 && m->geo_mode != 1) return GS_EINVAL;
     if (m->geo_mode == 1 && m->geo.state == GS_FP8E4M3) return GS_EUNSUPPORTED;
-    if (m->optimizer != GS_OPT_ADAM && m->optimizer != GS_OPT_SGD_MOMENTUM) return GS_EINVAL;
-    if (m->optimizer == GS_OPT_SGD_MOMENTUM &&
+    if (m->optimizer != GS_OPT_ADAM && m->optimizer != GS_OPT_SGD_MOMENTUM && m->optimizer != GS_OPT_ADAMW)
+        return GS_EINVAL;
+    if (m->optimizer != GS_OPT_ADAM &&
         (m->geo_mode != 0 || m->geo.state == GS_FP8E4M3 || m->app.state == GS_FP8E4M3))
         return GS_EUNSUPPORTED;
+    if (m->optimizer == GS_OPT_ADAMW) {
+        float rates[gsdp::kMaxDecayClasses];
+        if (decay_classes(m, rates, nullptr) < 0) return GS_EUNSUPPORTED;
+    }
     return GS_OK;
 }
 
@@ -1213,6 +1278,29 @@ int dmax_for(const gs_model *m, int64_t t_row)
     return (int)dm;
 }
 
+// AdamW decay classes: the distinct column rates in order of first
+// appearance (G columns 0..9, then A columns); cls[lane] is the class of the
+// column lane (0..9 G, 10.. A).  Returns the number of classes, -1 if > 8.
+int decay_classes(const gs_model *m, float *rates, uint8_t *cls)
+{
+    int nc = 0;
+    for (int lane = 0; lane < 64; ++lane) {
+        if (cls) cls[lane] = 0;
+        float r;
+        if (lane < 10) r = m->geo.lr[lane];
+        else if (lane - 10 < m->app.dim) r = m->app.lr[lane - 10];
+        else continue;
+        int c = 0;
+        while (c < nc && memcmp(&rates[c], &r, sizeof r) != 0) ++c;
+        if (c == nc) {
+            if (nc == gsdp::kMaxDecayClasses) return -1;
+            rates[nc++] = r;
+        }
+        if (cls) cls[lane] = (uint8_t)c;
+    }
+    return nc;
+}
+
 void fill_rows(RowArgs &a, const gs_model *m)
 {
     memset(&a, 0, sizeof a);
@@ -1234,6 +1322,14 @@ void fill_rows(RowArgs &a, const gs_model *m)
     a.sr_seed = m->sr_seed;
     a.geo_dense = m->geo_mode == 1;
     a.sgd = m->optimizer == GS_OPT_SGD_MOMENTUM;
+    a.adamw = m->optimizer == GS_OPT_ADAMW;
+    if (a.adamw) {
+        float rates[gsdp::kMaxDecayClasses];
+        decay_classes(m, rates, a.cls);
+        a.aw_base = static_cast<const float *>(m->lut) + gsdp::lut_layout(m->lut_max_steps, m->max_defer).total;
+        a.aw_per = gsdp::adamw_class_floats(m->lut_max_steps, m->max_defer);
+        a.aw_nW = gsdp::lut_layout(m->lut_max_steps, m->max_defer).nW;
+    }
     a.last = m->last_step;
     a.n = m->n;
 }
@@ -1818,6 +1914,55 @@ int gs_lut_build_sgd_momentum(double momentum, int32_t max_steps, int32_t max_de
     return e == hipSuccess ? GS_OK : hip_fail(e, "gs_lut_build_sgd_momentum: hipMemcpy");
 }
 
+int gs_lut_bytes_adamw(const gs_model *model, size_t *bytes)
+{
+    if (!model || !bytes) return GS_EINVAL;
+    size_t base = 0;
+    int rc = gs_lut_bytes(model->lut_max_steps, model->max_defer, &base);
+    if (rc) return rc;
+    float rates[gsdp::kMaxDecayClasses];
+    const int nc = decay_classes(model, rates, nullptr);
+    if (nc < 0) return GS_EUNSUPPORTED;
+    *bytes = sizeof(float) * (size_t)gsdp::adamw_total_floats(model->lut_max_steps, model->max_defer, nc);
+    return GS_OK;
+}
+
+int gs_lut_build_adamw_host(const gs_model *model, double weight_decay, const double *lr_scale, void *lut_host,
+                            size_t bytes)
+{
+    size_t need = 0;
+    int rc = gs_lut_bytes_adamw(model, &need);
+    if (rc) return rc;
+    if (!lut_host || !(weight_decay >= 0.0) || !std::isfinite(weight_decay)) return GS_EINVAL;
+    if (!(model->beta1 > 0.0 && model->beta1 < 1.0 && model->beta2 > 0.0 && model->beta2 < 1.0)) return GS_EINVAL;
+    if (bytes < need) return GS_ESPACE;
+    const int32_t T = model->lut_max_steps;
+    if (lr_scale)
+        for (int64_t t = 0; t <= (int64_t)T + 1; ++t)
+            if (!(lr_scale[t] >= 0.0) || !std::isfinite(lr_scale[t])) return GS_EINVAL;
+    float rates[gsdp::kMaxDecayClasses];
+    const int nc = decay_classes(model, rates, nullptr);
+    return gsdp::build_lut_adamw_host(model->beta1, model->beta2, weight_decay, rates, nc, T, model->max_defer,
+                                      lr_scale, static_cast<float *>(lut_host), (int64_t)(bytes / sizeof(float))) == 0
+               ? GS_OK
+               : GS_ESPACE;
+}
+
+int gs_lut_build_adamw(const gs_model *model, double weight_decay, const double *lr_scale, void *lut_dev,
+                       size_t bytes)
+{
+    size_t need = 0;
+    int rc = gs_lut_bytes_adamw(model, &need);
+    if (rc) return rc;
+    if (!lut_dev) return GS_EINVAL;
+    if (bytes < need) return GS_ESPACE;
+    std::vector<float> host(need / sizeof(float));
+    rc = gs_lut_build_adamw_host(model, weight_decay, lr_scale, host.data(), need);
+    if (rc) return rc;
+    hipError_t e = hipMemcpy(lut_dev, host.data(), need, hipMemcpyHostToDevice);
+    return e == hipSuccess ? GS_OK : hip_fail(e, "gs_lut_build_adamw: hipMemcpy");
+}
+
 int gs_workspace_bytes(const gs_model *model, size_t *bytes)
 {
     if (!model || !bytes || model->n < 0 || model->max_defer < 0) return GS_EINVAL;
@@ -1853,7 +1998,19 @@ int gs_cull(const gs_model *model, const gs_camera *cam, int64_t step, uint32_t 
     a.mode = (model->cull_mode == 1 && model->eps > 0.0 && std::isfinite(a.rb)) ? 1 : 0;
     // the band bound rests on |m|/sqrt(v) <= rb, which a momentum buffer lacks
     a.sgd = model->optimizer == GS_OPT_SGD_MOMENTUM;
-    if (a.sgd) a.mode = 0;
+    // with weight decay a restore also moves w by (1 - P) |w|, outside the band bound
+    a.adamw = model->optimizer == GS_OPT_ADAMW;
+    if (a.sgd || a.adamw) a.mode = 0;
+    if (a.adamw) {
+        float rates[gsdp::kMaxDecayClasses];
+        uint8_t cls[64];
+        decay_classes(model, rates, cls);
+        for (int j = 0; j < 10; ++j) a.cls[j] = cls[j];
+        a.aw_base = static_cast<const float *>(model->lut) +
+                    gsdp::lut_layout(model->lut_max_steps, model->max_defer).total;
+        a.aw_per = gsdp::adamw_class_floats(model->lut_max_steps, model->max_defer);
+        a.aw_nW = gsdp::lut_layout(model->lut_max_steps, model->max_defer).nW;
+    }
     pack_camera(model, cam, a.cam, a.band);
     a.geo_dense = model->geo_mode == 1;
     a.K = model->max_defer;

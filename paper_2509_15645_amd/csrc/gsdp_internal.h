@@ -30,6 +30,16 @@ inline LutLayout lut_layout(int64_t T, int64_t K)
     return L;
 }
 
+// AdamW tables follow the Adam tables (whose Mf, Vf, SS, BC they share): for
+// every decay class c (a distinct column rate) the decayed restore rows Wl and
+// the decay products P (both in the W row layout) and the step decays q[t].
+constexpr int kMaxDecayClasses = 8;
+inline int64_t adamw_class_floats(int64_t T, int64_t K) { return 2 * lut_layout(T, K).nW + (T + 2); }
+inline int64_t adamw_total_floats(int64_t T, int64_t K, int nclass)
+{
+    return lut_layout(T, K).total + nclass * adamw_class_floats(T, K);
+}
+
 // Offset of W row t (t >= 1).
 inline int64_t lut_w_row(int64_t t, int64_t K) { return K > 0 ? (t - 1) * (K + 1) : t * (t - 1) / 2; }
 
@@ -77,5 +87,7 @@ inline int64_t ws_bytes_for(int64_t n, int32_t K, int32_t fp8)
 
 int build_lut_host(double b1, double b2, int32_t T, int32_t K, const double *sched, float *out, int64_t nfloats);
 int build_lut_sgdm_host(double mu, int32_t T, int32_t K, const double *sched, float *out, int64_t nfloats);
+int build_lut_adamw_host(double b1, double b2, double lam, const float *rates, int nclass, int32_t T, int32_t K,
+                         const double *sched, float *out, int64_t nfloats);
 
 }  // namespace gsdp

@@ -93,4 +93,52 @@ int build_lut_sgdm_host(double mu, int32_t T, int32_t K, const double *sched, fl
     return 0;
 }
 
+// AdamW: every step k first scales w by q_k = 1 - lr s[k] lambda, so the
+// catch-up of d skipped steps is w P[d] - lr (m/(sqrt(v)+eps)) Wl[d] with
+//   Wl[d] = r Wl[d-1] + P[d-1] s[t-d] c(t-d),   P[d] = P[d-1] q_{t-d},
+// and step t scales by q_t before its Adam update.  The tables depend on the
+// column rate through q: one set per decay class (distinct rate).
+int build_lut_adamw_host(double b1, double b2, double lam, const float *rates, int nclass, int32_t T, int32_t K,
+                         const double *sched, float *out, int64_t nfloats)
+{
+    const LutLayout L = lut_layout(T, K);
+    if (nfloats < adamw_total_floats(T, K, nclass)) return -1;
+    if (build_lut_host(b1, b2, T, K, sched, out, L.total) != 0) return -1;
+    std::vector<double> P1(T + 2), P2(T + 2), Ck(T + 2, 0.0);
+    P1[0] = 1.0;
+    P2[0] = 1.0;
+    for (int64_t k = 1; k <= T + 1; ++k) {
+        P1[k] = P1[k - 1] * b1;
+        P2[k] = P2[k - 1] * b2;
+    }
+    for (int64_t k = 1; k <= T; ++k) {
+        Ck[k] = b1 / (std::sqrt(b2 / (1.0 - P2[k])) * (1.0 - P1[k]));
+        if (sched) Ck[k] = sched[k] * Ck[k];
+    }
+    const double r = b1 / std::sqrt(b2);
+    for (int c = 0; c < nclass; ++c) {
+        const double lr = (double)rates[c];
+        float *base = out + L.total + c * adamw_class_floats(T, K);
+        float *Wl = base, *P = base + L.nW, *q = base + 2 * L.nW;
+        for (int64_t i = 0; i < 2 * L.nW + T + 2; ++i) base[i] = 0.0f;
+        for (int64_t t = 1; t <= T + 1; ++t) {
+            float *wrow = Wl + lut_w_row(t, K), *prow = P + lut_w_row(t, K);
+            int64_t dm = t - 1;
+            if (K > 0 && dm > K) dm = K;
+            double W = 0.0, Pd = 1.0;
+            wrow[0] = 0.0f;
+            prow[0] = 1.0f;
+            for (int64_t d = 1; d <= dm; ++d) {
+                const int64_t k = t - d;
+                W = r * W + Pd * Ck[k];
+                Pd = Pd * (1.0 - lr * (sched ? sched[k] : 1.0) * lam);
+                wrow[d] = (float)W;
+                prow[d] = (float)Pd;
+            }
+        }
+        for (int64_t t = 0; t <= T + 1; ++t) q[t] = (float)(1.0 - lr * (sched ? sched[t] : 1.0) * lam);
+    }
+    return 0;
+}
+
 }  // namespace gsdp

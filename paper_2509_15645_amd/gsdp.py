@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(PKG, "libgsdp.so")
 
 GS_OK, GS_EINVAL, GS_EHIP, GS_EUNSUPPORTED, GS_ESPACE = 0, -1, -2, -3, -4
 GS_F32, GS_BF16, GS_FP8E4M3 = 0, 1, 2
-GS_OPT_ADAM, GS_OPT_SGD_MOMENTUM = 0, 2
+GS_OPT_ADAM, GS_OPT_ADAMW, GS_OPT_SGD_MOMENTUM = 0, 1, 2
 
 # exported C symbols (kept in sync with include/gsdp.h)
 SYMBOLS = ("gs_lut_bytes", "gs_lut_build", "gs_lut_build_host", "gs_lut_build_schedule",
@@ -28,7 +28,7 @@ SYMBOLS = ("gs_lut_bytes", "gs_lut_build", "gs_lut_build_host", "gs_lut_build_sc
            "gs_device_cu_count", "gs_status_string", "gs_last_hip_error", "gs_step_advance",
            "gs_camera_pack_bytes", "gs_camera_pack", "gs_multi_workspace_bytes", "gs_cull_multi",
            "gs_cull_multi_autotune", "gs_grad_sum_multi", "gs_plan_image_split", "gs_lut_build_sgd_momentum",
-           "gs_lut_build_sgd_momentum_host")
+           "gs_lut_build_sgd_momentum_host", "gs_lut_bytes_adamw", "gs_lut_build_adamw", "gs_lut_build_adamw_host")
 
 
 class GsCamera(C.Structure):
@@ -75,6 +75,9 @@ def _load():
         "gs_lut_build_schedule_host": (C.c_int, [f64, f64, i32, i32, vp, vp, sz]),
         "gs_lut_build_sgd_momentum": (C.c_int, [f64, i32, i32, vp, vp, sz]),
         "gs_lut_build_sgd_momentum_host": (C.c_int, [f64, i32, i32, vp, vp, sz]),
+        "gs_lut_bytes_adamw": (C.c_int, [P(GsModel), P(sz)]),
+        "gs_lut_build_adamw": (C.c_int, [P(GsModel), f64, vp, vp, sz]),
+        "gs_lut_build_adamw_host": (C.c_int, [P(GsModel), f64, vp, vp, sz]),
         "gs_workspace_bytes": (C.c_int, [P(GsModel), P(sz)]),
         "gs_cull": (C.c_int, [P(GsModel), P(GsCamera), i64, vp, vp, u32, vp, sz, vp]),
         "gs_gather": (C.c_int, [P(GsModel), i64, vp, vp, u32, vp, vp, vp]),
@@ -211,7 +214,7 @@ class Model:
 
     def __init__(self, geo, app, lr_geo, lr_app, *, beta1=0.9, beta2=0.999, eps=1e-15, max_defer=0,
                  max_steps=1000, cull_mode=0, app_layout="separate", geo_state="f32", app_state="f32",
-                 sr_seed=0, geo_mode=0, lr_scale=None, optimizer="adam", device=None):
+                 sr_seed=0, geo_mode=0, lr_scale=None, optimizer="adam", weight_decay=0.0, device=None):
         device = device or torch.device("cuda")
         geo = torch.as_tensor(geo, dtype=torch.float32)
         app = torch.as_tensor(app, dtype=torch.float32)
@@ -273,18 +276,9 @@ class Model:
         self.app_ms, self.app_vs = zs(acode), zs(acode)
         self.last_step = torch.zeros(n, dtype=torch.int32, device=device)
         self.max_steps, self.max_defer = int(max_steps), int(max_defer)
-        self.lut = torch.empty(gs_lut_bytes(self.max_steps, self.max_defer) // 4, dtype=torch.float32,
-                               device=device)
         self.optimizer = optimizer
-        if optimizer == "sgd_momentum":
-            # beta1 is the momentum; the v buffers are allocated but unused
-            gs_lut_build_sgd_momentum(beta1, self.max_steps, self.max_defer, lr_scale, self.lut)
-        elif optimizer != "adam":
+        if optimizer not in ("adam", "adamw", "sgd_momentum"):
             raise ValueError(optimizer)
-        elif lr_scale is None:
-            gs_lut_build(beta1, beta2, self.max_steps, self.max_defer, self.lut)
-        else:
-            gs_lut_build_schedule(beta1, beta2, self.max_steps, self.max_defer, lr_scale, self.lut)
         self.lr_geo = np.asarray(lr_geo, np.float32)
         self.lr_app = np.asarray(lr_app, np.float32)
 
@@ -304,14 +298,31 @@ class Model:
             for k in range(dim):
                 grp.lr[k] = float(lr[k])
         c.last_step = self.last_step.data_ptr()
-        c.lut = self.lut.data_ptr()
         c.lut_max_steps = self.max_steps
         c.max_defer = self.max_defer
         c.beta1, c.beta2, c.eps = float(beta1), float(beta2), float(eps)
         c.cull_mode = int(cull_mode)
         c.sr_seed = int(sr_seed)
         c.geo_mode = int(geo_mode)
-        c.optimizer = GS_OPT_SGD_MOMENTUM if optimizer == "sgd_momentum" else GS_OPT_ADAM
+        c.optimizer = {"adam": GS_OPT_ADAM, "adamw": GS_OPT_ADAMW, "sgd_momentum": GS_OPT_SGD_MOMENTUM}[optimizer]
+        if optimizer == "adamw":
+            b = C.c_size_t()
+            _check(lib.gs_lut_bytes_adamw(C.byref(c), C.byref(b)), "gs_lut_bytes_adamw")
+            self.lut = torch.empty(b.value // 4, dtype=torch.float32, device=device)
+            sc = None if lr_scale is None else np.ascontiguousarray(lr_scale, np.float64)
+            _check(lib.gs_lut_build_adamw(C.byref(c), float(weight_decay), None if sc is None else sc.ctypes.data,
+                                          _ptr(self.lut), b.value), "gs_lut_build_adamw")
+        else:
+            self.lut = torch.empty(gs_lut_bytes(self.max_steps, self.max_defer) // 4, dtype=torch.float32,
+                                   device=device)
+            if optimizer == "sgd_momentum":
+                # beta1 is the momentum; the v buffers are allocated but unused
+                gs_lut_build_sgd_momentum(beta1, self.max_steps, self.max_defer, lr_scale, self.lut)
+            elif lr_scale is None:
+                gs_lut_build(beta1, beta2, self.max_steps, self.max_defer, self.lut)
+            else:
+                gs_lut_build_schedule(beta1, beta2, self.max_steps, self.max_defer, lr_scale, self.lut)
+        c.lut = self.lut.data_ptr()
         # device step counter for graph replay (calls with step == 0 read it)
         self.step_dev = torch.zeros(1, dtype=torch.int32, device=device)
         c.step_dev = self.step_dev.data_ptr()

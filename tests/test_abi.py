@@ -175,3 +175,50 @@ def test_host_sgd_momentum_tables_equal_oracle_bitwise(gsdp, max_defer, sched):
         assert lut[offSS + t].view(np.uint32) == np.float32(ss).view(np.uint32)
     small = np.zeros(4, np.float32)
     assert gsdp.lib.gs_lut_build_sgd_momentum_host(1.0, 10, 0, None, small.ctypes.data, 16) == gsdp.GS_EINVAL
+
+
+@pytest.mark.parametrize("max_defer,sched", [(0, False), (15, True)])
+def test_host_adamw_tables_equal_oracle_bitwise(gsdp, max_defer, sched):
+    import gs_inputs as gi
+    T, lam = 70, 0.05
+    lg, la = gi.lr_columns()
+    m = gsdp.GsModel()
+    m.n = 10
+    m.geo.dim, m.app.dim = 10, 49
+    for k in range(10):
+        m.geo.lr[k] = float(lg[k])
+    for k in range(49):
+        m.app.lr[k] = float(la[k])
+    m.lut_max_steps, m.max_defer = T, max_defer
+    m.beta1, m.beta2 = 0.9, 0.999
+    m.optimizer = gsdp.GS_OPT_ADAMW
+    sc = None
+    if sched:
+        rng = np.random.default_rng(3)
+        sc = 0.01 ** (np.arange(T + 2) / (T + 1)) * rng.uniform(0.5, 2.0, T + 2)
+    b = C.c_size_t()
+    assert gsdp.lib.gs_lut_bytes_adamw(C.byref(m), C.byref(b)) == 0
+    out = np.zeros(b.value // 4, np.float32)
+    scp = None if sc is None else np.ascontiguousarray(sc).ctypes.data
+    assert gsdp.lib.gs_lut_build_adamw_host(C.byref(m), lam, scp, out.ctypes.data, b.value) == 0
+    K = max_defer
+    rows = T + 1
+    nW = rows * (K + 1) if K else rows * (rows + 1) // 2
+    nMV = (K if K else T) + 1
+    base = nW + 2 * nMV + 2 * (T + 2)
+    per = 2 * nW + T + 2
+    rates = [np.float32(lg[0]), np.float32(lg[3])]          # classes in order of first appearance
+    assert b.value // 4 == base + len(rates) * per
+    for c, r in enumerate(rates):
+        for t in [1, 2, 16, 17, 40, T, T + 1]:
+            row = (t - 1) * (K + 1) if K else t * (t - 1) // 2
+            dmax = min(t - 1, K) if K else t - 1
+            Wf, Pf, qt = orc.lut_adamw_spec(0.9, 0.999, lam, r, t, dmax, sc)
+            cb = base + c * per
+            assert np.array_equal(out[cb + row:cb + row + dmax + 1].view(np.uint32), Wf.view(np.uint32)), (c, t)
+            assert np.array_equal(out[cb + nW + row:cb + nW + row + dmax + 1].view(np.uint32), Pf.view(np.uint32))
+            assert out[cb + 2 * nW + t].view(np.uint32) == np.float32(qt).view(np.uint32)
+    # too many distinct rates are rejected
+    for k in range(10):
+        m.geo.lr[k] = 1e-3 * (k + 1)
+    assert gsdp.lib.gs_lut_bytes_adamw(C.byref(m), C.byref(b)) == gsdp.GS_EUNSUPPORTED

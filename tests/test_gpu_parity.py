@@ -303,15 +303,18 @@ def test_small_workload_path_vs_oracle(g, max_defer, layout, grad_mode, cull_mod
     assert model.ws_header()["error"] == 0
 
 
-@pytest.mark.parametrize("max_defer,layout,states,sched", [
-    (0, "interleaved", ("f32", "f32"), False),
-    (15, "separate", ("f32", "f32"), True),
-    (0, "fused", ("bf16", "bf16"), True),
+@pytest.mark.parametrize("opt,max_defer,layout,states,sched", [
+    ("sgd_momentum", 0, "interleaved", ("f32", "f32"), False),
+    ("sgd_momentum", 15, "separate", ("f32", "f32"), True),
+    ("sgd_momentum", 0, "fused", ("bf16", "bf16"), True),
+    ("adamw", 0, "interleaved", ("f32", "f32"), True),
+    ("adamw", 15, "separate", ("bf16", "f32"), False),
 ])
-def test_small_workload_sgd_momentum_vs_oracle(g, max_defer, layout, states, sched):
-    """Deferred SGD with momentum (the momentum-optimizer extension): ids,
-    gathered rows and stored state bit-exact vs the FP32 oracle model every
-    step and after the flush; FP32 state within 1e-6 of dense FP64 SGD."""
+def test_small_workload_optimizer_variants_vs_oracle(g, opt, max_defer, layout, states, sched):
+    """Deferred SGD with momentum and deferred AdamW (the optimizer extensions
+    of Sec. 4.3): ids, gathered rows and stored state bit-exact vs the FP32
+    oracle model every step and after the flush; FP32 state within 1e-6 of the
+    dense FP64 definition."""
     w = gi.workload("small")
     sc = gi.make_scene(w.n, seed=0, box=w.scene_box)
     lg, la = gi.lr_columns()
@@ -319,13 +322,18 @@ def test_small_workload_sgd_momentum_vs_oracle(g, max_defer, layout, states, sch
     if sched:
         rng = np.random.default_rng(4)
         lr_scale = 0.01 ** (np.arange(34) / 33.0) * rng.uniform(0.5, 2.0, 34)
-    mu = 0.9
+    mu, lam = 0.9, 0.05
     model = g.Model(sc.geo, sc.app, lg, la, beta1=mu, max_steps=32, max_defer=max_defer, app_layout=layout,
                     cull_mode=1, geo_state=states[0], app_state=states[1], sr_seed=5, lr_scale=lr_scale,
-                    optimizer="sgd_momentum")
-    o3 = orc.DeferredSGDMF32(sc.geo, sc.app, lg, la, mu=mu, max_defer=max_defer, state=states[0],
-                             app_state=states[1], sr_seed=5, sched=lr_scale)
-    dense = orc.DenseSGDMF64(sc.geo, sc.app, lg, la, mu=mu, sched=lr_scale)
+                    optimizer=opt, weight_decay=lam)
+    if opt == "sgd_momentum":
+        o3 = orc.DeferredSGDMF32(sc.geo, sc.app, lg, la, mu=mu, max_defer=max_defer, state=states[0],
+                                 app_state=states[1], sr_seed=5, sched=lr_scale)
+        dense = orc.DenseSGDMF64(sc.geo, sc.app, lg, la, mu=mu, sched=lr_scale)
+    else:
+        o3 = orc.DeferredAdamWF32(sc.geo, sc.app, lg, la, weight_decay=lam, max_defer=max_defer, state=states[0],
+                                  app_state=states[1], sr_seed=5, sched=lr_scale)
+        dense = orc.DenseAdamWF64(sc.geo, sc.app, lg, la, weight_decay=lam, sched=lr_scale)
     n = w.n
     out_g = torch.zeros((n, 10), dtype=torch.float32, device="cuda")
     out_a = torch.zeros((n, 49), dtype=torch.float32, device="cuda")
@@ -333,7 +341,8 @@ def test_small_workload_sgd_momentum_vs_oracle(g, max_defer, layout, states, sch
     def compare(tag):
         st = model.state()
         for k, name in ((0, "geo"), (1, "app")):
-            for part, ref in (("w", o3.w[k]), ("m", o3.m[k])):
+            parts = [("w", o3.w[k]), ("m", o3.m[k])] + ([("v", o3.v[k])] if opt == "adamw" else [])
+            for part, ref in parts:
                 assert np.array_equal(bits(st[f"{name}_{part}"]), bits(ref)), f"{tag}: {name}_{part}"
 
     for t in range(1, w.steps + 1):
@@ -353,7 +362,7 @@ def test_small_workload_sgd_momentum_vs_oracle(g, max_defer, layout, states, sch
         if t % 5 == 0:
             compare(f"step {t}")
             assert np.array_equal(model.last_step.cpu().numpy(), o3.last_step(t))
-        say(f"[sgd-momentum K={max_defer} {layout} {states}] step {t}: M={m}")
+        say(f"[{opt} K={max_defer} {layout} {states}] step {t}: M={m}")
     g.gs_adam_flush(model, w.steps)
     o3.flush(w.steps)
     compare("after flush")
@@ -361,7 +370,7 @@ def test_small_workload_sgd_momentum_vs_oracle(g, max_defer, layout, states, sch
         st = model.state()
         e_geo = np.abs(st["geo_w"] - dense.w[0]) / np.maximum(np.abs(dense.w[0]), TAU_GEO)
         e_app = np.abs(st["app_w"] - dense.w[1]) / np.maximum(np.abs(dense.w[1]), TAU_APP)
-        say(f"[sgd-momentum] vs dense FP64: geo max {e_geo.max():.3e}; app max {e_app.max():.3e}")
+        say(f"[{opt}] vs dense FP64: geo max {e_geo.max():.3e}; app max {e_app.max():.3e}")
         assert e_geo.max() <= 1e-6 and e_app.max() <= 1e-6
 
 
