@@ -1031,3 +1031,109 @@ void orc_adamw_flush_rows_f32(int dim, float *w, void *m, void *v, int state, in
         }
     }
 }
+
+/* ------------------------------------------------------------------------ */
+/* Densification (Sec. 2.4 step 7: Gaussians with large accumulated gradients
+ * are cloned or split, low-opacity ones pruned), with the procedure of 3D
+ * Gaussian Splatting the paper builds on.  Per row i on current FP32 values:
+ *   g      = accum/denom (0 when denom = 0);  grad = g >= grad_thr
+ *   smax   = largest of the three log-scales
+ *   clone  = grad and smax <= log_dense;   split = grad and smax > log_dense
+ *   low    = opacity logit < logit_min;    big = big_on and smax > log_big
+ *   screen = radii given, max_screen > 0 and radii > max_screen (originals only)
+ *   kept original: not split, not low, not big, not screen
+ *   kept clone (a copy):   clone, not low, not big
+ *   kept children (two):   split, not low, not big on the child's scales
+ * A child j of row i has scales s - log_split and position
+ *   mu + Q (exp(s) * z),  z_a = normal-approximation draw of (seed, i, j, a),
+ * Q the rotation of the normalised quaternion (same expressions as the cull).
+ * Output order: kept originals, kept clones, kept children (parent order,
+ * child 0 before child 1), as 3DGS's append-then-prune leaves them.
+ * Returns the number of output rows (capacity permitting, rows past cap are
+ * only counted); counts[3] = originals, clones, children. */
+static float split_normal(uint64_t seed, int64_t row, int child, int axis)
+{
+    uint64_t h = sm_at(sm_at(sm_at(seed, (uint64_t)row), (uint64_t)child), (uint64_t)axis);
+    uint64_t u = (h & 0xffffull) + ((h >> 16) & 0xffffull) + ((h >> 32) & 0xffffull) + ((h >> 48) & 0xffffull);
+    const double inv_sd = 1.0 / sqrt(4.0 * (65536.0 * 65536.0 - 1.0) / 12.0);
+    return (float)(((double)u - 131070.0) * inv_sd);
+}
+
+int64_t orc_densify(int64_t n, int adim, const float *geo, const float *app, const float *accum,
+                    const float *denom, const float *radii, float grad_thr, float log_dense, int big_on,
+                    float log_big, float logit_min, float max_screen, float log_split, uint64_t seed,
+                    int64_t cap, float *out_geo, float *out_app, int64_t *src, uint8_t *kind, int64_t *counts)
+{
+    uint8_t *code = (uint8_t *)malloc((size_t)(n > 0 ? n : 1));
+    int64_t nk = 0, nc = 0, ns = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        const float *g = geo + i * 10;
+        float gr = denom[i] > 0.0f ? accum[i] / denom[i] : 0.0f;
+        int grad = gr >= grad_thr;
+        float smax = g[3];
+        if (g[4] > smax) smax = g[4];
+        if (g[5] > smax) smax = g[5];
+        int clone = grad && (smax <= log_dense);
+        int split = grad && (smax > log_dense);
+        int low = app[i * adim] < logit_min;  /* opacity logit: appearance column 0 */
+        int big = big_on && (smax > log_big);
+        int screen = radii && max_screen > 0.0f && radii[i] > max_screen;
+        float cmax = smax - log_split;
+        int cbig = big_on && (cmax > log_big);
+        uint8_t c = 0;
+        if (!split && !low && !big && !screen) { c |= 1; ++nk; }
+        if (clone && !low && !big) { c |= 2; ++nc; }
+        if (split && !low && !cbig) { c |= 4; ns += 2; }
+        code[i] = c;
+    }
+    counts[0] = nk; counts[1] = nc; counts[2] = ns;
+    int64_t pos[3] = {0, nk, nk + nc};
+    for (int pass = 0; pass < 3; ++pass) {
+        for (int64_t i = 0; i < n; ++i) {
+            if (!(code[i] & (1 << pass))) continue;
+            const float *g = geo + i * 10;
+            int nchild = pass == 2 ? 2 : 1;
+            for (int j = 0; j < nchild; ++j) {
+                int64_t o = pos[pass]++;
+                if (o >= cap) continue;
+                float *og = out_geo + o * 10;
+                for (int k = 0; k < 10; ++k) og[k] = g[k];
+                for (int k = 0; k < adim; ++k) out_app[o * adim + k] = app[i * adim + k];
+                src[o] = i;
+                kind[o] = (uint8_t)(pass == 2 ? 2 + j : pass);
+                if (pass != 2) continue;
+                float qw = g[6], qx = g[7], qy = g[8], qz = g[9];
+                float n2 = ((qw * qw + qx * qx) + qy * qy) + qz * qz;
+                float inv = 1.0f / sqrtf(n2);
+                qw = qw * inv; qx = qx * inv; qy = qy * inv; qz = qz * inv;
+                float Q[9];
+                Q[0] = 1.0f - 2.0f * (qy * qy + qz * qz);
+                Q[1] = 2.0f * (qx * qy - qw * qz);
+                Q[2] = 2.0f * (qx * qz + qw * qy);
+                Q[3] = 2.0f * (qx * qy + qw * qz);
+                Q[4] = 1.0f - 2.0f * (qx * qx + qz * qz);
+                Q[5] = 2.0f * (qy * qz - qw * qx);
+                Q[6] = 2.0f * (qx * qz - qw * qy);
+                Q[7] = 2.0f * (qy * qz + qw * qx);
+                Q[8] = 1.0f - 2.0f * (qx * qx + qy * qy);
+                float v[3];
+                for (int a = 0; a < 3; ++a) v[a] = orc_exp_gs(g[3 + a]) * split_normal(seed, i, j, a);
+                for (int a = 0; a < 3; ++a)
+                    og[a] = g[a] + ((Q[3 * a] * v[0] + Q[3 * a + 1] * v[1]) + Q[3 * a + 2] * v[2]);
+                for (int a = 0; a < 3; ++a) og[3 + a] = g[3 + a] - log_split;
+            }
+        }
+    }
+    free(code);
+    return nk + nc + ns;
+}
+
+/* Thresholds of the densification criteria, computed in FP64 and rounded
+ * once: log(percent_dense extent), log(0.1 extent), logit(min_opacity), log(1.6). */
+void orc_densify_thresholds(double percent_dense, double extent, double min_opacity, float *out4)
+{
+    out4[0] = (float)log(percent_dense * extent);
+    out4[1] = (float)log(0.1 * extent);
+    out4[2] = (float)log(min_opacity / (1.0 - min_opacity));
+    out4[3] = (float)log(1.6);
+}

@@ -103,6 +103,9 @@ def lib():
                                                   f32, vp]),
             "orc_adamw_flush_rows_f32": (None, [i32, vp, vp, vp, i32, i64, i64, vp, vp, vp, f64, vp, vp, i64, vp,
                                                 vp, f32, C.c_uint64, i64, i32]),
+            "orc_densify": (i64, [i64, i32, vp, vp, vp, vp, vp, f32, f32, i32, f32, f32, f32, f32, C.c_uint64,
+                                  i64, vp, vp, vp, vp, vp]),
+            "orc_densify_thresholds": (None, [f64, f64, f64, vp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -764,6 +767,35 @@ class DeferredAdamWF32(_Deferred):
                                            rows.shape[0], _p(rows32), _p(delta), _p(self.lr[k]), self.eps, _p(W),
                                            _p(P), dm + 1, _p(Mf), _p(Vf), self.rb, self.sr_seed, t_done, self.col0[k])
         self.counter[:] = 0
+
+
+# ---------------------------------------------------------------------------
+# densification (Sec. 2.4 step 7, the 3DGS procedure)
+# ---------------------------------------------------------------------------
+def densify_thresholds(percent_dense, extent, min_opacity):
+    """FP32 (log_dense, log_big, logit_min, log_split) from FP64 logs."""
+    out = np.zeros(4, np.float32)
+    lib().orc_densify_thresholds(percent_dense, extent, min_opacity, _p(out))
+    return out
+
+
+def densify(geo, app, accum, denom, radii=None, grad_thr=2e-4, percent_dense=0.01, extent=100.0,
+            min_opacity=0.005, prune_big=True, max_screen=0.0, seed=0):
+    """Densify current FP32 rows.  Returns (geo_out, app_out, src, kind, counts):
+    src = source row, kind 0 original, 1 clone, 2/3 split child 0/1."""
+    geo = np.ascontiguousarray(geo, np.float32)
+    app = np.ascontiguousarray(app, np.float32)
+    n, adim = geo.shape[0], app.shape[1]
+    th = densify_thresholds(percent_dense, extent, min_opacity)
+    cap = 3 * n + 1
+    og = np.zeros((cap, 10), np.float32); oa = np.zeros((cap, adim), np.float32)
+    src = np.zeros(cap, np.int64); kind = np.zeros(cap, np.uint8); counts = np.zeros(3, np.int64)
+    rad = None if radii is None else np.ascontiguousarray(radii, np.float32)
+    m = lib().orc_densify(n, adim, _p(geo), _p(app), _p(np.ascontiguousarray(accum, np.float32)),
+                          _p(np.ascontiguousarray(denom, np.float32)), _p(rad), np.float32(grad_thr), float(th[0]),
+                          int(prune_big), float(th[1]), float(th[2]), np.float32(max_screen), float(th[3]),
+                          int(seed), cap, _p(og), _p(oa), _p(src), _p(kind), _p(counts))
+    return og[:m], oa[:m], src[:m], kind[:m], counts
 
 
 def simulate(models, scene_geo_rows_keys, cams_for_step, grads_for, steps, t0=1):
