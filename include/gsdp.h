@@ -313,6 +313,51 @@ int gs_grad_sum_multi(const gs_multi *desc, int32_t adim, const float *g_cam, fl
 int gs_plan_image_split(const gs_model *model, const gs_camera *cam, int64_t step, double mem_limit, gs_multi *desc,
                         void *ws, size_t ws_bytes, void *stream, int32_t *split_x, uint32_t *counts);
 
+/* ----------------------------------------------------------- densification */
+
+/* Densification (Sec. 2.4 step 7: rows with large accumulated gradients are
+ * cloned or split, insignificant low-opacity rows pruned), with the criteria
+ * of 3D Gaussian Splatting on current FP32 values (flush the model at `step`
+ * first).  Per row: g = accum/denom (0 when denom = 0); grad = g >= threshold;
+ * smax = largest log-scale; clone if grad and smax <= log(percent_dense *
+ * extent), split if grad and above; prune if the opacity logit (appearance
+ * column 0) < logit(min_opacity), if prune_big and smax > log(0.1 extent), or
+ * (originals only) if max_screen_size > 0 and radii > max_screen_size.  A clone
+ * copies its row; a split row is replaced by two children with log-scales
+ * s - log 1.6 and positions mu + R(q) (exp(s) * z), z a normal-approximation
+ * draw (sum of the four 16-bit fields of SplitMix64(seed, row, child, axis),
+ * centred and scaled to unit variance in FP64); children are pruned on their
+ * own scales.  Output rows: kept originals in order, then kept clones, then
+ * kept children (parent order, child 0 first).  New rows start with zero
+ * moments; every output row has last_step = step.  Thresholds are FP64 logs
+ * rounded once to FP32.  FP32 or BF16 state (FP8 block scales do not move
+ * with rows). */
+typedef struct gs_densify_params {
+    float grad_threshold;  /* 3DGS: 0.0002 */
+    float percent_dense;   /* 3DGS: 0.01 */
+    float scene_extent;    /* > 0 */
+    float min_opacity;     /* 3DGS: 0.005, in (0, 1) */
+    float max_screen_size; /* pixels; 0 = off */
+    int32_t prune_big;     /* 1: prune rows larger than 0.1 extent in world space */
+    uint64_t seed;         /* split draws */
+} gs_densify_params;
+
+/* Workspace of the two calls below (per-row codes and per-tile counts). */
+int gs_densify_workspace_bytes(const gs_model *model, size_t *bytes);
+
+/* Classify every row of `model` and count the output rows (originals, clones,
+ * children; counts optional, 3 entries).  grad_accum, grad_denom: device [n];
+ * max_radii2d: device [n] or NULL.  Synchronises `stream` to return *n_out. */
+int gs_densify_plan(const gs_model *model, const float *grad_accum, const float *grad_denom,
+                    const float *max_radii2d, const gs_densify_params *params, void *ws, size_t ws_bytes,
+                    void *stream, int64_t *n_out, int64_t *counts);
+
+/* Write the planned rows into `dst` (dst->n == *n_out of the plan, same
+ * column rates, appearance dim and moment storage as src; any layout).  Reads
+ * the codes the plan left in `ws`; asynchronous. */
+int gs_densify_apply(const gs_model *src, const gs_densify_params *params, const gs_model *dst, int64_t step,
+                     void *ws, size_t ws_bytes, void *stream);
+
 /* --------------------------------------------------------------- harness */
 
 /* Synthetic gradients for benchmarks and tests (not part of the method):

@@ -786,6 +786,8 @@ def densify(geo, app, accum, denom, radii=None, grad_thr=2e-4, percent_dense=0.0
     geo = np.ascontiguousarray(geo, np.float32)
     app = np.ascontiguousarray(app, np.float32)
     n, adim = geo.shape[0], app.shape[1]
+    # the library takes these parameters as FP32 values
+    percent_dense, extent, min_opacity = (float(np.float32(x)) for x in (percent_dense, extent, min_opacity))
     th = densify_thresholds(percent_dense, extent, min_opacity)
     cap = 3 * n + 1
     og = np.zeros((cap, 10), np.float32); oa = np.zeros((cap, adim), np.float32)

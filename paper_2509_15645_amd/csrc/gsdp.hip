@@ -1719,6 +1719,258 @@ __global__ __launch_bounds__(256) void k_grad_sum(GradSumArgs a)
 
 __global__ void k_step_advance(int32_t *t) { *t += 1; }
 
+// ---------------------------------------------------------------------------
+// densification: plan (codes + tile counts) -> scan -> apply (row copies)
+// ---------------------------------------------------------------------------
+struct DensArgs {
+    const float *gw, *aw;            // source current values
+    int64_t aw_ld;
+    int32_t adim, big_on;
+    const float *accum, *denom, *radii;
+    float thr, log_dense, log_big, logit_min, max_screen, log_split;
+    u64 seed;
+    int64_t n, tiles;
+    uint8_t *code;                   // [n] bit 0 original kept, 1 clone kept, 2 children kept
+    u32 *cnt, *off;                  // [3][tiles]
+    u32 *totals;                     // [4]
+    // apply
+    MomRef sgm, sgv, sam, sav;       // source moments
+    int32_t gst, ast;
+    float *dgw, *daw;
+    int64_t daw_ld;
+    MomRef dgm, dgv, dam, dav;       // destination moments
+    int32_t *dlast;
+    int64_t dn;
+    int32_t step, pad;
+};
+
+__device__ __forceinline__ u32 dens_code(const DensArgs &a, int64_t i)
+{
+    const float *g = a.gw + i * 10;
+    const float den = a.denom[i];
+    const float gr = den > 0.0f ? a.accum[i] / den : 0.0f;
+    const bool grad = gr >= a.thr;
+    float smax = g[3];
+    if (g[4] > smax) smax = g[4];
+    if (g[5] > smax) smax = g[5];
+    const bool clone = grad && (smax <= a.log_dense);
+    const bool split = grad && (smax > a.log_dense);
+    const bool low = a.aw[i * a.aw_ld] < a.logit_min;
+    const bool big = a.big_on && (smax > a.log_big);
+    const bool screen = a.radii && a.max_screen > 0.0f && a.radii[i] > a.max_screen;
+    const float cmax = smax - a.log_split;
+    const bool cbig = a.big_on && (cmax > a.log_big);
+    u32 c = 0;
+    if (!split && !low && !big && !screen) c |= 1u;
+    if (clone && !low && !big) c |= 2u;
+    if (split && !low && !cbig) c |= 4u;
+    return c;
+}
+
+__global__ __launch_bounds__(kCullBlock) void k_dens_plan(DensArgs a)
+{
+    __shared__ u32 sCnt[kCullIpt * 4][3];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t tile = blockIdx.x, row0 = tile * kCullTile;
+#pragma unroll
+    for (int k = 0; k < kCullIpt; ++k) {
+        const int64_t i = row0 + k * kCullBlock + tid;
+        const u32 c = i < a.n ? dens_code(a, i) : 0u;
+        if (i < a.n) a.code[i] = (uint8_t)c;
+        const int slab = k * 4 + wave;
+        const u64 b0 = __ballot(c & 1u), b1 = __ballot(c & 2u), b2 = __ballot(c & 4u);
+        if (lane == 0) {
+            sCnt[slab][0] = (u32)__popcll(b0);
+            sCnt[slab][1] = (u32)__popcll(b1);
+            sCnt[slab][2] = 2u * (u32)__popcll(b2);
+        }
+    }
+    __syncthreads();
+    if (tid < 3) {
+        u32 o = 0;
+        for (int sl = 0; sl < kCullIpt * 4; ++sl) o += sCnt[sl][tid];
+        a.cnt[(int64_t)tid * a.tiles + tile] = o;
+    }
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_dens_scan(DensArgs a)
+{
+    __shared__ u64 sWave[kScanThreads / 64 + 1];
+    const int tid = threadIdx.x;
+    const int64_t per = (a.tiles + kScanThreads - 1) / kScanThreads;
+    const int64_t t0 = min((int64_t)tid * per, a.tiles), t1 = min(t0 + per, a.tiles);
+    for (int j = 0; j < 3; ++j) {
+        const u32 *cj = a.cnt + (int64_t)j * a.tiles;
+        u32 *oj = a.off + (int64_t)j * a.tiles;
+        u64 sum = 0;
+        for (int64_t i = t0; i < t1; ++i) sum += cj[i];
+        u64 tot = 0;
+        u64 run = block_excl_scan_u64(sum, sWave, &tot);
+        for (int64_t i = t0; i < t1; ++i) {
+            oj[i] = (u32)run;
+            run += cj[i];
+        }
+        if (tid == 0) a.totals[j] = (u32)tot;
+    }
+}
+
+// One block per tile: output positions of the tile's rows from ballots and
+// the tile prefixes, then one wavefront per row copies it (lane c < 10: G
+// column c, lane 10 + c: A column c).
+template <int GST, int AST>
+__global__ __launch_bounds__(kCullBlock) void k_dens_apply(DensArgs a)
+{
+    __shared__ u32 sCnt[kCullIpt * 4][3];
+    __shared__ u32 sOff[kCullIpt * 4][3];
+    __shared__ int64_t sPos[kCullTile][3];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t tile = blockIdx.x, row0 = tile * kCullTile;
+    const int rows = (int)min((int64_t)kCullTile, a.n - row0);
+    const u64 lt = (1ull << lane) - 1ull;
+    u32 cv[kCullIpt];
+    u64 bb[kCullIpt][3];
+#pragma unroll
+    for (int k = 0; k < kCullIpt; ++k) {
+        const int r = k * kCullBlock + tid;
+        cv[k] = r < rows ? (u32)a.code[row0 + r] : 0u;
+        const int slab = k * 4 + wave;
+        bb[k][0] = __ballot(cv[k] & 1u);
+        bb[k][1] = __ballot(cv[k] & 2u);
+        bb[k][2] = __ballot(cv[k] & 4u);
+        if (lane == 0) {
+            sCnt[slab][0] = (u32)__popcll(bb[k][0]);
+            sCnt[slab][1] = (u32)__popcll(bb[k][1]);
+            sCnt[slab][2] = 2u * (u32)__popcll(bb[k][2]);
+        }
+    }
+    __syncthreads();
+    if (tid < 3) {
+        u32 o = a.off[(int64_t)tid * a.tiles + tile];
+        if (tid >= 1) o += a.totals[0];
+        if (tid == 2) o += a.totals[1];
+        for (int sl = 0; sl < kCullIpt * 4; ++sl) {
+            sOff[sl][tid] = o;
+            o += sCnt[sl][tid];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kCullIpt; ++k) {
+        const int r = k * kCullBlock + tid;
+        const int slab = k * 4 + wave;
+        if (r < rows) {
+            sPos[r][0] = (cv[k] & 1u) ? (int64_t)(sOff[slab][0] + (u32)__popcll(bb[k][0] & lt)) : -1;
+            sPos[r][1] = (cv[k] & 2u) ? (int64_t)(sOff[slab][1] + (u32)__popcll(bb[k][1] & lt)) : -1;
+            sPos[r][2] = (cv[k] & 4u) ? (int64_t)(sOff[slab][2] + 2u * (u32)__popcll(bb[k][2] & lt)) : -1;
+        }
+    }
+    __syncthreads();
+
+    const bool isG = lane < 10;
+    const bool act = lane < 10 + a.adim;
+    const int ca = lane - 10;
+    for (int r = wave; r < rows; r += kCullBlock / 64) {
+        const int64_t i = row0 + r;
+        const int64_t p0 = sPos[r][0], p1 = sPos[r][1], p2 = sPos[r][2];
+        if (p0 < 0 && p1 < 0 && p2 < 0) continue;
+        float x = 0.0f, m = 0.0f, v = 0.0f;
+        if (act) {
+            x = isG ? a.gw[i * 10 + lane] : a.aw[i * a.aw_ld + ca];
+            if (p0 >= 0) {
+                if (isG) {
+                    m = mom_load<GST>(a.sgm, i, lane, false);
+                    v = mom_load<GST>(a.sgv, i, lane, true);
+                } else {
+                    m = mom_load<AST>(a.sam, i, ca, false);
+                    v = mom_load<AST>(a.sav, i, ca, true);
+                }
+            }
+        }
+        // copies of the source row: the original keeps its moments, a clone starts at zero
+        for (int kind = 0; kind < 2; ++kind) {
+            const int64_t o = kind == 0 ? p0 : p1;
+            if (o < 0 || o >= a.dn || !act) continue;
+            const float mo = kind == 0 ? m : 0.0f, vo = kind == 0 ? v : 0.0f;
+            if (isG) {
+                a.dgw[o * 10 + lane] = x;
+                mom_store<GST>(a.dgm, o, lane, mo, 0u, false);
+                mom_store<GST>(a.dgv, o, lane, vo, 0u, true);
+            } else {
+                a.daw[o * a.daw_ld + ca] = x;
+                mom_store<AST>(a.dam, o, ca, mo, 0u, false);
+                mom_store<AST>(a.dav, o, ca, vo, 0u, true);
+            }
+        }
+        if (lane == 0) {
+            if (p0 >= 0 && p0 < a.dn) a.dlast[p0] = a.step;
+            if (p1 >= 0 && p1 < a.dn) a.dlast[p1] = a.step;
+        }
+        if (p2 < 0) continue;
+        // two split children: scales s - log 1.6, positions mu + Q (exp(s) z)
+        float cx = x;
+        if (isG && lane < 6) {
+            const float *g = a.gw + i * 10;
+            float qw = g[6], qx = g[7], qy = g[8], qz = g[9];
+            const float n2 = ((qw * qw + qx * qx) + qy * qy) + qz * qz;
+            const float inv = 1.0f / sqrtf(n2);
+            qw = qw * inv;
+            qx = qx * inv;
+            qy = qy * inv;
+            qz = qz * inv;
+            float Qr[3];
+            if (lane == 0) {
+                Qr[0] = 1.0f - 2.0f * (qy * qy + qz * qz);
+                Qr[1] = 2.0f * (qx * qy - qw * qz);
+                Qr[2] = 2.0f * (qx * qz + qw * qy);
+            } else if (lane == 1) {
+                Qr[0] = 2.0f * (qx * qy + qw * qz);
+                Qr[1] = 1.0f - 2.0f * (qx * qx + qz * qz);
+                Qr[2] = 2.0f * (qy * qz - qw * qx);
+            } else {
+                Qr[0] = 2.0f * (qx * qz - qw * qy);
+                Qr[1] = 2.0f * (qy * qz + qw * qx);
+                Qr[2] = 1.0f - 2.0f * (qx * qx + qy * qy);
+            }
+            const float sg0 = exp_cw(g[3]), sg1 = exp_cw(g[4]), sg2 = exp_cw(g[5]);
+            for (int j = 0; j < 2; ++j) {
+                const int64_t o = p2 + j;
+                if (o >= a.dn) continue;
+                float val;
+                if (lane < 3) {
+                    float z[3];
+                    for (int ax = 0; ax < 3; ++ax) {
+                        const u64 h = sm_at(sm_at(sm_at(a.seed, (u64)i), (u64)j), (u64)ax);
+                        const u64 u = (h & 0xffffull) + ((h >> 16) & 0xffffull) + ((h >> 32) & 0xffffull) +
+                                      ((h >> 48) & 0xffffull);
+                        const double inv_sd = 1.0 / sqrt(4.0 * (65536.0 * 65536.0 - 1.0) / 12.0);
+                        z[ax] = (float)(((double)u - 131070.0) * inv_sd);
+                    }
+                    const float v0 = sg0 * z[0], v1 = sg1 * z[1], v2 = sg2 * z[2];
+                    val = g[lane] + ((Qr[0] * v0 + Qr[1] * v1) + Qr[2] * v2);
+                } else {
+                    val = g[lane] - a.log_split;
+                }
+                a.dgw[o * 10 + lane] = val;
+            }
+            cx = 0.0f;  // written above
+        }
+        for (int j = 0; j < 2; ++j) {
+            const int64_t o = p2 + j;
+            if (o >= a.dn || !act) continue;
+            if (isG) {
+                if (lane >= 6) a.dgw[o * 10 + lane] = cx;
+                mom_store<GST>(a.dgm, o, lane, 0.0f, 0u, false);
+                mom_store<GST>(a.dgv, o, lane, 0.0f, 0u, true);
+            } else {
+                a.daw[o * a.daw_ld + ca] = cx;
+                mom_store<AST>(a.dam, o, ca, 0.0f, 0u, false);
+                mom_store<AST>(a.dav, o, ca, 0.0f, 0u, true);
+            }
+            if (lane == 0) a.dlast[o] = a.step;
+        }
+    }
+}
+
 }  // namespace
 
 namespace {
@@ -2211,6 +2463,127 @@ int gs_adam_flush(const gs_model *model, int64_t step, void *stream)
     a.Vf = L.Vf;
     launch_rows<kFlush>(model, row_grid(model->n), (hipStream_t)stream, a);
     return launched("gs_adam_flush");
+}
+
+// ------------------------------------------------------------ densification
+namespace {
+
+int64_t dens_ws_bytes(int64_t n)
+{
+    const int64_t tiles = gsdp::cull_tiles(n);
+    return gsdp::kWsHeader + (n + 255) / 256 * 256 + 2 * 3 * 4 * tiles;
+}
+
+int dens_args(const gs_model *m, const gs_densify_params *p, void *ws, size_t ws_bytes, DensArgs &a)
+{
+    int rc = check_model(m);
+    if (rc) return rc;
+    if (!p || !ws || !aligned(ws, 256)) return GS_EINVAL;
+    if (m->geo.state == GS_FP8E4M3 || m->app.state == GS_FP8E4M3) return GS_EUNSUPPORTED;
+    if (!(p->scene_extent > 0.0f) || !(p->percent_dense > 0.0f) || !(p->min_opacity > 0.0f && p->min_opacity < 1.0f) ||
+        !(p->max_screen_size >= 0.0f) || !(p->grad_threshold == p->grad_threshold))
+        return GS_EINVAL;
+    if ((int64_t)ws_bytes < dens_ws_bytes(m->n)) return GS_ESPACE;
+    memset(&a, 0, sizeof a);
+    a.gw = m->geo.w;
+    a.aw = m->app.w;
+    a.aw_ld = m->app.w_ld;
+    a.adim = m->app.dim;
+    a.big_on = p->prune_big != 0;
+    a.thr = p->grad_threshold;
+    // thresholds: FP64 logs rounded once
+    a.log_dense = (float)std::log((double)p->percent_dense * (double)p->scene_extent);
+    a.log_big = (float)std::log(0.1 * (double)p->scene_extent);
+    a.logit_min = (float)std::log((double)p->min_opacity / (1.0 - (double)p->min_opacity));
+    a.log_split = (float)std::log(1.6);
+    a.max_screen = p->max_screen_size;
+    a.seed = p->seed;
+    a.n = m->n;
+    a.tiles = gsdp::cull_tiles(m->n);
+    char *wsb = static_cast<char *>(ws);
+    a.totals = reinterpret_cast<u32 *>(wsb);
+    a.code = reinterpret_cast<uint8_t *>(wsb + gsdp::kWsHeader);
+    a.cnt = reinterpret_cast<u32 *>(wsb + gsdp::kWsHeader + (m->n + 255) / 256 * 256);
+    a.off = a.cnt + 3 * a.tiles;
+    return GS_OK;
+}
+
+}  // namespace
+
+int gs_densify_workspace_bytes(const gs_model *model, size_t *bytes)
+{
+    if (!model || !bytes || model->n < 0) return GS_EINVAL;
+    *bytes = (size_t)dens_ws_bytes(model->n);
+    return GS_OK;
+}
+
+int gs_densify_plan(const gs_model *model, const float *grad_accum, const float *grad_denom,
+                    const float *max_radii2d, const gs_densify_params *params, void *ws, size_t ws_bytes,
+                    void *stream, int64_t *n_out, int64_t *counts)
+{
+    DensArgs a;
+    int rc = dens_args(model, params, ws, ws_bytes, a);
+    if (rc) return rc;
+    if (!n_out || (model->n > 0 && (!grad_accum || !grad_denom))) return GS_EINVAL;
+    if (params->max_screen_size > 0.0f && model->n > 0 && !max_radii2d) return GS_EINVAL;
+    if (a.tiles > 0x7fffffff) return GS_EINVAL;
+    a.accum = grad_accum;
+    a.denom = grad_denom;
+    a.radii = params->max_screen_size > 0.0f ? max_radii2d : nullptr;
+    hipStream_t st = (hipStream_t)stream;
+    if (a.tiles > 0) {
+        hipLaunchKernelGGL(k_dens_plan, dim3((unsigned)a.tiles), dim3(kCullBlock), 0, st, a);
+        rc = launched("gs_densify_plan");
+        if (rc) return rc;
+    }
+    hipLaunchKernelGGL(k_dens_scan, dim3(1), dim3(kScanThreads), 0, st, a);
+    rc = launched("gs_densify_plan (scan)");
+    if (rc) return rc;
+    u32 tot[3] = {0, 0, 0};
+    hipError_t e = hipMemcpyAsync(tot, a.totals, sizeof tot, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "gs_densify_plan: totals");
+    *n_out = (int64_t)tot[0] + tot[1] + tot[2];
+    if (counts)
+        for (int j = 0; j < 3; ++j) counts[j] = tot[j];
+    return GS_OK;
+}
+
+int gs_densify_apply(const gs_model *src, const gs_densify_params *params, const gs_model *dst, int64_t step,
+                     void *ws, size_t ws_bytes, void *stream)
+{
+    DensArgs a;
+    int rc = dens_args(src, params, ws, ws_bytes, a);
+    if (rc) return rc;
+    rc = check_model(dst);
+    if (rc) return rc;
+    if (step < 0 || step > 0x7fffffff) return GS_EINVAL;
+    if (dst->app.dim != src->app.dim || dst->geo.state != src->geo.state || dst->app.state != src->app.state)
+        return GS_EINVAL;
+    if (dst->n > 0 && !dst->last_step) return GS_EINVAL;
+    a.sgm = {src->geo.m, src->geo.m_scale, src->geo.m_ld};
+    a.sgv = {src->geo.v, src->geo.v_scale, src->geo.v_ld};
+    a.sam = {src->app.m, src->app.m_scale, src->app.m_ld};
+    a.sav = {src->app.v, src->app.v_scale, src->app.v_ld};
+    a.dgw = dst->geo.w;
+    a.daw = dst->app.w;
+    a.daw_ld = dst->app.w_ld;
+    a.dgm = {dst->geo.m, dst->geo.m_scale, dst->geo.m_ld};
+    a.dgv = {dst->geo.v, dst->geo.v_scale, dst->geo.v_ld};
+    a.dam = {dst->app.m, dst->app.m_scale, dst->app.m_ld};
+    a.dav = {dst->app.v, dst->app.v_scale, dst->app.v_ld};
+    a.dlast = dst->last_step;
+    a.dn = dst->n;
+    a.step = (int32_t)step;
+    if (a.tiles == 0) return GS_OK;
+    if (a.tiles > 0x7fffffff) return GS_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    const bool gb = src->geo.state == GS_BF16, ab = src->app.state == GS_BF16;
+    if (!gb && !ab) hipLaunchKernelGGL((k_dens_apply<GS_F32, GS_F32>), dim3((unsigned)a.tiles), dim3(kCullBlock), 0, st, a);
+    else if (!gb && ab) hipLaunchKernelGGL((k_dens_apply<GS_F32, GS_BF16>), dim3((unsigned)a.tiles), dim3(kCullBlock), 0, st, a);
+    else if (gb && !ab) hipLaunchKernelGGL((k_dens_apply<GS_BF16, GS_F32>), dim3((unsigned)a.tiles), dim3(kCullBlock), 0, st, a);
+    else hipLaunchKernelGGL((k_dens_apply<GS_BF16, GS_BF16>), dim3((unsigned)a.tiles), dim3(kCullBlock), 0, st, a);
+    return launched("gs_densify_apply");
 }
 
 int gs_synth_grad(uint64_t seed, int64_t step, const uint32_t *ids, const uint32_t *count_dev, uint32_t capacity,

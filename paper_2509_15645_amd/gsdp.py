@@ -28,7 +28,8 @@ SYMBOLS = ("gs_lut_bytes", "gs_lut_build", "gs_lut_build_host", "gs_lut_build_sc
            "gs_device_cu_count", "gs_status_string", "gs_last_hip_error", "gs_step_advance",
            "gs_camera_pack_bytes", "gs_camera_pack", "gs_multi_workspace_bytes", "gs_cull_multi",
            "gs_cull_multi_autotune", "gs_grad_sum_multi", "gs_plan_image_split", "gs_lut_build_sgd_momentum",
-           "gs_lut_build_sgd_momentum_host", "gs_lut_bytes_adamw", "gs_lut_build_adamw", "gs_lut_build_adamw_host")
+           "gs_lut_build_sgd_momentum_host", "gs_lut_bytes_adamw", "gs_lut_build_adamw", "gs_lut_build_adamw_host",
+           "gs_densify_workspace_bytes", "gs_densify_plan", "gs_densify_apply")
 
 
 class GsCamera(C.Structure):
@@ -79,6 +80,9 @@ def _load():
         "gs_lut_build_adamw": (C.c_int, [P(GsModel), f64, vp, vp, sz]),
         "gs_lut_build_adamw_host": (C.c_int, [P(GsModel), f64, vp, vp, sz]),
         "gs_workspace_bytes": (C.c_int, [P(GsModel), P(sz)]),
+        "gs_densify_workspace_bytes": (C.c_int, [P(GsModel), P(sz)]),
+        "gs_densify_plan": (C.c_int, [P(GsModel), vp, vp, vp, vp, vp, sz, vp, P(C.c_int64), vp]),
+        "gs_densify_apply": (C.c_int, [P(GsModel), vp, P(GsModel), i64, vp, sz, vp]),
         "gs_cull": (C.c_int, [P(GsModel), P(GsCamera), i64, vp, vp, u32, vp, sz, vp]),
         "gs_gather": (C.c_int, [P(GsModel), i64, vp, vp, u32, vp, vp, vp]),
         "gs_scatter_grad": (C.c_int, [vp, vp, u32, i32, vp, vp, i32, vp]),
@@ -216,6 +220,11 @@ class Model:
                  max_steps=1000, cull_mode=0, app_layout="separate", geo_state="f32", app_state="f32",
                  sr_seed=0, geo_mode=0, lr_scale=None, optimizer="adam", weight_decay=0.0, device=None):
         device = device or torch.device("cuda")
+        # constructor settings, reused by densify() for the resized model
+        self._kw = dict(beta1=beta1, beta2=beta2, eps=eps, max_defer=max_defer, max_steps=max_steps,
+                        cull_mode=cull_mode, app_layout=app_layout, geo_state=geo_state, app_state=app_state,
+                        sr_seed=sr_seed, geo_mode=geo_mode, lr_scale=lr_scale, optimizer=optimizer,
+                        weight_decay=weight_decay, device=device)
         geo = torch.as_tensor(geo, dtype=torch.float32)
         app = torch.as_tensor(app, dtype=torch.float32)
         n, adim = geo.shape[0], app.shape[1]
@@ -395,6 +404,41 @@ def gs_synth_grad(seed: int, step: int, ids, count, out, col0: int, sigma=1e-3, 
     cap = out.shape[0] if capacity is None else int(capacity)
     _check(lib.gs_synth_grad(int(seed), int(step), _ptr(ids), _ptr(count), cap, out.shape[1], int(col0),
                              float(sigma), _ptr(out), _stream(stream)), "gs_synth_grad")
+
+
+# ---------------------------------------------------------------------------
+# densification
+# ---------------------------------------------------------------------------
+class GsDensifyParams(C.Structure):
+    _fields_ = [("grad_threshold", C.c_float), ("percent_dense", C.c_float), ("scene_extent", C.c_float),
+                ("min_opacity", C.c_float), ("max_screen_size", C.c_float), ("prune_big", C.c_int32),
+                ("seed", C.c_uint64)]
+
+
+def densify(model: Model, step: int, grad_accum, grad_denom, max_radii2d=None, *, grad_threshold=2e-4,
+            percent_dense=0.01, scene_extent=1.0, min_opacity=0.005, max_screen_size=0.0, prune_big=True,
+            seed=0, stream=None):
+    """Clone / split / prune the rows of a flushed `model` (gs_adam_flush at
+    `step` first) into a new Model of the planned size with the same
+    settings.  Returns (new_model, counts[originals, clones, children])."""
+    p = GsDensifyParams(grad_threshold, percent_dense, scene_extent, min_opacity, max_screen_size,
+                        int(bool(prune_big)), int(seed))
+    b = C.c_size_t()
+    _check(lib.gs_densify_workspace_bytes(C.byref(model.c), C.byref(b)), "gs_densify_workspace_bytes")
+    ws = torch.zeros(max(b.value // 4, 64), dtype=torch.int32, device=model.device)
+    n_out = C.c_int64()
+    counts = (C.c_int64 * 3)()
+    _check(lib.gs_densify_plan(C.byref(model.c), _ptr(grad_accum), _ptr(grad_denom), _ptr(max_radii2d),
+                               C.byref(p), _ptr(ws), ws.numel() * 4, _stream(stream), C.byref(n_out), counts),
+           "gs_densify_plan")
+    n = int(n_out.value)
+    dev = model.device
+    new = Model(torch.zeros((n, 10), dtype=torch.float32, device=dev),
+                torch.zeros((n, model.adim), dtype=torch.float32, device=dev), model.lr_geo, model.lr_app,
+                **model._kw)
+    _check(lib.gs_densify_apply(C.byref(model.c), C.byref(p), C.byref(new.c), int(step), _ptr(ws), ws.numel() * 4,
+                                _stream(stream)), "gs_densify_apply")
+    return new, [int(x) for x in counts]
 
 
 def gs_step_advance(step_dev, stream=None):
