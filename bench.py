@@ -53,6 +53,9 @@ def parse():
     p.add_argument("--pool", type=int, default=4)
     p.add_argument("--device-scene", type=int, default=None,
                    help="1 = draw the scene on the device (default for more than 8M Gaussians)")
+    p.add_argument("--order", default="generated", choices=["generated", "morton"],
+                   help="row order of the scene: as generated (spatially random) or sorted by the Morton code "
+                        "of the position (visible rows then form contiguous runs)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample", type=int, default=1 << 20)
     p.add_argument("--cpu-steps", type=int, default=6)
@@ -91,8 +94,11 @@ def cpu_baseline(w, geo_all, app_all, sample, steps, lg, la):
                       f"(median step {med * 1e3:.1f} ms): FP32 cull + ids + synthetic grads + dense FP64 Adam"}
 
 
-KERNEL_SYMBOL = {"cull": "k_cull", "gather": "k_rows<0", "adam": "k_rows<1", "cull_multi": "k_cull_multi",
-                 "grad_sum": "k_grad_sum", "adam_bf16": "k_rows<1"}
+# the launches behind each timed call (the cull is three launches: tile cull,
+# one-block tile scan, id scatter; the batched cull likewise)
+KERNEL_SYMBOLS = {"cull": ["k_cull", "k_tile_scan", "k_tile_ids"], "gather": ["k_rows<0"],
+                  "adam": ["k_rows<1"], "cull_multi": ["k_cull_multi", "k_multi_scan", "k_multi_ids"],
+                  "grad_sum": ["k_grad_sum"], "adam_bf16": ["k_rows<1"]}
 
 
 def source_digest():
@@ -119,7 +125,24 @@ def measured_traffic(kernel, config_key):
             cur = f[1]
         elif len(f) >= 4 and f[0] == "bytes_per_launch" and cur == digest and f[1] == config_key:
             found[f[2]] = float(f[3])
-    return found.get(KERNEL_SYMBOL.get(kernel, kernel))
+    syms = KERNEL_SYMBOLS.get(kernel, [kernel])
+    if not all(x in found for x in syms):
+        return None
+    return sum(found[x] for x in syms)
+
+
+def morton_order(pos, box):
+    """Permutation sorting rows by the 63-bit Morton code of their position
+    quantised to 21 bits per axis inside `box` (a torch tensor in, out)."""
+    import torch
+    lo = torch.tensor([b[0] for b in box], dtype=torch.float64, device=pos.device)
+    hi = torch.tensor([b[1] for b in box], dtype=torch.float64, device=pos.device)
+    q = ((pos.double() - lo) / (hi - lo) * (2 ** 21 - 1)).clamp(0, 2 ** 21 - 1).long()
+    code = torch.zeros(pos.shape[0], dtype=torch.int64, device=pos.device)
+    for b in range(21):
+        for a in range(3):
+            code |= ((q[:, a] >> b) & 1) << (3 * b + a)
+    return torch.argsort(code)
 
 
 def device_scene(n, box, seed, dev):
@@ -261,7 +284,7 @@ def run_batched(args):
 def config_key(args, workload):
     """Names the launch configuration a counter summary was taken with."""
     return (f"{workload}/{args.state}/{args.geo_state or args.state}/{args.layout}/cull{args.cull_mode}"
-            f"/geo{args.geo_mode}/K{args.max_defer}/tilt{args.tilt.replace(',', '-')}")
+            f"/geo{args.geo_mode}/K{args.max_defer}/tilt{args.tilt.replace(',', '-')}/{args.order}")
 
 
 def main():
@@ -299,6 +322,14 @@ def main():
     else:
         sc = gi.make_scene(w.n, seed=0, box=w.scene_box)
         geo0, app0 = sc.geo, sc.app
+    if args.order == "morton":
+        import torch as _t
+        g_t = _t.as_tensor(geo0)
+        perm = morton_order(g_t[:, :3], w.scene_box)
+        geo0 = g_t[perm].contiguous()
+        app0 = _t.as_tensor(app0)[perm.to(_t.as_tensor(app0).device)].contiguous()
+        if not on_dev:
+            geo0, app0 = geo0.numpy(), app0.numpy()
     lg, la = gi.lr_columns()
     total_steps = args.warmup + args.steps
     geo_state = args.geo_state or args.state
@@ -416,7 +447,8 @@ def main():
         "ms_per_step": ms_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
-        "config": {"workload": w.name, "n_gaussians": n, "scene_drawn_on": "device" if on_dev else "host", "cameras": len(w.cameras),
+        "config": {"workload": w.name, "n_gaussians": n, "scene_drawn_on": "device" if on_dev else "host",
+                   "row_order": args.order, "cameras": len(w.cameras),
                    "image": f"{w.cameras[0].width}x{w.cameras[0].height}", "oblique_tilt_deg": list(tilt),
                    "visible_fraction": f, "visible_per_step": M, "restored_per_step": R,
                    "state": args.state, "geo_state": geo_state, "app_layout": args.layout,
@@ -424,9 +456,9 @@ def main():
         "kernels_ms": {"cull": cull_ms, "gather": gather_ms, "adam": adam_ms},
         "graph_ms_per_step": graph_ms,
         "kernels_gbs": {k: v[1] / (v[0] * 1e-3) / 1e9 for k, v in kernels.items()},
-        "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom, config_key(args, w.name)),
-                     "algorithmic_bytes": dbytes},
+        "roofline": {"kernel": dom, "launches": KERNEL_SYMBOLS[dom], "bound": "hbm", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(dom, config_key(args, w.name)), "algorithmic_bytes": dbytes},
         "setup_s": setup_s,
     }
     if not args.no_cpu_baseline:
