@@ -878,15 +878,30 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
             const int dd = d[u];
             if (MODE == kAdamMax) {
                 const bool fp8 = isG ? GST == GS_FP8E4M3 : AST == GS_FP8E4M3;
+                const int64_t b = r / kFp8Block;
+                u32 xm = 0u, xv = 0u;
                 if (act && fp8) {
                     const float m1 = a.Mf[dd] * m[u] + a.omb1 * g[u];
                     const float v1 = a.Vf[dd] * v[u] + (a.omb2 * g[u]) * g[u];
                     const float r1 = sqrtf(v1);
-                    const int64_t b = r / kFp8Block;
                     const float am = fabsf(m1);
-                    if (am > 448.0f * qm.s[b]) atomicMax(&a.fp8max[isG ? 0 : 2][b], __float_as_uint(am));
-                    if (r1 > 448.0f * qv.s[b]) atomicMax(&a.fp8max[isG ? 1 : 3][b], __float_as_uint(r1));
+                    if (am > 448.0f * qm.s[b]) xm = __float_as_uint(am);
+                    if (r1 > 448.0f * qv.s[b]) xv = __float_as_uint(r1);
                 }
+                // maxima over the group's lanes (non-negative floats order as
+                // their bit patterns), then at most four atomics per row
+                u32 mx[4] = {isG ? xm : 0u, isG ? xv : 0u, isG ? 0u : xm, isG ? 0u : xv};
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const u32 y = (u32)__shfl_xor((int)mx[k], o);
+                        mx[k] = y > mx[k] ? y : mx[k];
+                    }
+                if (lane == 0)
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+                        if (mx[k]) atomicMax(&a.fp8max[k][b], mx[k]);
                 continue;
             }
             if (MODE == kFlush && dd == 0) continue;
