@@ -222,3 +222,57 @@ def test_host_adamw_tables_equal_oracle_bitwise(gsdp, max_defer, sched):
     for k in range(10):
         m.geo.lr[k] = 1e-3 * (k + 1)
     assert gsdp.lib.gs_lut_bytes_adamw(C.byref(m), C.byref(b)) == gsdp.GS_EUNSUPPORTED
+
+
+def _host_model(gsdp, n=8, state=0, opt=0):
+    """A gs_model over host buffers, only for argument checks that return
+    before any device work."""
+    bufs = {k: np.zeros(n * 64, np.float32) for k in ("gw", "gm", "gv", "aw", "am", "av", "last", "lut", "sc")}
+    m = gsdp.GsModel()
+    m.n = n
+    for grp, pre, dim in ((m.geo, "g", 10), (m.app, "a", 49)):
+        grp.w, grp.m, grp.v = (bufs[pre + x].ctypes.data for x in "wmv")
+        grp.dim = dim
+        grp.w_ld = grp.m_ld = grp.v_ld = dim
+        grp.state = state
+        grp.m_scale = grp.v_scale = bufs["sc"].ctypes.data
+        for k in range(dim):
+            grp.lr[k] = 1e-3
+    m.last_step = bufs["last"].ctypes.data
+    m.lut = bufs["lut"].ctypes.data
+    m.lut_max_steps = 8
+    m.beta1, m.beta2, m.eps = 0.9, 0.999, 1e-15
+    m.optimizer = opt
+    return m, bufs
+
+
+def test_densify_and_optimizer_checks_need_no_device(gsdp):
+    L = gsdp.lib
+    b = C.c_size_t()
+    assert L.gs_densify_workspace_bytes(None, C.byref(b)) == gsdp.GS_EINVAL
+    m, keep = _host_model(gsdp)
+    assert L.gs_densify_workspace_bytes(C.byref(m), C.byref(b)) == 0 and b.value >= 256 + 8
+    p = gsdp.GsDensifyParams(2e-4, 0.01, 10.0, 0.005, 0.0, 1, 0)
+    n_out = C.c_int64()
+    raw = np.zeros(2048, np.float32)
+    ws = raw[(-raw.ctypes.data % 256) // 4:]            # 256-byte aligned view
+    assert ws.ctypes.data % 256 == 0
+    # missing parameters / statistics, bad parameters, unsupported FP8 state
+    assert L.gs_densify_plan(C.byref(m), None, None, None, None, ws.ctypes.data, 4096, None, C.byref(n_out),
+                             None) == gsdp.GS_EINVAL
+    assert L.gs_densify_plan(C.byref(m), None, None, None, C.byref(p), ws.ctypes.data, 4096, None,
+                             C.byref(n_out), None) == gsdp.GS_EINVAL
+    bad = gsdp.GsDensifyParams(2e-4, 0.01, -1.0, 0.005, 0.0, 1, 0)
+    acc = np.zeros(8, np.float32)
+    assert L.gs_densify_plan(C.byref(m), acc.ctypes.data, acc.ctypes.data, None, C.byref(bad), ws.ctypes.data,
+                             4096, None, C.byref(n_out), None) == gsdp.GS_EINVAL
+    m8, keep8 = _host_model(gsdp, state=gsdp.GS_FP8E4M3)
+    assert L.gs_densify_plan(C.byref(m8), acc.ctypes.data, acc.ctypes.data, None, C.byref(p), ws.ctypes.data,
+                             4096, None, C.byref(n_out), None) == gsdp.GS_EUNSUPPORTED
+    # optimizer extensions: FP8 state and the batched form are rejected
+    for opt in (gsdp.GS_OPT_SGD_MOMENTUM, gsdp.GS_OPT_ADAMW):
+        mo, keepo = _host_model(gsdp, state=gsdp.GS_FP8E4M3, opt=opt)
+        assert L.gs_workspace_bytes(C.byref(mo), C.byref(b)) == 0
+        assert L.gs_adam_flush(C.byref(mo), 1, None) == gsdp.GS_EUNSUPPORTED
+    mu, keepu = _host_model(gsdp, opt=7)
+    assert L.gs_adam_flush(C.byref(mu), 1, None) == gsdp.GS_EINVAL
