@@ -676,6 +676,46 @@ __global__ __launch_bounds__(kScanThreads) void k_tile_scan(ScanArgs a)
     }
 }
 
+// Exclusive prefix of one u32 count per tile, by the whole block, through LDS
+// in chunks (coalesced loads and stores); returns the total.  sV holds
+// kScanChunk entries, sWave kScanThreads/64 + 1.
+__device__ u64 scan_counts_u32(const u32 *cnt, u32 *off, int64_t tiles, u64 *sV, u64 *sWave)
+{
+    const int tid = threadIdx.x;
+    u64 carry = 0;
+    for (int64_t c0 = 0; c0 < tiles; c0 += kScanChunk) {
+        const int64_t nc = min((int64_t)kScanChunk, tiles - c0);
+#pragma unroll
+        for (int q = 0; q < kScanPer; ++q) {
+            const int64_t i = (int64_t)q * kScanThreads + tid;
+            sV[i] = i < nc ? (u64)cnt[c0 + i] : 0ull;
+        }
+        __syncthreads();
+        u64 v[kScanPer], sum = 0;
+#pragma unroll
+        for (int q = 0; q < kScanPer; ++q) {
+            v[q] = sV[tid * kScanPer + q];
+            sum += v[q];
+        }
+        u64 tot = 0;
+        u64 run = carry + block_excl_scan_u64(sum, sWave, &tot);
+#pragma unroll
+        for (int q = 0; q < kScanPer; ++q) {
+            sV[tid * kScanPer + q] = run;
+            run += v[q];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kScanPer; ++q) {
+            const int64_t i = (int64_t)q * kScanThreads + tid;
+            if (i < nc) off[c0 + i] = (u32)sV[i];
+        }
+        carry += tot;
+        __syncthreads();
+    }
+    return carry;
+}
+
 // One wavefront per tile: visible (and saturated) ids in ascending order from
 // the tile's ballots and exclusive prefix.
 struct IdsArgs {
@@ -1572,40 +1612,16 @@ __global__ __launch_bounds__(BLOCK) void k_cull_multi(MultiArgs a)
 // scene starts.
 __global__ __launch_bounds__(kScanThreads) void k_multi_scan(MultiArgs a)
 {
+    __shared__ u64 sV[kScanChunk];
     __shared__ u64 sWave[kScanThreads / 64 + 1];
-    const int tid = threadIdx.x;
-    const int64_t per = (a.tiles + kScanThreads - 1) / kScanThreads;
-    const int64_t t0 = min((int64_t)tid * per, a.tiles), t1 = min(t0 + per, a.tiles);
     const int C = a.C;
     for (int j = 0; j < 1 + C; ++j) {
-        const u32 *cj = a.cnt + (int64_t)j * a.stride;
-        u32 *oj = a.off + (int64_t)j * a.stride;
-        constexpr int kIlp = 8;
-        u64 sum = 0;
-        for (int64_t i0 = t0; i0 < t1; i0 += kIlp) {
-            u32 c[kIlp];
-#pragma unroll
-            for (int q = 0; q < kIlp; ++q) c[q] = i0 + q < t1 ? cj[i0 + q] : 0u;
-#pragma unroll
-            for (int q = 0; q < kIlp; ++q) sum += c[q];
-        }
-        u64 tot = 0;
-        u64 run = block_excl_scan_u64(sum, sWave, &tot);
-        for (int64_t i0 = t0; i0 < t1; i0 += kIlp) {
-            u32 c[kIlp];
-#pragma unroll
-            for (int q = 0; q < kIlp; ++q) c[q] = i0 + q < t1 ? cj[i0 + q] : 0u;
-#pragma unroll
-            for (int q = 0; q < kIlp; ++q) {
-                if (i0 + q < t1) oj[i0 + q] = (u32)run;
-                run += c[q];
-            }
-        }
-        if (tid == 0) {
+        const u64 tot = scan_counts_u32(a.cnt + (int64_t)j * a.stride, a.off + (int64_t)j * a.stride, a.tiles, sV,
+                                        sWave);
+        if (threadIdx.x == 0) {
             if (j == 0) *a.union_count = (u32)tot;
             else a.cam_count[j - 1] = (u32)tot;
         }
-        __syncthreads();   // sWave is reused by the next counter
     }
 }
 
@@ -1810,22 +1826,11 @@ __global__ __launch_bounds__(kCullBlock) void k_dens_plan(DensArgs a)
 
 __global__ __launch_bounds__(kScanThreads) void k_dens_scan(DensArgs a)
 {
+    __shared__ u64 sV[kScanChunk];
     __shared__ u64 sWave[kScanThreads / 64 + 1];
-    const int tid = threadIdx.x;
-    const int64_t per = (a.tiles + kScanThreads - 1) / kScanThreads;
-    const int64_t t0 = min((int64_t)tid * per, a.tiles), t1 = min(t0 + per, a.tiles);
     for (int j = 0; j < 3; ++j) {
-        const u32 *cj = a.cnt + (int64_t)j * a.tiles;
-        u32 *oj = a.off + (int64_t)j * a.tiles;
-        u64 sum = 0;
-        for (int64_t i = t0; i < t1; ++i) sum += cj[i];
-        u64 tot = 0;
-        u64 run = block_excl_scan_u64(sum, sWave, &tot);
-        for (int64_t i = t0; i < t1; ++i) {
-            oj[i] = (u32)run;
-            run += cj[i];
-        }
-        if (tid == 0) a.totals[j] = (u32)tot;
+        const u64 tot = scan_counts_u32(a.cnt + (int64_t)j * a.tiles, a.off + (int64_t)j * a.tiles, a.tiles, sV, sWave);
+        if (threadIdx.x == 0) a.totals[j] = (u32)tot;
     }
 }
 
