@@ -386,7 +386,7 @@ def main():
     t1 = time.perf_counter()
     h1 = model.ws_header()
     if h1["error"]:
-        raise RuntimeError(f"cull look-back reported an error flag: {h1}")
+        raise RuntimeError(f"cull reported an error flag: {h1}")
     ms_step = (t1 - t0) * 1e3 / args.steps
 
     graph_ms = None

@@ -7,17 +7,22 @@
 // written as the exact sequence of IEEE operations that defines the result.
 //
 // Kernels
-//   k_cull      each block claims 512-row tiles with a ticket,
-//               stages the tile's geometry through LDS with 128-bit loads,
-//               restores deferred rows, culls, and compacts the kept rows in
-//               id order: wave ballot + mbcnt, block scan in LDS, decoupled
-//               look-back across tiles (single pass, deterministic).
+//   k_cull, k_tile_scan, k_tile_ids
+//               one block per 512-row tile stages the geometry through LDS
+//               with 128-bit loads, restores deferred rows (band classifier
+//               first), culls and stores wave ballots and tile counts; one
+//               block scans the tile counts; one wavefront per tile writes the
+//               ids in order.  Deterministic, no global atomics, no waits.
 //   k_rows      one wavefront per Gaussian row, lanes 0..9 = G columns,
-//               lanes 10..10+dim = A columns; three modes:
+//               lanes 10..10+dim = A columns; modes:
 //                 gather  restore current values into compact buffers
-//                 adam    restore + Adam with fused gradient scatter
+//                 adam    restore + Adam (AdamW, SGD with momentum) with fused
+//                         gradient scatter
 //                 flush   catch up every deferred row
-//   k_scatter   compact -> dense gradient rows
+//                 max     FP8 first pass (block maxima of new moments)
+//   k_fp8_rescale, k_dense_geo, k_scatter
+//   k_cull_multi, k_multi_scan, k_multi_ids, k_grad_sum   batched form
+//   k_dens_plan, k_dens_scan, k_dens_apply                densification
 //   k_synth     synthetic gradients (harness only)
 #include <hip/hip_runtime.h>
 
@@ -1462,7 +1467,7 @@ int row_grid(int64_t rows)
 //   cam_pos[c]: for camera slot c, the union positions of the rows it sees
 //               (ascending, all scenes back to back; scene_start gives each
 //               scene's first entry in every list)
-// with a decoupled look-back whose payload is 33 counters.
+// from per-tile counts of 33 counters (union and 32 camera slots).
 constexpr int kMaxCams = 32;
 constexpr int kNCnt = kMaxCams + 1;
 constexpr int kMultiAlign = 1024;
