@@ -886,7 +886,9 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
             if (!need) continue;
             const int64_t r = id[u];
             if (MODE != kAdamMax) w[u] = isG ? a.gw[r * a.gw_ld + lane] : a.aw[r * a.aw_ld + ca];
-            if ((MODE == kAdam || MODE == kAdamMax || d[u] > 0) && grest) {
+            // the gather loads the moments without waiting for last_step: most
+            // visible rows are deferred, and the loads then overlap the last_step one
+            if ((MODE == kAdam || MODE == kAdamMax || MODE == kGather || d[u] > 0) && grest) {
                 if (isG) {
                     m[u] = mom_load<GST>(qm, r, col, false);
                     if (!sgd) v[u] = mom_load<GST>(qv, r, col, true);
