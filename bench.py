@@ -41,7 +41,7 @@ def parse():
     p.add_argument("--copy-probe", type=int, default=0,
                    help="only copy this many MiB device-to-device 5 times (calibrates HBM byte counters)")
     p.add_argument("--n", type=int, default=None, help="override the Gaussian count")
-    p.add_argument("--layout", default="interleaved", choices=["separate", "interleaved", "fused"])
+    p.add_argument("--layout", default="fused", choices=["separate", "interleaved", "fused"])
     p.add_argument("--max-defer", type=int, default=0)
     p.add_argument("--cull-mode", type=int, default=1)
     p.add_argument("--state", default="f32", choices=["f32", "bf16", "fp8"], help="Adam moment storage (both groups)")

@@ -342,8 +342,10 @@ __device__ __forceinline__ RowPre classify_pre(const float *g, float wd, const B
     const float smax = fmaxf(fmaxf(g[3], g[4]), g[5]) + dscl + 1e-6f * fmaxf(fmaxf(fabsf(g[3]), fabsf(g[4])), fabsf(g[5]));
     const float sig = __expf(fminf(smax, 80.0f)) * 1.001f;
     p.sig2 = sig * sig;
-    const float qn = sqrtf(((g[6] * g[6] + g[7] * g[7]) + g[8] * g[8]) + g[9] * g[9]);
-    p.ok = (fin && smax < 80.0f) ? (qn > 2.002f * dq + 1e-6f ? 3 : 1) : 0;
+    // |q| > 2.002 dq + 1e-6, compared squared (the 0.1% margin covers the rounding)
+    const float qn2 = ((g[6] * g[6] + g[7] * g[7]) + g[8] * g[8]) + g[9] * g[9];
+    const float qmin = 2.002f * dq + 1e-6f;
+    p.ok = (fin && smax < 80.0f) ? (qn2 > 1.001f * (qmin * qmin) ? 3 : 1) : 0;
     return p;
 }
 
@@ -363,10 +365,12 @@ __device__ __forceinline__ int classify_cam(const float *g, const RowPre &p, con
     const float zlo = z - ez, zhi = z + ez;
     if (zhi <= c.zn || zlo >= c.zf) return 0;
     if (!(zlo > 0.0f)) return 2;
-    const float izl = 1.0f / zlo, izh = 1.0f / zhi;
+    // the hardware reciprocal and square root (about 1 ulp) suffice: every
+    // bound below carries a margin of 1e-5 relative or more
+    const float izl = __builtin_amdgcn_rcpf(zlo), izh = __builtin_amdgcn_rcpf(zhi);
     const float S = ((b.jf2 * izl) * izl) * p.sig2;
     const float lam = 1.001f * S + 0.95f;
-    const float rup = 3.0f * sqrtf(lam) * 1.001f + 1.0f;
+    const float rup = 3.0f * __builtin_amdgcn_sqrtf(lam) * 1.001f + 1.0f;
     const float xlo = x - ex, xhi = x + ex, ylo = y - ey, yhi = y + ey;
     const float qxlo = fminf(xlo * izl, xlo * izh), qxhi = fmaxf(xhi * izl, xhi * izh);
     const float qylo = fminf(ylo * izl, ylo * izh), qyhi = fmaxf(yhi * izl, yhi * izh);
