@@ -1074,6 +1074,14 @@ __global__ __launch_bounds__(256) void k_fp8_rescale(RescaleArgs a)
             const bool is_v = wq & 1;
             uint8_t *q = a.q[wq];
             const int64_t ld = a.ld[wq];
+            // scales are powers of two: a normal code that stays normal only loses
+            // kshift from its exponent field (the stochastic rounding of an exactly
+            // representable value returns it), so only the rest takes the full
+            // decode / round path
+            int eo = 0, en = 0;
+            frexpf(sold, &eo);
+            frexpf(snew, &en);
+            const int kshift = sold > 0.0f ? en - eo : 99;
             // flattened (row, column) elements, kIlp loads in flight per lane
             for (int64_t e0 = 0; e0 < nel; e0 += 64 * kIlp) {
                 uint8_t code[kIlp];
@@ -1091,6 +1099,11 @@ __global__ __launch_bounds__(256) void k_fp8_rescale(RescaleArgs a)
 #pragma unroll
                 for (int k = 0; k < kIlp; ++k) {
                     if (off[k] < 0) continue;
+                    const int ef = (code[k] >> 3) & 15, mf = code[k] & 7;
+                    if (ef >= 1 && !(ef == 15 && mf == 7) && ef - kshift >= 1) {
+                        q[off[k]] = (uint8_t)((code[k] & 0x80) | ((ef - kshift) << 3) | mf);
+                        continue;
+                    }
                     const float x = e4m3_dec(code[k]) * sold;
                     const u64 h = sm_at(sm_at(s_step, (u64)row[k]), (u64)(a.col0[wq] + col[k] + 64));
                     const u32 rr = (u32)((is_v ? h >> 16 : h) & 0xffffull);

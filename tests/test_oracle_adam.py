@@ -384,3 +384,21 @@ def test_f32_model_with_schedule_within_fp32_rounding_of_dense():
     o3.flush(steps)
     for k, tau in ((0, TAU_GEO), (1, TAU_APP)):
         assert np.max(rel_err(o3.w[k], dense.w[k], tau)) < 1e-6
+
+
+def test_e4m3_exponent_shift_is_exact_stochastic_rounding():
+    """Growing a block scale by 2^k re-encodes each code as SR(x / 2^k).  For a
+    normal code whose exponent stays normal the value is exactly representable,
+    so every random draw gives the code with k taken off the exponent field
+    (the rescale kernel's fast path); all other codes need the full rounding."""
+    f = orc.lib().orc_e4m3_sr
+    for code in range(256):
+        e, m = (code >> 3) & 15, code & 7
+        if e == 0 or (e == 15 and m == 7):
+            continue
+        x = float(orc.e4m3_decode(np.array([code], np.uint8))[0])
+        for k in range(1, 12):
+            y = np.float32(x * 2.0 ** -k)
+            got = {f(float(y), r) for r in (0, 1, 0x7fff, 0xfffe, 0xffff)}
+            if e - k >= 1:
+                assert got == {(code & 0x80) | ((e - k) << 3) | m}, (code, k)
