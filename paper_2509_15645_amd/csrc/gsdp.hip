@@ -799,6 +799,8 @@ struct RowArgs {
     float *gd_geo, *gd_app;          // dense gradients (read and cleared)
     float *out_geo, *out_app;        // gather outputs
     u32 *fp8max[4];                  // per-block max |m'|, sqrt(v') that outgrew the scale (G m, G v, A m, A v)
+    u32 *fp8list, *fp8count;         // tasks (moment * nb + block) that outgrew their scale, and their count
+    int64_t nb;
 };
 
 // One wavefront per Gaussian row: lane c < 10 owns G column c, lane 10+c owns
@@ -854,6 +856,8 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
         bc = a.BC[t];
     }
     const float step = lr * ss;
+    // the rescale (previous launch) has consumed the task list of this step
+    if (MODE == kAdam && a.fp8count && blockIdx.x == 0 && threadIdx.x == 0) *a.fp8count = 0u;
     const bool quant = (GST != GS_F32) || (AST != GS_F32);
     const u64 s_step = quant ? sm_at(a.sr_seed, (u64)t) : 0ull;
 
@@ -952,7 +956,14 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
                 if (lane == 0)
 #pragma unroll
                     for (int k = 0; k < 4; ++k)
-                        if (mx[k]) atomicMax(&a.fp8max[k][b], mx[k]);
+                        if (mx[k]) {
+                            // the first record of a task this step lists it for the rescale
+                            const u32 old = atomicMax(&a.fp8max[k][b], mx[k]);
+                            if (old == 0u) {
+                                const u32 at = atomicAdd(a.fp8count, 1u);
+                                if ((int64_t)at < 4 * a.nb) a.fp8list[at] = (u32)(k * a.nb + b);
+                            }
+                        }
                 continue;
             }
             if (MODE == kFlush && dd == 0) continue;
@@ -1031,42 +1042,31 @@ struct RescaleArgs {
     int64_t n, nb;
     u64 sr_seed;
     StepK step;
+    const u32 *list, *count;         // tasks that outgrew their scale this step
 };
 
+// One workgroup per listed task (moment, 128-row block): grow the scale to the
+// smallest power of two that fits the recorded max and re-encode the block.
 __global__ __launch_bounds__(256) void k_fp8_rescale(RescaleArgs a)
 {
-    constexpr int kIlp = 8;
-    const int lane = threadIdx.x & 63;
-    const int64_t wid = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int64_t nw = (int64_t)gridDim.x * 4;
+    constexpr int kIlp = 4;
+    __shared__ float sOld;
+    const int tid = threadIdx.x;
     const float *Wrow;
     int dmax;
     const int t = resolve_step(a.step, 0, &Wrow, &dmax);
     const u64 s_step = sm_at(a.sr_seed, (u64)t);
-    const int64_t ntask = 4 * a.nb;
-    // lane-parallel scan: each wave checks 64 (moment, block) tasks with one
-    // load and then re-encodes the blocks that grew, whole wave per block
-    for (int64_t g0 = wid * 64; g0 < ntask; g0 += nw * 64) {
-        const int64_t task = g0 + lane;
-        int which = 0;
-        int64_t b = 0;
-        u32 mb = 0;
-        if (task < ntask) {
-            which = (int)(task / a.nb);
-            b = task - (int64_t)which * a.nb;
-            if (a.fp8[which]) mb = a.maxb[which][b];
-        }
-        u64 todo = __ballot(mb != 0u);
-        if (mb != 0u) a.maxb[which][b] = 0u;
-        while (todo) {
-            const int src = __builtin_ctzll(todo);
-            todo &= todo - 1;
-            const int wq = __shfl(which, src);
-            const int64_t bq = (int64_t)__shfl((long long)b, src);
-            const float amax = __uint_as_float((u32)__shfl((int)mb, src));
-            const float sold = a.s[wq][bq];
-            const float snew = fp8_scale_for(amax);
-            if (!(snew > sold)) continue;
+    const u32 ntask = (u32)min((int64_t)*a.count, 4 * a.nb);
+    for (u32 i = blockIdx.x; i < ntask; i += gridDim.x) {
+        const u32 task = a.list[i];
+        const int wq = (int)(task / (u32)a.nb);
+        const int64_t bq = (int64_t)(task - (u32)wq * (u32)a.nb);
+        const float amax = __uint_as_float(a.maxb[wq][bq]);
+        if (tid == 0) sOld = a.s[wq][bq];
+        __syncthreads();
+        const float sold = sOld;
+        const float snew = fp8_scale_for(amax);
+        if (snew > sold) {
             const int dim = a.dim[wq];
             const int64_t r0 = bq * kFp8Block;
             const int64_t nrow = min((int64_t)kFp8Block, a.n - r0);
@@ -1076,20 +1076,18 @@ __global__ __launch_bounds__(256) void k_fp8_rescale(RescaleArgs a)
             const int64_t ld = a.ld[wq];
             // scales are powers of two: a normal code that stays normal only loses
             // kshift from its exponent field (the stochastic rounding of an exactly
-            // representable value returns it), so only the rest takes the full
-            // decode / round path
+            // representable value returns it); the rest take the full rounding
             int eo = 0, en = 0;
             frexpf(sold, &eo);
             frexpf(snew, &en);
             const int kshift = sold > 0.0f ? en - eo : 99;
-            // flattened (row, column) elements, kIlp loads in flight per lane
-            for (int64_t e0 = 0; e0 < nel; e0 += 64 * kIlp) {
+            for (int64_t e0 = 0; e0 < nel; e0 += 256 * kIlp) {
                 uint8_t code[kIlp];
                 int64_t off[kIlp], row[kIlp];
                 int col[kIlp];
 #pragma unroll
                 for (int k = 0; k < kIlp; ++k) {
-                    const int64_t e = e0 + k * 64 + lane;
+                    const int64_t e = e0 + k * 256 + tid;
                     const int64_t rr = e / dim;
                     row[k] = r0 + rr;
                     col[k] = (int)(e - rr * dim);
@@ -1110,7 +1108,11 @@ __global__ __launch_bounds__(256) void k_fp8_rescale(RescaleArgs a)
                     q[off[k]] = (uint8_t)e4m3_sr(x / snew, rr);
                 }
             }
-            if (lane == 0) a.s[wq][bq] = snew;
+        }
+        __syncthreads();              // every thread has read sold and the codes
+        if (tid == 0) {
+            if (snew > sold) a.s[wq][bq] = snew;
+            a.maxb[wq][bq] = 0u;
         }
     }
 }
@@ -2462,6 +2464,9 @@ int gs_adam_step_deferred(const gs_model *model, int64_t step, const uint32_t *i
         const int64_t nb = gsdp::fp8_blocks(model->n);
         u32 *mx = reinterpret_cast<u32 *>(wsb + gsdp::ws_fp8_offset(model->n, model->max_defer));
         for (int k = 0; k < 4; ++k) a.fp8max[k] = mx + k * nb;
+        a.fp8list = mx + 4 * nb;
+        a.fp8count = mx + 8 * nb;
+        a.nb = nb;
         launch_rows<kAdamMax>(model, row_grid(rows), (hipStream_t)stream, a);
         int rc1 = launched("gs_adam_step_deferred (fp8 max pass)");
         if (rc1) return rc1;
@@ -2484,7 +2489,10 @@ int gs_adam_step_deferred(const gs_model *model, int64_t step, const uint32_t *i
         ra.nb = nb;
         ra.sr_seed = model->sr_seed;
         ra.step = step_k(model, step);
-        hipLaunchKernelGGL(k_fp8_rescale, dim3(row_grid(4 * nb * kRowUnroll / 64 + 1)), dim3(256), 0,
+        ra.list = a.fp8list;
+        ra.count = a.fp8count;
+        const int cu = cu_count();
+        hipLaunchKernelGGL(k_fp8_rescale, dim3((unsigned)((cu > 0 ? cu : 256) * 4)), dim3(256), 0,
                            (hipStream_t)stream, ra);
         rc1 = launched("gs_adam_step_deferred (fp8 rescale)");
         if (rc1) return rc1;

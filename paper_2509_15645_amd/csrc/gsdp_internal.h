@@ -78,10 +78,13 @@ inline int64_t ws_fp8_offset(int64_t n, int32_t K)
     const int64_t b = ws_sat_offset(n, K) + (K > 0 ? 4 * n : 0);
     return (b + 7) / 8 * 8;
 }
-// fp8: per-block max arrays for G m, G v, A m, A v (u32 each)
+// fp8: per-block max arrays for G m, G v, A m, A v (u32 each), the list of
+// (moment, block) tasks that outgrew their scale this step (u32 each) and its
+// length (u32, reset by the update pass)
+inline int64_t ws_fp8_bytes(int64_t n) { return 32 * fp8_blocks(n) + 64; }
 inline int64_t ws_bytes_for(int64_t n, int32_t K, int32_t fp8)
 {
-    const int64_t b = ws_fp8_offset(n, K) + (fp8 ? 16 * fp8_blocks(n) : 0);
+    const int64_t b = ws_fp8_offset(n, K) + (fp8 ? ws_fp8_bytes(n) : 0);
     return (b + 255) / 256 * 256;
 }
 
