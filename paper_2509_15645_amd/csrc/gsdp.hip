@@ -590,19 +590,8 @@ __global__ __launch_bounds__(kCullBlock) void k_cull(CullArgs a)
     }
 }
 
-// Exclusive prefix of (visible, saturated) over tiles by one block.  Tiles
-// go through LDS in chunks of kScanChunk: coalesced loads into LDS, then each
-// thread scans a contiguous run of 8 from LDS, a block scan of the 1024 run
-// sums, and coalesced stores of the prefixes; a carry links the chunks.
-struct ScanArgs {
-    const u64 *tile_vs;              // [tiles] visible << 32 | saturated
-    const u32 *tile_rest;            // [tiles]
-    u64 *tile_off;                   // [tiles] exclusive prefix, same packing
-    int64_t tiles;
-    u32 *count;                      // visible total (device, the caller's count)
-    gsdp::WsHeader *hdr;
-};
-
+// Block scans used by the one-block counter scans of the batched cull and of
+// densification.
 constexpr int kScanThreads = 1024;
 constexpr int kScanPer = 7;           // 56 KB of LDS per chunk
 constexpr int kScanChunk = kScanThreads * kScanPer;
@@ -633,56 +622,6 @@ __device__ __forceinline__ u64 block_excl_scan_u64(u64 x, u64 *sWave, u64 *total
     const u64 r = sWave[wave] + inc - x;
     __syncthreads();                 // sWave may be reused by the caller's next scan
     return r;
-}
-
-__global__ __launch_bounds__(kScanThreads) void k_tile_scan(ScanArgs a)
-{
-    __shared__ u64 sV[kScanChunk];
-    __shared__ u64 sWave[kScanThreads / 64 + 1];
-    const int tid = threadIdx.x;
-    u64 carry = 0, rest = 0;
-    for (int64_t c0 = 0; c0 < a.tiles; c0 += kScanChunk) {
-        const int64_t nc = min((int64_t)kScanChunk, a.tiles - c0);
-#pragma unroll
-        for (int q = 0; q < kScanPer; ++q) {
-            const int64_t i = (int64_t)q * kScanThreads + tid;
-            sV[i] = i < nc ? a.tile_vs[c0 + i] : 0ull;
-            if (i < nc) rest += a.tile_rest[c0 + i];
-        }
-        __syncthreads();
-        u64 v[kScanPer], sum = 0;
-#pragma unroll
-        for (int q = 0; q < kScanPer; ++q) {
-            v[q] = sV[tid * kScanPer + q];
-            sum += v[q];
-        }
-        u64 tot = 0;
-        u64 run = carry + block_excl_scan_u64(sum, sWave, &tot);
-#pragma unroll
-        for (int q = 0; q < kScanPer; ++q) {
-            sV[tid * kScanPer + q] = run;
-            run += v[q];
-        }
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < kScanPer; ++q) {
-            const int64_t i = (int64_t)q * kScanThreads + tid;
-            if (i < nc) a.tile_off[c0 + i] = sV[i];
-        }
-        carry += tot;
-        __syncthreads();             // sV is refilled by the next chunk
-    }
-    u64 rtot = 0;
-    block_excl_scan_u64(rest, sWave, &rtot);
-    if (tid == 0) {
-        const u32 vis = (u32)(carry >> 32);
-        *a.count = vis;
-        a.hdr->vis_total = vis;
-        a.hdr->sat_total = (u32)carry;
-        a.hdr->restored_last = (u32)rtot;
-        a.hdr->vis_accum += vis;
-        a.hdr->restored_accum += rtot;
-    }
 }
 
 // Exclusive prefix of one u32 count per tile, by the whole block, through LDS
@@ -725,26 +664,104 @@ __device__ u64 scan_counts_u32(const u32 *cnt, u32 *off, int64_t tiles, u64 *sV,
     return carry;
 }
 
-// One wavefront per tile: visible (and saturated) ids in ascending order from
-// the tile's ballots and exclusive prefix.
+// Prefix of the tile counts in two launches of many blocks.  k_tile_reduce:
+// one wavefront per group of 64 tiles sums its (visible, saturated) and
+// restored counts.  k_tile_ids: one block per group adds the sums of all
+// earlier groups (read from L2), scans its 64 tiles in one wavefront, stores
+// the tile prefixes, and then writes the visible (and saturated) ids of its
+// tiles in ascending order from the ballots, one wavefront per tile; the last
+// group's block writes the totals.
 struct IdsArgs {
     const u64 *keep_bits, *sat_bits;
-    const u64 *tile_off;             // visible << 32 | saturated before the tile
-    int64_t tiles, n;
+    const u64 *tile_vs;              // visible << 32 | saturated of each tile
+    const u32 *tile_rest;
+    u64 *tile_off;                   // visible << 32 | saturated before the tile
+    u64 *grp_vs, *grp_rest;          // per group of 64 tiles
+    int64_t tiles, groups, n;
     u32 *ids;
     u32 cap, pad;
     u32 *sat_ids;
+    u32 *count;
+    gsdp::WsHeader *hdr;
 };
+
+__global__ __launch_bounds__(256) void k_tile_reduce(IdsArgs a)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t g = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (g >= a.groups) return;
+    const int64_t tile = g * gsdp::kGroupTiles + lane;
+    u64 vs = 0, rest = 0;
+    if (tile < a.tiles) {
+        vs = a.tile_vs[tile];
+        rest = a.tile_rest[tile];
+    }
+    vs = wave_sum_u64(vs);
+    rest = wave_sum_u64(rest);
+    if (lane == 0) {
+        a.grp_vs[g] = vs;
+        a.grp_rest[g] = rest;
+    }
+}
 
 __global__ __launch_bounds__(256) void k_tile_ids(IdsArgs a)
 {
-    const int lane = threadIdx.x & 63;
-    const int64_t wid = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int64_t nw = (int64_t)gridDim.x * 4;
+    __shared__ u64 sRed[2][4];
+    __shared__ u64 sPre[gsdp::kGroupTiles];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t g = blockIdx.x;
+    const bool last = g == (a.groups > 0 ? a.groups - 1 : 0);
+    // sums of the earlier groups (and, for the last block, of all groups)
+    const int64_t upto = last ? a.groups : g;
+    u64 base = 0, rest = 0;
+    for (int64_t i = tid; i < upto; i += 256) {
+        if (i < g) base += a.grp_vs[i];
+        if (last) rest += a.grp_rest[i];
+    }
+    base = wave_sum_u64(base);
+    rest = wave_sum_u64(rest);
+    if (lane == 0) {
+        sRed[0][wave] = base;
+        sRed[1][wave] = rest;
+    }
+    __syncthreads();
+    base = (sRed[0][0] + sRed[0][1]) + (sRed[0][2] + sRed[0][3]);
+    if (last) {
+        // the last block also knows every total
+        const u64 tot = base + (g < a.groups ? a.grp_vs[g] : 0ull);
+        const u64 rtot = (sRed[1][0] + sRed[1][1]) + (sRed[1][2] + sRed[1][3]);
+        if (tid == 0) {
+            const u32 vis = (u32)(tot >> 32);
+            *a.count = vis;
+            a.hdr->vis_total = vis;
+            a.hdr->sat_total = (u32)tot;
+            a.hdr->restored_last = (u32)rtot;
+            a.hdr->vis_accum += vis;
+            a.hdr->restored_accum += rtot;
+        }
+    }
+    if (g >= a.groups) return;
+    const int64_t t0 = g * gsdp::kGroupTiles;
+    if (wave == 0) {
+        const int64_t tile = t0 + lane;
+        const u64 c = tile < a.tiles ? a.tile_vs[tile] : 0ull;
+        u64 inc = c;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const u64 y = (u64)__shfl_up((long long)inc, o);
+            if (lane >= o) inc += y;
+        }
+        const u64 pre = base + inc - c;
+        sPre[lane] = pre;
+        if (tile < a.tiles) a.tile_off[tile] = pre;
+    }
+    __syncthreads();
     const u64 lt = (1ull << lane) - 1ull;
-    for (int64_t tile = wid; tile < a.tiles; tile += nw) {
+    for (int j = wave; j < gsdp::kGroupTiles; j += 4) {
+        const int64_t tile = t0 + j;
+        if (tile >= a.tiles) break;
         const int64_t row0 = tile * kCullTile;
-        const u64 o = a.tile_off[tile];
+        const u64 o = sPre[j];
         u64 kw = 0, sw = 0;
         if (lane < gsdp::kWordsPerTile) {
             kw = a.keep_bits[tile * gsdp::kWordsPerTile + lane];
@@ -1518,6 +1535,8 @@ struct MultiArgs {
     u32 *scene_start;                // [S][1+C]
     u32 *cnt;                        // [kNCnt][stride] per-tile counts (union, camera slots)
     u32 *off;                        // [kNCnt][stride] exclusive prefixes over tiles
+    u32 *grp;                        // [kNCnt][gstride] sums over groups of 64 tiles
+    int64_t gstride;
     u32 *mask;                       // [n] camera bits of every row
     int64_t tiles;                   // tiles of this launch
     int64_t stride;                  // tiles of the smallest tile size
@@ -1634,19 +1653,56 @@ __global__ __launch_bounds__(BLOCK) void k_cull_multi(MultiArgs a)
     }
 }
 
-// Exclusive prefixes over tiles of every counter (one block), totals and the
-// scene starts.
-__global__ __launch_bounds__(kScanThreads) void k_multi_scan(MultiArgs a)
+// Exclusive prefixes over tiles of every counter in two launches of many
+// blocks: k_multi_reduce sums each group of 64 tiles (one wavefront per group);
+// k_multi_offsets (one block per group) adds the sums of the earlier groups and
+// scans the group's tiles; the last group's block writes the totals.
+__global__ __launch_bounds__(256) void k_multi_reduce(MultiArgs a)
 {
-    __shared__ u64 sV[kScanChunk];
-    __shared__ u64 sWave[kScanThreads / 64 + 1];
-    const int C = a.C;
-    for (int j = 0; j < 1 + C; ++j) {
-        const u64 tot = scan_counts_u32(a.cnt + (int64_t)j * a.stride, a.off + (int64_t)j * a.stride, a.tiles, sV,
-                                        sWave);
-        if (threadIdx.x == 0) {
-            if (j == 0) *a.union_count = (u32)tot;
-            else a.cam_count[j - 1] = (u32)tot;
+    const int lane = threadIdx.x & 63;
+    const int64_t g = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t groups = (a.tiles + 63) / 64;
+    if (g >= groups) return;
+    const int64_t tile = g * 64 + lane;
+    for (int j = 0; j < 1 + a.C; ++j) {
+        const u64 c = tile < a.tiles ? (u64)a.cnt[(int64_t)j * a.stride + tile] : 0ull;
+        const u64 sum = wave_sum_u64(c);
+        if (lane == 0) a.grp[(int64_t)j * a.gstride + g] = (u32)sum;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_multi_offsets(MultiArgs a)
+{
+    __shared__ u64 sRed[4][kNCnt];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t g = blockIdx.x;
+    const int64_t groups = (a.tiles + 63) / 64;
+    const bool last = g == (groups > 0 ? groups - 1 : 0);
+    const int ncnt = 1 + a.C;
+    for (int j = 0; j < ncnt; ++j) {
+        u64 base = 0;
+        for (int64_t i = tid; i < g; i += 256) base += a.grp[(int64_t)j * a.gstride + i];
+        base = wave_sum_u64(base);
+        if (lane == 0) sRed[wave][j] = base;
+    }
+    __syncthreads();
+    if (wave == 0) {
+        const int64_t tile = g * 64 + lane;
+        for (int j = 0; j < ncnt; ++j) {
+            const u64 base = (sRed[0][j] + sRed[1][j]) + (sRed[2][j] + sRed[3][j]);
+            const u64 c = (g < groups && tile < a.tiles) ? (u64)a.cnt[(int64_t)j * a.stride + tile] : 0ull;
+            u64 inc = c;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const u64 y = (u64)__shfl_up((long long)inc, o);
+                if (lane >= o) inc += y;
+            }
+            if (g < groups && tile < a.tiles) a.off[(int64_t)j * a.stride + tile] = (u32)(base + inc - c);
+            if (last && lane == 63) {
+                const u32 tot = (u32)(base + inc);
+                if (j == 0) *a.union_count = tot;
+                else a.cam_count[j - 1] = tot;
+            }
         }
     }
 }
@@ -2029,7 +2085,8 @@ constexpr int kMultiIpt[kMultiVariants] = {1, 2, 4, 1, 2, 4};
 int64_t multi_ws_bytes(int64_t n)
 {
     const int64_t tiles = (n + kMultiMinTile - 1) / kMultiMinTile;
-    return gsdp::kWsHeader + 2 * tiles * kNCnt * 4 + 4 * ((n + 1) / 2 * 2);
+    const int64_t groups = (tiles + 63) / 64;
+    return gsdp::kWsHeader + 2 * tiles * kNCnt * 4 + groups * kNCnt * 4 + 4 * ((n + 1) / 2 * 2);
 }
 
 int multi_args(const gs_model *model, const gs_multi *d, int64_t step, void *ws, size_t ws_bytes, MultiArgs &a)
@@ -2072,7 +2129,9 @@ int multi_args(const gs_model *model, const gs_multi *d, int64_t step, void *ws,
     const int64_t max_tiles = (model->n + kMultiMinTile - 1) / kMultiMinTile;
     a.cnt = reinterpret_cast<u32 *>(wsb + gsdp::kWsHeader);
     a.off = a.cnt + max_tiles * kNCnt;
-    a.mask = a.off + max_tiles * kNCnt;
+    a.gstride = (max_tiles + 63) / 64;
+    a.grp = a.off + max_tiles * kNCnt;
+    a.mask = a.grp + a.gstride * kNCnt;
     a.tiles = max_tiles;  // replaced per variant in launch_multi
     return GS_OK;
 }
@@ -2087,7 +2146,9 @@ void launch_multi_t(MultiArgs a, int64_t n, int64_t max_tiles, hipStream_t st)
     a.stride = max_tiles;
     a.tile_rows = TR;
     if (a.tiles > 0) hipLaunchKernelGGL((k_cull_multi<BLOCK, IPT>), dim3((unsigned)a.tiles), dim3(BLOCK), 0, st, a);
-    hipLaunchKernelGGL(k_multi_scan, dim3(1), dim3(kScanThreads), 0, st, a);
+    const int64_t groups = (a.tiles + 63) / 64;
+    if (groups > 0) hipLaunchKernelGGL(k_multi_reduce, dim3((unsigned)((groups + 3) / 4)), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_multi_offsets, dim3((unsigned)(groups > 0 ? groups : 1)), dim3(256), 0, st, a);
     if (a.tiles > 0) hipLaunchKernelGGL((k_multi_ids<BLOCK, IPT>), dim3((unsigned)a.tiles), dim3(BLOCK), 0, st, a);
 }
 
@@ -2326,28 +2387,30 @@ int gs_cull(const gs_model *model, const gs_camera *cam, int64_t step, uint32_t 
         int rc1 = launched("gs_cull (tiles)");
         if (rc1) return rc1;
     }
-    ScanArgs sa;
-    sa.tile_vs = a.tile_vs;
-    sa.tile_rest = a.tile_rest;
-    sa.tile_off = reinterpret_cast<u64 *>(wsb + gsdp::ws_off_offset(n));
-    sa.tiles = a.tiles;
-    sa.count = count_dev;
-    sa.hdr = reinterpret_cast<gsdp::WsHeader *>(wsb);
-    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(kScanThreads), 0, st, sa);
-    int rc2 = launched("gs_cull (scan)");
-    if (rc2 || a.tiles == 0) return rc2;
     IdsArgs ia;
+    memset(&ia, 0, sizeof ia);
     ia.keep_bits = a.keep_bits;
     ia.sat_bits = a.sat_bits;
-    ia.tile_off = sa.tile_off;
+    ia.tile_vs = a.tile_vs;
+    ia.tile_rest = a.tile_rest;
+    ia.tile_off = reinterpret_cast<u64 *>(wsb + gsdp::ws_off_offset(n));
+    ia.grp_vs = reinterpret_cast<u64 *>(wsb + gsdp::ws_grp_offset(n));
+    ia.grp_rest = ia.grp_vs + gsdp::cull_groups(n);
     ia.tiles = a.tiles;
+    ia.groups = gsdp::cull_groups(n);
     ia.n = n;
     ia.ids = ids;
     ia.cap = capacity;
-    ia.pad = 0;
     ia.sat_ids = model->max_defer > 0 ? reinterpret_cast<u32 *>(wsb + gsdp::ws_sat_offset(n, model->max_defer))
                                       : nullptr;
-    hipLaunchKernelGGL(k_tile_ids, dim3(row_grid(a.tiles * kRowUnroll)), dim3(256), 0, st, ia);
+    ia.count = count_dev;
+    ia.hdr = reinterpret_cast<gsdp::WsHeader *>(wsb);
+    if (ia.groups > 0) {
+        hipLaunchKernelGGL(k_tile_reduce, dim3((unsigned)((ia.groups + 3) / 4)), dim3(256), 0, st, ia);
+        int rc2 = launched("gs_cull (group sums)");
+        if (rc2) return rc2;
+    }
+    hipLaunchKernelGGL(k_tile_ids, dim3((unsigned)(ia.groups > 0 ? ia.groups : 1)), dim3(256), 0, st, ia);
     return launched("gs_cull");
 }
 

@@ -48,9 +48,10 @@ constexpr int kCullBlock = 256;
 constexpr int kCullIpt = 2;
 constexpr int kCullTile = kCullBlock * kCullIpt;
 
-// Workspace layout (bytes): header | tile counts [tiles][4] (u32) | tile prefixes
-// [tiles][2] (u32) | keep ballots [tiles][8] (u64) | saturated ballots [tiles][8]
-// (u64, max_defer > 0) | saturated ids [n] (u32, max_defer > 0) | FP8 block maxima
+// Workspace layout (bytes): header | tile counts (u64 visible<<32|saturated, then
+// u32 restored) | tile prefixes (u64) | group sums [groups][2] (u64) | keep ballots
+// [tiles][8] (u64) | saturated ballots [tiles][8] (u64, max_defer > 0) |
+// saturated ids [n] (u32, max_defer > 0) | FP8 block maxima and task list
 constexpr int64_t kWsHeader = 256;
 struct WsHeader {
     uint32_t vis_total;      // visible rows of the last cull
@@ -66,7 +67,11 @@ inline int64_t cull_tiles(int64_t n) { return (n + kCullTile - 1) / kCullTile; }
 constexpr int kWordsPerTile = kCullTile / 64;
 inline int64_t ws_cnt_offset(int64_t) { return kWsHeader; }
 inline int64_t ws_off_offset(int64_t n) { return kWsHeader + 16 * cull_tiles(n); }
-inline int64_t ws_keep_offset(int64_t n) { return ws_off_offset(n) + 8 * cull_tiles(n); }
+// groups of kGroupTiles tiles: per-group sums of (visible, saturated) and restored
+constexpr int kGroupTiles = 64;
+inline int64_t cull_groups(int64_t n) { return (cull_tiles(n) + kGroupTiles - 1) / kGroupTiles; }
+inline int64_t ws_grp_offset(int64_t n) { return ws_off_offset(n) + 8 * cull_tiles(n); }
+inline int64_t ws_keep_offset(int64_t n) { return ws_grp_offset(n) + 16 * cull_groups(n); }
 inline int64_t ws_satbits_offset(int64_t n) { return ws_keep_offset(n) + 8 * kWordsPerTile * cull_tiles(n); }
 inline int64_t ws_sat_offset(int64_t n, int32_t K)
 {
