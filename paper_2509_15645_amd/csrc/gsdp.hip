@@ -1022,7 +1022,10 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
                 }
                 u32 rm = 0, rv = 0;
                 if (quant) {
-                    const u64 h = sm_at(sm_at(s_step, (u64)r), (u64)lane);
+                    // the row's part of the random stream is the same on every
+                    // lane: compute it once, on the scalar unit
+                    const u32 ru = (u32)__builtin_amdgcn_readfirstlane((int)r);
+                    const u64 h = sm_at(sm_at(s_step, (u64)ru), (u64)lane);
                     rm = (u32)(h & 0xffffull);
                     rv = (u32)((h >> 16) & 0xffffull);
                 }
