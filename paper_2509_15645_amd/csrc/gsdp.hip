@@ -704,9 +704,12 @@ __global__ __launch_bounds__(256) void k_tile_reduce(IdsArgs a)
     }
 }
 
-__global__ __launch_bounds__(256) void k_tile_ids(IdsArgs a)
+constexpr int kIdsThreads = 1024;    // 16 wavefronts per group of 64 tiles
+
+__global__ __launch_bounds__(kIdsThreads) void k_tile_ids(IdsArgs a)
 {
-    __shared__ u64 sRed[2][4];
+    constexpr int NW = kIdsThreads / 64;
+    __shared__ u64 sRed[2][NW];
     __shared__ u64 sPre[gsdp::kGroupTiles];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t g = blockIdx.x;
@@ -714,7 +717,7 @@ __global__ __launch_bounds__(256) void k_tile_ids(IdsArgs a)
     // sums of the earlier groups (and, for the last block, of all groups)
     const int64_t upto = last ? a.groups : g;
     u64 base = 0, rest = 0;
-    for (int64_t i = tid; i < upto; i += 256) {
+    for (int64_t i = tid; i < upto; i += kIdsThreads) {
         if (i < g) base += a.grp_vs[i];
         if (last) rest += a.grp_rest[i];
     }
@@ -725,11 +728,17 @@ __global__ __launch_bounds__(256) void k_tile_ids(IdsArgs a)
         sRed[1][wave] = rest;
     }
     __syncthreads();
-    base = (sRed[0][0] + sRed[0][1]) + (sRed[0][2] + sRed[0][3]);
+    base = 0;
+    u64 rsum = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        base += sRed[0][w];
+        rsum += sRed[1][w];
+    }
     if (last) {
         // the last block also knows every total
         const u64 tot = base + (g < a.groups ? a.grp_vs[g] : 0ull);
-        const u64 rtot = (sRed[1][0] + sRed[1][1]) + (sRed[1][2] + sRed[1][3]);
+        const u64 rtot = rsum;
         if (tid == 0) {
             const u32 vis = (u32)(tot >> 32);
             *a.count = vis;
@@ -757,7 +766,7 @@ __global__ __launch_bounds__(256) void k_tile_ids(IdsArgs a)
     }
     __syncthreads();
     const u64 lt = (1ull << lane) - 1ull;
-    for (int j = wave; j < gsdp::kGroupTiles; j += 4) {
+    for (int j = wave; j < gsdp::kGroupTiles; j += NW) {
         const int64_t tile = t0 + j;
         if (tile >= a.tiles) break;
         const int64_t row0 = tile * kCullTile;
@@ -2413,7 +2422,7 @@ int gs_cull(const gs_model *model, const gs_camera *cam, int64_t step, uint32_t 
         int rc2 = launched("gs_cull (group sums)");
         if (rc2) return rc2;
     }
-    hipLaunchKernelGGL(k_tile_ids, dim3((unsigned)(ia.groups > 0 ? ia.groups : 1)), dim3(256), 0, st, ia);
+    hipLaunchKernelGGL(k_tile_ids, dim3((unsigned)(ia.groups > 0 ? ia.groups : 1)), dim3(kIdsThreads), 0, st, ia);
     return launched("gs_cull");
 }
 
