@@ -327,18 +327,22 @@ struct BandK {
 struct RowPre {
     float dp;       // position drift bound incl. rounding of the restore
     float sig2;     // bound of sigma_max^2 after the restore
+    float mu;       // largest |position coordinate|
     int ok;         // 0: undecidable (non-finite, huge scale); bit 1: quaternion stays away from 0
 };
 
 __device__ __forceinline__ RowPre classify_pre(const float *g, float wd, const BandK &b)
 {
     RowPre p;
-    bool fin = true;
-#pragma unroll
-    for (int j = 0; j < 10; ++j) fin &= __builtin_isfinite(g[j]);
+    // one finiteness test of a sum: a NaN or an infinity anywhere (or a sum that
+    // overflows) makes it non-finite, which only sends the row to the exact path
+    const float fsum = (((fabsf(g[0]) + fabsf(g[1])) + (fabsf(g[2]) + fabsf(g[3]))) +
+                        ((fabsf(g[4]) + fabsf(g[5])) + (fabsf(g[6]) + fabsf(g[7])))) + (fabsf(g[8]) + fabsf(g[9]));
+    const bool fin = __builtin_isfinite(fsum);
     const float dpos = b.kpos * wd, dscl = b.kscl * wd, dq = b.kq * wd;
     const float mu = fmaxf(fmaxf(fabsf(g[0]), fabsf(g[1])), fabsf(g[2]));
     p.dp = dpos + 1e-6f * mu;
+    p.mu = mu;
     const float smax = fmaxf(fmaxf(g[3], g[4]), g[5]) + dscl + 1e-6f * fmaxf(fmaxf(fabsf(g[3]), fabsf(g[4])), fabsf(g[5]));
     const float sig = __expf(fminf(smax, 80.0f)) * 1.001f;
     p.sig2 = sig * sig;
@@ -356,9 +360,11 @@ __device__ __forceinline__ int classify_cam(const float *g, const RowPre &p, con
     const float x = ((c.R[0] * g[0] + c.R[1] * g[1]) + c.R[2] * g[2]) + c.T[0];
     const float y = ((c.R[3] * g[0] + c.R[4] * g[1]) + c.R[5] * g[2]) + c.T[1];
     const float z = ((c.R[6] * g[0] + c.R[7] * g[1]) + c.R[8] * g[2]) + c.T[2];
-    const float sx = fabsf(c.R[0] * g[0]) + fabsf(c.R[1] * g[1]) + fabsf(c.R[2] * g[2]) + fabsf(c.T[0]);
-    const float sy = fabsf(c.R[3] * g[0]) + fabsf(c.R[4] * g[1]) + fabsf(c.R[5] * g[2]) + fabsf(c.T[1]);
-    const float sz = fabsf(c.R[6] * g[0]) + fabsf(c.R[7] * g[1]) + fabsf(c.R[8] * g[2]) + fabsf(c.T[2]);
+    // magnitude of the terms of each transform row, bounded by |R_i|_1 max|mu| + |T_i|
+    // (rounds up by far less than the 1e-6 relative slack it feeds)
+    const float sx = b.rs0 * p.mu + fabsf(c.T[0]);
+    const float sy = b.rs1 * p.mu + fabsf(c.T[1]);
+    const float sz = b.rs2 * p.mu + fabsf(c.T[2]);
     const float ex = b.rs0 * dp + 1e-6f * (sx + b.rs0 * dp) + 1e-6f;
     const float ey = b.rs1 * dp + 1e-6f * (sy + b.rs1 * dp) + 1e-6f;
     const float ez = b.rs2 * dp + 1e-6f * (sz + b.rs2 * dp) + 1e-6f;
