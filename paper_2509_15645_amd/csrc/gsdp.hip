@@ -1799,7 +1799,7 @@ struct GradSumArgs {
     float *out_geo, *out_app;        // [cap_union][10], [cap_union][adim]
 };
 
-constexpr int kSumRows = 32;
+constexpr int kSumRows = 128;
 
 __device__ __forceinline__ u32 lower_bound_u32(const u32 *a, u32 n, u32 key)
 {
@@ -1812,37 +1812,73 @@ __device__ __forceinline__ u32 lower_bound_u32(const u32 *a, u32 n, u32 key)
     return lo;
 }
 
+// One block per chunk of kSumRows union positions: (1) each camera's entries in
+// the chunk are found by binary search and scattered into an LDS table
+// (row, camera) -> entry, with the row's camera bits; (2) one wavefront per
+// row (lane = column) adds the row's camera gradients in slot order,
+// (((0 + g_c0) + g_c1) + ...), so the sum is deterministic.
 __global__ __launch_bounds__(256) void k_grad_sum(GradSumArgs a)
 {
-    __shared__ float acc[kSumRows][64];
-    __shared__ u32 sLo[kMaxCams], sHi[kMaxCams];
-    const int tid = threadIdx.x;
+    __shared__ u32 sIdx[kSumRows][kMaxCams];
+    __shared__ u32 sMask[kSumRows];
+    __shared__ u32 sLo[kMaxCams], sOff[kMaxCams + 1];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int D = 10 + a.adim;
+    const int C = a.C;
     const u32 U = min(*a.union_count, a.cap_union);
     for (u32 p0 = blockIdx.x * kSumRows; p0 < U; p0 += gridDim.x * kSumRows) {
-        for (int e = tid; e < kSumRows * 64; e += 256) acc[e / 64][e % 64] = 0.0f;
-        if (tid < a.C) {
+        for (int e = tid; e < kSumRows; e += 256) sMask[e] = 0u;
+        if (tid < C) {
             const u32 nc = min(a.cam_count[tid], a.cap_cam);
             const u32 *lst = a.cam_pos + (size_t)tid * a.cap_cam;
-            sLo[tid] = lower_bound_u32(lst, nc, p0);
-            sHi[tid] = lower_bound_u32(lst, nc, p0 + kSumRows);
+            const u32 lo = lower_bound_u32(lst, nc, p0);
+            sLo[tid] = lo;
+            sOff[tid + 1] = lower_bound_u32(lst, nc, p0 + kSumRows) - lo;
         }
         __syncthreads();
-        for (int c = 0; c < a.C; ++c) {
-            const u32 lo = sLo[c], cnt = sHi[c] - lo;
-            const u32 *lst = a.cam_pos + (size_t)c * a.cap_cam;
-            const float *gc = a.g_cam + (size_t)c * a.cap_cam * D;
-            for (u32 e = tid; e < cnt * (u32)D; e += 256) {
-                const u32 i = lo + e / D, col = e % D;
-                acc[lst[i] - p0][col] += gc[(size_t)i * D + col];
-            }
-            __syncthreads();
+        if (tid == 0) {
+            sOff[0] = 0;
+            for (int c = 0; c < C; ++c) sOff[c + 1] += sOff[c];
         }
+        __syncthreads();
+        const u32 total = sOff[C];
+        for (u32 e = tid; e < total; e += 256) {
+            int c = 0;
+            while (e >= sOff[c + 1]) ++c;
+            const u32 i = sLo[c] + (e - sOff[c]);
+            const u32 p = a.cam_pos[(size_t)c * a.cap_cam + i] - p0;
+            sIdx[p][c] = i;
+            atomicOr(&sMask[p], 1u << c);
+        }
+        __syncthreads();
         const u32 np = min((u32)kSumRows, U - p0);
-        for (u32 e = tid; e < np * (u32)D; e += 256) {
-            const u32 r = e / D, col = e % D;
-            if (col < 10) a.out_geo[(size_t)(p0 + r) * 10 + col] = acc[r][col];
-            else a.out_app[(size_t)(p0 + r) * a.adim + (col - 10)] = acc[r][col];
+        for (u32 r = wave; r < np; r += 4) {
+            u32 m = sMask[r];
+            float acc = 0.0f;
+            // loads first (independent), then the adds in slot order
+            while (m) {
+                float v[8];
+                int cs[8];
+                int k = 0;
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    cs[q] = -1;
+                    v[q] = 0.0f;
+                    if (m) {
+                        const int c = __builtin_ctz(m);
+                        m &= m - 1u;
+                        cs[q] = c;
+                        if (lane < D) v[q] = a.g_cam[((size_t)c * a.cap_cam + sIdx[r][c]) * D + lane];
+                        ++k;
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    if (cs[q] >= 0) acc = acc + v[q];
+                (void)k;
+            }
+            if (lane < 10) a.out_geo[(size_t)(p0 + r) * 10 + lane] = acc;
+            else if (lane < D) a.out_app[(size_t)(p0 + r) * a.adim + (lane - 10)] = acc;
         }
         __syncthreads();
     }
