@@ -291,6 +291,33 @@ __device__ __forceinline__ void mom_store<GS_FP8E4M3>(const MomRef &q, int64_t r
     static_cast<uint8_t *>(q.p)[row * q.ld + col] = sc > 0.0f ? (uint8_t)e4m3_sr(y / sc, r16) : (uint8_t)0;
 }
 
+// Loads and stores of one moment element at an element address (the row's
+// base computed once per row on the scalar unit, plus the lane's column);
+// same arithmetic as mom_load / mom_store.  s is the row's FP8 block scale.
+template <int ST> __device__ __forceinline__ float mload(const char *e, float s, bool is_v)
+{
+    if (ST == GS_F32) return *reinterpret_cast<const float *>(e);
+    if (ST == GS_BF16) return __uint_as_float((u32) * reinterpret_cast<const uint16_t *>(e) << 16);
+    const float x = e4m3_dec(*reinterpret_cast<const uint8_t *>(e)) * s;
+    return is_v ? x * x : x;
+}
+template <int ST> __device__ __forceinline__ void mstore(char *e, float s, float x, u32 r16, bool is_v)
+{
+    if (ST == GS_F32) {
+        *reinterpret_cast<float *>(e) = x;
+    } else if (ST == GS_BF16) {
+        const u32 u = __float_as_uint(x);
+        uint16_t h;
+        if ((u & 0x7f800000u) == 0x7f800000u) h = (uint16_t)((u >> 16) | ((u & 0x007fffffu) ? 0x0040u : 0u));
+        else h = (uint16_t)((u + r16) >> 16);
+        *reinterpret_cast<uint16_t *>(e) = h;
+    } else {
+        const float y = is_v ? sqrtf(x) : x;
+        *reinterpret_cast<uint8_t *>(e) = s > 0.0f ? (uint8_t)e4m3_sr(y / s, r16) : (uint8_t)0;
+    }
+}
+template <int ST> constexpr int msize() { return ST == GS_F32 ? 4 : (ST == GS_BF16 ? 2 : 1); }
+
 // Adam step of one element, (st m1) / (sqrt(v1)/bc + eps), clamped to
 // st bc rb: moments grown from zero keep |m1|/sqrt(v1) below 7.27 < rb, so the
 // clamp never acts on an FP32 state; it bounds the step when quantised
@@ -846,7 +873,9 @@ template <int MODE, int GST, int AST>
 __global__ __launch_bounds__(256) void k_rows(RowArgs a)
 {
     const int lane = threadIdx.x & 63;
-    const int64_t wid = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    // the wavefront index is uniform: keep it (and so every row index and row
+    // id below) in scalar registers
+    const int64_t wid = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int64_t nw = (int64_t)gridDim.x * 4;
     const bool isG = lane < 10;
     // with dense geometry, G columns are updated elsewhere and never deferred
@@ -857,8 +886,6 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
     const int ca = lane - 10;
     const int col = isG ? lane : ca;
     const float lr = a.lr[lane];
-    const MomRef &qm = isG ? a.gm : a.am;
-    const MomRef &qv = isG ? a.gv : a.av;
     const float *Wrow;
     int dmax;
     const int t = resolve_step(a.step, MODE == kFlush ? 1 : 0, &Wrow, &dmax);
@@ -918,28 +945,65 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
             }
             d[u] = dd;
         }
+        // per row: element addresses of this lane's column.  The row id is the
+        // same on every lane, so the row bases are computed on the scalar unit
+        // and each lane only adds its column (no per-lane 64-bit multiplies).
         float w[kRowUnroll], m[kRowUnroll], v[kRowUnroll], g[kRowUnroll];
+        float *wp[kRowUnroll];
+        char *mp[kRowUnroll], *vp[kRowUnroll];
+        float ms[kRowUnroll], vs[kRowUnroll];
+#pragma unroll
+        for (int u = 0; u < kRowUnroll; ++u) {
+            const int64_t ru = (int64_t)(u32)__builtin_amdgcn_readfirstlane((int)id[u]);
+            float *gw_row = a.gw + ru * a.gw_ld;
+            float *aw_row = a.aw + ru * a.aw_ld;
+            wp[u] = isG ? gw_row + lane : aw_row + ca;
+            char *gm_row = static_cast<char *>(a.gm.p) + ru * a.gm.ld * msize<GST>();
+            char *gv_row = static_cast<char *>(a.gv.p) + ru * a.gv.ld * msize<GST>();
+            char *am_row = static_cast<char *>(a.am.p) + ru * a.am.ld * msize<AST>();
+            char *av_row = static_cast<char *>(a.av.p) + ru * a.av.ld * msize<AST>();
+            mp[u] = isG ? gm_row + lane * msize<GST>() : am_row + ca * msize<AST>();
+            vp[u] = isG ? gv_row + lane * msize<GST>() : av_row + ca * msize<AST>();
+            ms[u] = vs[u] = 0.0f;
+            if (GST == GS_FP8E4M3 || AST == GS_FP8E4M3) {
+                const int64_t b = ru / kFp8Block;
+                const float gms = GST == GS_FP8E4M3 ? a.gm.s[b] : 0.0f, gvs = GST == GS_FP8E4M3 ? a.gv.s[b] : 0.0f;
+                const float ams = AST == GS_FP8E4M3 ? a.am.s[b] : 0.0f, avs = AST == GS_FP8E4M3 ? a.av.s[b] : 0.0f;
+                ms[u] = isG ? gms : ams;
+                vs[u] = isG ? gvs : avs;
+            }
+        }
 #pragma unroll
         for (int u = 0; u < kRowUnroll; ++u) {
             w[u] = m[u] = v[u] = g[u] = 0.0f;
             const bool need = ok[u] && act && (MODE != kFlush || d[u] > 0);
             if (!need) continue;
-            const int64_t r = id[u];
-            if (MODE != kAdamMax) w[u] = isG ? a.gw[r * a.gw_ld + lane] : a.aw[r * a.aw_ld + ca];
+            if (MODE != kAdamMax) w[u] = *wp[u];
             // the gather loads the moments without waiting for last_step: most
             // visible rows are deferred, and the loads then overlap the last_step one
             if ((MODE == kAdam || MODE == kAdamMax || MODE == kGather || d[u] > 0) && grest) {
-                if (isG) {
-                    m[u] = mom_load<GST>(qm, r, col, false);
-                    if (!sgd) v[u] = mom_load<GST>(qv, r, col, true);
+                if (GST == AST) {
+                    m[u] = mload<GST>(mp[u], ms[u], false);
+                    if (!sgd) v[u] = mload<GST>(vp[u], vs[u], true);
+                } else if (isG) {
+                    m[u] = mload<GST>(mp[u], ms[u], false);
+                    if (!sgd) v[u] = mload<GST>(vp[u], vs[u], true);
                 } else {
-                    m[u] = mom_load<AST>(qm, r, col, false);
-                    if (!sgd) v[u] = mom_load<AST>(qv, r, col, true);
+                    m[u] = mload<AST>(mp[u], ms[u], false);
+                    if (!sgd) v[u] = mload<AST>(vp[u], vs[u], true);
                 }
             }
             if ((MODE == kAdam || MODE == kAdamMax) && base + u < nvis) {
-                if (a.g_geo) g[u] = isG ? a.g_geo[(base + u) * 10 + lane] : a.g_app[(base + u) * a.adim + ca];
-                else g[u] = isG ? a.gd_geo[r * 10 + lane] : a.gd_app[r * a.adim + ca];
+                if (a.g_geo) {
+                    const float *gg_row = a.g_geo + (base + u) * 10;
+                    const float *ga_row = a.g_app + (base + u) * a.adim;
+                    g[u] = *(isG ? gg_row + lane : ga_row + ca);
+                } else {
+                    const int64_t ru = (int64_t)(u32)__builtin_amdgcn_readfirstlane((int)id[u]);
+                    const float *gg_row = a.gd_geo + ru * 10;
+                    const float *ga_row = a.gd_app + ru * a.adim;
+                    g[u] = *(isG ? gg_row + lane : ga_row + ca);
+                }
             }
         }
 #pragma unroll
@@ -965,15 +1029,15 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
             const int dd = d[u];
             if (MODE == kAdamMax) {
                 const bool fp8 = isG ? GST == GS_FP8E4M3 : AST == GS_FP8E4M3;
-                const int64_t b = r / kFp8Block;
+                const int64_t b = (int64_t)(u32)__builtin_amdgcn_readfirstlane((int)r) / kFp8Block;
                 u32 xm = 0u, xv = 0u;
                 if (act && fp8) {
                     const float m1 = a.Mf[dd] * m[u] + a.omb1 * g[u];
                     const float v1 = a.Vf[dd] * v[u] + (a.omb2 * g[u]) * g[u];
                     const float r1 = sqrtf(v1);
                     const float am = fabsf(m1);
-                    if (am > 448.0f * qm.s[b]) xm = __float_as_uint(am);
-                    if (r1 > 448.0f * qv.s[b]) xv = __float_as_uint(r1);
+                    if (am > 448.0f * ms[u]) xm = __float_as_uint(am);
+                    if (r1 > 448.0f * vs[u]) xv = __float_as_uint(r1);
                 }
                 // maxima over the group's lanes (non-negative floats order as
                 // their bit patterns), then at most four atomics per row
@@ -1044,14 +1108,16 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
                     rm = (u32)(h & 0xffffull);
                     rv = (u32)((h >> 16) & 0xffffull);
                 }
-                if (isG) {
-                    a.gw[r * a.gw_ld + lane] = x;
-                    mom_store<GST>(qm, r, col, m1, rm, false);
-                    if (!sgd) mom_store<GST>(qv, r, col, v1, rv, true);
+                *wp[u] = x;
+                if (GST == AST) {
+                    mstore<GST>(mp[u], ms[u], m1, rm, false);
+                    if (!sgd) mstore<GST>(vp[u], vs[u], v1, rv, true);
+                } else if (isG) {
+                    mstore<GST>(mp[u], ms[u], m1, rm, false);
+                    if (!sgd) mstore<GST>(vp[u], vs[u], v1, rv, true);
                 } else {
-                    a.aw[r * a.aw_ld + ca] = x;
-                    mom_store<AST>(qm, r, col, m1, rm, false);
-                    if (!sgd) mom_store<AST>(qv, r, col, v1, rv, true);
+                    mstore<AST>(mp[u], ms[u], m1, rm, false);
+                    if (!sgd) mstore<AST>(vp[u], vs[u], v1, rv, true);
                 }
                 if (MODE == kAdam && !a.g_geo && base + u < nvis) {
                     if (isG) a.gd_geo[r * 10 + lane] = 0.0f;
