@@ -461,10 +461,11 @@ __device__ __forceinline__ int resolve_step(const StepK &s, int extra, const flo
 
 // ---------------------------------------------------------------------------
 // cull + ordered compaction, in three launches without inter-block waits:
-//   k_cull       one block per 512-row tile: cull every row, store the keep
-//                (and saturated) ballots and the tile's counts
-//   k_tile_scan  one block: exclusive prefix of the tile counts, totals
-//   k_tile_ids   one wavefront per tile: ids from ballots + tile prefix
+//   k_cull         one block per 512-row tile: cull every row, store the keep
+//                  (and saturated) ballots and the tile's counts
+//   k_tile_reduce  one wavefront per group of 64 tiles: the group's sums
+//   k_tile_ids     one block per group: tile prefixes from the earlier
+//                  groups' sums, then ids from ballots + tile prefix
 // No same-address atomics and no spin-waits: on this multi-die part a
 // device-scope atomic on one word serialises across all dies, which costs
 // more than the two extra launches.
@@ -517,13 +518,27 @@ __global__ __launch_bounds__(kCullBlock) void k_cull(CullArgs a)
     const int nf = rows * 10, nf4 = nf >> 2;
     const float *src = a.gw + row0 * 10;
     const float4 *src4 = reinterpret_cast<const float4 *>(src);
-    for (int j = tid; j < nf4; j += kCullBlock) sG4[j] = src4[j];
-    for (int j = nf4 * 4 + tid; j < nf; j += kCullBlock) sG[j] = src[j];
     int lastv[kCullIpt];
+    if (rows == kCullTile) {
+        // full tile: every load of the thread is issued before the first one
+        // is waited for (the tile is a few round trips of latency otherwise)
+        constexpr int P = kCullTile * 10 / 4 / kCullBlock;
+        static_assert(P * kCullBlock * 4 == kCullTile * 10, "tile is a whole number of float4 per thread");
+        float4 x[P];
 #pragma unroll
-    for (int k = 0; k < kCullIpt; ++k) {
-        const int r = k * kCullBlock + tid;
-        lastv[k] = r < rows ? a.last[row0 + r] : 0;
+        for (int k = 0; k < P; ++k) x[k] = src4[k * kCullBlock + tid];
+#pragma unroll
+        for (int k = 0; k < kCullIpt; ++k) lastv[k] = a.last[row0 + k * kCullBlock + tid];
+#pragma unroll
+        for (int k = 0; k < P; ++k) sG4[k * kCullBlock + tid] = x[k];
+    } else {
+        for (int j = tid; j < nf4; j += kCullBlock) sG4[j] = src4[j];
+        for (int j = nf4 * 4 + tid; j < nf; j += kCullBlock) sG[j] = src[j];
+#pragma unroll
+        for (int k = 0; k < kCullIpt; ++k) {
+            const int r = k * kCullBlock + tid;
+            lastv[k] = r < rows ? a.last[row0 + r] : 0;
+        }
     }
     __syncthreads();
 
@@ -900,6 +915,8 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
         qdec = cb[2 * a.aw_nW + t];
     }
 
+    // an empty model has no row 0 for the clamped loads below
+    if (a.n <= 0) return;
     int64_t nvis, total;
     if (MODE == kFlush) {
         nvis = a.n;
@@ -921,29 +938,53 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
     const u64 s_step = quant ? sm_at(a.sr_seed, (u64)t) : 0ull;
 
     for (int64_t base = wid * kRowUnroll; base < total; base += nw * kRowUnroll) {
+        // Three rounds of loads per iteration, each issued in full before it
+        // is waited for: the row ids, their last steps, then the rows' state
+        // and table entries.  Loads use clamped indices (position base and
+        // row 0 always exist here) so that none sits behind a branch.
         int64_t id[kRowUnroll];
         int d[kRowUnroll];
         bool ok[kRowUnroll];
+        if (MODE == kFlush) {
 #pragma unroll
-        for (int u = 0; u < kRowUnroll; ++u) {
-            const int64_t i = base + u;
-            int64_t r = -1;
-            if (i < total) {
-                if (MODE == kFlush) r = i;
-                else r = i < nvis ? (int64_t)a.ids[i] : (int64_t)a.sat_ids[i - nvis];
+            for (int u = 0; u < kRowUnroll; ++u) {
+                ok[u] = base + u < total;
+                id[u] = ok[u] ? base + u : 0;
             }
-            ok[u] = r >= 0 && r < a.n;
-            id[u] = ok[u] ? r : 0;
+        } else {
+            u32 rid[kRowUnroll];
+#pragma unroll
+            for (int u = 0; u < kRowUnroll; ++u) {
+                const int64_t i = base + u < total ? base + u : base;
+                const u32 *src = i < nvis ? a.ids : a.sat_ids;
+                rid[u] = src[i < nvis ? i : i - nvis];
+            }
+#pragma unroll
+            for (int u = 0; u < kRowUnroll; ++u) {
+                ok[u] = base + u < total && (int64_t)rid[u] < a.n;
+                id[u] = ok[u] ? (int64_t)rid[u] : 0;
+            }
         }
+        int lastv[kRowUnroll];
+#pragma unroll
+        for (int u = 0; u < kRowUnroll; ++u) lastv[u] = a.last[id[u]];
 #pragma unroll
         for (int u = 0; u < kRowUnroll; ++u) {
-            int dd = 0;
-            if (ok[u]) {
-                const int last = a.last[id[u]];
-                dd = (MODE == kFlush) ? t - last : t - 1 - last;
-                dd = dd < 0 ? 0 : (dd > dmax ? dmax : dd);
+            int dd = (MODE == kFlush) ? t - lastv[u] : t - 1 - lastv[u];
+            dd = dd < 0 ? 0 : (dd > dmax ? dmax : dd);
+            d[u] = ok[u] ? dd : 0;
+        }
+        // table entries of each row's gap, loaded with the state below
+        float Wd[kRowUnroll], Mfd[kRowUnroll], Vfd[kRowUnroll];
+#pragma unroll
+        for (int u = 0; u < kRowUnroll; ++u) {
+            Wd[u] = Wrow[d[u]];
+            Mfd[u] = Vfd[u] = 0.0f;
+            if (MODE == kAdam || MODE == kAdamMax || MODE == kFlush) {
+                const int j = MODE == kFlush ? (d[u] > 0 ? d[u] - 1 : 0) : d[u];
+                Mfd[u] = a.Mf[j];
+                Vfd[u] = a.Vf[j];
             }
-            d[u] = dd;
         }
         // per row: element addresses of this lane's column.  The row id is the
         // same on every lane, so the row bases are computed on the scalar unit
@@ -1013,9 +1054,9 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
             if (MODE == kGather) {
                 float x = w[u];
                 if (d[u] > 0 && grest) {
-                    if (sgd) x = x - (Wrow[d[u]] * lr) * m[u];
+                    if (sgd) x = x - (Wd[u] * lr) * m[u];
                     else if (adamw) x = restore_w(x, m[u], v[u], WlRow[d[u]], PRow[d[u]], lr, a.eps, a.rb);
-                    else x = restore1(x, m[u], v[u], Wrow[d[u]], lr, a.eps, a.rb);
+                    else x = restore1(x, m[u], v[u], Wd[u], lr, a.eps, a.rb);
                 }
                 if (act) {
                     if (isG) {
@@ -1032,8 +1073,8 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
                 const int64_t b = (int64_t)(u32)__builtin_amdgcn_readfirstlane((int)r) / kFp8Block;
                 u32 xm = 0u, xv = 0u;
                 if (act && fp8) {
-                    const float m1 = a.Mf[dd] * m[u] + a.omb1 * g[u];
-                    const float v1 = a.Vf[dd] * v[u] + (a.omb2 * g[u]) * g[u];
+                    const float m1 = Mfd[u] * m[u] + a.omb1 * g[u];
+                    const float v1 = Vfd[u] * v[u] + (a.omb2 * g[u]) * g[u];
                     const float r1 = sqrtf(v1);
                     const float am = fabsf(m1);
                     if (am > 448.0f * ms[u]) xm = __float_as_uint(am);
@@ -1068,36 +1109,36 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
                 if (MODE == kAdam && sgd) {
                     // SGD with momentum: catch up, buf = mu^(d+1) buf + g, w -= (lr s_t) buf
                     x = w[u];
-                    if (dd > 0) x = x - (Wrow[dd] * lr) * m[u];
-                    m1 = a.Mf[dd] * m[u] + g[u];
+                    if (dd > 0) x = x - (Wd[u] * lr) * m[u];
+                    m1 = Mfd[u] * m[u] + g[u];
                     v1 = 0.0f;
                     x = x - step * m1;
                 } else if (MODE == kAdam && adamw) {
                     // AdamW: decayed catch-up, Adam moments, w = q_t w - step
                     x = w[u];
                     if (dd > 0) x = restore_w(x, m[u], v[u], WlRow[dd], PRow[dd], lr, a.eps, a.rb);
-                    m1 = a.Mf[dd] * m[u] + a.omb1 * g[u];
-                    v1 = a.Vf[dd] * v[u] + (a.omb2 * g[u]) * g[u];
+                    m1 = Mfd[u] * m[u] + a.omb1 * g[u];
+                    v1 = Vfd[u] * v[u] + (a.omb2 * g[u]) * g[u];
                     const float xq = qdec * x;
                     x = xq - adam_step(m1, v1, step, bc, a.eps, a.rb);
                 } else if (MODE == kAdam) {
                     x = w[u];
-                    if (dd > 0) x = restore1(x, m[u], v[u], Wrow[dd], lr, a.eps, a.rb);
-                    m1 = a.Mf[dd] * m[u] + a.omb1 * g[u];
-                    v1 = a.Vf[dd] * v[u] + (a.omb2 * g[u]) * g[u];
+                    if (dd > 0) x = restore1(x, m[u], v[u], Wd[u], lr, a.eps, a.rb);
+                    m1 = Mfd[u] * m[u] + a.omb1 * g[u];
+                    v1 = Vfd[u] * v[u] + (a.omb2 * g[u]) * g[u];
                     x = x - adam_step(m1, v1, step, bc, a.eps, a.rb);
                 } else if (adamw) {
                     x = restore_w(w[u], m[u], v[u], WlRow[dd], PRow[dd], lr, a.eps, a.rb);
-                    m1 = a.Mf[dd - 1] * m[u];
-                    v1 = a.Vf[dd - 1] * v[u];
+                    m1 = Mfd[u] * m[u];
+                    v1 = Vfd[u] * v[u];
                 } else if (sgd) {
-                    x = w[u] - (Wrow[dd] * lr) * m[u];
-                    m1 = a.Mf[dd - 1] * m[u];
+                    x = w[u] - (Wd[u] * lr) * m[u];
+                    m1 = Mfd[u] * m[u];
                     v1 = 0.0f;
                 } else {
-                    x = restore1(w[u], m[u], v[u], Wrow[dd], lr, a.eps, a.rb);
-                    m1 = a.Mf[dd - 1] * m[u];
-                    v1 = a.Vf[dd - 1] * v[u];
+                    x = restore1(w[u], m[u], v[u], Wd[u], lr, a.eps, a.rb);
+                    m1 = Mfd[u] * m[u];
+                    v1 = Vfd[u] * v[u];
                 }
                 u32 rm = 0, rv = 0;
                 if (quant) {
