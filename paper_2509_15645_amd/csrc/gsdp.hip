@@ -937,55 +937,65 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
     const bool quant = (GST != GS_F32) || (AST != GS_F32);
     const u64 s_step = quant ? sm_at(a.sr_seed, (u64)t) : 0ull;
 
-    for (int64_t base = wid * kRowUnroll; base < total; base += nw * kRowUnroll) {
-        // Three rounds of loads per iteration, each issued in full before it
-        // is waited for: the row ids, their last steps, then the rows' state
-        // and table entries.  Loads use clamped indices (position base and
-        // row 0 always exist here) so that none sits behind a branch.
-        int64_t id[kRowUnroll];
-        int d[kRowUnroll];
-        bool ok[kRowUnroll];
-        if (MODE == kFlush) {
+    // Software pipeline over iterations of kRowUnroll rows: while one
+    // iteration's state is loaded, the next iteration's last steps and the
+    // ids of the one after are loaded too, so an iteration waits for one
+    // round of memory latency instead of three (ids -> last step -> state).
+    // The prefetched words are loaded at an index plus a zero that the
+    // compiler must treat as per-lane, so they stay in vector registers and
+    // are waited for where they are moved to scalar registers, at the end of
+    // the iteration, not right after the load.  Positions past the end give
+    // ok = false and row 0 / the last position (clamped indices: no load sits
+    // behind a branch).  Rows are unique within a launch, so reading a later
+    // row's last step before this iteration's stores is safe.
+    int vzero;
+    asm volatile("v_mov_b32 %0, 0" : "=v"(vzero));
+    const int64_t stride = nw * kRowUnroll;
+    auto fetch_raw = [&](int64_t b, u32 *rid) {
+        if (MODE == kFlush) return;
 #pragma unroll
-            for (int u = 0; u < kRowUnroll; ++u) {
-                ok[u] = base + u < total;
-                id[u] = ok[u] ? base + u : 0;
-            }
-        } else {
-            u32 rid[kRowUnroll];
-#pragma unroll
-            for (int u = 0; u < kRowUnroll; ++u) {
-                const int64_t i = base + u < total ? base + u : base;
-                const u32 *src = i < nvis ? a.ids : a.sat_ids;
-                rid[u] = src[i < nvis ? i : i - nvis];
-            }
-#pragma unroll
-            for (int u = 0; u < kRowUnroll; ++u) {
-                ok[u] = base + u < total && (int64_t)rid[u] < a.n;
-                id[u] = ok[u] ? (int64_t)rid[u] : 0;
-            }
+        for (int u = 0; u < kRowUnroll; ++u) {
+            const int64_t i = b + u < total ? b + u : total - 1;
+            const u32 *src = i < nvis ? a.ids : a.sat_ids;
+            rid[u] = src[(i < nvis ? i : i - nvis) + vzero];
         }
+    };
+    auto decode = [&](int64_t b, const u32 *rid, int64_t *idv, bool *okv) {
+#pragma unroll
+        for (int u = 0; u < kRowUnroll; ++u) {
+            const int64_t r = MODE == kFlush ? b + u : (int64_t)(u32)__builtin_amdgcn_readfirstlane((int)rid[u]);
+            okv[u] = b + u < total && r < a.n;
+            idv[u] = okv[u] ? r : 0;
+        }
+    };
+    auto gap = [&](int lastv, bool okv) {
+        const int l = __builtin_amdgcn_readfirstlane(lastv);
+        int dd = (MODE == kFlush) ? t - l : t - 1 - l;
+        dd = dd < 0 ? 0 : (dd > dmax ? dmax : dd);
+        return okv ? dd : 0;
+    };
+    int64_t id[kRowUnroll], idn[kRowUnroll];
+    bool ok[kRowUnroll], okn[kRowUnroll];
+    int d[kRowUnroll];
+    u32 rid[kRowUnroll], ridn[kRowUnroll];
+    int64_t base = wid * kRowUnroll;
+    if (base < total) {
+        fetch_raw(base, rid);
+        decode(base, rid, id, ok);
         int lastv[kRowUnroll];
 #pragma unroll
-        for (int u = 0; u < kRowUnroll; ++u) lastv[u] = a.last[id[u]];
+        for (int u = 0; u < kRowUnroll; ++u) lastv[u] = a.last[id[u] + vzero];
+        fetch_raw(base + stride, ridn);
 #pragma unroll
-        for (int u = 0; u < kRowUnroll; ++u) {
-            int dd = (MODE == kFlush) ? t - lastv[u] : t - 1 - lastv[u];
-            dd = dd < 0 ? 0 : (dd > dmax ? dmax : dd);
-            d[u] = ok[u] ? dd : 0;
-        }
-        // table entries of each row's gap, loaded with the state below
-        float Wd[kRowUnroll], Mfd[kRowUnroll], Vfd[kRowUnroll];
+        for (int u = 0; u < kRowUnroll; ++u) d[u] = gap(lastv[u], ok[u]);
+        decode(base + stride, ridn, idn, okn);
+    }
+    for (; base < total; base += stride) {
+        int lastn[kRowUnroll];
 #pragma unroll
-        for (int u = 0; u < kRowUnroll; ++u) {
-            Wd[u] = Wrow[d[u]];
-            Mfd[u] = Vfd[u] = 0.0f;
-            if (MODE == kAdam || MODE == kAdamMax || MODE == kFlush) {
-                const int j = MODE == kFlush ? (d[u] > 0 ? d[u] - 1 : 0) : d[u];
-                Mfd[u] = a.Mf[j];
-                Vfd[u] = a.Vf[j];
-            }
-        }
+        for (int u = 0; u < kRowUnroll; ++u) lastn[u] = a.last[idn[u] + vzero];
+        u32 ridnn[kRowUnroll];
+        fetch_raw(base + 2 * stride, ridnn);
         // per row: element addresses of this lane's column.  The row id is the
         // same on every lane, so the row bases are computed on the scalar unit
         // and each lane only adds its column (no per-lane 64-bit multiplies).
@@ -1020,8 +1030,8 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
             const bool need = ok[u] && act && (MODE != kFlush || d[u] > 0);
             if (!need) continue;
             if (MODE != kAdamMax) w[u] = *wp[u];
-            // the gather loads the moments without waiting for last_step: most
-            // visible rows are deferred, and the loads then overlap the last_step one
+            // the gather and Adam read the moments of every row (most visible
+            // rows are deferred); the flush only those it catches up
             if ((MODE == kAdam || MODE == kAdamMax || MODE == kGather || d[u] > 0) && grest) {
                 if (GST == AST) {
                     m[u] = mload<GST>(mp[u], ms[u], false);
@@ -1045,6 +1055,19 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
                     const float *ga_row = a.gd_app + ru * a.adim;
                     g[u] = *(isG ? gg_row + lane : ga_row + ca);
                 }
+            }
+        }
+        // table entries of each row's gap (issued after the state loads, which
+        // do not depend on them)
+        float Wd[kRowUnroll], Mfd[kRowUnroll], Vfd[kRowUnroll];
+#pragma unroll
+        for (int u = 0; u < kRowUnroll; ++u) {
+            Wd[u] = Wrow[d[u]];
+            Mfd[u] = Vfd[u] = 0.0f;
+            if (MODE == kAdam || MODE == kAdamMax || MODE == kFlush) {
+                const int j = MODE == kFlush ? (d[u] > 0 ? d[u] - 1 : 0) : d[u];
+                Mfd[u] = a.Mf[j];
+                Vfd[u] = a.Vf[j];
             }
         }
 #pragma unroll
@@ -1167,6 +1190,13 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
             }
             if (lane == 0) a.last[r] = t;
         }
+#pragma unroll
+        for (int u = 0; u < kRowUnroll; ++u) {
+            d[u] = gap(lastn[u], okn[u]);
+            id[u] = idn[u];
+            ok[u] = okn[u];
+        }
+        decode(base + 2 * stride, ridnn, idn, okn);
     }
 }
 
