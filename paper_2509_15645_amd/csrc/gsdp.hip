@@ -291,6 +291,26 @@ __device__ __forceinline__ void mom_store<GS_FP8E4M3>(const MomRef &q, int64_t r
     static_cast<uint8_t *>(q.p)[row * q.ld + col] = sc > 0.0f ? (uint8_t)e4m3_sr(y / sc, r16) : (uint8_t)0;
 }
 
+// Byte address of row r (stride s bytes) of the array at p, as a value the
+// compiler cannot see through: it then addresses the lanes' columns as this
+// scalar base plus a 32-bit lane offset, instead of re-associating the sum
+// into per-lane 64-bit arithmetic.
+typedef __attribute__((address_space(1))) char gchar;
+// A 32-bit lane offset, zero-extended where it is used: the hardware adds it
+// to a scalar base (no 64-bit lane address), but only if the extension is in
+// the same block as the access, so it is not left for the compiler to hoist.
+__device__ __forceinline__ u64 lane_off(u32 o)
+{
+    asm volatile("" : "+v"(o));
+    return (u64)o;
+}
+__device__ __forceinline__ gchar *srow(const void *p, u64 r, u32 s)
+{
+    gchar *q = (gchar *)p + r * (u64)s;
+    asm("" : "+s"(q));
+    return q;
+}
+
 // Loads and stores of one moment element at an element address (the row's
 // base computed once per row on the scalar unit, plus the lane's column);
 // same arithmetic as mom_load / mom_store.  s is the row's FP8 block scale.
@@ -846,7 +866,7 @@ __global__ __launch_bounds__(kIdsThreads) void k_tile_ids(IdsArgs a)
 // row kernels: gather / adam / flush
 // ---------------------------------------------------------------------------
 enum RowMode { kGather = 0, kAdam = 1, kFlush = 2, kAdamMax = 3 };
-constexpr int kRowUnroll = 4;
+constexpr int kRowUnroll = 2;
 
 struct RowArgs {
     float *gw, *aw;
@@ -857,9 +877,8 @@ struct RowArgs {
     float lr[64];                    // lane-indexed: 0..9 G, 10.. A
     float eps, omb1, omb2, rb;       // rb: clamp of the restore factor and of the Adam step
     u64 sr_seed;
-    int32_t geo_dense;
-    int32_t sgd;                     // SGD with momentum: buffer in m, no v
-    int32_t adamw, pad6;             // AdamW: decayed tables of the lane's rate class
+    int32_t geo_dense, pad6;
+    // the optimizer is a template parameter of the kernel; for AdamW:
     const float *aw_base;            // first class's tables
     int64_t aw_per, aw_nW;           // floats per class, floats of one W layout
     uint8_t cls[64];                 // rate class of each lane
@@ -884,7 +903,7 @@ struct RowArgs {
 //   kFlush    catch-up of deferred rows
 //   kAdamMax  first pass for FP8 moments: new moments only, recording per
 //             block the largest magnitude that no longer fits the block scale
-template <int MODE, int GST, int AST>
+template <int MODE, int GST, int AST, int OPT>
 __global__ __launch_bounds__(256) void k_rows(RowArgs a)
 {
     const int lane = threadIdx.x & 63;
@@ -896,10 +915,24 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
     // with dense geometry, G columns are updated elsewhere and never deferred
     const bool act = lane < 10 + a.adim && !(isG && a.geo_dense && MODE != kGather);
     const bool grest = !(isG && a.geo_dense);
-    const bool sgd = a.sgd != 0;
-    const bool adamw = a.adamw != 0;
+    constexpr bool sgd = OPT == GS_OPT_SGD_MOMENTUM;
+    constexpr bool adamw = OPT == GS_OPT_ADAMW;
     const int ca = lane - 10;
     const int col = isG ? lane : ca;
+    // Addressing: a row's base in each array is wave-uniform (scalar
+    // registers); each lane adds a 32-bit byte offset of its column that is
+    // fixed for the whole launch.  G and A lanes take their loads and stores
+    // in two exec-masked halves, so no per-lane 64-bit address arithmetic.
+    const u32 off4 = (u32)col * 4u;
+    const u32 offm = (u32)col * (u32)(isG ? msize<GST>() : msize<AST>());
+    // row strides in bytes (a row is at most a few KB)
+    const u32 sGW = (u32)a.gw_ld * 4u, sAW = (u32)a.aw_ld * 4u;
+    const u32 sGM = (u32)a.gm.ld * msize<GST>(), sGV = (u32)a.gv.ld * msize<GST>();
+    const u32 sAM = (u32)a.am.ld * msize<AST>(), sAV = (u32)a.av.ld * msize<AST>();
+    const u32 sAG = (u32)a.adim * 4u;
+    // element of row r (stride s bytes) at this lane's byte offset o; the row
+    // base goes through srow, so it stays a scalar base of the access
+    auto elem = [](const void *p, u64 r, u32 s, u32 o) { return (char *)(srow(p, r, s) + lane_off(o)); };
     const float lr = a.lr[lane];
     const float *Wrow;
     int dmax;
@@ -996,65 +1029,57 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
         for (int u = 0; u < kRowUnroll; ++u) lastn[u] = a.last[idn[u] + vzero];
         u32 ridnn[kRowUnroll];
         fetch_raw(base + 2 * stride, ridnn);
-        // per row: element addresses of this lane's column.  The row id is the
-        // same on every lane, so the row bases are computed on the scalar unit
-        // and each lane only adds its column (no per-lane 64-bit multiplies).
         float w[kRowUnroll], m[kRowUnroll], v[kRowUnroll], g[kRowUnroll];
-        float *wp[kRowUnroll];
-        char *mp[kRowUnroll], *vp[kRowUnroll];
         float ms[kRowUnroll], vs[kRowUnroll];
 #pragma unroll
         for (int u = 0; u < kRowUnroll; ++u) {
-            const int64_t ru = (int64_t)(u32)__builtin_amdgcn_readfirstlane((int)id[u]);
-            float *gw_row = a.gw + ru * a.gw_ld;
-            float *aw_row = a.aw + ru * a.aw_ld;
-            wp[u] = isG ? gw_row + lane : aw_row + ca;
-            char *gm_row = static_cast<char *>(a.gm.p) + ru * a.gm.ld * msize<GST>();
-            char *gv_row = static_cast<char *>(a.gv.p) + ru * a.gv.ld * msize<GST>();
-            char *am_row = static_cast<char *>(a.am.p) + ru * a.am.ld * msize<AST>();
-            char *av_row = static_cast<char *>(a.av.p) + ru * a.av.ld * msize<AST>();
-            mp[u] = isG ? gm_row + lane * msize<GST>() : am_row + ca * msize<AST>();
-            vp[u] = isG ? gv_row + lane * msize<GST>() : av_row + ca * msize<AST>();
-            ms[u] = vs[u] = 0.0f;
-            if (GST == GS_FP8E4M3 || AST == GS_FP8E4M3) {
-                const int64_t b = ru / kFp8Block;
-                const float gms = GST == GS_FP8E4M3 ? a.gm.s[b] : 0.0f, gvs = GST == GS_FP8E4M3 ? a.gv.s[b] : 0.0f;
-                const float ams = AST == GS_FP8E4M3 ? a.am.s[b] : 0.0f, avs = AST == GS_FP8E4M3 ? a.av.s[b] : 0.0f;
-                ms[u] = isG ? gms : ams;
-                vs[u] = isG ? gvs : avs;
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < kRowUnroll; ++u) {
             w[u] = m[u] = v[u] = g[u] = 0.0f;
+            ms[u] = vs[u] = 0.0f;
+            const u64 ru = (u64)id[u], cp = (u64)(base + u);
+            float gms = 0.0f, gvs = 0.0f, ams = 0.0f, avs = 0.0f;
+            if (GST == GS_FP8E4M3 || AST == GS_FP8E4M3) {
+                const u64 b = ru / kFp8Block;
+                if (GST == GS_FP8E4M3) {
+                    gms = a.gm.s[b];
+                    gvs = a.gv.s[b];
+                }
+                if (AST == GS_FP8E4M3) {
+                    ams = a.am.s[b];
+                    avs = a.av.s[b];
+                }
+            }
             const bool need = ok[u] && act && (MODE != kFlush || d[u] > 0);
-            if (!need) continue;
-            if (MODE != kAdamMax) w[u] = *wp[u];
             // the gather and Adam read the moments of every row (most visible
             // rows are deferred); the flush only those it catches up
-            if ((MODE == kAdam || MODE == kAdamMax || MODE == kGather || d[u] > 0) && grest) {
-                if (GST == AST) {
-                    m[u] = mload<GST>(mp[u], ms[u], false);
-                    if (!sgd) v[u] = mload<GST>(vp[u], vs[u], true);
-                } else if (isG) {
-                    m[u] = mload<GST>(mp[u], ms[u], false);
-                    if (!sgd) v[u] = mload<GST>(vp[u], vs[u], true);
-                } else {
-                    m[u] = mload<AST>(mp[u], ms[u], false);
-                    if (!sgd) v[u] = mload<AST>(vp[u], vs[u], true);
+            const bool ldm = MODE == kAdam || MODE == kAdamMax || MODE == kGather || d[u] > 0;
+            const bool ldg = (MODE == kAdam || MODE == kAdamMax) && base + u < nvis;
+            if (!need) continue;
+            if (isG) {
+                if (MODE != kAdamMax) w[u] = *reinterpret_cast<const float *>(elem(a.gw, ru, sGW, off4));
+                if (ldm && !a.geo_dense) {
+                    m[u] = mload<GST>(elem(a.gm.p, ru, sGM, offm), gms, false);
+                    if (!sgd) v[u] = mload<GST>(elem(a.gv.p, ru, sGV, offm), gvs, true);
                 }
-            }
-            if ((MODE == kAdam || MODE == kAdamMax) && base + u < nvis) {
-                if (a.g_geo) {
-                    const float *gg_row = a.g_geo + (base + u) * 10;
-                    const float *ga_row = a.g_app + (base + u) * a.adim;
-                    g[u] = *(isG ? gg_row + lane : ga_row + ca);
-                } else {
-                    const int64_t ru = (int64_t)(u32)__builtin_amdgcn_readfirstlane((int)id[u]);
-                    const float *gg_row = a.gd_geo + ru * 10;
-                    const float *ga_row = a.gd_app + ru * a.adim;
-                    g[u] = *(isG ? gg_row + lane : ga_row + ca);
+                if (ldg)
+                    g[u] = a.g_geo ? *reinterpret_cast<const float *>(elem(a.g_geo, cp, 40u, off4))
+                                   : *reinterpret_cast<const float *>(elem(a.gd_geo, ru, 40u, off4));
+                ms[u] = gms;
+                vs[u] = gvs;
+                // distinct markers end the two halves: otherwise the compiler
+                // merges their accesses into one with a per-lane address
+                asm volatile("; G columns");
+            } else {
+                if (MODE != kAdamMax) w[u] = *reinterpret_cast<const float *>(elem(a.aw, ru, sAW, off4));
+                if (ldm) {
+                    m[u] = mload<AST>(elem(a.am.p, ru, sAM, offm), ams, false);
+                    if (!sgd) v[u] = mload<AST>(elem(a.av.p, ru, sAV, offm), avs, true);
                 }
+                if (ldg)
+                    g[u] = a.g_app ? *reinterpret_cast<const float *>(elem(a.g_app, cp, sAG, off4))
+                                   : *reinterpret_cast<const float *>(elem(a.gd_app, ru, sAG, off4));
+                ms[u] = ams;
+                vs[u] = avs;
+                asm volatile("; A columns");
             }
         }
         // table entries of each row's gap (issued after the state loads, which
@@ -1082,10 +1107,11 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
                     else x = restore1(x, m[u], v[u], Wd[u], lr, a.eps, a.rb);
                 }
                 if (act) {
+                    const u64 cp = (u64)(base + u);
                     if (isG) {
-                        if (a.out_geo) a.out_geo[(base + u) * 10 + lane] = x;
+                        if (a.out_geo) *reinterpret_cast<float *>(elem(a.out_geo, cp, 40u, off4)) = x;
                     } else if (a.out_app) {
-                        a.out_app[(base + u) * a.adim + ca] = x;
+                        *reinterpret_cast<float *>(elem(a.out_app, cp, sAG, off4)) = x;
                     }
                 }
                 continue;
@@ -1172,20 +1198,20 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
                     rm = (u32)(h & 0xffffull);
                     rv = (u32)((h >> 16) & 0xffffull);
                 }
-                *wp[u] = x;
-                if (GST == AST) {
-                    mstore<GST>(mp[u], ms[u], m1, rm, false);
-                    if (!sgd) mstore<GST>(vp[u], vs[u], v1, rv, true);
-                } else if (isG) {
-                    mstore<GST>(mp[u], ms[u], m1, rm, false);
-                    if (!sgd) mstore<GST>(vp[u], vs[u], v1, rv, true);
+                const u64 ru = (u64)r;
+                const bool clr = MODE == kAdam && !a.g_geo && base + u < nvis;
+                if (isG) {
+                    *reinterpret_cast<float *>(elem(a.gw, ru, sGW, off4)) = x;
+                    mstore<GST>(elem(a.gm.p, ru, sGM, offm), ms[u], m1, rm, false);
+                    if (!sgd) mstore<GST>(elem(a.gv.p, ru, sGV, offm), vs[u], v1, rv, true);
+                    if (clr) *reinterpret_cast<float *>(elem(a.gd_geo, ru, 40u, off4)) = 0.0f;
+                    asm volatile("; G columns");
                 } else {
-                    mstore<AST>(mp[u], ms[u], m1, rm, false);
-                    if (!sgd) mstore<AST>(vp[u], vs[u], v1, rv, true);
-                }
-                if (MODE == kAdam && !a.g_geo && base + u < nvis) {
-                    if (isG) a.gd_geo[r * 10 + lane] = 0.0f;
-                    else a.gd_app[r * a.adim + ca] = 0.0f;
+                    *reinterpret_cast<float *>(elem(a.aw, ru, sAW, off4)) = x;
+                    mstore<AST>(elem(a.am.p, ru, sAM, offm), ms[u], m1, rm, false);
+                    if (!sgd) mstore<AST>(elem(a.av.p, ru, sAV, offm), vs[u], v1, rv, true);
+                    if (clr) *reinterpret_cast<float *>(elem(a.gd_app, ru, sAG, off4)) = 0.0f;
+                    asm volatile("; A columns");
                 }
             }
             if (lane == 0) a.last[r] = t;
@@ -1574,9 +1600,7 @@ void fill_rows(RowArgs &a, const gs_model *m)
     a.rb = restore_bound(m->beta1, m->beta2);
     a.sr_seed = m->sr_seed;
     a.geo_dense = m->geo_mode == 1;
-    a.sgd = m->optimizer == GS_OPT_SGD_MOMENTUM;
-    a.adamw = m->optimizer == GS_OPT_ADAMW;
-    if (a.adamw) {
+    if (m->optimizer == GS_OPT_ADAMW) {
         float rates[gsdp::kMaxDecayClasses];
         decay_classes(m, rates, a.cls);
         a.aw_base = static_cast<const float *>(m->lut) + gsdp::lut_layout(m->lut_max_steps, m->max_defer).total;
@@ -1622,22 +1646,33 @@ void pack_camera(const gs_model *model, const gs_camera *cam, CamK &k, BandK &b)
     b.jf2 = (float)((fx * fx * (1.0 + (double)limx * limx) + fy * fy * (1.0 + (double)limy * limy)) * (1.0 + 1e-4));
 }
 
-// Launch k_rows<MODE> for the moment storage types of the model's groups.
-template <int MODE, int G>
+// Launch k_rows<MODE> for the moment storage types and the optimizer of the
+// model's groups.
+template <int MODE, int G, int OPT>
 void launch_rows_a(int ast, int grid, hipStream_t st, const RowArgs &a)
 {
-    if (ast == GS_F32) hipLaunchKernelGGL((k_rows<MODE, G, GS_F32>), dim3(grid), dim3(256), 0, st, a);
-    else if (ast == GS_BF16) hipLaunchKernelGGL((k_rows<MODE, G, GS_BF16>), dim3(grid), dim3(256), 0, st, a);
-    else hipLaunchKernelGGL((k_rows<MODE, G, GS_FP8E4M3>), dim3(grid), dim3(256), 0, st, a);
+    if (ast == GS_F32) hipLaunchKernelGGL((k_rows<MODE, G, GS_F32, OPT>), dim3(grid), dim3(256), 0, st, a);
+    else if (ast == GS_BF16) hipLaunchKernelGGL((k_rows<MODE, G, GS_BF16, OPT>), dim3(grid), dim3(256), 0, st, a);
+    else if constexpr (OPT == GS_OPT_ADAM)
+        hipLaunchKernelGGL((k_rows<MODE, G, GS_FP8E4M3, OPT>), dim3(grid), dim3(256), 0, st, a);
+}
+
+// FP8 moments are Adam only (checked with the model)
+template <int MODE, int OPT>
+void launch_rows_o(const gs_model *m, int grid, hipStream_t st, const RowArgs &a)
+{
+    const int g = m->geo.state, p = m->app.state;
+    if (g == GS_F32) launch_rows_a<MODE, GS_F32, OPT>(p, grid, st, a);
+    else if (g == GS_BF16) launch_rows_a<MODE, GS_BF16, OPT>(p, grid, st, a);
+    else if constexpr (OPT == GS_OPT_ADAM) launch_rows_a<MODE, GS_FP8E4M3, OPT>(p, grid, st, a);
 }
 
 template <int MODE>
 void launch_rows(const gs_model *m, int grid, hipStream_t st, const RowArgs &a)
 {
-    const int g = m->geo.state, p = m->app.state;
-    if (g == GS_F32) launch_rows_a<MODE, GS_F32>(p, grid, st, a);
-    else if (g == GS_BF16) launch_rows_a<MODE, GS_BF16>(p, grid, st, a);
-    else launch_rows_a<MODE, GS_FP8E4M3>(p, grid, st, a);
+    if (m->optimizer == GS_OPT_SGD_MOMENTUM) launch_rows_o<MODE, GS_OPT_SGD_MOMENTUM>(m, grid, st, a);
+    else if (m->optimizer == GS_OPT_ADAMW) launch_rows_o<MODE, GS_OPT_ADAMW>(m, grid, st, a);
+    else launch_rows_o<MODE, GS_OPT_ADAM>(m, grid, st, a);
 }
 
 int row_grid(int64_t rows)
