@@ -314,11 +314,29 @@ __device__ __forceinline__ gchar *srow(const void *p, u64 r, u32 s)
 // Loads and stores of one moment element at an element address (the row's
 // base computed once per row on the scalar unit, plus the lane's column);
 // same arithmetic as mom_load / mom_store.  s is the row's FP8 block scale.
-template <int ST> __device__ __forceinline__ float mload(const char *e, float s, bool is_v)
+// A load is split into the raw storage word and its decoding, so that the
+// decoding of a row's moments does not wait for them before the next row's
+// loads are issued.
+// A register value the compiler takes as defined but that no instruction sets
+// (for values that are never used where no load wrote them).
+template <typename T> __device__ __forceinline__ T undef_v()
 {
-    if (ST == GS_F32) return *reinterpret_cast<const float *>(e);
-    if (ST == GS_BF16) return __uint_as_float((u32) * reinterpret_cast<const uint16_t *>(e) << 16);
-    const float x = e4m3_dec(*reinterpret_cast<const uint8_t *>(e)) * s;
+    u32 t;
+    asm volatile("" : "=v"(t));
+    return (T)t;
+}
+template <int ST> struct RawT { typedef u32 T; };
+template <> struct RawT<GS_BF16> { typedef uint16_t T; };
+template <> struct RawT<GS_FP8E4M3> { typedef uint8_t T; };
+template <int ST> __device__ __forceinline__ typename RawT<ST>::T mraw(const char *e)
+{
+    return *reinterpret_cast<const typename RawT<ST>::T *>(e);
+}
+template <int ST> __device__ __forceinline__ float mdec(u32 raw, float s, bool is_v)
+{
+    if (ST == GS_F32) return __uint_as_float(raw);
+    if (ST == GS_BF16) return __uint_as_float(raw << 16);
+    const float x = e4m3_dec(raw) * s;
     return is_v ? x * x : x;
 }
 template <int ST> __device__ __forceinline__ void mstore(char *e, float s, float x, u32 r16, bool is_v)
@@ -1029,12 +1047,24 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
         for (int u = 0; u < kRowUnroll; ++u) lastn[u] = a.last[idn[u] + vzero];
         u32 ridnn[kRowUnroll];
         fetch_raw(base + 2 * stride, ridnn);
-        float w[kRowUnroll], m[kRowUnroll], v[kRowUnroll], g[kRowUnroll];
+        // Raw words first (every row's loads in flight), selected and decoded
+        // afterwards.  The G and A halves load into separate registers that
+        // start undefined: a write of a default value to a register with a
+        // load of the other half still pending would have to wait for it.
+        u32 Gw[kRowUnroll], Gg[kRowUnroll], Aw[kRowUnroll], Ag[kRowUnroll];
+        typename RawT<GST>::T Gm[kRowUnroll], Gv[kRowUnroll];
+        typename RawT<AST>::T Am[kRowUnroll], Av[kRowUnroll];
         float ms[kRowUnroll], vs[kRowUnroll];
 #pragma unroll
         for (int u = 0; u < kRowUnroll; ++u) {
-            w[u] = m[u] = v[u] = g[u] = 0.0f;
-            ms[u] = vs[u] = 0.0f;
+            Gw[u] = undef_v<u32>();
+            Gg[u] = undef_v<u32>();
+            Aw[u] = undef_v<u32>();
+            Ag[u] = undef_v<u32>();
+            Gm[u] = undef_v<typename RawT<GST>::T>();
+            Gv[u] = undef_v<typename RawT<GST>::T>();
+            Am[u] = undef_v<typename RawT<AST>::T>();
+            Av[u] = undef_v<typename RawT<AST>::T>();
             const u64 ru = (u64)id[u], cp = (u64)(base + u);
             float gms = 0.0f, gvs = 0.0f, ams = 0.0f, avs = 0.0f;
             if (GST == GS_FP8E4M3 || AST == GS_FP8E4M3) {
@@ -1048,6 +1078,8 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
                     avs = a.av.s[b];
                 }
             }
+            ms[u] = isG ? gms : ams;
+            vs[u] = isG ? gvs : avs;
             const bool need = ok[u] && act && (MODE != kFlush || d[u] > 0);
             // the gather and Adam read the moments of every row (most visible
             // rows are deferred); the flush only those it catches up
@@ -1055,31 +1087,45 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
             const bool ldg = (MODE == kAdam || MODE == kAdamMax) && base + u < nvis;
             if (!need) continue;
             if (isG) {
-                if (MODE != kAdamMax) w[u] = *reinterpret_cast<const float *>(elem(a.gw, ru, sGW, off4));
+                if (MODE != kAdamMax) Gw[u] = *reinterpret_cast<const u32 *>(elem(a.gw, ru, sGW, off4));
                 if (ldm && !a.geo_dense) {
-                    m[u] = mload<GST>(elem(a.gm.p, ru, sGM, offm), gms, false);
-                    if (!sgd) v[u] = mload<GST>(elem(a.gv.p, ru, sGV, offm), gvs, true);
+                    Gm[u] = mraw<GST>(elem(a.gm.p, ru, sGM, offm));
+                    if (!sgd) Gv[u] = mraw<GST>(elem(a.gv.p, ru, sGV, offm));
                 }
                 if (ldg)
-                    g[u] = a.g_geo ? *reinterpret_cast<const float *>(elem(a.g_geo, cp, 40u, off4))
-                                   : *reinterpret_cast<const float *>(elem(a.gd_geo, ru, 40u, off4));
-                ms[u] = gms;
-                vs[u] = gvs;
+                    Gg[u] = a.g_geo ? *reinterpret_cast<const u32 *>(elem(a.g_geo, cp, 40u, off4))
+                                    : *reinterpret_cast<const u32 *>(elem(a.gd_geo, ru, 40u, off4));
                 // distinct markers end the two halves: otherwise the compiler
                 // merges their accesses into one with a per-lane address
                 asm volatile("; G columns");
             } else {
-                if (MODE != kAdamMax) w[u] = *reinterpret_cast<const float *>(elem(a.aw, ru, sAW, off4));
+                if (MODE != kAdamMax) Aw[u] = *reinterpret_cast<const u32 *>(elem(a.aw, ru, sAW, off4));
                 if (ldm) {
-                    m[u] = mload<AST>(elem(a.am.p, ru, sAM, offm), ams, false);
-                    if (!sgd) v[u] = mload<AST>(elem(a.av.p, ru, sAV, offm), avs, true);
+                    Am[u] = mraw<AST>(elem(a.am.p, ru, sAM, offm));
+                    if (!sgd) Av[u] = mraw<AST>(elem(a.av.p, ru, sAV, offm));
                 }
                 if (ldg)
-                    g[u] = a.g_app ? *reinterpret_cast<const float *>(elem(a.g_app, cp, sAG, off4))
-                                   : *reinterpret_cast<const float *>(elem(a.gd_app, ru, sAG, off4));
-                ms[u] = ams;
-                vs[u] = avs;
+                    Ag[u] = a.g_app ? *reinterpret_cast<const u32 *>(elem(a.g_app, cp, sAG, off4))
+                                    : *reinterpret_cast<const u32 *>(elem(a.gd_app, ru, sAG, off4));
                 asm volatile("; A columns");
+            }
+        }
+        // no instruction that waits for a load may be moved between the loads
+        __builtin_amdgcn_sched_barrier(0);
+        // values of lanes or rows that loaded nothing are never stored; a
+        // saturated row (no compact gradient) takes g = 0
+        float w[kRowUnroll], m[kRowUnroll], v[kRowUnroll], g[kRowUnroll];
+#pragma unroll
+        for (int u = 0; u < kRowUnroll; ++u) {
+            w[u] = __uint_as_float(isG ? Gw[u] : Aw[u]);
+            const bool ldg = (MODE == kAdam || MODE == kAdamMax) && base + u < nvis;
+            g[u] = ldg ? __uint_as_float(isG ? Gg[u] : Ag[u]) : 0.0f;
+            if (GST == AST) {
+                m[u] = mdec<GST>(isG ? (u32)Gm[u] : (u32)Am[u], ms[u], false);
+                v[u] = mdec<GST>(isG ? (u32)Gv[u] : (u32)Av[u], vs[u], true);
+            } else {
+                m[u] = isG ? mdec<GST>(Gm[u], ms[u], false) : mdec<AST>(Am[u], ms[u], false);
+                v[u] = isG ? mdec<GST>(Gv[u], vs[u], true) : mdec<AST>(Av[u], vs[u], true);
             }
         }
         // table entries of each row's gap (issued after the state loads, which
