@@ -306,7 +306,8 @@ __device__ __forceinline__ u64 lane_off(u32 o)
 }
 __device__ __forceinline__ gchar *srow(const void *p, u64 r, u32 s)
 {
-    gchar *q = (gchar *)p + r * (u64)s;
+    // rows and strides fit 32 bits: one 32 x 32 -> 64-bit product
+    gchar *q = (gchar *)p + (u64)(u32)r * (u64)s;
     asm("" : "+s"(q));
     return q;
 }
