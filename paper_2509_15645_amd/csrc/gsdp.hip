@@ -413,7 +413,7 @@ __device__ __forceinline__ RowPre classify_pre(const float *g, float wd, const B
     const float sig = __expf(fminf(smax, 80.0f)) * 1.001f;
     p.sig2 = sig * sig;
     // |q| > 2.002 dq + 1e-6, compared squared (the 0.1% margin covers the rounding)
-    const float qn2 = ((g[6] * g[6] + g[7] * g[7]) + g[8] * g[8]) + g[9] * g[9];
+    const float qn2 = fmaf(g[9], g[9], fmaf(g[8], g[8], fmaf(g[7], g[7], g[6] * g[6])));
     const float qmin = 2.002f * dq + 1e-6f;
     p.ok = (fin && smax < 80.0f) ? (qn2 > 1.001f * (qmin * qmin) ? 3 : 1) : 0;
     return p;
@@ -423,17 +423,21 @@ __device__ __forceinline__ int classify_cam(const float *g, const RowPre &p, con
 {
     if (!p.ok) return 2;
     const float dp = p.dp;
-    const float x = ((c.R[0] * g[0] + c.R[1] * g[1]) + c.R[2] * g[2]) + c.T[0];
-    const float y = ((c.R[3] * g[0] + c.R[4] * g[1]) + c.R[5] * g[2]) + c.T[1];
-    const float z = ((c.R[6] * g[0] + c.R[7] * g[1]) + c.R[8] * g[2]) + c.T[2];
+    // The bounds below are evaluated with fused multiply-adds: any evaluation
+    // order of these short sums differs from the exact path's by a few ulp of
+    // the terms' magnitude, far inside the 1e-6 relative slack.
+    const float x = fmaf(c.R[2], g[2], fmaf(c.R[1], g[1], fmaf(c.R[0], g[0], c.T[0])));
+    const float y = fmaf(c.R[5], g[2], fmaf(c.R[4], g[1], fmaf(c.R[3], g[0], c.T[1])));
+    const float z = fmaf(c.R[8], g[2], fmaf(c.R[7], g[1], fmaf(c.R[6], g[0], c.T[2])));
     // magnitude of the terms of each transform row, bounded by |R_i|_1 max|mu| + |T_i|
     // (rounds up by far less than the 1e-6 relative slack it feeds)
-    const float sx = b.rs0 * p.mu + fabsf(c.T[0]);
-    const float sy = b.rs1 * p.mu + fabsf(c.T[1]);
-    const float sz = b.rs2 * p.mu + fabsf(c.T[2]);
-    const float ex = b.rs0 * dp + 1e-6f * (sx + b.rs0 * dp) + 1e-6f;
-    const float ey = b.rs1 * dp + 1e-6f * (sy + b.rs1 * dp) + 1e-6f;
-    const float ez = b.rs2 * dp + 1e-6f * (sz + b.rs2 * dp) + 1e-6f;
+    const float sx = fmaf(b.rs0, p.mu, fabsf(c.T[0]));
+    const float sy = fmaf(b.rs1, p.mu, fabsf(c.T[1]));
+    const float sz = fmaf(b.rs2, p.mu, fabsf(c.T[2]));
+    const float dx = b.rs0 * dp, dy = b.rs1 * dp, dz = b.rs2 * dp;
+    const float ex = fmaf(1e-6f, sx + dx, dx) + 1e-6f;
+    const float ey = fmaf(1e-6f, sy + dy, dy) + 1e-6f;
+    const float ez = fmaf(1e-6f, sz + dz, dz) + 1e-6f;
     const float zlo = z - ez, zhi = z + ez;
     if (zhi <= c.zn || zlo >= c.zf) return 0;
     if (!(zlo > 0.0f)) return 2;
@@ -441,15 +445,15 @@ __device__ __forceinline__ int classify_cam(const float *g, const RowPre &p, con
     // bound below carries a margin of 1e-5 relative or more
     const float izl = __builtin_amdgcn_rcpf(zlo), izh = __builtin_amdgcn_rcpf(zhi);
     const float S = ((b.jf2 * izl) * izl) * p.sig2;
-    const float lam = 1.001f * S + 0.95f;
-    const float rup = 3.0f * __builtin_amdgcn_sqrtf(lam) * 1.001f + 1.0f;
+    const float lam = fmaf(1.001f, S, 0.95f);
+    const float rup = fmaf(3.003f, __builtin_amdgcn_sqrtf(lam), 1.0f);
     const float xlo = x - ex, xhi = x + ex, ylo = y - ey, yhi = y + ey;
     const float qxlo = fminf(xlo * izl, xlo * izh), qxhi = fmaxf(xhi * izl, xhi * izh);
     const float qylo = fminf(ylo * izl, ylo * izh), qyhi = fmaxf(yhi * izl, yhi * izh);
-    const float eu = 1e-5f * (c.fx * fmaxf(fabsf(qxlo), fabsf(qxhi)) + fabsf(c.cx)) + 1e-3f;
-    const float ev = 1e-5f * (c.fy * fmaxf(fabsf(qylo), fabsf(qyhi)) + fabsf(c.cy)) + 1e-3f;
-    const float ulo = c.fx * qxlo + c.cx - eu, uhi = c.fx * qxhi + c.cx + eu;
-    const float vlo = c.fy * qylo + c.cy - ev, vhi = c.fy * qyhi + c.cy + ev;
+    const float eu = fmaf(1e-5f, fmaf(c.fx, fmaxf(fabsf(qxlo), fabsf(qxhi)), fabsf(c.cx)), 1e-3f);
+    const float ev = fmaf(1e-5f, fmaf(c.fy, fmaxf(fabsf(qylo), fabsf(qyhi)), fabsf(c.cy)), 1e-3f);
+    const float ulo = fmaf(c.fx, qxlo, c.cx) - eu, uhi = fmaf(c.fx, qxhi, c.cx) + eu;
+    const float vlo = fmaf(c.fy, qylo, c.cy) - ev, vhi = fmaf(c.fy, qyhi, c.cy) + ev;
     if (uhi + rup <= 0.0f || ulo - rup >= c.W || vhi + rup <= 0.0f || vlo - rup >= c.H) return 0;
     if ((p.ok & 2) && zlo > c.zn && zhi < c.zf && ulo > -1.5f && uhi < c.W + 1.5f && vlo > -1.5f &&
         vhi < c.H + 1.5f && lam <= 1000.0f)
@@ -885,7 +889,7 @@ __global__ __launch_bounds__(kIdsThreads) void k_tile_ids(IdsArgs a)
 // row kernels: gather / adam / flush
 // ---------------------------------------------------------------------------
 enum RowMode { kGather = 0, kAdam = 1, kFlush = 2, kAdamMax = 3 };
-constexpr int kRowUnroll = 2;
+constexpr int kRowUnroll = 4;
 
 struct RowArgs {
     float *gw, *aw;
