@@ -419,9 +419,12 @@ __device__ __forceinline__ RowPre classify_pre(const float *g, float wd, const B
     return p;
 }
 
+// Decision of one row against one camera: 0 sure-out, 1 sure-in, 2 exact
+// path.  Evaluated without branches: every bound is computed and the tests are
+// combined in their order of precedence (a row of a wavefront rarely leaves
+// early together with all 63 others, so branching would only add mask work).
 __device__ __forceinline__ int classify_cam(const float *g, const RowPre &p, const CamK &c, const BandK &b)
 {
-    if (!p.ok) return 2;
     const float dp = p.dp;
     // The bounds below are evaluated with fused multiply-adds: any evaluation
     // order of these short sums differs from the exact path's by a few ulp of
@@ -439,10 +442,12 @@ __device__ __forceinline__ int classify_cam(const float *g, const RowPre &p, con
     const float ey = fmaf(1e-6f, sy + dy, dy) + 1e-6f;
     const float ez = fmaf(1e-6f, sz + dz, dz) + 1e-6f;
     const float zlo = z - ez, zhi = z + ez;
-    if (zhi <= c.zn || zlo >= c.zf) return 0;
-    if (!(zlo > 0.0f)) return 2;
+    // bitwise, not short-circuit, combinations: no branches
+    const bool out_z = (zhi <= c.zn) | (zlo >= c.zf);
+    const bool z_pos = zlo > 0.0f;
     // the hardware reciprocal and square root (about 1 ulp) suffice: every
-    // bound below carries a margin of 1e-5 relative or more
+    // bound below carries a margin of 1e-5 relative or more (their values
+    // are ignored when zlo <= 0)
     const float izl = __builtin_amdgcn_rcpf(zlo), izh = __builtin_amdgcn_rcpf(zhi);
     const float S = ((b.jf2 * izl) * izl) * p.sig2;
     const float lam = fmaf(1.001f, S, 0.95f);
@@ -454,11 +459,11 @@ __device__ __forceinline__ int classify_cam(const float *g, const RowPre &p, con
     const float ev = fmaf(1e-5f, fmaf(c.fy, fmaxf(fabsf(qylo), fabsf(qyhi)), fabsf(c.cy)), 1e-3f);
     const float ulo = fmaf(c.fx, qxlo, c.cx) - eu, uhi = fmaf(c.fx, qxhi, c.cx) + eu;
     const float vlo = fmaf(c.fy, qylo, c.cy) - ev, vhi = fmaf(c.fy, qyhi, c.cy) + ev;
-    if (uhi + rup <= 0.0f || ulo - rup >= c.W || vhi + rup <= 0.0f || vlo - rup >= c.H) return 0;
-    if ((p.ok & 2) && zlo > c.zn && zhi < c.zf && ulo > -1.5f && uhi < c.W + 1.5f && vlo > -1.5f &&
-        vhi < c.H + 1.5f && lam <= 1000.0f)
-        return 1;
-    return 2;
+    const bool out_uv = (uhi + rup <= 0.0f) | (ulo - rup >= c.W) | (vhi + rup <= 0.0f) | (vlo - rup >= c.H);
+    const bool in = ((p.ok & 2) != 0) & (zlo > c.zn) & (zhi < c.zf) & (ulo > -1.5f) & (uhi < c.W + 1.5f) &
+                    (vlo > -1.5f) & (vhi < c.H + 1.5f) & (lam <= 1000.0f);
+    const int cls = out_z ? 0 : (!z_pos ? 2 : (out_uv ? 0 : (in ? 1 : 2)));
+    return p.ok ? cls : 2;
 }
 
 __device__ __forceinline__ int classify(const float *g, float wd, const CamK &c, const BandK &b)
@@ -1848,8 +1853,8 @@ __global__ __launch_bounds__(BLOCK) void k_cull_multi(MultiArgs a)
             const RowPre pre = classify_pre(g, wd, cams[0].band);
             for (int c = 0; c < C; ++c) {
                 const int cls = a.mode == 1 ? classify_cam(g, pre, cams[c].cam, cams[c].band) : 2;
-                if (cls == 1) mk |= 1u << c;
-                else if (cls == 2) undecided |= 1u << c;
+                mk |= (u32)(cls == 1) << c;
+                undecided |= (u32)(cls == 2) << c;
             }
             if (undecided) {
                 if (d > 0) {
