@@ -2028,6 +2028,8 @@ struct GradSumArgs {
 };
 
 constexpr int kSumRows = 128;
+constexpr int kGsRows = 4;           // rows of a wavefront summed together
+constexpr int kGsSlots = 8;          // camera entries per row loaded up front
 
 __device__ __forceinline__ u32 lower_bound_u32(const u32 *a, u32 n, u32 key)
 {
@@ -2050,7 +2052,7 @@ __global__ __launch_bounds__(256) void k_grad_sum(GradSumArgs a)
     __shared__ u32 sIdx[kSumRows][kMaxCams];
     __shared__ u32 sMask[kSumRows];
     __shared__ u32 sLo[kMaxCams], sOff[kMaxCams + 1];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int D = 10 + a.adim;
     const int C = a.C;
     const u32 U = min(*a.union_count, a.cap_union);
@@ -2080,33 +2082,50 @@ __global__ __launch_bounds__(256) void k_grad_sum(GradSumArgs a)
         }
         __syncthreads();
         const u32 np = min((u32)kSumRows, U - p0);
-        for (u32 r = wave; r < np; r += 4) {
-            u32 m = sMask[r];
-            float acc = 0.0f;
-            // loads first (independent), then the adds in slot order
-            while (m) {
-                float v[8];
-                int cs[8];
-                int k = 0;
+        // kGsRows rows of this wavefront at a time: the first kGsSlots camera
+        // entries of each are loaded before the first add (rows rarely have
+        // more; those take the rest one by one).  Entry addresses are uniform:
+        // scalar bases plus the lane's column.  A missing slot adds +0, which
+        // leaves the sum's bits unchanged (a sum started at +0 is never -0).
+        for (u32 r0 = wave; r0 < np; r0 += 4 * kGsRows) {
+            float v[kGsRows][kGsSlots];
+            u32 rest[kGsRows];
 #pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    cs[q] = -1;
-                    v[q] = 0.0f;
+            for (int q = 0; q < kGsRows; ++q) {
+                const u32 r = r0 + 4 * q;
+                u32 m = r < np ? (u32)__builtin_amdgcn_readfirstlane((int)sMask[r]) : 0u;
+#pragma unroll
+                for (int sl = 0; sl < kGsSlots; ++sl) {
+                    // a zero the compiler cannot fold into the add below (it
+                    // would then move the add next to the load and wait there)
+                    asm volatile("v_mov_b32 %0, 0" : "=v"(v[q][sl]));
                     if (m) {
                         const int c = __builtin_ctz(m);
                         m &= m - 1u;
-                        cs[q] = c;
-                        if (lane < D) v[q] = a.g_cam[((size_t)c * a.cap_cam + sIdx[r][c]) * D + lane];
-                        ++k;
+                        const u32 idx = (u32)__builtin_amdgcn_readfirstlane((int)sIdx[r][c]);
+                        const float *src = a.g_cam + ((u64)c * a.cap_cam + idx) * (u64)D;
+                        if (lane < D) v[q][sl] = src[lane];
                     }
                 }
-#pragma unroll
-                for (int q = 0; q < 8; ++q)
-                    if (cs[q] >= 0) acc = acc + v[q];
-                (void)k;
+                rest[q] = m;
             }
-            if (lane < 10) a.out_geo[(size_t)(p0 + r) * 10 + lane] = acc;
-            else if (lane < D) a.out_app[(size_t)(p0 + r) * a.adim + (lane - 10)] = acc;
+#pragma unroll
+            for (int q = 0; q < kGsRows; ++q) {
+                const u32 r = r0 + 4 * q;
+                float acc = 0.0f;
+#pragma unroll
+                for (int sl = 0; sl < kGsSlots; ++sl) acc = acc + v[q][sl];
+                for (u32 m = rest[q]; m; m &= m - 1u) {
+                    const int c = __builtin_ctz(m);
+                    const u32 idx = (u32)__builtin_amdgcn_readfirstlane((int)sIdx[r][c]);
+                    const float *src = a.g_cam + ((u64)c * a.cap_cam + idx) * (u64)D;
+                    acc = acc + (lane < D ? src[lane] : 0.0f);
+                }
+                if (r < np) {
+                    if (lane < 10) a.out_geo[(size_t)(p0 + r) * 10 + lane] = acc;
+                    else if (lane < D) a.out_app[(size_t)(p0 + r) * a.adim + (lane - 10)] = acc;
+                }
+            }
         }
         __syncthreads();
     }
