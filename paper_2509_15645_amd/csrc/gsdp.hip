@@ -545,7 +545,11 @@ struct CullArgs {
     int64_t tiles;
 };
 
-__global__ __launch_bounds__(kCullBlock) void k_cull(CullArgs a)
+// Seven blocks per CU (the LDS tiles allow seven): the register budget this
+// implies (72) keeps one more tile's loads in flight per CU than the six the
+// kernel's natural register count allows; it spills a few registers of the
+// rarely taken exact path.
+__global__ __launch_bounds__(kCullBlock, 7) void k_cull(CullArgs a)
 {
     __shared__ float4 sG4[kCullTile * 10 / 4];
     __shared__ u32 sCntV[kCullIpt * 4], sCntS[kCullIpt * 4];
