@@ -941,8 +941,11 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
     const int lane = threadIdx.x & 63;
     // the wavefront index is uniform: keep it (and so every row index and row
     // id below) in scalar registers
-    const int64_t wid = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int64_t nw = (int64_t)gridDim.x * 4;
+    // Row counts, positions and ids fit 31 bits (checked with the model) and
+    // are kept 32-bit: comparisons and products of them then stay on the
+    // scalar unit.
+    const u32 wid = blockIdx.x * 4u + (u32)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const u32 nw = gridDim.x * 4u;
     const bool isG = lane < 10;
     // with dense geometry, G columns are updated elsewhere and never deferred
     const bool act = lane < 10 + a.adim && !(isG && a.geo_dense && MODE != kGather);
@@ -982,14 +985,15 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
 
     // an empty model has no row 0 for the clamped loads below
     if (a.n <= 0) return;
-    int64_t nvis, total;
+    const u32 n = (u32)a.n;
+    u32 nvis, total;
     if (MODE == kFlush) {
-        nvis = a.n;
-        total = a.n;
+        nvis = n;
+        total = n;
     } else {
         const u32 c = *a.count;
         nvis = c < a.cap ? c : a.cap;
-        total = nvis + (((MODE == kAdam || MODE == kAdamMax) && a.sat_count) ? (int64_t)*a.sat_count : 0);
+        total = nvis + (((MODE == kAdam || MODE == kAdamMax) && a.sat_count) ? *a.sat_count : 0u);
     }
     float ss = 0.0f, bc = 1.0f;
     if (MODE == kAdam) {
@@ -1015,22 +1019,22 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
     // row's last step before this iteration's stores is safe.
     int vzero;
     asm volatile("v_mov_b32 %0, 0" : "=v"(vzero));
-    const int64_t stride = nw * kRowUnroll;
-    auto fetch_raw = [&](int64_t b, u32 *rid) {
+    const u32 stride = nw * kRowUnroll;
+    auto fetch_raw = [&](u32 b, u32 *rid) {
         if (MODE == kFlush) return;
 #pragma unroll
         for (int u = 0; u < kRowUnroll; ++u) {
-            const int64_t i = b + u < total ? b + u : total - 1;
+            const u32 i = b + u < total ? b + u : total - 1u;
             const u32 *src = i < nvis ? a.ids : a.sat_ids;
             rid[u] = src[(i < nvis ? i : i - nvis) + vzero];
         }
     };
-    auto decode = [&](int64_t b, const u32 *rid, int64_t *idv, bool *okv) {
+    auto decode = [&](u32 b, const u32 *rid, u32 *idv, bool *okv) {
 #pragma unroll
         for (int u = 0; u < kRowUnroll; ++u) {
-            const int64_t r = MODE == kFlush ? b + u : (int64_t)(u32)__builtin_amdgcn_readfirstlane((int)rid[u]);
-            okv[u] = b + u < total && r < a.n;
-            idv[u] = okv[u] ? r : 0;
+            const u32 r = MODE == kFlush ? b + u : (u32)__builtin_amdgcn_readfirstlane((int)rid[u]);
+            okv[u] = b + u < total && r < n;
+            idv[u] = okv[u] ? r : 0u;
         }
     };
     auto gap = [&](int lastv, bool okv) {
@@ -1039,11 +1043,11 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
         dd = dd < 0 ? 0 : (dd > dmax ? dmax : dd);
         return okv ? dd : 0;
     };
-    int64_t id[kRowUnroll], idn[kRowUnroll];
+    u32 id[kRowUnroll], idn[kRowUnroll];
     bool ok[kRowUnroll], okn[kRowUnroll];
     int d[kRowUnroll];
     u32 rid[kRowUnroll], ridn[kRowUnroll];
-    int64_t base = wid * kRowUnroll;
+    u32 base = wid * kRowUnroll;
     if (base < total) {
         fetch_raw(base, rid);
         decode(base, rid, id, ok);
@@ -1158,7 +1162,7 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
 #pragma unroll
         for (int u = 0; u < kRowUnroll; ++u) {
             if (!ok[u]) continue;
-            const int64_t r = id[u];
+            const u32 r = id[u];
             if (MODE == kGather) {
                 float x = w[u];
                 if (d[u] > 0 && grest) {
@@ -1179,7 +1183,7 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
             const int dd = d[u];
             if (MODE == kAdamMax) {
                 const bool fp8 = isG ? GST == GS_FP8E4M3 : AST == GS_FP8E4M3;
-                const int64_t b = (int64_t)(u32)__builtin_amdgcn_readfirstlane((int)r) / kFp8Block;
+                const u32 b = r / kFp8Block;
                 u32 xm = 0u, xv = 0u;
                 if (act && fp8) {
                     const float m1 = Mfd[u] * m[u] + a.omb1 * g[u];
@@ -1253,8 +1257,7 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
                 if (quant) {
                     // the row's part of the random stream is the same on every
                     // lane: compute it once, on the scalar unit
-                    const u32 ru = (u32)__builtin_amdgcn_readfirstlane((int)r);
-                    const u64 h = sm_at(sm_at(s_step, (u64)ru), (u64)lane);
+                    const u64 h = sm_at(sm_at(s_step, (u64)r), (u64)lane);
                     rm = (u32)(h & 0xffffull);
                     rv = (u32)((h >> 16) & 0xffffull);
                 }
