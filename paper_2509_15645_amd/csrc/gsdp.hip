@@ -3,16 +3,20 @@
 //
 // Build flags matter for exactness: -ffp-contract=off (no FMA contraction),
 // correctly rounded FP32 division and square root, denormals preserved, and
-// packed-FP32 instructions disabled.  Every floating-point expression below is
-// written as the exact sequence of IEEE operations that defines the result.
+// packed-FP32 instructions disabled.  Every floating-point expression that
+// defines a result is written as the exact sequence of IEEE operations of its
+// definition; only the band classifier's conservative bounds (which decide
+// nothing near a boundary) use fused multiply-adds and the hardware
+// reciprocal and square root, inside stated margins.
 //
 // Kernels
-//   k_cull, k_tile_scan, k_tile_ids
+//   k_cull, k_tile_reduce, k_tile_ids
 //               one block per 512-row tile stages the geometry through LDS
 //               with 128-bit loads, restores deferred rows (band classifier
-//               first), culls and stores wave ballots and tile counts; one
-//               block scans the tile counts; one wavefront per tile writes the
-//               ids in order.  Deterministic, no global atomics, no waits.
+//               first), culls and stores wave ballots and tile counts; group
+//               sums of 64 tiles (skipped for small models); one block per
+//               group writes the tile prefixes and the ids in order.
+//               Deterministic, no global atomics, no waits.
 //   k_rows      one wavefront per Gaussian row, lanes 0..9 = G columns,
 //               lanes 10..10+dim = A columns; modes:
 //                 gather  restore current values into compact buffers
@@ -21,7 +25,8 @@
 //                 flush   catch up every deferred row
 //                 max     FP8 first pass (block maxima of new moments)
 //   k_fp8_rescale, k_dense_geo, k_scatter
-//   k_cull_multi, k_multi_scan, k_multi_ids, k_grad_sum   batched form
+//   k_cull_multi, k_multi_reduce, k_multi_offsets, k_multi_ids, k_grad_sum
+//               batched form
 //   k_dens_plan, k_dens_scan, k_dens_apply                densification
 //   k_synth     synthetic gradients (harness only)
 #include <hip/hip_runtime.h>
@@ -770,7 +775,11 @@ __device__ u64 scan_counts_u32(const u32 *cnt, u32 *off, int64_t tiles, u64 *sV,
 // earlier groups (read from L2), scans its 64 tiles in one wavefront, stores
 // the tile prefixes, and then writes the visible (and saturated) ids of its
 // tiles in ascending order from the ballots, one wavefront per tile; the last
-// group's block writes the totals.
+// group's block writes the totals.  Up to kDirectTiles tiles (8M rows) the
+// group sums are skipped: each k_tile_ids block sums the counts of all
+// earlier tiles itself (at most 16 loads per thread, from L2), which costs
+// less than the second launch.
+constexpr int64_t kDirectTiles = 16384;
 struct IdsArgs {
     const u64 *keep_bits, *sat_bits;
     const u64 *tile_vs;              // visible << 32 | saturated of each tile
@@ -779,7 +788,8 @@ struct IdsArgs {
     u64 *grp_vs, *grp_rest;          // per group of 64 tiles
     int64_t tiles, groups, n;
     u32 *ids;
-    u32 cap, pad;
+    u32 cap;
+    int32_t direct;                  // sum earlier tiles directly (no group sums)
     u32 *sat_ids;
     u32 *count;
     gsdp::WsHeader *hdr;
@@ -809,35 +819,65 @@ constexpr int kIdsThreads = 1024;    // 16 wavefronts per group of 64 tiles
 __global__ __launch_bounds__(kIdsThreads) void k_tile_ids(IdsArgs a)
 {
     constexpr int NW = kIdsThreads / 64;
-    __shared__ u64 sRed[2][NW];
+    __shared__ u64 sRed[3][NW];
     __shared__ u64 sPre[gsdp::kGroupTiles];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t g = blockIdx.x;
     const bool last = g == (a.groups > 0 ? a.groups - 1 : 0);
-    // sums of the earlier groups (and, for the last block, of all groups)
-    const int64_t upto = last ? a.groups : g;
-    u64 base = 0, rest = 0;
-    for (int64_t i = tid; i < upto; i += kIdsThreads) {
-        if (i < g) base += a.grp_vs[i];
-        if (last) rest += a.grp_rest[i];
+    u64 base = 0, rest = 0, own = 0;
+    if (a.direct) {
+        // sums of the earlier tiles (the last block: of all tiles, its own
+        // group's apart), eight independent loads per thread per round
+        const int64_t t0g = g * gsdp::kGroupTiles;
+        const int64_t upto = last ? a.tiles : t0g;
+        for (int64_t i0 = tid; i0 < upto; i0 += 8 * kIdsThreads) {
+            u64 c[8];
+            u32 r[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int64_t i = i0 + (int64_t)k * kIdsThreads;
+                const int64_t ic = i < upto ? i : 0;
+                c[k] = a.tile_vs[ic];
+                r[k] = last ? a.tile_rest[ic] : 0u;
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int64_t i = i0 + (int64_t)k * kIdsThreads;
+                if (i < upto) {
+                    if (i < t0g) base += c[k];
+                    else own += c[k];
+                    rest += r[k];
+                }
+            }
+        }
+    } else {
+        // sums of the earlier groups (and, for the last block, of all groups)
+        const int64_t upto = last ? a.groups : g;
+        for (int64_t i = tid; i < upto; i += kIdsThreads) {
+            if (i < g) base += a.grp_vs[i];
+            if (last) rest += a.grp_rest[i];
+        }
     }
     base = wave_sum_u64(base);
     rest = wave_sum_u64(rest);
+    own = wave_sum_u64(own);
     if (lane == 0) {
         sRed[0][wave] = base;
         sRed[1][wave] = rest;
+        sRed[2][wave] = own;
     }
     __syncthreads();
     base = 0;
-    u64 rsum = 0;
+    u64 rsum = 0, osum = 0;
 #pragma unroll
     for (int w = 0; w < NW; ++w) {
         base += sRed[0][w];
         rsum += sRed[1][w];
+        osum += sRed[2][w];
     }
     if (last) {
         // the last block also knows every total
-        const u64 tot = base + (g < a.groups ? a.grp_vs[g] : 0ull);
+        const u64 tot = base + (a.direct ? osum : (g < a.groups ? a.grp_vs[g] : 0ull));
         const u64 rtot = rsum;
         if (tid == 0) {
             const u32 vis = (u32)(tot >> 32);
@@ -2713,7 +2753,8 @@ int gs_cull(const gs_model *model, const gs_camera *cam, int64_t step, uint32_t 
                                       : nullptr;
     ia.count = count_dev;
     ia.hdr = reinterpret_cast<gsdp::WsHeader *>(wsb);
-    if (ia.groups > 0) {
+    ia.direct = ia.tiles <= kDirectTiles;
+    if (ia.groups > 0 && !ia.direct) {
         hipLaunchKernelGGL(k_tile_reduce, dim3((unsigned)((ia.groups + 3) / 4)), dim3(256), 0, st, ia);
         int rc2 = launched("gs_cull (group sums)");
         if (rc2) return rc2;

@@ -89,6 +89,25 @@ def test_cull_aerial_full_scale_step1(g):
     say(f"[cull aerial] visible fractions {fr}")
 
 
+def test_cull_aerial18m_group_prefix(g):
+    """18M Gaussians (the large aerial configuration): more than 16384 tiles,
+    so the compaction takes the per-group sums (the smaller models sum the
+    earlier tiles directly).  Ids bit-exact against the oracle's cull."""
+    w = gi.workload("aerial18m")
+    say(f"[cull aerial18m] n={w.n}")
+    sc = gi.make_scene(w.n, seed=1, box=w.scene_box)
+    model = model_for(g, sc.geo, np.zeros((w.n, 1), np.float32))
+    del sc.app
+    for t in (1, 2):
+        cam = w.camera_for_step(t)
+        ids, count, m = run_cull(g, model, cam, 1)
+        ref = orc.compact(orc.cull(sc.geo, cam))
+        assert m == ref.shape[0]
+        assert np.array_equal(u32(ids[:m]), ref)
+        say(f"[cull aerial18m] step {t}: M={m}")
+    assert model.ws_header()["error"] == 0
+
+
 def _boundary_scene(cam, n, rng):
     """Gaussians whose centres sit on and around the image border and the
     near/far planes, plus NaN, Inf and behind-camera rows."""
