@@ -814,37 +814,48 @@ __global__ __launch_bounds__(256) void k_tile_reduce(IdsArgs a)
     }
 }
 
-constexpr int kIdsThreads = 1024;    // 16 wavefronts per group of 64 tiles
+// one thread per 64-row ballot word of a group of 64 tiles
+constexpr int kIdsThreads = gsdp::kGroupTiles * gsdp::kWordsPerTile;
 
 __global__ __launch_bounds__(kIdsThreads) void k_tile_ids(IdsArgs a)
 {
     constexpr int NW = kIdsThreads / 64;
     __shared__ u64 sRed[3][NW];
-    __shared__ u64 sPre[gsdp::kGroupTiles];
+    __shared__ u64 sWave[NW];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t g = blockIdx.x;
     const bool last = g == (a.groups > 0 ? a.groups - 1 : 0);
+    // this thread's word (keep and saturated ballots of 64 rows), loaded
+    // first: it does not depend on the prefix, so its latency overlaps the
+    // sums below
+    const int64_t t0 = g * gsdp::kGroupTiles;
+    const int64_t word = t0 * gsdp::kWordsPerTile + tid;
+    const bool has = g < a.groups && word < a.tiles * gsdp::kWordsPerTile;
+    u64 kw = 0ull, sw = 0ull;
+    if (has) {
+        kw = a.keep_bits[word];
+        if (a.sat_ids) sw = a.sat_bits[word];
+    }
     u64 base = 0, rest = 0, own = 0;
     if (a.direct) {
         // sums of the earlier tiles (the last block: of all tiles, its own
-        // group's apart), eight independent loads per thread per round
-        const int64_t t0g = g * gsdp::kGroupTiles;
-        const int64_t upto = last ? a.tiles : t0g;
-        for (int64_t i0 = tid; i0 < upto; i0 += 8 * kIdsThreads) {
-            u64 c[8];
-            u32 r[8];
+        // group's apart), four independent loads per thread per round
+        const int64_t upto = last ? a.tiles : t0;
+        for (int64_t i0 = tid; i0 < upto; i0 += 4 * kIdsThreads) {
+            u64 c[4];
+            u32 r[4];
 #pragma unroll
-            for (int k = 0; k < 8; ++k) {
+            for (int k = 0; k < 4; ++k) {
                 const int64_t i = i0 + (int64_t)k * kIdsThreads;
                 const int64_t ic = i < upto ? i : 0;
                 c[k] = a.tile_vs[ic];
                 r[k] = last ? a.tile_rest[ic] : 0u;
             }
 #pragma unroll
-            for (int k = 0; k < 8; ++k) {
+            for (int k = 0; k < 4; ++k) {
                 const int64_t i = i0 + (int64_t)k * kIdsThreads;
                 if (i < upto) {
-                    if (i < t0g) base += c[k];
+                    if (i < t0) base += c[k];
                     else own += c[k];
                     rest += r[k];
                 }
@@ -861,77 +872,54 @@ __global__ __launch_bounds__(kIdsThreads) void k_tile_ids(IdsArgs a)
     base = wave_sum_u64(base);
     rest = wave_sum_u64(rest);
     own = wave_sum_u64(own);
+    // inclusive scan of the words' (visible << 32 | saturated) counts
+    const u64 c = ((u64)__popcll(kw) << 32) | (u64)__popcll(sw);
+    u64 inc = c;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const u64 y = (u64)__shfl_up((long long)inc, o);
+        if (lane >= o) inc += y;
+    }
     if (lane == 0) {
         sRed[0][wave] = base;
         sRed[1][wave] = rest;
         sRed[2][wave] = own;
     }
+    if (lane == 63) sWave[wave] = inc;
     __syncthreads();
     base = 0;
-    u64 rsum = 0, osum = 0;
+    u64 rsum = 0, osum = 0, before = 0, gsum = 0;
 #pragma unroll
     for (int w = 0; w < NW; ++w) {
         base += sRed[0][w];
         rsum += sRed[1][w];
         osum += sRed[2][w];
+        before += w < wave ? sWave[w] : 0ull;
+        gsum += sWave[w];
     }
-    if (last) {
+    if (last && tid == 0) {
         // the last block also knows every total
         const u64 tot = base + (a.direct ? osum : (g < a.groups ? a.grp_vs[g] : 0ull));
-        const u64 rtot = rsum;
-        if (tid == 0) {
-            const u32 vis = (u32)(tot >> 32);
-            *a.count = vis;
-            a.hdr->vis_total = vis;
-            a.hdr->sat_total = (u32)tot;
-            a.hdr->restored_last = (u32)rtot;
-            a.hdr->vis_accum += vis;
-            a.hdr->restored_accum += rtot;
-        }
+        const u32 vis = (u32)(tot >> 32);
+        *a.count = vis;
+        a.hdr->vis_total = vis;
+        a.hdr->sat_total = (u32)tot;
+        a.hdr->restored_last = (u32)rsum;
+        a.hdr->vis_accum += vis;
+        a.hdr->restored_accum += rsum;
     }
-    if (g >= a.groups) return;
-    const int64_t t0 = g * gsdp::kGroupTiles;
-    if (wave == 0) {
-        const int64_t tile = t0 + lane;
-        const u64 c = tile < a.tiles ? a.tile_vs[tile] : 0ull;
-        u64 inc = c;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const u64 y = (u64)__shfl_up((long long)inc, o);
-            if (lane >= o) inc += y;
-        }
-        const u64 pre = base + inc - c;
-        sPre[lane] = pre;
-        if (tile < a.tiles) a.tile_off[tile] = pre;
-    }
-    __syncthreads();
-    const u64 lt = (1ull << lane) - 1ull;
-    for (int j = wave; j < gsdp::kGroupTiles; j += NW) {
-        const int64_t tile = t0 + j;
-        if (tile >= a.tiles) break;
-        const int64_t row0 = tile * kCullTile;
-        const u64 o = sPre[j];
-        u64 kw = 0, sw = 0;
-        if (lane < gsdp::kWordsPerTile) {
-            kw = a.keep_bits[tile * gsdp::kWordsPerTile + lane];
-            if (a.sat_ids) sw = a.sat_bits[tile * gsdp::kWordsPerTile + lane];
-        }
-        u32 pv = (u32)(o >> 32), ps = (u32)o;
-#pragma unroll
-        for (int sl = 0; sl < gsdp::kWordsPerTile; ++sl) {
-            const u64 bv = (u64)__shfl((long long)kw, sl);
-            if ((bv >> lane) & 1ull) {
-                const u32 pos = pv + (u32)__popcll(bv & lt);
-                if (pos < a.cap) a.ids[pos] = (u32)(row0 + sl * 64 + lane);
-            }
-            pv += (u32)__popcll(bv);
-            if (a.sat_ids) {
-                const u64 bs = (u64)__shfl((long long)sw, sl);
-                if ((bs >> lane) & 1ull) a.sat_ids[ps + (u32)__popcll(bs & lt)] = (u32)(row0 + sl * 64 + lane);
-                ps += (u32)__popcll(bs);
-            }
-        }
-    }
+    (void)gsum;
+    if (!has) return;
+    // exclusive prefix of this word: earlier groups + earlier words of the group
+    const u64 pre = base + before + inc - c;
+    if ((tid % gsdp::kWordsPerTile) == 0) a.tile_off[t0 + tid / gsdp::kWordsPerTile] = pre;
+    // ids of the word's set bits, ascending
+    const int64_t row0 = word * 64;
+    u32 pv = (u32)(pre >> 32), ps = (u32)pre;
+    for (u64 m = kw; m; m &= m - 1ull, ++pv)
+        if (pv < a.cap) a.ids[pv] = (u32)(row0 + __builtin_ctzll(m));
+    if (a.sat_ids)
+        for (u64 m = sw; m; m &= m - 1ull, ++ps) a.sat_ids[ps] = (u32)(row0 + __builtin_ctzll(m));
 }
 
 // ---------------------------------------------------------------------------
