@@ -954,6 +954,10 @@ struct RowArgs {
     u32 *fp8max[4];                  // per-block max |m'|, sqrt(v') that outgrew the scale (G m, G v, A m, A v)
     u32 *fp8list, *fp8count;         // tasks (moment * nb + block) that outgrew their scale, and their count
     int64_t nb;
+    // fused layout: A w, A m, A v, G m and G v of a row lie in one byte row of
+    // fz_s bytes starting at aw (offsets in bytes); the kernel then addresses
+    // them all from one row base
+    u32 fz_s, fz_ogm, fz_ogv, fz_oam, fz_oav, pad8;
 };
 
 // One wavefront per Gaussian row: lane c < 10 owns G column c, lane 10+c owns
@@ -963,7 +967,9 @@ struct RowArgs {
 //   kFlush    catch-up of deferred rows
 //   kAdamMax  first pass for FP8 moments: new moments only, recording per
 //             block the largest magnitude that no longer fits the block scale
-template <int MODE, int GST, int AST, int OPT>
+// FZ: the fused layout with one storage type for both groups; the moments of
+// every lane are then one access from the row's single base.
+template <int MODE, int GST, int AST, int OPT, bool FZ>
 __global__ __launch_bounds__(256) void k_rows(RowArgs a)
 {
     const int lane = threadIdx.x & 63;
@@ -993,6 +999,9 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
     const u32 sGM = (u32)a.gm.ld * msize<GST>(), sGV = (u32)a.gv.ld * msize<GST>();
     const u32 sAM = (u32)a.am.ld * msize<AST>(), sAV = (u32)a.av.ld * msize<AST>();
     const u32 sAG = (u32)a.adim * 4u;
+    static_assert(!FZ || GST == AST, "the fused single access needs one storage type");
+    const u32 fzm = isG ? a.fz_ogm + (u32)lane * msize<GST>() : a.fz_oam + (u32)ca * msize<AST>();
+    const u32 fzv = isG ? a.fz_ogv + (u32)lane * msize<GST>() : a.fz_oav + (u32)ca * msize<AST>();
     // element of row r (stride s bytes) at this lane's byte offset o; the row
     // base goes through srow, so it stays a scalar base of the access
     auto elem = [](const void *p, u64 r, u32 s, u32 o) { return (char *)(srow(p, r, s) + lane_off(o)); };
@@ -1132,9 +1141,13 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
             const bool ldm = MODE == kAdam || MODE == kAdamMax || MODE == kGather || d[u] > 0;
             const bool ldg = (MODE == kAdam || MODE == kAdamMax) && base + u < nvis;
             if (!need) continue;
+            if (FZ && ldm && grest) {
+                Gm[u] = mraw<GST>(elem(a.aw, ru, a.fz_s, fzm));
+                if (!sgd) Gv[u] = mraw<GST>(elem(a.aw, ru, a.fz_s, fzv));
+            }
             if (isG) {
                 if (MODE != kAdamMax) Gw[u] = *reinterpret_cast<const u32 *>(elem(a.gw, ru, sGW, off4));
-                if (ldm && !a.geo_dense) {
+                if (!FZ && ldm && !a.geo_dense) {
                     Gm[u] = mraw<GST>(elem(a.gm.p, ru, sGM, offm));
                     if (!sgd) Gv[u] = mraw<GST>(elem(a.gv.p, ru, sGV, offm));
                 }
@@ -1146,7 +1159,7 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
                 asm volatile("; G columns");
             } else {
                 if (MODE != kAdamMax) Aw[u] = *reinterpret_cast<const u32 *>(elem(a.aw, ru, sAW, off4));
-                if (ldm) {
+                if (!FZ && ldm) {
                     Am[u] = mraw<AST>(elem(a.am.p, ru, sAM, offm));
                     if (!sgd) Av[u] = mraw<AST>(elem(a.av.p, ru, sAV, offm));
                 }
@@ -1166,7 +1179,10 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
             w[u] = __uint_as_float(isG ? Gw[u] : Aw[u]);
             const bool ldg = (MODE == kAdam || MODE == kAdamMax) && base + u < nvis;
             g[u] = ldg ? __uint_as_float(isG ? Gg[u] : Ag[u]) : 0.0f;
-            if (GST == AST) {
+            if (FZ) {
+                m[u] = mdec<GST>((u32)Gm[u], ms[u], false);
+                v[u] = mdec<GST>((u32)Gv[u], vs[u], true);
+            } else if (GST == AST) {
                 m[u] = mdec<GST>(isG ? (u32)Gm[u] : (u32)Am[u], ms[u], false);
                 v[u] = mdec<GST>(isG ? (u32)Gv[u] : (u32)Av[u], vs[u], true);
             } else {
@@ -1291,16 +1307,24 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
                 }
                 const u64 ru = (u64)r;
                 const bool clr = MODE == kAdam && !a.g_geo && base + u < nvis;
+                if (FZ) {
+                    mstore<GST>(elem(a.aw, ru, a.fz_s, fzm), ms[u], m1, rm, false);
+                    if (!sgd) mstore<GST>(elem(a.aw, ru, a.fz_s, fzv), vs[u], v1, rv, true);
+                }
                 if (isG) {
                     *reinterpret_cast<float *>(elem(a.gw, ru, sGW, off4)) = x;
-                    mstore<GST>(elem(a.gm.p, ru, sGM, offm), ms[u], m1, rm, false);
-                    if (!sgd) mstore<GST>(elem(a.gv.p, ru, sGV, offm), vs[u], v1, rv, true);
+                    if (!FZ) {
+                        mstore<GST>(elem(a.gm.p, ru, sGM, offm), ms[u], m1, rm, false);
+                        if (!sgd) mstore<GST>(elem(a.gv.p, ru, sGV, offm), vs[u], v1, rv, true);
+                    }
                     if (clr) *reinterpret_cast<float *>(elem(a.gd_geo, ru, 40u, off4)) = 0.0f;
                     asm volatile("; G columns");
                 } else {
                     *reinterpret_cast<float *>(elem(a.aw, ru, sAW, off4)) = x;
-                    mstore<AST>(elem(a.am.p, ru, sAM, offm), ms[u], m1, rm, false);
-                    if (!sgd) mstore<AST>(elem(a.av.p, ru, sAV, offm), vs[u], v1, rv, true);
+                    if (!FZ) {
+                        mstore<AST>(elem(a.am.p, ru, sAM, offm), ms[u], m1, rm, false);
+                        if (!sgd) mstore<AST>(elem(a.av.p, ru, sAV, offm), vs[u], v1, rv, true);
+                    }
                     if (clr) *reinterpret_cast<float *>(elem(a.gd_app, ru, sAG, off4)) = 0.0f;
                     asm volatile("; A columns");
                 }
@@ -1671,9 +1695,38 @@ int decay_classes(const gs_model *m, float *rates, uint8_t *cls)
     return nc;
 }
 
+// Byte offset of p inside the row of the fused block at base, or -1.
+int64_t fused_off(const void *base, const void *p, int64_t row_bytes)
+{
+    const int64_t o = static_cast<const char *>(p) - static_cast<const char *>(base);
+    return (o >= 0 && o < row_bytes) ? o : -1;
+}
+
+// The fused layout: every state array of a row but G w in one byte row.
+bool fused_layout(const gs_model *m, u32 *S, u32 *ogm, u32 *ogv, u32 *oam, u32 *oav)
+{
+    const int64_t gs = (int64_t)mom_bytes(m->geo.state), as = (int64_t)mom_bytes(m->app.state);
+    const int64_t row = (int64_t)m->app.w_ld * 4;
+    if (row <= 0 || row > 0xffff) return false;
+    if ((int64_t)m->app.m_ld * as != row || (int64_t)m->app.v_ld * as != row || (int64_t)m->geo.m_ld * gs != row ||
+        (int64_t)m->geo.v_ld * gs != row)
+        return false;
+    const int64_t o[4] = {fused_off(m->app.w, m->geo.m, row), fused_off(m->app.w, m->geo.v, row),
+                          fused_off(m->app.w, m->app.m, row), fused_off(m->app.w, m->app.v, row)};
+    for (int k = 0; k < 4; ++k)
+        if (o[k] < 0) return false;
+    *S = (u32)row;
+    *ogm = (u32)o[0];
+    *ogv = (u32)o[1];
+    *oam = (u32)o[2];
+    *oav = (u32)o[3];
+    return true;
+}
+
 void fill_rows(RowArgs &a, const gs_model *m)
 {
     memset(&a, 0, sizeof a);
+    if (!fused_layout(m, &a.fz_s, &a.fz_ogm, &a.fz_ogv, &a.fz_oam, &a.fz_oav)) a.fz_s = 0;
     a.gw = m->geo.w;
     a.gw_ld = m->geo.w_ld;
     a.gm = {m->geo.m, m->geo.m_scale, m->geo.m_ld};
@@ -1742,10 +1795,19 @@ void pack_camera(const gs_model *model, const gs_camera *cam, CamK &k, BandK &b)
 template <int MODE, int G, int OPT>
 void launch_rows_a(int ast, int grid, hipStream_t st, const RowArgs &a)
 {
-    if (ast == GS_F32) hipLaunchKernelGGL((k_rows<MODE, G, GS_F32, OPT>), dim3(grid), dim3(256), 0, st, a);
-    else if (ast == GS_BF16) hipLaunchKernelGGL((k_rows<MODE, G, GS_BF16, OPT>), dim3(grid), dim3(256), 0, st, a);
-    else if constexpr (OPT == GS_OPT_ADAM)
-        hipLaunchKernelGGL((k_rows<MODE, G, GS_FP8E4M3, OPT>), dim3(grid), dim3(256), 0, st, a);
+    // the fused single access when both groups share the storage type
+    const bool fz = a.fz_s != 0 && ast == G;
+    if (ast == GS_F32) {
+        if (fz && G == GS_F32) hipLaunchKernelGGL((k_rows<MODE, G, GS_F32, OPT, G == GS_F32>), dim3(grid), dim3(256), 0, st, a);
+        else hipLaunchKernelGGL((k_rows<MODE, G, GS_F32, OPT, false>), dim3(grid), dim3(256), 0, st, a);
+    } else if (ast == GS_BF16) {
+        if (fz && G == GS_BF16) hipLaunchKernelGGL((k_rows<MODE, G, GS_BF16, OPT, G == GS_BF16>), dim3(grid), dim3(256), 0, st, a);
+        else hipLaunchKernelGGL((k_rows<MODE, G, GS_BF16, OPT, false>), dim3(grid), dim3(256), 0, st, a);
+    } else if constexpr (OPT == GS_OPT_ADAM) {
+        if (fz && G == GS_FP8E4M3)
+            hipLaunchKernelGGL((k_rows<MODE, G, GS_FP8E4M3, OPT, G == GS_FP8E4M3>), dim3(grid), dim3(256), 0, st, a);
+        else hipLaunchKernelGGL((k_rows<MODE, G, GS_FP8E4M3, OPT, false>), dim3(grid), dim3(256), 0, st, a);
+    }
 }
 
 // FP8 moments are Adam only (checked with the model)
