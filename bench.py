@@ -202,7 +202,7 @@ def run_batched(args):
     lg, la = gi.lr_columns()
     total_steps = args.warmup + args.steps + 2
     model = gsdp.Model(geo, app, lg, la, max_steps=total_steps + 4, cull_mode=args.cull_mode,
-                       app_layout=args.layout, geo_state=args.geo_state or "f32", app_state="bf16", sr_seed=9)
+                       app_layout=args.layout, geo_state=args.geo_state or "bf16", app_state="bf16", sr_seed=9)
     del geo, app
     cap_cam = max(1, int(N * 0.08))      # one camera slot over all scenes sees up to ~5% of the rows
     multi = gsdp.Multi(model, row0, sets, cap_union=N, cap_cam=cap_cam)
@@ -258,7 +258,7 @@ def run_batched(args):
         raise RuntimeError("camera list capacity exceeded")
     k_ms = np.array([[e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2]), e[2].elapsed_time(e[3])] for e in ev]).mean(0)
     U, CC = U_tot / 3.0, cc_tot / 3.0
-    sg = 4 if (args.geo_state or "f32") == "f32" else 2
+    sg = 4 if (args.geo_state or "bf16") == "f32" else 2
     cull_bytes = 44.0 * N + 4.0 * U + 4.0 * CC
     sum_bytes = CC * (D * 4 + 4) + U * D * 4
     adam_bytes = U * (12 + 10 * (12 + 4 * sg) + 49 * (12 + 4 * 2))
@@ -272,6 +272,7 @@ def run_batched(args):
         "vs_baseline": None, "dtype": "f32 math, bf16 moments", "data": "synthetic",
         "config": {"workload": "batched16", "scenes": len(sizes), "scene_sizes": sizes, "n_gaussians": n_real,
                    "rows_padded": N, "cameras_per_scene": C, "union_per_step": U, "camera_entries_per_step": CC,
+                   "geo_state": args.geo_state or "bf16", "app_state": "bf16",
                    "autotune_ms": times, "variant": int(multi.c.variant), "hipgraph": True},
         "kernels_ms": {k: float(v[0]) for k, v in kern.items()},
         "kernels_gbs": {k: v[1] / (v[0] * 1e-3) / 1e9 for k, v in kern.items()},
@@ -438,6 +439,19 @@ def main():
         adam_bytes += n * 10 * (8 + 4 * sg) + n / 8.0 + M * 40
     kernels = {"cull": (cull_ms, cull_bytes), "gather": (gather_ms, gather_bytes), "adam": (adam_ms, adam_bytes)}
     dom = max(kernels, key=lambda k: kernels[k][0])
+    # achievable read bandwidth of the cull's main stream: a plain streaming
+    # read of the [n][10] geometry array, timed the same way
+    flat = model.geo_w.view(-1)
+    flat = flat[: (flat.numel() // 4) * 4]
+    sink = torch.zeros(1, dtype=torch.float32, device="cuda")
+    pe = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    gsdp.gs_stream_read_probe(flat, sink)
+    pe[0].record()
+    for _ in range(5):
+        gsdp.gs_stream_read_probe(flat, sink)
+    pe[1].record()
+    torch.cuda.synchronize()
+    probe_gbs = flat.numel() * 4 * 5 / (pe[0].elapsed_time(pe[1]) * 1e-3) / 1e9
     dms, dbytes = kernels[dom]
     achieved = dbytes / (dms * 1e-3) / 1e9
     out = {
@@ -460,6 +474,8 @@ def main():
         "roofline": {"kernel": dom, "launches": KERNEL_SYMBOLS[dom], "bound": "hbm", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(dom, config_key(args, w.name)), "algorithmic_bytes": dbytes},
+        "stream_probe": {"what": "streaming read of the [n][10] geometry array", "bytes": flat.numel() * 4,
+                         "gbs": probe_gbs, "frac_of_peak": probe_gbs / HBM_PEAK_GBS},
         "setup_s": setup_s,
     }
     if not args.no_cpu_baseline:

@@ -370,6 +370,15 @@ int gs_synth_grad(uint64_t seed, int64_t step, const uint32_t *ids, const uint32
                   uint32_t capacity, int32_t dim, int32_t col0, double sigma, float *out,
                   void *stream);
 
+/* Measurement helper (not part of the method): one streaming read of `bytes`
+ * bytes at device address `buf` (16-byte aligned, bytes a multiple of 16),
+ * eight independent 16-byte loads per thread in flight, eight blocks per CU.
+ * Timing it on the [n][10] geometry array gives the read bandwidth the cull's
+ * main stream can reach on this part.  *sink (device float) is written only
+ * when the data sum to a value finite data never sum to, so nothing is
+ * stored in practice.  Returns GS_EINVAL on a null or misaligned argument. */
+int gs_stream_read_probe(const void *buf, size_t bytes, float *sink, void *stream);
+
 /* Number of compute units of the current device (0 when none). */
 int gs_device_cu_count(void);
 

@@ -2230,6 +2230,28 @@ __global__ __launch_bounds__(256) void k_grad_sum(GradSumArgs a)
 
 __global__ void k_step_advance(int32_t *t) { *t += 1; }
 
+// Read-bandwidth probe: eight independent 16-byte loads per thread in flight,
+// grid-stride; the sum is stored only if it equals a value finite data never
+// sum to, so the loads cannot be dropped and nothing is written in practice.
+__global__ __launch_bounds__(256) void k_stream_read(const float4 *p, int64_t n4, float *sink)
+{
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    float acc = 0.0f;
+    for (; i + 7 * stride < n4; i += 8 * stride) {
+        float4 x[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) x[k] = p[i + k * stride];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) acc += (x[k].x + x[k].y) + (x[k].z + x[k].w);
+    }
+    for (; i < n4; i += stride) {
+        const float4 x = p[i];
+        acc += (x.x + x.y) + (x.z + x.w);
+    }
+    if (acc == -1.5e-38f) *sink = acc;
+}
+
 // ---------------------------------------------------------------------------
 // densification: plan (codes + tile counts) -> scan -> apply (row copies)
 // ---------------------------------------------------------------------------
@@ -3291,6 +3313,17 @@ int gs_plan_image_split(const gs_model *model, const gs_camera *cam, int64_t ste
     desc->cap_union = cap_u;
     desc->cap_cam = cap_c;
     return rc;
+}
+
+int gs_stream_read_probe(const void *buf, size_t bytes, float *sink, void *stream)
+{
+    if (!buf || !sink || (bytes % 16) != 0 || !aligned(buf, 16)) return GS_EINVAL;
+    if (bytes == 0) return GS_OK;
+    const int cu = cu_count();
+    const int grid = (cu > 0 ? cu : 256) * 8;
+    hipLaunchKernelGGL(k_stream_read, dim3(grid), dim3(256), 0, (hipStream_t)stream,
+                       static_cast<const float4 *>(buf), (int64_t)(bytes / 16), sink);
+    return launched("gs_stream_read_probe");
 }
 
 int gs_step_advance(int32_t *step_dev, void *stream)

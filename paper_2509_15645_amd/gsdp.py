@@ -25,7 +25,7 @@ GS_OPT_ADAM, GS_OPT_ADAMW, GS_OPT_SGD_MOMENTUM = 0, 1, 2
 SYMBOLS = ("gs_lut_bytes", "gs_lut_build", "gs_lut_build_host", "gs_lut_build_schedule",
            "gs_lut_build_schedule_host", "gs_workspace_bytes", "gs_cull",
            "gs_gather", "gs_scatter_grad", "gs_adam_step_deferred", "gs_adam_flush", "gs_synth_grad",
-           "gs_device_cu_count", "gs_status_string", "gs_last_hip_error", "gs_step_advance",
+           "gs_device_cu_count", "gs_status_string", "gs_last_hip_error", "gs_step_advance", "gs_stream_read_probe",
            "gs_camera_pack_bytes", "gs_camera_pack", "gs_multi_workspace_bytes", "gs_cull_multi",
            "gs_cull_multi_autotune", "gs_grad_sum_multi", "gs_plan_image_split", "gs_lut_build_sgd_momentum",
            "gs_lut_build_sgd_momentum_host", "gs_lut_bytes_adamw", "gs_lut_build_adamw", "gs_lut_build_adamw_host",
@@ -91,6 +91,7 @@ def _load():
         "gs_synth_grad": (C.c_int, [u64, i64, vp, vp, u32, i32, i32, f64, vp, vp]),
         "gs_device_cu_count": (C.c_int, []),
         "gs_step_advance": (C.c_int, [vp, vp]),
+        "gs_stream_read_probe": (C.c_int, [vp, C.c_size_t, vp, vp]),
         "gs_camera_pack_bytes": (C.c_int, [P(sz)]),
         "gs_camera_pack": (C.c_int, [P(GsModel), vp, i32, vp]),
         "gs_multi_workspace_bytes": (C.c_int, [P(GsModel), P(sz)]),
@@ -443,6 +444,12 @@ def densify(model: Model, step: int, grad_accum, grad_denom, max_radii2d=None, *
 
 def gs_step_advance(step_dev, stream=None):
     _check(lib.gs_step_advance(_ptr(step_dev), _stream(stream)), "gs_step_advance")
+
+
+def gs_stream_read_probe(buf, sink, stream=None):
+    """One streaming read of the whole tensor `buf` (measurement helper)."""
+    _check(lib.gs_stream_read_probe(_ptr(buf), buf.numel() * buf.element_size(), _ptr(sink), _stream(stream)),
+           "gs_stream_read_probe")
 
 
 def gs_device_cu_count() -> int:

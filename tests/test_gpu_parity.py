@@ -458,3 +458,18 @@ def test_aerial_full_scale_path_vs_oracle(g):
         o3.step(t, valid, *gi.step_grads(0, t, valid))
         say(f"[aerial] step {t}: M={m} ({m / n:.4f}) restored={model.ws_header()['restored_last']}")
     _compare_state(model, o3, f"aerial after {steps} steps")
+
+
+def test_stream_read_probe(g):
+    """The measurement helper reads and stores nothing; misaligned or ragged
+    sizes are rejected."""
+    buf = torch.ones(1 << 20, dtype=torch.float32, device="cuda")
+    sink = torch.full((1,), 7.0, dtype=torch.float32, device="cuda")
+    g.gs_stream_read_probe(buf, sink)
+    g.gs_stream_read_probe(buf[: 4 * 1001], sink)
+    torch.cuda.synchronize()
+    assert float(sink.item()) == 7.0
+    with pytest.raises(RuntimeError):
+        g.gs_stream_read_probe(buf[:6], sink)
+    with pytest.raises(RuntimeError):
+        g.gs_stream_read_probe(buf[1:5], sink)
