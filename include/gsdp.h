@@ -266,6 +266,11 @@ typedef struct gs_multi {
     uint32_t *cam_pos, *cam_count;
     uint32_t cap_union, cap_cam;
     uint32_t *scene_start;       /* device [n_scenes][1 + cams_per_scene] */
+    uint32_t *chunk_start;       /* optional device [ceil(cap_union / 128) + 1][cams_per_scene]:
+                                    for union position 128 k and camera slot c, the index in list c
+                                    of its first entry at a position >= 128 k (written by
+                                    gs_cull_multi, read by gs_grad_sum_multi instead of binary
+                                    searches); NULL: gs_grad_sum_multi searches */
 } gs_multi;
 
 /* Size of one camera record, and packing of `count` cameras for `model`

@@ -1860,6 +1860,9 @@ struct CamPack {                     // one camera with its band-classifier cons
     float pad[5];
 };
 
+// union positions per chunk of the batched gradient sum
+constexpr int kSumRows = 128;
+
 struct MultiArgs {
     const float *gw;
     MomRef gm, gv;
@@ -1876,6 +1879,7 @@ struct MultiArgs {
     u32 *cam_pos, *cam_count;
     u32 cap_union, cap_cam;
     u32 *scene_start;                // [S][1+C]
+    u32 *chunk_start;                // [ceil(cap_union / kSumRows) + 1][C] or null
     u32 *cnt;                        // [kNCnt][stride] per-tile counts (union, camera slots)
     u32 *off;                        // [kNCnt][stride] exclusive prefixes over tiles
     u32 *grp;                        // [kNCnt][gstride] sums over groups of 64 tiles
@@ -2101,13 +2105,15 @@ __global__ __launch_bounds__(BLOCK) void k_multi_ids(MultiArgs a)
         const u64 ub = __ballot(mk != 0u);
         const u32 p = sOff[slab][0] + lane_rank(ub);
         if (mk && p < a.cap_union) a.union_ids[p] = (u32)(row0 + k * BLOCK + tid);
+        // the union row at the start of a chunk of kSumRows positions records,
+        // per camera slot, the index of that slot's first entry at or after it
+        const bool chunk0 = a.chunk_start && mk && p < a.cap_union && (p % kSumRows) == 0;
         for (int c = 0; c < C; ++c) {
             const bool on = (mk >> c) & 1u;
             const u64 cb = __ballot(on);
-            if (on) {
-                const u32 q = sOff[slab][1 + c] + lane_rank(cb);
-                if (q < a.cap_cam) a.cam_pos[(size_t)c * a.cap_cam + q] = p;
-            }
+            const u32 q = sOff[slab][1 + c] + lane_rank(cb);
+            if (on && q < a.cap_cam) a.cam_pos[(size_t)c * a.cap_cam + q] = p;
+            if (chunk0) a.chunk_start[(size_t)(p / kSumRows) * C + c] = q;
         }
     }
 }
@@ -2115,16 +2121,17 @@ __global__ __launch_bounds__(BLOCK) void k_multi_ids(MultiArgs a)
 // Deterministic sum of the per-camera gradients onto the union rows:
 // out[p] = (...((0 + g_c0) + g_c1) + ...) over the camera slots that see p, in
 // slot order.  cam_pos[c] is ascending, so the entries of a block of union
-// positions form one contiguous range per camera (binary search).
+// positions form one contiguous range per camera: read from the chunk starts
+// the compaction records, or found by binary search without them.
 struct GradSumArgs {
     const u32 *cam_pos, *cam_count, *union_count;
+    const u32 *chunk_start;          // per chunk and camera slot: first entry index, or null
     u32 cap_cam, cap_union;
     int32_t C, adim;
     const float *g_cam;              // [C][cap_cam][10 + adim]
     float *out_geo, *out_app;        // [cap_union][10], [cap_union][adim]
 };
 
-constexpr int kSumRows = 128;
 constexpr int kGsRows = 4;           // rows of a wavefront summed together
 constexpr int kGsSlots = 8;          // camera entries per row loaded up front
 
@@ -2140,7 +2147,7 @@ __device__ __forceinline__ u32 lower_bound_u32(const u32 *a, u32 n, u32 key)
 }
 
 // One block per chunk of kSumRows union positions: (1) each camera's entries in
-// the chunk are found by binary search and scattered into an LDS table
+// the chunk (its range of the list) are scattered into an LDS table
 // (row, camera) -> entry, with the row's camera bits; (2) one wavefront per
 // row (lane = column) adds the row's camera gradients in slot order,
 // (((0 + g_c0) + g_c1) + ...), so the sum is deterministic.
@@ -2157,10 +2164,19 @@ __global__ __launch_bounds__(256) void k_grad_sum(GradSumArgs a)
         for (int e = tid; e < kSumRows; e += 256) sMask[e] = 0u;
         if (tid < C) {
             const u32 nc = min(a.cam_count[tid], a.cap_cam);
-            const u32 *lst = a.cam_pos + (size_t)tid * a.cap_cam;
-            const u32 lo = lower_bound_u32(lst, nc, p0);
+            u32 lo, hi;
+            if (a.chunk_start) {
+                // the chunk's range of each list, recorded by the compaction
+                const size_t q = p0 / kSumRows;
+                lo = min(a.chunk_start[q * C + tid], nc);
+                hi = p0 + kSumRows < U ? min(a.chunk_start[(q + 1) * C + tid], nc) : nc;
+            } else {
+                const u32 *lst = a.cam_pos + (size_t)tid * a.cap_cam;
+                lo = lower_bound_u32(lst, nc, p0);
+                hi = lower_bound_u32(lst, nc, p0 + kSumRows);
+            }
             sLo[tid] = lo;
-            sOff[tid + 1] = lower_bound_u32(lst, nc, p0 + kSumRows) - lo;
+            sOff[tid + 1] = hi - lo;
         }
         __syncthreads();
         if (tid == 0) {
@@ -2545,6 +2561,7 @@ int multi_args(const gs_model *model, const gs_multi *d, int64_t step, void *ws,
     a.cap_union = d->cap_union;
     a.cap_cam = d->cap_cam;
     a.scene_start = d->scene_start;
+    a.chunk_start = d->chunk_start;
     char *wsb = static_cast<char *>(ws);
     const int64_t max_tiles = (model->n + kMultiMinTile - 1) / kMultiMinTile;
     a.cnt = reinterpret_cast<u32 *>(wsb + gsdp::kWsHeader);
@@ -3221,6 +3238,7 @@ int gs_grad_sum_multi(const gs_multi *desc, int32_t adim, const float *g_cam, fl
     a.cam_pos = desc->cam_pos;
     a.cam_count = desc->cam_count;
     a.union_count = desc->union_count;
+    a.chunk_start = desc->chunk_start;
     a.cap_cam = desc->cap_cam;
     a.cap_union = desc->cap_union;
     a.C = desc->cams_per_scene;

@@ -58,7 +58,7 @@ class GsMulti(C.Structure):
                 ("variant", C.c_int32), ("scene_row0", C.c_void_p), ("cams", C.c_void_p),
                 ("union_ids", C.c_void_p), ("union_count", C.c_void_p), ("cam_pos", C.c_void_p),
                 ("cam_count", C.c_void_p), ("cap_union", C.c_uint32), ("cap_cam", C.c_uint32),
-                ("scene_start", C.c_void_p)]
+                ("scene_start", C.c_void_p), ("chunk_start", C.c_void_p)]
 
 
 def _load():
@@ -497,6 +497,8 @@ class Multi:
         self.cam_pos = torch.zeros((Cc, max(self.cap_cam, 1)), dtype=torch.int32, device=dev)
         self.cam_count = torch.zeros(Cc, dtype=torch.int32, device=dev)
         self.scene_start = torch.zeros((S, 1 + Cc), dtype=torch.int32, device=dev)
+        self.chunk_start = torch.zeros(((max(self.cap_union, 1) + 127) // 128 + 1, Cc), dtype=torch.int32,
+                                       device=dev)
         wb = C.c_size_t()
         _check(lib.gs_multi_workspace_bytes(C.byref(model.c), C.byref(wb)), "gs_multi_workspace_bytes")
         self.ws = torch.zeros((wb.value + 3) // 4, dtype=torch.int32, device=dev)
@@ -510,6 +512,7 @@ class Multi:
         d.cam_count = self.cam_count.data_ptr()
         d.cap_union, d.cap_cam = self.cap_union, self.cap_cam
         d.scene_start = self.scene_start.data_ptr()
+        d.chunk_start = self.chunk_start.data_ptr()
         self.c = d
 
     def lists(self):

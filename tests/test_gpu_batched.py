@@ -84,6 +84,23 @@ def test_batched_scenes_cameras_vs_oracle(g):
         torch.cuda.synchronize()
         assert np.array_equal(bits(out_g[:u].cpu().numpy()), bits(gsum[:, :10])), t
         assert np.array_equal(bits(out_a[:u].cpu().numpy()), bits(gsum[:, 10:])), t
+        # the recorded chunk starts: per 128 union positions and camera slot,
+        # the first list entry at or after the chunk (a sorted-search of the lists)
+        nch = (u + 127) // 128
+        cs = multi.chunk_start[:nch].cpu().numpy().view(np.uint32)
+        pos = multi.cam_pos.cpu().numpy().view(np.uint32)
+        for c in range(C):
+            want = np.searchsorted(pos[c, :cc[c]], 128 * np.arange(nch), side="left")
+            assert np.array_equal(cs[:, c], want), (t, c)
+        # and the same sum with binary searches instead of the chunk starts
+        saved = multi.c.chunk_start
+        multi.c.chunk_start = None
+        og2, oa2 = torch.zeros_like(out_g), torch.zeros_like(out_a)
+        g.gs_grad_sum_multi(multi, 49, g_cam_dev, og2, oa2)
+        multi.c.chunk_start = saved
+        torch.cuda.synchronize()
+        assert torch.equal(og2[:u].view(torch.int32), out_g[:u].view(torch.int32)), t
+        assert torch.equal(oa2[:u].view(torch.int32), out_a[:u].view(torch.int32)), t
         g.gs_adam_step_deferred(model, t, multi.union_ids, multi.union_count, out_g, out_a,
                                 capacity=multi.cap_union)
         o4.step(t, ref[0], gsum[:, :10], gsum[:, 10:])
