@@ -36,7 +36,6 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
-#include <type_traits>
 #include <vector>
 
 #include "gsdp.h"
@@ -778,7 +777,7 @@ __device__ u64 scan_counts_u32(const u32 *cnt, u32 *off, int64_t tiles, u64 *sV,
 // tiles in ascending order from the ballots, one wavefront per tile; the last
 // group's block writes the totals.  Up to kDirectTiles tiles (8M rows) the
 // group sums are skipped: each k_tile_ids block sums the counts of all
-// earlier tiles itself (at most 16 loads per thread, from L2), which costs
+// earlier tiles itself (at most 32 loads per thread, from L2), which costs
 // less than the second launch.
 constexpr int64_t kDirectTiles = 16384;
 struct IdsArgs {
@@ -818,6 +817,7 @@ __global__ __launch_bounds__(256) void k_tile_reduce(IdsArgs a)
 // one thread per 64-row ballot word of a group of 64 tiles
 constexpr int kIdsThreads = gsdp::kGroupTiles * gsdp::kWordsPerTile;
 
+template <bool DIRECT>
 __global__ __launch_bounds__(kIdsThreads) void k_tile_ids(IdsArgs a)
 {
     constexpr int NW = kIdsThreads / 64;
@@ -838,22 +838,23 @@ __global__ __launch_bounds__(kIdsThreads) void k_tile_ids(IdsArgs a)
         if (a.sat_ids) sw = a.sat_bits[word];
     }
     u64 base = 0, rest = 0, own = 0;
-    if (a.direct) {
+    if (DIRECT) {
         // sums of the earlier tiles (the last block: of all tiles, its own
-        // group's apart), four independent loads per thread per round
+        // group's apart), sixteen independent loads per thread per round (one
+        // round up to 8192 tiles)
         const int64_t upto = last ? a.tiles : t0;
-        for (int64_t i0 = tid; i0 < upto; i0 += 4 * kIdsThreads) {
-            u64 c[4];
-            u32 r[4];
+        for (int64_t i0 = tid; i0 < upto; i0 += 16 * kIdsThreads) {
+            u64 c[16];
+            u32 r[16];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
+            for (int k = 0; k < 16; ++k) {
                 const int64_t i = i0 + (int64_t)k * kIdsThreads;
                 const int64_t ic = i < upto ? i : 0;
                 c[k] = a.tile_vs[ic];
                 r[k] = last ? a.tile_rest[ic] : 0u;
             }
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
+            for (int k = 0; k < 16; ++k) {
                 const int64_t i = i0 + (int64_t)k * kIdsThreads;
                 if (i < upto) {
                     if (i < t0) base += c[k];
@@ -900,7 +901,7 @@ __global__ __launch_bounds__(kIdsThreads) void k_tile_ids(IdsArgs a)
     }
     if (last && tid == 0) {
         // the last block also knows every total
-        const u64 tot = base + (a.direct ? osum : (g < a.groups ? a.grp_vs[g] : 0ull));
+        const u64 tot = base + (DIRECT ? osum : (g < a.groups ? a.grp_vs[g] : 0ull));
         const u32 vis = (u32)(tot >> 32);
         *a.count = vis;
         a.hdr->vis_total = vis;
@@ -1103,247 +1104,235 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
         for (int u = 0; u < kRowUnroll; ++u) lastn[u] = a.last[idn[u] + vzero];
         u32 ridnn[kRowUnroll];
         fetch_raw(base + 2 * stride, ridnn);
-        // Most iterations hold kRowUnroll valid rows (and, for the Adam step,
-        // a compact gradient for each): that case runs a copy of the body
-        // without the per-row validity tests.
-        bool full = true;
+        // Raw words first (every row's loads in flight), selected and decoded
+        // afterwards.  The G and A halves load into separate registers that
+        // start undefined: a write of a default value to a register with a
+        // load of the other half still pending would have to wait for it.
+        u32 Gw[kRowUnroll], Gg[kRowUnroll], Aw[kRowUnroll], Ag[kRowUnroll];
+        typename RawT<GST>::T Gm[kRowUnroll], Gv[kRowUnroll];
+        typename RawT<AST>::T Am[kRowUnroll], Av[kRowUnroll];
+        float ms[kRowUnroll], vs[kRowUnroll];
 #pragma unroll
-        for (int u = 0; u < kRowUnroll; ++u) full = full && ok[u];
-        if (MODE == kAdam || MODE == kAdamMax) full = full && base + kRowUnroll <= nvis;
-        auto body = [&](auto fullc) {
-            constexpr bool FULL = decltype(fullc)::value;
-            // Raw words first (every row's loads in flight), selected and decoded
-            // afterwards.  The G and A halves load into separate registers that
-            // start undefined: a write of a default value to a register with a
-            // load of the other half still pending would have to wait for it.
-            u32 Gw[kRowUnroll], Gg[kRowUnroll], Aw[kRowUnroll], Ag[kRowUnroll];
-            typename RawT<GST>::T Gm[kRowUnroll], Gv[kRowUnroll];
-            typename RawT<AST>::T Am[kRowUnroll], Av[kRowUnroll];
-            float ms[kRowUnroll], vs[kRowUnroll];
+        for (int u = 0; u < kRowUnroll; ++u) {
+            Gw[u] = undef_v<u32>();
+            Gg[u] = undef_v<u32>();
+            Aw[u] = undef_v<u32>();
+            Ag[u] = undef_v<u32>();
+            Gm[u] = undef_v<typename RawT<GST>::T>();
+            Gv[u] = undef_v<typename RawT<GST>::T>();
+            Am[u] = undef_v<typename RawT<AST>::T>();
+            Av[u] = undef_v<typename RawT<AST>::T>();
+            const u64 ru = (u64)id[u], cp = (u64)(base + u);
+            float gms = 0.0f, gvs = 0.0f, ams = 0.0f, avs = 0.0f;
+            if (GST == GS_FP8E4M3 || AST == GS_FP8E4M3) {
+                const u64 b = ru / kFp8Block;
+                if (GST == GS_FP8E4M3) {
+                    gms = a.gm.s[b];
+                    gvs = a.gv.s[b];
+                }
+                if (AST == GS_FP8E4M3) {
+                    ams = a.am.s[b];
+                    avs = a.av.s[b];
+                }
+            }
+            ms[u] = isG ? gms : ams;
+            vs[u] = isG ? gvs : avs;
+            const bool need = ok[u] && act && (MODE != kFlush || d[u] > 0);
+            // the gather and Adam read the moments of every row (most visible
+            // rows are deferred); the flush only those it catches up
+            const bool ldm = MODE == kAdam || MODE == kAdamMax || MODE == kGather || d[u] > 0;
+            const bool ldg = (MODE == kAdam || MODE == kAdamMax) && base + u < nvis;
+            if (!need) continue;
+            if (FZ && ldm && grest) {
+                Gm[u] = mraw<GST>(elem(a.aw, ru, a.fz_s, fzm));
+                if (!sgd) Gv[u] = mraw<GST>(elem(a.aw, ru, a.fz_s, fzv));
+            }
+            if (isG) {
+                if (MODE != kAdamMax) Gw[u] = *reinterpret_cast<const u32 *>(elem(a.gw, ru, sGW, off4));
+                if (!FZ && ldm && !a.geo_dense) {
+                    Gm[u] = mraw<GST>(elem(a.gm.p, ru, sGM, offm));
+                    if (!sgd) Gv[u] = mraw<GST>(elem(a.gv.p, ru, sGV, offm));
+                }
+                if (ldg)
+                    Gg[u] = a.g_geo ? *reinterpret_cast<const u32 *>(elem(a.g_geo, cp, 40u, off4))
+                                    : *reinterpret_cast<const u32 *>(elem(a.gd_geo, ru, 40u, off4));
+                // distinct markers end the two halves: otherwise the compiler
+                // merges their accesses into one with a per-lane address
+                asm volatile("; G columns");
+            } else {
+                if (MODE != kAdamMax) Aw[u] = *reinterpret_cast<const u32 *>(elem(a.aw, ru, sAW, off4));
+                if (!FZ && ldm) {
+                    Am[u] = mraw<AST>(elem(a.am.p, ru, sAM, offm));
+                    if (!sgd) Av[u] = mraw<AST>(elem(a.av.p, ru, sAV, offm));
+                }
+                if (ldg)
+                    Ag[u] = a.g_app ? *reinterpret_cast<const u32 *>(elem(a.g_app, cp, sAG, off4))
+                                    : *reinterpret_cast<const u32 *>(elem(a.gd_app, ru, sAG, off4));
+                asm volatile("; A columns");
+            }
+        }
+        // no instruction that waits for a load may be moved between the loads
+        __builtin_amdgcn_sched_barrier(0);
+        // values of lanes or rows that loaded nothing are never stored; a
+        // saturated row (no compact gradient) takes g = 0
+        float w[kRowUnroll], m[kRowUnroll], v[kRowUnroll], g[kRowUnroll];
 #pragma unroll
-            for (int u = 0; u < kRowUnroll; ++u) {
-                Gw[u] = undef_v<u32>();
-                Gg[u] = undef_v<u32>();
-                Aw[u] = undef_v<u32>();
-                Ag[u] = undef_v<u32>();
-                Gm[u] = undef_v<typename RawT<GST>::T>();
-                Gv[u] = undef_v<typename RawT<GST>::T>();
-                Am[u] = undef_v<typename RawT<AST>::T>();
-                Av[u] = undef_v<typename RawT<AST>::T>();
-                const u64 ru = (u64)id[u], cp = (u64)(base + u);
-                float gms = 0.0f, gvs = 0.0f, ams = 0.0f, avs = 0.0f;
-                if (GST == GS_FP8E4M3 || AST == GS_FP8E4M3) {
-                    const u64 b = ru / kFp8Block;
-                    if (GST == GS_FP8E4M3) {
-                        gms = a.gm.s[b];
-                        gvs = a.gv.s[b];
-                    }
-                    if (AST == GS_FP8E4M3) {
-                        ams = a.am.s[b];
-                        avs = a.av.s[b];
+        for (int u = 0; u < kRowUnroll; ++u) {
+            w[u] = __uint_as_float(isG ? Gw[u] : Aw[u]);
+            const bool ldg = (MODE == kAdam || MODE == kAdamMax) && base + u < nvis;
+            g[u] = ldg ? __uint_as_float(isG ? Gg[u] : Ag[u]) : 0.0f;
+            if (FZ) {
+                m[u] = mdec<GST>((u32)Gm[u], ms[u], false);
+                v[u] = mdec<GST>((u32)Gv[u], vs[u], true);
+            } else if (GST == AST) {
+                m[u] = mdec<GST>(isG ? (u32)Gm[u] : (u32)Am[u], ms[u], false);
+                v[u] = mdec<GST>(isG ? (u32)Gv[u] : (u32)Av[u], vs[u], true);
+            } else {
+                m[u] = isG ? mdec<GST>(Gm[u], ms[u], false) : mdec<AST>(Am[u], ms[u], false);
+                v[u] = isG ? mdec<GST>(Gv[u], vs[u], true) : mdec<AST>(Av[u], vs[u], true);
+            }
+        }
+        // table entries of each row's gap (issued after the state loads, which
+        // do not depend on them)
+        float Wd[kRowUnroll], Mfd[kRowUnroll], Vfd[kRowUnroll];
+#pragma unroll
+        for (int u = 0; u < kRowUnroll; ++u) {
+            Wd[u] = Wrow[d[u]];
+            Mfd[u] = Vfd[u] = 0.0f;
+            if (MODE == kAdam || MODE == kAdamMax || MODE == kFlush) {
+                const int j = MODE == kFlush ? (d[u] > 0 ? d[u] - 1 : 0) : d[u];
+                Mfd[u] = a.Mf[j];
+                Vfd[u] = a.Vf[j];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kRowUnroll; ++u) {
+            if (!ok[u]) continue;
+            const u32 r = id[u];
+            if (MODE == kGather) {
+                float x = w[u];
+                if (d[u] > 0 && grest) {
+                    if (sgd) x = x - (Wd[u] * lr) * m[u];
+                    else if (adamw) x = restore_w(x, m[u], v[u], WlRow[d[u]], PRow[d[u]], lr, a.eps, a.rb);
+                    else x = restore1(x, m[u], v[u], Wd[u], lr, a.eps, a.rb);
+                }
+                if (act) {
+                    const u64 cp = (u64)(base + u);
+                    if (isG) {
+                        if (a.out_geo) *reinterpret_cast<float *>(elem(a.out_geo, cp, 40u, off4)) = x;
+                    } else if (a.out_app) {
+                        *reinterpret_cast<float *>(elem(a.out_app, cp, sAG, off4)) = x;
                     }
                 }
-                ms[u] = isG ? gms : ams;
-                vs[u] = isG ? gvs : avs;
-                const bool need = (FULL || ok[u]) && act && (MODE != kFlush || d[u] > 0);
-                // the gather and Adam read the moments of every row (most visible
-                // rows are deferred); the flush only those it catches up
-                const bool ldm = MODE == kAdam || MODE == kAdamMax || MODE == kGather || d[u] > 0;
-                const bool ldg = (MODE == kAdam || MODE == kAdamMax) && (FULL || base + u < nvis);
-                if (!need) continue;
-                if (FZ && ldm && grest) {
-                    Gm[u] = mraw<GST>(elem(a.aw, ru, a.fz_s, fzm));
-                    if (!sgd) Gv[u] = mraw<GST>(elem(a.aw, ru, a.fz_s, fzv));
+                continue;
+            }
+            const int dd = d[u];
+            if (MODE == kAdamMax) {
+                const bool fp8 = isG ? GST == GS_FP8E4M3 : AST == GS_FP8E4M3;
+                const u32 b = r / kFp8Block;
+                u32 xm = 0u, xv = 0u;
+                if (act && fp8) {
+                    const float m1 = Mfd[u] * m[u] + a.omb1 * g[u];
+                    const float v1 = Vfd[u] * v[u] + (a.omb2 * g[u]) * g[u];
+                    const float r1 = sqrtf(v1);
+                    const float am = fabsf(m1);
+                    if (am > 448.0f * ms[u]) xm = __float_as_uint(am);
+                    if (r1 > 448.0f * vs[u]) xv = __float_as_uint(r1);
+                }
+                // maxima over the group's lanes (non-negative floats order as
+                // their bit patterns), then at most four atomics per row
+                u32 mx[4] = {isG ? xm : 0u, isG ? xv : 0u, isG ? 0u : xm, isG ? 0u : xv};
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const u32 y = (u32)__shfl_xor((int)mx[k], o);
+                        mx[k] = y > mx[k] ? y : mx[k];
+                    }
+                if (lane == 0)
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+                        if (mx[k]) {
+                            // the first record of a task this step lists it for the rescale
+                            const u32 old = atomicMax(&a.fp8max[k][b], mx[k]);
+                            if (old == 0u) {
+                                const u32 at = atomicAdd(a.fp8count, 1u);
+                                if ((int64_t)at < 4 * a.nb) a.fp8list[at] = (u32)(k * a.nb + b);
+                            }
+                        }
+                continue;
+            }
+            if (MODE == kFlush && dd == 0) continue;
+            if (act) {
+                float x, m1, v1;
+                if (MODE == kAdam && sgd) {
+                    // SGD with momentum: catch up, buf = mu^(d+1) buf + g, w -= (lr s_t) buf
+                    x = w[u];
+                    if (dd > 0) x = x - (Wd[u] * lr) * m[u];
+                    m1 = Mfd[u] * m[u] + g[u];
+                    v1 = 0.0f;
+                    x = x - step * m1;
+                } else if (MODE == kAdam && adamw) {
+                    // AdamW: decayed catch-up, Adam moments, w = q_t w - step
+                    x = w[u];
+                    if (dd > 0) x = restore_w(x, m[u], v[u], WlRow[dd], PRow[dd], lr, a.eps, a.rb);
+                    m1 = Mfd[u] * m[u] + a.omb1 * g[u];
+                    v1 = Vfd[u] * v[u] + (a.omb2 * g[u]) * g[u];
+                    const float xq = qdec * x;
+                    x = xq - adam_step(m1, v1, step, bc, a.eps, a.rb);
+                } else if (MODE == kAdam) {
+                    x = w[u];
+                    if (dd > 0) x = restore1(x, m[u], v[u], Wd[u], lr, a.eps, a.rb);
+                    m1 = Mfd[u] * m[u] + a.omb1 * g[u];
+                    v1 = Vfd[u] * v[u] + (a.omb2 * g[u]) * g[u];
+                    x = x - adam_step(m1, v1, step, bc, a.eps, a.rb);
+                } else if (adamw) {
+                    x = restore_w(w[u], m[u], v[u], WlRow[dd], PRow[dd], lr, a.eps, a.rb);
+                    m1 = Mfd[u] * m[u];
+                    v1 = Vfd[u] * v[u];
+                } else if (sgd) {
+                    x = w[u] - (Wd[u] * lr) * m[u];
+                    m1 = Mfd[u] * m[u];
+                    v1 = 0.0f;
+                } else {
+                    x = restore1(w[u], m[u], v[u], Wd[u], lr, a.eps, a.rb);
+                    m1 = Mfd[u] * m[u];
+                    v1 = Vfd[u] * v[u];
+                }
+                u32 rm = 0, rv = 0;
+                if (quant) {
+                    // the row's part of the random stream is the same on every
+                    // lane: compute it once, on the scalar unit
+                    const u64 h = sm_at(sm_at(s_step, (u64)r), (u64)lane);
+                    rm = (u32)(h & 0xffffull);
+                    rv = (u32)((h >> 16) & 0xffffull);
+                }
+                const u64 ru = (u64)r;
+                const bool clr = MODE == kAdam && !a.g_geo && base + u < nvis;
+                if (FZ) {
+                    mstore<GST>(elem(a.aw, ru, a.fz_s, fzm), ms[u], m1, rm, false);
+                    if (!sgd) mstore<GST>(elem(a.aw, ru, a.fz_s, fzv), vs[u], v1, rv, true);
                 }
                 if (isG) {
-                    if (MODE != kAdamMax) Gw[u] = *reinterpret_cast<const u32 *>(elem(a.gw, ru, sGW, off4));
-                    if (!FZ && ldm && !a.geo_dense) {
-                        Gm[u] = mraw<GST>(elem(a.gm.p, ru, sGM, offm));
-                        if (!sgd) Gv[u] = mraw<GST>(elem(a.gv.p, ru, sGV, offm));
+                    *reinterpret_cast<float *>(elem(a.gw, ru, sGW, off4)) = x;
+                    if (!FZ) {
+                        mstore<GST>(elem(a.gm.p, ru, sGM, offm), ms[u], m1, rm, false);
+                        if (!sgd) mstore<GST>(elem(a.gv.p, ru, sGV, offm), vs[u], v1, rv, true);
                     }
-                    if (ldg)
-                        Gg[u] = a.g_geo ? *reinterpret_cast<const u32 *>(elem(a.g_geo, cp, 40u, off4))
-                                        : *reinterpret_cast<const u32 *>(elem(a.gd_geo, ru, 40u, off4));
-                    // distinct markers end the two halves: otherwise the compiler
-                    // merges their accesses into one with a per-lane address
+                    if (clr) *reinterpret_cast<float *>(elem(a.gd_geo, ru, 40u, off4)) = 0.0f;
                     asm volatile("; G columns");
                 } else {
-                    if (MODE != kAdamMax) Aw[u] = *reinterpret_cast<const u32 *>(elem(a.aw, ru, sAW, off4));
-                    if (!FZ && ldm) {
-                        Am[u] = mraw<AST>(elem(a.am.p, ru, sAM, offm));
-                        if (!sgd) Av[u] = mraw<AST>(elem(a.av.p, ru, sAV, offm));
+                    *reinterpret_cast<float *>(elem(a.aw, ru, sAW, off4)) = x;
+                    if (!FZ) {
+                        mstore<AST>(elem(a.am.p, ru, sAM, offm), ms[u], m1, rm, false);
+                        if (!sgd) mstore<AST>(elem(a.av.p, ru, sAV, offm), vs[u], v1, rv, true);
                     }
-                    if (ldg)
-                        Ag[u] = a.g_app ? *reinterpret_cast<const u32 *>(elem(a.g_app, cp, sAG, off4))
-                                        : *reinterpret_cast<const u32 *>(elem(a.gd_app, ru, sAG, off4));
+                    if (clr) *reinterpret_cast<float *>(elem(a.gd_app, ru, sAG, off4)) = 0.0f;
                     asm volatile("; A columns");
                 }
             }
-            // no instruction that waits for a load may be moved between the loads
-            __builtin_amdgcn_sched_barrier(0);
-            // values of lanes or rows that loaded nothing are never stored; a
-            // saturated row (no compact gradient) takes g = 0
-            float w[kRowUnroll], m[kRowUnroll], v[kRowUnroll], g[kRowUnroll];
-#pragma unroll
-            for (int u = 0; u < kRowUnroll; ++u) {
-                w[u] = __uint_as_float(isG ? Gw[u] : Aw[u]);
-                const bool ldg = (MODE == kAdam || MODE == kAdamMax) && (FULL || base + u < nvis);
-                g[u] = ldg ? __uint_as_float(isG ? Gg[u] : Ag[u]) : 0.0f;
-                if (FZ) {
-                    m[u] = mdec<GST>((u32)Gm[u], ms[u], false);
-                    v[u] = mdec<GST>((u32)Gv[u], vs[u], true);
-                } else if (GST == AST) {
-                    m[u] = mdec<GST>(isG ? (u32)Gm[u] : (u32)Am[u], ms[u], false);
-                    v[u] = mdec<GST>(isG ? (u32)Gv[u] : (u32)Av[u], vs[u], true);
-                } else {
-                    m[u] = isG ? mdec<GST>(Gm[u], ms[u], false) : mdec<AST>(Am[u], ms[u], false);
-                    v[u] = isG ? mdec<GST>(Gv[u], vs[u], true) : mdec<AST>(Av[u], vs[u], true);
-                }
-            }
-            // table entries of each row's gap (issued after the state loads, which
-            // do not depend on them)
-            float Wd[kRowUnroll], Mfd[kRowUnroll], Vfd[kRowUnroll];
-#pragma unroll
-            for (int u = 0; u < kRowUnroll; ++u) {
-                Wd[u] = Wrow[d[u]];
-                Mfd[u] = Vfd[u] = 0.0f;
-                if (MODE == kAdam || MODE == kAdamMax || MODE == kFlush) {
-                    const int j = MODE == kFlush ? (d[u] > 0 ? d[u] - 1 : 0) : d[u];
-                    Mfd[u] = a.Mf[j];
-                    Vfd[u] = a.Vf[j];
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < kRowUnroll; ++u) {
-                if (!(FULL || ok[u])) continue;
-                const u32 r = id[u];
-                if (MODE == kGather) {
-                    float x = w[u];
-                    if (d[u] > 0 && grest) {
-                        if (sgd) x = x - (Wd[u] * lr) * m[u];
-                        else if (adamw) x = restore_w(x, m[u], v[u], WlRow[d[u]], PRow[d[u]], lr, a.eps, a.rb);
-                        else x = restore1(x, m[u], v[u], Wd[u], lr, a.eps, a.rb);
-                    }
-                    if (act) {
-                        const u64 cp = (u64)(base + u);
-                        if (isG) {
-                            if (a.out_geo) *reinterpret_cast<float *>(elem(a.out_geo, cp, 40u, off4)) = x;
-                        } else if (a.out_app) {
-                            *reinterpret_cast<float *>(elem(a.out_app, cp, sAG, off4)) = x;
-                        }
-                    }
-                    continue;
-                }
-                const int dd = d[u];
-                if (MODE == kAdamMax) {
-                    const bool fp8 = isG ? GST == GS_FP8E4M3 : AST == GS_FP8E4M3;
-                    const u32 b = r / kFp8Block;
-                    u32 xm = 0u, xv = 0u;
-                    if (act && fp8) {
-                        const float m1 = Mfd[u] * m[u] + a.omb1 * g[u];
-                        const float v1 = Vfd[u] * v[u] + (a.omb2 * g[u]) * g[u];
-                        const float r1 = sqrtf(v1);
-                        const float am = fabsf(m1);
-                        if (am > 448.0f * ms[u]) xm = __float_as_uint(am);
-                        if (r1 > 448.0f * vs[u]) xv = __float_as_uint(r1);
-                    }
-                    // maxima over the group's lanes (non-negative floats order as
-                    // their bit patterns), then at most four atomics per row
-                    u32 mx[4] = {isG ? xm : 0u, isG ? xv : 0u, isG ? 0u : xm, isG ? 0u : xv};
-#pragma unroll
-                    for (int o = 32; o > 0; o >>= 1)
-#pragma unroll
-                        for (int k = 0; k < 4; ++k) {
-                            const u32 y = (u32)__shfl_xor((int)mx[k], o);
-                            mx[k] = y > mx[k] ? y : mx[k];
-                        }
-                    if (lane == 0)
-#pragma unroll
-                        for (int k = 0; k < 4; ++k)
-                            if (mx[k]) {
-                                // the first record of a task this step lists it for the rescale
-                                const u32 old = atomicMax(&a.fp8max[k][b], mx[k]);
-                                if (old == 0u) {
-                                    const u32 at = atomicAdd(a.fp8count, 1u);
-                                    if ((int64_t)at < 4 * a.nb) a.fp8list[at] = (u32)(k * a.nb + b);
-                                }
-                            }
-                    continue;
-                }
-                if (MODE == kFlush && dd == 0) continue;
-                if (act) {
-                    float x, m1, v1;
-                    if (MODE == kAdam && sgd) {
-                        // SGD with momentum: catch up, buf = mu^(d+1) buf + g, w -= (lr s_t) buf
-                        x = w[u];
-                        if (dd > 0) x = x - (Wd[u] * lr) * m[u];
-                        m1 = Mfd[u] * m[u] + g[u];
-                        v1 = 0.0f;
-                        x = x - step * m1;
-                    } else if (MODE == kAdam && adamw) {
-                        // AdamW: decayed catch-up, Adam moments, w = q_t w - step
-                        x = w[u];
-                        if (dd > 0) x = restore_w(x, m[u], v[u], WlRow[dd], PRow[dd], lr, a.eps, a.rb);
-                        m1 = Mfd[u] * m[u] + a.omb1 * g[u];
-                        v1 = Vfd[u] * v[u] + (a.omb2 * g[u]) * g[u];
-                        const float xq = qdec * x;
-                        x = xq - adam_step(m1, v1, step, bc, a.eps, a.rb);
-                    } else if (MODE == kAdam) {
-                        x = w[u];
-                        if (dd > 0) x = restore1(x, m[u], v[u], Wd[u], lr, a.eps, a.rb);
-                        m1 = Mfd[u] * m[u] + a.omb1 * g[u];
-                        v1 = Vfd[u] * v[u] + (a.omb2 * g[u]) * g[u];
-                        x = x - adam_step(m1, v1, step, bc, a.eps, a.rb);
-                    } else if (adamw) {
-                        x = restore_w(w[u], m[u], v[u], WlRow[dd], PRow[dd], lr, a.eps, a.rb);
-                        m1 = Mfd[u] * m[u];
-                        v1 = Vfd[u] * v[u];
-                    } else if (sgd) {
-                        x = w[u] - (Wd[u] * lr) * m[u];
-                        m1 = Mfd[u] * m[u];
-                        v1 = 0.0f;
-                    } else {
-                        x = restore1(w[u], m[u], v[u], Wd[u], lr, a.eps, a.rb);
-                        m1 = Mfd[u] * m[u];
-                        v1 = Vfd[u] * v[u];
-                    }
-                    u32 rm = 0, rv = 0;
-                    if (quant) {
-                        // the row's part of the random stream is the same on every
-                        // lane: compute it once, on the scalar unit
-                        const u64 h = sm_at(sm_at(s_step, (u64)r), (u64)lane);
-                        rm = (u32)(h & 0xffffull);
-                        rv = (u32)((h >> 16) & 0xffffull);
-                    }
-                    const u64 ru = (u64)r;
-                    const bool clr = MODE == kAdam && !a.g_geo && (FULL || base + u < nvis);
-                    if (FZ) {
-                        mstore<GST>(elem(a.aw, ru, a.fz_s, fzm), ms[u], m1, rm, false);
-                        if (!sgd) mstore<GST>(elem(a.aw, ru, a.fz_s, fzv), vs[u], v1, rv, true);
-                    }
-                    if (isG) {
-                        *reinterpret_cast<float *>(elem(a.gw, ru, sGW, off4)) = x;
-                        if (!FZ) {
-                            mstore<GST>(elem(a.gm.p, ru, sGM, offm), ms[u], m1, rm, false);
-                            if (!sgd) mstore<GST>(elem(a.gv.p, ru, sGV, offm), vs[u], v1, rv, true);
-                        }
-                        if (clr) *reinterpret_cast<float *>(elem(a.gd_geo, ru, 40u, off4)) = 0.0f;
-                        asm volatile("; G columns");
-                    } else {
-                        *reinterpret_cast<float *>(elem(a.aw, ru, sAW, off4)) = x;
-                        if (!FZ) {
-                            mstore<AST>(elem(a.am.p, ru, sAM, offm), ms[u], m1, rm, false);
-                            if (!sgd) mstore<AST>(elem(a.av.p, ru, sAV, offm), vs[u], v1, rv, true);
-                        }
-                        if (clr) *reinterpret_cast<float *>(elem(a.gd_app, ru, sAG, off4)) = 0.0f;
-                        asm volatile("; A columns");
-                    }
-                }
-                if (lane == 0) a.last[r] = t;
-            }
-        };
-        if (full) body(std::true_type{});
-        else body(std::false_type{});
+            if (lane == 0) a.last[r] = t;
+        }
 #pragma unroll
         for (int u = 0; u < kRowUnroll; ++u) {
             d[u] = gap(lastn[u], okn[u]);
@@ -2861,7 +2850,9 @@ int gs_cull(const gs_model *model, const gs_camera *cam, int64_t step, uint32_t 
         int rc2 = launched("gs_cull (group sums)");
         if (rc2) return rc2;
     }
-    hipLaunchKernelGGL(k_tile_ids, dim3((unsigned)(ia.groups > 0 ? ia.groups : 1)), dim3(kIdsThreads), 0, st, ia);
+    const dim3 ig((unsigned)(ia.groups > 0 ? ia.groups : 1));
+    if (ia.direct) hipLaunchKernelGGL(k_tile_ids<true>, ig, dim3(kIdsThreads), 0, st, ia);
+    else hipLaunchKernelGGL(k_tile_ids<false>, ig, dim3(kIdsThreads), 0, st, ia);
     return launched("gs_cull");
 }
 
