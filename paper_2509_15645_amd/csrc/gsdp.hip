@@ -989,7 +989,10 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
     constexpr bool sgd = OPT == GS_OPT_SGD_MOMENTUM;
     constexpr bool adamw = OPT == GS_OPT_ADAMW;
     const int ca = lane - 10;
-    const int col = isG ? lane : ca;
+    // Lanes past the last column load (but never store) the last column, so
+    // that the loads need no lane mask: a row's loads are then one uniform
+    // branch, not a mask of lanes.
+    const int col = isG ? lane : (ca < a.adim ? ca : a.adim - 1);
     // Addressing: a row's base in each array is wave-uniform (scalar
     // registers); each lane adds a 32-bit byte offset of its column that is
     // fixed for the whole launch.  G and A lanes take their loads and stores
@@ -1002,8 +1005,8 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
     const u32 sAM = (u32)a.am.ld * msize<AST>(), sAV = (u32)a.av.ld * msize<AST>();
     const u32 sAG = (u32)a.adim * 4u;
     static_assert(!FZ || GST == AST, "the fused single access needs one storage type");
-    const u32 fzm = isG ? a.fz_ogm + (u32)lane * msize<GST>() : a.fz_oam + (u32)ca * msize<AST>();
-    const u32 fzv = isG ? a.fz_ogv + (u32)lane * msize<GST>() : a.fz_oav + (u32)ca * msize<AST>();
+    const u32 fzm = isG ? a.fz_ogm + (u32)col * msize<GST>() : a.fz_oam + (u32)col * msize<AST>();
+    const u32 fzv = isG ? a.fz_ogv + (u32)col * msize<GST>() : a.fz_oav + (u32)col * msize<AST>();
     // element of row r (stride s bytes) at this lane's byte offset o; the row
     // base goes through srow, so it stays a scalar base of the access
     auto elem = [](const void *p, u64 r, u32 s, u32 o) { return (char *)(srow(p, r, s) + lane_off(o)); };
@@ -1059,13 +1062,15 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
     int vzero;
     asm volatile("v_mov_b32 %0, 0" : "=v"(vzero));
     const u32 stride = nw * kRowUnroll;
+    // positions past nvis index the saturated list (only rows in range are
+    // ever read through it)
+    const u32 *sat_base = a.sat_ids ? a.sat_ids - nvis : a.ids;
     auto fetch_raw = [&](u32 b, u32 *rid) {
         if (MODE == kFlush) return;
 #pragma unroll
         for (int u = 0; u < kRowUnroll; ++u) {
-            const u32 i = b + u < total ? b + u : total - 1u;
-            const u32 *src = i < nvis ? a.ids : a.sat_ids;
-            rid[u] = src[(i < nvis ? i : i - nvis) + vzero];
+            const u32 i = min(b + u, total - 1u);
+            rid[u] = (i < nvis ? a.ids : sat_base)[i + vzero];
         }
     };
     auto decode = [&](u32 b, const u32 *rid, u32 *idv, bool *okv) {
@@ -1137,13 +1142,15 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
             }
             ms[u] = isG ? gms : ams;
             vs[u] = isG ? gvs : avs;
-            const bool need = ok[u] && act && (MODE != kFlush || d[u] > 0);
+            const bool need = ok[u] && (MODE != kFlush || d[u] > 0);
             // the gather and Adam read the moments of every row (most visible
             // rows are deferred); the flush only those it catches up
             const bool ldm = MODE == kAdam || MODE == kAdamMax || MODE == kGather || d[u] > 0;
             const bool ldg = (MODE == kAdam || MODE == kAdamMax) && base + u < nvis;
             if (!need) continue;
-            if (FZ && ldm && grest) {
+            // (with dense geometry the G moments are current: loading them is
+            // harmless, and no lane mask is needed)
+            if (FZ && ldm) {
                 Gm[u] = mraw<GST>(elem(a.aw, ru, a.fz_s, fzm));
                 if (!sgd) Gv[u] = mraw<GST>(elem(a.aw, ru, a.fz_s, fzv));
             }
