@@ -1371,7 +1371,7 @@ struct RescaleArgs {
 // smallest power of two that fits the recorded max and re-encode the block.
 __global__ __launch_bounds__(256) void k_fp8_rescale(RescaleArgs a)
 {
-    constexpr int kIlp = 4;
+    constexpr int kIlp = 8;          // codes per thread in flight (a 49-column block: 3 rounds)
     __shared__ float sOld;
     const int tid = threadIdx.x;
     const float *Wrow;
@@ -1410,9 +1410,9 @@ __global__ __launch_bounds__(256) void k_fp8_rescale(RescaleArgs a)
 #pragma unroll
                 for (int k = 0; k < kIlp; ++k) {
                     const int64_t e = e0 + k * 256 + tid;
-                    const int64_t rr = e / dim;
+                    const u32 rr = (u32)e / (u32)dim;     // e < 128 * 54: 32-bit division
                     row[k] = r0 + rr;
-                    col[k] = (int)(e - rr * dim);
+                    col[k] = (int)((u32)e - rr * (u32)dim);
                     off[k] = e < nel ? row[k] * ld + col[k] : -1;
                     code[k] = off[k] >= 0 ? q[off[k]] : (uint8_t)0;
                 }
@@ -3004,7 +3004,7 @@ int gs_adam_step_deferred(const gs_model *model, int64_t step, const uint32_t *i
         ra.list = a.fp8list;
         ra.count = a.fp8count;
         const int cu = cu_count();
-        hipLaunchKernelGGL(k_fp8_rescale, dim3((unsigned)((cu > 0 ? cu : 256) * 4)), dim3(256), 0,
+        hipLaunchKernelGGL(k_fp8_rescale, dim3((unsigned)((cu > 0 ? cu : 256) * 8)), dim3(256), 0,
                            (hipStream_t)stream, ra);
         rc1 = launched("gs_adam_step_deferred (fp8 rescale)");
         if (rc1) return rc1;
