@@ -287,14 +287,6 @@ __device__ __forceinline__ void mom_store<GS_BF16>(const MomRef &q, int64_t row,
     else h = (uint16_t)((u + r16) >> 16);
     static_cast<uint16_t *>(q.p)[row * q.ld + col] = h;
 }
-template <>
-__device__ __forceinline__ void mom_store<GS_FP8E4M3>(const MomRef &q, int64_t row, int64_t col, float x, u32 r16,
-                                                      bool is_v)
-{
-    const float sc = q.s[row / kFp8Block];
-    const float y = is_v ? sqrtf(x) : x;
-    static_cast<uint8_t *>(q.p)[row * q.ld + col] = sc > 0.0f ? (uint8_t)e4m3_sr(y / sc, r16) : (uint8_t)0;
-}
 
 // Byte address of row r (stride s bytes) of the array at p, as a value the
 // compiler cannot see through: it then addresses the lanes' columns as this
@@ -1674,13 +1666,6 @@ StepK step_k(const gs_model *m, int64_t step)
     return k;
 }
 
-int dmax_for(const gs_model *m, int64_t t_row)
-{
-    int64_t dm = t_row - 1;
-    if (m->max_defer > 0 && dm > m->max_defer) dm = m->max_defer;
-    return (int)dm;
-}
-
 // AdamW decay classes: the distinct column rates in order of first
 // appearance (G columns 0..9, then A columns); cls[lane] is the class of the
 // column lane (0..9 G, 10.. A).  Returns the number of classes, -1 if > 8.
@@ -1860,7 +1845,6 @@ int row_grid(int64_t rows)
 // from per-tile counts of 33 counters (union and 32 camera slots).
 constexpr int kMaxCams = 32;
 constexpr int kNCnt = kMaxCams + 1;
-constexpr int kMultiAlign = 1024;
 constexpr int kMultiMinTile = 128;
 
 struct CamPack {                     // one camera with its band-classifier constants
@@ -2522,10 +2506,9 @@ __global__ __launch_bounds__(kCullBlock) void k_dens_apply(DensArgs a)
 
 namespace {
 
-// autotuned variants of the batched cull: (block size, rows per thread)
+// autotuned variants of the batched cull: (block size, rows per thread) =
+// (128, 1), (128, 2), (128, 4), (256, 1), (256, 2), (256, 4)
 constexpr int kMultiVariants = 6;
-constexpr int kMultiBlock[kMultiVariants] = {128, 128, 128, 256, 256, 256};
-constexpr int kMultiIpt[kMultiVariants] = {1, 2, 4, 1, 2, 4};
 
 int64_t multi_ws_bytes(int64_t n)
 {
@@ -3215,16 +3198,17 @@ int gs_cull_multi_autotune(const gs_model *model, gs_multi *desc, int64_t step, 
     for (int v = 0; v < kMultiVariants; ++v) {
         rc = launch_multi(v, a, model->n, st);  // warm-up
         if (rc) break;
-        hipEventRecord(e0, st);
-        for (int r = 0; r < 3; ++r) launch_multi(v, a, model->n, st);
-        hipEventRecord(e1, st);
-        hipError_t he = hipEventSynchronize(e1);
+        hipError_t he = hipEventRecord(e0, st);
+        for (int r = 0; r < 3 && !rc; ++r) rc = launch_multi(v, a, model->n, st);
+        if (rc) break;
+        if (he == hipSuccess) he = hipEventRecord(e1, st);
+        if (he == hipSuccess) he = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
         if (he != hipSuccess) {
             rc = hip_fail(he, "autotune");
             break;
         }
-        float ms = 0.0f;
-        hipEventElapsedTime(&ms, e0, e1);
         ms /= 3.0f;
         if (times_ms) times_ms[v] = ms;
         if (ms < best_ms) {
@@ -3232,8 +3216,8 @@ int gs_cull_multi_autotune(const gs_model *model, gs_multi *desc, int64_t step, 
             best = v;
         }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (rc) return rc;
     desc->variant = best;
     return GS_OK;
