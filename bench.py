@@ -146,24 +146,6 @@ def morton_order(pos, box):
     return torch.argsort(code)
 
 
-def device_scene(n, box, seed, dev):
-    """Seeded synthetic scene drawn on the device (same distributions as
-    gs_inputs.make_scene, torch's generator instead of numpy's)."""
-    import torch
-    gen = torch.Generator(device=dev)
-    gen.manual_seed(seed)
-    lo = torch.tensor([b[0] for b in box], device=dev, dtype=torch.float32)
-    hi = torch.tensor([b[1] for b in box], device=dev, dtype=torch.float32)
-    geo = torch.empty((n, 10), device=dev, dtype=torch.float32)
-    geo[:, 0:3] = torch.rand((n, 3), generator=gen, device=dev) * (hi - lo) + lo
-    geo[:, 3:6] = torch.randn((n, 3), generator=gen, device=dev) * 0.5 - 3.0
-    q = torch.randn((n, 4), generator=gen, device=dev)
-    geo[:, 6:10] = q / q.norm(dim=1, keepdim=True)
-    app = torch.randn((n, 49), generator=gen, device=dev) * 0.1
-    app[:, 0] = torch.randn(n, generator=gen, device=dev)
-    return geo, app
-
-
 def run_batched(args):
     """16 scenes of log-uniform size (0.5M-8M) x 32 cameras per step: one
     batched cull+compaction launch, deterministic per-camera gradient sum,
@@ -181,7 +163,7 @@ def run_batched(args):
     geos, apps, row0, sets = [], [], [0], [[] for _ in range(n_sets)]
     for sidx, n in enumerate(sizes):
         box, half = gi.aerial_box_for(n)
-        g_, a_ = device_scene(n, box, 1000 + sidx, dev)
+        g_, a_ = gi.device_scene(n, box, 1000 + sidx, dev)
         pad = (-n) % gsdp.MULTI_ALIGN
         if pad:
             gp = torch.full((pad, 10), float("nan"), device=dev)
@@ -321,7 +303,7 @@ def main():
     dev = torch.device("cuda")
     on_dev = args.device_scene if args.device_scene is not None else int(w.n > 8_000_000)
     if on_dev:
-        geo0, app0 = device_scene(w.n, w.scene_box, 0, dev)
+        geo0, app0 = gi.device_scene(w.n, w.scene_box, 0, dev)
     else:
         sc = gi.make_scene(w.n, seed=0, box=w.scene_box)
         geo0, app0 = sc.geo, sc.app

@@ -265,3 +265,21 @@ def aerial_box_for(n: int, n_ref: int = 4_000_000, side_ref: float = 1000.0, hei
     """Aerial box with the 4M-Gaussian workload's density: side 1000 * sqrt(n / 4M)."""
     half = side_ref * math.sqrt(n / n_ref) / 2
     return ((-half, half), (-half, half), (0.0, height)), half
+
+
+def device_scene(n, box, seed, dev):
+    """Seeded synthetic scene drawn on the device (same distributions as
+    make_scene, torch's generator instead of numpy's)."""
+    import torch
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(seed)
+    lo = torch.tensor([b[0] for b in box], device=dev, dtype=torch.float32)
+    hi = torch.tensor([b[1] for b in box], device=dev, dtype=torch.float32)
+    geo = torch.empty((n, 10), device=dev, dtype=torch.float32)
+    geo[:, 0:3] = torch.rand((n, 3), generator=gen, device=dev) * (hi - lo) + lo
+    geo[:, 3:6] = torch.randn((n, 3), generator=gen, device=dev) * 0.5 - 3.0
+    q = torch.randn((n, 4), generator=gen, device=dev)
+    geo[:, 6:10] = q / q.norm(dim=1, keepdim=True)
+    app = torch.randn((n, 49), generator=gen, device=dev) * 0.1
+    app[:, 0] = torch.randn(n, generator=gen, device=dev)
+    return geo, app
