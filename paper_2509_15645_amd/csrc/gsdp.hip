@@ -1883,10 +1883,11 @@ struct MultiArgs {
     int32_t tile_rows, pad5;         // rows per tile of this launch
 };
 
-// Batched cull in three launches (as the single-camera cull): k_cull_multi
-// writes every row's camera bits and the tile's counts, k_multi_scan takes
-// the exclusive prefixes over tiles for every counter, k_multi_ids writes the
-// union ids and the per-camera union positions.
+// Batched cull in four launches (as the single-camera cull): k_cull_multi
+// writes every row's camera bits and the tile's counts, k_multi_reduce and
+// k_multi_offsets take the exclusive prefixes over tiles for every counter,
+// k_multi_ids writes the union ids, the per-camera union positions and the
+// chunk starts of the gradient sum.
 template <int BLOCK, int IPT>
 __global__ __launch_bounds__(BLOCK) void k_cull_multi(MultiArgs a)
 {
