@@ -201,7 +201,7 @@ int gs_cull(const gs_model *model, const gs_camera *cam, int64_t step, uint32_t 
  * rows are restored with the w_scale LUT and their stored moments (Eq. 3);
  * nothing in the model is written (read-only forwarding, Sec. 4.3.3).
  * out_geo / out_app are dense [capacity][10] / [capacity][dim]; either may
- * be NULL to skip that group. */
+ * be NULL to skip that group.  Ids >= model->n are skipped. */
 int gs_gather(const gs_model *model, int64_t step, const uint32_t *ids, const uint32_t *count_dev,
               uint32_t capacity, float *out_geo, float *out_app, void *stream);
 
@@ -221,7 +221,8 @@ int gs_scatter_grad(const uint32_t *ids, const uint32_t *count_dev, uint32_t cap
  * Gradients: compact g_geo [capacity][10] / g_app [capacity][dim] aligned
  * with ids (the scatter is fused), or, when g_geo/g_app are NULL, dense rows
  * g_geo_dense[id] / g_app_dense[id] that are read and then cleared to zero.
- * Saturated rows use g = 0. */
+ * Saturated rows use g = 0.  The ids must be distinct (gs_cull's are); ids
+ * >= model->n are skipped. */
 /* (With geo_mode = 1 and compact gradients, the call must follow the gs_cull
  * of the same step on the same workspace: the dense geometric update finds
  * each visible row's compact gradient from the cull's keep ballots.) */
