@@ -377,12 +377,13 @@ int gs_synth_grad(uint64_t seed, int64_t step, const uint32_t *ids, const uint32
                   void *stream);
 
 /* Measurement helper (not part of the method): one streaming read of `bytes`
- * bytes at device address `buf` (16-byte aligned, bytes a multiple of 16),
- * eight independent 16-byte loads per thread in flight, eight blocks per CU.
- * Timing it on the [n][10] geometry array gives the read bandwidth the cull's
- * main stream can reach on this part.  *sink (device float) is written only
- * when the data sum to a value finite data never sum to, so nothing is
- * stored in practice.  Returns GS_EINVAL on a null or misaligned argument. */
+ * bytes at device address `buf` (16-byte aligned, bytes a multiple of 16) in
+ * the cull's access pattern: one block per 20 KB tile, non-temporal 16-byte
+ * loads all in flight before the first is used.  Timing it on the [n][10]
+ * geometry array gives the read bandwidth the cull's main stream can reach on
+ * this part.  *sink (device float) is written only when the data sum to a
+ * value finite data never sum to, so nothing is stored in practice.  Returns
+ * GS_EINVAL on a null or misaligned argument or more than 2^31 - 1 tiles. */
 int gs_stream_read_probe(const void *buf, size_t bytes, float *sink, void *stream);
 
 /* Number of compute units of the current device (0 when none). */
