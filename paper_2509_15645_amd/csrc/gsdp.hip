@@ -320,6 +320,13 @@ __device__ __forceinline__ float4 ld_once(const float4 *q)
     return make_float4(v.x, v.y, v.z, v.w);
 }
 __device__ __forceinline__ int ld_once(const int *q) { return __builtin_nontemporal_load(q); }
+// non-temporal when NT, an ordinary load otherwise
+template <bool NT, typename T>
+__device__ __forceinline__ T ld_sweep(const T *q)
+{
+    if (NT) return ld_once(q);
+    return *q;
+}
 
 // Loads and stores of one moment element at an element address (the row's
 // base computed once per row on the scalar unit, plus the lane's column);
@@ -557,7 +564,12 @@ struct CullArgs {
 // Seven blocks per CU (the LDS tiles allow seven): the register budget this
 // implies (72) keeps one more tile's loads in flight per CU than the six the
 // kernel's natural register count allows; it spills a few registers of the
-// rarely taken exact path.
+// rarely taken exact path.  NT: the sweep's loads are non-temporal (chosen
+// when the swept arrays exceed the last-level cache; below that, the lines
+// the sweep leaves cached serve the gather and the update that follow).
+// the last-level (Infinity) cache of the part
+constexpr int64_t kLastLevelCacheBytes = 256ll << 20;
+template <bool NT>
 __global__ __launch_bounds__(kCullBlock, 7) void k_cull(CullArgs a)
 {
     __shared__ float4 sG4[kCullTile * 10 / 4];
@@ -601,11 +613,11 @@ __global__ __launch_bounds__(kCullBlock, 7) void k_cull(CullArgs a)
         constexpr int P = kCullTile * 10 / 4 / kCullBlock;
         static_assert(P * kCullBlock * 4 == kCullTile * 10, "tile is a whole number of float4 per thread");
 #pragma unroll
-        for (int k = 0; k < kCullIpt; ++k) lastv[k] = ld_once(a.last + row0 + k * kCullBlock + tid);
+        for (int k = 0; k < kCullIpt; ++k) lastv[k] = ld_sweep<NT>(a.last + row0 + k * kCullBlock + tid);
         __builtin_amdgcn_sched_barrier(0);
         float4 x[P];
 #pragma unroll
-        for (int k = 0; k < P; ++k) x[k] = ld_once(src4 + k * kCullBlock + tid);
+        for (int k = 0; k < P; ++k) x[k] = ld_sweep<NT>(src4 + k * kCullBlock + tid);
         gaps();
 #pragma unroll
         for (int k = 0; k < P; ++k) sG4[k * kCullBlock + tid] = x[k];
@@ -2852,7 +2864,11 @@ int gs_cull(const gs_model *model, const gs_camera *cam, int64_t step, uint32_t 
     if (a.tiles > 0x7fffffff) return GS_EINVAL;
     hipStream_t st = (hipStream_t)stream;
     if (a.tiles > 0) {
-        hipLaunchKernelGGL(k_cull, dim3((unsigned)a.tiles), dim3(kCullBlock), 0, st, a);
+        // geometry and last step: 44 bytes a row
+        if ((int64_t)n * 44 > kLastLevelCacheBytes)
+            hipLaunchKernelGGL(k_cull<true>, dim3((unsigned)a.tiles), dim3(kCullBlock), 0, st, a);
+        else
+            hipLaunchKernelGGL(k_cull<false>, dim3((unsigned)a.tiles), dim3(kCullBlock), 0, st, a);
         int rc1 = launched("gs_cull (tiles)");
         if (rc1) return rc1;
     }
