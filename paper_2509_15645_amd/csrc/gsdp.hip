@@ -960,7 +960,10 @@ __global__ __launch_bounds__(kIdsThreads) void k_tile_ids(IdsArgs a)
 // row kernels: gather / adam / flush
 // ---------------------------------------------------------------------------
 enum RowMode { kGather = 0, kAdam = 1, kFlush = 2, kAdamMax = 3 };
-constexpr int kRowUnroll = 4;
+// rows per wavefront iteration: the gather (fewer loads a row, fewer
+// registers) runs faster with two, the update passes with four
+template <int MODE>
+constexpr int row_unroll() { return MODE == kGather ? 2 : 4; }
 
 struct RowArgs {
     float *gw, *aw;
@@ -1006,6 +1009,7 @@ struct RowArgs {
 template <int MODE, int GST, int AST, int OPT, bool FZ>
 __global__ __launch_bounds__(256) void k_rows(RowArgs a)
 {
+    constexpr int kRU = row_unroll<MODE>();
     const int lane = threadIdx.x & 63;
     // the wavefront index is uniform: keep it (and so every row index and row
     // id below) in scalar registers
@@ -1082,7 +1086,7 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
     const bool quant = (GST != GS_F32) || (AST != GS_F32);
     const u64 s_step = quant ? sm_at(a.sr_seed, (u64)t) : 0ull;
 
-    // Software pipeline over iterations of kRowUnroll rows: while one
+    // Software pipeline over iterations of kRU rows: while one
     // iteration's state is loaded, the next iteration's last steps and the
     // ids of the one after are loaded too, so an iteration waits for one
     // round of memory latency instead of three (ids -> last step -> state).
@@ -1095,21 +1099,21 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
     // row's last step before this iteration's stores is safe.
     int vzero;
     asm volatile("v_mov_b32 %0, 0" : "=v"(vzero));
-    const u32 stride = nw * kRowUnroll;
+    const u32 stride = nw * kRU;
     // positions past nvis index the saturated list (only rows in range are
     // ever read through it)
     const u32 *sat_base = a.sat_ids ? a.sat_ids - nvis : a.ids;
     auto fetch_raw = [&](u32 b, u32 *rid) {
         if (MODE == kFlush) return;
 #pragma unroll
-        for (int u = 0; u < kRowUnroll; ++u) {
+        for (int u = 0; u < kRU; ++u) {
             const u32 i = min(b + u, total - 1u);
             rid[u] = (i < nvis ? a.ids : sat_base)[i + vzero];
         }
     };
     auto decode = [&](u32 b, const u32 *rid, u32 *idv, bool *okv) {
 #pragma unroll
-        for (int u = 0; u < kRowUnroll; ++u) {
+        for (int u = 0; u < kRU; ++u) {
             const u32 r = MODE == kFlush ? b + u : (u32)__builtin_amdgcn_readfirstlane((int)rid[u]);
             okv[u] = b + u < total && r < n;
             idv[u] = okv[u] ? r : 0u;
@@ -1121,44 +1125,44 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
         dd = dd < 0 ? 0 : (dd > dmax ? dmax : dd);
         return okv ? dd : 0;
     };
-    u32 id[kRowUnroll], idn[kRowUnroll];
-    bool ok[kRowUnroll], okn[kRowUnroll];
-    int d[kRowUnroll];
-    u32 rid[kRowUnroll], ridn[kRowUnroll];
-    u32 base = wid * kRowUnroll;
+    u32 id[kRU], idn[kRU];
+    bool ok[kRU], okn[kRU];
+    int d[kRU];
+    u32 rid[kRU], ridn[kRU];
+    u32 base = wid * kRU;
     if (base < total) {
         fetch_raw(base, rid);
         decode(base, rid, id, ok);
-        int lastv[kRowUnroll];
+        int lastv[kRU];
 #pragma unroll
-        for (int u = 0; u < kRowUnroll; ++u) lastv[u] = a.last[id[u] + vzero];
+        for (int u = 0; u < kRU; ++u) lastv[u] = a.last[id[u] + vzero];
         fetch_raw(base + stride, ridn);
 #pragma unroll
-        for (int u = 0; u < kRowUnroll; ++u) d[u] = gap(lastv[u], ok[u]);
+        for (int u = 0; u < kRU; ++u) d[u] = gap(lastv[u], ok[u]);
         decode(base + stride, ridn, idn, okn);
     }
     for (; base < total; base += stride) {
-        int lastn[kRowUnroll];
+        int lastn[kRU];
 #pragma unroll
-        for (int u = 0; u < kRowUnroll; ++u) lastn[u] = a.last[idn[u] + vzero];
-        u32 ridnn[kRowUnroll];
+        for (int u = 0; u < kRU; ++u) lastn[u] = a.last[idn[u] + vzero];
+        u32 ridnn[kRU];
         fetch_raw(base + 2 * stride, ridnn);
         // Raw words first (every row's loads in flight), selected and decoded
         // afterwards.  The G and A halves load into separate registers that
         // start undefined: a write of a default value to a register with a
         // load of the other half still pending would have to wait for it.
-        u32 Gw[kRowUnroll], Gg[kRowUnroll], Aw[kRowUnroll], Ag[kRowUnroll];
-        typename RawT<GST>::T Gm[kRowUnroll], Gv[kRowUnroll];
-        typename RawT<AST>::T Am[kRowUnroll], Av[kRowUnroll];
-        float ms[kRowUnroll], vs[kRowUnroll];
+        u32 Gw[kRU], Gg[kRU], Aw[kRU], Ag[kRU];
+        typename RawT<GST>::T Gm[kRU], Gv[kRU];
+        typename RawT<AST>::T Am[kRU], Av[kRU];
+        float ms[kRU], vs[kRU];
         // Row bases of the weight rows (the fused rows too: their stride is
         // the A row's), computed once and kept for the stores; the compact
         // gradient rows of the iteration are consecutive, at constant offsets
         // from the first.
-        gchar *rA[kRowUnroll], *rG[kRowUnroll];
+        gchar *rA[kRU], *rG[kRU];
         gchar *const cG = srow(a.g_geo, base, 40u), *const cA = srow(a.g_app, base, sAG);
 #pragma unroll
-        for (int u = 0; u < kRowUnroll; ++u) {
+        for (int u = 0; u < kRU; ++u) {
             Gw[u] = undef_v<u32>();
             Gg[u] = undef_v<u32>();
             Aw[u] = undef_v<u32>();
@@ -1224,9 +1228,9 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
         __builtin_amdgcn_sched_barrier(0);
         // values of lanes or rows that loaded nothing are never stored; a
         // saturated row (no compact gradient) takes g = 0
-        float w[kRowUnroll], m[kRowUnroll], v[kRowUnroll], g[kRowUnroll];
+        float w[kRU], m[kRU], v[kRU], g[kRU];
 #pragma unroll
-        for (int u = 0; u < kRowUnroll; ++u) {
+        for (int u = 0; u < kRU; ++u) {
             w[u] = __uint_as_float(isG ? Gw[u] : Aw[u]);
             const bool ldg = (MODE == kAdam || MODE == kAdamMax) && base + u < nvis;
             g[u] = ldg ? __uint_as_float(isG ? Gg[u] : Ag[u]) : 0.0f;
@@ -1243,9 +1247,9 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
         }
         // table entries of each row's gap (issued after the state loads, which
         // do not depend on them)
-        float Wd[kRowUnroll], Mfd[kRowUnroll], Vfd[kRowUnroll];
+        float Wd[kRU], Mfd[kRU], Vfd[kRU];
 #pragma unroll
-        for (int u = 0; u < kRowUnroll; ++u) {
+        for (int u = 0; u < kRU; ++u) {
             Wd[u] = Wrow[d[u]];
             Mfd[u] = Vfd[u] = 0.0f;
             if (MODE == kAdam || MODE == kAdamMax || MODE == kFlush) {
@@ -1255,7 +1259,7 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
             }
         }
 #pragma unroll
-        for (int u = 0; u < kRowUnroll; ++u) {
+        for (int u = 0; u < kRU; ++u) {
             if (!ok[u]) continue;
             const u32 r = id[u];
             if (MODE == kGather) {
@@ -1383,7 +1387,7 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
             if (lane == 0) a.last[r] = t;
         }
 #pragma unroll
-        for (int u = 0; u < kRowUnroll; ++u) {
+        for (int u = 0; u < kRU; ++u) {
             d[u] = gap(lastn[u], okn[u]);
             id[u] = idn[u];
             ok[u] = okn[u];
@@ -1875,7 +1879,7 @@ void launch_rows(const gs_model *m, int grid, hipStream_t st, const RowArgs &a)
 int row_grid(int64_t rows)
 {
     const int cu = cu_count();
-    int64_t want = (rows + 4 * kRowUnroll - 1) / (4 * kRowUnroll);
+    int64_t want = (rows + 4 * row_unroll<kAdam>() - 1) / (4 * row_unroll<kAdam>());
     int64_t cap = (int64_t)(cu > 0 ? cu : 256) * 8;
     if (want > cap) want = cap;
     if (want < 1) want = 1;
