@@ -1876,11 +1876,15 @@ void launch_rows(const gs_model *m, int grid, hipStream_t st, const RowArgs &a)
     else launch_rows_o<MODE, GS_OPT_ADAM>(m, grid, st, a);
 }
 
-int row_grid(int64_t rows)
+constexpr int kRowBlocksGather = 8, kRowBlocksUpdate = 16;
+// blocks of a row launch: one iteration's rows per wavefront at least, at most
+// `per_cu` blocks per CU (the gather runs best at 8, the update passes at 16,
+// where short and long wavefronts even out)
+int row_grid(int64_t rows, int per_cu)
 {
     const int cu = cu_count();
     int64_t want = (rows + 4 * row_unroll<kAdam>() - 1) / (4 * row_unroll<kAdam>());
-    int64_t cap = (int64_t)(cu > 0 ? cu : 256) * 8;
+    int64_t cap = (int64_t)(cu > 0 ? cu : 256) * per_cu;
     if (want > cap) want = cap;
     if (want < 1) want = 1;
     return (int)want;
@@ -2922,7 +2926,7 @@ int gs_gather(const gs_model *model, int64_t step, const uint32_t *ids, const ui
     a.cap = capacity;
     a.out_geo = out_geo;
     a.out_app = out_app;
-    launch_rows<kGather>(model, row_grid(capacity), (hipStream_t)stream, a);
+    launch_rows<kGather>(model, row_grid(capacity, kRowBlocksGather), (hipStream_t)stream, a);
     return launched("gs_gather");
 }
 
@@ -3022,7 +3026,7 @@ int gs_adam_step_deferred(const gs_model *model, int64_t step, const uint32_t *i
         a.fp8list = mx + 4 * nb;
         a.fp8count = mx + 8 * nb;
         a.nb = nb;
-        launch_rows<kAdamMax>(model, row_grid(rows), (hipStream_t)stream, a);
+        launch_rows<kAdamMax>(model, row_grid(rows, kRowBlocksUpdate), (hipStream_t)stream, a);
         int rc1 = launched("gs_adam_step_deferred (fp8 max pass)");
         if (rc1) return rc1;
         // pass 2: grow scales and re-encode those blocks
@@ -3052,7 +3056,7 @@ int gs_adam_step_deferred(const gs_model *model, int64_t step, const uint32_t *i
         rc1 = launched("gs_adam_step_deferred (fp8 rescale)");
         if (rc1) return rc1;
     }
-    launch_rows<kAdam>(model, row_grid(rows), (hipStream_t)stream, a);
+    launch_rows<kAdam>(model, row_grid(rows, kRowBlocksUpdate), (hipStream_t)stream, a);
     return launched("gs_adam_step_deferred");
 }
 
@@ -3068,7 +3072,7 @@ int gs_adam_flush(const gs_model *model, int64_t step, void *stream)
     const LutPtrs L = lut_ptrs(model, step + 1);
     a.Mf = L.Mf;
     a.Vf = L.Vf;
-    launch_rows<kFlush>(model, row_grid(model->n), (hipStream_t)stream, a);
+    launch_rows<kFlush>(model, row_grid(model->n, kRowBlocksUpdate), (hipStream_t)stream, a);
     return launched("gs_adam_flush");
 }
 
