@@ -164,6 +164,10 @@ def run_batched(args):
     for sidx, n in enumerate(sizes):
         box, half = gi.aerial_box_for(n)
         g_, a_ = gi.device_scene(n, box, 1000 + sidx, dev)
+        if args.order == "morton":
+            perm = morton_order(g_[:, :3], box)
+            g_, a_ = g_[perm], a_[perm]
+            del perm
         pad = (-n) % gsdp.MULTI_ALIGN
         if pad:
             gp = torch.full((pad, 10), float("nan"), device=dev)
@@ -254,6 +258,7 @@ def run_batched(args):
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32 math, bf16 moments", "data": "synthetic",
         "config": {"workload": "batched16", "scenes": len(sizes), "scene_sizes": sizes, "n_gaussians": n_real,
+                   "row_order": args.order,
                    "rows_padded": N, "cameras_per_scene": C, "union_per_step": U, "camera_entries_per_step": CC,
                    "geo_state": args.geo_state or "bf16", "app_state": "bf16",
                    "autotune_ms": times, "variant": int(multi.c.variant), "hipgraph": True},

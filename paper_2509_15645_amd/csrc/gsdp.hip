@@ -487,6 +487,75 @@ __device__ __forceinline__ int classify(const float *g, float wd, const CamK &c,
     return classify_cam(g, classify_pre(g, wd, b), c, b);
 }
 
+// Bounds of a group of rows (a wavefront's) that classify_cam evaluates:
+// the box of their stored centres and the largest mu, position drift and
+// sigma_max^2 of their RowPre.  wave_sure_out(box, camera) is true only when
+// classify_cam returns 0 for every row of the group, so every one is culled.
+// It bounds the quantities classify_cam computes per row, over the group,
+// with twice its rounding margins:
+//   camera-space x, y, z over the box: the centre transform's range, each
+//     coordinate's term at the end of the box that minimises / maximises it;
+//   1/z between 1/zhi and 1/zlo of the group, so x/z is bounded at the
+//     group's z ends by the sign of x (x/z rises with x and, for x >= 0,
+//     falls with z; for x < 0 it rises with z);
+//   the footprint radius at the group's smallest z and largest sigma.
+// A group that may reach z <= 0 is not decided, as classify_cam leaves such
+// a row to the exact test.
+struct WaveBox {
+    float lo[3], hi[3];
+    float mu, dp, sig2;
+};
+
+__device__ __forceinline__ bool wave_sure_out(const WaveBox &w, const CamK &c, const BandK &b)
+{
+    float rlo[3], rhi[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        float lo = c.T[i], hi = c.T[i];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const float e0 = c.R[3 * i + j] * w.lo[j], e1 = c.R[3 * i + j] * w.hi[j];
+            lo += fminf(e0, e1);
+            hi += fmaxf(e0, e1);
+        }
+        const float rs = i == 0 ? b.rs0 : (i == 1 ? b.rs1 : b.rs2);
+        const float sx = fmaf(rs, w.mu, fabsf(c.T[i]));
+        const float dx = rs * w.dp;
+        const float ex = fmaf(3e-6f, sx + dx, dx) + 2e-6f;
+        rlo[i] = lo - ex;
+        rhi[i] = hi + ex;
+    }
+    if ((rhi[2] <= c.zn) | (rlo[2] >= c.zf)) return true;
+    if (!(rlo[2] > 0.0f)) return false;
+    // 1/z of every row lies in [izh, izl] (hardware reciprocal, widened)
+    const float izl = __builtin_amdgcn_rcpf(rlo[2]) * 1.00001f, izh = __builtin_amdgcn_rcpf(rhi[2]) * 0.99999f;
+    const float S = ((b.jf2 * izl) * izl) * w.sig2;
+    const float lam = fmaf(1.002f, S, 0.96f);
+    const float rup = fmaf(3.004f, __builtin_amdgcn_sqrtf(lam) * 1.00001f, 1.001f);
+    const float qxhi = rhi[0] >= 0.0f ? rhi[0] * izl : rhi[0] * izh;
+    const float qxlo = rlo[0] < 0.0f ? rlo[0] * izl : rlo[0] * izh;
+    const float qyhi = rhi[1] >= 0.0f ? rhi[1] * izl : rhi[1] * izh;
+    const float qylo = rlo[1] < 0.0f ? rlo[1] * izl : rlo[1] * izh;
+    const float eu = fmaf(2e-5f, fmaf(c.fx, fmaxf(fabsf(qxlo), fabsf(qxhi)), fabsf(c.cx)), 2e-3f);
+    const float ev = fmaf(2e-5f, fmaf(c.fy, fmaxf(fabsf(qylo), fabsf(qyhi)), fabsf(c.cy)), 2e-3f);
+    const float ulo = fmaf(c.fx, qxlo, c.cx) - eu, uhi = fmaf(c.fx, qxhi, c.cx) + eu;
+    const float vlo = fmaf(c.fy, qylo, c.cy) - ev, vhi = fmaf(c.fy, qyhi, c.cy) + ev;
+    return (uhi + rup <= 0.0f) | (ulo - rup >= c.W) | (vhi + rup <= 0.0f) | (vlo - rup >= c.H);
+}
+
+__device__ __forceinline__ float wave_min(float x)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) x = fminf(x, __shfl_xor(x, o));
+    return x;
+}
+__device__ __forceinline__ float wave_max(float x)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) x = fmaxf(x, __shfl_xor(x, o));
+    return x;
+}
+
 __device__ __forceinline__ u32 lane_rank(u64 mask)
 {
     return __builtin_amdgcn_mbcnt_hi((u32)(mask >> 32), __builtin_amdgcn_mbcnt_lo((u32)mask, 0u));
@@ -1989,22 +2058,47 @@ __global__ __launch_bounds__(BLOCK) void k_cull_multi(MultiArgs a)
 #pragma unroll
     for (int k = 0; k < IPT; ++k) {
         const int r = k * BLOCK + tid;
+        const bool valid = r < rows && in_scene;
         u32 mk = 0;
-        if (r < rows && in_scene) {
-            float g[10];
-            const float2 *p2 = reinterpret_cast<const float2 *>(sG + r * 10);
+        // every lane reads a row (past the tile's rows: stale LDS, never used)
+        float g[10];
+        const float2 *p2 = reinterpret_cast<const float2 *>(sG + r * 10);
 #pragma unroll
-            for (int j = 0; j < 5; ++j) {
-                const float2 q = p2[j];
-                g[2 * j] = q.x;
-                g[2 * j + 1] = q.y;
+        for (int j = 0; j < 5; ++j) {
+            const float2 q = p2[j];
+            g[2 * j] = q.x;
+            g[2 * j + 1] = q.y;
+        }
+        int d = t - 1 - lastv[k];
+        d = d < 0 ? 0 : (d > dmax ? dmax : d);
+        const float wd = d > 0 ? Wrow[d] : 0.0f;
+        const RowPre pre = classify_pre(g, wd, cams[0].band);
+        // The wavefront's box, for the band classifier only and only when it
+        // decides every row of the wavefront (none undecidable).  With rows
+        // in spatial order a camera's frustum misses most wavefronts' boxes,
+        // and the per-row classification is skipped for that camera.
+        // Lane c tests camera c against the box (C <= 32); the ballot is the
+        // set of cameras that cull the whole wavefront.
+        const bool box = a.mode == 1 && __ballot(valid && pre.ok == 0) == 0ull && __ballot(valid) != 0ull;
+        u32 out_mask = 0u;
+        if (box) {
+            WaveBox wb;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                wb.lo[i] = wave_min(valid ? g[i] : __builtin_huge_valf());
+                wb.hi[i] = wave_max(valid ? g[i] : -__builtin_huge_valf());
             }
-            int d = t - 1 - lastv[k];
-            d = d < 0 ? 0 : (d > dmax ? dmax : d);
-            const float wd = d > 0 ? Wrow[d] : 0.0f;
+            wb.mu = wave_max(valid ? pre.mu : 0.0f);
+            wb.dp = wave_max(valid ? pre.dp : 0.0f);
+            wb.sig2 = wave_max(valid ? pre.sig2 : 0.0f);
+            bool o = false;
+            if (lane < C) o = wave_sure_out(wb, cams[lane].cam, cams[lane].band);
+            out_mask = (u32)__ballot(o);
+        }
+        if (valid) {
             u32 undecided = 0;
-            const RowPre pre = classify_pre(g, wd, cams[0].band);
             for (int c = 0; c < C; ++c) {
+                if ((out_mask >> c) & 1u) continue;
                 const int cls = a.mode == 1 ? classify_cam(g, pre, cams[c].cam, cams[c].band) : 2;
                 mk |= (u32)(cls == 1) << c;
                 undecided |= (u32)(cls == 2) << c;

@@ -27,18 +27,35 @@ def bits(a):
     return np.ascontiguousarray(a, np.float32).view(np.uint32)
 
 
-def _batch(sizes, cams_per_scene, n_sets, seed=0):
+def _morton(pos):
+    """Permutation sorting rows by the 30-bit Morton code of their position
+    (10 bits per axis over the rows' bounding box)."""
+    lo, hi = pos.min(0), pos.max(0)
+    q = ((pos - lo) / np.maximum(hi - lo, 1e-30) * 1023).astype(np.int64).clip(0, 1023)
+    code = np.zeros(pos.shape[0], np.int64)
+    for b in range(10):
+        for a in range(3):
+            code |= ((q[:, a] >> b) & 1) << (3 * b + a)
+    return np.argsort(code, kind="stable")
+
+
+def _batch(sizes, cams_per_scene, n_sets, seed=0, spatial=False):
     """Scenes of uneven size concatenated on 1024-row boundaries (padding rows
-    have NaN positions and are never visible)."""
+    have NaN positions and are never visible); spatial: each scene's rows
+    sorted by the Morton code of their position."""
     geos, apps, row0 = [], [], [0]
     sets = [[] for _ in range(n_sets)]
     for s, n in enumerate(sizes):
         sc = gi.make_scene(n, seed=seed + s)
+        geo_s, app_s = sc.geo, sc.app
+        if spatial:
+            perm = _morton(geo_s[:, :3].astype(np.float64))
+            geo_s, app_s = geo_s[perm], app_s[perm]
         pad = (-n) % 1024
-        g = np.concatenate([sc.geo, np.full((pad, 10), np.nan, np.float32)])
+        g = np.concatenate([geo_s, np.full((pad, 10), np.nan, np.float32)])
         g[n:, 6] = 1.0
         geos.append(g)
-        apps.append(np.concatenate([sc.app, np.zeros((pad, 49), np.float32)]))
+        apps.append(np.concatenate([app_s, np.zeros((pad, 49), np.float32)]))
         row0.append(row0[-1] + n + pad)
         cams = gi.orbit_cameras(cams_per_scene * n_sets, seed=seed + 100 * s)
         for k in range(n_sets):
@@ -58,9 +75,13 @@ def _compare_lists(multi, ref, tag):
     return u, cc
 
 
-def test_batched_scenes_cameras_vs_oracle(g):
+@pytest.mark.parametrize("spatial", [False, True], ids=["generated", "morton"])
+def test_batched_scenes_cameras_vs_oracle(g, spatial):
+    """With rows in spatial order most wavefronts lie outside most cameras'
+    frusta, so the wavefront box test decides them; the lists, sums and
+    states must not change."""
     sizes, C, n_sets, steps = [30_000, 100_000, 7_000, 60_000], 8, 2, 3
-    geo, app, row0, sets = _batch(sizes, C, n_sets)
+    geo, app, row0, sets = _batch(sizes, C, n_sets, spatial=spatial)
     lg, la = gi.lr_columns()
     model = g.Model(geo, app, lg, la, max_steps=16, cull_mode=1, app_state="bf16", sr_seed=5)
     o4 = orc.DeferredF32(geo, app, lg, la, app_state="bf16", sr_seed=5)
