@@ -12,7 +12,8 @@
 // Kernels
 //   k_cull, k_tile_reduce, k_tile_ids
 //               one block per 512-row tile stages the geometry through LDS
-//               with 128-bit loads, restores deferred rows (band classifier
+//               with 128-bit loads (non-temporal when the swept arrays exceed
+//               the last-level cache), restores deferred rows (band classifier
 //               first), culls and stores wave ballots and tile counts; group
 //               sums of 64 tiles (skipped for small models); one block per
 //               group writes the tile prefixes and the ids in order.
@@ -26,7 +27,8 @@
 //                 max     FP8 first pass (block maxima of new moments)
 //   k_fp8_rescale, k_dense_geo, k_scatter
 //   k_cull_multi, k_multi_reduce, k_multi_offsets, k_multi_ids, k_grad_sum
-//               batched form
+//               batched form; a wavefront's box of rows is tested against
+//               all cameras at once (one per lane) before the per-row tests
 //   k_dens_plan, k_dens_scan, k_dens_apply                densification
 //   k_synth     synthetic gradients (harness only)
 #include <hip/hip_runtime.h>
