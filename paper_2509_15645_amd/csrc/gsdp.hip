@@ -2280,8 +2280,8 @@ struct GradSumArgs {
     float *out_geo, *out_app;        // [cap_union][10], [cap_union][adim]
 };
 
-constexpr int kGsRows = 4;           // rows of a wavefront summed together
-constexpr int kGsSlots = 8;          // camera entries per row loaded up front
+constexpr int kGsRows = 8;           // rows of a wavefront summed together
+constexpr int kGsSlots = 4;          // camera entries per row loaded up front
 
 __device__ __forceinline__ u32 lower_bound_u32(const u32 *a, u32 n, u32 key)
 {
