@@ -39,14 +39,20 @@ def _morton(pos):
     return np.argsort(code, kind="stable")
 
 
-def _batch(sizes, cams_per_scene, n_sets, seed=0, spatial=False):
+def _batch(sizes, cams_per_scene, n_sets, seed=0, spatial=False, aerial=False):
     """Scenes of uneven size concatenated on 1024-row boundaries (padding rows
     have NaN positions and are never visible); spatial: each scene's rows
-    sorted by the Morton code of their position."""
+    sorted by the Morton code of their position; aerial: the aerial box of
+    the scene's size with nadir and oblique cameras above it (else a cube
+    with orbiting cameras)."""
     geos, apps, row0 = [], [], [0]
     sets = [[] for _ in range(n_sets)]
     for s, n in enumerate(sizes):
-        sc = gi.make_scene(n, seed=seed + s)
+        if aerial:
+            box, half = gi.aerial_box_for(n)
+            sc = gi.make_scene(n, seed=seed + s, box=box)
+        else:
+            sc = gi.make_scene(n, seed=seed + s)
         geo_s, app_s = sc.geo, sc.app
         if spatial:
             perm = _morton(geo_s[:, :3].astype(np.float64))
@@ -57,7 +63,10 @@ def _batch(sizes, cams_per_scene, n_sets, seed=0, spatial=False):
         geos.append(g)
         apps.append(np.concatenate([app_s, np.zeros((pad, 49), np.float32)]))
         row0.append(row0[-1] + n + pad)
-        cams = gi.orbit_cameras(cams_per_scene * n_sets, seed=seed + 100 * s)
+        if aerial:
+            cams = gi.aerial_cameras(cams_per_scene * n_sets, half, half, seed=seed + 100 * s)
+        else:
+            cams = gi.orbit_cameras(cams_per_scene * n_sets, seed=seed + 100 * s)
         for k in range(n_sets):
             sets[k].append(cams[k * cams_per_scene:(k + 1) * cams_per_scene])
     return np.concatenate(geos), np.concatenate(apps), np.array(row0), sets
@@ -75,13 +84,17 @@ def _compare_lists(multi, ref, tag):
     return u, cc
 
 
-@pytest.mark.parametrize("spatial", [False, True], ids=["generated", "morton"])
-def test_batched_scenes_cameras_vs_oracle(g, spatial):
+@pytest.mark.parametrize("kind", ["generated", "morton", "aerial-morton"])
+def test_batched_scenes_cameras_vs_oracle(g, kind):
     """With rows in spatial order most wavefronts lie outside most cameras'
     frusta, so the wavefront box test decides them; the lists, sums and
-    states must not change."""
-    sizes, C, n_sets, steps = [30_000, 100_000, 7_000, 60_000], 8, 2, 3
-    geo, app, row0, sets = _batch(sizes, C, n_sets, spatial=spatial)
+    states must not change.  The aerial case uses all 32 camera slots."""
+    if kind == "aerial-morton":
+        sizes, C = [40_000, 120_000, 25_000], 32
+    else:
+        sizes, C = [30_000, 100_000, 7_000, 60_000], 8
+    n_sets, steps = 2, 3
+    geo, app, row0, sets = _batch(sizes, C, n_sets, spatial=kind != "generated", aerial=kind.startswith("aerial"))
     lg, la = gi.lr_columns()
     model = g.Model(geo, app, lg, la, max_steps=16, cull_mode=1, app_state="bf16", sr_seed=5)
     o4 = orc.DeferredF32(geo, app, lg, la, app_state="bf16", sr_seed=5)
