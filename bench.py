@@ -2,15 +2,19 @@
 
 One step = gs_cull (cull + ordered compaction of every Gaussian) ->
 gs_gather (restored visible rows) -> gs_adam_step_deferred (fused scatter +
-deferred Adam), on the 4M-Gaussian aerial workload (1000x1000x100 box, 1600
-nadir/oblique cameras 1152x864 f=1100, one camera per step), FP32 state.
+deferred Adam), on the 40M-Gaussian aerial workload (3000x3000x200 box, 4000
+nadir/oblique cameras 1152x864 f=1100, one camera per step), FP32 moment
+state; the same steps with BF16 moment state on the same scene are reported
+beside it.
 Synthetic gradients are generated on the device before the timed region (a
 pool of compact gradient buffers, one per step mod pool size) and stand in
 for the renderer's backward pass.
 
 Prints one JSON line: value = Gaussians/s = N / (ms per step), with a
-roofline object for the dominant kernel (HIP events on the launch stream,
-algorithmic bytes per launch) and the CPU oracle timed on a row sample.
+roofline object for the dominant call (HIP events on the launch stream,
+algorithmic bytes per launch), the whole step's algorithmic bytes over its
+median time, step-time percentiles, and the CPU oracle timed on a row sample
+with all host cores and with one thread.
 """
 from __future__ import annotations
 
@@ -26,6 +30,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+METRIC = "train-step Gaussians/s (cull+gather+Adam), HBM % of peak, fp32 vs bf16-state"
 
 
 def parse():
@@ -33,7 +38,7 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=100)
     p.add_argument("--warmup", type=int, default=10)
-    p.add_argument("--workload", default="aerial4m",
+    p.add_argument("--workload", default="aerial40m",
                    choices=["small", "aerial4m", "aerial18m", "aerial40m", "batched16"])
     p.add_argument("--scenes", type=int, default=16, help="batched16: number of scenes")
     p.add_argument("--cams", type=int, default=32, help="batched16: cameras per scene per step")
@@ -45,6 +50,8 @@ def parse():
     p.add_argument("--max-defer", type=int, default=0)
     p.add_argument("--cull-mode", type=int, default=1)
     p.add_argument("--state", default="f32", choices=["f32", "bf16", "fp8"], help="Adam moment storage (both groups)")
+    p.add_argument("--compare-state", default="bf16", choices=["", "f32", "bf16", "fp8"],
+                   help="a second moment storage timed on the same scene and reported beside the first")
     p.add_argument("--geo-state", default=None, choices=["f32", "bf16", "fp8"])
     p.add_argument("--graph", action="store_true",
                    help="also time the step captured in a hipGraph (camera table + device step counter)")
@@ -65,8 +72,9 @@ def parse():
 def cpu_baseline(w, geo_all, app_all, sample, steps, lg, la):
     """The oracle as it stands, on a seeded row sample of the same workload:
     FP32 cull of the sample's geometry + ids + synthetic grads + dense FP64
-    Adam on every sampled row (Eq. 1), per step.  Gaussians/s = sample / t.
-    geo_all / app_all: host arrays or device tensors of the initial scene."""
+    Adam on every sampled row (Eq. 1), per step, with all host cores and with
+    one thread.  Gaussians/s = sample / median step time (the first step is
+    not counted); p10 / p90 of the step times beside it."""
     from oracle import oracle as orc
     import gs_inputs as gi
     rng = np.random.default_rng(123)
@@ -78,20 +86,35 @@ def cpu_baseline(w, geo_all, app_all, sample, steps, lg, la):
         import torch
         return x.index_select(0, torch.from_numpy(rows).to(x.device)).cpu().numpy()
     geo, app = take(geo_all), take(app_all)
-    dense = orc.DenseAdamF64(geo, app, lg, la)
-    times = []
-    for t in range(1, steps + 1):
-        t0 = time.perf_counter()
-        keep = orc.cull(dense.w[0].astype(np.float32), w.camera_for_step(t))
-        valid = orc.compact(keep)
-        gg, ga = gi.step_grads(0, t, rows[valid])
-        dense.step(t, valid, gg, ga)
-        times.append(time.perf_counter() - t0)
-    med = float(np.median(times[1:] if len(times) > 1 else times))
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+
+    def leg(nsteps):
+        dense = orc.DenseAdamF64(geo, app, lg, la)
+        times = []
+        for t in range(1, nsteps + 1):
+            t0 = time.perf_counter()
+            keep = orc.cull(dense.w[0].astype(np.float32), w.camera_for_step(t))
+            valid = orc.compact(keep)
+            gg, ga = gi.step_grads(0, t, rows[valid])
+            dense.step(t, valid, gg, ga)
+            times.append(time.perf_counter() - t0)
+        ts = np.array(times[1:] if len(times) > 1 else times)
+        med = float(np.median(ts))
+        return med, float(np.percentile(ts, 10)), float(np.percentile(ts, 90))
+
+    cores = orc.set_threads(0)
+    med, p10, p90 = leg(steps)
+    orc.set_threads(1)
+    med1, p10_1, p90_1 = leg(max(3, steps // 2))
+    orc.set_threads(cores)
+    model, numa = host_cpu()
+    what = (f"{rows.shape[0]} seeded rows of the {w.n}-Gaussian workload: FP32 cull + ids + synthetic grads + "
+            f"dense FP64 Adam per step")
     return {"value": rows.shape[0] / med, "unit": "Gaussians/s", "cores": cores, "kind": "oracle",
-            "sample": f"{rows.shape[0]} seeded rows of the {w.n}-Gaussian workload, {steps} steps "
-                      f"(median step {med * 1e3:.1f} ms): FP32 cull + ids + synthetic grads + dense FP64 Adam"}
+            "sample": f"{what}; {steps} steps, median {med * 1e3:.1f} ms (p10 {p10 * 1e3:.1f}, p90 {p90 * 1e3:.1f})",
+            "step_ms": {"p10": p10 * 1e3, "p50": med * 1e3, "p90": p90 * 1e3},
+            "single_thread": {"value": rows.shape[0] / med1, "unit": "Gaussians/s", "cores": 1,
+                              "step_ms": {"p10": p10_1 * 1e3, "p50": med1 * 1e3, "p90": p90_1 * 1e3}},
+            "cpu_model": model, "numa_nodes": numa}
 
 
 # the launches behind each timed call (the cull is three launches: tile cull,
@@ -271,64 +294,64 @@ def run_batched(args):
     print(json.dumps(out), flush=True)
 
 
-def config_key(args, workload):
+def config_key(args, workload, state=None):
     """Names the launch configuration a counter summary was taken with."""
-    return (f"{workload}/{args.state}/{args.geo_state or args.state}/{args.layout}/cull{args.cull_mode}"
+    st = state or args.state
+    return (f"{workload}/{st}/{args.geo_state or st}/{args.layout}/cull{args.cull_mode}"
             f"/geo{args.geo_mode}/K{args.max_defer}/tilt{args.tilt.replace(',', '-')}/{args.order}")
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is a design note only",
-                          "n_gpus": args.gpus}))
-        sys.exit(2)
-    if args.copy_probe:
-        import torch
-        n = args.copy_probe * (1 << 20) // 4
-        a = torch.ones(n, dtype=torch.float32, device="cuda")
-        b = torch.empty_like(a)
-        for _ in range(5):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_probe_mib": args.copy_probe, "launches": 5}))
-        return
-    if args.workload == "batched16":
-        run_batched(args)
-        return
+def host_cpu():
+    """CPU model name and NUMA node count of this host."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        nodes = len([d for d in os.listdir("/sys/devices/system/node") if d.startswith("node") and d[4:].isdigit()])
+    except OSError:
+        nodes = None
+    return model, nodes
+
+
+def step_bytes(n, M, R, geo_state, app_state, geo_mode):
+    """Algorithmic bytes of one step per call (sg / sa: bytes per stored moment
+    of G / A): cull 44 per Gaussian + 20 sg per restored row + 4 per visible id;
+    gather id + last step + G w, m, v + A w, m, v + the 236-byte output row;
+    Adam id + last step read and write + per column w, g read, w written and
+    m, v read and written."""
+    msz = {"f32": 4, "bf16": 2, "fp8": 1}
+    sg, sa = msz[geo_state], msz[app_state]
+    gcols = 0 if geo_mode else 10                       # G columns handled by the sparse kernels
+    cull = 44.0 * n + 20.0 * sg * R + 4.0 * M
+    gather = M * (4 + 4 + 8 * 10 + 2 * sg * gcols + 8 * 49 + 2 * sa * 49)
+    adam = M * (4 + 4 + 4 + gcols * (12 + 4 * sg) + 49 * (12 + 4 * sa))
+    if geo_mode:                                        # dense G Adam over every row
+        adam += n * 10 * (8 + 4 * sg) + n / 8.0 + M * 40
+    return {"cull": cull, "gather": gather, "adam": adam}
+
+
+def run_single(args, w, geo0, app0, state, tilt, on_dev):
+    """Times K steps of one moment-state configuration; returns its result
+    record (the scene tensors are not modified)."""
     import torch
 
     import gs_inputs as gi
     from paper_2509_15645_amd import gsdp
-
-    torch.cuda.set_device(0)
-    tilt = tuple(float(x) for x in args.tilt.split(","))
-    w = gi.workload(args.workload, n=args.n, tilt_deg=tilt)
-    t_setup = time.perf_counter()
     dev = torch.device("cuda")
-    on_dev = args.device_scene if args.device_scene is not None else int(w.n > 8_000_000)
-    if on_dev:
-        geo0, app0 = gi.device_scene(w.n, w.scene_box, 0, dev)
-    else:
-        sc = gi.make_scene(w.n, seed=0, box=w.scene_box)
-        geo0, app0 = sc.geo, sc.app
-    if args.order == "morton":
-        import torch as _t
-        g_t = _t.as_tensor(geo0)
-        perm = morton_order(g_t[:, :3], w.scene_box)
-        geo0 = g_t[perm].contiguous()
-        app0 = _t.as_tensor(app0)[perm.to(_t.as_tensor(app0).device)].contiguous()
-        if not on_dev:
-            geo0, app0 = geo0.numpy(), app0.numpy()
+    t_setup = time.perf_counter()
     lg, la = gi.lr_columns()
     total_steps = args.warmup + args.steps
-    geo_state = args.geo_state or args.state
-    model = gsdp.Model(geo0, app0, lg, la, max_steps=2 * total_steps + 8, max_defer=args.max_defer,
+    geo_state = args.geo_state or state
+    geo_in = geo0.clone() if torch.is_tensor(geo0) else geo0
+    model = gsdp.Model(geo_in, app0, lg, la, max_steps=2 * total_steps + 8, max_defer=args.max_defer,
                        cull_mode=args.cull_mode, app_layout=args.layout, geo_state=geo_state,
-                       app_state=args.state, geo_mode=args.geo_mode, sr_seed=9)
-    if on_dev:
-        geo0 = model.geo_w.clone()                  # the oracle sample reads the initial scene
-        app0 = app0 if app0.data_ptr() != model.app_w.data_ptr() else model.app_w.clone()
+                       app_state=state, geo_mode=args.geo_mode, sr_seed=9)
+    del geo_in
     n = w.n
     cap = max(1, n // 4)
     ids = torch.zeros(cap, dtype=torch.int32, device=dev)
@@ -346,7 +369,6 @@ def main():
     cams = [gsdp.camera_struct(w.camera_for_step(t)) for t in range(1, total_steps + 1)]
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t_setup
-
     stream = torch.cuda.current_stream()
 
     def step(t, ev=None):
@@ -411,26 +433,98 @@ def main():
     k_ms = np.array([[e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2]), e[2].elapsed_time(e[3])]
                      for e in evs])
     cull_ms, gather_ms, adam_ms = k_ms.mean(0)
+    step_ev = k_ms.sum(1)
     vis_total = h1["vis_accum"] - h0["vis_accum"]
     rest_total = h1["restored_accum"] - h0["restored_accum"]
     M = vis_total / args.steps
     R = rest_total / args.steps
     f = M / n
-    # algorithmic bytes per launch (sg / sa: bytes per stored moment of G / A)
-    msz = {"f32": 4, "bf16": 2, "fp8": 1}
-    sg, sa = msz[geo_state], msz[args.state]
-    gcols = 0 if args.geo_mode else 10                  # G columns handled by the sparse kernels
-    cull_bytes = 44.0 * n + 20.0 * sg * R + 4.0 * M
-    gather_bytes = M * (4 + 4 + 8 * 10 + 2 * sg * gcols + 8 * 49 + 2 * sa * 49)
-    adam_bytes = M * (4 + 4 + 4 + gcols * (12 + 4 * sg) + 49 * (12 + 4 * sa))
-    if args.geo_mode:                                   # dense G Adam over every row
-        adam_bytes += n * 10 * (8 + 4 * sg) + n / 8.0 + M * 40
-    kernels = {"cull": (cull_ms, cull_bytes), "gather": (gather_ms, gather_bytes), "adam": (adam_ms, adam_bytes)}
+    by = step_bytes(n, M, R, geo_state, state, args.geo_mode)
+    kernels = {k: (float(ms), by[k]) for k, ms in (("cull", cull_ms), ("gather", gather_ms), ("adam", adam_ms))}
     dom = max(kernels, key=lambda k: kernels[k][0])
+    dms, dbytes = kernels[dom]
+    achieved = dbytes / (dms * 1e-3) / 1e9
+    tot_bytes = sum(by.values())
+    p10, p50, p90 = (float(x) for x in np.percentile(step_ev, [10, 50, 90]))
+    step_gbs = tot_bytes / (p50 * 1e-3) / 1e9
+    rec = {
+        "value": n / (ms_step * 1e-3), "ms_per_step": ms_step,
+        "step_ms": {"p10": p10, "p50": p50, "p90": p90, "from": "HIP events around the three calls of each step"},
+        "value_p50": n / (p50 * 1e-3),
+        "config": {"workload": w.name, "n_gaussians": n, "scene_drawn_on": "device" if on_dev else "host",
+                   "row_order": args.order, "cameras": len(w.cameras),
+                   "image": f"{w.cameras[0].width}x{w.cameras[0].height}", "oblique_tilt_deg": list(tilt),
+                   "visible_fraction": f, "visible_per_step": M, "restored_per_step": R,
+                   "state": state, "geo_state": geo_state, "app_layout": args.layout,
+                   "max_defer": args.max_defer, "cull_mode": args.cull_mode, "geo_mode": args.geo_mode},
+        "kernels_ms": {k: v[0] for k, v in kernels.items()},
+        "graph_ms_per_step": graph_ms,
+        "kernels_gbs": {k: v[1] / (v[0] * 1e-3) / 1e9 for k, v in kernels.items()},
+        "roofline": {"kernel": dom, "launches": KERNEL_SYMBOLS[dom], "bound": "hbm", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(dom, config_key(args, w.name, state)),
+                     "traffic_from": "profiles/hbm_traffic.txt (rocprofv3 FETCH_SIZE, WRITE_SIZE), "
+                                     "used only while the library sources match its digest",
+                     "algorithmic_bytes": dbytes},
+        "step_roofline": {"bound": "hbm", "algorithmic_bytes": tot_bytes, "ms": p50, "achieved": step_gbs,
+                          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": step_gbs / HBM_PEAK_GBS,
+                          "what": "all three calls' algorithmic bytes over the median step time"},
+        "setup_s": setup_s,
+    }
+    del model, pool, out_g, out_a
+    torch.cuda.empty_cache()
+    return rec
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is a design note only",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    if args.copy_probe:
+        import torch
+        n = args.copy_probe * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_mib": args.copy_probe, "launches": 5}))
+        return
+    if args.workload == "batched16":
+        run_batched(args)
+        return
+    import torch
+
+    import gs_inputs as gi
+    from paper_2509_15645_amd import gsdp
+
+    torch.cuda.set_device(0)
+    tilt = tuple(float(x) for x in args.tilt.split(","))
+    w = gi.workload(args.workload, n=args.n, tilt_deg=tilt)
+    dev = torch.device("cuda")
+    on_dev = args.device_scene if args.device_scene is not None else int(w.n > 8_000_000)
+    if on_dev:
+        geo0, app0 = gi.device_scene(w.n, w.scene_box, 0, dev)
+    else:
+        sc = gi.make_scene(w.n, seed=0, box=w.scene_box)
+        geo0, app0 = sc.geo, sc.app
+    if args.order == "morton":
+        g_t = torch.as_tensor(geo0)
+        perm = morton_order(g_t[:, :3], w.scene_box)
+        geo0 = g_t[perm].contiguous()
+        app0 = torch.as_tensor(app0)[perm.to(torch.as_tensor(app0).device)].contiguous()
+        if not on_dev:
+            geo0, app0 = geo0.numpy(), app0.numpy()
+    main_rec = run_single(args, w, geo0, app0, args.state, tilt, on_dev)
+    second = None
+    if args.compare_state and args.compare_state != args.state:
+        second = run_single(args, w, geo0, app0, args.compare_state, tilt, on_dev)
     # achievable read bandwidth of the cull's main stream: a plain streaming
     # read of the [n][10] geometry array, timed the same way
-    flat = model.geo_w.view(-1)
-    flat = flat[: (flat.numel() // 4) * 4]
+    gflat = torch.as_tensor(geo0).to(dev).reshape(-1)
+    flat = gflat[: (gflat.numel() // 4) * 4]
     sink = torch.zeros(1, dtype=torch.float32, device="cuda")
     pe = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     gsdp.gs_stream_read_probe(flat, sink)
@@ -440,34 +534,23 @@ def main():
     pe[1].record()
     torch.cuda.synchronize()
     probe_gbs = flat.numel() * 4 * 5 / (pe[0].elapsed_time(pe[1]) * 1e-3) / 1e9
-    dms, dbytes = kernels[dom]
-    achieved = dbytes / (dms * 1e-3) / 1e9
     out = {
-        "metric": f"train-step Gaussians/s (cull+gather+Adam), {args.state.upper()} moment state",
-        "value": n / (ms_step * 1e-3),
+        "metric": METRIC,
+        "value": main_rec["value"],
         "unit": "Gaussians/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": main_rec["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
-        "config": {"workload": w.name, "n_gaussians": n, "scene_drawn_on": "device" if on_dev else "host",
-                   "row_order": args.order, "cameras": len(w.cameras),
-                   "image": f"{w.cameras[0].width}x{w.cameras[0].height}", "oblique_tilt_deg": list(tilt),
-                   "visible_fraction": f, "visible_per_step": M, "restored_per_step": R,
-                   "state": args.state, "geo_state": geo_state, "app_layout": args.layout,
-                   "max_defer": args.max_defer, "cull_mode": args.cull_mode, "geo_mode": args.geo_mode},
-        "kernels_ms": {"cull": cull_ms, "gather": gather_ms, "adam": adam_ms},
-        "graph_ms_per_step": graph_ms,
-        "kernels_gbs": {k: v[1] / (v[0] * 1e-3) / 1e9 for k, v in kernels.items()},
-        "roofline": {"kernel": dom, "launches": KERNEL_SYMBOLS[dom], "bound": "hbm", "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(dom, config_key(args, w.name)), "algorithmic_bytes": dbytes},
-        "stream_probe": {"what": "streaming read of the [n][10] geometry array", "bytes": flat.numel() * 4,
-                         "gbs": probe_gbs, "frac_of_peak": probe_gbs / HBM_PEAK_GBS},
-        "setup_s": setup_s,
     }
+    out.update({k: v for k, v in main_rec.items() if k not in ("value", "ms_per_step")})
+    if second is not None:
+        out[f"{args.compare_state}_state"] = second
+    out["stream_probe"] = {"what": "streaming read of the [n][10] geometry array", "bytes": flat.numel() * 4,
+                           "gbs": probe_gbs, "frac_of_peak": probe_gbs / HBM_PEAK_GBS}
+    del gflat, flat
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, geo0, app0, args.cpu_sample, args.cpu_steps, lg, la)
+        out["cpu_baseline"] = cpu_baseline(w, geo0, app0, args.cpu_sample, args.cpu_steps, *gi.lr_columns())
     print(json.dumps(out), flush=True)
 
 

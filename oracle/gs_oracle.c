@@ -29,6 +29,9 @@
 #include <stdint.h>
 #include <string.h>
 #include <stdlib.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 /* ------------------------------------------------------------------------ */
 /* exp for the cull: Cody-Waite argument reduction with ln2 split into a
@@ -166,6 +169,20 @@ void orc_cull_v1(int64_t n, const float *geo, const float *cam, uint8_t *keep, f
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i)
         keep[i] = (uint8_t)cull_one(geo + 10 * i, cam, detail ? detail + 11 * i : NULL);
+}
+
+/* Thread count of the OpenMP loops (the CPU baseline times one thread and
+ * all cores); returns the previous maximum. */
+int orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    int old = omp_get_max_threads();
+    if (n > 0) omp_set_num_threads(n);
+    return old;
+#else
+    (void)n;
+    return 1;
+#endif
 }
 
 /* valid_ids: ids of kept rows in ascending order.  Returns the count. */
@@ -436,32 +453,179 @@ static float adam_step32(float m1, float v1, float st, float bc, float eps, floa
     return upd;
 }
 
+/* ------------------------------------------------------------------------ */
+/* A-posteriori error bound of the quantised-moment models (O4) against dense
+ * FP64 Adam (Eq. 1), carried along the model's own trajectory.
+ *
+ * Given the visible sets and the gradients, the moments of an element evolve
+ * independently of w, and every move of w is a sum of per-step terms:
+ *   exact (dense FP64):  lr c_k m_k / (sqrt(v_k) + eps_k)      c_k = s_k bc_k / (1 - b1^k)
+ *   model:               lr c_k clamp(m~ / (sqrt(v~) + eps), +-rb)
+ * (a deferred row's catch-up is the sum over its skipped steps k of
+ * lr c_k r^j with r = b1/sqrt(b2), i.e. lr W[d] times one ratio).  Per
+ * element we keep
+ *   em >= |m~ - m|, ev >= |v~ - v|   the stored (decoded) moments against the
+ *                                    exact ones: each update multiplies the
+ *                                    old bound by b^(d+1) and adds the actual
+ *                                    rounding of the store (|stored - value|,
+ *                                    an FP8 re-encode adds its own) plus an
+ *                                    FP32 arithmetic slack;
+ *   bw >= |w~ - w|                   the sum over steps of lr c_k times the
+ *                                    largest ratio difference over every
+ *                                    exact (m, v) inside the moment bounds,
+ *                                    plus the FP32 rounding of w.
+ * Exact moments grown from zero obey |m| / sqrt(v) <= cs = (1-b1) /
+ * sqrt((1-b2)(1 - b1^2/b2)) (Cauchy-Schwarz), so the exact ratio is clipped
+ * to [-cs, cs]; the model's ratio is clamped to [-rb, rb].  Nothing else is
+ * assumed: a code far below its block scale (E4M3 subnormals, a lost second
+ * moment) widens the interval and the bound falls back towards lr c_k (rb + cs)
+ * per step. */
+typedef struct orc_track {
+    const uint32_t *keys;   /* stochastic-rounding key of each local row (NULL: the row index) */
+    double *em, *ev, *bw;   /* [n][ld] bounds, or NULL (no tracking) */
+    double cs;              /* Cauchy-Schwarz bound of |m| / sqrt(v) */
+} orc_track;
+
+#define ORC_U32 5.9604644775390625e-08      /* 2^-24: unit roundoff of binary32 */
+
+static int64_t sr_key(const orc_track *trk, int64_t id)
+{
+    return (trk && trk->keys) ? (int64_t)trk->keys[id] : id;
+}
+
+/* Largest |clamp(mt / (sqrt(vt) + eps), +-rb) - m / (sqrt(v) + eps)| over
+ * m in [mt - em, mt + em], v in [max(vt - ev, 0), vt + ev], with the exact
+ * ratio clipped to [-cs, cs].  The model evaluates its ratio in FP32: three
+ * roundings of at most 2^-24 relative are added. */
+static double ratio_dev(double mt, double vt, double em, double ev, double eps, double rb, double cs)
+{
+    double a = mt / (sqrt(vt) + eps);
+    if (!(a == a)) return rb + cs;
+    if (a > rb) a = rb;
+    else if (a < -rb) a = -rb;
+    double mlo = mt - em, mhi = mt + em;
+    double vlo = vt - ev;
+    if (vlo < 0.0) vlo = 0.0;
+    double dlo = sqrt(vlo) + eps, dhi = sqrt(vt + ev) + eps;
+    if (dlo < 1e-300) dlo = 1e-300;
+    double ulo, uhi;
+    if (mlo >= 0.0) {
+        ulo = mlo / dhi;
+        uhi = mhi / dlo;
+    } else if (mhi <= 0.0) {
+        ulo = mlo / dlo;
+        uhi = mhi / dhi;
+    } else {
+        ulo = mlo / dlo;
+        uhi = mhi / dlo;
+    }
+    if (ulo < -cs) ulo = -cs;
+    if (ulo > cs) ulo = cs;
+    if (uhi < -cs) uhi = -cs;
+    if (uhi > cs) uhi = cs;
+    double d = fabs(a - ulo);
+    if (fabs(a - uhi) > d) d = fabs(a - uhi);
+    return d * (1.0 + 1e-12) + 4.0 * ORC_U32 * fabs(a);
+}
+
+/* Bound of the catch-up of one element deferred d > 0 steps (restore of
+ * Eq. 3 with the stored moments mt, vt): lr W (ratio difference + the eps
+ * factor-out), plus FP32 slack.  The exact skipped step j after the last
+ * update divides m by sqrt(v) + e' with e' = eps bc_k b2^(-j/2) in
+ * [eps sqrt(1-b2), eps b2^(-d/2)] instead of sqrt(v) + eps, which changes the
+ * ratio by at most |m| e_max / ((sqrt(v) + eps)(sqrt(v) + e_min)) (and by at
+ * most cs, both ratios lying in [-cs, cs]). */
+static double restore_dev(double mt, double vt, double em, double ev, double eps, double rb, double cs,
+                          double wd, double lr, int64_t d, double b2)
+{
+    double dev = ratio_dev(mt, vt, em, ev, eps, rb, cs);
+    double vlo = vt - ev;
+    double sv = vlo > 0.0 ? sqrt(vlo) : 0.0;
+    double emax = eps * pow(b2, -0.5 * (double)d), emin = eps * sqrt(1.0 - b2);
+    double mabs = fabs(mt) + em;
+    double et = 0.0;
+    if (mabs > 0.0) {
+        double den = (sv + eps) * (sv + emin);
+        et = den > 0.0 ? mabs * emax / den : cs;
+        if (!(et <= cs)) et = cs;
+    }
+    return fabs(lr) * wd * (1.0 + 4.0 * ORC_U32) * (dev + et);
+}
+
 /* O3/O4 update of the rows rows[j] (defer count d[j], FP32 compact gradient
  * g[j][:] or zero when g == NULL).  w is [n][ld] FP32; m, v are [n][ld] in the
  * given storage.  Global column of k is col0 + k (SR random stream). */
+/* Bound bookkeeping of one update of a tracked element (see orc_track):
+ * stored moments (mk, vk) with gap d, restore w0 -> wr (d > 0), new FP32
+ * moments (m1, v1) from gradient gk, Adam step upd (wr -> w1), stored
+ * results decoded as (ms, vs). */
+static void track_update(const orc_track *trk, int64_t e, int64_t d, double Wd, double Mfd, double Vfd,
+                         double omb1, double omb2, double gk, double lr, double ss, double bc, double eps,
+                         double rb, double b2, double w0, double wr, double w1, double upd, double mk,
+                         double vk, double m1, double v1, double ms, double vs)
+{
+    const double u = ORC_U32, cs = trk->cs;
+    double em0 = trk->em[e], ev0 = trk->ev[e], b = trk->bw[e];
+    if (d > 0) b += restore_dev(mk, vk, em0, ev0, eps, rb, cs, Wd, lr, d, b2) + 4.0 * u * fabs(w0 - wr);
+    /* the FP32 moment update against the exact one: decayed old bound plus
+     * the roundings of the tables (1 - b1 and b^(d+1) rounded once) and of the
+     * three operations */
+    double em1 = Mfd * em0 * (1.0 + 2.0 * u) + 4.0 * u * (fabs(Mfd * mk) + fabs(omb1 * gk)) + 1e-14 * fabs(m1);
+    double ev1 = Vfd * ev0 * (1.0 + 2.0 * u) + 5.0 * u * (fabs(Vfd * vk) + fabs(omb2 * gk * gk)) + 1e-14 * fabs(v1);
+    /* the Adam step lr ss bc clamp(m1 / (sqrt(v1) + bc eps)), evaluated in FP32
+     * with tables rounded once: about nine roundings of the step */
+    b += fabs(lr) * ss * bc * ratio_dev(m1, v1, em1, ev1, bc * eps, rb, cs) + 12.0 * u * fabs(upd);
+    /* FP32 rounding of the two subtractions from w */
+    b += 2.0 * u * (fabs(w0) + fabs(wr) + fabs(w1));
+    trk->em[e] = em1 + fabs(ms - m1);
+    trk->ev[e] = ev1 + fabs(vs - v1);
+    trk->bw[e] = b;
+}
+
+/* Bound bookkeeping of one flushed element (delta skipped steps, moments
+ * decayed by Mfd = b1^delta, Vfd = b2^delta, then stored as ms, vs). */
+static void track_flush(const orc_track *trk, int64_t e, int64_t dl, double Wn, double Mfd, double Vfd,
+                        double lr, double eps, double rb, double b2, double w0, double w1, double mk, double vk,
+                        double ms, double vs)
+{
+    const double u = ORC_U32, cs = trk->cs;
+    double em0 = trk->em[e], ev0 = trk->ev[e];
+    trk->bw[e] += restore_dev(mk, vk, em0, ev0, eps, rb, cs, Wn, lr, dl, b2) + 4.0 * u * fabs(w0 - w1) +
+                  2.0 * u * (fabs(w0) + fabs(w1));
+    double m1 = Mfd * mk, v1 = Vfd * vk;
+    trk->em[e] = Mfd * em0 * (1.0 + 2.0 * u) + 2.0 * u * fabs(m1) + fabs(ms - (double)(float)m1);
+    trk->ev[e] = Vfd * ev0 * (1.0 + 2.0 * u) + 2.0 * u * fabs(v1) + fabs(vs - (double)(float)v1);
+}
+
+/* trk (optional): stochastic-rounding keys and the error-bound bookkeeping. */
 void orc_deferred_rows_f32(int dim, float *w, void *m, void *v, int state, int64_t ld, int64_t n_rows,
                            const uint32_t *rows, const int64_t *d, const float *g, int64_t g_ld,
                            const float *lr, double b1, double b2, double eps,
                            const float *Wf, const float *Mf, const float *Vf, float ss, float bc, float rb,
-                           uint64_t seed, int64_t t, int col0)
+                           uint64_t seed, int64_t t, int col0, const orc_track *trk)
 {
     const float omb1 = (float)(1.0 - b1), omb2 = (float)(1.0 - b2), eps32 = (float)eps;
+    const int track = trk && trk->bw;
 #pragma omp parallel for schedule(static)
     for (int64_t j = 0; j < n_rows; ++j) {
         int64_t id = rows[j];
         int64_t dj = d[j];
         for (int k = 0; k < dim; ++k) {
             int64_t e = id * ld + k;
-            float wk = w[e], mk = mom_load(m, state, e), vk = mom_load(v, state, e);
+            float w0 = w[e], wk = w0, mk = mom_load(m, state, e), vk = mom_load(v, state, e);
             float gk = g ? g[j * g_ld + k] : 0.0f;
             if (dj > 0) wk = restore32(wk, mk, vk, Wf[dj], lr[k], eps32, rb);
             float m1 = Mf[dj] * mk + omb1 * gk;
             float v1 = Vf[dj] * vk + (omb2 * gk) * gk;
             float st = lr[k] * ss;
-            w[e] = wk - adam_step32(m1, v1, st, bc, eps32, rb);
-            uint64_t r = state ? sr_bits(seed, t, id, col0 + k) : 0;
+            float upd = adam_step32(m1, v1, st, bc, eps32, rb);
+            w[e] = wk - upd;
+            uint64_t r = state ? sr_bits(seed, t, sr_key(trk, id), col0 + k) : 0;
             mom_store(m, state, e, m1, (uint32_t)(r & 0xffffu));
             mom_store(v, state, e, v1, (uint32_t)((r >> 16) & 0xffffu));
+            if (track)
+                track_update(trk, e, dj, Wf[dj], Mf[dj], Vf[dj], omb1, omb2, gk, lr[k], ss, bc, eps, rb, b2, w0,
+                             wk, w[e], upd, mk, vk, m1, v1, mom_load(m, state, e), mom_load(v, state, e));
         }
     }
 }
@@ -490,20 +654,24 @@ void orc_restore_rows_f32(int dim, const float *w, const void *m, const void *v,
 void orc_flush_rows_f32(int dim, float *w, void *m, void *v, int state, int64_t ld, int64_t n_rows,
                         const uint32_t *rows, const int64_t *delta, const float *lr, double eps,
                         const float *Wf_next, const float *Mf, const float *Vf, float rb,
-                        uint64_t seed, int64_t t, int col0)
+                        uint64_t seed, int64_t t, int col0, double b2, const orc_track *trk)
 {
     const float eps32 = (float)eps;
+    const int track = trk && trk->bw;
 #pragma omp parallel for schedule(static)
     for (int64_t j = 0; j < n_rows; ++j) {
         int64_t id = rows[j];
         int64_t dl = delta[j];
         for (int k = 0; k < dim; ++k) {
             int64_t e = id * ld + k;
-            float mk = mom_load(m, state, e), vk = mom_load(v, state, e);
-            w[e] = restore32(w[e], mk, vk, Wf_next[dl], lr[k], eps32, rb);
-            uint64_t r = state ? sr_bits(seed, t, id, col0 + k) : 0;
+            float w0 = w[e], mk = mom_load(m, state, e), vk = mom_load(v, state, e);
+            w[e] = restore32(w0, mk, vk, Wf_next[dl], lr[k], eps32, rb);
+            uint64_t r = state ? sr_bits(seed, t, sr_key(trk, id), col0 + k) : 0;
             mom_store(m, state, e, Mf[dl - 1] * mk, (uint32_t)(r & 0xffffu));
             mom_store(v, state, e, Vf[dl - 1] * vk, (uint32_t)((r >> 16) & 0xffffu));
+            if (track)
+                track_flush(trk, e, dl, Wf_next[dl], Mf[dl - 1], Vf[dl - 1], lr[k], eps, rb, b2, w0, w[e], mk, vk,
+                            mom_load(m, state, e), mom_load(v, state, e));
         }
     }
 }
@@ -588,8 +756,9 @@ void orc_deferred_rows_fp8(int dim, float *w, uint8_t *mq, uint8_t *vq, float *m
                            int64_t n, int64_t n_rows, const uint32_t *rows, const int64_t *d, const float *g,
                            int64_t g_ld, const float *lr, double b1, double b2, double eps, const float *Wf,
                            const float *Mf, const float *Vf, float ss, float bc, float rb, uint64_t seed,
-                           int64_t t, int col0)
+                           int64_t t, int col0, const orc_track *trk)
 {
+    const int track = trk && trk->bw;
     const float omb1 = (float)(1.0 - b1), omb2 = (float)(1.0 - b2), eps32 = (float)eps;
     const int64_t nb = (n + FP8_BLOCK - 1) / FP8_BLOCK;
     float *amax_m = (float *)calloc((size_t)nb, sizeof(float));
@@ -618,8 +787,14 @@ void orc_deferred_rows_fp8(int dim, float *w, uint8_t *mq, uint8_t *vq, float *m
                 for (int k = 0; k < dim; ++k) {
                     int64_t e = id * ld + k;
                     float x = e4m3_decode(q[e]) * sc[b];
-                    uint64_t r = sr_bits(seed, t, id, col0 + k + 64);
+                    uint64_t r = sr_bits(seed, t, sr_key(trk, id), col0 + k + 64);
                     q[e] = orc_e4m3_sr(x / snew, (uint32_t)((mv ? r >> 16 : r) & 0xffffu));
+                    if (track) {
+                        /* the re-encode moves the decoded moment (v = code^2 scale^2) */
+                        double xo = x, xn = (double)e4m3_decode(q[e]) * snew;
+                        if (mv) trk->ev[e] += fabs(xn * xn - xo * xo);
+                        else trk->em[e] += fabs(xn - xo);
+                    }
                 }
             sc[b] = snew;
         }
@@ -631,16 +806,22 @@ void orc_deferred_rows_fp8(int dim, float *w, uint8_t *mq, uint8_t *vq, float *m
         int64_t id = rows[j], dj = d[j], b = id / FP8_BLOCK;
         for (int k = 0; k < dim; ++k) {
             int64_t e = id * ld + k;
-            float wk = w[e], mk = fp8_load(mq, ms, id, e), vk = fp8_load_v(vq, vs, id, e);
+            float w0 = w[e], wk = w0, mk = fp8_load(mq, ms, id, e), vk = fp8_load_v(vq, vs, id, e);
             float gk = g ? g[j * g_ld + k] : 0.0f;
             if (dj > 0) wk = restore32(wk, mk, vk, Wf[dj], lr[k], eps32, rb);
             float m1 = Mf[dj] * mk + omb1 * gk;
             float v1 = Vf[dj] * vk + (omb2 * gk) * gk;
             float st = lr[k] * ss;
-            w[e] = wk - adam_step32(m1, v1, st, bc, eps32, rb);
-            uint64_t r = sr_bits(seed, t, id, col0 + k);
+            float upd = adam_step32(m1, v1, st, bc, eps32, rb);
+            w[e] = wk - upd;
+            uint64_t r = sr_bits(seed, t, sr_key(trk, id), col0 + k);
             mq[e] = ms[b] > 0.0f ? orc_e4m3_sr(m1 / ms[b], (uint32_t)(r & 0xffffu)) : 0;
             vq[e] = vs[b] > 0.0f ? orc_e4m3_sr(sqrtf(v1) / vs[b], (uint32_t)((r >> 16) & 0xffffu)) : 0;
+            if (track) {
+                double rs = (double)e4m3_decode(vq[e]) * vs[b];
+                track_update(trk, e, dj, Wf[dj], Mf[dj], Vf[dj], omb1, omb2, gk, lr[k], ss, bc, eps, rb, b2, w0,
+                             wk, w[e], upd, mk, vk, m1, v1, (double)e4m3_decode(mq[e]) * ms[b], rs * rs);
+            }
         }
     }
 }
@@ -666,19 +847,25 @@ void orc_restore_rows_fp8(int dim, const float *w, const uint8_t *mq, const uint
 void orc_flush_rows_fp8(int dim, float *w, uint8_t *mq, uint8_t *vq, const float *ms, const float *vs,
                         int64_t ld, int64_t n_rows, const uint32_t *rows, const int64_t *delta, const float *lr,
                         double eps, const float *Wf_next, const float *Mf, const float *Vf, float rb, uint64_t seed,
-                        int64_t t, int col0)
+                        int64_t t, int col0, double b2, const orc_track *trk)
 {
     const float eps32 = (float)eps;
+    const int track = trk && trk->bw;
 #pragma omp parallel for schedule(static)
     for (int64_t j = 0; j < n_rows; ++j) {
         int64_t id = rows[j], dl = delta[j], b = id / FP8_BLOCK;
         for (int k = 0; k < dim; ++k) {
             int64_t e = id * ld + k;
-            float mk = fp8_load(mq, ms, id, e), vk = fp8_load_v(vq, vs, id, e);
-            w[e] = restore32(w[e], mk, vk, Wf_next[dl], lr[k], eps32, rb);
-            uint64_t r = sr_bits(seed, t, id, col0 + k);
+            float w0 = w[e], mk = fp8_load(mq, ms, id, e), vk = fp8_load_v(vq, vs, id, e);
+            w[e] = restore32(w0, mk, vk, Wf_next[dl], lr[k], eps32, rb);
+            uint64_t r = sr_bits(seed, t, sr_key(trk, id), col0 + k);
             mq[e] = ms[b] > 0.0f ? orc_e4m3_sr(Mf[dl - 1] * mk / ms[b], (uint32_t)(r & 0xffffu)) : 0;
             vq[e] = vs[b] > 0.0f ? orc_e4m3_sr(sqrtf(Vf[dl - 1] * vk) / vs[b], (uint32_t)((r >> 16) & 0xffffu)) : 0;
+            if (track) {
+                double rs = (double)e4m3_decode(vq[e]) * vs[b];
+                track_flush(trk, e, dl, Wf_next[dl], Mf[dl - 1], Vf[dl - 1], lr[k], eps, rb, b2, w0, w[e], mk, vk,
+                            (double)e4m3_decode(mq[e]) * ms[b], rs * rs);
+            }
         }
     }
 }

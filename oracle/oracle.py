@@ -70,15 +70,15 @@ def lib():
             "orc_e4m3_sr": (C.c_uint8, [f32, C.c_uint32]),
             "orc_fp8_scale_for": (f32, [f32]),
             "orc_deferred_rows_fp8": (None, [i32, vp, vp, vp, vp, vp, i64, i64, i64, vp, vp, vp, i64, vp,
-                                             f64, f64, f64, vp, vp, vp, f32, f32, f32, C.c_uint64, i64, i32]),
+                                             f64, f64, f64, vp, vp, vp, f32, f32, f32, C.c_uint64, i64, i32, vp]),
             "orc_restore_rows_fp8": (None, [i32, vp, vp, vp, vp, vp, i64, i64, vp, vp, vp, f64, vp, f32, vp]),
             "orc_flush_rows_fp8": (None, [i32, vp, vp, vp, vp, vp, i64, i64, vp, vp, vp, f64, vp, vp, vp, f32,
-                                          C.c_uint64, i64, i32]),
+                                          C.c_uint64, i64, i32, f64, vp]),
             "orc_deferred_rows_f32": (None, [i32, vp, vp, vp, i32, i64, i64, vp, vp, vp, i64, vp,
-                                             f64, f64, f64, vp, vp, vp, f32, f32, f32, C.c_uint64, i64, i32]),
+                                             f64, f64, f64, vp, vp, vp, f32, f32, f32, C.c_uint64, i64, i32, vp]),
             "orc_restore_rows_f32": (None, [i32, vp, vp, vp, i32, i64, i64, vp, vp, vp, f64, vp, f32, vp]),
             "orc_flush_rows_f32": (None, [i32, vp, vp, vp, i32, i64, i64, vp, vp, vp, f64, vp, vp, vp, f32,
-                                          C.c_uint64, i64, i32]),
+                                          C.c_uint64, i64, i32, f64, vp]),
             "orc_sgdm_dense_sparse_grad_f64": (None, [i64, i32, vp, vp, i64, vp, vp, vp, f64, f64]),
             "orc_lut_sgdm_f64": (None, [f64, i64, i32, vp, vp, vp]),
             "orc_lut_sgdm_spec": (None, [f64, i64, i32, vp, vp, vp, vp]),
@@ -106,6 +106,7 @@ def lib():
             "orc_densify": (i64, [i64, i32, vp, vp, vp, vp, vp, f32, f32, i32, f32, f32, f32, f32, C.c_uint64,
                                   i64, vp, vp, vp, vp, vp]),
             "orc_densify_thresholds": (None, [f64, f64, f64, vp]),
+            "orc_set_threads": (i32, [i32]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -113,6 +114,11 @@ def lib():
             fn.argtypes = args
         _lib = L
     return _lib
+
+
+def set_threads(n: int) -> int:
+    """Thread count of the oracle's OpenMP loops; returns the previous one."""
+    return int(lib().orc_set_threads(int(n)))
 
 
 def _p(a, dtype=None):
@@ -210,6 +216,35 @@ class DenseAdamF64:
             lib().orc_adam_dense_sparse_grad_f64(w.shape[0], w.shape[1], _p(w), _p(m), _p(v),
                                                  ids.shape[0], _p(ids), _p(g), _p(lr),
                                                  self.b1, self.b2, self.eps, t)
+
+
+class DenseAdamF32:
+    """Eq. 1 in FP32 on every row every step (numpy float32 arithmetic, one
+    operation at a time; bias corrections rounded once from FP64).  It is the
+    yardstick of FP32 rounding: an FP32-state deferred run is judged against
+    dense FP64 Adam relative to the error this plain FP32 Adam makes."""
+
+    def __init__(self, geo, app, lr_geo, lr_app, b1=0.9, b2=0.999, eps=1e-15):
+        self.w = [np.array(geo, np.float32), np.array(app, np.float32)]
+        self.m = [np.zeros_like(x) for x in self.w]
+        self.v = [np.zeros_like(x) for x in self.w]
+        self.lr = [np.asarray(lr_geo, np.float32), np.asarray(lr_app, np.float32)]
+        self.b1, self.b2, self.eps = np.float32(b1), np.float32(b2), np.float32(eps)
+        self.omb1, self.omb2 = np.float32(1.0 - b1), np.float32(1.0 - b2)
+        self.B1, self.B2 = b1, b2
+
+    def step(self, t: int, ids: np.ndarray, g_geo: np.ndarray, g_app: np.ndarray):
+        ids = np.asarray(ids, np.int64)
+        bc1 = np.float32(1.0 - self.B1 ** t)
+        bc2 = np.float32(1.0 - self.B2 ** t)
+        for k, g in enumerate((g_geo, g_app)):
+            gd = np.zeros_like(self.w[k])
+            gd[ids] = np.asarray(g, np.float32)
+            m = self.b1 * self.m[k] + self.omb1 * gd
+            v = self.b2 * self.v[k] + (self.omb2 * gd) * gd
+            self.m[k], self.v[k] = m, v
+            den = np.sqrt(v / bc2) + self.eps
+            self.w[k] = self.w[k] - (self.lr[k] * (m / bc1)) / den
 
 
 # ---------------------------------------------------------------------------
@@ -322,6 +357,18 @@ def e4m3_decode(codes: np.ndarray) -> np.ndarray:
     return np.where(c & 0x80, -a, a).astype(np.float32)
 
 
+class _Track(C.Structure):
+    """Mirror of orc_track: stochastic-rounding keys of the rows and the
+    per-element error-bound arrays of the quantised models."""
+    _fields_ = [("keys", C.c_void_p), ("em", C.c_void_p), ("ev", C.c_void_p), ("bw", C.c_void_p),
+                ("cs", C.c_double)]
+
+
+def adam_ratio_bound(b1: float, b2: float) -> float:
+    """Cauchy-Schwarz bound of |m| / sqrt(v) for Adam moments grown from zero."""
+    return (1.0 - b1) / np.sqrt((1.0 - b2) * (1.0 - b1 * b1 / b2)) * (1.0 + 1e-12)
+
+
 class DeferredF32(_Deferred):
     """Model O3 (state='f32') / O4 (state='bf16'): deferred algorithm with FP32
     math, moments stored in FP32 or in BF16 with stochastic rounding (random
@@ -330,7 +377,8 @@ class DeferredF32(_Deferred):
     the rounding stream); default 0..n-1."""
 
     def __init__(self, geo, app, lr_geo, lr_app, b1=0.9, b2=0.999, eps=1e-15, max_defer=0,
-                 state="f32", sr_seed=0, keys=None, app_state=None, geo_dense=False, sched=None):
+                 state="f32", sr_seed=0, keys=None, app_state=None, geo_dense=False, sched=None,
+                 track_bound=False):
         super().__init__(geo.shape[0], max_defer)
         self.sched = _sched(sched)
         # geo_dense: the geometric group takes a plain Adam step on every row
@@ -349,9 +397,27 @@ class DeferredF32(_Deferred):
         self.rb = float(restore_bound(b1, b2))
         self.sr_seed = int(sr_seed)
         self.col0 = [0, self.w[0].shape[1]]
-        if keys is not None:
-            assert np.array_equal(np.asarray(keys), np.arange(geo.shape[0])), \
-                "row sampling with quantised state needs keys == row index"
+        # keys: the Gaussian ids of the rows, which key the stochastic rounding
+        # (a sample of whole 128-row blocks keeps FP8 block scales exact)
+        self.keys = None if keys is None else np.ascontiguousarray(keys, np.uint32)
+        if self.keys is not None:
+            assert self.keys.shape[0] == geo.shape[0]
+        # track_bound: carry the a-posteriori bound of |w - w64| (dense FP64
+        # Adam on the same visible sets and gradients) per element
+        self.bw = self.em = self.ev = None
+        if track_bound:
+            self.bw = [np.zeros(x.shape, np.float64) for x in self.w]
+            self.em = [np.zeros(x.shape, np.float64) for x in self.w]
+            self.ev = [np.zeros(x.shape, np.float64) for x in self.w]
+        cs = adam_ratio_bound(b1, b2)
+        self._trk = []
+        for k in range(2):
+            tr = _Track()
+            tr.keys = None if self.keys is None else self.keys.ctypes.data
+            if track_bound:
+                tr.em, tr.ev, tr.bw = self.em[k].ctypes.data, self.ev[k].ctypes.data, self.bw[k].ctypes.data
+            tr.cs = cs
+            self._trk.append(tr)
 
     def moments_f32(self, k):
         """FP32 view of the stored moments of group k."""
@@ -416,12 +482,13 @@ class DeferredF32(_Deferred):
                                             _p(self.vs[k]), dim, self.w[k].shape[0], krows.shape[0], _p(krows),
                                             _p(kd), _p(gg), dim, _p(self.lr[k]), self.b1, self.b2, self.eps,
                                             _p(Wf), _p(Mf), _p(Vf), float(ss), float(bc), self.rb,
-                                            self.sr_seed, t, self.col0[k])
+                                            self.sr_seed, t, self.col0[k], C.byref(self._trk[k]))
                 continue
             lib().orc_deferred_rows_f32(dim, _p(self.w[k]), _p(self.m[k]), _p(self.v[k]), self.sid[k], dim,
                                         krows.shape[0], _p(krows), _p(kd), _p(gg), dim, _p(self.lr[k]),
                                         self.b1, self.b2, self.eps, _p(Wf), _p(Mf), _p(Vf),
-                                        float(ss), float(bc), self.rb, self.sr_seed, t, self.col0[k])
+                                        float(ss), float(bc), self.rb, self.sr_seed, t, self.col0[k],
+                                        C.byref(self._trk[k]))
         self.bump(valid, sat)
         return valid, sat
 
@@ -441,11 +508,12 @@ class DeferredF32(_Deferred):
                 lib().orc_flush_rows_fp8(dim, _p(self.w[k]), _p(self.m[k]), _p(self.v[k]), _p(self.ms[k]),
                                          _p(self.vs[k]), dim, rows.shape[0], _p(rows32), _p(delta),
                                          _p(self.lr[k]), self.eps, _p(Wn), _p(Mf), _p(Vf), self.rb,
-                                         self.sr_seed, t_done, self.col0[k])
+                                         self.sr_seed, t_done, self.col0[k], self.b2, C.byref(self._trk[k]))
                 continue
             lib().orc_flush_rows_f32(dim, _p(self.w[k]), _p(self.m[k]), _p(self.v[k]), self.sid[k], dim,
                                      rows.shape[0], _p(rows32), _p(delta), _p(self.lr[k]), self.eps,
-                                     _p(Wn), _p(Mf), _p(Vf), self.rb, self.sr_seed, t_done, self.col0[k])
+                                     _p(Wn), _p(Mf), _p(Vf), self.rb, self.sr_seed, t_done, self.col0[k],
+                                     self.b2, C.byref(self._trk[k]))
         self.counter[:] = 0
 
 

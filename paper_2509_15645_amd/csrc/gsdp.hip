@@ -2333,16 +2333,22 @@ __global__ __launch_bounds__(256) void k_grad_sum(GradSumArgs a)
         }
         __syncthreads();
         const u32 total = sOff[C];
+        // positions of this chunk: the union list may hold more rows than
+        // cap_union (then the camera lists still name the positions past it,
+        // and the last chunk's range reaches them); only p0 .. p0 + np - 1 are
+        // summed, so entries outside that window are skipped
+        const u32 np = min((u32)kSumRows, U - p0);
         for (u32 e = tid; e < total; e += 256) {
             int c = 0;
             while (e >= sOff[c + 1]) ++c;
             const u32 i = sLo[c] + (e - sOff[c]);
             const u32 p = a.cam_pos[(size_t)c * a.cap_cam + i] - p0;
-            sIdx[p][c] = i;
-            atomicOr(&sMask[p], 1u << c);
+            if (p < np) {
+                sIdx[p][c] = i;
+                atomicOr(&sMask[p], 1u << c);
+            }
         }
         __syncthreads();
-        const u32 np = min((u32)kSumRows, U - p0);
         // kGsRows rows of this wavefront at a time: the first kGsSlots camera
         // entries of each are loaded before the first add (rows rarely have
         // more; those take the rest one by one).  Entry addresses are uniform:

@@ -146,6 +146,49 @@ def test_batched_scenes_cameras_vs_oracle(g, kind):
             assert np.array_equal(bits(got), bits(refv)), f"{name}_{part}"
 
 
+def test_grad_sum_union_capacity_overflow(g):
+    """A union capacity below the union's size, with a ragged last chunk: the
+    union count is reported in full, the first cap_union ids are written, the
+    camera lists (large enough) still name positions past the capacity, and
+    the gradient sums of the first cap_union positions equal the oracle's,
+    with the recorded chunk starts and with binary searches."""
+    sizes, C = [30_000, 60_000], 8
+    geo, app, row0, sets = _batch(sizes, C, 1, seed=13)
+    lg, la = gi.lr_columns()
+    model = g.Model(geo, app, lg, la, max_steps=8, cull_mode=1)
+    ref = orc.cull_multi(geo, row0, sets[0])
+    U = ref[0].shape[0]
+    cap = (U // 2) // 128 * 128 + 37
+    assert 128 < cap < U
+    multi = g.Multi(model, row0, sets, cap_union=cap)
+    g.gs_cull_multi(model, multi, 1)
+    torch.cuda.synchronize()
+    u, ids, cc, cams, _ = multi.lists()
+    assert u == U and np.array_equal(ids, ref[0][:cap].astype(np.uint32))
+    assert any(int(c.max()) >= cap for c in cams if c.size), "no list names a position past the capacity"
+    for c in range(C):
+        assert np.array_equal(cams[c], ref[1][c].astype(np.uint32)), c
+    D = 59
+    rng = np.random.default_rng(17)
+    g_cam = [rng.normal(0, 1e-3, (cc[c], D)).astype(np.float32) for c in range(C)]
+    g_cam_dev = torch.zeros((C, multi.cap_cam, D), dtype=torch.float32, device="cuda")
+    for c in range(C):
+        g_cam_dev[c, :cc[c]] = torch.from_numpy(g_cam[c]).cuda()
+    gsum = orc.grad_sum_multi(ref[1], g_cam, U)
+    for use_chunks in (True, False):
+        saved = multi.c.chunk_start
+        if not use_chunks:
+            multi.c.chunk_start = None
+        out_g = torch.full((cap, 10), 7.0, dtype=torch.float32, device="cuda")
+        out_a = torch.full((cap, 49), 7.0, dtype=torch.float32, device="cuda")
+        g.gs_grad_sum_multi(multi, 49, g_cam_dev, out_g, out_a)
+        multi.c.chunk_start = saved
+        torch.cuda.synchronize()
+        assert np.array_equal(bits(out_g.cpu().numpy()), bits(gsum[:cap, :10])), use_chunks
+        assert np.array_equal(bits(out_a.cpu().numpy()), bits(gsum[:cap, 10:])), use_chunks
+    say(f"[union overflow] union {U} capacity {cap}: sums of the first {cap} positions equal the oracle's")
+
+
 def test_batched_variants_agree_and_autotune(g):
     sizes, C = [50_000, 20_000, 80_000], 16
     geo, app, row0, sets = _batch(sizes, C, 1, seed=3)

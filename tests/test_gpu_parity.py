@@ -14,6 +14,7 @@ import torch
 
 import gs_inputs as gi
 from oracle import oracle as orc
+from precision_bound import check_bound
 
 pytestmark = pytest.mark.gpu
 
@@ -247,9 +248,9 @@ def test_small_workload_path_vs_oracle(g, max_defer, layout, grad_mode, cull_mod
     model = g.Model(sc.geo, sc.app, lg, la, max_steps=32, max_defer=max_defer, app_layout=layout,
                     cull_mode=cull_mode, geo_state=states[0], app_state=states[1], sr_seed=77,
                     geo_mode=geo_mode, lr_scale=lr_scale)
-    o3 = orc.DeferredF32(sc.geo, sc.app, lg, la, max_defer=max_defer, state=states[0], app_state=states[1],
-                         sr_seed=77, geo_dense=bool(geo_mode), sched=lr_scale)
     quant = states != ("f32", "f32")
+    o3 = orc.DeferredF32(sc.geo, sc.app, lg, la, max_defer=max_defer, state=states[0], app_state=states[1],
+                         sr_seed=77, geo_dense=bool(geo_mode), sched=lr_scale, track_bound=quant)
     dense = orc.DenseAdamF64(sc.geo, sc.app, lg, la, sched=lr_scale)
     n = w.n
     out_g = torch.zeros((n, 10), dtype=torch.float32, device="cuda")
@@ -303,22 +304,11 @@ def test_small_workload_path_vs_oracle(g, max_defer, layout, grad_mode, cull_mod
     if not quant:
         assert e_geo.max() <= 1e-6 and e_app.max() <= 1e-6
     else:
-        # quantised moments, relative to the largest possible movement lr * steps:
-        # BF16 max 2e-2; FP8 max 0.3 and mean 2e-2.  Derivation: one stochastic
-        # rounding moves a stored value by less than one ulp, 2^-7 (BF16) or 2^-3
-        # (E4M3 normals) relative, so one step's m/sqrt(v) is off by at most
-        # (1 + 2^-7)/(1 - 2^-8) - 1 = 1.2% (BF16, v stored) or
-        # (1 + 2^-3)/(1 - 2^-3) - 1 = 28.6% (E4M3, sqrt(v) stored); with
-        # |m_hat/sqrt(v_hat)| <= 1 per step (moments of i.i.d. gradients; 7.27 is
-        # the hard limit), T steps move w by at most that
-        # fraction of lr T.  The mean is far below the max (unbiased rounding).
-        for k, (got, lr) in enumerate(((st["geo_w"], lg), (st["app_w"], la))):
-            err = np.abs(got - dense.w[k]) / (lr.astype(np.float64) * w.steps)
-            say(f"[path {states}] group {k}: |w - w64| / (lr T) max {err.max():.3e} mean {err.mean():.3e}")
-            if states[k] == "fp8":
-                assert err.max() <= 0.3 and err.mean() <= 2e-2
-            elif states[k] == "bf16":
-                assert err.max() <= 2e-2
+        # quantised moments: every element within the a-posteriori bound the
+        # oracle carried along its (bit-identical) trajectory
+        res = check_bound((st["geo_w"], st["app_w"]), o3, dense, w.steps, (lg, la), f"path {states}")
+        for k, (e, b) in enumerate(res):
+            say(f"[path {states}] group {k}: |w - w64| / (lr T) max {e:.3e}, bound max {b:.3e}")
     assert model.ws_header()["error"] == 0
 
 
@@ -431,33 +421,6 @@ def test_band_cull_adversarial_deferred_rows(g, seed):
         assert np.array_equal(got[mode][0], valid), mode
     say(f"[band adversarial {seed}] M={valid.shape[0]} restored exact={got[0][1]} band={got[1][1]}")
     assert got[1][1] < got[0][1]
-
-
-def test_aerial_full_scale_path_vs_oracle(g):
-    """4M Gaussians, aerial cameras, 6 steps with device-generated gradients:
-    full visible-id lists and the full state bit-exact vs O3 on the host."""
-    w = gi.workload("aerial4m")
-    steps = 6
-    sc = gi.make_scene(w.n, seed=0, box=w.scene_box)
-    lg, la = gi.lr_columns()
-    model = g.Model(sc.geo, sc.app, lg, la, max_steps=w.steps, cull_mode=1, app_layout="interleaved")
-    o3 = orc.DeferredF32(sc.geo, sc.app, lg, la)
-    n = w.n
-    cap = n // 4
-    gbuf_g = torch.zeros((cap, 10), dtype=torch.float32, device="cuda")
-    gbuf_a = torch.zeros((cap, 49), dtype=torch.float32, device="cuda")
-    for t in range(1, steps + 1):
-        cam = w.camera_for_step(t)
-        ids, count, m = run_cull(g, model, cam, t, cap=cap)
-        valid = o3.cull_current(t, cam)
-        assert m == valid.shape[0], f"step {t}"
-        assert np.array_equal(u32(ids[:m]), valid), f"step {t}"
-        g.gs_synth_grad(0, t, ids, count, gbuf_g, 0)
-        g.gs_synth_grad(0, t, ids, count, gbuf_a, 10)
-        g.gs_adam_step_deferred(model, t, ids, count, gbuf_g, gbuf_a)
-        o3.step(t, valid, *gi.step_grads(0, t, valid))
-        say(f"[aerial] step {t}: M={m} ({m / n:.4f}) restored={model.ws_header()['restored_last']}")
-    _compare_state(model, o3, f"aerial after {steps} steps")
 
 
 def test_stream_read_probe(g):
