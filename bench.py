@@ -119,10 +119,10 @@ def cpu_baseline(w, geo_all, app_all, sample, steps, lg, la):
 
 # the launches behind each timed call (the cull is three launches: tile cull,
 # group sums, prefixes + id scatter; the batched cull four)
-KERNEL_SYMBOLS = {"cull": ["k_cull", "k_tile_reduce", "k_tile_ids"], "gather": ["k_rows<0"],
-                  "adam": ["k_rows<1"], "cull_multi": ["k_cull_multi", "k_multi_reduce", "k_multi_offsets",
+KERNEL_SYMBOLS = {"cull": ["k_cull", "k_tile_reduce", "k_tile_ids"], "gather": ["k_rows_fz<0"],
+                  "adam": ["k_rows_fz<1"], "cull_multi": ["k_cull_multi", "k_multi_reduce", "k_multi_offsets",
                                                       "k_multi_ids"],
-                  "grad_sum": ["k_grad_sum"], "adam_bf16": ["k_rows<1"]}
+                  "grad_sum": ["k_grad_sum"], "adam_bf16": ["k_rows_fz<1"]}
 
 
 def source_digest():

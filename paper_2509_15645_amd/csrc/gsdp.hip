@@ -173,8 +173,9 @@ __device__ __forceinline__ float restore1(float w, float m, float v, float wd, f
 {
     const float den = sqrtf(v) + eps;
     float q = m / den;
-    if (q > rb) q = rb;
-    else if (q < -rb) q = -rb;
+    // selects, not branches: a NaN stays NaN
+    q = q > rb ? rb : q;
+    q = q < -rb ? -rb : q;
     const float wsc = wd * lr;
     return w - wsc * q;
 }
@@ -186,8 +187,8 @@ __device__ __forceinline__ float restore_w(float w, float m, float v, float wd, 
 {
     const float den = sqrtf(v) + eps;
     float q = m / den;
-    if (q > rb) q = rb;
-    else if (q < -rb) q = -rb;
+    q = q > rb ? rb : q;
+    q = q < -rb ? -rb : q;
     const float a = pd * w;
     const float b = (wd * lr) * q;
     return a - b;
@@ -384,8 +385,8 @@ __device__ __forceinline__ float adam_step(float m1, float v1, float st, float b
     const float den = sqrtf(v1) / bc + eps;
     float upd = (st * m1) / den;
     const float lim = (st * bc) * rb;
-    if (upd > lim) upd = lim;
-    else if (upd < -lim) upd = -lim;
+    upd = upd > lim ? lim : upd;
+    upd = upd < -lim ? -lim : upd;
     return upd;
 }
 
@@ -1467,6 +1468,189 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
     }
 }
 
+// ---------------------------------------------------------------------------
+// Row kernels of the common configuration: Adam, one moment storage type
+// (FP32 or BF16) for both groups, the fused layout with the moments of the
+// two groups contiguous (A w | G m, A m | G v, A v), compact gradients and
+// deferred geometry.  Same arithmetic and lane mapping as k_rows (lane c < 10
+// is G column c, lane 10 + c is A column c), with far fewer instructions a
+// row:
+//  - each lane's weight, gradient and output element is one per-lane 64-bit
+//    address, a 32 x 32 + 64-bit multiply-add of the wave-uniform row index
+//    with the lane's stride and base (G lanes: the [n][10] array; A lanes: the
+//    fused row), so G and A lanes load and store together, with no exec-mask
+//    halves and no per-row scalar bases of either group;
+//  - the moments of all lanes are one run each in the fused row: the row's
+//    scalar base plus the lane's 32-bit offset.
+// ---------------------------------------------------------------------------
+struct FastArgs {
+    const float *gw;                 // [n][10] G weights
+    char *fz;                        // fused rows (A w at offset 0)
+    int32_t *last;
+    const u32 *ids, *count;
+    const u32 *sat_ids, *sat_count;  // saturated rows (max_defer > 0)
+    const float *g_geo, *g_app;      // compact gradients (update)
+    float *out_geo, *out_app;        // compact outputs (gather)
+    const float *Mf, *Vf, *SS, *BC;
+    StepK step;
+    float lr[64];                    // lane-indexed: 0..9 G, 10.. A
+    float eps, omb1, omb2, rb;
+    u64 sr_seed;
+    u32 n, cap, adim, fz_s;          // rows, id capacity, A columns, fused row bytes
+    u32 om, ov, pad0, pad1;          // byte offsets of the G m and G v runs in the fused row
+};
+
+// Pointers into the global and the constant address space: global loads and
+// stores need no flat-address checks, and uniform loads of read-only tables
+// through a constant-space pointer become scalar loads.
+typedef __attribute__((address_space(1))) float gfloat;
+typedef __attribute__((address_space(1))) u32 gu32;
+typedef __attribute__((address_space(4))) const float cfloat;
+__device__ __forceinline__ gfloat *gptr(u64 a) { return (gfloat *)a; }
+__device__ __forceinline__ const cfloat *cptr(const float *p) { return (const cfloat *)(uintptr_t)p; }
+
+template <int MODE, int ST, int RU>
+__global__ __launch_bounds__(256) void k_rows_fz(FastArgs a)
+{
+    static_assert(MODE == kGather || MODE == kAdam, "gather and update only");
+    static_assert(ST == GS_F32 || ST == GS_BF16, "FP32 or BF16 moments");
+    static_assert(RU >= 1 && RU <= 8 && (RU & (RU - 1)) == 0, "rows per iteration: a power of two up to 8");
+    constexpr u32 MS = (u32)msize<ST>();
+    const int lane = threadIdx.x & 63;
+    const u32 wid = blockIdx.x * 4u + (u32)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const u32 nw = gridDim.x * 4u;
+    const u32 adim = a.adim;
+    const bool isG = lane < 10;
+    const bool act = (u32)lane < 10u + adim;
+    // lanes past the last column load (never store) the last column
+    const u32 col = isG ? (u32)lane : min((u32)lane - 10u, adim - 1u);
+    const u32 mcol = isG ? (u32)lane : 10u + col;
+    const u32 mo = a.om + mcol * MS, vo = a.ov + mcol * MS;
+    const u64 wb = isG ? (u64)(a.gw + lane) : (u64)(a.fz + 4u * col);
+    const u32 wst = isG ? 40u : a.fz_s;
+    const u64 cb = MODE == kAdam ? (isG ? (u64)(a.g_geo + lane) : (u64)(a.g_app + col))
+                                 : (isG ? (u64)(a.out_geo + lane) : (u64)(a.out_app + col));
+    const u32 cst = isG ? 40u : 4u * adim;
+    const float lr = a.lr[lane];
+    const float *Wrow;
+    int dmax;
+    const int t = resolve_step(a.step, 0, &Wrow, &dmax);
+    const cfloat *W4 = cptr(Wrow), *Mf4 = cptr(a.Mf), *Vf4 = cptr(a.Vf);
+    if (a.n == 0) return;
+    const u32 n = a.n;
+    u32 nvis, total;
+    {
+        const u32 c = *a.count;
+        nvis = c < a.cap ? c : a.cap;
+        total = nvis + ((MODE == kAdam && a.sat_count) ? *a.sat_count : 0u);
+    }
+    float ss = 0.0f, bc = 1.0f;
+    if (MODE == kAdam) {
+        ss = cptr(a.SS)[t];
+        bc = cptr(a.BC)[t];
+    }
+    const float step = lr * ss;
+    const u64 s_step = ST == GS_BF16 ? sm_at(a.sr_seed, (u64)t) : 0ull;
+
+    // Row bookkeeping in vector registers, lane u (mod RU) holding row u of an
+    // iteration: the iteration's ids and last steps are one load each, read
+    // into scalar registers lane by lane.  Software pipeline: the ids two
+    // iterations ahead and the last steps one iteration ahead are in flight
+    // while an iteration's rows load; positions past the end read the last
+    // position and give row 0, which is loaded but never stored.
+    const u32 stride = nw * RU;
+    const u32 lu = (u32)lane & (RU - 1u);
+    auto fetch_id = [&](u32 b) -> u32 {
+        const u32 i = min(b + lu, total - 1u);
+        const u32 *p = i < nvis ? a.ids + i : a.sat_ids + (i - nvis);
+        return *(const gu32 *)p;
+    };
+    auto valid_id = [&](u32 b, u32 raw) -> u32 { return (b + lu < total && raw < n) ? raw : 0xffffffffu; };
+    auto fetch_last = [&](u32 idv) -> int { return a.last[idv < n ? idv : 0u]; };
+    u32 base = wid * RU;
+    if (base >= total) return;
+    u32 idc = valid_id(base, fetch_id(base));
+    int lastc = fetch_last(idc);
+    u32 idn = fetch_id(base + stride);
+    for (; base < total; base += stride) {
+        // rows of this iteration (scalar)
+        u32 id[RU];
+        bool ok[RU];
+        int d[RU];
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            const u32 r = (u32)__builtin_amdgcn_readlane((int)idc, u);
+            ok[u] = r != 0xffffffffu;
+            id[u] = ok[u] ? r : 0u;
+            int dd = t - 1 - __builtin_amdgcn_readlane(lastc, u);
+            dd = dd < 0 ? 0 : (dd > dmax ? dmax : dd);
+            d[u] = ok[u] ? dd : 0;
+        }
+        // next iteration's last steps and the ids after it
+        const u32 idnv = valid_id(base + stride, idn);
+        const int lastn = fetch_last(idnv);
+        const u32 idnn = fetch_id(base + 2 * stride);
+        u32 wr[RU], gr[RU];
+        typename RawT<ST>::T mr[RU], vr[RU];
+        gfloat *wa[RU];
+        gchar *fb[RU];
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            wa[u] = gptr(wb + (u64)id[u] * (u64)wst);
+            fb[u] = srow(a.fz, id[u], a.fz_s);
+            wr[u] = __float_as_uint(*wa[u]);
+            mr[u] = mraw<ST>((const char *)(fb[u] + lane_off(mo)));
+            vr[u] = mraw<ST>((const char *)(fb[u] + lane_off(vo)));
+            gr[u] = 0u;
+            if (MODE == kAdam && base + u < nvis) gr[u] = *(const gu32 *)(cb + (u64)(base + u) * (u64)cst);
+        }
+        float Wd[RU], Mfd[RU], Vfd[RU];
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            Wd[u] = W4[d[u]];
+            if (MODE == kAdam) {
+                Mfd[u] = Mf4[d[u]];
+                Vfd[u] = Vf4[d[u]];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            const float w = __uint_as_float(wr[u]);
+            const float m = mdec<ST>((u32)mr[u], 0.0f, false);
+            const float v = mdec<ST>((u32)vr[u], 0.0f, true);
+            if (MODE == kGather) {
+                float x = w;
+                if (d[u] > 0) x = restore1(x, m, v, Wd[u], lr, a.eps, a.rb);
+                if (ok[u] && act) *gptr(cb + (u64)(base + u) * (u64)cst) = x;
+                continue;
+            }
+            const float g = __uint_as_float(gr[u]);
+            float x = w;
+            if (d[u] > 0) x = restore1(x, m, v, Wd[u], lr, a.eps, a.rb);
+            const float m1 = Mfd[u] * m + a.omb1 * g;
+            const float v1 = Vfd[u] * v + (a.omb2 * g) * g;
+            x = x - adam_step(m1, v1, step, bc, a.eps, a.rb);
+            u32 rm = 0, rv = 0;
+            if (ST == GS_BF16) {
+                const u64 h = sm_at(sm_at(s_step, (u64)id[u]), (u64)lane);
+                rm = (u32)(h & 0xffffull);
+                rv = (u32)((h >> 16) & 0xffffull);
+            }
+            if (ok[u]) {
+                if (act) {
+                    *wa[u] = x;
+                    mstore<ST>((char *)(fb[u] + lane_off(mo)), 0.0f, m1, rm, false);
+                    mstore<ST>((char *)(fb[u] + lane_off(vo)), 0.0f, v1, rv, true);
+                }
+                if (lane == 0) a.last[id[u]] = t;
+            }
+        }
+        idc = idnv;
+        lastc = lastn;
+        idn = idnn;
+    }
+}
+
 // FP8 scale growth between the two Adam passes: every 128-row block whose
 // recorded max outgrew its scale gets the smallest power-of-two scale that
 // fits, and all its rows are re-encoded (random column = column + 64); the
@@ -1874,6 +2058,46 @@ void fill_rows(RowArgs &a, const gs_model *m)
     a.n = m->n;
 }
 
+// The configuration of k_rows_fz: Adam, both groups' moments in FP32 or both
+// in BF16, deferred geometry, G w dense, and the fused layout with the G and
+// A moment runs adjacent (A m right after G m, A v right after G v).  Fills
+// everything but the per-call pointers; false when the model does not qualify.
+bool fill_fast(FastArgs &f, const gs_model *m)
+{
+    memset(&f, 0, sizeof f);
+    if (m->optimizer != GS_OPT_ADAM || m->geo_mode != 0) return false;
+    const int st = m->geo.state;
+    if (st != m->app.state || (st != GS_F32 && st != GS_BF16)) return false;
+    if (m->geo.w_ld != 10 || m->n <= 0 || m->n > 0x7fffffff) return false;
+    u32 S, ogm, ogv, oam, oav;
+    if (!fused_layout(m, &S, &ogm, &ogv, &oam, &oav)) return false;
+    const u32 ms = (u32)mom_bytes(st);
+    if (oam != ogm + 10u * ms || oav != ogv + 10u * ms) return false;
+    f.gw = m->geo.w;
+    f.fz = reinterpret_cast<char *>(m->app.w);
+    f.last = m->last_step;
+    for (int c = 0; c < 10; ++c) f.lr[c] = m->geo.lr[c];
+    for (int c = 0; c < m->app.dim; ++c) f.lr[10 + c] = m->app.lr[c];
+    f.eps = (float)m->eps;
+    f.omb1 = (float)(1.0 - m->beta1);
+    f.omb2 = (float)(1.0 - m->beta2);
+    f.rb = restore_bound(m->beta1, m->beta2);
+    f.sr_seed = m->sr_seed;
+    f.n = (u32)m->n;
+    f.adim = (u32)m->app.dim;
+    f.fz_s = S;
+    f.om = ogm;
+    f.ov = ogv;
+    return true;
+}
+
+template <int MODE, int RU>
+void launch_fast(int st, int grid, hipStream_t s, const FastArgs &f)
+{
+    if (st == GS_F32) hipLaunchKernelGGL((k_rows_fz<MODE, GS_F32, RU>), dim3(grid), dim3(256), 0, s, f);
+    else hipLaunchKernelGGL((k_rows_fz<MODE, GS_BF16, RU>), dim3(grid), dim3(256), 0, s, f);
+}
+
 // Camera constants of cull_v1 and of the band classifier (bounds rounded up).
 void pack_camera(const gs_model *model, const gs_camera *cam, CamK &k, BandK &b)
 {
@@ -1948,6 +2172,8 @@ void launch_rows(const gs_model *m, int grid, hipStream_t st, const RowArgs &a)
 }
 
 constexpr int kRowBlocksGather = 8, kRowBlocksUpdate = 16;
+// rows per wavefront iteration of k_rows_fz
+constexpr int kFastGatherRows = 2, kFastUpdateRows = 4;
 // blocks of a row launch: one iteration's rows per wavefront at least, at most
 // `per_cu` blocks per CU (the gather runs best at 8, the update passes at 16,
 // where short and long wavefronts even out)
@@ -3020,6 +3246,18 @@ int gs_gather(const gs_model *model, int64_t step, const uint32_t *ids, const ui
     if (!count_dev || (capacity > 0 && !ids)) return GS_EINVAL;
     if (!step_ok(model, step)) return GS_EINVAL;
     if (capacity == 0 || (!out_geo && !out_app)) return GS_OK;
+    FastArgs f;
+    if (out_geo && out_app && fill_fast(f, model)) {
+        f.step = step_k(model, step);
+        f.ids = ids;
+        f.count = count_dev;
+        f.cap = capacity;
+        f.out_geo = out_geo;
+        f.out_app = out_app;
+        launch_fast<kGather, kFastGatherRows>(model->geo.state, row_grid(capacity, kRowBlocksGather),
+                                              (hipStream_t)stream, f);
+        return launched("gs_gather");
+    }
     RowArgs a;
     fill_rows(a, model);
     a.step = step_k(model, step);
@@ -3157,6 +3395,24 @@ int gs_adam_step_deferred(const gs_model *model, int64_t step, const uint32_t *i
                            (hipStream_t)stream, ra);
         rc1 = launched("gs_adam_step_deferred (fp8 rescale)");
         if (rc1) return rc1;
+    }
+    FastArgs f;
+    if (compact && !geo_dense && fill_fast(f, model)) {
+        f.step = a.step;
+        f.ids = ids;
+        f.count = count_dev;
+        f.cap = capacity;
+        f.sat_ids = a.sat_ids;
+        f.sat_count = a.sat_count;
+        f.g_geo = g_geo;
+        f.g_app = g_app;
+        f.Mf = a.Mf;
+        f.Vf = a.Vf;
+        f.SS = a.SS;
+        f.BC = a.BC;
+        launch_fast<kAdam, kFastUpdateRows>(model->geo.state, row_grid(rows, kRowBlocksUpdate), (hipStream_t)stream,
+                                            f);
+        return launched("gs_adam_step_deferred");
     }
     launch_rows<kAdam>(model, row_grid(rows, kRowBlocksUpdate), (hipStream_t)stream, a);
     return launched("gs_adam_step_deferred");

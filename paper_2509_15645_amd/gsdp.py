@@ -244,14 +244,16 @@ class Model:
             self.geo_m = torch.zeros((n, 10), dtype=gdt, device=device)
             self.geo_v = torch.zeros((n, 10), dtype=gdt, device=device)
         if app_layout == "fused":
-            # one byte row per Gaussian: A w | A m | A v | G m | G v, padded to 64 bytes,
-            # so a visible row's state is a single contiguous span
+            # one byte row per Gaussian: A w | G m, A m | G v, A v, padded to 64 bytes,
+            # so a visible row's state is a single contiguous span and each moment
+            # of all 10 + dim columns is one run (lane c of a row kernel at c)
             wbytes, mbytes, gbytes = 4 * adim, asz * adim, gsz * 10
-            o_am, o_av = wbytes, wbytes + mbytes
-            o_gm = wbytes + 2 * mbytes
-            o_gm = (o_gm + gsz - 1) // gsz * gsz
-            o_gv = o_gm + gbytes
-            row = (o_gv + gbytes + 63) // 64 * 64
+            o_gm = wbytes
+            o_am = o_gm + gbytes
+            o_gv = o_am + mbytes
+            o_gv = (o_gv + gsz - 1) // gsz * gsz
+            o_av = o_gv + gbytes
+            row = (o_av + mbytes + 63) // 64 * 64
             assert row % 4 == 0 and row % asz == 0 and row % gsz == 0
             self.app_state_bytes = torch.zeros((n, row), dtype=torch.uint8, device=device)
             st = self.app_state_bytes

@@ -230,6 +230,9 @@ def _compare_state(model, o3, tag):
     (0, "separate", "dense", 0, ("bf16", "fp8"), 0, False),
     (0, "fused", "compact", 1, ("f32", "f32"), 0, False),
     (15, "fused", "compact", 1, ("bf16", "fp8"), 0, False),
+    (15, "fused", "compact", 1, ("bf16", "bf16"), 0, False),
+    (0, "fused", "compact", 0, ("f32", "f32"), 0, True),
+    (15, "fused", "dense", 1, ("f32", "f32"), 0, False),
     (15, "interleaved", "compact", 1, ("f32", "f32"), 0, True),
     (0, "separate", "dense", 0, ("f32", "f32"), 1, True),
 ])
