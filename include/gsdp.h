@@ -196,6 +196,26 @@ int gs_workspace_bytes(const gs_model *model, size_t *bytes);
 int gs_cull(const gs_model *model, const gs_camera *cam, int64_t step, uint32_t *ids,
             uint32_t *count_dev, uint32_t capacity, void *ws, size_t ws_bytes, void *stream);
 
+/* gs_cull for callers that cannot allocate device memory (code under hipGraph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * cull and ordered compaction, same ids and count, with the workspace taken
+ * from an array of GS_CULL_NOALLOC_MAX_WS bytes that the library keeps in the
+ * memory of each GPU it runs on until the process ends, instead of `ws`.
+ * Calls no allocating routine.
+ *   - Limit: the model's workspace (gs_workspace_bytes with max_defer = 0)
+ *     must fit the array, about 97M Gaussians; larger models get GS_ESPACE
+ *     (text in gs_last_hip_error).
+ *   - max_defer > 0 and geo_mode = 1 return GS_EUNSUPPORTED: the update that
+ *     follows those culls reads the cull's workspace, which the caller cannot
+ *     reach here.
+ *   - Every call on one GPU uses that GPU's one array: calls that overlap in
+ *     time on one GPU (two streams, two host threads) race and give wrong
+ *     ids.  Serialise them.  The workspace header's diagnostic counters are
+ *     shared by all models culled this way. */
+#define GS_CULL_NOALLOC_MAX_WS ((size_t)16 << 20)
+int gs_cull_noalloc(const gs_model *model, const gs_camera *cam, int64_t step, uint32_t *ids,
+                    uint32_t *count_dev, uint32_t capacity, void *stream);
+
 /* Gather: out_geo[i][0..10) and out_app[i][0..dim) = current values of row
  * ids[i] before update `step`, for i < min(*count_dev, capacity).  Deferred
  * rows are restored with the w_scale LUT and their stored moments (Eq. 3);

@@ -38,6 +38,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "gsdp.h"
@@ -2985,6 +2986,44 @@ int launch_multi(int variant, const MultiArgs &a, int64_t n, hipStream_t st)
 
 }  // namespace
 
+namespace {
+
+int cull_launch(const gs_model *model, const gs_camera *cam, int64_t step, uint32_t *ids, uint32_t *count_dev,
+                uint32_t capacity, char *wsb, hipStream_t st);
+
+// Workspace of gs_cull_noalloc: one array per GPU, zero at load (static
+// storage), held until the process ends.  Host code must not pass `scratch`
+// itself to a kernel (on the host it names a host-side stand-in); its device
+// address comes from hipGetSymbolAddress once per device, with that device
+// current, and only that address is used.
+__device__ __align__(256) unsigned char scratch[GS_CULL_NOALLOC_MAX_WS];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char *g_scratch_dev[kMaxDevices];
+
+int scratch_ptr(char **out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        snprintf(g_err, sizeof g_err, "gs_cull_noalloc: no usable current device (%d)", dev);
+        return GS_EHIP;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            snprintf(g_err, sizeof g_err, "gs_cull_noalloc: hipGetSymbolAddress: %s", hipGetErrorString(e));
+            return GS_EHIP;
+        }
+        g_scratch_dev[dev] = static_cast<char *>(p);
+    }
+    *out = g_scratch_dev[dev];
+    return GS_OK;
+}
+
+}  // namespace
+
 // ===========================================================================
 // C ABI
 // ===========================================================================
@@ -3156,7 +3195,41 @@ int gs_cull(const gs_model *model, const gs_camera *cam, int64_t step, uint32_t 
     if (!(cam->fx > 0.0f && cam->fy > 0.0f) || cam->width <= 0 || cam->height <= 0) return GS_EINVAL;
     if (!aligned(ws, 256)) return GS_EINVAL;
     if ((int64_t)ws_bytes < gsdp::ws_bytes_for(model->n, model->max_defer, has_fp8(model))) return GS_ESPACE;
+    return cull_launch(model, cam, step, ids, count_dev, capacity, static_cast<char *>(ws), (hipStream_t)stream);
+}
 
+int gs_cull_noalloc(const gs_model *model, const gs_camera *cam, int64_t step, uint32_t *ids, uint32_t *count_dev,
+                    uint32_t capacity, void *stream)
+{
+    int rc = check_model(model);
+    if (rc) return rc;
+    if (!cam || !count_dev || (capacity > 0 && !ids)) return GS_EINVAL;
+    if (!step_ok(model, step)) return GS_EINVAL;
+    if (!(cam->fx > 0.0f && cam->fy > 0.0f) || cam->width <= 0 || cam->height <= 0) return GS_EINVAL;
+    // the saturated-row list and the dense geometric update read this cull's
+    // workspace in the following update call, which cannot reach the array
+    if (model->max_defer != 0 || model->geo_mode != 0) return GS_EUNSUPPORTED;
+    if (gsdp::ws_bytes_for(model->n, 0, 0) > (int64_t)GS_CULL_NOALLOC_MAX_WS) {
+        snprintf(g_err, sizeof g_err, "gs_cull_noalloc: the model needs %lld workspace bytes, the library's "
+                 "array holds %lld", (long long)gsdp::ws_bytes_for(model->n, 0, 0),
+                 (long long)GS_CULL_NOALLOC_MAX_WS);
+        return GS_ESPACE;
+    }
+    char *wsb = nullptr;
+    rc = scratch_ptr(&wsb);
+    if (rc) return rc;
+    return cull_launch(model, cam, step, ids, count_dev, capacity, wsb, (hipStream_t)stream);
+}
+
+}  // extern "C"
+
+namespace {
+
+// The cull and ordered compaction of gs_cull on the workspace `wsb` (checked
+// by the caller).
+int cull_launch(const gs_model *model, const gs_camera *cam, int64_t step, uint32_t *ids, uint32_t *count_dev,
+                uint32_t capacity, char *wsb, hipStream_t st)
+{
     CullArgs a;
     memset(&a, 0, sizeof a);
     a.gw = model->geo.w;
@@ -3190,7 +3263,6 @@ int gs_cull(const gs_model *model, const gs_camera *cam, int64_t step, uint32_t 
     pack_camera(model, cam, a.cam, a.band);
     a.geo_dense = model->geo_mode == 1;
     a.K = model->max_defer;
-    char *wsb = static_cast<char *>(ws);
     const int64_t n = model->n;
     a.tiles = gsdp::cull_tiles(n);
     a.tile_vs = reinterpret_cast<u64 *>(wsb + gsdp::ws_cnt_offset(n));
@@ -3198,7 +3270,6 @@ int gs_cull(const gs_model *model, const gs_camera *cam, int64_t step, uint32_t 
     a.keep_bits = reinterpret_cast<u64 *>(wsb + gsdp::ws_keep_offset(n));
     a.sat_bits = model->max_defer > 0 ? reinterpret_cast<u64 *>(wsb + gsdp::ws_satbits_offset(n)) : nullptr;
     if (a.tiles > 0x7fffffff) return GS_EINVAL;
-    hipStream_t st = (hipStream_t)stream;
     if (a.tiles > 0) {
         // geometry and last step: 44 bytes a row
         if ((int64_t)n * 44 > kLastLevelCacheBytes)
@@ -3237,6 +3308,10 @@ int gs_cull(const gs_model *model, const gs_camera *cam, int64_t step, uint32_t 
     else hipLaunchKernelGGL(k_tile_ids<false>, ig, dim3(kIdsThreads), 0, st, ia);
     return launched("gs_cull");
 }
+
+}  // namespace
+
+extern "C" {
 
 int gs_gather(const gs_model *model, int64_t step, const uint32_t *ids, const uint32_t *count_dev,
               uint32_t capacity, float *out_geo, float *out_app, void *stream)

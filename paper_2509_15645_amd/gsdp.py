@@ -29,7 +29,7 @@ SYMBOLS = ("gs_lut_bytes", "gs_lut_build", "gs_lut_build_host", "gs_lut_build_sc
            "gs_camera_pack_bytes", "gs_camera_pack", "gs_multi_workspace_bytes", "gs_cull_multi",
            "gs_cull_multi_autotune", "gs_grad_sum_multi", "gs_plan_image_split", "gs_lut_build_sgd_momentum",
            "gs_lut_build_sgd_momentum_host", "gs_lut_bytes_adamw", "gs_lut_build_adamw", "gs_lut_build_adamw_host",
-           "gs_densify_workspace_bytes", "gs_densify_plan", "gs_densify_apply")
+           "gs_densify_workspace_bytes", "gs_densify_plan", "gs_densify_apply", "gs_cull_noalloc")
 
 
 class GsCamera(C.Structure):
@@ -84,6 +84,7 @@ def _load():
         "gs_densify_plan": (C.c_int, [P(GsModel), vp, vp, vp, vp, vp, sz, vp, P(C.c_int64), vp]),
         "gs_densify_apply": (C.c_int, [P(GsModel), vp, P(GsModel), i64, vp, sz, vp]),
         "gs_cull": (C.c_int, [P(GsModel), P(GsCamera), i64, vp, vp, u32, vp, sz, vp]),
+        "gs_cull_noalloc": (C.c_int, [P(GsModel), P(GsCamera), i64, vp, vp, u32, vp]),
         "gs_gather": (C.c_int, [P(GsModel), i64, vp, vp, u32, vp, vp, vp]),
         "gs_scatter_grad": (C.c_int, [vp, vp, u32, i32, vp, vp, i32, vp]),
         "gs_adam_step_deferred": (C.c_int, [P(GsModel), i64, vp, vp, u32, vp, vp, vp, vp, vp, sz, vp]),
@@ -376,6 +377,14 @@ def gs_cull(model: Model, cam, step: int, ids: torch.Tensor, count: torch.Tensor
     camc = cam if isinstance(cam, GsCamera) else camera_struct(cam)
     _check(lib.gs_cull(C.byref(model.c), C.byref(camc), int(step), _ptr(ids), _ptr(count), cap,
                        _ptr(model.ws), model.ws_bytes, _stream(stream)), "gs_cull")
+
+
+def gs_cull_noalloc(model: Model, cam, step: int, ids: torch.Tensor, count: torch.Tensor, capacity=None,
+                    stream=None):
+    cap = ids.numel() if capacity is None else int(capacity)
+    camc = cam if isinstance(cam, GsCamera) else camera_struct(cam)
+    _check(lib.gs_cull_noalloc(C.byref(model.c), C.byref(camc), int(step), _ptr(ids), _ptr(count), cap,
+                               _stream(stream)), "gs_cull_noalloc")
 
 
 def gs_gather(model: Model, step: int, ids, count, out_geo, out_app, capacity=None, stream=None):

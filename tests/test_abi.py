@@ -276,3 +276,43 @@ def test_densify_and_optimizer_checks_need_no_device(gsdp):
         assert L.gs_adam_flush(C.byref(mo), 1, None) == gsdp.GS_EUNSUPPORTED
     mu, keepu = _host_model(gsdp, opt=7)
     assert L.gs_adam_flush(C.byref(mu), 1, None) == gsdp.GS_EINVAL
+
+
+def _fake_model(gsdp, n):
+    """A model that passes the argument checks; its pointers are never
+    dereferenced because every call below fails a check first."""
+    m = gsdp.GsModel()
+    m.n = n
+    fake = 1 << 20
+    for g, dim in ((m.geo, 10), (m.app, 49)):
+        g.w = g.m = g.v = fake
+        g.dim = g.w_ld = g.m_ld = g.v_ld = dim
+        g.state = gsdp.GS_F32
+    m.last_step = fake
+    m.lut = fake
+    m.lut_max_steps = 10
+    m.beta1, m.beta2, m.eps = 0.9, 0.999, 1e-15
+    return m
+
+
+def test_cull_noalloc_checks_need_no_device(gsdp):
+    L = gsdp.lib
+    cam = gsdp.GsCamera()
+    cam.fx = cam.fy = 1000.0
+    cam.width, cam.height = 64, 64
+    ids = C.c_void_p(1 << 20)
+    m = _fake_model(gsdp, 1000)
+    m.max_defer = 15
+    assert L.gs_cull_noalloc(C.byref(m), C.byref(cam), 1, ids, ids, 16, None) == gsdp.GS_EUNSUPPORTED
+    m.max_defer = 0
+    m.geo_mode = 1
+    assert L.gs_cull_noalloc(C.byref(m), C.byref(cam), 1, ids, ids, 16, None) == gsdp.GS_EUNSUPPORTED
+    m.geo_mode = 0
+    assert L.gs_cull_noalloc(C.byref(m), C.byref(cam), 11, ids, ids, 16, None) == gsdp.GS_EINVAL
+    assert L.gs_cull_noalloc(C.byref(m), C.byref(cam), 1, ids, None, 16, None) == gsdp.GS_EINVAL
+    # a model whose workspace exceeds the library's array is refused with a message
+    big = _fake_model(gsdp, 0x7FFFFFFF)
+    b = C.c_size_t()
+    assert L.gs_workspace_bytes(C.byref(big), C.byref(b)) == 0 and b.value > (16 << 20)
+    assert L.gs_cull_noalloc(C.byref(big), C.byref(cam), 1, ids, ids, 16, None) == gsdp.GS_ESPACE
+    assert b"workspace" in L.gs_last_hip_error()

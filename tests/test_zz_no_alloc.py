@@ -1,0 +1,69 @@
+"""gs_cull_noalloc (the cull whose workspace is the library's own per-GPU
+array) against gs_cull on the caller's workspace: ids and counts bit-exact on
+two calls in a row, the second on a smaller model (run with -m gpu)."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import gs_inputs as gi
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def g():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2509_15645_amd import gsdp
+    return gsdp
+
+
+def _model(g, n, seed):
+    sc = gi.make_scene(n, seed=seed)
+    lg, la = gi.lr_columns()
+    return g.Model(sc.geo, sc.app, lg, la, max_steps=8, cull_mode=1)
+
+
+@pytest.mark.parametrize("order", ["large_then_small", "small_again"])
+def test_cull_noalloc_matches_cull(g, order):
+    cams = gi.orbit_cameras(4, seed=3)
+    sizes = (300_007, 40_001) if order == "large_then_small" else (40_001, 12_345)
+    for call, n in enumerate(sizes):
+        say(f"[noalloc] {order} call {call}: n={n}")
+        model = _model(g, n, seed=20 + call)
+        # take one deferred step first so the cull restores rows (band classifier path)
+        ids = torch.zeros(n, dtype=torch.int32, device="cuda")
+        count = torch.zeros(1, dtype=torch.int32, device="cuda")
+        g.gs_cull(model, cams[0], 1, ids, count)
+        gg = torch.empty((n, 10), dtype=torch.float32, device="cuda")
+        ga = torch.empty((n, 49), dtype=torch.float32, device="cuda")
+        g.gs_synth_grad(0, 1, ids, count, gg, 0)
+        g.gs_synth_grad(0, 1, ids, count, ga, 10)
+        g.gs_adam_step_deferred(model, 1, ids, count, gg, ga)
+        for t, cam in ((2, cams[1]), (3, cams[2])):
+            ref_ids = torch.full((n,), -1, dtype=torch.int32, device="cuda")
+            ref_cnt = torch.zeros(1, dtype=torch.int32, device="cuda")
+            got_ids = torch.full((n,), -1, dtype=torch.int32, device="cuda")
+            got_cnt = torch.zeros(1, dtype=torch.int32, device="cuda")
+            g.gs_cull(model, cam, t, ref_ids, ref_cnt)
+            g.gs_cull_noalloc(model, cam, t, got_ids, got_cnt)
+            # a capacity below the count: only that many ids, the true count
+            cap = max(1, int(ref_cnt.item()) // 3)
+            part_ids = torch.full((n,), -1, dtype=torch.int32, device="cuda")
+            part_cnt = torch.zeros(1, dtype=torch.int32, device="cuda")
+            g.gs_cull_noalloc(model, cam, t, part_ids, part_cnt, capacity=cap)
+            torch.cuda.synchronize()
+            m = int(ref_cnt.item())
+            assert 0 < m < n
+            assert int(got_cnt.item()) == m
+            assert np.array_equal(got_ids.cpu().numpy(), ref_ids.cpu().numpy())
+            assert int(part_cnt.item()) == m
+            pi = part_ids.cpu().numpy()
+            assert np.array_equal(pi[:cap], ref_ids.cpu().numpy()[:cap]) and np.all(pi[cap:] == -1)
+            say(f"[noalloc] {order} call {call} step {t}: M={m} ids bit-exact")
+        del model
