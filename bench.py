@@ -120,7 +120,7 @@ def cpu_baseline(w, geo_all, app_all, sample, steps, lg, la):
 # the launches behind each timed call (the cull is three launches: tile cull,
 # group sums, prefixes + id scatter; the batched cull four)
 KERNEL_SYMBOLS = {"cull": ["k_cull", "k_tile_reduce", "k_tile_ids"], "gather": ["k_rows_fz<0"],
-                  "adam": ["k_rows_fz<1"], "cull_multi": ["k_cull_multi", "k_multi_reduce", "k_multi_offsets",
+                  "adam": ["k_rows_fz<1"], "cull_multi": ["k_cull_multi", "k_multi_reduce", "k_multi_gscan", "k_multi_offsets",
                                                       "k_multi_ids"],
                   "grad_sum": ["k_grad_sum"], "adam_bf16": ["k_rows_fz<1"]}
 
@@ -170,8 +170,9 @@ def morton_order(pos, box):
 
 
 def run_batched(args):
-    """16 scenes of log-uniform size (0.5M-8M) x 32 cameras per step: one
-    batched cull+compaction launch, deterministic per-camera gradient sum,
+    """16 scenes of log-uniform size (0.5M-8M) x 32 cameras per step: the
+    batched cull + compaction, the gather of the union's current rows (once
+    for all cameras), the deterministic per-camera gradient sum and the
     BF16-moment deferred Adam on the union; the step is captured in a hipGraph
     with a device step counter and replayed."""
     import torch
@@ -220,11 +221,14 @@ def run_batched(args):
     g_cam.normal_(0.0, 1e-3, generator=torch.Generator(device=dev).manual_seed(5))
     out_g = torch.zeros((N, 10), dtype=torch.float32, device=dev)
     out_a = torch.zeros((N, 49), dtype=torch.float32, device=dev)
+    gath_g = torch.zeros((N, 10), dtype=torch.float32, device=dev)
+    gath_a = torch.zeros((N, 49), dtype=torch.float32, device=dev)
     model.step_dev.fill_(1)
     setup_s = time.perf_counter() - t_setup
 
     def step_dev_only():
         gsdp.gs_cull_multi(model, multi, 0)
+        gsdp.gs_gather(model, 0, multi.union_ids, multi.union_count, gath_g, gath_a, capacity=multi.cap_union)
         gsdp.gs_grad_sum_multi(multi, 49, g_cam, out_g, out_a)
         gsdp.gs_adam_step_deferred(model, 0, multi.union_ids, multi.union_count, out_g, out_a,
                                    capacity=multi.cap_union)
@@ -249,30 +253,35 @@ def run_batched(args):
     ms_step = (t1 - t0) * 1e3 / args.steps
     # per-kernel attribution: the same steps eagerly with HIP events
     stream = torch.cuda.current_stream()
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(3)]
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(3)]
     U_tot, cc_tot = 0, 0
     for k in range(3):
         ev[k][0].record(stream)
         gsdp.gs_cull_multi(model, multi, 0)
         ev[k][1].record(stream)
-        gsdp.gs_grad_sum_multi(multi, 49, g_cam, out_g, out_a)
+        gsdp.gs_gather(model, 0, multi.union_ids, multi.union_count, gath_g, gath_a, capacity=multi.cap_union)
         ev[k][2].record(stream)
+        gsdp.gs_grad_sum_multi(multi, 49, g_cam, out_g, out_a)
+        ev[k][3].record(stream)
         gsdp.gs_adam_step_deferred(model, 0, multi.union_ids, multi.union_count, out_g, out_a,
                                    capacity=multi.cap_union)
-        ev[k][3].record(stream)
+        ev[k][4].record(stream)
         gsdp.gs_step_advance(model.step_dev)
         torch.cuda.synchronize()
         U_tot += int(multi.union_count.item())
         cc_tot += int(multi.cam_count.sum().item())
     if int(multi.cam_count.max().item()) > cap_cam:
         raise RuntimeError("camera list capacity exceeded")
-    k_ms = np.array([[e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2]), e[2].elapsed_time(e[3])] for e in ev]).mean(0)
+    k_ms = np.array([[e[i].elapsed_time(e[i + 1]) for i in range(4)] for e in ev]).mean(0)
     U, CC = U_tot / 3.0, cc_tot / 3.0
     sg = 4 if (args.geo_state or "bf16") == "f32" else 2
     cull_bytes = 44.0 * N + 4.0 * U + 4.0 * CC
+    # gather: id + last step + G w and A w, m, v (+ G m, v) + the 236-byte output row
+    gather_bytes = U * (4 + 4 + 40 + 2 * 10 * sg + 49 * (4 + 2 * 2) + 236)
     sum_bytes = CC * (D * 4 + 4) + U * D * 4
     adam_bytes = U * (12 + 10 * (12 + 4 * sg) + 49 * (12 + 4 * 2))
-    kern = {"cull_multi": (k_ms[0], cull_bytes), "grad_sum": (k_ms[1], sum_bytes), "adam_bf16": (k_ms[2], adam_bytes)}
+    kern = {"cull_multi": (k_ms[0], cull_bytes), "gather": (k_ms[1], gather_bytes), "grad_sum": (k_ms[2], sum_bytes),
+            "adam_bf16": (k_ms[3], adam_bytes)}
     dom = max(kern, key=lambda k: kern[k][0])
     achieved = kern[dom][1] / (kern[dom][0] * 1e-3) / 1e9
     out = {

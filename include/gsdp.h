@@ -310,9 +310,14 @@ int gs_multi_workspace_bytes(const gs_model *model, size_t *bytes);
 int gs_cull_multi(const gs_model *model, const gs_multi *desc, int64_t step, void *ws, size_t ws_bytes,
                   void *stream);
 
-/* Times every (block size, rows per thread) variant of gs_cull_multi on the
- * given inputs (synchronising `stream`), stores the fastest in desc->variant
- * and, when times_ms is not NULL, each variant's mean time. */
+/* Times every variant of gs_cull_multi on the given inputs (synchronising
+ * `stream`), stores the fastest in desc->variant and, when times_ms is not
+ * NULL, each variant's mean time (times_ms holds GS_MULTI_VARIANTS floats).
+ * Variant v = (block size, rows per thread): 0..4 = (64; 1, 2, 4, 8, 16),
+ * 5..8 = (128; 1, 2, 4, 8), 9..11 = (256; 1, 2, 4), 12..13 = (512; 1, 2),
+ * 14 = (1024, 1).  A tile of block x rows is at most 1024 rows because a tile
+ * must lie inside one scene. */
+#define GS_MULTI_VARIANTS 15
 int gs_cull_multi_autotune(const gs_model *model, gs_multi *desc, int64_t step, void *ws, size_t ws_bytes,
                            void *stream, float *times_ms, int32_t *n_variants);
 

@@ -2201,7 +2201,7 @@ int row_grid(int64_t rows, int per_cu)
 // from per-tile counts of 33 counters (union and 32 camera slots).
 constexpr int kMaxCams = 32;
 constexpr int kNCnt = kMaxCams + 1;
-constexpr int kMultiMinTile = 128;
+constexpr int kMultiMinTile = 64;
 
 struct CamPack {                     // one camera with its band-classifier constants
     CamK cam;
@@ -2375,10 +2375,11 @@ __global__ __launch_bounds__(BLOCK) void k_cull_multi(MultiArgs a)
     }
 }
 
-// Exclusive prefixes over tiles of every counter in two launches of many
-// blocks: k_multi_reduce sums each group of 64 tiles (one wavefront per group);
-// k_multi_offsets (one block per group) adds the sums of the earlier groups and
-// scans the group's tiles; the last group's block writes the totals.
+// Exclusive prefixes over tiles of every counter in three launches:
+// k_multi_reduce sums each group of 64 tiles (one wavefront per group);
+// k_multi_gscan scans the group sums of each counter (one block per counter)
+// and writes the totals; k_multi_offsets (one wavefront per group) scans the
+// group's tiles on top of its group prefix.
 __global__ __launch_bounds__(256) void k_multi_reduce(MultiArgs a)
 {
     const int lane = threadIdx.x & 63;
@@ -2393,39 +2394,41 @@ __global__ __launch_bounds__(256) void k_multi_reduce(MultiArgs a)
     }
 }
 
+// Exclusive prefix over the groups of one counter (block j = counter j), in
+// place, and that counter's total: linear in the number of groups.
+__global__ __launch_bounds__(kScanThreads) void k_multi_gscan(MultiArgs a)
+{
+    __shared__ u64 sV[kScanChunk];
+    __shared__ u64 sWave[kScanThreads / 64 + 1];
+    const int j = blockIdx.x;
+    const int64_t groups = (a.tiles + 63) / 64;
+    u32 *g = a.grp + (int64_t)j * a.gstride;
+    const u64 tot = scan_counts_u32(g, g, groups, sV, sWave);
+    if (threadIdx.x == 0) {
+        if (j == 0) *a.union_count = (u32)tot;
+        else a.cam_count[j - 1] = (u32)tot;
+    }
+}
+
+// One wavefront per group of 64 tiles: the group's prefix (from
+// k_multi_gscan) plus the scan of its tiles' counts, for every counter.
 __global__ __launch_bounds__(256) void k_multi_offsets(MultiArgs a)
 {
-    __shared__ u64 sRed[4][kNCnt];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int64_t g = blockIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int64_t g = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int64_t groups = (a.tiles + 63) / 64;
-    const bool last = g == (groups > 0 ? groups - 1 : 0);
-    const int ncnt = 1 + a.C;
-    for (int j = 0; j < ncnt; ++j) {
-        u64 base = 0;
-        for (int64_t i = tid; i < g; i += 256) base += a.grp[(int64_t)j * a.gstride + i];
-        base = wave_sum_u64(base);
-        if (lane == 0) sRed[wave][j] = base;
-    }
-    __syncthreads();
-    if (wave == 0) {
-        const int64_t tile = g * 64 + lane;
-        for (int j = 0; j < ncnt; ++j) {
-            const u64 base = (sRed[0][j] + sRed[1][j]) + (sRed[2][j] + sRed[3][j]);
-            const u64 c = (g < groups && tile < a.tiles) ? (u64)a.cnt[(int64_t)j * a.stride + tile] : 0ull;
-            u64 inc = c;
+    if (g >= groups) return;
+    const int64_t tile = g * 64 + lane;
+    for (int j = 0; j < 1 + a.C; ++j) {
+        const u64 base = a.grp[(int64_t)j * a.gstride + g];
+        const u64 c = tile < a.tiles ? (u64)a.cnt[(int64_t)j * a.stride + tile] : 0ull;
+        u64 inc = c;
 #pragma unroll
-            for (int o = 1; o < 64; o <<= 1) {
-                const u64 y = (u64)__shfl_up((long long)inc, o);
-                if (lane >= o) inc += y;
-            }
-            if (g < groups && tile < a.tiles) a.off[(int64_t)j * a.stride + tile] = (u32)(base + inc - c);
-            if (last && lane == 63) {
-                const u32 tot = (u32)(base + inc);
-                if (j == 0) *a.union_count = tot;
-                else a.cam_count[j - 1] = tot;
-            }
+        for (int o = 1; o < 64; o <<= 1) {
+            const u64 y = (u64)__shfl_up((long long)inc, o);
+            if (lane >= o) inc += y;
         }
+        if (tile < a.tiles) a.off[(int64_t)j * a.stride + tile] = (u32)(base + inc - c);
     }
 }
 
@@ -2895,9 +2898,10 @@ __global__ __launch_bounds__(kCullBlock) void k_dens_apply(DensArgs a)
 
 namespace {
 
-// autotuned variants of the batched cull: (block size, rows per thread) =
-// (128, 1), (128, 2), (128, 4), (256, 1), (256, 2), (256, 4)
-constexpr int kMultiVariants = 6;
+// autotuned variants of the batched cull: (block size, rows per thread) with
+// block in 64..1024 and a tile of block x rows <= 1024 rows (scenes start at
+// multiples of 1024 rows and a tile must lie in one scene)
+constexpr int kMultiVariants = GS_MULTI_VARIANTS;
 
 int64_t multi_ws_bytes(int64_t n)
 {
@@ -2965,8 +2969,10 @@ void launch_multi_t(MultiArgs a, int64_t n, int64_t max_tiles, hipStream_t st)
     a.tile_rows = TR;
     if (a.tiles > 0) hipLaunchKernelGGL((k_cull_multi<BLOCK, IPT>), dim3((unsigned)a.tiles), dim3(BLOCK), 0, st, a);
     const int64_t groups = (a.tiles + 63) / 64;
-    if (groups > 0) hipLaunchKernelGGL(k_multi_reduce, dim3((unsigned)((groups + 3) / 4)), dim3(256), 0, st, a);
-    hipLaunchKernelGGL(k_multi_offsets, dim3((unsigned)(groups > 0 ? groups : 1)), dim3(256), 0, st, a);
+    const unsigned gblocks = (unsigned)((groups + 3) / 4);
+    if (groups > 0) hipLaunchKernelGGL(k_multi_reduce, dim3(gblocks), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_multi_gscan, dim3((unsigned)(1 + a.C)), dim3(kScanThreads), 0, st, a);
+    if (groups > 0) hipLaunchKernelGGL(k_multi_offsets, dim3(gblocks), dim3(256), 0, st, a);
     if (a.tiles > 0) hipLaunchKernelGGL((k_multi_ids<BLOCK, IPT>), dim3((unsigned)a.tiles), dim3(BLOCK), 0, st, a);
 }
 
@@ -2974,12 +2980,21 @@ int launch_multi(int variant, const MultiArgs &a, int64_t n, hipStream_t st)
 {
     const int64_t max_tiles = (n + kMultiMinTile - 1) / kMultiMinTile;
     switch (variant) {
-    case 0: launch_multi_t<128, 1>(a, n, max_tiles, st); break;
-    case 1: launch_multi_t<128, 2>(a, n, max_tiles, st); break;
-    case 2: launch_multi_t<128, 4>(a, n, max_tiles, st); break;
-    case 3: launch_multi_t<256, 1>(a, n, max_tiles, st); break;
-    case 4: launch_multi_t<256, 2>(a, n, max_tiles, st); break;
-    default: launch_multi_t<256, 4>(a, n, max_tiles, st); break;
+    case 0: launch_multi_t<64, 1>(a, n, max_tiles, st); break;
+    case 1: launch_multi_t<64, 2>(a, n, max_tiles, st); break;
+    case 2: launch_multi_t<64, 4>(a, n, max_tiles, st); break;
+    case 3: launch_multi_t<64, 8>(a, n, max_tiles, st); break;
+    case 4: launch_multi_t<64, 16>(a, n, max_tiles, st); break;
+    case 5: launch_multi_t<128, 1>(a, n, max_tiles, st); break;
+    case 6: launch_multi_t<128, 2>(a, n, max_tiles, st); break;
+    case 7: launch_multi_t<128, 4>(a, n, max_tiles, st); break;
+    case 8: launch_multi_t<128, 8>(a, n, max_tiles, st); break;
+    case 9: launch_multi_t<256, 1>(a, n, max_tiles, st); break;
+    case 10: launch_multi_t<256, 2>(a, n, max_tiles, st); break;
+    case 11: launch_multi_t<256, 4>(a, n, max_tiles, st); break;
+    case 12: launch_multi_t<512, 1>(a, n, max_tiles, st); break;
+    case 13: launch_multi_t<512, 2>(a, n, max_tiles, st); break;
+    default: launch_multi_t<1024, 1>(a, n, max_tiles, st); break;
     }
     return launched("gs_cull_multi");
 }

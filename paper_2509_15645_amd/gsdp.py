@@ -542,7 +542,7 @@ def gs_cull_multi(model: Model, multi: Multi, step: int, stream=None):
 
 
 def gs_cull_multi_autotune(model: Model, multi: Multi, step: int, stream=None):
-    times = (C.c_float * 16)()
+    times = (C.c_float * 32)()
     nv = C.c_int32()
     _check(lib.gs_cull_multi_autotune(C.byref(model.c), C.byref(multi.c), int(step), _ptr(multi.ws),
                                       multi.ws.numel() * 4, _stream(stream), times, C.byref(nv)),

@@ -103,12 +103,19 @@ def test_batched_scenes_cameras_vs_oracle(g, kind):
     g_cam_dev = torch.zeros((C, multi.cap_cam, D), dtype=torch.float32, device="cuda")
     out_g = torch.zeros((multi.cap_union, 10), dtype=torch.float32, device="cuda")
     out_a = torch.zeros((multi.cap_union, 49), dtype=torch.float32, device="cuda")
+    gath_g = torch.zeros((multi.cap_union, 10), dtype=torch.float32, device="cuda")
+    gath_a = torch.zeros((multi.cap_union, 49), dtype=torch.float32, device="cuda")
     rng = np.random.default_rng(7)
     for t in range(1, steps + 1):
         g.gs_cull_multi(model, multi, t)
+        # the union's current rows, gathered once for all cameras
+        g.gs_gather(model, t, multi.union_ids, multi.union_count, gath_g, gath_a, capacity=multi.cap_union)
         torch.cuda.synchronize()
         ref = orc.cull_multi(o4.current_geo(t), row0, sets[(t - 1) % n_sets])
         u, cc = _compare_lists(multi, ref, f"step {t}")
+        cg, ca = o4.current(t, ref[0])
+        assert np.array_equal(bits(gath_g[:u].cpu().numpy()), bits(cg)), f"gather geo step {t}"
+        assert np.array_equal(bits(gath_a[:u].cpu().numpy()), bits(ca)), f"gather app step {t}"
         g_cam = [rng.normal(0, 1e-3, (cc[c], D)).astype(np.float32) for c in range(C)]
         g_cam_dev.zero_()
         for c in range(C):
@@ -196,14 +203,14 @@ def test_batched_variants_agree_and_autotune(g):
     model = g.Model(geo, app, lg, la, max_steps=8, cull_mode=1)
     multi = g.Multi(model, row0, sets)
     ref = orc.cull_multi(geo, row0, sets[0])
-    for v in range(6):
+    for v in range(15):
         multi.c.variant = v
         g.gs_cull_multi(model, multi, 1)
         torch.cuda.synchronize()
         _compare_lists(multi, ref, f"variant {v}")
     times = g.gs_cull_multi_autotune(model, multi, 1)
     say(f"[autotune] times ms {['%.3f' % x for x in times]} -> variant {multi.c.variant}")
-    assert len(times) == 6 and 0 <= multi.c.variant < 6
+    assert len(times) == 15 and 0 <= multi.c.variant < 15
     assert times[multi.c.variant] == min(times)
     g.gs_cull_multi(model, multi, 1)
     torch.cuda.synchronize()
@@ -211,8 +218,9 @@ def test_batched_variants_agree_and_autotune(g):
     assert model.ws_header()["error"] == 0
 
 
-def _graph_step(g, model, multi, g_cam_dev, out_g, out_a):
+def _graph_step(g, model, multi, g_cam_dev, out_g, out_a, gath_g, gath_a):
     g.gs_cull_multi(model, multi, 0)
+    g.gs_gather(model, 0, multi.union_ids, multi.union_count, gath_g, gath_a, capacity=multi.cap_union)
     g.gs_grad_sum_multi(multi, 49, g_cam_dev, out_g, out_a)
     g.gs_adam_step_deferred(model, 0, multi.union_ids, multi.union_count, out_g, out_a, capacity=multi.cap_union)
     g.gs_step_advance(model.step_dev)
@@ -231,7 +239,8 @@ def test_batched_step_graph_replay_matches_eager(g):
     bufs = {}
     for name, mu in (("e", me), ("g", mg)):
         gc = torch.from_numpy(np.random.default_rng(1).normal(0, 1e-3, (C, mu.cap_cam, D)).astype(np.float32)).cuda()
-        bufs[name] = (gc, torch.zeros((mu.cap_union, 10), device="cuda"), torch.zeros((mu.cap_union, 49), device="cuda"))
+        bufs[name] = (gc, torch.zeros((mu.cap_union, 10), device="cuda"), torch.zeros((mu.cap_union, 49), device="cuda"),
+                      torch.zeros((mu.cap_union, 10), device="cuda"), torch.zeros((mu.cap_union, 49), device="cuda"))
     graphed.step_dev.fill_(1)
     torch.cuda.synchronize()
     s = torch.cuda.Stream()
@@ -242,8 +251,9 @@ def test_batched_step_graph_replay_matches_eager(g):
         _graph_step(g, graphed, mg, *bufs["g"])
     torch.cuda.synchronize()
     for t in range(1, 5):
-        ge, oge, oae = bufs["e"]
+        ge, oge, oae, gge, gae = bufs["e"]
         g.gs_cull_multi(eager, me, t)
+        g.gs_gather(eager, t, me.union_ids, me.union_count, gge, gae, capacity=me.cap_union)
         g.gs_grad_sum_multi(me, 49, ge, oge, oae)
         g.gs_adam_step_deferred(eager, t, me.union_ids, me.union_count, oge, oae, capacity=me.cap_union)
         graph.replay()
@@ -255,6 +265,9 @@ def test_batched_step_graph_replay_matches_eager(g):
             assert a[key].tobytes() == b[key].tobytes(), (t, key)
         ue, ug = me.lists(), mg.lists()
         assert ue[0] == ug[0] and np.array_equal(ue[1], ug[1])
+        u = ue[0]
+        for k in (3, 4):
+            assert torch.equal(bufs["e"][k][:u].view(torch.int32), bufs["g"][k][:u].view(torch.int32)), (t, k)
         say(f"[graph] replay {t}: union {ue[0]} identical to eager")
 
 
