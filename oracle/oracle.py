@@ -934,3 +934,45 @@ def grad_sum_multi(cam_pos, g_cam, n_union: int) -> np.ndarray:
     for c, pos in enumerate(cam_pos):
         out[pos] = out[pos] + np.asarray(g_cam[c], np.float32)
     return out
+
+
+# ---------------------------------------------------------------------------
+# balance-aware image split (Sec. 4.4)
+# ---------------------------------------------------------------------------
+def crop_camera(cam, x0: int, x1: int) -> np.ndarray:
+    """The camera of image columns [x0, x1): same rotation, translation and
+    focal lengths, principal point moved left by x0, width x1 - x0 (as the 20
+    floats the cull takes)."""
+    f = cam_floats(cam).copy()
+    f[14] = np.float32(f[14] - np.float32(x0))
+    f[16] = np.float32(x1 - x0)
+    return f
+
+
+def image_split_plan(geo_current: np.ndarray, cam, mem_limit: float, search_steps: int = 5):
+    """Where to split an image whose visible set is too large (Sec. 4.4; the
+    paper gives the idea, not the search): no split (x = 0) when at most
+    mem_limit * n rows are visible; otherwise start at the middle column and
+    move toward the side with fewer visible rows by halving, search_steps
+    times.  Returns (x, (visible in the whole image, left crop, right crop))."""
+    n = geo_current.shape[0]
+    width = int(cam_floats(cam)[16])
+    full = int(cull(geo_current, cam).sum())
+    if full <= mem_limit * n:
+        return 0, (full, 0, 0)
+
+    def sides(x):
+        left = int(cull(geo_current, crop_camera(cam, 0, x)).sum())
+        right = int(cull(geo_current, crop_camera(cam, x, width)).sum())
+        return left, right
+
+    lo, hi, x = 1, width - 1, width // 2
+    for _ in range(search_steps):
+        left, right = sides(x)
+        if left > right:
+            hi = x
+        else:
+            lo = x
+        x = (lo + hi) // 2
+    left, right = sides(x)
+    return x, (full, left, right)

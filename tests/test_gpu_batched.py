@@ -283,30 +283,82 @@ def test_image_split_planner_matches_oracle_search(g):
     model = g.Model(sc.geo, sc.app, lg, la, max_steps=8, cull_mode=1)
     for cam in gi.orbit_cameras(3, seed=22):
         x, counts = g.gs_plan_image_split(model, cam, 1, 0.3)
-        full = int(orc.cull(sc.geo, cam).sum())
-        assert counts[0] == full
-        if full <= 0.3 * sc.n:
-            assert x == 0
+        xx, ref = orc.image_split_plan(sc.geo, cam, 0.3)
+        say(f"[split] full {ref[0]} -> x={x} left {counts[1]} right {counts[2]}")
+        assert counts[0] == ref[0] and x == xx
+        if x == 0:
             continue
-        lo, hi, xx = 1, cam.width - 1, cam.width // 2
-        for _ in range(5):
-            nl = int(orc.cull(sc.geo, _crop(cam, 0, xx)).sum())
-            nr = int(orc.cull(sc.geo, _crop(cam, xx, cam.width)).sum())
-            if nl > nr:
-                hi = xx
-            else:
-                lo = xx
-            xx = (lo + hi) // 2
-        nl = int(orc.cull(sc.geo, _crop(cam, 0, xx)).sum())
-        nr = int(orc.cull(sc.geo, _crop(cam, xx, cam.width)).sum())
-        say(f"[split] full {full} -> x={x} left {counts[1]} right {counts[2]}")
-        assert x == xx and counts[1] == nl and counts[2] == nr
-        assert abs(nl - nr) < 0.35 * (nl + nr)
+        assert counts[1] == ref[1] and counts[2] == ref[2]
+        assert abs(ref[1] - ref[2]) < 0.35 * (ref[1] + ref[2])
         # the split image trains as a batch of the two crops
         multi = g.Multi(model, [0, model.n], [[[_crop(cam, 0, x), _crop(cam, x, cam.width)]]])
         g.gs_cull_multi(model, multi, 1)
         torch.cuda.synchronize()
-        ref = orc.cull_multi(sc.geo, [0, model.n], [[_crop(cam, 0, x), _crop(cam, x, cam.width)]])
-        _compare_lists(multi, ref, "split batch")
+        ref_l = orc.cull_multi(sc.geo, [0, model.n], [[orc.crop_camera(cam, 0, x), orc.crop_camera(cam, x, cam.width)]])
+        _compare_lists(multi, ref_l, "split batch")
     x, _ = g.gs_plan_image_split(model, gi.orbit_cameras(1, seed=22)[0], 1, 0.99)
     assert x == 0
+
+
+def test_split_image_training_steps_vs_oracle(g):
+    """Training with the balance-aware split (Sec. 4.4) end to end: each step
+    plans the split on the current geometry, culls both crops as one batch,
+    gathers the union, sums the two crops' gradients in crop order and takes
+    one deferred Adam step.  Split column, lists, gathered rows, summed
+    gradients and the final state against the oracle's plan, cull, restore,
+    sum and FP32 deferred model, bit for bit."""
+    n, steps, D = 100_000, 4, 59
+    sc = gi.make_scene(n, seed=31)
+    lg, la = gi.lr_columns()
+    model = g.Model(sc.geo, sc.app, lg, la, max_steps=8, cull_mode=1)
+    o3 = orc.DeferredF32(sc.geo, sc.app, lg, la)
+    cams = gi.orbit_cameras(steps, seed=32)
+    rng = np.random.default_rng(33)
+    splits = 0
+    for t in range(1, steps + 1):
+        cam = cams[t - 1]
+        x, counts = g.gs_plan_image_split(model, cam, t, 0.3)
+        cur = o3.current_geo(t)
+        xx, ref_counts = orc.image_split_plan(cur, cam, 0.3)
+        assert x == xx and counts[0] == ref_counts[0], t
+        if x:
+            assert tuple(counts[1:]) == tuple(ref_counts[1:]), t
+        if x:
+            crops, ref_crops = [_crop(cam, 0, x), _crop(cam, x, cam.width)], \
+                [orc.crop_camera(cam, 0, x), orc.crop_camera(cam, x, cam.width)]
+            splits += 1
+        else:
+            crops, ref_crops = [cam], [cam]
+        multi = g.Multi(model, [0, n], [[crops]])
+        gath_g = torch.zeros((multi.cap_union, 10), device="cuda")
+        gath_a = torch.zeros((multi.cap_union, 49), device="cuda")
+        out_g = torch.zeros((multi.cap_union, 10), device="cuda")
+        out_a = torch.zeros((multi.cap_union, 49), device="cuda")
+        # the batch's camera set is (t - 1) % n_sets = 0 with one set
+        g.gs_cull_multi(model, multi, t)
+        g.gs_gather(model, t, multi.union_ids, multi.union_count, gath_g, gath_a, capacity=multi.cap_union)
+        torch.cuda.synchronize()
+        ref = orc.cull_multi(cur, [0, n], [ref_crops])
+        u, cc = _compare_lists(multi, ref, f"split step {t}")
+        cg, ca = o3.current(t, ref[0])
+        assert np.array_equal(bits(gath_g[:u].cpu().numpy()), bits(cg)), t
+        assert np.array_equal(bits(gath_a[:u].cpu().numpy()), bits(ca)), t
+        g_cam = [rng.normal(0, 1e-3, (cc[c], D)).astype(np.float32) for c in range(len(crops))]
+        g_cam_dev = torch.zeros((len(crops), multi.cap_cam, D), dtype=torch.float32, device="cuda")
+        for c in range(len(crops)):
+            g_cam_dev[c, :cc[c]] = torch.from_numpy(g_cam[c]).cuda()
+        g.gs_grad_sum_multi(multi, 49, g_cam_dev, out_g, out_a)
+        g.gs_adam_step_deferred(model, t, multi.union_ids, multi.union_count, out_g, out_a, capacity=multi.cap_union)
+        gsum = orc.grad_sum_multi(ref[1], g_cam, u)
+        torch.cuda.synchronize()
+        assert np.array_equal(bits(out_g[:u].cpu().numpy()), bits(gsum[:, :10])), t
+        assert np.array_equal(bits(out_a[:u].cpu().numpy()), bits(gsum[:, 10:])), t
+        o3.step(t, ref[0].astype(np.uint32), gsum[:, :10], gsum[:, 10:])
+        say(f"[split train] step {t}: x={x} union {u} crops {cc}")
+    assert splits >= 2
+    g.gs_adam_flush(model, steps)
+    o3.flush(steps)
+    st = model.state()
+    for k, name in ((0, "geo"), (1, "app")):
+        for part, refv in (("w", o3.w[k]), ("m", o3.m[k]), ("v", o3.v[k])):
+            assert np.array_equal(bits(st[f"{name}_{part}"]), bits(refv)), f"{name}_{part}"
