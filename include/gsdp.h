@@ -87,7 +87,9 @@ typedef struct gs_model {
     gs_group geo;
     gs_group app;
     int32_t *last_step;    /* [n] */
-    const void *lut;       /* device tables written by gs_lut_build */
+    void *lut;             /* device tables from gs_lut_build (or its variants); every
+                              gs_adam_step_deferred moves their restore rows to the next
+                              step, and calls record step mismatches in their header */
     int32_t lut_max_steps; /* largest update step the tables cover */
     int32_t max_defer;     /* 0 = unbounded; K > 0: a row deferred K steps is force-updated
                               (the paper's saturating counter, MAX = 15) */
@@ -122,24 +124,53 @@ enum { GS_OPT_ADAM = 0, GS_OPT_ADAMW = 1, GS_OPT_SGD_MOMENTUM = 2 };
 
 /* ---------------------------------------------------------------- tables */
 
-/* Bytes of the device tables for updates 1..max_steps (plus the flush table
- * of step max_steps+1).  max_defer as in gs_model.  The deferred-update LUT
- * (w_scale of Eq. 3, m_scale/v_scale of Eq. 2, Sec. 4.3.2 pseudocode) is
- * stored for every step: max_defer = 0 needs (T+1)(T+2)/2 floats for
- * T = max_steps, max_defer = K needs (T+1)(K+1). */
+/* Tables of the deferred update (Sec. 4.3.2 and its pseudocode, Eq. 2-3).
+ * The paper precomputes, for the current step, the restore coefficient w_scale
+ * of Eq. 3 for every defer count, and m_scale = b1^(d+1), v_scale = b2^(d+1) of
+ * Eq. 2.  Here the tables hold the restore coefficients of two steps only (two
+ * row slots, slot = step & 1) and each gs_adam_step_deferred(t) ends by
+ * computing the rows of step t + 1 from those of t on the device: a row
+ * deferred d steps at t is deferred d + 1 at t + 1 and has also skipped step
+ * t, so W_{t+1}[d+1] = W_t[d] + (b1/sqrt(b2))^d c(t), with c(k) the unit-rate
+ * bias-corrected step of Eq. 3, in FP64 (each entry rounded once to FP32).
+ * Memory is O(max_steps + max_defer): with D = max_defer, or max_steps when
+ * max_defer = 0, about 40 D + 16 max_steps bytes (a 30000-step run with
+ * unbounded deferral needs 1.7 MB).  Byte layout (8-byte aligned):
+ *   header (64 B: int32 t_row[2] = step held by each slot, T, K, nclass,
+ *           error, kind, reserved)
+ *   Wf [2][D+1] f32 | Mf [D+1] f32 | Vf [D+1] f32 | SS [T+2] f32 | BC [T+2] f32
+ *   | pad to 8 | Wd [2][D+1] f64 | R [D+1] f64 | Cn [T+2] f64
+ *   | per AdamW decay class: Wlf [2][D+1] f32, Pf [2][D+1] f32, qf [T+2] f32,
+ *     pad to 8, Wld [2][D+1] f64, Pd [2][D+1] f64, qd [T+2] f64
+ * A call of step t (cull, gather, update; the flush of t reads the rows of
+ * t + 1) whose row slot does not hold that step -- steps must run 1, 2, 3 ...
+ * -- or whose step lies outside [1, T] sets the header's error word (bit 0:
+ * wrong step, bit 1: out of range); the update and the flush then store
+ * nothing.  One table buffer serves one model. */
 int gs_lut_bytes(int32_t max_steps, int32_t max_defer, size_t *bytes);
 
-/* Compute the tables on the host in FP64 (powers by repeated multiplication,
- * the LUT recurrence of the Sec. 4.3.2 pseudocode with unit learning rate), round them once to
- * FP32 and copy them to `lut_dev` (a device buffer of at least
- * gs_lut_bytes bytes).  Synchronous: returns after the copy completed. */
+/* Compute the tables of step 1 on the host in FP64 (powers by repeated
+ * multiplication, unit learning rate), round them once to FP32 and copy them
+ * to `lut_dev` (a device buffer of at least gs_lut_bytes bytes, 8-byte
+ * aligned).  Synchronous: returns after the copy completed. */
 int gs_lut_build(double beta1, double beta2, int32_t max_steps, int32_t max_defer,
                  void *lut_dev, size_t bytes);
 
+/* Move the tables of `model` forward to `step` (>= the step they hold, <=
+ * lut_max_steps + 1), doing each step's advance in turn on `stream`, so that
+ * a model can start (or resume) at any step.  Synchronises `stream` before
+ * and after (setup only). */
+int gs_lut_seek(const gs_model *model, int64_t step, void *stream);
+
+/* The same on a host image of the tables (from the *_host builders): the
+ * same FP64 operations as the device advance, so the rows agree bit for bit. */
+int gs_lut_seek_host(void *lut_host, size_t bytes, int64_t step);
+
 /* Tables of deferred SGD with momentum (same layout and size as the Adam
- * tables): W[t][d] = sum_{i=1..d} s[t-i] mu^(d+1-i) by the recurrence
- * W[d] = mu (W[d-1] + s[t-d]); the first-moment table holds mu^(d+1), the step
- * table s[t] (lr_scale may be NULL: s = 1), the others 1.  FP64, rounded once. */
+ * tables): W_t[d] = sum_{i=1..d} s[t-i] mu^(d+1-i), advanced as
+ * W_{t+1}[d+1] = W_t[d] + mu^(d+1) s[t]; the first-moment table holds
+ * mu^(d+1), the step table s[t] (lr_scale may be NULL: s = 1), the others 1.
+ * FP64, rounded once. */
 int gs_lut_build_sgd_momentum(double momentum, int32_t max_steps, int32_t max_defer, const double *lr_scale,
                               void *lut_dev, size_t bytes);
 int gs_lut_build_sgd_momentum_host(double momentum, int32_t max_steps, int32_t max_defer, const double *lr_scale,
@@ -149,9 +180,10 @@ int gs_lut_build_sgd_momentum_host(double momentum, int32_t max_steps, int32_t m
  * max_defer) with weight decay lambda >= 0 and an optional rate schedule
  * (as gs_lut_build_schedule).  The Adam tables come first, then per decay
  * class c -- the distinct column rates in order of first appearance, G columns
- * before A columns -- the decayed restore rows, the decay products (both laid
- * out like W) and the step decays 1 - lr s[t] lambda.  gs_lut_bytes_adamw
- * gives the size; model->lut is not read. */
+ * before A columns -- the decayed restore rows Wl, the decay products P (both
+ * two slots like W) and the step decays q[t] = 1 - lr s[t] lambda; advanced as
+ * Wl_{t+1}[d+1] = q[t] Wl_t[d] + r^d c(t), P_{t+1}[d+1] = q[t] P_t[d].
+ * gs_lut_bytes_adamw gives the size; model->lut is not read. */
 int gs_lut_bytes_adamw(const gs_model *model, size_t *bytes);
 int gs_lut_build_adamw(const gs_model *model, double weight_decay, const double *lr_scale, void *lut_dev,
                        size_t bytes);

@@ -16,9 +16,10 @@
  *                       Sec. 3.4 challenge 1; formula fixed as the 3-sigma EWA box)
  *   orc_compact         ascending ids of the kept rows (valid_ids, Sec. 4.1)
  *   orc_adam_dense_f64  dense Adam, Eq. 1 -- the definition the method reaches
- *   orc_lut_paper_f64   LUTs of the deferred-update figure (param/mom/var LUT)
- *   orc_deferred_rows_f64  restore + Adam of the figure, FP64 (model O2)
- *   orc_lut_spec        FP32 LUT of the implementation spec (model O3)
+ *   orc_restore_coeff_f64  restore coefficients of Eq. 3 as the sum over the
+ *                       skipped steps, FP64 (the paper's lookup tables)
+ *   orc_deferred_rows_f64  restore + decayed moments + Adam step, FP64 (model O2)
+ *   orc_lut_spec        FP32 tables of the implementation spec (model O3)
  *   orc_restore_bound   clamp of the restore factor (above the Adam ratio bound)
  *   orc_deferred_rows_f32  the same update with FP32 math and FP32 (O3) or
  *                       BF16 stochastically rounded (O4) moments, fixed op order
@@ -232,62 +233,67 @@ void orc_adam_dense_sparse_grad_f64(int64_t n, int dim, double *w, double *m, do
 }
 
 /* ------------------------------------------------------------------------ */
-/* LUTs of the deferred-update figure, FP64, for update step `step`, with a
- * unit learning rate (W is linear in lr; callers multiply by the column's lr):
- *   param_lut[0] = 0
- *   param_lut[i] = (b1/sqrt(b2)) param_lut[i-1]
- *                  + b1 / ( sqrt(b2 / (1 - b2^(step-i))) * (1 - b1^(step-i)) )
- *   mom_lut[i] = b1^(i+1),  var_lut[i] = b2^(i+1)          for i = 0..dmax
- * Entries exist for d = 0..dmax with dmax <= step-1: a row cannot have been
- * deferred for step-1 or more steps, and step-i = 0 would divide by zero. */
-/* sched (optional): learning-rate multiplier of each step; the listing's
- * (lr*b1) term of the skipped step step-i then uses that step's rate. */
-void orc_lut_paper_f64(double b1, double b2, int64_t step, int dmax, const double *sched,
-                       double *param_lut, double *mom_lut, double *var_lut)
+/* Restore coefficients of Eq. 3, FP64, for update t with a unit learning rate
+ * (the restore is linear in lr; callers multiply by the column's rate).  A row
+ * deferred d steps last took update s0 = t-1-d and skipped k = s0+1 .. t-1.
+ * With g = 0 its moments at step k are b1^(k-s0) m and b2^(k-s0) v, so step k
+ * moves w by lr (b1^(k-s0) m/(1-b1^k)) / (sqrt(b2^(k-s0) v/(1-b2^k)) + eps);
+ * with eps moved out of the sum (the paper's approximation, Sec. 4.3.1) the d
+ * steps move w by lr coef[d] m/(sqrt(v)+eps), where
+ *   coef[d] = sum_{k=s0+1}^{t-1} s_k (b1/sqrt(b2))^(k-s0) sqrt(1-b2^k)/(1-b1^k)
+ * (s_k: the rate multiplier of step k under a schedule, else 1).  The moments
+ * reach m_dec[d] m, v_dec[d] v at step t before its own gradient is added:
+ *   m_dec[d] = b1^(d+1),  v_dec[d] = b2^(d+1).
+ * Entries exist for d = 0..dmax, dmax <= t-1 (a row cannot have skipped more). */
+void orc_restore_coeff_f64(double b1, double b2, int64_t t, int dmax, const double *sched,
+                           double *coef, double *m_dec, double *v_dec)
 {
-    double scale = b1 / sqrt(b2);
-    param_lut[0] = 0.0;
-    for (int i = 1; i <= dmax; ++i)
-        param_lut[i] = scale * param_lut[i - 1]
-                       + ((sched ? sched[step - i] : 1.0) * b1)
-                             / (sqrt(b2 / (1.0 - pow(b2, (double)(step - i)))) * (1.0 - pow(b1, (double)(step - i))));
-    for (int i = 0; i <= dmax; ++i) {
-        mom_lut[i] = pow(b1, (double)(i + 1));
-        var_lut[i] = pow(b2, (double)(i + 1));
+    for (int d = 0; d <= dmax; ++d) {
+        const int64_t s0 = t - 1 - d;
+        double sum = 0.0;
+        for (int64_t k = s0 + 1; k <= t - 1; ++k) {
+            const double decay = pow(b1 / sqrt(b2), (double)(k - s0));
+            const double corr = sqrt(1.0 - pow(b2, (double)k)) / (1.0 - pow(b1, (double)k));
+            sum += (sched ? sched[k] : 1.0) * decay * corr;
+        }
+        coef[d] = sum;
+        m_dec[d] = pow(b1, (double)(d + 1));
+        v_dec[d] = pow(b2, (double)(d + 1));
     }
 }
 
-/* Model O2: restore + Adam of the deferred-update figure in FP64, for the
- * update rows rows[j] with defer counts d[j] and compact gradients g[j][:]
- * (zero rows for saturated Gaussians).  Per column k with learning rate lr[k]:
- *   w -= (W[d] lr m) / (sqrt(v) + eps)            restore with the OLD moments
- *   m' = b1^(d+1) m + (1-b1) g ;  v' = b2^(d+1) v + (1-b2) g g
- *   w  = w - (lr/(1-b1^t)) m' / (sqrt(v')/sqrt(1-b2^t) + eps)
- * The last line uses the new variance; the printed listing's use of the old
- * one would make the step diverge and contradicts the text ("the standard
- * Adam update is applied"). */
+/* Model O2: the deferred update in FP64 for the update rows rows[j] with
+ * defer counts d[j] and compact gradients g[j][:] (zero rows for saturated
+ * Gaussians).  Per column k with rate lr[k] (Eq. 2-3):
+ *   restore the skipped steps with the stored moments:
+ *       w -= lr coef[d] m / (sqrt(v) + eps)                     (d > 0)
+ *   decay the moments over them and add this step's gradient (Eq. 2):
+ *       m <- b1^(d+1) m + (1-b1) g,   v <- b2^(d+1) v + (1-b2) g^2
+ *   take the ordinary Adam step of update t with the new moments (Eq. 1):
+ *       w -= (lr s_t / (1-b1^t)) m / (sqrt(v) / sqrt(1-b2^t) + eps)
+ * (The new v belongs in the last line: the text applies the standard Adam
+ * update there; the old v would make the step diverge.) */
 void orc_deferred_rows_f64(int dim, double *w, double *m, double *v, int64_t n_rows,
                            const uint32_t *rows, const int64_t *d, const double *g,
                            const double *lr, double b1, double b2, double eps, int64_t t, double lr_scale_t,
-                           const double *param_lut, const double *mom_lut, const double *var_lut)
+                           const double *coef, const double *m_dec, const double *v_dec)
 {
-    const double bias_correction = sqrt(1.0 - pow(b2, (double)t));
+    const double corr2 = sqrt(1.0 - pow(b2, (double)t));
+    const double corr1 = 1.0 - pow(b1, (double)t);
 #pragma omp parallel for schedule(static)
     for (int64_t j = 0; j < n_rows; ++j) {
-        int64_t id = rows[j];
-        int64_t dj = d[j];
-        double w_scale = param_lut[dj], m_scale = mom_lut[dj], v_scale = var_lut[dj];
+        const int64_t id = rows[j];
+        const int64_t dj = d[j];
         for (int k = 0; k < dim; ++k) {
-            int64_t e = id * dim + k;
-            double wk = w[e], mk = m[e], vk = v[e], gk = g ? g[j * dim + k] : 0.0;
-            double m_new = m_scale * mk + (1.0 - b1) * gk;
-            double v_new = v_scale * vk + (1.0 - b2) * gk * gk;
-            m[e] = m_new;
-            v[e] = v_new;
-            if (dj > 0) wk -= (w_scale * lr[k] * mk) / (sqrt(vk) + eps);
-            double denom = sqrt(v_new) / bias_correction + eps;
-            double step_size = (lr[k] * lr_scale_t) / (1.0 - pow(b1, (double)t));
-            w[e] = wk - step_size * m_new / denom;
+            const int64_t e = id * dim + k;
+            const double gk = g ? g[j * dim + k] : 0.0;
+            double wk = w[e];
+            if (dj > 0) wk -= (coef[dj] * lr[k] * m[e]) / (sqrt(v[e]) + eps);
+            const double m1 = m_dec[dj] * m[e] + (1.0 - b1) * gk;
+            const double v1 = v_dec[dj] * v[e] + (1.0 - b2) * gk * gk;
+            m[e] = m1;
+            v[e] = v1;
+            w[e] = wk - ((lr[k] * lr_scale_t) / corr1) * m1 / (sqrt(v1) / corr2 + eps);
         }
     }
 }
@@ -295,14 +301,14 @@ void orc_deferred_rows_f64(int dim, double *w, double *m, double *v, int64_t n_r
 /* Restore-only in FP64: current value of rows with defer count d (read-only). */
 void orc_restore_rows_f64(int dim, const double *w, const double *m, const double *v,
                           int64_t n_rows, const uint32_t *rows, const int64_t *d,
-                          const double *lr, double eps, const double *param_lut, double *out)
+                          const double *lr, double eps, const double *coef, double *out)
 {
     for (int64_t j = 0; j < n_rows; ++j) {
         int64_t id = rows[j];
         for (int k = 0; k < dim; ++k) {
             int64_t e = id * dim + k;
             double wk = w[e];
-            if (d[j] > 0) wk -= (param_lut[d[j]] * lr[k] * m[e]) / (sqrt(v[e]) + eps);
+            if (d[j] > 0) wk -= (coef[d[j]] * lr[k] * m[e]) / (sqrt(v[e]) + eps);
             out[j * dim + k] = wk;
         }
     }
@@ -310,17 +316,17 @@ void orc_restore_rows_f64(int dim, const double *w, const double *m, const doubl
 
 /* Flush in FP64 after update `t`: rows rows[j] skipped delta[j] >= 1 steps.
  * Their value after update t is the restore of update t+1 with d = delta
- * (param_lut of step t+1), and the moments decay by b^delta. */
+ * (coef_next: the coefficients of step t+1), and the moments decay by b^delta. */
 void orc_flush_rows_f64(int dim, double *w, double *m, double *v, int64_t n_rows,
                         const uint32_t *rows, const int64_t *delta, const double *lr,
-                        double b1, double b2, double eps, const double *param_lut_next)
+                        double b1, double b2, double eps, const double *coef_next)
 {
     for (int64_t j = 0; j < n_rows; ++j) {
         int64_t id = rows[j];
         int64_t dl = delta[j];
         for (int k = 0; k < dim; ++k) {
             int64_t e = id * dim + k;
-            w[e] -= (param_lut_next[dl] * lr[k] * m[e]) / (sqrt(v[e]) + eps);
+            w[e] -= (coef_next[dl] * lr[k] * m[e]) / (sqrt(v[e]) + eps);
             m[e] *= pow(b1, (double)dl);
             v[e] *= pow(b2, (double)dl);
         }
@@ -332,32 +338,41 @@ void orc_flush_rows_f64(int dim, double *w, double *m, double *v, int64_t n_rows
  *
  * FP32 tables for update step t (computed in FP64, rounded once):
  *   P1[k] = b1^k, P2[k] = b2^k by repeated multiplication from P[0] = 1
- *   C[k]  = b1 / ( sqrt(b2 / (1 - P2[k])) * (1 - P1[k]) )              k >= 1
- *   W[0]  = 0,  W[d] = (b1/sqrt(b2)) W[d-1] + C[t-d]                   d >= 1
+ *   C[k]  = s_k b1 / ( sqrt(b2 / (1 - P2[k])) * (1 - P1[k]) )       k >= 1
+ *   R[j]  = (b1/sqrt(b2))^j by repeated multiplication from R[0] = 1
+ *   W[d]  = the restore coefficient of Eq. 3 summed over the skipped steps in
+ *           time order, k = t-d .. t-1, from 0:
+ *           (((0 + R[0] C[t-d]) + R[1] C[t-d+1]) + ...) + R[d-1] C[t-1]
+ *           (the implementation keeps these sums for the current step and
+ *           extends them by one skipped step per update)
  *   Wf[d] = W[d], Mf[d] = P1[d+1], Vf[d] = P2[d+1],
- *   ss = 1/(1 - P1[t]),  bc = sqrt(1 - P2[t])                (all as FP32)     */
+ *   ss = s_t/(1 - P1[t]),  bc = sqrt(1 - P2[t])              (all as FP32)     */
 void orc_lut_spec(double b1, double b2, int64_t t, int dmax, const double *sched, float *Wf, float *Mf,
                   float *Vf, float *ss, float *bc)
 {
     int64_t kmax = t > dmax + 1 ? t : dmax + 1;
     double *P1 = (double *)malloc(sizeof(double) * (size_t)(kmax + 1));
     double *P2 = (double *)malloc(sizeof(double) * (size_t)(kmax + 1));
+    double *C = (double *)calloc((size_t)(kmax + 1), sizeof(double));
+    double *R = (double *)malloc(sizeof(double) * (size_t)(dmax + 1));
     P1[0] = 1.0; P2[0] = 1.0;
     for (int64_t k = 1; k <= kmax; ++k) { P1[k] = P1[k - 1] * b1; P2[k] = P2[k - 1] * b2; }
+    for (int64_t k = 1; k < t; ++k) {
+        C[k] = b1 / (sqrt(b2 / (1.0 - P2[k])) * (1.0 - P1[k]));
+        if (sched) C[k] = sched[k] * C[k];
+    }
     double r = b1 / sqrt(b2);
-    double W = 0.0;
-    Wf[0] = 0.0f;
-    for (int d = 1; d <= dmax; ++d) {
-        int64_t k = t - d;
-        double C = b1 / (sqrt(b2 / (1.0 - P2[k])) * (1.0 - P1[k]));
-        if (sched) C = sched[k] * C;
-        W = r * W + C;
+    R[0] = 1.0;
+    for (int j = 1; j <= dmax; ++j) R[j] = R[j - 1] * r;
+    for (int d = 0; d <= dmax; ++d) {
+        double W = 0.0;
+        for (int j = 0; j < d; ++j) W = W + R[j] * C[t - d + j];
         Wf[d] = (float)W;
     }
     for (int d = 0; d <= dmax; ++d) { Mf[d] = (float)P1[d + 1]; Vf[d] = (float)P2[d + 1]; }
     *ss = sched ? (float)(sched[t] / (1.0 - P1[t])) : (float)(1.0 / (1.0 - P1[t]));
     *bc = (float)sqrt(1.0 - P2[t]);
-    free(P1); free(P2);
+    free(P1); free(P2); free(C); free(R);
 }
 
 /* Bound on the restore factor m/(sqrt(v)+eps).  For Adam moments grown from
@@ -896,32 +911,41 @@ void orc_sgdm_dense_sparse_grad_f64(int64_t n, int dim, double *w, double *m, in
     free(gd);
 }
 
-/* Tables of update t in FP64: Ws[d] by the recurrence Ws[d] = mu (Ws[d-1] +
- * s_{t-d}), Mf[d] = mu^(d+1) by repeated multiplication. */
+/* Tables of update t in FP64.  With g = 0 the momentum buffer decays as mu^j,
+ * so the skipped steps k = t-d .. t-1 of a row last updated at s0 = t-1-d
+ * move w by lr buf Ws[d] with Ws[d] = sum_{k=s0+1}^{t-1} s_k mu^(k-s0)
+ * (pow for the powers); Mf[d] = mu^(d+1) is the buffer's decay to step t. */
 void orc_lut_sgdm_f64(double mu, int64_t t, int dmax, const double *sched, double *Ws, double *Mf)
 {
-    Ws[0] = 0.0;
-    for (int d = 1; d <= dmax; ++d) Ws[d] = mu * (Ws[d - 1] + (sched ? sched[t - d] : 1.0));
-    double p = 1.0;
     for (int d = 0; d <= dmax; ++d) {
-        p = p * mu;
-        Mf[d] = p;
+        const int64_t s0 = t - 1 - d;
+        double sum = 0.0;
+        for (int64_t k = s0 + 1; k <= t - 1; ++k) sum += (sched ? sched[k] : 1.0) * pow(mu, (double)(k - s0));
+        Ws[d] = sum;
+        Mf[d] = pow(mu, (double)(d + 1));
     }
 }
 
-/* The same tables rounded once to FP32, and the step multiplier s_t. */
+/* FP32 tables of the implementation spec: R[j] = mu^(j+1) by repeated
+ * multiplication, Ws[d] summed over the skipped steps in time order from 0,
+ * (((0 + R[0] s_{t-d}) + R[1] s_{t-d+1}) + ...) + R[d-1] s_{t-1}, Mf[d] =
+ * R[d], each rounded once; and the step multiplier s_t. */
 void orc_lut_sgdm_spec(double mu, int64_t t, int dmax, const double *sched, float *Wf, float *Mf, float *ss)
 {
-    double *W = (double *)malloc(sizeof(double) * (size_t)(dmax + 1));
-    double *M = (double *)malloc(sizeof(double) * (size_t)(dmax + 1));
-    orc_lut_sgdm_f64(mu, t, dmax, sched, W, M);
+    double *R = (double *)malloc(sizeof(double) * (size_t)(dmax + 1));
+    double p = 1.0;
     for (int d = 0; d <= dmax; ++d) {
-        Wf[d] = (float)W[d];
-        Mf[d] = (float)M[d];
+        p = p * mu;
+        R[d] = p;
+        Mf[d] = (float)p;
+    }
+    for (int d = 0; d <= dmax; ++d) {
+        double W = 0.0;
+        for (int j = 0; j < d; ++j) W = W + R[j] * (sched ? sched[t - d + j] : 1.0);
+        Wf[d] = (float)W;
     }
     *ss = sched ? (float)sched[t] : 1.0f;
-    free(W);
-    free(M);
+    free(R);
 }
 
 /* Deferred update in FP64, the paper's order: catch up the d skipped steps,
@@ -1040,29 +1064,44 @@ void orc_adamw_dense_sparse_grad_f64(int64_t n, int dim, double *w, double *m, d
     orc_adam_dense_sparse_grad_f64(n, dim, w, m, v, n_ids, ids, g_rows, lr, b1, b2, eps, t);
 }
 
-/* FP64 tables of update t for one column rate lr (paper form: pow for c). */
+/* FP64 tables of update t for one column rate lr.  Step k first scales w by
+ * q_k = 1 - lr s_k lambda, then takes its Adam step; with g = 0 the skipped
+ * steps k = t-d .. t-1 of a row last updated at s0 = t-1-d move it to
+ * P[d] w - lr Wl[d] m/(sqrt(v)+eps) (eps moved out as in Eq. 3), where every
+ * skipped step's Adam term is shrunk by the decays of the later skipped steps:
+ *   Wl[d] = sum_{k=s0+1}^{t-1} (prod_{j=k+1}^{t-1} q_j) s_k (b1/sqrt(b2))^(k-s0)
+ *                               sqrt(1-b2^k)/(1-b1^k),
+ *   P[d]  = prod_{k=s0+1}^{t-1} q_k                      (pow for the powers) */
 void orc_lut_adamw_f64(double b1, double b2, double lam, double lr, int64_t t, int dmax, const double *sched,
                        double *Wl, double *P)
 {
-    const double r = b1 / sqrt(b2);
-    Wl[0] = 0.0;
-    P[0] = 1.0;
-    for (int d = 1; d <= dmax; ++d) {
-        int64_t k = t - d;
-        double s = sched ? sched[k] : 1.0;
-        double c = b1 / (sqrt(b2 / (1.0 - pow(b2, (double)k))) * (1.0 - pow(b1, (double)k)));
-        Wl[d] = r * Wl[d - 1] + P[d - 1] * (s * c);
-        P[d] = P[d - 1] * (1.0 - lr * s * lam);
+    for (int d = 0; d <= dmax; ++d) {
+        const int64_t s0 = t - 1 - d;
+        double sum = 0.0, prod = 1.0;
+        for (int64_t k = s0 + 1; k <= t - 1; ++k) {
+            double later = 1.0;
+            for (int64_t j = k + 1; j <= t - 1; ++j) later *= 1.0 - lr * (sched ? sched[j] : 1.0) * lam;
+            const double s = sched ? sched[k] : 1.0;
+            sum += later * s * pow(b1 / sqrt(b2), (double)(k - s0)) * sqrt(1.0 - pow(b2, (double)k)) /
+                   (1.0 - pow(b1, (double)k));
+            prod *= 1.0 - lr * s * lam;
+        }
+        Wl[d] = sum;
+        P[d] = prod;
     }
 }
 
-/* The same tables with repeated-multiplication powers, rounded once to FP32,
- * and the decay factor of step t. */
+/* FP32 tables of the implementation spec: C[k] = s_k b1/(sqrt(b2/(1-P2[k]))
+ * (1-P1[k])) with repeated-multiplication powers, R[j] = (b1/sqrt(b2))^j,
+ * q_k = 1 - lr s_k lambda; over the skipped steps k = t-d+j in time order,
+ * from Wl = 0, P = 1:  Wl = q_k Wl + R[j] C[k],  P = q_k P  (each product and
+ * sum one binary64 operation, rounded once to FP32); and q_t. */
 void orc_lut_adamw_spec(double b1, double b2, double lam, double lr, int64_t t, int dmax, const double *sched,
                         float *Wf, float *Pf, float *qt)
 {
     double P1 = 1.0, P2 = 1.0;
     double *C = (double *)calloc((size_t)t + 1, sizeof(double));
+    double *R = (double *)malloc(sizeof(double) * (size_t)(dmax + 1));
     for (int64_t k = 1; k <= t; ++k) {
         P1 = P1 * b1;
         P2 = P2 * b2;
@@ -1070,18 +1109,22 @@ void orc_lut_adamw_spec(double b1, double b2, double lam, double lr, int64_t t, 
         if (sched) C[k] = sched[k] * C[k];
     }
     const double r = b1 / sqrt(b2);
-    double W = 0.0, P = 1.0;
-    Wf[0] = 0.0f;
-    Pf[0] = 1.0f;
-    for (int d = 1; d <= dmax; ++d) {
-        int64_t k = t - d;
-        W = r * W + P * C[k];
-        P = P * (1.0 - lr * (sched ? sched[k] : 1.0) * lam);
+    R[0] = 1.0;
+    for (int j = 1; j <= dmax; ++j) R[j] = R[j - 1] * r;
+    for (int d = 0; d <= dmax; ++d) {
+        double W = 0.0, P = 1.0;
+        for (int j = 0; j < d; ++j) {
+            const int64_t k = t - d + j;
+            const double q = 1.0 - lr * (sched ? sched[k] : 1.0) * lam;
+            W = q * W + R[j] * C[k];
+            P = q * P;
+        }
         Wf[d] = (float)W;
         Pf[d] = (float)P;
     }
     *qt = (float)(1.0 - lr * (sched ? sched[t] : 1.0) * lam);
     free(C);
+    free(R);
 }
 
 /* FP64 deferred rows (paper order).  Wl, P: per column tables [dim][ldt]. */

@@ -59,7 +59,7 @@ def lib():
             "orc_adam_dense_f64": (None, [i64, i32, vp, vp, vp, vp, vp, f64, f64, f64, i64]),
             "orc_adam_dense_sparse_grad_f64": (None, [i64, i32, vp, vp, vp, i64, vp, vp, vp,
                                                        f64, f64, f64, i64]),
-            "orc_lut_paper_f64": (None, [f64, f64, i64, i32, vp, vp, vp, vp]),
+            "orc_restore_coeff_f64": (None, [f64, f64, i64, i32, vp, vp, vp, vp]),
             "orc_deferred_rows_f64": (None, [i32, vp, vp, vp, i64, vp, vp, vp, vp, f64, f64, f64,
                                              i64, f64, vp, vp, vp]),
             "orc_restore_rows_f64": (None, [i32, vp, vp, vp, i64, vp, vp, vp, f64, vp, vp]),
@@ -173,13 +173,15 @@ def _sched(sched):
     return None if sched is None else np.ascontiguousarray(sched, np.float64)
 
 
-def lut_paper(b1: float, b2: float, step: int, dmax: int, sched=None):
-    """param_lut, mom_lut, var_lut (FP64, unit lr) of the deferred-update figure;
-    sched: optional per-step learning-rate multiplier (index = step)."""
-    p = np.zeros(dmax + 1); mo = np.zeros(dmax + 1); va = np.zeros(dmax + 1)
+def restore_coeff(b1: float, b2: float, step: int, dmax: int, sched=None):
+    """(coef, m_dec, v_dec), FP64, unit rate, d = 0..dmax: the restore
+    coefficient of Eq. 3 summed over a row's skipped steps, and the moments'
+    decay b1^(d+1), b2^(d+1) to update `step`; sched: optional per-step
+    learning-rate multiplier (index = step)."""
+    coef = np.zeros(dmax + 1); mdec = np.zeros(dmax + 1); vdec = np.zeros(dmax + 1)
     sc = _sched(sched)
-    lib().orc_lut_paper_f64(b1, b2, step, dmax, _p(sc), _p(p), _p(mo), _p(va))
-    return p, mo, va
+    lib().orc_restore_coeff_f64(b1, b2, step, dmax, _p(sc), _p(coef), _p(mdec), _p(vdec))
+    return coef, mdec, vdec
 
 
 def lut_spec(b1: float, b2: float, step: int, dmax: int, sched=None):
@@ -283,7 +285,8 @@ class _Deferred:
 
 
 class DeferredF64(_Deferred):
-    """Model O2: the paper's deferred algorithm with FP64 state."""
+    """Model O2: the deferred update of Sec. 4.3 (restore with the stored
+    moments, decayed moments, Adam step; Eq. 1-3) with FP64 state."""
 
     def __init__(self, geo, app, lr_geo, lr_app, b1=0.9, b2=0.999, eps=1e-15, max_defer=0, sched=None):
         super().__init__(geo.shape[0], max_defer)
@@ -299,13 +302,13 @@ class DeferredF64(_Deferred):
         rows = np.arange(self.counter.shape[0]) if rows is None else np.asarray(rows)
         rows32 = np.ascontiguousarray(rows, np.uint32)
         d = np.ascontiguousarray(self.counter[rows], np.int64)
-        lut, _, _ = lut_paper(self.b1, self.b2, t, max(self.dmax(t), 0), self.sched)
+        coef, _, _ = restore_coeff(self.b1, self.b2, t, max(self.dmax(t), 0), self.sched)
         out = []
         for k in range(2):
             o = np.zeros((rows.shape[0], self.w[k].shape[1]))
             lib().orc_restore_rows_f64(self.w[k].shape[1], _p(self.w[k]), _p(self.m[k]), _p(self.v[k]),
                                        rows.shape[0], _p(rows32), _p(d), _p(self.lr[k]), self.eps,
-                                       _p(lut), _p(o))
+                                       _p(coef), _p(o))
             out.append(o)
         return out[0], out[1]
 
@@ -313,7 +316,7 @@ class DeferredF64(_Deferred):
         valid, sat = self.update_set(valid)
         rows = np.ascontiguousarray(np.concatenate([valid, sat]), np.uint32)
         d = np.ascontiguousarray(self.counter[rows.astype(np.int64)], np.int64)
-        lut, mom, var = lut_paper(self.b1, self.b2, t, max(self.dmax(t), 0), self.sched)
+        coef, m_dec, v_dec = restore_coeff(self.b1, self.b2, t, max(self.dmax(t), 0), self.sched)
         s_t = 1.0 if self.sched is None else float(self.sched[t])
         for k, g in enumerate((g_geo, g_app)):
             dim = self.w[k].shape[1]
@@ -321,7 +324,7 @@ class DeferredF64(_Deferred):
             gg[:valid.shape[0]] = np.asarray(g, np.float64)
             lib().orc_deferred_rows_f64(dim, _p(self.w[k]), _p(self.m[k]), _p(self.v[k]), rows.shape[0],
                                         _p(rows), _p(d), _p(gg), _p(self.lr[k]), self.b1, self.b2,
-                                        self.eps, t, s_t, _p(lut), _p(mom), _p(var))
+                                        self.eps, t, s_t, _p(coef), _p(m_dec), _p(v_dec))
         self.bump(valid, sat)
         return valid, sat
 
@@ -330,12 +333,12 @@ class DeferredF64(_Deferred):
         if rows.shape[0] == 0:
             return
         delta = np.ascontiguousarray(self.counter[rows], np.int64)
-        lut, _, _ = lut_paper(self.b1, self.b2, t_done + 1, int(delta.max()), self.sched)
+        coef, _, _ = restore_coeff(self.b1, self.b2, t_done + 1, int(delta.max()), self.sched)
         rows32 = np.ascontiguousarray(rows, np.uint32)
         for k in range(2):
             lib().orc_flush_rows_f64(self.w[k].shape[1], _p(self.w[k]), _p(self.m[k]), _p(self.v[k]),
                                      rows.shape[0], _p(rows32), _p(delta), _p(self.lr[k]),
-                                     self.b1, self.b2, self.eps, _p(lut))
+                                     self.b1, self.b2, self.eps, _p(coef))
         self.counter[:] = 0
 
 
@@ -732,7 +735,7 @@ class DeferredAdamWF64(_Deferred):
         rows = np.ascontiguousarray(np.concatenate([valid, sat]), np.uint32)
         d = np.ascontiguousarray(self.counter[rows.astype(np.int64)], np.int64)
         dmax = max(self.dmax(t), 0)
-        _, mom, var = lut_paper(self.b1, self.b2, t, dmax, self.sched)
+        _, m_dec, v_dec = restore_coeff(self.b1, self.b2, t, dmax, self.sched)
         s_t = 1.0 if self.sched is None else float(self.sched[t])
         for k, g in enumerate((g_geo, g_app)):
             dim = self.w[k].shape[1]
@@ -741,7 +744,7 @@ class DeferredAdamWF64(_Deferred):
             gg[:valid.shape[0]] = np.asarray(g, np.float64)
             lib().orc_adamw_deferred_rows_f64(dim, _p(self.w[k]), _p(self.m[k]), _p(self.v[k]), rows.shape[0],
                                               _p(rows), _p(d), _p(gg), _p(self.lr[k]), self.b1, self.b2, self.eps,
-                                              t, s_t, self.lam, _p(W), _p(P), dmax + 1, _p(mom), _p(var))
+                                              t, s_t, self.lam, _p(W), _p(P), dmax + 1, _p(m_dec), _p(v_dec))
         self.bump(valid, sat)
         return valid, sat
 

@@ -576,20 +576,37 @@ __device__ __forceinline__ u64 wave_sum_u64(u64 x)
 // t_dev clamped to [1, T]; returns the table row of step t (+1 for a flush)
 // and the largest defer count that row holds.
 struct StepK {
-    int32_t t, T, K, pad;
+    int32_t t, T, K, nrow;           // nrow: entries of a restore row
     const int32_t *t_dev;
-    const float *lut;                // table base (W rows start at 0)
+    const float *lut;                // the two FP32 restore rows (slot 0, slot 1)
+    gsdp::LutHeader *hdr;            // step held by each slot, error word
 };
 
-__device__ __forceinline__ int resolve_step(const StepK &s, int extra, const float **wrow, int *dmax)
+// The step of a launch (from the device counter when t_dev is set) and the
+// restore row of step + extra: slot (step + extra) & 1 of the tables, whose
+// header says which step it holds.  ok = false when the step lies outside
+// [1, T] or the slot holds another step; the header's error word then records
+// it (bit 1, bit 0), the step is clamped for indexing, and callers that store
+// state skip their stores.
+__device__ __forceinline__ int resolve_step(const StepK &s, int extra, const float **wrow, int *dmax,
+                                            bool *ok = nullptr)
 {
-    int t = s.t;
+    int t = s.t;                     // an explicit step was checked against [1, T] by the host
+    int err = 0;
     if (s.t_dev) {
         t = *s.t_dev;
-        t = t < 1 ? 1 : (t > s.T ? s.T : t);
+        if (t < 1 || t > s.T) {
+            err = 2;
+            t = t < 1 ? 1 : s.T;
+        }
     }
-    const int64_t tr = (int64_t)t + extra;
-    *wrow = s.lut + (s.K > 0 ? (tr - 1) * (s.K + 1) : tr * (tr - 1) / 2);
+    const int tr = t + extra;
+    const int slot = tr & 1;
+    if (s.hdr->t_row[slot] != tr) err |= 1;
+    // err is uniform (the header word is the same for every lane)
+    if (err) atomicOr(&s.hdr->error, err);
+    if (ok) *ok = err == 0;
+    *wrow = s.lut + (int64_t)slot * s.nrow;
     int64_t dm = tr - 1;
     if (s.K > 0 && dm > s.K) dm = s.K;
     *dmax = (int)dm;
@@ -1038,6 +1055,53 @@ enum RowMode { kGather = 0, kAdam = 1, kFlush = 2, kAdamMax = 3 };
 template <int MODE>
 constexpr int row_unroll() { return MODE == kGather ? 2 : 4; }
 
+// The update of step t also moves the tables' restore rows to step t + 1:
+// every row deferred d steps at t is deferred d + 1 steps at t + 1 and has
+// also skipped step t, so (entries d = 0 .. min(t, Dn) - 1)
+//   W'[d+1] = W[d] + R[d] Cn[t]                      W'[0] = 0
+//   Wl'[d+1] = q[t] Wl[d] + R[d] Cn[t],  P'[d+1] = q[t] P[d]   (AdamW classes)
+// in FP64 from the FP64 rows of slot t & 1 into slot (t+1) & 1, each entry
+// rounded once to FP32 beside it.  The update kernel reads slot t & 1 only,
+// so its threads do this (entries i0, i0 + stride, ...) beside their rows.
+struct LutAdv {
+    double *Wd;                      // [2][nrow]
+    float *Wf;                       // [2][nrow]
+    const double *R, *Cn;
+    char *cls;                       // first AdamW class block
+    int64_t cls_bytes, cWlf, cPf, cWld, cPd, cqd;
+    int32_t nclass, on;              // on: this launch advances the tables
+};
+
+__device__ __forceinline__ void lut_advance_slice(const LutAdv &a, const StepK &s, int t, int64_t i0,
+                                                  int64_t stride)
+{
+    const int64_t nrow = s.nrow;
+    const int64_t so = (int64_t)(t & 1) * nrow, sn = (int64_t)((t + 1) & 1) * nrow;
+    const int64_t dn = (int64_t)t < nrow - 1 ? (int64_t)t : nrow - 1;
+    const double c = a.Cn[t];
+    for (int64_t i = i0; i <= dn; i += stride) {
+        double w = 0.0;
+        if (i > 0) w = a.Wd[so + i - 1] + a.R[i - 1] * c;
+        a.Wd[sn + i] = w;
+        a.Wf[sn + i] = (float)w;
+        for (int cl = 0; cl < a.nclass; ++cl) {
+            char *b = a.cls + cl * a.cls_bytes;
+            double *Wl = reinterpret_cast<double *>(b + a.cWld), *P = reinterpret_cast<double *>(b + a.cPd);
+            const double q = reinterpret_cast<const double *>(b + a.cqd)[t];
+            double l = 0.0, p = 1.0;
+            if (i > 0) {
+                l = q * Wl[so + i - 1] + a.R[i - 1] * c;
+                p = q * P[so + i - 1];
+            }
+            Wl[sn + i] = l;
+            P[sn + i] = p;
+            reinterpret_cast<float *>(b + a.cWlf)[sn + i] = (float)l;
+            reinterpret_cast<float *>(b + a.cPf)[sn + i] = (float)p;
+        }
+    }
+    if (i0 == 0) s.hdr->t_row[(t + 1) & 1] = t + 1;
+}
+
 struct RowArgs {
     float *gw, *aw;
     int64_t gw_ld, aw_ld;
@@ -1068,6 +1132,7 @@ struct RowArgs {
     // fz_s bytes starting at aw (offsets in bytes); the kernel then addresses
     // them all from one row base
     u32 fz_s, fz_ogm, fz_ogv, fz_oam, fz_oav, pad8;
+    LutAdv adv;                      // kAdam: the tables' advance to the next step
 };
 
 // One wavefront per Gaussian row: lane c < 10 owns G column c, lane 10+c owns
@@ -1124,7 +1189,13 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
     const float lr = a.lr[lane];
     const float *Wrow;
     int dmax;
-    const int t = resolve_step(a.step, MODE == kFlush ? 1 : 0, &Wrow, &dmax);
+    bool step_ok;
+    const int t = resolve_step(a.step, MODE == kFlush ? 1 : 0, &Wrow, &dmax, &step_ok);
+    // the tables do not hold this step: nothing is stored (the gather still
+    // writes its outputs; the header's error word says they are not valid)
+    if (!step_ok && MODE != kGather) return;
+    if (MODE == kAdam && a.adv.on)
+        lut_advance_slice(a.adv, a.step, t, (int64_t)blockIdx.x * 256 + threadIdx.x, (int64_t)gridDim.x * 256);
     // AdamW: this lane's rate class tables, same row offset as Wrow
     const float *WlRow = Wrow, *PRow = Wrow;
     float qdec = 1.0f;
@@ -1499,6 +1570,7 @@ struct FastArgs {
     u64 sr_seed;
     u32 n, cap, adim, fz_s;          // rows, id capacity, A columns, fused row bytes
     u32 om, ov, pad0, pad1;          // byte offsets of the G m and G v runs in the fused row
+    LutAdv adv;                      // kAdam: the tables' advance to the next step
 };
 
 // Pointers into the global and the constant address space: global loads and
@@ -1535,7 +1607,11 @@ __global__ __launch_bounds__(256) void k_rows_fz(FastArgs a)
     const float lr = a.lr[lane];
     const float *Wrow;
     int dmax;
-    const int t = resolve_step(a.step, 0, &Wrow, &dmax);
+    bool step_ok;
+    const int t = resolve_step(a.step, 0, &Wrow, &dmax, &step_ok);
+    if (!step_ok && MODE == kAdam) return;
+    if (MODE == kAdam && a.adv.on)
+        lut_advance_slice(a.adv, a.step, t, (int64_t)blockIdx.x * 256 + threadIdx.x, (int64_t)gridDim.x * 256);
     const cfloat *W4 = cptr(Wrow), *Mf4 = cptr(a.Mf), *Vf4 = cptr(a.Vf);
     if (a.n == 0) return;
     const u32 n = a.n;
@@ -1678,7 +1754,9 @@ __global__ __launch_bounds__(256) void k_fp8_rescale(RescaleArgs a)
     const int tid = threadIdx.x;
     const float *Wrow;
     int dmax;
-    const int t = resolve_step(a.step, 0, &Wrow, &dmax);
+    bool ok;
+    const int t = resolve_step(a.step, 0, &Wrow, &dmax, &ok);
+    if (!ok) return;
     const u64 s_step = sm_at(a.sr_seed, (u64)t);
     const u32 ntask = (u32)min((int64_t)*a.count, 4 * a.nb);
     for (u32 i = blockIdx.x; i < ntask; i += gridDim.x) {
@@ -1789,7 +1867,9 @@ __global__ __launch_bounds__(256) void k_dense_geo(DenseArgs a)
     }
     const float *Wrow;
     int dmax;
-    const int t = resolve_step(a.step, 0, &Wrow, &dmax);
+    bool ok;
+    const int t = resolve_step(a.step, 0, &Wrow, &dmax, &ok);
+    if (!ok) return;
     const float ss = a.SS[t], bc = a.BC[t];
     const u64 s_step = GST != GS_F32 ? sm_at(a.sr_seed, (u64)t) : 0ull;
     for (int e = tid; e < rows * 10; e += 256) {
@@ -1945,15 +2025,54 @@ int check_model(const gs_model *m)
     return GS_OK;
 }
 
+// The tables that do not move with the step: b^(d+1), step sizes and bias terms.
 struct LutPtrs {
-    const float *W, *Mf, *Vf, *SS, *BC;
+    const float *Mf, *Vf, *SS, *BC;
 };
 
-LutPtrs lut_ptrs(const gs_model *m, int64_t t)
+LutPtrs lut_ptrs(const gs_model *m)
 {
     const gsdp::LutLayout L = gsdp::lut_layout(m->lut_max_steps, m->max_defer);
-    const float *base = static_cast<const float *>(m->lut);
-    return {base + gsdp::lut_w_row(t, m->max_defer), base + L.offM, base + L.offV, base + L.offSS, base + L.offBC};
+    const char *base = static_cast<const char *>(m->lut);
+    auto f = [&](int64_t o) { return reinterpret_cast<const float *>(base + o); };
+    return {f(L.oMf), f(L.oVf), f(L.oSS), f(L.oBC)};
+}
+
+// AdamW class tables in the kernels' float units: the first class's restore
+// rows, floats per class block, and the distance from the restore rows to
+// the decay-product rows (the step decays follow at twice that).
+// The tables' advance of `m` (on = 1).
+LutAdv lut_adv(const gs_model *m)
+{
+    const gsdp::LutLayout L = gsdp::lut_layout(m->lut_max_steps, m->max_defer);
+    char *base = static_cast<char *>(m->lut);
+    LutAdv a;
+    memset(&a, 0, sizeof a);
+    a.Wd = reinterpret_cast<double *>(base + L.oWd);
+    a.Wf = reinterpret_cast<float *>(base + L.oWf);
+    a.R = reinterpret_cast<const double *>(base + L.oR);
+    a.Cn = reinterpret_cast<const double *>(base + L.oC);
+    a.cls = base + L.oCls;
+    a.cls_bytes = L.cls_bytes;
+    a.cWlf = L.cWlf;
+    a.cPf = L.cPf;
+    a.cWld = L.cWld;
+    a.cPd = L.cPd;
+    a.cqd = L.cqd;
+    if (m->optimizer == GS_OPT_ADAMW) {
+        float rates[gsdp::kMaxDecayClasses];
+        a.nclass = decay_classes(m, rates, nullptr);
+    }
+    a.on = 1;
+    return a;
+}
+
+void adamw_ptrs(const gs_model *m, const float **base, int64_t *per, int64_t *nW)
+{
+    const gsdp::LutLayout L = gsdp::lut_layout(m->lut_max_steps, m->max_defer);
+    *base = reinterpret_cast<const float *>(static_cast<const char *>(m->lut) + L.oCls + L.cWlf);
+    *per = L.cls_bytes / 4;
+    *nW = 2 * L.nrow;
 }
 
 // step >= 1: that step; step == 0: the step is read from *step_dev when the
@@ -1968,11 +2087,14 @@ StepK step_k(const gs_model *m, int64_t step)
 {
     StepK k;
     memset(&k, 0, sizeof k);
+    const gsdp::LutLayout L = gsdp::lut_layout(m->lut_max_steps, m->max_defer);
     k.t = (int32_t)step;
     k.T = m->lut_max_steps;
     k.K = m->max_defer;
+    k.nrow = (int32_t)L.nrow;
     k.t_dev = step == 0 ? m->step_dev : nullptr;
-    k.lut = static_cast<const float *>(m->lut);
+    k.hdr = static_cast<gsdp::LutHeader *>(m->lut);
+    k.lut = reinterpret_cast<const float *>(static_cast<const char *>(m->lut) + L.oWf);
     return k;
 }
 
@@ -2051,9 +2173,7 @@ void fill_rows(RowArgs &a, const gs_model *m)
     if (m->optimizer == GS_OPT_ADAMW) {
         float rates[gsdp::kMaxDecayClasses];
         decay_classes(m, rates, a.cls);
-        a.aw_base = static_cast<const float *>(m->lut) + gsdp::lut_layout(m->lut_max_steps, m->max_defer).total;
-        a.aw_per = gsdp::adamw_class_floats(m->lut_max_steps, m->max_defer);
-        a.aw_nW = gsdp::lut_layout(m->lut_max_steps, m->max_defer).nW;
+        adamw_ptrs(m, &a.aw_base, &a.aw_per, &a.aw_nW);
     }
     a.last = m->last_step;
     a.n = m->n;
@@ -2630,6 +2750,17 @@ __global__ __launch_bounds__(256) void k_grad_sum(GradSumArgs a)
 
 __global__ void k_step_advance(int32_t *t) { *t += 1; }
 
+// The advance alone (gs_lut_seek: one launch per step).
+__global__ __launch_bounds__(256) void k_lut_advance(StepK step, LutAdv adv)
+{
+    const float *wrow;
+    int dmax;
+    bool ok;
+    const int t = resolve_step(step, 0, &wrow, &dmax, &ok);
+    if (!ok) return;
+    lut_advance_slice(adv, step, t, (int64_t)blockIdx.x * 256 + threadIdx.x, (int64_t)gridDim.x * 256);
+}
+
 // Read-bandwidth probe in the cull's own access pattern: one block per
 // 20 KB tile (5 non-temporal 16-byte loads per thread, all issued before the
 // first is used), seven blocks per CU; the last block's tail is guarded.  The
@@ -3006,6 +3137,15 @@ namespace {
 int cull_launch(const gs_model *model, const gs_camera *cam, int64_t step, uint32_t *ids, uint32_t *count_dev,
                 uint32_t capacity, char *wsb, hipStream_t st);
 
+// Launch the move of the tables' restore rows from `step` to step + 1.
+int lut_advance(const gs_model *m, int64_t step, hipStream_t st)
+{
+    const gsdp::LutLayout L = gsdp::lut_layout(m->lut_max_steps, m->max_defer);
+    const int64_t blocks = std::min<int64_t>((L.nrow + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_lut_advance, dim3((unsigned)blocks), dim3(256), 0, st, step_k(m, step), lut_adv(m));
+    return launched("table advance");
+}
+
 // Workspace of gs_cull_noalloc: one array per GPU, zero at load (static
 // storage), held until the process ends.  Host code must not pass `scratch`
 // itself to a kernel (on the host it names a host-side stand-in); its device
@@ -3063,7 +3203,7 @@ int gs_device_cu_count(void) { return cu_count(); }
 int gs_lut_bytes(int32_t max_steps, int32_t max_defer, size_t *bytes)
 {
     if (!bytes || max_steps < 1 || max_defer < 0) return GS_EINVAL;
-    *bytes = (size_t)gsdp::lut_layout(max_steps, max_defer).total * sizeof(float);
+    *bytes = (size_t)gsdp::lut_total_bytes(max_steps, max_defer, 0);
     return GS_OK;
 }
 
@@ -3073,14 +3213,13 @@ int gs_lut_build_schedule_host(double beta1, double beta2, int32_t max_steps, in
     size_t need = 0;
     int rc = gs_lut_bytes(max_steps, max_defer, &need);
     if (rc) return rc;
-    if (!lut_host) return GS_EINVAL;
+    if (!lut_host || !aligned(lut_host, 8)) return GS_EINVAL;
     if (!(beta1 > 0.0 && beta1 < 1.0 && beta2 > 0.0 && beta2 < 1.0)) return GS_EINVAL;
     if (bytes < need) return GS_ESPACE;
     if (lr_scale)
         for (int64_t t = 0; t <= (int64_t)max_steps + 1; ++t)
             if (!(lr_scale[t] >= 0.0) || !std::isfinite(lr_scale[t])) return GS_EINVAL;
-    return gsdp::build_lut_host(beta1, beta2, max_steps, max_defer, lr_scale, static_cast<float *>(lut_host),
-                                (int64_t)(bytes / sizeof(float))) == 0
+    return gsdp::build_lut_host(beta1, beta2, max_steps, max_defer, lr_scale, lut_host, (int64_t)bytes) == 0
                ? GS_OK
                : GS_ESPACE;
 }
@@ -3099,7 +3238,7 @@ int gs_lut_build_schedule(double beta1, double beta2, int32_t max_steps, int32_t
     if (rc) return rc;
     if (!lut_dev) return GS_EINVAL;
     if (bytes < need) return GS_ESPACE;
-    std::vector<float> host(need / sizeof(float));
+    std::vector<double> host(need / sizeof(double));
     rc = gs_lut_build_schedule_host(beta1, beta2, max_steps, max_defer, lr_scale, host.data(), need);
     if (rc) return rc;
     hipError_t e = hipMemcpy(lut_dev, host.data(), need, hipMemcpyHostToDevice);
@@ -3117,14 +3256,13 @@ int gs_lut_build_sgd_momentum_host(double momentum, int32_t max_steps, int32_t m
     size_t need = 0;
     int rc = gs_lut_bytes(max_steps, max_defer, &need);
     if (rc) return rc;
-    if (!lut_host) return GS_EINVAL;
+    if (!lut_host || !aligned(lut_host, 8)) return GS_EINVAL;
     if (!(momentum > 0.0 && momentum < 1.0)) return GS_EINVAL;
     if (bytes < need) return GS_ESPACE;
     if (lr_scale)
         for (int64_t t = 0; t <= (int64_t)max_steps + 1; ++t)
             if (!(lr_scale[t] >= 0.0) || !std::isfinite(lr_scale[t])) return GS_EINVAL;
-    return gsdp::build_lut_sgdm_host(momentum, max_steps, max_defer, lr_scale, static_cast<float *>(lut_host),
-                                     (int64_t)(bytes / sizeof(float))) == 0
+    return gsdp::build_lut_sgdm_host(momentum, max_steps, max_defer, lr_scale, lut_host, (int64_t)bytes) == 0
                ? GS_OK
                : GS_ESPACE;
 }
@@ -3137,11 +3275,38 @@ int gs_lut_build_sgd_momentum(double momentum, int32_t max_steps, int32_t max_de
     if (rc) return rc;
     if (!lut_dev) return GS_EINVAL;
     if (bytes < need) return GS_ESPACE;
-    std::vector<float> host(need / sizeof(float));
+    std::vector<double> host(need / sizeof(double));
     rc = gs_lut_build_sgd_momentum_host(momentum, max_steps, max_defer, lr_scale, host.data(), need);
     if (rc) return rc;
     hipError_t e = hipMemcpy(lut_dev, host.data(), need, hipMemcpyHostToDevice);
     return e == hipSuccess ? GS_OK : hip_fail(e, "gs_lut_build_sgd_momentum: hipMemcpy");
+}
+
+int gs_lut_seek_host(void *lut_host, size_t bytes, int64_t step)
+{
+    if (!lut_host || !aligned(lut_host, 8)) return GS_EINVAL;
+    return gsdp::seek_lut_host(lut_host, (int64_t)bytes, step) == 0 ? GS_OK : GS_EINVAL;
+}
+
+int gs_lut_seek(const gs_model *model, int64_t step, void *stream)
+{
+    int rc = check_model(model);
+    if (rc) return rc;
+    if (step < 1 || step > (int64_t)model->lut_max_steps + 1) return GS_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    gsdp::LutHeader h;
+    hipError_t e = hipStreamSynchronize(st);
+    if (e == hipSuccess) e = hipMemcpy(&h, model->lut, sizeof h, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "gs_lut_seek");
+    if (h.T != model->lut_max_steps || h.K != model->max_defer) return GS_EINVAL;
+    const int64_t cur = h.t_row[0] > h.t_row[1] ? h.t_row[0] : h.t_row[1];
+    if (cur < 1 || step < cur) return GS_EINVAL;
+    for (int64_t t = cur; t < step; ++t) {
+        rc = lut_advance(model, t, st);
+        if (rc) return rc;
+    }
+    e = hipStreamSynchronize(st);
+    return e == hipSuccess ? GS_OK : hip_fail(e, "gs_lut_seek");
 }
 
 int gs_lut_bytes_adamw(const gs_model *model, size_t *bytes)
@@ -3153,7 +3318,7 @@ int gs_lut_bytes_adamw(const gs_model *model, size_t *bytes)
     float rates[gsdp::kMaxDecayClasses];
     const int nc = decay_classes(model, rates, nullptr);
     if (nc < 0) return GS_EUNSUPPORTED;
-    *bytes = sizeof(float) * (size_t)gsdp::adamw_total_floats(model->lut_max_steps, model->max_defer, nc);
+    *bytes = (size_t)gsdp::lut_total_bytes(model->lut_max_steps, model->max_defer, nc);
     return GS_OK;
 }
 
@@ -3163,7 +3328,8 @@ int gs_lut_build_adamw_host(const gs_model *model, double weight_decay, const do
     size_t need = 0;
     int rc = gs_lut_bytes_adamw(model, &need);
     if (rc) return rc;
-    if (!lut_host || !(weight_decay >= 0.0) || !std::isfinite(weight_decay)) return GS_EINVAL;
+    if (!lut_host || !aligned(lut_host, 8) || !(weight_decay >= 0.0) || !std::isfinite(weight_decay))
+        return GS_EINVAL;
     if (!(model->beta1 > 0.0 && model->beta1 < 1.0 && model->beta2 > 0.0 && model->beta2 < 1.0)) return GS_EINVAL;
     if (bytes < need) return GS_ESPACE;
     const int32_t T = model->lut_max_steps;
@@ -3173,7 +3339,7 @@ int gs_lut_build_adamw_host(const gs_model *model, double weight_decay, const do
     float rates[gsdp::kMaxDecayClasses];
     const int nc = decay_classes(model, rates, nullptr);
     return gsdp::build_lut_adamw_host(model->beta1, model->beta2, weight_decay, rates, nc, T, model->max_defer,
-                                      lr_scale, static_cast<float *>(lut_host), (int64_t)(bytes / sizeof(float))) == 0
+                                      lr_scale, lut_host, (int64_t)bytes) == 0
                ? GS_OK
                : GS_ESPACE;
 }
@@ -3186,7 +3352,7 @@ int gs_lut_build_adamw(const gs_model *model, double weight_decay, const double 
     if (rc) return rc;
     if (!lut_dev) return GS_EINVAL;
     if (bytes < need) return GS_ESPACE;
-    std::vector<float> host(need / sizeof(float));
+    std::vector<double> host(need / sizeof(double));
     rc = gs_lut_build_adamw_host(model, weight_decay, lr_scale, host.data(), need);
     if (rc) return rc;
     hipError_t e = hipMemcpy(lut_dev, host.data(), need, hipMemcpyHostToDevice);
@@ -3270,10 +3436,7 @@ int cull_launch(const gs_model *model, const gs_camera *cam, int64_t step, uint3
         uint8_t cls[64];
         decay_classes(model, rates, cls);
         for (int j = 0; j < 10; ++j) a.cls[j] = cls[j];
-        a.aw_base = static_cast<const float *>(model->lut) +
-                    gsdp::lut_layout(model->lut_max_steps, model->max_defer).total;
-        a.aw_per = gsdp::adamw_class_floats(model->lut_max_steps, model->max_defer);
-        a.aw_nW = gsdp::lut_layout(model->lut_max_steps, model->max_defer).nW;
+        adamw_ptrs(model, &a.aw_base, &a.aw_per, &a.aw_nW);
     }
     pack_camera(model, cam, a.cam, a.band);
     a.geo_dense = model->geo_mode == 1;
@@ -3393,7 +3556,7 @@ int gs_adam_step_deferred(const gs_model *model, int64_t step, const uint32_t *i
     RowArgs a;
     fill_rows(a, model);
     a.step = step_k(model, step);
-    const LutPtrs L = lut_ptrs(model, step);
+    const LutPtrs L = lut_ptrs(model);
     a.Mf = L.Mf;
     a.Vf = L.Vf;
     a.SS = L.SS;
@@ -3500,11 +3663,13 @@ int gs_adam_step_deferred(const gs_model *model, int64_t step, const uint32_t *i
         f.Vf = a.Vf;
         f.SS = a.SS;
         f.BC = a.BC;
+        f.adv = lut_adv(model);
         launch_fast<kAdam, kFastUpdateRows>(model->geo.state, row_grid(rows, kRowBlocksUpdate), (hipStream_t)stream,
                                             f);
-        return launched("gs_adam_step_deferred");
+    } else {
+        a.adv = lut_adv(model);
+        launch_rows<kAdam>(model, row_grid(rows, kRowBlocksUpdate), (hipStream_t)stream, a);
     }
-    launch_rows<kAdam>(model, row_grid(rows, kRowBlocksUpdate), (hipStream_t)stream, a);
     return launched("gs_adam_step_deferred");
 }
 
@@ -3517,7 +3682,7 @@ int gs_adam_flush(const gs_model *model, int64_t step, void *stream)
     RowArgs a;
     fill_rows(a, model);
     a.step = step_k(model, step);
-    const LutPtrs L = lut_ptrs(model, step + 1);
+    const LutPtrs L = lut_ptrs(model);
     a.Mf = L.Mf;
     a.Vf = L.Vf;
     launch_rows<kFlush>(model, row_grid(model->n, kRowBlocksUpdate), (hipStream_t)stream, a);

@@ -4,14 +4,46 @@
 
 namespace gsdp {
 
-// Device tables for the deferred update (all FP32, offsets in floats):
-//   W  : rows t = 1..T+1; row t holds w_scale for d = 0..min(t-1, K) (K = 0: unbounded)
-//   Mf : b1^(d+1),  Vf : b2^(d+1)   for d = 0..Dm
-//   SS : 1/(1-b1^t),  BC : sqrt(1-b2^t)   indexed by t = 0..T+1
+// Device tables of the deferred update, O(T + K) bytes for T = max_steps and
+// K = max_defer (Dn = K > 0 ? K : T is the largest defer count a row can hold,
+// nrow = Dn + 1 entries per row).  Only the restore rows of two steps are
+// held, in two slots (slot = step & 1): the update of step t reads the row
+// of t and writes the row of t + 1 into the other slot.  Byte layout:
+//   LutHeader                      64 bytes
+//   Wf   [2][nrow] FP32            restore coefficient rows (unit rate)
+//   Mf   [nrow]    FP32            b1^(d+1)
+//   Vf   [nrow]    FP32            b2^(d+1)
+//   SS   [T+2]     FP32            step size 1/(1-b1^t) (times the rate multiplier s[t])
+//   BC   [T+2]     FP32            sqrt(1-b2^t)
+//   Wd   [2][nrow] FP64            the rows before rounding (what the step advance accumulates)
+//   R    [nrow]    FP64            weight of a newly skipped step at entry d+1
+//   Cn   [T+2]     FP64            unit-rate contribution of skipped step k
+//   per AdamW decay class: Wlf [2][nrow] FP32, Pf [2][nrow] FP32, qf [T+2] FP32,
+//                          Wld [2][nrow] FP64, Pd [2][nrow] FP64, qd [T+2] FP64
+// Advancing the rows from step t to t + 1 (d = 0 .. min(t, Dn) - 1):
+//   W'[0] = 0,  W'[d+1] = W[d] + R[d] Cn[t]                  (Adam, SGD with momentum)
+//   Wl'[0] = 0, Wl'[d+1] = q[t] Wl[d] + R[d] Cn[t],  P'[0] = 1, P'[d+1] = q[t] P[d]   (AdamW)
+// every entry one IEEE binary64 multiply and add, rounded once to FP32.
+struct LutHeader {
+    int32_t t_row[2];        // step whose rows slot s holds (0: none)
+    int32_t T, K;            // max_steps, max_defer
+    int32_t nclass;          // AdamW decay classes (0 for Adam and SGD with momentum)
+    int32_t error;           // bit 0: a call's step was not the one its row slot held;
+                             // bit 1: a step outside [1, T] (graph replay past the tables)
+    int32_t kind;            // 0 Adam, 1 SGD with momentum, 2 AdamW
+    int32_t reserved[9];
+};
+static_assert(sizeof(LutHeader) == 64, "table header layout");
+enum { kLutAdam = 0, kLutSgdm = 1, kLutAdamw = 2 };
+
+inline int64_t align8(int64_t b) { return (b + 7) / 8 * 8; }
+
 struct LutLayout {
-    int64_t T, K;
-    int64_t nW, nMV;
-    int64_t offM, offV, offSS, offBC, total;
+    int64_t T, K, nrow;
+    // byte offsets from the table base
+    int64_t oWf, oMf, oVf, oSS, oBC, oWd, oR, oC, oCls;
+    // byte offsets inside an AdamW class block, and its size
+    int64_t cWlf, cPf, cqf, cWld, cPd, cqd, cls_bytes;
 };
 
 inline LutLayout lut_layout(int64_t T, int64_t K)
@@ -19,29 +51,37 @@ inline LutLayout lut_layout(int64_t T, int64_t K)
     LutLayout L;
     L.T = T;
     L.K = K;
-    const int64_t rows = T + 1;
-    L.nW = K > 0 ? rows * (K + 1) : rows * (rows + 1) / 2;
-    L.nMV = (K > 0 ? K : T) + 1;
-    L.offM = L.nW;
-    L.offV = L.offM + L.nMV;
-    L.offSS = L.offV + L.nMV;
-    L.offBC = L.offSS + (T + 2);
-    L.total = L.offBC + (T + 2);
+    L.nrow = (K > 0 ? K : T) + 1;
+    int64_t o = (int64_t)sizeof(LutHeader);
+    L.oWf = o; o += 4 * 2 * L.nrow;
+    L.oMf = o; o += 4 * L.nrow;
+    L.oVf = o; o += 4 * L.nrow;
+    L.oSS = o; o += 4 * (T + 2);
+    L.oBC = o; o += 4 * (T + 2);
+    o = align8(o);
+    L.oWd = o; o += 8 * 2 * L.nrow;
+    L.oR = o; o += 8 * L.nrow;
+    L.oC = o; o += 8 * (T + 2);
+    L.oCls = o;
+    int64_t c = 0;
+    L.cWlf = c; c += 4 * 2 * L.nrow;
+    L.cPf = c; c += 4 * 2 * L.nrow;
+    L.cqf = c; c += 4 * (T + 2);
+    c = align8(c);
+    L.cWld = c; c += 8 * 2 * L.nrow;
+    L.cPd = c; c += 8 * 2 * L.nrow;
+    L.cqd = c; c += 8 * (T + 2);
+    L.cls_bytes = c;
     return L;
 }
 
-// AdamW tables follow the Adam tables (whose Mf, Vf, SS, BC they share): for
-// every decay class c (a distinct column rate) the decayed restore rows Wl and
-// the decay products P (both in the W row layout) and the step decays q[t].
-constexpr int kMaxDecayClasses = 8;
-inline int64_t adamw_class_floats(int64_t T, int64_t K) { return 2 * lut_layout(T, K).nW + (T + 2); }
-inline int64_t adamw_total_floats(int64_t T, int64_t K, int nclass)
+inline int64_t lut_total_bytes(int64_t T, int64_t K, int nclass)
 {
-    return lut_layout(T, K).total + nclass * adamw_class_floats(T, K);
+    const LutLayout L = lut_layout(T, K);
+    return L.oCls + nclass * L.cls_bytes;
 }
 
-// Offset of W row t (t >= 1).
-inline int64_t lut_w_row(int64_t t, int64_t K) { return K > 0 ? (t - 1) * (K + 1) : t * (t - 1) / 2; }
+constexpr int kMaxDecayClasses = 8;
 
 // Cull tiles: 256 threads x 2 rows (512 rows, 20 KB of geometry in LDS).
 constexpr int kCullBlock = 256;
@@ -93,9 +133,13 @@ inline int64_t ws_bytes_for(int64_t n, int32_t K, int32_t fp8)
     return (b + 255) / 256 * 256;
 }
 
-int build_lut_host(double b1, double b2, int32_t T, int32_t K, const double *sched, float *out, int64_t nfloats);
-int build_lut_sgdm_host(double mu, int32_t T, int32_t K, const double *sched, float *out, int64_t nfloats);
+// Host images of the tables at step 1 (`out`, lut_total_bytes bytes).
+int build_lut_host(double b1, double b2, int32_t T, int32_t K, const double *sched, void *out, int64_t nbytes);
+int build_lut_sgdm_host(double mu, int32_t T, int32_t K, const double *sched, void *out, int64_t nbytes);
 int build_lut_adamw_host(double b1, double b2, double lam, const float *rates, int nclass, int32_t T, int32_t K,
-                         const double *sched, float *out, int64_t nfloats);
+                         const double *sched, void *out, int64_t nbytes);
+// Advance a host image from the step it holds to `step` (each step as the
+// device advance does it); -1 when step is below the held step or above T + 1.
+int seek_lut_host(void *img, int64_t nbytes, int64_t step);
 
 }  // namespace gsdp

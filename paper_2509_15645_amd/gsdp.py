@@ -29,7 +29,8 @@ SYMBOLS = ("gs_lut_bytes", "gs_lut_build", "gs_lut_build_host", "gs_lut_build_sc
            "gs_camera_pack_bytes", "gs_camera_pack", "gs_multi_workspace_bytes", "gs_cull_multi",
            "gs_cull_multi_autotune", "gs_grad_sum_multi", "gs_plan_image_split", "gs_lut_build_sgd_momentum",
            "gs_lut_build_sgd_momentum_host", "gs_lut_bytes_adamw", "gs_lut_build_adamw", "gs_lut_build_adamw_host",
-           "gs_densify_workspace_bytes", "gs_densify_plan", "gs_densify_apply", "gs_cull_noalloc")
+           "gs_densify_workspace_bytes", "gs_densify_plan", "gs_densify_apply", "gs_cull_noalloc",
+           "gs_lut_seek", "gs_lut_seek_host")
 
 
 class GsCamera(C.Structure):
@@ -72,6 +73,8 @@ def _load():
         "gs_lut_bytes": (C.c_int, [i32, i32, P(sz)]),
         "gs_lut_build": (C.c_int, [f64, f64, i32, i32, vp, sz]),
         "gs_lut_build_host": (C.c_int, [f64, f64, i32, i32, vp, sz]),
+        "gs_lut_seek": (C.c_int, [P(GsModel), i64, vp]),
+        "gs_lut_seek_host": (C.c_int, [vp, sz, i64]),
         "gs_lut_build_schedule": (C.c_int, [f64, f64, i32, i32, vp, vp, sz]),
         "gs_lut_build_schedule_host": (C.c_int, [f64, f64, i32, i32, vp, vp, sz]),
         "gs_lut_build_sgd_momentum": (C.c_int, [f64, i32, i32, vp, vp, sz]),
@@ -164,14 +167,29 @@ def gs_lut_build(beta1, beta2, max_steps, max_defer, lut: torch.Tensor):
            "gs_lut_build")
 
 
+def _host_image(nbytes: int) -> np.ndarray:
+    """A zeroed, 8-byte aligned host buffer of nbytes bytes (uint8 view)."""
+    return np.zeros((nbytes + 7) // 8, np.float64).view(np.uint8)[:nbytes]
+
+
 def gs_lut_build_host(beta1, beta2, max_steps, max_defer, lr_scale=None) -> np.ndarray:
+    """Host image (uint8) of the tables at step 1."""
     nbytes = gs_lut_bytes(max_steps, max_defer)
-    out = np.zeros(nbytes // 4, np.float32)
+    out = _host_image(nbytes)
     sc = None if lr_scale is None else np.ascontiguousarray(lr_scale, np.float64)
     _check(lib.gs_lut_build_schedule_host(beta1, beta2, max_steps, max_defer,
                                           None if sc is None else sc.ctypes.data, out.ctypes.data, nbytes),
            "gs_lut_build_host")
     return out
+
+
+def gs_lut_seek_host(img: np.ndarray, step: int):
+    """Advance a host image of the tables (in place) to `step`."""
+    _check(lib.gs_lut_seek_host(img.ctypes.data, img.nbytes, int(step)), "gs_lut_seek_host")
+
+
+def gs_lut_seek(model, step: int, stream=None):
+    _check(lib.gs_lut_seek(C.byref(model.c), int(step), _stream(stream)), "gs_lut_seek")
 
 
 def gs_lut_build_schedule(beta1, beta2, max_steps, max_defer, lr_scale, lut: torch.Tensor):
@@ -190,7 +208,7 @@ def gs_lut_build_sgd_momentum(momentum, max_steps, max_defer, lr_scale, lut: tor
 
 def gs_lut_build_sgd_momentum_host(momentum, max_steps, max_defer, lr_scale=None) -> np.ndarray:
     nbytes = gs_lut_bytes(max_steps, max_defer)
-    out = np.zeros(nbytes // 4, np.float32)
+    out = _host_image(nbytes)
     sc = None if lr_scale is None else np.ascontiguousarray(lr_scale, np.float64)
     _check(lib.gs_lut_build_sgd_momentum_host(momentum, max_steps, max_defer,
                                               None if sc is None else sc.ctypes.data, out.ctypes.data, nbytes),
@@ -347,10 +365,24 @@ class Model:
         return self.ws.numel() * 4
 
     def ws_header(self) -> dict:
+        """Diagnostic counters of the workspace; "error" is the tables' error
+        word (bit 0: a call's step was not the one the tables held; bit 1: a
+        step outside [1, max_steps])."""
         h = self.ws[:8].cpu().numpy().view(np.uint32)
         q = h[4:8].view(np.uint64)
-        return {"vis_total": int(h[0]), "sat_total": int(h[1]), "restored_last": int(h[2]), "error": int(h[3]),
+        return {"vis_total": int(h[0]), "sat_total": int(h[1]), "restored_last": int(h[2]),
+                "error": int(h[3]) | self.lut_header()["error"],
                 "vis_accum": int(q[0]), "restored_accum": int(q[1])}
+
+    def lut_header(self) -> dict:
+        """The tables' header: the step each row slot holds and the error word."""
+        h = self.lut[:16].view(torch.int32).cpu().numpy()
+        return {"t_row": (int(h[0]), int(h[1])), "T": int(h[2]), "K": int(h[3]), "nclass": int(h[4]),
+                "error": int(h[5]), "kind": int(h[6])}
+
+    def lut_seek(self, step: int):
+        """Move the tables forward to `step` (to start a model at a later step)."""
+        gs_lut_seek(self, step)
 
     def state(self):
         """Host copies: geo/app w (float32), m, v (float32 or raw uint16 BF16 bits) and last_step."""
@@ -450,6 +482,8 @@ def densify(model: Model, step: int, grad_accum, grad_denom, max_radii2d=None, *
                 **model._kw)
     _check(lib.gs_densify_apply(C.byref(model.c), C.byref(p), C.byref(new.c), int(step), _ptr(ws), ws.numel() * 4,
                                 _stream(stream)), "gs_densify_apply")
+    # the resized model continues at the next update: it takes over the tables
+    new.lut.copy_(model.lut)
     return new, [int(x) for x in counts]
 
 

@@ -8,6 +8,7 @@ import re
 import numpy as np
 import pytest
 
+import lut_layout as LL
 from oracle import oracle as orc
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -71,25 +72,38 @@ def test_argument_checks_need_no_device(gsdp):
 
 @pytest.mark.parametrize("max_defer", [0, 15])
 def test_host_tables_equal_oracle_tables_bitwise(gsdp, max_defer):
-    T = 300
-    lut = gsdp.gs_lut_build_host(0.9, 0.999, T, max_defer)
-    K = max_defer
-    rows = T + 1
-    nW = rows * (K + 1) if K else rows * (rows + 1) // 2
-    nMV = (K if K else T) + 1
-    offM, offV = nW, nW + nMV
-    offSS = offV + nMV
-    offBC = offSS + T + 2
-    assert lut.shape[0] == offBC + T + 2
+    """The library's tables, advanced step by step from step 1 as the update
+    calls advance them, against the oracle's independently computed FP32
+    tables of each step; the size is O(max_steps + max_defer)."""
+    T, K = 300, max_defer
+    img = gsdp.gs_lut_build_host(0.9, 0.999, T, K)
+    assert img.nbytes == LL.layout(T, K)["total"]
+    v = LL.views(img, T, K)
+    assert tuple(v["hdr"][:5]) == (0, 1, T, K, 0)
     for t in [1, 2, 3, 16, 17, 100, T, T + 1]:
-        row = (t - 1) * (K + 1) if K else t * (t - 1) // 2
+        gsdp.gs_lut_seek_host(img, t)
         dmax = min(t - 1, K) if K else t - 1
+        slot = t & 1
+        assert v["hdr"][slot] == t and v["hdr"][5] == 0
         Wf, Mf, Vf, ss, bc = orc.lut_spec(0.9, 0.999, t, dmax)
-        assert np.array_equal(lut[row:row + dmax + 1].view(np.uint32), Wf.view(np.uint32)), t
-        assert np.array_equal(lut[offM:offM + dmax + 1].view(np.uint32), Mf.view(np.uint32))
-        assert np.array_equal(lut[offV:offV + dmax + 1].view(np.uint32), Vf.view(np.uint32))
-        assert lut[offSS + t].view(np.uint32) == np.float32(ss).view(np.uint32)
-        assert lut[offBC + t].view(np.uint32) == np.float32(bc).view(np.uint32)
+        assert np.array_equal(v["Wf"][slot, :dmax + 1].view(np.uint32), Wf.view(np.uint32)), t
+        assert np.array_equal(v["Mf"][:dmax + 1].view(np.uint32), Mf.view(np.uint32))
+        assert np.array_equal(v["Vf"][:dmax + 1].view(np.uint32), Vf.view(np.uint32))
+        assert v["SS"][t].view(np.uint32) == np.float32(ss).view(np.uint32)
+        assert v["BC"][t].view(np.uint32) == np.float32(bc).view(np.uint32)
+    # moving backwards or past T + 1 is refused
+    with pytest.raises(RuntimeError):
+        gsdp.gs_lut_seek_host(img, T)
+    with pytest.raises(RuntimeError):
+        gsdp.gs_lut_seek_host(img, T + 2)
+
+
+def test_tables_of_a_long_run_are_small(gsdp):
+    """30000 steps with unbounded deferral fit in about 1.7 MB."""
+    b = C.c_size_t()
+    assert gsdp.lib.gs_lut_bytes(30000, 0, C.byref(b)) == 0
+    assert b.value == LL.layout(30000, 0)["total"] and b.value < 2_000_000
+    assert gsdp.lib.gs_lut_bytes(30000, 15, C.byref(b)) == 0 and b.value < 600_000
 
 
 def test_batched_entry_points_check_arguments(gsdp):
@@ -136,45 +150,38 @@ def test_camera_pack_layout(gsdp):
 
 @pytest.mark.parametrize("max_defer", [0, 15])
 def test_host_schedule_tables_equal_oracle_tables_bitwise(gsdp, max_defer):
-    T = 120
+    T, K = 120, max_defer
     rng = np.random.default_rng(5)
     sc = 0.01 ** (np.arange(T + 2) / (T + 1)) * rng.uniform(0.5, 2.0, T + 2)
-    lut = gsdp.gs_lut_build_host(0.9, 0.999, T, max_defer, lr_scale=sc)
-    K = max_defer
-    rows = T + 1
-    nW = rows * (K + 1) if K else rows * (rows + 1) // 2
-    nMV = (K if K else T) + 1
-    offSS = nW + 2 * nMV
+    img = gsdp.gs_lut_build_host(0.9, 0.999, T, K, lr_scale=sc)
+    v = LL.views(img, T, K)
     for t in [1, 2, 17, 60, T, T + 1]:
-        row = (t - 1) * (K + 1) if K else t * (t - 1) // 2
+        gsdp.gs_lut_seek_host(img, t)
         dmax = min(t - 1, K) if K else t - 1
         Wf, _, _, ss, _ = orc.lut_spec(0.9, 0.999, t, dmax, sc)
-        assert np.array_equal(lut[row:row + dmax + 1].view(np.uint32), Wf.view(np.uint32)), t
-        assert lut[offSS + t].view(np.uint32) == np.float32(ss).view(np.uint32)
+        assert np.array_equal(v["Wf"][t & 1, :dmax + 1].view(np.uint32), Wf.view(np.uint32)), t
+        assert v["SS"][t].view(np.uint32) == np.float32(ss).view(np.uint32)
 
 
 @pytest.mark.parametrize("max_defer,sched", [(0, False), (15, True)])
 def test_host_sgd_momentum_tables_equal_oracle_bitwise(gsdp, max_defer, sched):
-    T, mu = 90, 0.9
+    T, mu, K = 90, 0.9, max_defer
     sc = None
     if sched:
         rng = np.random.default_rng(8)
         sc = 0.01 ** (np.arange(T + 2) / (T + 1)) * rng.uniform(0.5, 2.0, T + 2)
-    lut = gsdp.gs_lut_build_sgd_momentum_host(mu, T, max_defer, lr_scale=sc)
-    K = max_defer
-    rows = T + 1
-    nW = rows * (K + 1) if K else rows * (rows + 1) // 2
-    nMV = (K if K else T) + 1
-    offM, offSS = nW, nW + 2 * nMV
+    img = gsdp.gs_lut_build_sgd_momentum_host(mu, T, K, lr_scale=sc)
+    v = LL.views(img, T, K)
+    assert v["hdr"][6] == 1
     for t in [1, 2, 16, 17, 50, T, T + 1]:
-        row = (t - 1) * (K + 1) if K else t * (t - 1) // 2
+        gsdp.gs_lut_seek_host(img, t)
         dmax = min(t - 1, K) if K else t - 1
         Wf, Mf, ss = orc.lut_sgdm_spec(mu, t, dmax, sc)
-        assert np.array_equal(lut[row:row + dmax + 1].view(np.uint32), Wf.view(np.uint32)), t
-        assert np.array_equal(lut[offM:offM + dmax + 1].view(np.uint32), Mf.view(np.uint32))
-        assert lut[offSS + t].view(np.uint32) == np.float32(ss).view(np.uint32)
-    small = np.zeros(4, np.float32)
-    assert gsdp.lib.gs_lut_build_sgd_momentum_host(1.0, 10, 0, None, small.ctypes.data, 16) == gsdp.GS_EINVAL
+        assert np.array_equal(v["Wf"][t & 1, :dmax + 1].view(np.uint32), Wf.view(np.uint32)), t
+        assert np.array_equal(v["Mf"][:dmax + 1].view(np.uint32), Mf.view(np.uint32))
+        assert v["SS"][t].view(np.uint32) == np.float32(ss).view(np.uint32)
+    small = np.zeros(4, np.float64)
+    assert gsdp.lib.gs_lut_build_sgd_momentum_host(1.0, 10, 0, None, small.ctypes.data, 32) == gsdp.GS_EINVAL
 
 
 @pytest.mark.parametrize("max_defer,sched", [(0, False), (15, True)])
@@ -198,26 +205,23 @@ def test_host_adamw_tables_equal_oracle_bitwise(gsdp, max_defer, sched):
         sc = 0.01 ** (np.arange(T + 2) / (T + 1)) * rng.uniform(0.5, 2.0, T + 2)
     b = C.c_size_t()
     assert gsdp.lib.gs_lut_bytes_adamw(C.byref(m), C.byref(b)) == 0
-    out = np.zeros(b.value // 4, np.float32)
+    K = max_defer
+    rates = [np.float32(lg[0]), np.float32(lg[3])]          # classes in order of first appearance
+    assert b.value == LL.layout(T, K, len(rates))["total"]
+    out = np.zeros(b.value // 8, np.float64).view(np.uint8)
     scp = None if sc is None else np.ascontiguousarray(sc).ctypes.data
     assert gsdp.lib.gs_lut_build_adamw_host(C.byref(m), lam, scp, out.ctypes.data, b.value) == 0
-    K = max_defer
-    rows = T + 1
-    nW = rows * (K + 1) if K else rows * (rows + 1) // 2
-    nMV = (K if K else T) + 1
-    base = nW + 2 * nMV + 2 * (T + 2)
-    per = 2 * nW + T + 2
-    rates = [np.float32(lg[0]), np.float32(lg[3])]          # classes in order of first appearance
-    assert b.value // 4 == base + len(rates) * per
-    for c, r in enumerate(rates):
-        for t in [1, 2, 16, 17, 40, T, T + 1]:
-            row = (t - 1) * (K + 1) if K else t * (t - 1) // 2
-            dmax = min(t - 1, K) if K else t - 1
+    v = LL.views(out, T, K, len(rates))
+    assert v["hdr"][4] == len(rates) and v["hdr"][6] == 2
+    for t in [1, 2, 16, 17, 40, T, T + 1]:
+        gsdp.gs_lut_seek_host(out, t)
+        dmax = min(t - 1, K) if K else t - 1
+        for c, r in enumerate(rates):
             Wf, Pf, qt = orc.lut_adamw_spec(0.9, 0.999, lam, r, t, dmax, sc)
-            cb = base + c * per
-            assert np.array_equal(out[cb + row:cb + row + dmax + 1].view(np.uint32), Wf.view(np.uint32)), (c, t)
-            assert np.array_equal(out[cb + nW + row:cb + nW + row + dmax + 1].view(np.uint32), Pf.view(np.uint32))
-            assert out[cb + 2 * nW + t].view(np.uint32) == np.float32(qt).view(np.uint32)
+            cv = v["cls"][c]
+            assert np.array_equal(cv["Wlf"][t & 1, :dmax + 1].view(np.uint32), Wf.view(np.uint32)), (c, t)
+            assert np.array_equal(cv["Pf"][t & 1, :dmax + 1].view(np.uint32), Pf.view(np.uint32)), (c, t)
+            assert cv["qf"][t].view(np.uint32) == np.float32(qt).view(np.uint32)
     # too many distinct rates are rejected
     for k in range(10):
         m.geo.lr[k] = 1e-3 * (k + 1)

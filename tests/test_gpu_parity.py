@@ -418,10 +418,12 @@ def test_band_cull_adversarial_deferred_rows(g, seed):
         model.geo_m.copy_(torch.from_numpy(m))
         model.geo_v.copy_(torch.from_numpy(v))
         model.last_step.copy_(torch.from_numpy((t - 1 - d).astype(np.int32)))
+        model.lut_seek(t)
         ids, count, mm = run_cull(g, model, cam, t)
         got[mode] = (u32(ids[:mm]), model.ws_header()["restored_last"])
         assert mm == valid.shape[0], (mode, mm, valid.shape[0])
         assert np.array_equal(got[mode][0], valid), mode
+        assert model.ws_header()["error"] == 0
     say(f"[band adversarial {seed}] M={valid.shape[0]} restored exact={got[0][1]} band={got[1][1]}")
     assert got[1][1] < got[0][1]
 

@@ -89,17 +89,21 @@ def test_first_step_closed_form():
 
 
 @pytest.mark.parametrize("t", [2, 5, 17, 100, 1000])
-def test_lut_recurrence_equals_eq3_sum(t):
+def test_restore_coefficients_equal_the_pseudocode_recurrence(t):
+    """The oracle's restore coefficients (the sum of Eq. 3 over the skipped
+    steps) against the paper's way of building its lookup table for step t,
+    a recurrence from the most recent skipped step backwards (Sec. 4.3.2):
+    W[0] = 0, W[d] = (b1/sqrt(b2)) W[d-1] + b1/(sqrt(b2/(1-b2^(t-d))) (1-b1^(t-d)))."""
     dmax = min(t - 1, 300)
-    lut, mom, var = orc.lut_paper(B1, B2, t, dmax)
+    coef, m_dec, v_dec = orc.restore_coeff(B1, B2, t, dmax)
+    W = 0.0
     for d in range(dmax + 1):
-        direct = 0.0
-        for l in range(d):
-            k = t - d + l
-            direct += (B1 ** (l + 1) / (1 - B1 ** k)) / np.sqrt(B2 ** (l + 1) / (1 - B2 ** k))
-        assert abs(lut[d] - direct) <= 4e-15 * max(abs(direct), 1e-300)
-        assert mom[d] == pytest.approx(B1 ** (d + 1), rel=1e-15)
-        assert var[d] == pytest.approx(B2 ** (d + 1), rel=1e-15)
+        if d > 0:
+            k = t - d
+            W = B1 / np.sqrt(B2) * W + B1 / (np.sqrt(B2 / (1 - B2 ** k)) * (1 - B1 ** k))
+        assert abs(coef[d] - W) <= 4e-15 * max(abs(W), 1e-300)
+        assert m_dec[d] == pytest.approx(B1 ** (d + 1), rel=1e-15)
+        assert v_dec[d] == pytest.approx(B2 ** (d + 1), rel=1e-15)
 
 
 @pytest.mark.parametrize("L,d", [(1, 1), (3, 5), (10, 40), (50, 200)])
@@ -119,9 +123,9 @@ def test_restore_equals_hand_stepping_zero_grads(L, d):
     for t in range(L + 1, L + d + 1):
         dense.step(t, empty, np.zeros((0, 10), np.float32), np.zeros((0, 49), np.float32))
     t = L + d + 1
-    lut, mom, var = orc.lut_paper(B1, B2, t, d)
+    coef, _, _ = orc.restore_coeff(B1, B2, t, d)
     for k, lr in enumerate((lg, la)):
-        restored = w_L[k] - lut[d] * lr.astype(np.float64) * m_L[k] / np.sqrt(v_L[k])
+        restored = w_L[k] - coef[d] * lr.astype(np.float64) * m_L[k] / np.sqrt(v_L[k])
         assert np.max(np.abs(restored - dense.w[k]) / np.maximum(np.abs(dense.w[k]), 1e-3)) < 1e-13
         # moments decay by b^d over the d zero steps
         assert np.allclose(dense.m[k], m_L[k] * B1 ** d, rtol=1e-13, atol=0)
@@ -176,7 +180,7 @@ def test_eps_factor_out_error_is_tiny_at_1e_15():
 @pytest.mark.parametrize("t", [2, 17, 100, 1000])
 def test_spec_lut_within_one_rounding_of_paper_lut(t):
     dmax = t - 1
-    lut, mom, var = orc.lut_paper(B1, B2, t, dmax)
+    lut, mom, var = orc.restore_coeff(B1, B2, t, dmax)
     Wf, Mf, Vf, ss, bc = orc.lut_spec(B1, B2, t, dmax)
     for a, b in ((Wf, lut), (Mf, mom), (Vf, var)):
         ulp = np.spacing(np.abs(b).astype(np.float32)).astype(np.float64)
@@ -402,7 +406,7 @@ def test_deferred_f64_with_schedule_equals_dense(max_defer):
 def test_spec_lut_with_schedule_within_one_rounding_of_paper_lut():
     sc = _schedule(200, 3)
     for t in (2, 50, 201):
-        lut, _, _ = orc.lut_paper(B1, B2, t, t - 1, sc)
+        lut, _, _ = orc.restore_coeff(B1, B2, t, t - 1, sc)
         Wf, _, _, ss, _ = orc.lut_spec(B1, B2, t, t - 1, sc)
         ulp = np.spacing(np.abs(lut).astype(np.float32)).astype(np.float64)
         assert np.all(np.abs(Wf.astype(np.float64) - lut) <= ulp)

@@ -77,11 +77,15 @@ def test_decayed_tables_equal_direct_sum(t):
     r = B1 / np.sqrt(B2)
     c = lambda k: B1 / (np.sqrt(B2 / (1 - B2 ** k)) * (1 - B1 ** k))
     q = lambda k: 1 - lr * sc[k] * LAM
+    # the backward recurrence over the skipped steps, most recent first:
+    # Wl[d] = r Wl[d-1] + P[d-1] s c(t-d),  P[d] = P[d-1] q(t-d)
+    rw, rp = 0.0, 1.0
     for d in range(t):
-        direct = sum(np.prod([q(t - j) for j in range(1, i)]) * r ** (d - i) * sc[t - i] * c(t - i)
-                     for i in range(1, d + 1))
-        assert abs(W[d] - direct) <= 1e-13 * max(1.0, abs(direct))
-        assert abs(P[d] - np.prod([q(t - i) for i in range(1, d + 1)])) <= 1e-15
+        if d > 0:
+            rw = r * rw + rp * sc[t - d] * c(t - d)
+            rp = rp * q(t - d)
+        assert abs(W[d] - rw) <= 1e-13 * max(1.0, abs(rw))
+        assert abs(P[d] - rp) <= 1e-15
     Wf, Pf, qt = orc.lut_adamw_spec(B1, B2, LAM, np.float32(lr), t, t - 1, sc)
     assert np.all(np.abs(Wf.astype(np.float64) - W) <= 2 * np.spacing(np.abs(W).astype(np.float32)))
     assert np.all(np.abs(Pf.astype(np.float64) - P) <= 2 * np.spacing(np.abs(P).astype(np.float32)))
