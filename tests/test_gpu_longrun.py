@@ -8,7 +8,8 @@ factor-out; these tests check it over the long runs of the aerial workloads:
     (O3); on a seeded row sample, the flushed parameters against dense FP64
     Adam within max(1e-6, 3 x the error of a plain dense FP32 Adam) per element
     (relative to max(|w64|, tau)).
-  * 18M and 40M Gaussians on a seeded sample of whole 128-row blocks (exact:
+  * 18M and 40M Gaussians (and the 40M workload with the visible fraction
+    matched to the paper's 8.28%) on a seeded sample of whole 128-row blocks (exact:
     Adam is per row given the visible sets, and an FP8 block scale depends on
     its block's rows only): every step the sample's visible ids and gathered
     rows bit-exact against the oracle's own cull and restore of the sample,
@@ -136,7 +137,8 @@ def test_aerial4m_long_run_vs_oracle(g, max_defer, steps):
 
 
 @pytest.mark.parametrize("workload,state,steps", [("aerial18m", "f32", 200), ("aerial40m", "f32", 300),
-                                                  ("aerial40m", "bf16", 300), ("aerial40m", "fp8", 300)])
+                                                  ("aerial40m", "bf16", 300), ("aerial40m", "fp8", 300),
+                                                  ("aerial40m_f8", "f32", 60), ("aerial40m_f8", "bf16", 60)])
 def test_aerial_sampled_long_run(g, workload, state, steps):
     w = gi.workload(workload)
     n, dev = w.n, torch.device("cuda")
@@ -155,7 +157,7 @@ def test_aerial_sampled_long_run(g, workload, state, steps):
     o3 = orc.DeferredF32(gs_, as_, lg, la, state=state, sr_seed=11, keys=sample, track_bound=quant)
     dense = orc.DenseAdamF64(gs_, as_, lg, la)
     d32 = None if quant else orc.DenseAdamF32(gs_, as_, lg, la)
-    cap = n // 4
+    cap = n // 2                     # a high oblique camera of the 8% workload sees up to 27%
     ids = torch.zeros(cap, dtype=torch.int32, device=dev)
     count = torch.zeros(1, dtype=torch.int32, device=dev)
     out_g = torch.zeros((cap, 10), dtype=torch.float32, device=dev)
@@ -167,8 +169,9 @@ def test_aerial_sampled_long_run(g, workload, state, steps):
         g.gs_gather(model, t, ids, count, out_g, out_a)
         m = int(count.item())
         assert m <= cap
-        gg = torch.empty((m, 10), dtype=torch.float32, device=dev)
-        ga = torch.empty((m, 49), dtype=torch.float32, device=dev)
+        # (a camera at the edge of the box may see nothing: keep the buffers non-empty)
+        gg = torch.empty((max(m, 1), 10), dtype=torch.float32, device=dev)
+        ga = torch.empty((max(m, 1), 49), dtype=torch.float32, device=dev)
         mt = torch.tensor([m], dtype=torch.int32, device=dev)
         g.gs_synth_grad(31, t, None, mt, gg, 0)
         g.gs_synth_grad(31, t, None, mt, ga, 10)
