@@ -235,6 +235,10 @@ def _compare_state(model, o3, tag):
     (15, "fused", "dense", 1, ("f32", "f32"), 0, False),
     (15, "interleaved", "compact", 1, ("f32", "f32"), 0, True),
     (0, "separate", "dense", 0, ("f32", "f32"), 1, True),
+    # FP8 moments with MAX = inf and compact gradients in the fused and separate layouts
+    (0, "fused", "compact", 1, ("fp8", "fp8"), 0, False),
+    (0, "separate", "compact", 0, ("f32", "fp8"), 0, False),
+    (0, "fused", "compact", 1, ("bf16", "fp8"), 0, True),
 ])
 def test_small_workload_path_vs_oracle(g, max_defer, layout, grad_mode, cull_mode, states, geo_mode, sched):
     """100k Gaussians, 10 orbit cameras, 20 steps: every step's visible ids and
