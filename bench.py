@@ -63,6 +63,8 @@ def parse():
     p.add_argument("--order", default="generated", choices=["generated", "morton"],
                    help="row order of the scene: as generated (spatially random) or sorted by the Morton code "
                         "of the position (visible rows then form contiguous runs)")
+    p.add_argument("--metrics-jsonl", default=None,
+                   help="append one JSON record per timed step (HIP event times per call) to this file")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample", type=int, default=1 << 20)
     p.add_argument("--cpu-steps", type=int, default=6)
@@ -441,6 +443,12 @@ def run_single(args, w, geo0, app0, state, tilt, on_dev):
         graph_ms = (time.perf_counter() - g0) * 1e3 / reps
     k_ms = np.array([[e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2]), e[2].elapsed_time(e[3])]
                      for e in evs])
+    if args.metrics_jsonl:
+        with open(args.metrics_jsonl, "a") as fh:
+            for k, row in enumerate(k_ms):
+                fh.write(json.dumps({"workload": w.name, "state": state, "step": args.warmup + 1 + k,
+                                     "cull_ms": float(row[0]), "gather_ms": float(row[1]),
+                                     "adam_ms": float(row[2]), "step_ms": float(row.sum())}) + "\n")
     cull_ms, gather_ms, adam_ms = k_ms.mean(0)
     step_ev = k_ms.sum(1)
     vis_total = h1["vis_accum"] - h0["vis_accum"]
