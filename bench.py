@@ -103,8 +103,24 @@ def cpu_baseline(w, geo_all, app_all, sample, steps, lg, la):
         med = float(np.median(ts))
         return med, float(np.percentile(ts, 10)), float(np.percentile(ts, 90))
 
+    def paper_leg(nsteps):
+        # the paper's own CPU method on this host: the deferred update (FP32
+        # state, OpenMP) of the visible rows only, after the cull of the
+        # sample's current geometry
+        model = orc.DeferredF32(geo, app, lg, la)
+        times = []
+        for t in range(1, nsteps + 1):
+            t0 = time.perf_counter()
+            valid = model.cull_current(t, w.camera_for_step(t))
+            gg, ga = gi.step_grads(0, t, rows[valid])
+            model.step(t, valid, gg, ga)
+            times.append(time.perf_counter() - t0)
+        ts = np.array(times[1:] if len(times) > 1 else times)
+        return float(np.median(ts))
+
     cores = orc.set_threads(0)
     med, p10, p90 = leg(steps)
+    med_paper = paper_leg(steps)
     orc.set_threads(1)
     med1, p10_1, p90_1 = leg(max(3, steps // 2))
     orc.set_threads(cores)
@@ -116,6 +132,10 @@ def cpu_baseline(w, geo_all, app_all, sample, steps, lg, la):
             "step_ms": {"p10": p10 * 1e3, "p50": med * 1e3, "p90": p90 * 1e3},
             "single_thread": {"value": rows.shape[0] / med1, "unit": "Gaussians/s", "cores": 1,
                               "step_ms": {"p10": p10_1 * 1e3, "p50": med1 * 1e3, "p90": p90_1 * 1e3}},
+            "paper_method_on_host": {"value": rows.shape[0] / med_paper, "unit": "Gaussians/s", "cores": cores,
+                                     "what": "the paper's deferred update (FP32 state, OpenMP) of the visible rows "
+                                             "after the cull of the sample's current geometry, median step "
+                                             f"{med_paper * 1e3:.1f} ms"},
             "cpu_model": model, "numa_nodes": numa}
 
 
