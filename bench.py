@@ -294,6 +294,14 @@ def run_batched(args):
         cc_tot += int(multi.cam_count.sum().item())
     if int(multi.cam_count.max().item()) > cap_cam:
         raise RuntimeError("camera list capacity exceeded")
+    hdr = model.lut_header()
+    if hdr["error"]:
+        raise RuntimeError(f"deferred-update tables report an error: {hdr}")
+    # rows behind the current step (deferred) and their mean defer count
+    t_now = int(model.step_dev.item())
+    lag = (t_now - 1) - model.last_step.long()
+    deferred = {"step": t_now, "rows_deferred_frac": float((lag > 0).double().mean().item()),
+                "mean_defer": float(lag.clamp(min=0).double().mean().item())}
     k_ms = np.array([[e[i].elapsed_time(e[i + 1]) for i in range(4)] for e in ev]).mean(0)
     U, CC = U_tot / 3.0, cc_tot / 3.0
     sg = 4 if (args.geo_state or "bf16") == "f32" else 2
@@ -315,7 +323,8 @@ def run_batched(args):
                    "row_order": args.order,
                    "rows_padded": N, "cameras_per_scene": C, "union_per_step": U, "camera_entries_per_step": CC,
                    "geo_state": args.geo_state or "bf16", "app_state": "bf16",
-                   "autotune_ms": times, "variant": int(multi.c.variant), "hipgraph": True},
+                   "autotune_ms": times, "variant": int(multi.c.variant), "hipgraph": True,
+                   "deferral": deferred},
         "kernels_ms": {k: float(v[0]) for k, v in kern.items()},
         "kernels_gbs": {k: v[1] / (v[0] * 1e-3) / 1e9 for k, v in kern.items()},
         "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -584,33 +584,38 @@ struct StepK {
 
 // The step of a launch (from the device counter when t_dev is set) and the
 // restore row of step + extra: slot (step + extra) & 1 of the tables, whose
-// header says which step it holds.  ok = false when the step lies outside
-// [1, T] or the slot holds another step; the header's error word then records
-// it (bit 1, bit 0), the step is clamped for indexing, and callers that store
-// state skip their stores.
-__device__ __forceinline__ int resolve_step(const StepK &s, int extra, const float **wrow, int *dmax,
-                                            bool *ok = nullptr)
+// header says which step it holds.  *err (uniform over the grid) is nonzero
+// when the step lies outside [1, T] (bit 1) or the slot holds another step
+// (bit 0); the step is then clamped for indexing, callers that store state
+// skip their stores, and step_flag records the error in the header.
+__device__ __forceinline__ int resolve_step(const StepK &s, int extra, const float **wrow, int *dmax, int *err)
 {
     int t = s.t;                     // an explicit step was checked against [1, T] by the host
-    int err = 0;
+    int e = 0;
     if (s.t_dev) {
         t = *s.t_dev;
         if (t < 1 || t > s.T) {
-            err = 2;
+            e = 2;
             t = t < 1 ? 1 : s.T;
         }
     }
     const int tr = t + extra;
     const int slot = tr & 1;
-    if (s.hdr->t_row[slot] != tr) err |= 1;
-    // err is uniform (the header word is the same for every lane)
-    if (err) atomicOr(&s.hdr->error, err);
-    if (ok) *ok = err == 0;
+    if (s.hdr->t_row[slot] != tr) e |= 1;
+    *err = e;
     *wrow = s.lut + (int64_t)slot * s.nrow;
     int64_t dm = tr - 1;
     if (s.K > 0 && dm > s.K) dm = s.K;
     *dmax = (int)dm;
     return t;
+}
+
+// Records a step error in the header's error word.  Kernels call it after
+// their last load of model data: a store or atomic that may precede a load
+// keeps the compiler from reading uniform data through the scalar cache.
+__device__ __forceinline__ void step_flag(const StepK &s, int err)
+{
+    if (err) atomicOr(&s.hdr->error, err);
 }
 
 // ---------------------------------------------------------------------------
@@ -670,8 +675,8 @@ __global__ __launch_bounds__(kCullBlock, 7) void k_cull(CullArgs a)
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t tile = blockIdx.x;
     const float *Wrow;
-    int dmax;
-    const int t = resolve_step(a.step, 0, &Wrow, &dmax);
+    int dmax, step_err;
+    const int t = resolve_step(a.step, 0, &Wrow, &dmax, &step_err);
     const int K = a.K;
     if (tid == 0) sRestored = 0;
     const int64_t row0 = tile * kCullTile;
@@ -815,6 +820,7 @@ __global__ __launch_bounds__(kCullBlock, 7) void k_cull(CullArgs a)
         a.tile_vs[tile] = ((u64)sv << 32) | (u64)ss;
         a.tile_rest[tile] = sRestored;
     }
+    step_flag(a.step, step_err);
 }
 
 // Block scans used by the one-block counter scans of the batched cull and of
@@ -1145,7 +1151,7 @@ struct RowArgs {
 // FZ: the fused layout with one storage type for both groups; the moments of
 // every lane are then one access from the row's single base.
 template <int MODE, int GST, int AST, int OPT, bool FZ>
-__global__ __launch_bounds__(256) void k_rows(RowArgs a)
+__device__ __forceinline__ void rows_work(const RowArgs &a, const int t, const float *const Wrow, const int dmax)
 {
     constexpr int kRU = row_unroll<MODE>();
     const int lane = threadIdx.x & 63;
@@ -1187,15 +1193,6 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
     // the same at a row base already computed
     auto at = [](gchar *b, u32 o) { return (char *)(b + lane_off(o)); };
     const float lr = a.lr[lane];
-    const float *Wrow;
-    int dmax;
-    bool step_ok;
-    const int t = resolve_step(a.step, MODE == kFlush ? 1 : 0, &Wrow, &dmax, &step_ok);
-    // the tables do not hold this step: nothing is stored (the gather still
-    // writes its outputs; the header's error word says they are not valid)
-    if (!step_ok && MODE != kGather) return;
-    if (MODE == kAdam && a.adv.on)
-        lut_advance_slice(a.adv, a.step, t, (int64_t)blockIdx.x * 256 + threadIdx.x, (int64_t)gridDim.x * 256);
     // AdamW: this lane's rate class tables, same row offset as Wrow
     const float *WlRow = Wrow, *PRow = Wrow;
     float qdec = 1.0f;
@@ -1540,6 +1537,26 @@ __global__ __launch_bounds__(256) void k_rows(RowArgs a)
     }
 }
 
+// The step, the rows, then the tables' advance to the next step: its stores
+// follow every load of the rows, so the rows' uniform loads stay scalar.
+template <int MODE, int GST, int AST, int OPT, bool FZ>
+__global__ __launch_bounds__(256) void k_rows(RowArgs a)
+{
+    const float *Wrow;
+    int dmax, step_err;
+    const int t = resolve_step(a.step, MODE == kFlush ? 1 : 0, &Wrow, &dmax, &step_err);
+    // the tables do not hold this step: nothing is stored (the gather still
+    // writes its outputs; the header's error word says they are not valid)
+    if (step_err && MODE != kGather) {
+        step_flag(a.step, step_err);
+        return;
+    }
+    rows_work<MODE, GST, AST, OPT, FZ>(a, t, Wrow, dmax);
+    if (MODE == kAdam && a.adv.on)
+        lut_advance_slice(a.adv, a.step, t, (int64_t)blockIdx.x * 256 + threadIdx.x, (int64_t)gridDim.x * 256);
+    step_flag(a.step, step_err);
+}
+
 // ---------------------------------------------------------------------------
 // Row kernels of the common configuration: Adam, one moment storage type
 // (FP32 or BF16) for both groups, the fused layout with the moments of the
@@ -1583,7 +1600,7 @@ __device__ __forceinline__ gfloat *gptr(u64 a) { return (gfloat *)a; }
 __device__ __forceinline__ const cfloat *cptr(const float *p) { return (const cfloat *)(uintptr_t)p; }
 
 template <int MODE, int ST, int RU>
-__global__ __launch_bounds__(256) void k_rows_fz(FastArgs a)
+__device__ __forceinline__ void rows_fz_work(const FastArgs &a, const int t, const float *const Wrow, const int dmax)
 {
     static_assert(MODE == kGather || MODE == kAdam, "gather and update only");
     static_assert(ST == GS_F32 || ST == GS_BF16, "FP32 or BF16 moments");
@@ -1605,13 +1622,6 @@ __global__ __launch_bounds__(256) void k_rows_fz(FastArgs a)
                                  : (isG ? (u64)(a.out_geo + lane) : (u64)(a.out_app + col));
     const u32 cst = isG ? 40u : 4u * adim;
     const float lr = a.lr[lane];
-    const float *Wrow;
-    int dmax;
-    bool step_ok;
-    const int t = resolve_step(a.step, 0, &Wrow, &dmax, &step_ok);
-    if (!step_ok && MODE == kAdam) return;
-    if (MODE == kAdam && a.adv.on)
-        lut_advance_slice(a.adv, a.step, t, (int64_t)blockIdx.x * 256 + threadIdx.x, (int64_t)gridDim.x * 256);
     const cfloat *W4 = cptr(Wrow), *Mf4 = cptr(a.Mf), *Vf4 = cptr(a.Vf);
     if (a.n == 0) return;
     const u32 n = a.n;
@@ -1728,6 +1738,23 @@ __global__ __launch_bounds__(256) void k_rows_fz(FastArgs a)
     }
 }
 
+// The step, the rows, then the tables' advance (after every load of the rows).
+template <int MODE, int ST, int RU>
+__global__ __launch_bounds__(256) void k_rows_fz(FastArgs a)
+{
+    const float *Wrow;
+    int dmax, step_err;
+    const int t = resolve_step(a.step, 0, &Wrow, &dmax, &step_err);
+    if (step_err && MODE == kAdam) {
+        step_flag(a.step, step_err);
+        return;
+    }
+    rows_fz_work<MODE, ST, RU>(a, t, Wrow, dmax);
+    if (MODE == kAdam && a.adv.on)
+        lut_advance_slice(a.adv, a.step, t, (int64_t)blockIdx.x * 256 + threadIdx.x, (int64_t)gridDim.x * 256);
+    step_flag(a.step, step_err);
+}
+
 // FP8 scale growth between the two Adam passes: every 128-row block whose
 // recorded max outgrew its scale gets the smallest power-of-two scale that
 // fits, and all its rows are re-encoded (random column = column + 64); the
@@ -1753,10 +1780,12 @@ __global__ __launch_bounds__(256) void k_fp8_rescale(RescaleArgs a)
     __shared__ float sOld;
     const int tid = threadIdx.x;
     const float *Wrow;
-    int dmax;
-    bool ok;
-    const int t = resolve_step(a.step, 0, &Wrow, &dmax, &ok);
-    if (!ok) return;
+    int dmax, step_err;
+    const int t = resolve_step(a.step, 0, &Wrow, &dmax, &step_err);
+    if (step_err) {
+        step_flag(a.step, step_err);
+        return;
+    }
     const u64 s_step = sm_at(a.sr_seed, (u64)t);
     const u32 ntask = (u32)min((int64_t)*a.count, 4 * a.nb);
     for (u32 i = blockIdx.x; i < ntask; i += gridDim.x) {
@@ -1866,10 +1895,12 @@ __global__ __launch_bounds__(256) void k_dense_geo(DenseArgs a)
         __syncthreads();
     }
     const float *Wrow;
-    int dmax;
-    bool ok;
-    const int t = resolve_step(a.step, 0, &Wrow, &dmax, &ok);
-    if (!ok) return;
+    int dmax, step_err;
+    const int t = resolve_step(a.step, 0, &Wrow, &dmax, &step_err);
+    if (step_err) {
+        step_flag(a.step, step_err);
+        return;
+    }
     const float ss = a.SS[t], bc = a.BC[t];
     const u64 s_step = GST != GS_F32 ? sm_at(a.sr_seed, (u64)t) : 0ull;
     for (int e = tid; e < rows * 10; e += 256) {
@@ -2376,8 +2407,8 @@ __global__ __launch_bounds__(BLOCK) void k_cull_multi(MultiArgs a)
     float *sG = reinterpret_cast<float *>(sG4);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const float *Wrow;
-    int dmax;
-    const int t = resolve_step(a.step, 0, &Wrow, &dmax);
+    int dmax, step_err;
+    const int t = resolve_step(a.step, 0, &Wrow, &dmax, &step_err);
     const int C = a.C;
     const int set = (t - 1) % a.n_sets;
     const int64_t tile = blockIdx.x;
@@ -2493,6 +2524,7 @@ __global__ __launch_bounds__(BLOCK) void k_cull_multi(MultiArgs a)
         for (int sl = 0; sl < NSLAB; ++sl) o += sCnt[sl][tid];
         a.cnt[(int64_t)tid * a.stride + tile] = o;
     }
+    step_flag(a.step, step_err);
 }
 
 // Exclusive prefixes over tiles of every counter in three launches:
@@ -2754,10 +2786,12 @@ __global__ void k_step_advance(int32_t *t) { *t += 1; }
 __global__ __launch_bounds__(256) void k_lut_advance(StepK step, LutAdv adv)
 {
     const float *wrow;
-    int dmax;
-    bool ok;
-    const int t = resolve_step(step, 0, &wrow, &dmax, &ok);
-    if (!ok) return;
+    int dmax, step_err;
+    const int t = resolve_step(step, 0, &wrow, &dmax, &step_err);
+    if (step_err) {
+        step_flag(step, step_err);
+        return;
+    }
     lut_advance_slice(adv, step, t, (int64_t)blockIdx.x * 256 + threadIdx.x, (int64_t)gridDim.x * 256);
 }
 
