@@ -49,6 +49,8 @@ def parse():
     p.add_argument("--layout", default="fused", choices=["separate", "interleaved", "fused"])
     p.add_argument("--max-defer", type=int, default=0)
     p.add_argument("--cull-mode", type=int, default=1)
+    p.add_argument("--cull-summary", type=int, default=1, choices=[0, 1],
+                   help="1: the band cull reads the 16-byte cull summaries; 0: the geometry rows")
     p.add_argument("--state", default="f32", choices=["f32", "bf16", "fp8"], help="Adam moment storage (both groups)")
     p.add_argument("--compare-state", default="bf16", choices=["", "f32", "bf16", "fp8"],
                    help="a second moment storage timed on the same scene and reported beside the first")
@@ -141,7 +143,8 @@ def cpu_baseline(w, geo_all, app_all, sample, steps, lg, la):
 
 # the launches behind each timed call (the cull is three launches: tile cull,
 # group sums, prefixes + id scatter; the batched cull four)
-KERNEL_SYMBOLS = {"cull": ["k_cull", "k_tile_reduce", "k_tile_ids"], "gather": ["k_rows_fz<0"],
+KERNEL_SYMBOLS = {"cull": ["k_cull", "k_tile_reduce", "k_tile_ids"],
+                  "cull_sum": ["k_cull_sum", "k_tile_reduce", "k_tile_ids"], "gather": ["k_rows_fz<0"],
                   "adam": ["k_rows_fz<1"], "cull_multi": ["k_cull_multi", "k_multi_reduce", "k_multi_gscan", "k_multi_offsets",
                                                       "k_multi_ids"],
                   "grad_sum": ["k_grad_sum"], "adam_bf16": ["k_rows_fz<1"]}
@@ -233,8 +236,10 @@ def run_batched(args):
     n_real = sum(sizes)
     lg, la = gi.lr_columns()
     total_steps = args.warmup + args.steps + 2
+    # (the batched cull reads the geometry rows: no summaries to keep)
     model = gsdp.Model(geo, app, lg, la, max_steps=total_steps + 4, cull_mode=args.cull_mode,
-                       app_layout=args.layout, geo_state=args.geo_state or "bf16", app_state="bf16", sr_seed=9)
+                       app_layout=args.layout, geo_state=args.geo_state or "bf16", app_state="bf16", sr_seed=9,
+                       cull_summary=False)
     del geo, app
     cap_cam = max(1, int(N * 0.08))      # one camera slot over all scenes sees up to ~5% of the rows
     multi = gsdp.Multi(model, row0, sets, cap_union=N, cap_cam=cap_cam)
@@ -337,8 +342,10 @@ def run_batched(args):
 def config_key(args, workload, state=None):
     """Names the launch configuration a counter summary was taken with."""
     st = state or args.state
+    summ = args.cull_summary and args.cull_mode == 1 and args.geo_mode == 0
     return (f"{workload}/{st}/{args.geo_state or st}/{args.layout}/cull{args.cull_mode}"
-            f"/geo{args.geo_mode}/K{args.max_defer}/tilt{args.tilt.replace(',', '-')}/{args.order}")
+            f"/geo{args.geo_mode}/K{args.max_defer}/tilt{args.tilt.replace(',', '-')}/{args.order}"
+            f"/sum{int(bool(summ))}")
 
 
 def host_cpu():
@@ -358,18 +365,24 @@ def host_cpu():
     return model, nodes
 
 
-def step_bytes(n, M, R, geo_state, app_state, geo_mode):
+def step_bytes(n, M, R, geo_state, app_state, geo_mode, summary=False):
     """Algorithmic bytes of one step per call (sg / sa: bytes per stored moment
-    of G / A): cull 44 per Gaussian + 20 sg per restored row + 4 per visible id;
-    gather id + last step + G w, m, v + A w, m, v + the 236-byte output row;
-    Adam id + last step read and write + per column w, g read, w written and
-    m, v read and written."""
+    of G / A): cull 44 per Gaussian (geometry row + last step) + 20 sg per
+    restored row + 4 per visible id, or with cull summaries 20 per Gaussian
+    (summary + last step) + (40 + 20 sg) per restored row (its geometry row and
+    moments; undecided rows that need no restore are not counted) + 4 per
+    visible id; gather id + last step + G w, m, v + A w, m, v + the 236-byte
+    output row; Adam id + last step read and write + per column w, g read, w
+    written and m, v read and written (+ the 16-byte summary written)."""
     msz = {"f32": 4, "bf16": 2, "fp8": 1}
     sg, sa = msz[geo_state], msz[app_state]
     gcols = 0 if geo_mode else 10                       # G columns handled by the sparse kernels
-    cull = 44.0 * n + 20.0 * sg * R + 4.0 * M
+    if summary:
+        cull = 20.0 * n + (40.0 + 20.0 * sg) * R + 4.0 * M
+    else:
+        cull = 44.0 * n + 20.0 * sg * R + 4.0 * M
     gather = M * (4 + 4 + 8 * 10 + 2 * sg * gcols + 8 * 49 + 2 * sa * 49)
-    adam = M * (4 + 4 + 4 + gcols * (12 + 4 * sg) + 49 * (12 + 4 * sa))
+    adam = M * (4 + 4 + 4 + gcols * (12 + 4 * sg) + 49 * (12 + 4 * sa) + (16 if summary else 0))
     if geo_mode:                                        # dense G Adam over every row
         adam += n * 10 * (8 + 4 * sg) + n / 8.0 + M * 40
     return {"cull": cull, "gather": gather, "adam": adam}
@@ -390,7 +403,9 @@ def run_single(args, w, geo0, app0, state, tilt, on_dev):
     geo_in = geo0.clone() if torch.is_tensor(geo0) else geo0
     model = gsdp.Model(geo_in, app0, lg, la, max_steps=2 * total_steps + 8, max_defer=args.max_defer,
                        cull_mode=args.cull_mode, app_layout=args.layout, geo_state=geo_state,
-                       app_state=state, geo_mode=args.geo_mode, sr_seed=9)
+                       app_state=state, geo_mode=args.geo_mode, sr_seed=9,
+                       cull_summary=None if args.cull_summary else False)
+    summ = model.cull_sum is not None
     del geo_in
     n = w.n
     cap = max(1, n // 2)             # a high oblique camera of the 8% workload sees up to 27%
@@ -485,9 +500,10 @@ def run_single(args, w, geo0, app0, state, tilt, on_dev):
     M = vis_total / args.steps
     R = rest_total / args.steps
     f = M / n
-    by = step_bytes(n, M, R, geo_state, state, args.geo_mode)
+    by = step_bytes(n, M, R, geo_state, state, args.geo_mode, summ)
     kernels = {k: (float(ms), by[k]) for k, ms in (("cull", cull_ms), ("gather", gather_ms), ("adam", adam_ms))}
     dom = max(kernels, key=lambda k: kernels[k][0])
+    sym = "cull_sum" if (dom == "cull" and summ) else dom   # the launches of the dominant call
     dms, dbytes = kernels[dom]
     achieved = dbytes / (dms * 1e-3) / 1e9
     tot_bytes = sum(by.values())
@@ -502,13 +518,14 @@ def run_single(args, w, geo0, app0, state, tilt, on_dev):
                    "image": f"{w.cameras[0].width}x{w.cameras[0].height}", "oblique_tilt_deg": list(tilt),
                    "visible_fraction": f, "visible_per_step": M, "restored_per_step": R,
                    "state": state, "geo_state": geo_state, "app_layout": args.layout,
-                   "max_defer": args.max_defer, "cull_mode": args.cull_mode, "geo_mode": args.geo_mode},
+                   "max_defer": args.max_defer, "cull_mode": args.cull_mode, "geo_mode": args.geo_mode,
+                   "cull_summary": summ},
         "kernels_ms": {k: v[0] for k, v in kernels.items()},
         "graph_ms_per_step": graph_ms,
         "kernels_gbs": {k: v[1] / (v[0] * 1e-3) / 1e9 for k, v in kernels.items()},
-        "roofline": {"kernel": dom, "launches": KERNEL_SYMBOLS[dom], "bound": "hbm", "achieved": achieved,
+        "roofline": {"kernel": dom, "launches": KERNEL_SYMBOLS[sym], "bound": "hbm", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(dom, config_key(args, w.name, state)),
+                     "traffic": measured_traffic(sym, config_key(args, w.name, state)),
                      "traffic_from": "profiles/hbm_traffic.txt (rocprofv3 FETCH_SIZE, WRITE_SIZE), "
                                      "used only while the library sources match its digest",
                      "algorithmic_bytes": dbytes},

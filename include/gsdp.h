@@ -103,6 +103,8 @@ typedef struct gs_model {
     const int32_t *step_dev; /* device step counter used by calls with step == 0 */
     int32_t optimizer;     /* GS_OPT_ADAM (default), GS_OPT_ADAMW or GS_OPT_SGD_MOMENTUM */
     int32_t reserved_;
+    float *cull_sum;       /* optional device [n][4], 16-byte aligned: the cull summary of each
+                              row (see gs_cull_summary_build), or NULL */
 } gs_model;
 
 /* Optimizers.  GS_OPT_SGD_MOMENTUM is the momentum-optimizer extension the
@@ -247,6 +249,24 @@ int gs_cull(const gs_model *model, const gs_camera *cam, int64_t step, uint32_t 
 #define GS_CULL_NOALLOC_MAX_WS ((size_t)16 << 20)
 int gs_cull_noalloc(const gs_model *model, const gs_camera *cam, int64_t step, uint32_t *ids,
                     uint32_t *count_dev, uint32_t capacity, void *stream);
+
+/* Cull summaries (a data layout of this library, not of the paper).  When
+ * model->cull_sum is set, the band cull (cull_mode 1, Adam) reads per row a
+ * 16-byte summary and the 4-byte last step instead of the 40-byte geometry
+ * row and the last step, and loads the row only where its conservative
+ * classification cannot decide; the visible list is the same as without
+ * summaries.  cull_sum[i] = (x, y, z, s): the centre of row i and s = the
+ * largest of its three log-scales plus 1e-6 times the largest of their
+ * magnitudes, or s = NaN when a geometric value is not finite, s >= 80, or
+ * the quaternion's squared norm is below 1/4.
+ * Every call of this library that stores geometry (gs_adam_step_deferred,
+ * gs_adam_flush, gs_densify_apply into dst) also stores the summaries of the
+ * rows it writes; after
+ * geometry is written any other way (initialisation, loading, densification,
+ * a caller's own kernels), call this to recompute all n summaries from
+ * model->geo.w.  Not available with geo_mode 1 (GS_EUNSUPPORTED from every
+ * call).  GS_EINVAL when cull_sum is NULL. */
+int gs_cull_summary_build(const gs_model *model, void *stream);
 
 /* Gather: out_geo[i][0..10) and out_app[i][0..dim) = current values of row
  * ids[i] before update `step`, for i < min(*count_dev, capacity).  Deferred

@@ -491,6 +491,56 @@ __device__ __forceinline__ int classify(const float *g, float wd, const CamK &c,
     return classify_cam(g, classify_pre(g, wd, b), c, b);
 }
 
+// Cull summary of one geometry row, 16 bytes: its centre and s, the largest
+// log-scale plus the classifier's rounding slack, or s = NaN when the band
+// classifier must leave the row to the exact test: a non-finite value, s of
+// 80 or more, or a quaternion of squared norm below 1/4 (the sure-in decision
+// then needs the quaternion itself).  The band cull reads these 16 bytes and
+// the last step instead of the 40-byte row; it loads the row only for the
+// rows the classifier leaves undecided.
+__device__ __forceinline__ float4 cull_summary(const float *g)
+{
+    const float fsum = (((fabsf(g[0]) + fabsf(g[1])) + (fabsf(g[2]) + fabsf(g[3]))) +
+                        ((fabsf(g[4]) + fabsf(g[5])) + (fabsf(g[6]) + fabsf(g[7])))) + (fabsf(g[8]) + fabsf(g[9]));
+    const float sm = fmaxf(fmaxf(g[3], g[4]), g[5]) + 1e-6f * fmaxf(fmaxf(fabsf(g[3]), fabsf(g[4])), fabsf(g[5]));
+    const float qn2 = fmaf(g[9], g[9], fmaf(g[8], g[8], fmaf(g[7], g[7], g[6] * g[6])));
+    const bool ok = __builtin_isfinite(fsum) && sm < 80.0f && qn2 >= 0.25f;
+    return make_float4(g[0], g[1], g[2], ok ? sm : __builtin_nanf(""));
+}
+
+// classify_pre from a summary.  The bounds are those of classify_pre: the
+// centre is the row's, s already holds the slack that classify_pre adds after
+// the drift (the sum differs by at most an ulp, far inside the 0.1% margin
+// on sigma), a NaN s makes the row undecidable, and since the quaternion's
+// squared norm is at least 1/4 the sure-in condition on it holds whenever
+// 1.001 qmin^2 < 1/4.
+__device__ __forceinline__ RowPre classify_pre_sum(const float4 &v, float wd, const BandK &b)
+{
+    RowPre p;
+    const float dpos = b.kpos * wd, dscl = b.kscl * wd, dq = b.kq * wd;
+    const float mu = fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fabsf(v.z));
+    p.dp = dpos + 1e-6f * mu;
+    p.mu = mu;
+    const float smax = v.w + dscl;
+    const float sig = __expf(fminf(smax, 80.0f)) * 1.001f;
+    p.sig2 = sig * sig;
+    const float qmin = 2.002f * dq + 1e-6f;
+    p.ok = smax < 80.0f ? (1.001f * (qmin * qmin) < 0.25f ? 3 : 1) : 0;
+    return p;
+}
+
+// Store the summary of a row whose new geometric values sit in lanes 0..9 of
+// the wavefront (value x of this lane); every lane of the wavefront takes
+// part, lane 0 stores.
+__device__ __forceinline__ void cull_summary_store_wave(float4 *sum, u32 row, float x)
+{
+    float g[10];
+#pragma unroll
+    for (int j = 0; j < 10; ++j) g[j] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), j));
+    const float4 v = cull_summary(g);
+    if ((threadIdx.x & 63) == 0) sum[row] = v;
+}
+
 // Bounds of a group of rows (a wavefront's) that classify_cam evaluates:
 // the box of their stored centres and the largest mu, position drift and
 // sigma_max^2 of their RowPre.  wave_sure_out(box, camera) is true only when
@@ -654,6 +704,7 @@ struct CullArgs {
     u64 *tile_vs;                    // [tiles] visible << 32 | saturated
     u32 *tile_rest;                  // [tiles] restored rows
     int64_t tiles;
+    const float4 *sum;               // [n] cull summaries (k_cull_sum)
 };
 
 // Seven blocks per CU (the LDS tiles allow seven): the register budget this
@@ -821,6 +872,165 @@ __global__ __launch_bounds__(kCullBlock, 7) void k_cull(CullArgs a)
         a.tile_rest[tile] = sRestored;
     }
     step_flag(a.step, step_err);
+}
+
+// The band cull from the cull summaries (Adam, geometry deferred).  A block
+// takes TPB consecutive 512-row tiles, kCullIpt * TPB rows a thread: every
+// row's summary and last step are loaded first (coalesced, no LDS staging),
+// then every row's step-table entry (entry 0 is 0, so the load needs no
+// branch), then the rows are classified.  The undecided rows (near a decision
+// boundary, or flagged by their summary) are rare: one loop, not unrolled,
+// loads each one's geometry row, restores it when deferred and takes the
+// exact test.  Same outputs as k_cull, tile by tile.
+constexpr int kCullSumTiles = 2;      // tiles of a k_cull_sum block (of 1, 2, 4, 8 the fastest at 40M rows)
+template <bool NT, int TPB>
+__global__ __launch_bounds__(kCullBlock) void k_cull_sum(CullArgs a)
+{
+    constexpr int RPT = kCullIpt * TPB;
+    static_assert(RPT <= 32, "row bits of a thread fit a word");
+    __shared__ u32 sCntV[TPB][kCullIpt * 4], sCntS[TPB][kCullIpt * 4];
+    __shared__ u32 sRestored[TPB];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t tile0 = (int64_t)blockIdx.x * TPB;
+    const float *Wrow;
+    int dmax, step_err;
+    const int t = resolve_step(a.step, 0, &Wrow, &dmax, &step_err);
+    const int K = a.K;
+    if (tid < TPB) sRestored[tid] = 0;
+    // row of slot q = j * kCullIpt + i: tile tile0 + j, rows i * kCullBlock + tid
+    auto row_of = [&](int q) -> int64_t {
+        return (tile0 + q / kCullIpt) * kCullTile + (int64_t)(q % kCullIpt) * kCullBlock + tid;
+    };
+    int lastv[RPT];
+    float4 sv[RPT];
+    u32 valid = 0;
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const int64_t row = row_of(q);
+        valid |= (u32)(row < a.n) << q;
+        const int64_t rc = row < a.n ? row : a.n - 1;
+        lastv[q] = ld_sweep<NT>(a.last + rc);
+        sv[q] = ld_sweep<NT>(a.sum + rc);
+    }
+    int dv[RPT];
+    float wdv[RPT];
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        int d = t - 1 - lastv[q];
+        d = d < 0 ? 0 : (d > dmax ? dmax : d);
+        dv[q] = d;
+        wdv[q] = Wrow[d];
+    }
+    // classification: keep bits and undecided bits of this thread's rows
+    u32 keepm = 0, und = 0;
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const float c3[3] = {sv[q].x, sv[q].y, sv[q].z};
+        const int cls = classify_cam(c3, classify_pre_sum(sv[q], wdv[q], a.band), a.cam, a.band);
+        keepm |= (u32)(cls == 1) << q;
+        und |= (u32)(cls == 2) << q;
+    }
+    und &= valid;
+    keepm &= valid;
+    u32 nrest[TPB];
+#pragma unroll
+    for (int j = 0; j < TPB; ++j) nrest[j] = 0;
+    // the exact test of the undecided rows
+    u32 left = und;
+#pragma unroll 1
+    while (left) {
+        const int q = __builtin_ctz(left);
+        left &= left - 1u;
+        const int64_t row = row_of(q);
+        float g[10];
+        const float2 *p2 = reinterpret_cast<const float2 *>(a.gw + row * 10);
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+            const float2 v = p2[j];
+            g[2 * j] = v.x;
+            g[2 * j + 1] = v.y;
+        }
+        int d = t - 1 - a.last[row];
+        d = d < 0 ? 0 : (d > dmax ? dmax : d);
+        if (d > 0) {
+            const float wd = Wrow[d];
+            float mv[10], vv[10];
+            if (a.gst == GS_F32) {
+#pragma unroll
+                for (int j = 0; j < 10; ++j) {
+                    mv[j] = mom_load<GS_F32>(a.gm, row, j, false);
+                    vv[j] = mom_load<GS_F32>(a.gv, row, j, true);
+                }
+            } else if (a.gst == GS_BF16) {
+#pragma unroll
+                for (int j = 0; j < 10; ++j) {
+                    mv[j] = mom_load<GS_BF16>(a.gm, row, j, false);
+                    vv[j] = mom_load<GS_BF16>(a.gv, row, j, true);
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < 10; ++j) {
+                    mv[j] = mom_load<GS_FP8E4M3>(a.gm, row, j, false);
+                    vv[j] = mom_load<GS_FP8E4M3>(a.gv, row, j, true);
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < 10; ++j) g[j] = restore1(g[j], mv[j], vv[j], wd, a.lr[j], a.eps, a.rb);
+#pragma unroll
+            for (int j = 0; j < TPB; ++j) nrest[j] += (u32)(q / kCullIpt == j);
+        }
+        keepm |= (u32)cull_v1(g, a.cam) << q;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const int j = q / kCullIpt, i = q % kCullIpt;
+        const bool keep = (keepm >> q) & 1u;
+        const bool sat = (K > 0) && ((valid >> q) & 1u) && !keep && dv[q] == K;
+        const u64 bv = __ballot(keep);
+        const u64 bs = __ballot(sat);
+        const int64_t tile = tile0 + j;
+        if (lane == 0) {
+            const int slab = i * 4 + wave;
+            sCntV[j][slab] = (u32)__popcll(bv);
+            sCntS[j][slab] = (u32)__popcll(bs);
+            if (tile < a.tiles) {
+                a.keep_bits[tile * gsdp::kWordsPerTile + slab] = bv;
+                if (K > 0) a.sat_bits[tile * gsdp::kWordsPerTile + slab] = bs;
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < TPB; ++j)
+        if (nrest[j]) atomicAdd(&sRestored[j], nrest[j]);
+    __syncthreads();
+    if (tid < TPB && tile0 + tid < a.tiles) {
+        u32 v = 0, ss = 0;
+        for (int e = 0; e < kCullIpt * 4; ++e) {
+            v += sCntV[tid][e];
+            ss += sCntS[tid][e];
+        }
+        a.tile_vs[tile0 + tid] = ((u64)v << 32) | (u64)ss;
+        a.tile_rest[tile0 + tid] = sRestored[tid];
+    }
+    step_flag(a.step, step_err);
+}
+
+// Summaries of rows [0, n) from the stored geometry (grid-stride, one row a
+// thread).
+__global__ __launch_bounds__(256) void k_cull_summary_build(const float *gw, float4 *sum, int64_t n)
+{
+    for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < n; r += (int64_t)gridDim.x * 256) {
+        float g[10];
+        const float2 *p2 = reinterpret_cast<const float2 *>(gw + r * 10);
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+            const float2 q = p2[j];
+            g[2 * j] = q.x;
+            g[2 * j + 1] = q.y;
+        }
+        sum[r] = cull_summary(g);
+    }
 }
 
 // Block scans used by the one-block counter scans of the batched cull and of
@@ -1139,6 +1349,7 @@ struct RowArgs {
     // them all from one row base
     u32 fz_s, fz_ogm, fz_ogv, fz_oam, fz_oav, pad8;
     LutAdv adv;                      // kAdam: the tables' advance to the next step
+    float4 *cull_sum;                // [n] cull summaries kept current (or null)
 };
 
 // One wavefront per Gaussian row: lane c < 10 owns G column c, lane 10+c owns
@@ -1457,6 +1668,7 @@ __device__ __forceinline__ void rows_work(const RowArgs &a, const int t, const f
                 continue;
             }
             if (MODE == kFlush && dd == 0) continue;
+            float xs = 0.0f;                 // this lane's new value (for the summary)
             if (act) {
                 float x, m1, v1;
                 if (MODE == kAdam && sgd) {
@@ -1507,6 +1719,7 @@ __device__ __forceinline__ void rows_work(const RowArgs &a, const int t, const f
                     mstore<GST>(at(rA[u], fzm), ms[u], m1, rm, false);
                     if (!sgd) mstore<GST>(at(rA[u], fzv), vs[u], v1, rv, true);
                 }
+                xs = x;
                 if (isG) {
                     *reinterpret_cast<float *>(at(rG[u], off4)) = x;
                     if (!FZ) {
@@ -1525,6 +1738,7 @@ __device__ __forceinline__ void rows_work(const RowArgs &a, const int t, const f
                     asm volatile("; A columns");
                 }
             }
+            if (a.cull_sum) cull_summary_store_wave(a.cull_sum, r, xs);
             if (lane == 0) a.last[r] = t;
         }
 #pragma unroll
@@ -1588,6 +1802,7 @@ struct FastArgs {
     u32 n, cap, adim, fz_s;          // rows, id capacity, A columns, fused row bytes
     u32 om, ov, pad0, pad1;          // byte offsets of the G m and G v runs in the fused row
     LutAdv adv;                      // kAdam: the tables' advance to the next step
+    float4 *cull_sum;                // [n] cull summaries kept current (or null)
 };
 
 // Pointers into the global and the constant address space: global loads and
@@ -1729,6 +1944,7 @@ __device__ __forceinline__ void rows_fz_work(const FastArgs &a, const int t, con
                     mstore<ST>((char *)(fb[u] + lane_off(mo)), 0.0f, m1, rm, false);
                     mstore<ST>((char *)(fb[u] + lane_off(vo)), 0.0f, v1, rv, true);
                 }
+                if (a.cull_sum) cull_summary_store_wave(a.cull_sum, id[u], x);
                 if (lane == 0) a.last[id[u]] = t;
             }
         }
@@ -2053,6 +2269,9 @@ int check_model(const gs_model *m)
         float rates[gsdp::kMaxDecayClasses];
         if (decay_classes(m, rates, nullptr) < 0) return GS_EUNSUPPORTED;
     }
+    // summaries stay current only where the row kernels store the geometry
+    if (m->cull_sum && !aligned(m->cull_sum, 16)) return GS_EINVAL;
+    if (m->cull_sum && m->geo_mode != 0) return GS_EUNSUPPORTED;
     return GS_OK;
 }
 
@@ -2208,6 +2427,7 @@ void fill_rows(RowArgs &a, const gs_model *m)
     }
     a.last = m->last_step;
     a.n = m->n;
+    a.cull_sum = reinterpret_cast<float4 *>(m->cull_sum);
 }
 
 // The configuration of k_rows_fz: Adam, both groups' moments in FP32 or both
@@ -2240,6 +2460,7 @@ bool fill_fast(FastArgs &f, const gs_model *m)
     f.fz_s = S;
     f.om = ogm;
     f.ov = ogv;
+    f.cull_sum = reinterpret_cast<float4 *>(m->cull_sum);
     return true;
 }
 
@@ -3436,6 +3657,19 @@ int gs_cull_noalloc(const gs_model *model, const gs_camera *cam, int64_t step, u
     return cull_launch(model, cam, step, ids, count_dev, capacity, wsb, (hipStream_t)stream);
 }
 
+int gs_cull_summary_build(const gs_model *model, void *stream)
+{
+    int rc = check_model(model);
+    if (rc) return rc;
+    if (!model->cull_sum) return GS_EINVAL;
+    if (model->n == 0) return GS_OK;
+    const int cu = cu_count();
+    const int64_t blocks = std::min<int64_t>((model->n + 255) / 256, (int64_t)(cu > 0 ? cu : 256) * 16);
+    hipLaunchKernelGGL(k_cull_summary_build, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, model->geo.w,
+                       reinterpret_cast<float4 *>(model->cull_sum), model->n);
+    return launched("gs_cull_summary_build");
+}
+
 }  // extern "C"
 
 namespace {
@@ -3483,11 +3717,20 @@ int cull_launch(const gs_model *model, const gs_camera *cam, int64_t step, uint3
     a.sat_bits = model->max_defer > 0 ? reinterpret_cast<u64 *>(wsb + gsdp::ws_satbits_offset(n)) : nullptr;
     if (a.tiles > 0x7fffffff) return GS_EINVAL;
     if (a.tiles > 0) {
-        // geometry and last step: 44 bytes a row
-        if ((int64_t)n * 44 > kLastLevelCacheBytes)
+        a.sum = reinterpret_cast<const float4 *>(model->cull_sum);
+        if (a.mode == 1 && a.sum && !a.geo_dense) {
+            // summary and last step: 20 bytes a row
+            const unsigned blocks = (unsigned)((a.tiles + kCullSumTiles - 1) / kCullSumTiles);
+            if ((int64_t)n * 20 > kLastLevelCacheBytes)
+                hipLaunchKernelGGL((k_cull_sum<true, kCullSumTiles>), dim3(blocks), dim3(kCullBlock), 0, st, a);
+            else
+                hipLaunchKernelGGL((k_cull_sum<false, kCullSumTiles>), dim3(blocks), dim3(kCullBlock), 0, st, a);
+        } else if ((int64_t)n * 44 > kLastLevelCacheBytes) {
+            // geometry and last step: 44 bytes a row
             hipLaunchKernelGGL(k_cull<true>, dim3((unsigned)a.tiles), dim3(kCullBlock), 0, st, a);
-        else
+        } else {
             hipLaunchKernelGGL(k_cull<false>, dim3((unsigned)a.tiles), dim3(kCullBlock), 0, st, a);
+        }
         int rc1 = launched("gs_cull (tiles)");
         if (rc1) return rc1;
     }
@@ -3841,7 +4084,9 @@ int gs_densify_apply(const gs_model *src, const gs_densify_params *params, const
     else if (!gb && ab) hipLaunchKernelGGL((k_dens_apply<GS_F32, GS_BF16>), dim3((unsigned)a.tiles), dim3(kCullBlock), 0, st, a);
     else if (gb && !ab) hipLaunchKernelGGL((k_dens_apply<GS_BF16, GS_F32>), dim3((unsigned)a.tiles), dim3(kCullBlock), 0, st, a);
     else hipLaunchKernelGGL((k_dens_apply<GS_BF16, GS_BF16>), dim3((unsigned)a.tiles), dim3(kCullBlock), 0, st, a);
-    return launched("gs_densify_apply");
+    rc = launched("gs_densify_apply");
+    if (rc || !dst->cull_sum) return rc;
+    return gs_cull_summary_build(dst, stream);
 }
 
 int gs_synth_grad(uint64_t seed, int64_t step, const uint32_t *ids, const uint32_t *count_dev, uint32_t capacity,

@@ -30,7 +30,7 @@ SYMBOLS = ("gs_lut_bytes", "gs_lut_build", "gs_lut_build_host", "gs_lut_build_sc
            "gs_cull_multi_autotune", "gs_grad_sum_multi", "gs_plan_image_split", "gs_lut_build_sgd_momentum",
            "gs_lut_build_sgd_momentum_host", "gs_lut_bytes_adamw", "gs_lut_build_adamw", "gs_lut_build_adamw_host",
            "gs_densify_workspace_bytes", "gs_densify_plan", "gs_densify_apply", "gs_cull_noalloc",
-           "gs_lut_seek", "gs_lut_seek_host")
+           "gs_lut_seek", "gs_lut_seek_host", "gs_cull_summary_build")
 
 
 class GsCamera(C.Structure):
@@ -51,7 +51,8 @@ class GsModel(C.Structure):
                 ("lut", C.c_void_p), ("lut_max_steps", C.c_int32), ("max_defer", C.c_int32),
                 ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double),
                 ("cull_mode", C.c_int32), ("geo_mode", C.c_int32), ("sr_seed", C.c_uint64),
-                ("step_dev", C.c_void_p), ("optimizer", C.c_int32), ("reserved_", C.c_int32)]
+                ("step_dev", C.c_void_p), ("optimizer", C.c_int32), ("reserved_", C.c_int32),
+                ("cull_sum", C.c_void_p)]
 
 
 class GsMulti(C.Structure):
@@ -88,6 +89,7 @@ def _load():
         "gs_densify_apply": (C.c_int, [P(GsModel), vp, P(GsModel), i64, vp, sz, vp]),
         "gs_cull": (C.c_int, [P(GsModel), P(GsCamera), i64, vp, vp, u32, vp, sz, vp]),
         "gs_cull_noalloc": (C.c_int, [P(GsModel), P(GsCamera), i64, vp, vp, u32, vp]),
+        "gs_cull_summary_build": (C.c_int, [P(GsModel), vp]),
         "gs_gather": (C.c_int, [P(GsModel), i64, vp, vp, u32, vp, vp, vp]),
         "gs_scatter_grad": (C.c_int, [vp, vp, u32, i32, vp, vp, i32, vp]),
         "gs_adam_step_deferred": (C.c_int, [P(GsModel), i64, vp, vp, u32, vp, vp, vp, vp, vp, sz, vp]),
@@ -238,13 +240,14 @@ class Model:
 
     def __init__(self, geo, app, lr_geo, lr_app, *, beta1=0.9, beta2=0.999, eps=1e-15, max_defer=0,
                  max_steps=1000, cull_mode=0, app_layout="separate", geo_state="f32", app_state="f32",
-                 sr_seed=0, geo_mode=0, lr_scale=None, optimizer="adam", weight_decay=0.0, device=None):
+                 sr_seed=0, geo_mode=0, lr_scale=None, optimizer="adam", weight_decay=0.0, device=None,
+                 cull_summary=None):
         device = device or torch.device("cuda")
         # constructor settings, reused by densify() for the resized model
         self._kw = dict(beta1=beta1, beta2=beta2, eps=eps, max_defer=max_defer, max_steps=max_steps,
                         cull_mode=cull_mode, app_layout=app_layout, geo_state=geo_state, app_state=app_state,
                         sr_seed=sr_seed, geo_mode=geo_mode, lr_scale=lr_scale, optimizer=optimizer,
-                        weight_decay=weight_decay, device=device)
+                        weight_decay=weight_decay, device=device, cull_summary=cull_summary)
         geo = torch.as_tensor(geo, dtype=torch.float32)
         app = torch.as_tensor(app, dtype=torch.float32)
         n, adim = geo.shape[0], app.shape[1]
@@ -357,8 +360,23 @@ class Model:
         # device step counter for graph replay (calls with step == 0 read it)
         self.step_dev = torch.zeros(1, dtype=torch.int32, device=device)
         c.step_dev = self.step_dev.data_ptr()
+        # cull summaries (16 bytes a row, read by the band cull instead of the
+        # 40-byte geometry rows): by default wherever the band cull runs
+        if cull_summary is None:
+            cull_summary = cull_mode == 1 and geo_mode == 0 and optimizer == "adam"
+        self.cull_sum = None
+        if cull_summary:
+            self.cull_sum = torch.empty((max(n, 1), 4), dtype=torch.float32, device=device)
+            c.cull_sum = self.cull_sum.data_ptr()
         self.c = c
         self.ws = torch.zeros(gs_workspace_bytes(self) // 4, dtype=torch.int32, device=device)
+        if self.cull_sum is not None:
+            self.cull_summary_build()
+
+    def cull_summary_build(self, stream=None):
+        """Recompute every row's cull summary from geo_w: needed after geo_w
+        is written other than by this library's calls (which keep them current)."""
+        _check(lib.gs_cull_summary_build(C.byref(self.c), _stream(stream)), "gs_cull_summary_build")
 
     @property
     def ws_bytes(self) -> int:

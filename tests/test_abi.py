@@ -320,3 +320,21 @@ def test_cull_noalloc_checks_need_no_device(gsdp):
     assert L.gs_workspace_bytes(C.byref(big), C.byref(b)) == 0 and b.value > (16 << 20)
     assert L.gs_cull_noalloc(C.byref(big), C.byref(cam), 1, ids, ids, 16, None) == gsdp.GS_ESPACE
     assert b"workspace" in L.gs_last_hip_error()
+
+
+def test_cull_summary_checks_need_no_device(gsdp):
+    """gs_cull_summary_build without summaries, misaligned summaries, and
+    summaries with dense geometry are refused before anything is launched."""
+    L = gsdp.lib
+    m = _fake_model(gsdp, 1000)
+    assert L.gs_cull_summary_build(C.byref(m), None) == gsdp.GS_EINVAL
+    m.cull_sum = (1 << 20) + 4
+    assert L.gs_cull_summary_build(C.byref(m), None) == gsdp.GS_EINVAL
+    m.cull_sum = 1 << 20
+    m.geo_mode = 1
+    assert L.gs_cull_summary_build(C.byref(m), None) == gsdp.GS_EUNSUPPORTED
+    cam = gsdp.GsCamera()
+    cam.fx = cam.fy = 1000.0
+    cam.width, cam.height = 64, 64
+    ids = C.c_void_p(1 << 20)
+    assert L.gs_cull_noalloc(C.byref(m), C.byref(cam), 1, ids, ids, 16, None) == gsdp.GS_EUNSUPPORTED

@@ -61,11 +61,17 @@ def model_for(g, geo, app=None, **kw):
 
 
 # ---------------------------------------------------------------- cull
+# cull_mode, cull summaries: the exact cull, the band cull from the geometry
+# rows and the band cull from the summaries
+CULLS = [(0, False), (1, False), (1, True)]
+
+
+@pytest.mark.parametrize("mode,summ", CULLS)
 @pytest.mark.parametrize("n", [0, 1, 5, 1023, 1024, 1025, 3007, 100_000])
-def test_cull_step1_matches_oracle(g, n):
-    say(f"[cull] n={n}")
+def test_cull_step1_matches_oracle(g, n, mode, summ):
+    say(f"[cull] n={n} mode={mode} summaries={summ}")
     sc = gi.make_scene(n, seed=n % 7)
-    model = model_for(g, sc.geo, sc.app)
+    model = model_for(g, sc.geo, sc.app, cull_mode=mode, cull_summary=summ)
     for cam in gi.orbit_cameras(4, seed=n % 5):
         ids, count, m = run_cull(g, model, cam, 1)
         ref = orc.compact(orc.cull(sc.geo, cam))
@@ -138,11 +144,12 @@ def _boundary_scene(cam, n, rng):
     return geo
 
 
-def test_cull_boundary_and_degenerate_rows(g):
+@pytest.mark.parametrize("mode,summ", CULLS)
+def test_cull_boundary_and_degenerate_rows(g, mode, summ):
     rng = np.random.default_rng(42)
     for seed, cam in enumerate(gi.orbit_cameras(3, seed=3)):
         geo = _boundary_scene(cam, 50_000, rng)
-        model = model_for(g, geo)
+        model = model_for(g, geo, cull_mode=mode, cull_summary=summ)
         ids, count, m = run_cull(g, model, cam, 1)
         keep = orc.cull(geo, cam)
         ref = orc.compact(keep)
@@ -404,6 +411,9 @@ def test_band_cull_adversarial_deferred_rows(g, seed):
     good = rng.random(n) < 0.97                       # keep a few NaN/Inf rows
     bad_rows = ~np.all(np.isfinite(geo), axis=1)
     geo[bad_rows & good] = np.nan_to_num(geo[bad_rows & good], nan=1.0, posinf=5.0, neginf=-5.0)
+    # quaternions of squared norm just below and above 1/4 (the summary's limit)
+    qs = rng.choice(n, n // 100, replace=False)
+    geo[qs, 6:10] *= rng.choice([0.3, 0.4999, 0.5, 0.5001, 0.7], qs.shape[0])[:, None].astype(np.float32)
     v = (10.0 ** rng.uniform(-12, -4, (n, 10))).astype(np.float32)
     ratio = rng.choice([7.26, 7.0, 3.0, 0.5], (n, 10)) * rng.choice([-1.0, 1.0], (n, 10))
     m = (ratio * np.sqrt(v.astype(np.float64))).astype(np.float32)
@@ -417,19 +427,23 @@ def test_band_cull_adversarial_deferred_rows(g, seed):
     o3.counter[:] = d
     valid = o3.cull_current(t, cam)
     got = {}
-    for mode in (0, 1):
-        model = g.Model(geo, np.zeros((n, 49), np.float32), lr_geo, la, max_steps=64, cull_mode=mode)
+    # exact cull, band cull from the geometry rows, band cull from the summaries
+    for mode, summ in ((0, False), (1, False), (1, True)):
+        model = g.Model(geo, np.zeros((n, 49), np.float32), lr_geo, la, max_steps=64, cull_mode=mode,
+                        cull_summary=summ)
         model.geo_m.copy_(torch.from_numpy(m))
         model.geo_v.copy_(torch.from_numpy(v))
         model.last_step.copy_(torch.from_numpy((t - 1 - d).astype(np.int32)))
         model.lut_seek(t)
         ids, count, mm = run_cull(g, model, cam, t)
-        got[mode] = (u32(ids[:mm]), model.ws_header()["restored_last"])
-        assert mm == valid.shape[0], (mode, mm, valid.shape[0])
-        assert np.array_equal(got[mode][0], valid), mode
+        key = (mode, summ)
+        got[key] = (u32(ids[:mm]), model.ws_header()["restored_last"])
+        assert mm == valid.shape[0], (key, mm, valid.shape[0])
+        assert np.array_equal(got[key][0], valid), key
         assert model.ws_header()["error"] == 0
-    say(f"[band adversarial {seed}] M={valid.shape[0]} restored exact={got[0][1]} band={got[1][1]}")
-    assert got[1][1] < got[0][1]
+    say(f"[band adversarial {seed}] M={valid.shape[0]} restored exact={got[(0, False)][1]} "
+        f"band={got[(1, False)][1]} band from summaries={got[(1, True)][1]}")
+    assert got[(1, False)][1] < got[(0, False)][1] and got[(1, True)][1] < got[(0, False)][1]
 
 
 def test_stream_read_probe(g):
