@@ -398,6 +398,13 @@ struct BandK {
     float kpos, kscl, kq;  // B * max lr over position / log-scale / quaternion columns
 };
 
+// Per-camera constants of side_out (host-computed, rounded up).
+struct SideK {
+    float ksig;            // 3.003 sqrt(1.001 jf2)
+    float cl, cr, ct, cb;  // cx + 3.93, W - cx + 3.93, cy + 3.93, H - cy + 3.93
+    float fmax, cmax;      // max(fx, fy); the largest of |cl|, |cr|, |ct|, |cb|, |cx|, |cy|
+};
+
 // Conservative classification of one Gaussian whose stored geometry g may be
 // stale by a restore of at most B*W[d]*lr per column.  B is the clamp of the
 // restore factor (1.03x the Cauchy-Schwarz bound (1-b1)/sqrt((1-b2)(1-b1^2/b2))
@@ -412,7 +419,8 @@ struct BandK {
 // classify_pre holds the camera-independent part of one row.
 struct RowPre {
     float dp;       // position drift bound incl. rounding of the restore
-    float sig2;     // bound of sigma_max^2 after the restore
+    float sig;      // bound of sigma_max after the restore
+    float sig2;     // its square
     float mu;       // largest |position coordinate|
     int ok;         // 0: undecidable (non-finite, huge scale); bit 1: quaternion stays away from 0
 };
@@ -431,6 +439,7 @@ __device__ __forceinline__ RowPre classify_pre(const float *g, float wd, const B
     p.mu = mu;
     const float smax = fmaxf(fmaxf(g[3], g[4]), g[5]) + dscl + 1e-6f * fmaxf(fmaxf(fabsf(g[3]), fabsf(g[4])), fabsf(g[5]));
     const float sig = __expf(fminf(smax, 80.0f)) * 1.001f;
+    p.sig = sig;
     p.sig2 = sig * sig;
     // |q| > 2.002 dq + 1e-6, compared squared (the 0.1% margin covers the rounding)
     const float qn2 = fmaf(g[9], g[9], fmaf(g[8], g[8], fmaf(g[7], g[7], g[6] * g[6])));
@@ -443,24 +452,68 @@ __device__ __forceinline__ RowPre classify_pre(const float *g, float wd, const B
 // path.  Evaluated without branches: every bound is computed and the tests are
 // combined in their order of precedence (a row of a wavefront rarely leaves
 // early together with all 63 others, so branching would only add mask work).
-__device__ __forceinline__ int classify_cam(const float *g, const RowPre &p, const CamK &c, const BandK &b)
+// Camera-space centre of the stored row and the half-widths of the interval
+// in which the exact test's camera-space coordinates of every admissible
+// restored geometry lie (drift and the exact path's rounding).
+struct CamBox {
+    float x, y, z, ex, ey, ez;
+};
+
+__device__ __forceinline__ CamBox cam_box(const float *g, const RowPre &p, const CamK &c, const BandK &b)
 {
+    CamBox q;
     const float dp = p.dp;
     // The bounds below are evaluated with fused multiply-adds: any evaluation
     // order of these short sums differs from the exact path's by a few ulp of
     // the terms' magnitude, far inside the 1e-6 relative slack.
-    const float x = fmaf(c.R[2], g[2], fmaf(c.R[1], g[1], fmaf(c.R[0], g[0], c.T[0])));
-    const float y = fmaf(c.R[5], g[2], fmaf(c.R[4], g[1], fmaf(c.R[3], g[0], c.T[1])));
-    const float z = fmaf(c.R[8], g[2], fmaf(c.R[7], g[1], fmaf(c.R[6], g[0], c.T[2])));
+    q.x = fmaf(c.R[2], g[2], fmaf(c.R[1], g[1], fmaf(c.R[0], g[0], c.T[0])));
+    q.y = fmaf(c.R[5], g[2], fmaf(c.R[4], g[1], fmaf(c.R[3], g[0], c.T[1])));
+    q.z = fmaf(c.R[8], g[2], fmaf(c.R[7], g[1], fmaf(c.R[6], g[0], c.T[2])));
     // magnitude of the terms of each transform row, bounded by |R_i|_1 max|mu| + |T_i|
     // (rounds up by far less than the 1e-6 relative slack it feeds)
     const float sx = fmaf(b.rs0, p.mu, fabsf(c.T[0]));
     const float sy = fmaf(b.rs1, p.mu, fabsf(c.T[1]));
     const float sz = fmaf(b.rs2, p.mu, fabsf(c.T[2]));
     const float dx = b.rs0 * dp, dy = b.rs1 * dp, dz = b.rs2 * dp;
-    const float ex = fmaf(1e-6f, sx + dx, dx) + 1e-6f;
-    const float ey = fmaf(1e-6f, sy + dy, dy) + 1e-6f;
-    const float ez = fmaf(1e-6f, sz + dz, dz) + 1e-6f;
+    q.ex = fmaf(1e-6f, sx + dx, dx) + 1e-6f;
+    q.ey = fmaf(1e-6f, sy + dy, dy) + 1e-6f;
+    q.ez = fmaf(1e-6f, sz + dz, dz) + 1e-6f;
+    return q;
+}
+
+// Sure-out test of the summary cull, without divisions or square roots: true
+// only when every admissible restored geometry is culled by cull_v1 (for a
+// row whose RowPre is decidable, ok != 0).  The exact test keeps a row only
+// if z' > zn > 0 and u + r > 0 (and the other three sides), with u its
+// rounded projected centre fx x'/z' + cx (within 2.5e-7 relative of the
+// exact value) and r its radius, r <= 3.003 sqrt(1.001 |J|_F^2 sigma'^2 +
+// 0.95) + 1 (the bound classify_cam uses) with |J|_F^2 <= jf2 / z'^2.  As
+// z' > 0, multiplying by z' and using sqrt(a + b) <= sqrt(a) + sqrt(b):
+//   fx x' + (cx + 3.93) z' + ksig sigma' + 2.5e-7 (fx |x'| + |cx| z') > 0.
+// Over the box |x' - x| <= ex, |z' - z| <= ez and sigma' <= sig, the left
+// side is at most fx x + cl z + fx ex + |cl| ez + ksig sig plus that term;
+// slack (1e-5 of the terms' magnitudes) covers it and this evaluation's own
+// rounding.  A value <= 0 therefore means no kept geometry: the row is out
+// on that side.  The same for the right (-fx x', cr), top (fy y', ct) and
+// bottom (-fy y', cb) sides; out_z is classify_cam's own test.  NaN bounds
+// make every comparison false (not out).
+__device__ __forceinline__ bool side_out(const CamBox &q, float sig, const CamK &c, const SideK &b)
+{
+    const bool out_z = (q.z + q.ez <= c.zn) | (q.z - q.ez >= c.zf);
+    const float ks = b.ksig * sig;
+    const float mag = fmaf(b.fmax, (fabsf(q.x) + fabsf(q.y)) + (q.ex + q.ey), fmaf(b.cmax, fabsf(q.z) + q.ez, ks));
+    const float base = fmaf(1e-5f, mag, ks);
+    const float fex = c.fx * q.ex, fey = c.fy * q.ey;
+    const float l = fmaf(c.fx, q.x, fmaf(b.cl, q.z, fmaf(fabsf(b.cl), q.ez, fex + base)));
+    const float r = fmaf(-c.fx, q.x, fmaf(b.cr, q.z, fmaf(fabsf(b.cr), q.ez, fex + base)));
+    const float t = fmaf(c.fy, q.y, fmaf(b.ct, q.z, fmaf(fabsf(b.ct), q.ez, fey + base)));
+    const float d = fmaf(-c.fy, q.y, fmaf(b.cb, q.z, fmaf(fabsf(b.cb), q.ez, fey + base)));
+    return out_z | (l <= 0.0f) | (r <= 0.0f) | (t <= 0.0f) | (d <= 0.0f);
+}
+
+__device__ __forceinline__ int classify_box(const CamBox &q, const RowPre &p, const CamK &c, const BandK &b)
+{
+    const float x = q.x, y = q.y, z = q.z, ex = q.ex, ey = q.ey, ez = q.ez;
     const float zlo = z - ez, zhi = z + ez;
     // bitwise, not short-circuit, combinations: no branches
     const bool out_z = (zhi <= c.zn) | (zlo >= c.zf);
@@ -484,6 +537,11 @@ __device__ __forceinline__ int classify_cam(const float *g, const RowPre &p, con
                     (vlo > -1.5f) & (vhi < c.H + 1.5f) & (lam <= 1000.0f);
     const int cls = out_z ? 0 : (!z_pos ? 2 : (out_uv ? 0 : (in ? 1 : 2)));
     return p.ok ? cls : 2;
+}
+
+__device__ __forceinline__ int classify_cam(const float *g, const RowPre &p, const CamK &c, const BandK &b)
+{
+    return classify_box(cam_box(g, p, c, b), p, c, b);
 }
 
 __device__ __forceinline__ int classify(const float *g, float wd, const CamK &c, const BandK &b)
@@ -523,6 +581,7 @@ __device__ __forceinline__ RowPre classify_pre_sum(const float4 &v, float wd, co
     p.mu = mu;
     const float smax = v.w + dscl;
     const float sig = __expf(fminf(smax, 80.0f)) * 1.001f;
+    p.sig = sig;
     p.sig2 = sig * sig;
     const float qmin = 2.002f * dq + 1e-6f;
     p.ok = smax < 80.0f ? (1.001f * (qmin * qmin) < 0.25f ? 3 : 1) : 0;
@@ -705,6 +764,7 @@ struct CullArgs {
     u32 *tile_rest;                  // [tiles] restored rows
     int64_t tiles;
     const float4 *sum;               // [n] cull summaries (k_cull_sum)
+    SideK side;                      // side_out constants (k_cull_sum)
 };
 
 // Seven blocks per CU (the LDS tiles allow seven): the register budget this
@@ -921,14 +981,21 @@ __global__ __launch_bounds__(kCullBlock) void k_cull_sum(CullArgs a)
         dv[q] = d;
         wdv[q] = Wrow[d];
     }
-    // classification: keep bits and undecided bits of this thread's rows
+    // classification: keep bits and undecided bits of this thread's rows.
+    // side_out settles most rows; the full classification runs for a slot
+    // only where some lane's row is left (a uniform branch).
     u32 keepm = 0, und = 0;
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
         const float c3[3] = {sv[q].x, sv[q].y, sv[q].z};
-        const int cls = classify_cam(c3, classify_pre_sum(sv[q], wdv[q], a.band), a.cam, a.band);
-        keepm |= (u32)(cls == 1) << q;
-        und |= (u32)(cls == 2) << q;
+        const RowPre pre = classify_pre_sum(sv[q], wdv[q], a.band);
+        const CamBox box = cam_box(c3, pre, a.cam, a.band);
+        const bool left = !(pre.ok != 0 && side_out(box, pre.sig, a.cam, a.side)) && ((valid >> q) & 1u);
+        if (__ballot(left) != 0ull) {
+            const int cls = left ? classify_box(box, pre, a.cam, a.band) : 0;
+            keepm |= (u32)(cls == 1) << q;
+            und |= (u32)(cls == 2) << q;
+        }
     }
     und &= valid;
     keepm &= valid;
@@ -2506,6 +2573,24 @@ void pack_camera(const gs_model *model, const gs_camera *cam, CamK &k, BandK &b)
     b.jf2 = (float)((fx * fx * (1.0 + (double)limx * limx) + fy * fy * (1.0 + (double)limy * limy)) * (1.0 + 1e-4));
 }
 
+// Constants of side_out, rounded up (a larger margin only keeps more rows).
+void pack_side(const gs_camera *cam, const BandK &b, SideK &k)
+{
+    const double up = 1.0 + 1e-6;
+    k.ksig = (float)(3.003 * std::sqrt(1.001 * (double)b.jf2) * up);
+    const double fx = cam->fx, fy = cam->fy;
+    const double cx = cam->cx, cy = cam->cy, W = cam->width, H = cam->height;
+    const double cl = cx + 3.93, cr = W - cx + 3.93, ct = cy + 3.93, cb = H - cy + 3.93;
+    auto rup = [&](double v) { return (float)(v + std::fabs(v) * 1e-6 + 1e-6); };
+    k.cl = rup(cl);
+    k.cr = rup(cr);
+    k.ct = rup(ct);
+    k.cb = rup(cb);
+    k.fmax = (float)(std::max(fx, fy) * up);
+    k.cmax = (float)(std::max({std::fabs(cl), std::fabs(cr), std::fabs(ct), std::fabs(cb), std::fabs(cx), std::fabs(cy)}) *
+                     up + 1e-6);
+}
+
 // Launch k_rows<MODE> for the moment storage types and the optimizer of the
 // model's groups.
 template <int MODE, int G, int OPT>
@@ -3707,6 +3792,7 @@ int cull_launch(const gs_model *model, const gs_camera *cam, int64_t step, uint3
         adamw_ptrs(model, &a.aw_base, &a.aw_per, &a.aw_nW);
     }
     pack_camera(model, cam, a.cam, a.band);
+    pack_side(cam, a.band, a.side);
     a.geo_dense = model->geo_mode == 1;
     a.K = model->max_defer;
     const int64_t n = model->n;
