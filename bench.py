@@ -365,20 +365,21 @@ def host_cpu():
     return model, nodes
 
 
-def step_bytes(n, M, R, geo_state, app_state, geo_mode, summary=False):
+def step_bytes(n, M, R, geo_state, app_state, geo_mode, summary=0):
     """Algorithmic bytes of one step per call (sg / sa: bytes per stored moment
     of G / A): cull 44 per Gaussian (geometry row + last step) + 20 sg per
-    restored row + 4 per visible id, or with cull summaries 20 per Gaussian
-    (summary + last step) + (40 + 20 sg) per restored row (its geometry row and
-    moments; undecided rows that need no restore are not counted) + 4 per
-    visible id; gather id + last step + G w, m, v + A w, m, v + the 236-byte
-    output row; Adam id + last step read and write + per column w, g read, w
-    written and m, v read and written (+ the 16-byte summary written)."""
+    restored row + 4 per visible id, or with cull summaries `summary` bytes per
+    Gaussian (16, or 20 with the last step past 2^16 steps) + (4 + 40 + 20 sg)
+    per restored row (last step, geometry row and moments; undecided rows that
+    need no restore are not counted) + 4 per visible id; gather id + last step
+    + G w, m, v + A w, m, v + the 236-byte output row; Adam id + last step
+    read and write + per column w, g read, w written and m, v read and written
+    (+ the 16-byte summary written)."""
     msz = {"f32": 4, "bf16": 2, "fp8": 1}
     sg, sa = msz[geo_state], msz[app_state]
     gcols = 0 if geo_mode else 10                       # G columns handled by the sparse kernels
     if summary:
-        cull = 20.0 * n + (40.0 + 20.0 * sg) * R + 4.0 * M
+        cull = float(summary) * n + (44.0 + 20.0 * sg) * R + 4.0 * M
     else:
         cull = 44.0 * n + 20.0 * sg * R + 4.0 * M
     gather = M * (4 + 4 + 8 * 10 + 2 * sg * gcols + 8 * 49 + 2 * sa * 49)
@@ -406,6 +407,7 @@ def run_single(args, w, geo0, app0, state, tilt, on_dev):
                        app_state=state, geo_mode=args.geo_mode, sr_seed=9,
                        cull_summary=None if args.cull_summary else False)
     summ = model.cull_sum is not None
+    sum_bytes = (16 if model.max_steps <= 65536 else 20) if summ else 0
     del geo_in
     n = w.n
     cap = max(1, n // 2)             # a high oblique camera of the 8% workload sees up to 27%
@@ -500,7 +502,7 @@ def run_single(args, w, geo0, app0, state, tilt, on_dev):
     M = vis_total / args.steps
     R = rest_total / args.steps
     f = M / n
-    by = step_bytes(n, M, R, geo_state, state, args.geo_mode, summ)
+    by = step_bytes(n, M, R, geo_state, state, args.geo_mode, sum_bytes)
     kernels = {k: (float(ms), by[k]) for k, ms in (("cull", cull_ms), ("gather", gather_ms), ("adam", adam_ms))}
     dom = max(kernels, key=lambda k: kernels[k][0])
     sym = "cull_sum" if (dom == "cull" and summ) else dom   # the launches of the dominant call
@@ -519,7 +521,7 @@ def run_single(args, w, geo0, app0, state, tilt, on_dev):
                    "visible_fraction": f, "visible_per_step": M, "restored_per_step": R,
                    "state": state, "geo_state": geo_state, "app_layout": args.layout,
                    "max_defer": args.max_defer, "cull_mode": args.cull_mode, "geo_mode": args.geo_mode,
-                   "cull_summary": summ},
+                   "cull_summary": summ, "cull_bytes_per_row": sum_bytes or 44},
         "kernels_ms": {k: v[0] for k, v in kernels.items()},
         "graph_ms_per_step": graph_ms,
         "kernels_gbs": {k: v[1] / (v[0] * 1e-3) / 1e9 for k, v in kernels.items()},

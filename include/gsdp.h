@@ -252,20 +252,22 @@ int gs_cull_noalloc(const gs_model *model, const gs_camera *cam, int64_t step, u
 
 /* Cull summaries (a data layout of this library, not of the paper).  When
  * model->cull_sum is set, the band cull (cull_mode 1, Adam) reads per row a
- * 16-byte summary and the 4-byte last step instead of the 40-byte geometry
- * row and the last step, and loads the row only where its conservative
- * classification cannot decide; the visible list is the same as without
- * summaries.  cull_sum[i] = (x, y, z, s): the centre of row i and s = the
- * largest of its three log-scales plus 1e-6 times the largest of their
- * magnitudes, or s = NaN when a geometric value is not finite, s >= 80, or
- * the quaternion's squared norm is below 1/4.
- * Every call of this library that stores geometry (gs_adam_step_deferred,
- * gs_adam_flush, gs_densify_apply into dst) also stores the summaries of the
- * rows it writes; after
- * geometry is written any other way (initialisation, loading, densification,
- * a caller's own kernels), call this to recompute all n summaries from
- * model->geo.w.  Not available with geo_mode 1 (GS_EUNSUPPORTED from every
- * call).  GS_EINVAL when cull_sum is NULL. */
+ * 16-byte summary instead of the 40-byte geometry row and the 4-byte last
+ * step (with lut_max_steps > 65536 it also reads the last step), and loads
+ * the row only where its conservative classification cannot decide; the
+ * visible list is the same as without summaries.  cull_sum[i] = (x, y, z, w):
+ * the centre of row i, and w whose high 16 bits are those of the FP32 value
+ * s = (largest of the three log-scales) + 1e-6 (largest of their magnitudes)
+ * rounded toward +infinity to 8 significand bits, or 0x7fc0 (a NaN) when a
+ * geometric value is not finite, s >= 80, or the quaternion's squared norm is
+ * below 1/4; the low 16 bits of w are last_step[i] modulo 2^16.
+ * Every call of this library that stores geometry or last steps
+ * (gs_adam_step_deferred, gs_adam_flush, gs_densify_apply into dst) also
+ * stores the summaries of the rows it writes; after geometry or last steps
+ * are written any other way (initialisation, loading, a caller's own
+ * kernels), call this to recompute all n summaries from model->geo.w and
+ * model->last_step.  Not available with geo_mode 1 (GS_EUNSUPPORTED from
+ * every call).  GS_EINVAL when cull_sum is NULL. */
 int gs_cull_summary_build(const gs_model *model, void *stream);
 
 /* Gather: out_geo[i][0..10) and out_app[i][0..dim) = current values of row

@@ -549,21 +549,30 @@ __device__ __forceinline__ int classify(const float *g, float wd, const CamK &c,
     return classify_cam(g, classify_pre(g, wd, b), c, b);
 }
 
-// Cull summary of one geometry row, 16 bytes: its centre and s, the largest
-// log-scale plus the classifier's rounding slack, or s = NaN when the band
-// classifier must leave the row to the exact test: a non-finite value, s of
-// 80 or more, or a quaternion of squared norm below 1/4 (the sure-in decision
-// then needs the quaternion itself).  The band cull reads these 16 bytes and
-// the last step instead of the 40-byte row; it loads the row only for the
-// rows the classifier leaves undecided.
-__device__ __forceinline__ float4 cull_summary(const float *g)
+// Cull summary of one geometry row, 16 bytes: its centre (x, y, z) and one
+// word w.  The high 16 bits of w are those of s, the largest log-scale plus
+// the classifier's rounding slack, rounded up to 8 significand bits (so
+// s_up = w & 0xffff0000, read as a float, is >= s), or of a quiet NaN when
+// the band classifier must leave the row to the exact test: a non-finite
+// value, s of 80 or more, or a quaternion of squared norm below 1/4 (the
+// sure-in decision then needs the quaternion itself).  The low 16 bits hold
+// the row's last update step modulo 2^16, from which the cull recovers the
+// defer count while the steps fit 16 bits.  The band cull reads these 16
+// bytes instead of the 40-byte row and the last step; it loads the row only
+// for the rows the classifier leaves undecided.
+__device__ __forceinline__ float4 cull_summary(const float *g, int last)
 {
     const float fsum = (((fabsf(g[0]) + fabsf(g[1])) + (fabsf(g[2]) + fabsf(g[3]))) +
                         ((fabsf(g[4]) + fabsf(g[5])) + (fabsf(g[6]) + fabsf(g[7])))) + (fabsf(g[8]) + fabsf(g[9]));
     const float sm = fmaxf(fmaxf(g[3], g[4]), g[5]) + 1e-6f * fmaxf(fmaxf(fabsf(g[3]), fabsf(g[4])), fabsf(g[5]));
     const float qn2 = fmaf(g[9], g[9], fmaf(g[8], g[8], fmaf(g[7], g[7], g[6] * g[6])));
     const bool ok = __builtin_isfinite(fsum) && sm < 80.0f && qn2 >= 0.25f;
-    return make_float4(g[0], g[1], g[2], ok ? sm : __builtin_nanf(""));
+    // round toward +infinity: a positive value's magnitude up, a negative one's down
+    u32 b = __float_as_uint(sm);
+    if (b >> 31) b &= 0xffff0000u;
+    else if (b & 0xffffu) b = (b & 0xffff0000u) + 0x10000u;
+    const u32 hi = ok ? (b & 0xffff0000u) : 0x7fc00000u;
+    return make_float4(g[0], g[1], g[2], __uint_as_float(hi | ((u32)last & 0xffffu)));
 }
 
 // classify_pre from a summary.  The bounds are those of classify_pre: the
@@ -589,14 +598,14 @@ __device__ __forceinline__ RowPre classify_pre_sum(const float4 &v, float wd, co
 }
 
 // Store the summary of a row whose new geometric values sit in lanes 0..9 of
-// the wavefront (value x of this lane); every lane of the wavefront takes
-// part, lane 0 stores.
-__device__ __forceinline__ void cull_summary_store_wave(float4 *sum, u32 row, float x)
+// the wavefront (value x of this lane) and whose last step becomes `last`;
+// every lane of the wavefront takes part, lane 0 stores.
+__device__ __forceinline__ void cull_summary_store_wave(float4 *sum, u32 row, float x, int last)
 {
     float g[10];
 #pragma unroll
     for (int j = 0; j < 10; ++j) g[j] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), j));
-    const float4 v = cull_summary(g);
+    const float4 v = cull_summary(g, last);
     if ((threadIdx.x & 63) == 0) sum[row] = v;
 }
 
@@ -936,14 +945,16 @@ __global__ __launch_bounds__(kCullBlock, 7) void k_cull(CullArgs a)
 
 // The band cull from the cull summaries (Adam, geometry deferred).  A block
 // takes TPB consecutive 512-row tiles, kCullIpt * TPB rows a thread: every
-// row's summary and last step are loaded first (coalesced, no LDS staging),
-// then every row's step-table entry (entry 0 is 0, so the load needs no
+// row's summary (and, unless PACKED, its last step) is loaded first
+// (coalesced, no LDS staging), then every row's step-table entry (entry 0 is 0, so the load needs no
 // branch), then the rows are classified.  The undecided rows (near a decision
 // boundary, or flagged by their summary) are rare: one loop, not unrolled,
 // loads each one's geometry row, restores it when deferred and takes the
 // exact test.  Same outputs as k_cull, tile by tile.
 constexpr int kCullSumTiles = 2;      // tiles of a k_cull_sum block (of 1, 2, 4, 8 the fastest at 40M rows)
-template <bool NT, int TPB>
+// PACKED (steps up to 2^16): each row's defer count comes from the low 16
+// bits of its summary word, and the last-step array is not read.
+template <bool NT, int TPB, bool PACKED>
 __global__ __launch_bounds__(kCullBlock) void k_cull_sum(CullArgs a)
 {
     constexpr int RPT = kCullIpt * TPB;
@@ -969,17 +980,20 @@ __global__ __launch_bounds__(kCullBlock) void k_cull_sum(CullArgs a)
         const int64_t row = row_of(q);
         valid |= (u32)(row < a.n) << q;
         const int64_t rc = row < a.n ? row : a.n - 1;
-        lastv[q] = ld_sweep<NT>(a.last + rc);
+        if (!PACKED) lastv[q] = ld_sweep<NT>(a.last + rc);
         sv[q] = ld_sweep<NT>(a.sum + rc);
     }
     int dv[RPT];
     float wdv[RPT];
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
-        int d = t - 1 - lastv[q];
+        const u32 wb = __float_as_uint(sv[q].w);
+        // t - 1 - last is in [0, 2^16) while the steps fit 16 bits
+        int d = PACKED ? (int)(((u32)(t - 1) - wb) & 0xffffu) : t - 1 - lastv[q];
         d = d < 0 ? 0 : (d > dmax ? dmax : d);
         dv[q] = d;
         wdv[q] = Wrow[d];
+        sv[q].w = __uint_as_float(wb & 0xffff0000u);      // s rounded up (or NaN)
     }
     // classification: keep bits and undecided bits of this thread's rows.
     // side_out settles most rows; the full classification runs for a slot
@@ -1085,7 +1099,8 @@ __global__ __launch_bounds__(kCullBlock) void k_cull_sum(CullArgs a)
 
 // Summaries of rows [0, n) from the stored geometry (grid-stride, one row a
 // thread).
-__global__ __launch_bounds__(256) void k_cull_summary_build(const float *gw, float4 *sum, int64_t n)
+__global__ __launch_bounds__(256) void k_cull_summary_build(const float *gw, const int32_t *last, float4 *sum,
+                                                            int64_t n)
 {
     for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < n; r += (int64_t)gridDim.x * 256) {
         float g[10];
@@ -1096,7 +1111,7 @@ __global__ __launch_bounds__(256) void k_cull_summary_build(const float *gw, flo
             g[2 * j] = q.x;
             g[2 * j + 1] = q.y;
         }
-        sum[r] = cull_summary(g);
+        sum[r] = cull_summary(g, last[r]);
     }
 }
 
@@ -1805,7 +1820,7 @@ __device__ __forceinline__ void rows_work(const RowArgs &a, const int t, const f
                     asm volatile("; A columns");
                 }
             }
-            if (a.cull_sum) cull_summary_store_wave(a.cull_sum, r, xs);
+            if (a.cull_sum) cull_summary_store_wave(a.cull_sum, r, xs, t);
             if (lane == 0) a.last[r] = t;
         }
 #pragma unroll
@@ -2011,7 +2026,7 @@ __device__ __forceinline__ void rows_fz_work(const FastArgs &a, const int t, con
                     mstore<ST>((char *)(fb[u] + lane_off(mo)), 0.0f, m1, rm, false);
                     mstore<ST>((char *)(fb[u] + lane_off(vo)), 0.0f, v1, rv, true);
                 }
-                if (a.cull_sum) cull_summary_store_wave(a.cull_sum, id[u], x);
+                if (a.cull_sum) cull_summary_store_wave(a.cull_sum, id[u], x, t);
                 if (lane == 0) a.last[id[u]] = t;
             }
         }
@@ -3751,7 +3766,7 @@ int gs_cull_summary_build(const gs_model *model, void *stream)
     const int cu = cu_count();
     const int64_t blocks = std::min<int64_t>((model->n + 255) / 256, (int64_t)(cu > 0 ? cu : 256) * 16);
     hipLaunchKernelGGL(k_cull_summary_build, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, model->geo.w,
-                       reinterpret_cast<float4 *>(model->cull_sum), model->n);
+                       model->last_step, reinterpret_cast<float4 *>(model->cull_sum), model->n);
     return launched("gs_cull_summary_build");
 }
 
@@ -3805,12 +3820,18 @@ int cull_launch(const gs_model *model, const gs_camera *cam, int64_t step, uint3
     if (a.tiles > 0) {
         a.sum = reinterpret_cast<const float4 *>(model->cull_sum);
         if (a.mode == 1 && a.sum && !a.geo_dense) {
-            // summary and last step: 20 bytes a row
+            // the summary (and the last step past 2^16 steps): 16 (20) bytes a row
             const unsigned blocks = (unsigned)((a.tiles + kCullSumTiles - 1) / kCullSumTiles);
-            if ((int64_t)n * 20 > kLastLevelCacheBytes)
-                hipLaunchKernelGGL((k_cull_sum<true, kCullSumTiles>), dim3(blocks), dim3(kCullBlock), 0, st, a);
+            const bool packed = model->lut_max_steps <= 65536;
+            const bool nt = (int64_t)n * (packed ? 16 : 20) > kLastLevelCacheBytes;
+            if (packed && nt)
+                hipLaunchKernelGGL((k_cull_sum<true, kCullSumTiles, true>), dim3(blocks), dim3(kCullBlock), 0, st, a);
+            else if (packed)
+                hipLaunchKernelGGL((k_cull_sum<false, kCullSumTiles, true>), dim3(blocks), dim3(kCullBlock), 0, st, a);
+            else if (nt)
+                hipLaunchKernelGGL((k_cull_sum<true, kCullSumTiles, false>), dim3(blocks), dim3(kCullBlock), 0, st, a);
             else
-                hipLaunchKernelGGL((k_cull_sum<false, kCullSumTiles>), dim3(blocks), dim3(kCullBlock), 0, st, a);
+                hipLaunchKernelGGL((k_cull_sum<false, kCullSumTiles, false>), dim3(blocks), dim3(kCullBlock), 0, st, a);
         } else if ((int64_t)n * 44 > kLastLevelCacheBytes) {
             // geometry and last step: 44 bytes a row
             hipLaunchKernelGGL(k_cull<true>, dim3((unsigned)a.tiles), dim3(kCullBlock), 0, st, a);

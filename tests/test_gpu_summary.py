@@ -25,10 +25,10 @@ def g():
     return gsdp
 
 
-def host_summary(geo):
-    """(x, y, z, s) of each row in FP32, as include/gsdp.h defines it; also
-    returns the rows whose quaternion test lies within rounding of 1/4 (the
-    device evaluates |q|^2 with fused multiply-adds)."""
+def host_summary(geo, last):
+    """(x, y, z, w) of each row as include/gsdp.h defines them, as uint32
+    words; also returns the rows whose quaternion test lies within rounding
+    of 1/4 (the device evaluates |q|^2 with fused multiply-adds)."""
     g = np.asarray(geo, np.float32)
     a = np.abs(g)
     with np.errstate(over="ignore", invalid="ignore"):
@@ -38,21 +38,27 @@ def host_summary(geo):
             np.float32(1e-6) * np.maximum(np.maximum(a[:, 3], a[:, 4]), a[:, 5])
         qn2 = (g[:, 6:10].astype(np.float64) ** 2).sum(1)
         ok = np.isfinite(fsum) & (sm < np.float32(80.0)) & (qn2 >= 0.25)
-    out = np.empty((g.shape[0], 4), np.float32)
-    out[:, :3] = g[:, :3]
-    out[:, 3] = np.where(ok, sm, np.nan)
+    b = sm.astype(np.float32).view(np.uint32)
+    neg = (b >> 31) == 1
+    up = np.where(neg, b & 0xFFFF0000, np.where(b & 0xFFFF, (b & 0xFFFF0000) + 0x10000, b))
+    hi = np.where(ok, up & 0xFFFF0000, 0x7FC00000).astype(np.uint32)
+    out = np.empty((g.shape[0], 4), np.uint32)
+    out[:, :3] = g[:, :3].view(np.uint32)
+    out[:, 3] = hi | (np.asarray(last, np.int64) & 0xFFFF).astype(np.uint32)
+    # the rounded-up s is not below s
+    s_up = (hi & 0xFFFF0000).view(np.float32)
+    assert np.all(s_up[ok] >= sm[ok])
     near = np.abs(qn2 - 0.25) < 1e-6
     return out, near
 
 
 def same_summary(a, b, skip=None):
-    """Equal as values (NaN where NaN); rows in `skip` are not compared."""
-    a = np.asarray(a)
-    b = np.asarray(b)
+    """Equal word for word; rows in `skip` are not compared."""
+    a = np.ascontiguousarray(a).view(np.uint32)
+    b = np.ascontiguousarray(b).view(np.uint32)
     if skip is not None:
         a, b = a[~skip], b[~skip]
-    na, nb = np.isnan(a), np.isnan(b)
-    return np.array_equal(na, nb) and np.array_equal(a[~na], b[~nb])
+    return np.array_equal(a, b)
 
 
 def _rows(rng, n):
@@ -78,10 +84,14 @@ def test_summary_build_matches_definition(g):
         lg, la = gi.lr_columns()
         model = g.Model(geo, np.zeros((n, 49), np.float32), lg, la, max_steps=8, cull_mode=1)
         assert model.cull_sum is not None
+        # last steps past 2^16 and at its multiples: only the low 16 bits are kept
+        last = rng.choice([0, 1, 7, 65535, 65536, 65537, 1 << 20, 2 ** 31 - 1], n).astype(np.int32)
+        model.last_step.copy_(torch.from_numpy(last))
+        model.cull_summary_build()
         torch.cuda.synchronize()
-        ref, near = host_summary(geo)
+        ref, near = host_summary(geo, last)
         got = model.cull_sum[:n].cpu().numpy()
-        say(f"[summary build] n={n}: {int(np.isnan(ref[:, 3]).sum())} rows left to the exact test, "
+        say(f"[summary build] n={n}: {int((ref[:, 3] >> 16 == 0x7FC0).sum())} rows left to the exact test, "
             f"{int(near.sum())} within rounding of the quaternion limit")
         assert same_summary(got, ref, skip=near)
 
