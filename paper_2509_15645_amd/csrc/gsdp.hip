@@ -398,11 +398,15 @@ struct BandK {
     float kpos, kscl, kq;  // B * max lr over position / log-scale / quaternion columns
 };
 
-// Per-camera constants of side_out (host-computed, rounded up).
+// Per-camera constants of side_out (host-computed in FP64, margins rounded
+// up): the four side planes in world coordinates, n . p + k, with
+// n_l = fx R_0 + cl R_2, k_l = fx T_0 + cl T_2 (cl = cx + 3.93), the right
+// side -fx and cr = W - cx + 3.93, the top fy, R_1, T_1 and ct = cy + 3.93,
+// the bottom -fy and cb = H - cy + 3.93; n1 their 1-norms.
 struct SideK {
+    float n[4][3], k[4], n1[4];
     float ksig;            // 3.003 sqrt(1.001 jf2)
-    float cl, cr, ct, cb;  // cx + 3.93, W - cx + 3.93, cy + 3.93, H - cy + 3.93
-    float fmax, cmax;      // max(fx, fy); the largest of |cl|, |cr|, |ct|, |cb|, |cx|, |cy|
+    float sa, sb;          // slack: 1e-5 (sa (mu + dp) + sb + ksig sig) covers every rounding
 };
 
 // Conservative classification of one Gaussian whose stored geometry g may be
@@ -489,26 +493,37 @@ __device__ __forceinline__ CamBox cam_box(const float *g, const RowPre &p, const
 // exact value) and r its radius, r <= 3.003 sqrt(1.001 |J|_F^2 sigma'^2 +
 // 0.95) + 1 (the bound classify_cam uses) with |J|_F^2 <= jf2 / z'^2.  As
 // z' > 0, multiplying by z' and using sqrt(a + b) <= sqrt(a) + sqrt(b):
-//   fx x' + (cx + 3.93) z' + ksig sigma' + 2.5e-7 (fx |x'| + |cx| z') > 0.
-// Over the box |x' - x| <= ex, |z' - z| <= ez and sigma' <= sig, the left
-// side is at most fx x + cl z + fx ex + |cl| ez + ksig sig plus that term;
-// slack (1e-5 of the terms' magnitudes) covers it and this evaluation's own
-// rounding.  A value <= 0 therefore means no kept geometry: the row is out
-// on that side.  The same for the right (-fx x', cr), top (fy y', ct) and
-// bottom (-fy y', cb) sides; out_z is classify_cam's own test.  NaN bounds
-// make every comparison false (not out).
-__device__ __forceinline__ bool side_out(const CamBox &q, float sig, const CamK &c, const SideK &b)
+//   fx x' + (cx + 3.93) z' + ksig sigma' + 2.5e-7 (fx |x'| + |cx| z') > 0,
+// where x', z' are the exact test's rounded camera coordinates of the
+// restored centre p': x' = R_0 p' + T_0 within 2.5e-7 (|R_0| |p'| + |T_0|).
+// So fx x' + cl z' <= n_l . p' + k_l plus rounding terms, and
+// n_l . p' <= n_l . p + n1_l dp for a drift of at most dp per coordinate.
+// With sigma' <= sig, keeping the row needs n_l . p + k_l + n1_l dp +
+// ksig sig + slack > 0, slack covering the rounding terms (at most 2.5e-7
+// (2 fx |R_0|_1 + (|cl| + |cx|) |R_2|_1) (mu + dp) plus the same with |T|)
+// and this evaluation's own rounding (1e-6 of its terms' magnitudes); the
+// host folds all of it into sa and sb with a tenfold margin.  A value <= 0
+// means no kept geometry: the row is out on that side.  The same for the
+// other three sides; out_z is classify_cam's own test.  NaN bounds make
+// every comparison false (not out).
+__device__ __forceinline__ bool side_out(const float4 &v, const RowPre &p, const CamK &c, const BandK &b,
+                                         const SideK &k)
 {
-    const bool out_z = (q.z + q.ez <= c.zn) | (q.z - q.ez >= c.zf);
-    const float ks = b.ksig * sig;
-    const float mag = fmaf(b.fmax, (fabsf(q.x) + fabsf(q.y)) + (q.ex + q.ey), fmaf(b.cmax, fabsf(q.z) + q.ez, ks));
-    const float base = fmaf(1e-5f, mag, ks);
-    const float fex = c.fx * q.ex, fey = c.fy * q.ey;
-    const float l = fmaf(c.fx, q.x, fmaf(b.cl, q.z, fmaf(fabsf(b.cl), q.ez, fex + base)));
-    const float r = fmaf(-c.fx, q.x, fmaf(b.cr, q.z, fmaf(fabsf(b.cr), q.ez, fex + base)));
-    const float t = fmaf(c.fy, q.y, fmaf(b.ct, q.z, fmaf(fabsf(b.ct), q.ez, fey + base)));
-    const float d = fmaf(-c.fy, q.y, fmaf(b.cb, q.z, fmaf(fabsf(b.cb), q.ez, fey + base)));
-    return out_z | (l <= 0.0f) | (r <= 0.0f) | (t <= 0.0f) | (d <= 0.0f);
+    const float z = fmaf(c.R[8], v.z, fmaf(c.R[7], v.y, fmaf(c.R[6], v.x, c.T[2])));
+    const float sz = fmaf(b.rs2, p.mu, fabsf(c.T[2]));
+    const float dz = b.rs2 * p.dp;
+    const float ez = fmaf(1e-6f, sz + dz, dz) + 1e-6f;
+    const bool out_z = (z + ez <= c.zn) | (z - ez >= c.zf);
+    const float ks = k.ksig * p.sig;
+    const float base = ks + 1e-5f * fmaf(k.sa, p.mu + p.dp, k.sb + ks);
+    bool out = out_z;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const float e = fmaf(k.n1[i], p.dp, k.k[i] + base);
+        const float l = fmaf(k.n[i][2], v.z, fmaf(k.n[i][1], v.y, fmaf(k.n[i][0], v.x, e)));
+        out |= l <= 0.0f;
+    }
+    return out;
 }
 
 __device__ __forceinline__ int classify_box(const CamBox &q, const RowPre &p, const CamK &c, const BandK &b)
@@ -1001,12 +1016,11 @@ __global__ __launch_bounds__(kCullBlock) void k_cull_sum(CullArgs a)
     u32 keepm = 0, und = 0;
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
-        const float c3[3] = {sv[q].x, sv[q].y, sv[q].z};
         const RowPre pre = classify_pre_sum(sv[q], wdv[q], a.band);
-        const CamBox box = cam_box(c3, pre, a.cam, a.band);
-        const bool left = !(pre.ok != 0 && side_out(box, pre.sig, a.cam, a.side)) && ((valid >> q) & 1u);
+        const bool left = !(pre.ok != 0 && side_out(sv[q], pre, a.cam, a.band, a.side)) && ((valid >> q) & 1u);
         if (__ballot(left) != 0ull) {
-            const int cls = left ? classify_box(box, pre, a.cam, a.band) : 0;
+            const float c3[3] = {sv[q].x, sv[q].y, sv[q].z};
+            const int cls = left ? classify_box(cam_box(c3, pre, a.cam, a.band), pre, a.cam, a.band) : 0;
             keepm |= (u32)(cls == 1) << q;
             und |= (u32)(cls == 2) << q;
         }
@@ -2588,22 +2602,41 @@ void pack_camera(const gs_model *model, const gs_camera *cam, CamK &k, BandK &b)
     b.jf2 = (float)((fx * fx * (1.0 + (double)limx * limx) + fy * fy * (1.0 + (double)limy * limy)) * (1.0 + 1e-4));
 }
 
-// Constants of side_out, rounded up (a larger margin only keeps more rows).
+// Constants of side_out (a larger margin only keeps more rows).
 void pack_side(const gs_camera *cam, const BandK &b, SideK &k)
 {
     const double up = 1.0 + 1e-6;
     k.ksig = (float)(3.003 * std::sqrt(1.001 * (double)b.jf2) * up);
     const double fx = cam->fx, fy = cam->fy;
     const double cx = cam->cx, cy = cam->cy, W = cam->width, H = cam->height;
-    const double cl = cx + 3.93, cr = W - cx + 3.93, ct = cy + 3.93, cb = H - cy + 3.93;
-    auto rup = [&](double v) { return (float)(v + std::fabs(v) * 1e-6 + 1e-6); };
-    k.cl = rup(cl);
-    k.cr = rup(cr);
-    k.ct = rup(ct);
-    k.cb = rup(cb);
-    k.fmax = (float)(std::max(fx, fy) * up);
-    k.cmax = (float)(std::max({std::fabs(cl), std::fabs(cr), std::fabs(ct), std::fabs(cb), std::fabs(cx), std::fabs(cy)}) *
-                     up + 1e-6);
+    const double c4[4] = {cx + 3.93, W - cx + 3.93, cy + 3.93, H - cy + 3.93};
+    const double f4[4] = {fx, -fx, fy, -fy};
+    const int row[4] = {0, 0, 1, 1};
+    double R[9], T[3];
+    for (int i = 0; i < 9; ++i) R[i] = cam->R[i];
+    for (int i = 0; i < 3; ++i) T[i] = cam->t[i];
+    auto r1 = [&](int r) { return std::fabs(R[3 * r]) + std::fabs(R[3 * r + 1]) + std::fabs(R[3 * r + 2]); };
+    double sa = 0.0, sb = 0.0;
+    for (int s = 0; s < 4; ++s) {
+        const int r = row[s];
+        double n1 = 0.0;
+        for (int j = 0; j < 3; ++j) {
+            const double nj = f4[s] * R[3 * r + j] + c4[s] * R[6 + j];
+            k.n[s][j] = (float)nj;
+            n1 += std::fabs(nj);
+        }
+        const double kk = f4[s] * T[r] + c4[s] * T[2];
+        k.k[s] = (float)kk;
+        k.n1[s] = (float)(n1 * up + 1e-30);
+        // rounding of the exact test's coordinates (2 |f| |R_r|_1 + (|c| + |c0|) |R_2|_1 per unit of
+        // mu + dp, the same with |T|) and of this test (|n|_1 per unit of mu + dp, |k|)
+        const double c0 = s < 2 ? std::fabs(cx) : std::fabs(cy);
+        sa = std::max(sa, 2.0 * std::fabs(f4[s]) * r1(r) + (std::fabs(c4[s]) + c0) * r1(2) + n1);
+        sb = std::max(sb, 2.0 * std::fabs(f4[s]) * std::fabs(T[r]) + (std::fabs(c4[s]) + c0) * std::fabs(T[2]) +
+                              std::fabs(kk));
+    }
+    k.sa = (float)(sa * up);
+    k.sb = (float)(sb * up + 1e-6);
 }
 
 // Launch k_rows<MODE> for the moment storage types and the optimizer of the
