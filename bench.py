@@ -460,20 +460,31 @@ def run_single(args, w, geo0, app0, state, tilt, on_dev):
 
     graph_ms = None
     if args.graph:
-        # the same step as one hipGraph: the single-camera cull runs as the batched
-        # cull with one scene and one camera per set (set k = the camera of step k+1)
+        # the same step as one hipGraph, the camera of step t read from a device
+        # table (gs_cull_table, the summary cull); without summaries the
+        # single-camera cull runs as the batched cull with one scene and one
+        # camera per set (set k = the camera of step k+1)
         ntab = total_steps + args.steps + 2
-        cam_sets = [[[w.camera_for_step(k + 1)]] for k in range(ntab)]
-        multi = gsdp.Multi(model, [0, n], cam_sets, cap_union=cap, cap_cam=1)
         gg, ga = pool[0]
         t_next = args.warmup + args.steps + 1
         model.step_dev.fill_(t_next)
+        if summ:
+            table = gsdp.camera_table(model, [w.camera_for_step(k + 1) for k in range(ntab)])
 
-        def gstep():
-            gsdp.gs_cull_multi(model, multi, 0)
-            gsdp.gs_gather(model, 0, multi.union_ids, multi.union_count, out_g, out_a, capacity=cap)
-            gsdp.gs_adam_step_deferred(model, 0, multi.union_ids, multi.union_count, gg, ga, capacity=cap)
-            gsdp.gs_step_advance(model.step_dev)
+            def gstep():
+                gsdp.gs_cull_table(model, table, 0, ids, count, capacity=cap)
+                gsdp.gs_gather(model, 0, ids, count, out_g, out_a, capacity=cap)
+                gsdp.gs_adam_step_deferred(model, 0, ids, count, gg, ga, capacity=cap)
+                gsdp.gs_step_advance(model.step_dev)
+        else:
+            cam_sets = [[[w.camera_for_step(k + 1)]] for k in range(ntab)]
+            multi = gsdp.Multi(model, [0, n], cam_sets, cap_union=cap, cap_cam=1)
+
+            def gstep():
+                gsdp.gs_cull_multi(model, multi, 0)
+                gsdp.gs_gather(model, 0, multi.union_ids, multi.union_count, out_g, out_a, capacity=cap)
+                gsdp.gs_adam_step_deferred(model, 0, multi.union_ids, multi.union_count, gg, ga, capacity=cap)
+                gsdp.gs_step_advance(model.step_dev)
 
         gstep()
         torch.cuda.synchronize()

@@ -270,6 +270,17 @@ int gs_cull_noalloc(const gs_model *model, const gs_camera *cam, int64_t step, u
  * every call).  GS_EINVAL when cull_sum is NULL. */
 int gs_cull_summary_build(const gs_model *model, void *stream);
 
+/* gs_cull with the camera taken from device memory: record (t - 1) % n_cams
+ * of `cams` (n_cams records from gs_camera_pack, uploaded by the caller,
+ * 16-byte aligned), t the update step (step, or with step == 0 the model's
+ * device step counter).  So a whole training step, its camera included, can
+ * be captured once in a hipGraph and replayed.  Same outputs as gs_cull with
+ * that camera.  Only the band cull from cull summaries reads its camera this
+ * way: GS_EUNSUPPORTED unless cull_mode = 1, eps > 0, Adam, geo_mode = 0 and
+ * cull_sum is set. */
+int gs_cull_table(const gs_model *model, const void *cams, int32_t n_cams, int64_t step, uint32_t *ids,
+                  uint32_t *count_dev, uint32_t capacity, void *ws, size_t ws_bytes, void *stream);
+
 /* Gather: out_geo[i][0..10) and out_app[i][0..dim) = current values of row
  * ids[i] before update `step`, for i < min(*count_dev, capacity).  Deferred
  * rows are restored with the w_scale LUT and their stored moments (Eq. 3);
@@ -348,8 +359,10 @@ typedef struct gs_multi {
                                     searches); NULL: gs_grad_sum_multi searches */
 } gs_multi;
 
-/* Size of one camera record, and packing of `count` cameras for `model`
- * (camera matrices plus the rounded-up constants of the band classifier). */
+/* Size of one camera record (256 bytes), and packing of `count` cameras for
+ * `model` (camera matrices plus the rounded-up constants of the band
+ * classifier and of the summary cull's side test).  Records feed
+ * gs_cull_multi and gs_cull_table. */
 int gs_camera_pack_bytes(size_t *bytes);
 int gs_camera_pack(const gs_model *model, const gs_camera *cams, int32_t count, void *out_host);
 

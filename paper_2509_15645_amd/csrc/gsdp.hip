@@ -409,6 +409,16 @@ struct SideK {
     float sa, sb;          // slack: 1e-5 (sa (mu + dp) + sb + ksig sig) covers every rounding
 };
 
+// One camera with its classifier constants: the records of gs_camera_pack,
+// read by the batched cull and by the single-camera cull from a device table.
+struct CamPack {
+    CamK cam;
+    BandK band;
+    SideK side;
+    float pad[14];
+};
+static_assert(sizeof(CamPack) == 256, "camera records are 256 bytes");
+
 // Conservative classification of one Gaussian whose stored geometry g may be
 // stale by a restore of at most B*W[d]*lr per column.  B is the clamp of the
 // restore factor (1.03x the Cauchy-Schwarz bound (1-b1)/sqrt((1-b2)(1-b1^2/b2))
@@ -789,6 +799,8 @@ struct CullArgs {
     int64_t tiles;
     const float4 *sum;               // [n] cull summaries (k_cull_sum)
     SideK side;                      // side_out constants (k_cull_sum)
+    const CamPack *cams;             // camera table (k_cull_sum<..., true>): record (t - 1) % n_cams
+    int32_t n_cams, pad9;
 };
 
 // Seven blocks per CU (the LDS tiles allow seven): the register budget this
@@ -968,8 +980,9 @@ __global__ __launch_bounds__(kCullBlock, 7) void k_cull(CullArgs a)
 // exact test.  Same outputs as k_cull, tile by tile.
 constexpr int kCullSumTiles = 2;      // tiles of a k_cull_sum block (of 1, 2, 4, 8 the fastest at 40M rows)
 // PACKED (steps up to 2^16): each row's defer count comes from the low 16
-// bits of its summary word, and the last-step array is not read.
-template <bool NT, int TPB, bool PACKED>
+// bits of its summary word, and the last-step array is not read.  CAMDEV:
+// the camera is record (t - 1) % n_cams of a device table (graph replay).
+template <bool NT, int TPB, bool PACKED, bool CAMDEV>
 __global__ __launch_bounds__(kCullBlock) void k_cull_sum(CullArgs a)
 {
     constexpr int RPT = kCullIpt * TPB;
@@ -982,6 +995,19 @@ __global__ __launch_bounds__(kCullBlock) void k_cull_sum(CullArgs a)
     int dmax, step_err;
     const int t = resolve_step(a.step, 0, &Wrow, &dmax, &step_err);
     const int K = a.K;
+    CamK cam;
+    BandK band;
+    SideK side;
+    if (CAMDEV) {
+        const CamPack &cp = a.cams[(t - 1) % a.n_cams];
+        cam = cp.cam;
+        band = cp.band;
+        side = cp.side;
+    } else {
+        cam = a.cam;
+        band = a.band;
+        side = a.side;
+    }
     if (tid < TPB) sRestored[tid] = 0;
     // row of slot q = j * kCullIpt + i: tile tile0 + j, rows i * kCullBlock + tid
     auto row_of = [&](int q) -> int64_t {
@@ -1016,11 +1042,11 @@ __global__ __launch_bounds__(kCullBlock) void k_cull_sum(CullArgs a)
     u32 keepm = 0, und = 0;
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
-        const RowPre pre = classify_pre_sum(sv[q], wdv[q], a.band);
-        const bool left = !(pre.ok != 0 && side_out(sv[q], pre, a.cam, a.band, a.side)) && ((valid >> q) & 1u);
+        const RowPre pre = classify_pre_sum(sv[q], wdv[q], band);
+        const bool left = !(pre.ok != 0 && side_out(sv[q], pre, cam, band, side)) && ((valid >> q) & 1u);
         if (__ballot(left) != 0ull) {
             const float c3[3] = {sv[q].x, sv[q].y, sv[q].z};
-            const int cls = left ? classify_box(cam_box(c3, pre, a.cam, a.band), pre, a.cam, a.band) : 0;
+            const int cls = left ? classify_box(cam_box(c3, pre, cam, band), pre, cam, band) : 0;
             keepm |= (u32)(cls == 1) << q;
             und |= (u32)(cls == 2) << q;
         }
@@ -1074,7 +1100,7 @@ __global__ __launch_bounds__(kCullBlock) void k_cull_sum(CullArgs a)
 #pragma unroll
             for (int j = 0; j < TPB; ++j) nrest[j] += (u32)(q / kCullIpt == j);
         }
-        keepm |= (u32)cull_v1(g, a.cam) << q;
+        keepm |= (u32)cull_v1(g, cam) << q;
     }
     __syncthreads();
 #pragma unroll
@@ -2708,11 +2734,6 @@ constexpr int kMaxCams = 32;
 constexpr int kNCnt = kMaxCams + 1;
 constexpr int kMultiMinTile = 64;
 
-struct CamPack {                     // one camera with its band-classifier constants
-    CamK cam;
-    BandK band;
-    float pad[5];
-};
 
 // union positions per chunk of the batched gradient sum
 constexpr int kSumRows = 128;
@@ -3523,7 +3544,7 @@ int launch_multi(int variant, const MultiArgs &a, int64_t n, hipStream_t st)
 namespace {
 
 int cull_launch(const gs_model *model, const gs_camera *cam, int64_t step, uint32_t *ids, uint32_t *count_dev,
-                uint32_t capacity, char *wsb, hipStream_t st);
+                uint32_t capacity, char *wsb, hipStream_t st, const void *cams = nullptr, int32_t n_cams = 0);
 
 // Launch the move of the tables' restore rows from `step` to step + 1.
 int lut_advance(const gs_model *m, int64_t step, hipStream_t st)
@@ -3767,6 +3788,22 @@ int gs_cull(const gs_model *model, const gs_camera *cam, int64_t step, uint32_t 
     return cull_launch(model, cam, step, ids, count_dev, capacity, static_cast<char *>(ws), (hipStream_t)stream);
 }
 
+int gs_cull_table(const gs_model *model, const void *cams, int32_t n_cams, int64_t step, uint32_t *ids,
+                  uint32_t *count_dev, uint32_t capacity, void *ws, size_t ws_bytes, void *stream)
+{
+    int rc = check_model(model);
+    if (rc) return rc;
+    if (!cams || n_cams < 1 || !count_dev || !ws || (capacity > 0 && !ids)) return GS_EINVAL;
+    if (!step_ok(model, step)) return GS_EINVAL;
+    if (!aligned(ws, 256) || !aligned(cams, 16)) return GS_EINVAL;
+    if ((int64_t)ws_bytes < gsdp::ws_bytes_for(model->n, model->max_defer, has_fp8(model))) return GS_ESPACE;
+    // only the summary cull reads its camera from device memory
+    const bool band = model->cull_mode == 1 && model->eps > 0.0 && std::isfinite(restore_bound(model->beta1, model->beta2));
+    if (!band || !model->cull_sum || model->geo_mode != 0 || model->optimizer != GS_OPT_ADAM) return GS_EUNSUPPORTED;
+    return cull_launch(model, nullptr, step, ids, count_dev, capacity, static_cast<char *>(ws), (hipStream_t)stream,
+                       cams, n_cams);
+}
+
 int gs_cull_noalloc(const gs_model *model, const gs_camera *cam, int64_t step, uint32_t *ids, uint32_t *count_dev,
                     uint32_t capacity, void *stream)
 {
@@ -3807,10 +3844,26 @@ int gs_cull_summary_build(const gs_model *model, void *stream)
 
 namespace {
 
+template <bool NT, bool PACKED>
+void launch_cull_sum_c(bool camdev, unsigned blocks, hipStream_t st, const CullArgs &a)
+{
+    if (camdev) hipLaunchKernelGGL((k_cull_sum<NT, kCullSumTiles, PACKED, true>), dim3(blocks), dim3(kCullBlock), 0, st, a);
+    else hipLaunchKernelGGL((k_cull_sum<NT, kCullSumTiles, PACKED, false>), dim3(blocks), dim3(kCullBlock), 0, st, a);
+}
+
+void launch_cull_sum(bool nt, bool packed, bool camdev, unsigned blocks, hipStream_t st, const CullArgs &a)
+{
+    if (nt && packed) launch_cull_sum_c<true, true>(camdev, blocks, st, a);
+    else if (packed) launch_cull_sum_c<false, true>(camdev, blocks, st, a);
+    else if (nt) launch_cull_sum_c<true, false>(camdev, blocks, st, a);
+    else launch_cull_sum_c<false, false>(camdev, blocks, st, a);
+}
+
 // The cull and ordered compaction of gs_cull on the workspace `wsb` (checked
-// by the caller).
+// by the caller).  With a camera table (`cams`, n_cams records; cam unused)
+// only the summary cull runs (the caller checked that the model has it).
 int cull_launch(const gs_model *model, const gs_camera *cam, int64_t step, uint32_t *ids, uint32_t *count_dev,
-                uint32_t capacity, char *wsb, hipStream_t st)
+                uint32_t capacity, char *wsb, hipStream_t st, const void *cams, int32_t n_cams)
 {
     CullArgs a;
     memset(&a, 0, sizeof a);
@@ -3839,8 +3892,13 @@ int cull_launch(const gs_model *model, const gs_camera *cam, int64_t step, uint3
         for (int j = 0; j < 10; ++j) a.cls[j] = cls[j];
         adamw_ptrs(model, &a.aw_base, &a.aw_per, &a.aw_nW);
     }
-    pack_camera(model, cam, a.cam, a.band);
-    pack_side(cam, a.band, a.side);
+    if (cams) {
+        a.cams = static_cast<const CamPack *>(cams);
+        a.n_cams = n_cams;
+    } else {
+        pack_camera(model, cam, a.cam, a.band);
+        pack_side(cam, a.band, a.side);
+    }
     a.geo_dense = model->geo_mode == 1;
     a.K = model->max_defer;
     const int64_t n = model->n;
@@ -3850,21 +3908,15 @@ int cull_launch(const gs_model *model, const gs_camera *cam, int64_t step, uint3
     a.keep_bits = reinterpret_cast<u64 *>(wsb + gsdp::ws_keep_offset(n));
     a.sat_bits = model->max_defer > 0 ? reinterpret_cast<u64 *>(wsb + gsdp::ws_satbits_offset(n)) : nullptr;
     if (a.tiles > 0x7fffffff) return GS_EINVAL;
+    a.sum = reinterpret_cast<const float4 *>(model->cull_sum);
+    if (a.cams && !(a.mode == 1 && a.sum && !a.geo_dense)) return GS_EUNSUPPORTED;
     if (a.tiles > 0) {
-        a.sum = reinterpret_cast<const float4 *>(model->cull_sum);
         if (a.mode == 1 && a.sum && !a.geo_dense) {
             // the summary (and the last step past 2^16 steps): 16 (20) bytes a row
             const unsigned blocks = (unsigned)((a.tiles + kCullSumTiles - 1) / kCullSumTiles);
             const bool packed = model->lut_max_steps <= 65536;
             const bool nt = (int64_t)n * (packed ? 16 : 20) > kLastLevelCacheBytes;
-            if (packed && nt)
-                hipLaunchKernelGGL((k_cull_sum<true, kCullSumTiles, true>), dim3(blocks), dim3(kCullBlock), 0, st, a);
-            else if (packed)
-                hipLaunchKernelGGL((k_cull_sum<false, kCullSumTiles, true>), dim3(blocks), dim3(kCullBlock), 0, st, a);
-            else if (nt)
-                hipLaunchKernelGGL((k_cull_sum<true, kCullSumTiles, false>), dim3(blocks), dim3(kCullBlock), 0, st, a);
-            else
-                hipLaunchKernelGGL((k_cull_sum<false, kCullSumTiles, false>), dim3(blocks), dim3(kCullBlock), 0, st, a);
+            launch_cull_sum(nt, packed, a.cams != nullptr, blocks, st, a);
         } else if ((int64_t)n * 44 > kLastLevelCacheBytes) {
             // geometry and last step: 44 bytes a row
             hipLaunchKernelGGL(k_cull<true>, dim3((unsigned)a.tiles), dim3(kCullBlock), 0, st, a);
@@ -4260,6 +4312,7 @@ int gs_camera_pack(const gs_model *model, const gs_camera *cams, int32_t count, 
         if (!(cams[i].fx > 0.0f && cams[i].fy > 0.0f) || cams[i].width <= 0 || cams[i].height <= 0) return GS_EINVAL;
         memset(&out[i], 0, sizeof(CamPack));
         pack_camera(model, &cams[i], out[i].cam, out[i].band);
+        pack_side(&cams[i], out[i].band, out[i].side);
     }
     return GS_OK;
 }

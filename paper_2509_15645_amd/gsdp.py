@@ -30,7 +30,7 @@ SYMBOLS = ("gs_lut_bytes", "gs_lut_build", "gs_lut_build_host", "gs_lut_build_sc
            "gs_cull_multi_autotune", "gs_grad_sum_multi", "gs_plan_image_split", "gs_lut_build_sgd_momentum",
            "gs_lut_build_sgd_momentum_host", "gs_lut_bytes_adamw", "gs_lut_build_adamw", "gs_lut_build_adamw_host",
            "gs_densify_workspace_bytes", "gs_densify_plan", "gs_densify_apply", "gs_cull_noalloc",
-           "gs_lut_seek", "gs_lut_seek_host", "gs_cull_summary_build")
+           "gs_lut_seek", "gs_lut_seek_host", "gs_cull_summary_build", "gs_cull_table")
 
 
 class GsCamera(C.Structure):
@@ -90,6 +90,7 @@ def _load():
         "gs_cull": (C.c_int, [P(GsModel), P(GsCamera), i64, vp, vp, u32, vp, sz, vp]),
         "gs_cull_noalloc": (C.c_int, [P(GsModel), P(GsCamera), i64, vp, vp, u32, vp]),
         "gs_cull_summary_build": (C.c_int, [P(GsModel), vp]),
+        "gs_cull_table": (C.c_int, [P(GsModel), vp, i32, i64, vp, vp, u32, vp, sz, vp]),
         "gs_gather": (C.c_int, [P(GsModel), i64, vp, vp, u32, vp, vp, vp]),
         "gs_scatter_grad": (C.c_int, [vp, vp, u32, i32, vp, vp, i32, vp]),
         "gs_adam_step_deferred": (C.c_int, [P(GsModel), i64, vp, vp, u32, vp, vp, vp, vp, vp, sz, vp]),
@@ -435,6 +436,29 @@ def gs_cull_noalloc(model: Model, cam, step: int, ids: torch.Tensor, count: torc
     camc = cam if isinstance(cam, GsCamera) else camera_struct(cam)
     _check(lib.gs_cull_noalloc(C.byref(model.c), C.byref(camc), int(step), _ptr(ids), _ptr(count), cap,
                                _stream(stream)), "gs_cull_noalloc")
+
+
+def camera_table(model: Model, cams):
+    """Device table of camera records (gs_camera_pack) for gs_cull_table."""
+    rb = C.c_size_t()
+    _check(lib.gs_camera_pack_bytes(C.byref(rb)), "gs_camera_pack_bytes")
+    flat = (GsCamera * len(cams))()
+    for i, cam in enumerate(cams):
+        flat[i] = cam if isinstance(cam, GsCamera) else camera_struct(cam)
+    recs = np.zeros(len(cams) * rb.value, np.uint8)
+    _check(lib.gs_camera_pack(C.byref(model.c), flat, len(cams), recs.ctypes.data), "gs_camera_pack")
+    return torch.from_numpy(recs).to(model.device)
+
+
+def gs_cull_table(model: Model, table, step: int, ids: torch.Tensor, count: torch.Tensor, capacity=None,
+                  stream=None):
+    """gs_cull with camera (t - 1) % len of a camera_table (step 0: the model's
+    device step counter)."""
+    cap = ids.numel() if capacity is None else int(capacity)
+    rb = C.c_size_t()
+    _check(lib.gs_camera_pack_bytes(C.byref(rb)), "gs_camera_pack_bytes")
+    _check(lib.gs_cull_table(C.byref(model.c), _ptr(table), table.numel() // rb.value, int(step), _ptr(ids),
+                             _ptr(count), cap, _ptr(model.ws), model.ws_bytes, _stream(stream)), "gs_cull_table")
 
 
 def gs_gather(model: Model, step: int, ids, count, out_geo, out_app, capacity=None, stream=None):

@@ -109,7 +109,7 @@ def test_tables_of_a_long_run_are_small(gsdp):
 def test_batched_entry_points_check_arguments(gsdp):
     L = gsdp.lib
     b = C.c_size_t()
-    assert L.gs_camera_pack_bytes(C.byref(b)) == 0 and b.value == 128
+    assert L.gs_camera_pack_bytes(C.byref(b)) == 0 and b.value == 256
     m = gsdp.GsModel()
     m.n = 5000
     assert L.gs_multi_workspace_bytes(C.byref(m), C.byref(b)) == 0
@@ -138,7 +138,9 @@ def test_camera_pack_layout(gsdp):
     for k in range(10):
         m.geo.lr[k] = 1.6e-4 if k < 3 else 5e-3
     cam = gi.orbit_cameras(1, seed=3)[0]
-    rec = np.zeros(32, np.float32)
+    b = C.c_size_t()
+    assert gsdp.lib.gs_camera_pack_bytes(C.byref(b)) == 0 and b.value == 256
+    rec = np.zeros(b.value // 4, np.float32)
     assert gsdp.lib.gs_camera_pack(C.byref(m), C.byref(gsdp.camera_struct(cam)), 1, rec.ctypes.data) == 0
     assert np.array_equal(rec[:9], cam.R.ravel()) and np.array_equal(rec[9:12], cam.t)
     assert rec[12] == cam.fx and rec[16] == cam.width and rec[17] == cam.height
@@ -146,6 +148,13 @@ def test_camera_pack_layout(gsdp):
     assert np.all(rec[20:23] >= rows) and np.all(rec[20:23] <= rows * (1 + 1e-5))
     rb = 1.03 * 0.1 / np.sqrt(0.001 * (1 - 0.81 / 0.999))
     assert rec[24] >= rb * 1.6e-4 and rec[25] >= rb * 5e-3 and rec[26] >= rb * 5e-3
+    # side-test constants: the left plane fx R_0 + (cx + 3.93) R_2, fx T_0 + (cx + 3.93) T_2, and
+    # ksig >= 3.003 sqrt(1.001 jf2)
+    R, t = cam.R.astype(np.float64), cam.t.astype(np.float64)
+    cl = cam.cx + 3.93
+    assert np.allclose(rec[27:30], cam.fx * R[0] + cl * R[2], rtol=1e-6, atol=1e-3)
+    assert np.isclose(rec[39], cam.fx * t[0] + cl * t[2], rtol=1e-6, atol=1e-3)
+    assert rec[47] >= 3.003 * np.sqrt(1.001 * float(rec[23]))
 
 
 @pytest.mark.parametrize("max_defer", [0, 15])

@@ -164,3 +164,68 @@ def test_summaries_after_densification(g):
     say(f"[summary densify] {n} -> {new.n} rows, counts {counts}")
     assert new.cull_sum is not None and new.n > n
     _check_current(new, "after densification")
+
+
+def test_camera_table_cull_eager_and_graph_replay(g):
+    """gs_cull_table (camera from a device table, step from the argument or
+    the device counter) lists what gs_cull lists; a whole step captured once
+    in a hipGraph and replayed, with eager work and synchronisations between
+    the replays, gives every step's list and the final state bit for bit."""
+    n, T = 100_000, 9
+    sc = gi.make_scene(n, seed=21)
+    lg, la = gi.lr_columns()
+    cams = gi.orbit_cameras(T, seed=21)
+    kw = dict(max_steps=T + 2, cull_mode=1, app_layout="fused", geo_state="bf16", app_state="bf16", sr_seed=8)
+    a = g.Model(sc.geo, sc.app, lg, la, **kw)
+    b = g.Model(sc.geo, sc.app, lg, la, **kw)
+    table = g.camera_table(b, cams)
+    bufs = []
+    for _ in range(2):
+        bufs.append((torch.zeros(n, dtype=torch.int32, device="cuda"), torch.zeros(1, dtype=torch.int32, device="cuda"),
+                     torch.empty((n, 10), dtype=torch.float32, device="cuda"),
+                     torch.empty((n, 49), dtype=torch.float32, device="cuda")))
+
+    def eager_step(t):
+        ids, cnt, gg, ga = bufs[0]
+        g.gs_cull(a, cams[t - 1], t, ids, cnt)
+        g.gs_synth_grad(3, 1, ids, cnt, gg, 0)
+        g.gs_synth_grad(3, 1, ids, cnt, ga, 10)
+        g.gs_adam_step_deferred(a, t, ids, cnt, gg, ga)
+        torch.cuda.synchronize()
+        return ids[:int(cnt.item())].clone()
+
+    def table_step(step):
+        ids, cnt, gg, ga = bufs[1]
+        g.gs_cull_table(b, table, step, ids, cnt)
+        g.gs_synth_grad(3, 1, ids, cnt, gg, 0)
+        g.gs_synth_grad(3, 1, ids, cnt, ga, 10)
+        g.gs_adam_step_deferred(b, step, ids, cnt, gg, ga)
+        if step == 0:
+            g.gs_step_advance(b.step_dev)
+
+    for t in (1, 2, 3):                               # explicit steps, eager
+        ref = eager_step(t)
+        table_step(t)
+        torch.cuda.synchronize()
+        m = int(bufs[1][1].item())
+        assert torch.equal(bufs[1][0][:m], ref), t
+    b.step_dev.fill_(4)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        table_step(0)
+    torch.cuda.synchronize()
+    assert int(b.step_dev.item()) == 4               # capture ran nothing
+    for t in range(4, T + 1):
+        ref = eager_step(t)
+        junk = torch.randn(1 << 16, device="cuda").sum()   # eager work between replays
+        graph.replay()
+        torch.cuda.synchronize()
+        assert int(b.step_dev.item()) == t + 1 and torch.isfinite(junk)
+        m = int(bufs[1][1].item())
+        assert m == ref.numel() and torch.equal(bufs[1][0][:m], ref), t
+    sa, sb = a.state(), b.state()
+    for key in sa:
+        assert sa[key].tobytes() == sb[key].tobytes(), key
+    assert a.ws_header()["error"] == 0 and b.ws_header()["error"] == 0
+    say(f"[camera table] {T} steps, 3 eager and {T - 3} graph replays equal gs_cull's")
