@@ -973,8 +973,9 @@ __global__ __launch_bounds__(kCullBlock, 7) void k_cull(CullArgs a)
 // The band cull from the cull summaries (Adam, geometry deferred).  A block
 // takes TPB consecutive 512-row tiles, kCullIpt * TPB rows a thread: every
 // row's summary (and, unless PACKED, its last step) is loaded first
-// (coalesced, no LDS staging), then every row's step-table entry (entry 0 is 0, so the load needs no
-// branch), then the rows are classified.  The undecided rows (near a decision
+// (coalesced, no LDS staging), then the rows are classified, a deferred one
+// with the tables' bound of every restore coefficient.  The undecided rows
+// (near a decision
 // boundary, or flagged by their summary) are rare: one loop, not unrolled,
 // loads each one's geometry row, restores it when deferred and takes the
 // exact test.  Same outputs as k_cull, tile by tile.
@@ -1024,6 +1025,10 @@ __global__ __launch_bounds__(kCullBlock) void k_cull_sum(CullArgs a)
         if (!PACKED) lastv[q] = ld_sweep<NT>(a.last + rc);
         sv[q] = ld_sweep<NT>(a.sum + rc);
     }
+    // A deferred row is classified with the tables' bound of every restore
+    // coefficient instead of its own W[d] (a looser band, no dependent load);
+    // the exact test below uses the row's own W[d].
+    const float wbound = a.step.hdr->wbound;
     int dv[RPT];
     float wdv[RPT];
 #pragma unroll
@@ -1033,7 +1038,7 @@ __global__ __launch_bounds__(kCullBlock) void k_cull_sum(CullArgs a)
         int d = PACKED ? (int)(((u32)(t - 1) - wb) & 0xffffu) : t - 1 - lastv[q];
         d = d < 0 ? 0 : (d > dmax ? dmax : d);
         dv[q] = d;
-        wdv[q] = Wrow[d];
+        wdv[q] = d > 0 ? wbound : 0.0f;
         sv[q].w = __uint_as_float(wb & 0xffff0000u);      // s rounded up (or NaN)
     }
     // classification: keep bits and undecided bits of this thread's rows.

@@ -31,7 +31,8 @@ struct LutHeader {
     int32_t error;           // bit 0: a call's step was not the one its row slot held;
                              // bit 1: a step outside [1, T] (graph replay past the tables)
     int32_t kind;            // 0 Adam, 1 SGD with momentum, 2 AdamW
-    int32_t reserved[9];
+    float wbound;            // >= every restore coefficient W_t[d] the tables hold, any t <= T + 1
+    int32_t reserved[8];
 };
 static_assert(sizeof(LutHeader) == 64, "table header layout");
 enum { kLutAdam = 0, kLutSgdm = 1, kLutAdamw = 2 };

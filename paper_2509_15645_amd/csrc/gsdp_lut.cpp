@@ -16,6 +16,7 @@
 // are fully determined by (b1, b2, t, d) and the schedule.  A learning-rate
 // schedule s[t] (a multiplier of every column's rate at update t) enters as
 // s[k] Cn[k] for the skipped step k and as s[t] / (1 - b1^t) in the step size.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -47,6 +48,8 @@ struct Img {
     double *Pd(int c, int s) const { return reinterpret_cast<double *>(cls(c) + L.cPd) + s * L.nrow; }
     double *qd(int c) const { return reinterpret_cast<double *>(cls(c) + L.cqd); }
 };
+
+void set_wbound(const Img &im);
 
 // Adam tables of a zeroed image: powers, Cn, R, Mf, Vf, SS, BC and the header
 // (row slot 1 holds step 1: W_1 = [0]).
@@ -87,6 +90,24 @@ void fill_adam(const Img &im, double b1, double b2, const double *sched, int kin
     h->nclass = nclass;
     h->kind = kind;
     h->error = 0;
+    set_wbound(im);
+}
+
+// A bound of every restore coefficient the tables will hold: W_t[d] is a sum
+// of d per-step contributions Cn[k] weighted by R[0..d-1], all positive, so
+// W_t[d] <= max_k Cn[k] * sum_{j < D} R[j] for the largest defer count D.
+// Raised by 1e-6 relative (the FP64 sums' and the FP32 rounding's error)
+// and rounded up to FP32.
+void set_wbound(const Img &im)
+{
+    const LutLayout &L = im.L;
+    double cmax = 0.0, rsum = 0.0;
+    for (int64_t k = 1; k <= L.T + 1; ++k) cmax = std::max(cmax, im.Cn()[k]);
+    for (int64_t d = 0; d + 1 < L.nrow; ++d) rsum += im.R()[d];
+    const double wb = cmax * rsum * (1.0 + 1e-6);
+    float f = (float)wb;
+    if ((double)f < wb) f = std::nextafter(f, HUGE_VALF);
+    im.h()->wbound = f;
 }
 
 bool open_image(void *out, int64_t nbytes, int32_t T, int32_t K, int nclass, Img *im)
@@ -173,6 +194,7 @@ int build_lut_sgdm_host(double mu, int32_t T, int32_t K, const double *sched, vo
     h->K = K;
     h->nclass = 0;
     h->kind = kLutSgdm;
+    set_wbound(im);
     return 0;
 }
 

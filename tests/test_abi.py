@@ -347,3 +347,26 @@ def test_cull_summary_checks_need_no_device(gsdp):
     cam.width, cam.height = 64, 64
     ids = C.c_void_p(1 << 20)
     assert L.gs_cull_noalloc(C.byref(m), C.byref(cam), 1, ids, ids, 16, None) == gsdp.GS_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("kind,max_defer,sched", [("adam", 0, False), ("adam", 15, False), ("adam", 0, True),
+                                                   ("sgdm", 15, True)])
+def test_table_bound_covers_every_restore_coefficient(gsdp, kind, max_defer, sched):
+    """The header's wbound (word 7) is at least every FP32 restore coefficient
+    the tables hold at every step up to max_steps + 1."""
+    T = 300
+    rng = np.random.default_rng(3)
+    sc = (0.01 ** (np.arange(T + 2) / (T + 1)) * rng.uniform(0.5, 2.0, T + 2)) if sched else None
+    if kind == "adam":
+        img = gsdp.gs_lut_build_host(0.9, 0.999, T, max_defer, lr_scale=sc)
+    else:
+        img = gsdp.gs_lut_build_sgd_momentum_host(0.9, T, max_defer, lr_scale=sc)
+    v = LL.views(img, T, max_defer)
+    wb = float(v["hdr"][7:8].view(np.float32)[0])
+    top = 0.0
+    for t in range(2, T + 2):
+        gsdp.gs_lut_seek_host(img, t)
+        top = max(top, float(v["Wf"][t & 1].max()))
+        assert v["Wf"][t & 1].max() <= wb, t
+    # not vacuous, and within a modest factor of the largest coefficient held
+    assert 0.0 < top <= wb < 4.0 * top
