@@ -1737,6 +1737,13 @@ __device__ __forceinline__ void rows_work(const RowArgs &a, const int t, const f
                 Vfd[u] = a.Vf[j];
             }
         }
+        // FP8 max pass: tasks this iteration's rows list first (one
+        // same-address atomic per iteration, not one per task)
+        u32 newt[kRU][4];
+#pragma unroll
+        for (int u = 0; u < kRU; ++u)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) newt[u][k] = 0xffffffffu;
 #pragma unroll
         for (int u = 0; u < kRU; ++u) {
             if (!ok[u]) continue;
@@ -1785,12 +1792,10 @@ __device__ __forceinline__ void rows_work(const RowArgs &a, const int t, const f
 #pragma unroll
                     for (int k = 0; k < 4; ++k)
                         if (mx[k]) {
-                            // the first record of a task this step lists it for the rescale
+                            // the first record of a task this step lists it for the
+                            // rescale (listed after the iteration's rows, below)
                             const u32 old = atomicMax(&a.fp8max[k][b], mx[k]);
-                            if (old == 0u) {
-                                const u32 at = atomicAdd(a.fp8count, 1u);
-                                if ((int64_t)at < 4 * a.nb) a.fp8list[at] = (u32)(k * a.nb + b);
-                            }
+                            if (old == 0u) newt[u][k] = (u32)(k * a.nb + b);
                         }
                 continue;
             }
@@ -1867,6 +1872,24 @@ __device__ __forceinline__ void rows_work(const RowArgs &a, const int t, const f
             }
             if (a.cull_sum) cull_summary_store_wave(a.cull_sum, r, xs, t);
             if (lane == 0) a.last[r] = t;
+        }
+        if (MODE == kAdamMax && lane == 0) {
+            u32 nn = 0;
+#pragma unroll
+            for (int u = 0; u < kRU; ++u)
+#pragma unroll
+                for (int k = 0; k < 4; ++k) nn += newt[u][k] != 0xffffffffu;
+            if (nn) {
+                u32 at = atomicAdd(a.fp8count, nn);
+#pragma unroll
+                for (int u = 0; u < kRU; ++u)
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+                        if (newt[u][k] != 0xffffffffu) {
+                            if ((int64_t)at < 4 * a.nb) a.fp8list[at] = newt[u][k];
+                            ++at;
+                        }
+            }
         }
 #pragma unroll
         for (int u = 0; u < kRU; ++u) {
@@ -2140,7 +2163,10 @@ __global__ __launch_bounds__(256) void k_fp8_rescale(RescaleArgs a)
         __syncthreads();
         const float sold = sOld;
         const float snew = fp8_scale_for(amax);
-        if (snew > sold) {
+        // A block still at scale 0 holds only 0x00 codes (stores under scale 0
+        // write 0x00 and scales only grow), which re-encode to 0x00: its rows
+        // are not touched, only its scale is set.
+        if (snew > sold && sold > 0.0f) {
             const int dim = a.dim[wq];
             const int64_t r0 = bq * kFp8Block;
             const int64_t nrow = min((int64_t)kFp8Block, a.n - r0);
@@ -2154,7 +2180,7 @@ __global__ __launch_bounds__(256) void k_fp8_rescale(RescaleArgs a)
             int eo = 0, en = 0;
             frexpf(sold, &eo);
             frexpf(snew, &en);
-            const int kshift = sold > 0.0f ? en - eo : 99;
+            const int kshift = en - eo;
             for (int64_t e0 = 0; e0 < nel; e0 += 256 * kIlp) {
                 uint8_t code[kIlp];
                 int64_t off[kIlp], row[kIlp];
