@@ -229,3 +229,38 @@ def test_camera_table_cull_eager_and_graph_replay(g):
         assert sa[key].tobytes() == sb[key].tobytes(), key
     assert a.ws_header()["error"] == 0 and b.ws_header()["error"] == 0
     say(f"[camera table] {T} steps, 3 eager and {T - 3} graph replays equal gs_cull's")
+
+
+@pytest.mark.parametrize("T,t0", [(70_000, 65_530), (65_536, 65_524)])
+def test_summary_cull_across_the_16_bit_step_boundary(g, T, t0):
+    """Past 2^16 steps the summary cull also reads the last-step array; at
+    exactly 2^16 it still uses the 16 bits of the summary.  Both agree with
+    the cull from the geometry rows on every step around the boundary."""
+    n = 50_000
+    sc = gi.make_scene(n, seed=31)
+    lg, la = gi.lr_columns()
+    cams = gi.orbit_cameras(16, seed=31)
+    kw = dict(max_steps=T, cull_mode=1, app_layout="fused", sr_seed=2)
+    a = g.Model(sc.geo, sc.app, lg, la, cull_summary=True, **kw)
+    b = g.Model(sc.geo, sc.app, lg, la, cull_summary=False, **kw)
+    for m in (a, b):
+        m.lut_seek(t0)
+    ids = [torch.zeros(n, dtype=torch.int32, device="cuda") for _ in range(2)]
+    cnt = [torch.zeros(1, dtype=torch.int32, device="cuda") for _ in range(2)]
+    gg = torch.empty((n, 10), dtype=torch.float32, device="cuda")
+    ga = torch.empty((n, 49), dtype=torch.float32, device="cuda")
+    for t in range(t0, min(T, t0 + 12) + 1):
+        for k, m in enumerate((a, b)):
+            g.gs_cull(m, cams[t % 16], t, ids[k], cnt[k])
+        torch.cuda.synchronize()
+        mm = int(cnt[0].item())
+        assert mm == int(cnt[1].item()) and torch.equal(ids[0][:mm], ids[1][:mm]), t
+        g.gs_synth_grad(4, t, ids[0], cnt[0], gg, 0)
+        g.gs_synth_grad(4, t, ids[0], cnt[0], ga, 10)
+        for m in (a, b):
+            g.gs_adam_step_deferred(m, t, ids[0], cnt[0], gg, ga)
+    sa, sb = a.state(), b.state()
+    for key in sa:
+        assert sa[key].tobytes() == sb[key].tobytes(), key
+    assert a.ws_header()["error"] == 0 and b.ws_header()["error"] == 0
+    say(f"[summary 16-bit boundary] T={T}: steps {t0}..{min(T, t0 + 12)} equal to the geometry cull")
