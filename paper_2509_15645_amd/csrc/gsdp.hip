@@ -1017,13 +1017,27 @@ __global__ __launch_bounds__(kCullBlock) void k_cull_sum(CullArgs a)
     int lastv[RPT];
     float4 sv[RPT];
     u32 valid = 0;
+    // every block but the last lies inside the model: no per-row clamps
+    const bool full = (tile0 + TPB) * kCullTile <= a.n;
+    const float4 *sb = a.sum + tile0 * kCullTile;
+    const int32_t *lb = a.last + tile0 * kCullTile;
+    if (full) {
+        valid = (RPT < 32 ? (1u << RPT) : 0u) - 1u;
 #pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-        const int64_t row = row_of(q);
-        valid |= (u32)(row < a.n) << q;
-        const int64_t rc = row < a.n ? row : a.n - 1;
-        if (!PACKED) lastv[q] = ld_sweep<NT>(a.last + rc);
-        sv[q] = ld_sweep<NT>(a.sum + rc);
+        for (int q = 0; q < RPT; ++q) {
+            const int o = (q / kCullIpt) * kCullTile + (q % kCullIpt) * kCullBlock + tid;
+            if (!PACKED) lastv[q] = ld_sweep<NT>(lb + o);
+            sv[q] = ld_sweep<NT>(sb + o);
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            const int64_t row = row_of(q);
+            valid |= (u32)(row < a.n) << q;
+            const int64_t rc = row < a.n ? row : a.n - 1;
+            if (!PACKED) lastv[q] = ld_sweep<NT>(a.last + rc);
+            sv[q] = ld_sweep<NT>(a.sum + rc);
+        }
     }
     // A deferred row is classified with the tables' bound of every restore
     // coefficient instead of its own W[d] (a looser band, no dependent load);
@@ -1112,9 +1126,9 @@ __global__ __launch_bounds__(kCullBlock) void k_cull_sum(CullArgs a)
     for (int q = 0; q < RPT; ++q) {
         const int j = q / kCullIpt, i = q % kCullIpt;
         const bool keep = (keepm >> q) & 1u;
-        const bool sat = (K > 0) && ((valid >> q) & 1u) && !keep && dv[q] == K;
         const u64 bv = __ballot(keep);
-        const u64 bs = __ballot(sat);
+        u64 bs = 0;
+        if (K > 0) bs = __ballot(((valid >> q) & 1u) && !keep && dv[q] == K);
         const int64_t tile = tile0 + j;
         if (lane == 0) {
             const int slab = i * 4 + wave;
