@@ -419,6 +419,21 @@ class Model:
                 out[name] = t.cpu().numpy()
         return out
 
+    def load_state(self, st, step=None):
+        """Write host arrays in the form state() returns (any subset) into the
+        model, recompute the cull summaries, and with `step` move the tables to
+        that update step (a model resumed after a flush at step - 1)."""
+        for name, a in st.items():
+            t = getattr(self, name)
+            src = torch.from_numpy(np.ascontiguousarray(a))
+            if t.dtype == torch.bfloat16:
+                src = src.view(torch.int16).view(torch.bfloat16)
+            t.copy_(src.to(t.device).view(t.shape))
+        if self.cull_sum is not None:
+            self.cull_summary_build()
+        if step is not None:
+            self.lut_seek(step)
+
 
 # ---------------------------------------------------------------------------
 # the path (same names as the C ABI)

@@ -37,30 +37,30 @@ def _steps(g, model, n, t0, t1, cams, seed):
     torch.cuda.synchronize()
 
 
-@pytest.mark.parametrize("layout,state", [("fused", "f32"), ("fused", "bf16"), ("separate", "f32")])
-def test_flush_save_load_resume_is_bit_exact(g, layout, state):
+@pytest.mark.parametrize("layout,state,max_defer", [("fused", "f32", 0), ("fused", "bf16", 0), ("separate", "f32", 0),
+                                                    ("fused", "f32", 15)])
+def test_flush_save_load_resume_is_bit_exact(g, layout, state, max_defer):
     n, T, t_save = 60_000, 32, 7
     sc = gi.make_scene(n, seed=41)
     lg, la = gi.lr_columns()
     cams = gi.orbit_cameras(T, seed=42)
-    kw = dict(max_steps=T, cull_mode=1, app_layout=layout, geo_state=state, app_state=state, sr_seed=3)
+    kw = dict(max_steps=T, cull_mode=1, app_layout=layout, geo_state=state, app_state=state, sr_seed=3,
+              max_defer=max_defer)
     a = g.Model(sc.geo, sc.app, lg, la, **kw)
     _steps(g, a, n, 1, t_save, cams, 5)
     g.gs_adam_flush(a, t_save)
     torch.cuda.synchronize()
     # checkpoint: host copies of every array of the state
-    names = ("geo_w", "geo_m", "geo_v", "app_w", "app_m", "app_v", "last_step")
-    ckpt = {k: getattr(a, k).cpu().clone() for k in names}
+    ckpt = a.state()
     # the original continues
     _steps(g, a, n, t_save + 1, T, cams, 5)
-    # a new model from the checkpoint, tables moved to the next update
-    b = g.Model(ckpt["geo_w"].numpy(), ckpt["app_w"].numpy(), lg, la, **kw)
-    for k in names:
-        getattr(b, k).copy_(ckpt[k].to("cuda"))
-    b.lut_seek(t_save + 1)
+    # a new model (initial scene) loaded from the checkpoint: its arrays, its
+    # cull summaries recomputed, the tables moved to the next update
+    b = g.Model(sc.geo, sc.app, lg, la, **kw)
+    b.load_state(ckpt, step=t_save + 1)
     _steps(g, b, n, t_save + 1, T, cams, 5)
     sa, sb = a.state(), b.state()
     for k in sa:
         assert sa[k].tobytes() == sb[k].tobytes(), k
     assert a.ws_header()["error"] == 0 and b.ws_header()["error"] == 0
-    say(f"[checkpoint] {layout} {state}: resumed at {t_save + 1}, bit-exact after step {T}")
+    say(f"[checkpoint] {layout} {state} K={max_defer}: resumed at {t_save + 1}, bit-exact after step {T}")
