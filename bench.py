@@ -458,6 +458,30 @@ def run_single(args, w, geo0, app0, state, tilt, on_dev):
         raise RuntimeError(f"cull reported an error flag: {h1}")
     ms_step = (t1 - t0) * 1e3 / args.steps
 
+    # the hardware's bandwidth for the last step's visible rows of the fused
+    # state: loads, and loads with unchanged stores (gs_row_probe)
+    row_probe = None
+    fz = getattr(model, "app_state_bytes", None)
+    if fz is not None and fz.shape[1] <= 1024 and fz.shape[1] % 16 == 0:
+        m_last = min(int(count.item()), cap)
+        sink = torch.zeros(1, dtype=torch.float32, device=dev)
+        row_probe = {"what": "the last step's visible rows of the fused state (one byte row per Gaussian): "
+                             "loads, then loads with the same bytes stored back", "rows": m_last,
+                     "row_bytes": int(fz.shape[1])}
+        for name, wr in (("read", False), ("read_write", True)):
+            pe = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+            for _ in range(2):
+                gsdp.gs_row_probe(ids, m_last, fz, wr, sink, stream=stream)
+            pe[0].record(stream)
+            reps = 10
+            for _ in range(reps):
+                gsdp.gs_row_probe(ids, m_last, fz, wr, sink, stream=stream)
+            pe[1].record(stream)
+            torch.cuda.synchronize()
+            us = pe[0].elapsed_time(pe[1]) * 1e3 / reps
+            moved = m_last * fz.shape[1] * (2 if wr else 1)
+            row_probe[name] = {"us": us, "gbs": moved / (us * 1e-6) / 1e9}
+
     graph_ms = None
     if args.graph:
         # the same step as one hipGraph, the camera of step t read from a device
@@ -546,6 +570,7 @@ def run_single(args, w, geo0, app0, state, tilt, on_dev):
                           "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": step_gbs / HBM_PEAK_GBS,
                           "what": "all three calls' algorithmic bytes over the median step time"},
         "setup_s": setup_s,
+        "row_probe": row_probe,
     }
     del model, pool, out_g, out_a
     torch.cuda.empty_cache()

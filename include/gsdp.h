@@ -478,6 +478,18 @@ int gs_synth_grad(uint64_t seed, int64_t step, const uint32_t *ids, const uint32
  * GS_EINVAL on a null or misaligned argument or more than 2^31 - 1 tiles. */
 int gs_stream_read_probe(const void *buf, size_t bytes, float *sink, void *stream);
 
+/* Measurement only: the row kernels' access pattern without their
+ * arithmetic.  For i < count, one wavefront loads row ids[i] (row_bytes, a
+ * multiple of 16 up to 1024, rows contiguous from `base`, 16-byte aligned)
+ * with 16-byte loads, four rows in flight; with write != 0 it stores every
+ * loaded 16 bytes back unchanged (the same bits: the traffic of a
+ * read-modify-write that changes nothing).  Ids >= n_rows are skipped.
+ * Timing it on a model's fused rows and an update's visible ids gives the
+ * bandwidth the hardware reaches for that row set.  GS_EINVAL on a null or
+ * misaligned argument or a row size out of range. */
+int gs_row_probe(const uint32_t *ids, uint32_t count, void *base, uint64_t n_rows, uint32_t row_bytes, int32_t write,
+                 float *sink, void *stream);
+
 /* Number of compute units of the current device (0 when none). */
 int gs_device_cu_count(void);
 

@@ -3238,6 +3238,42 @@ __global__ __launch_bounds__(256, 7) void k_stream_read(const float4 *p, int64_t
     if (acc == -1.5e-38f) *sink = acc;
 }
 
+// Row-access probe in the row kernels' pattern: one wavefront per listed row
+// (four rows an iteration, every row's loads issued before the first is
+// used), 16 bytes a lane, rows of up to 1024 bytes.  RW: every loaded 16
+// bytes are stored back unchanged (the same bits), so the probe moves the
+// traffic of a read-modify-write of the rows without changing them.  Read
+// only: the sum is stored only if it equals a value finite data never sum to.
+template <bool RW>
+__global__ __launch_bounds__(256) void k_row_probe(const u32 *ids, u32 count, u64 n_rows, float4 *base, u32 row_f4,
+                                                   float *sink)
+{
+    const u32 lane = threadIdx.x & 63u;
+    const u32 w = blockIdx.x * 4u + (threadIdx.x >> 6), nw = gridDim.x * 4u;
+    float acc = 0.0f;
+    for (u32 i = w * 4u; i < count; i += nw * 4u) {
+        float4 v[4];
+        u32 id[4];
+        bool on[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            id[u] = ids[min(i + (u32)u, count - 1u)];
+            // ids at or past n_rows are skipped
+            on[u] = lane < row_f4 && (u64)id[u] < n_rows;
+            v[u] = on[u] ? base[(u64)id[u] * row_f4 + lane] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (RW) {
+                if (on[u] && i + (u32)u < count) base[(u64)id[u] * row_f4 + lane] = v[u];
+            } else {
+                acc += (v[u].x + v[u].y) + (v[u].z + v[u].w);
+            }
+        }
+    }
+    if (!RW && acc == -1.5e-38f) *sink = acc;
+}
+
 // ---------------------------------------------------------------------------
 // densification: plan (codes + tile counts) -> scan -> apply (row copies)
 // ---------------------------------------------------------------------------
@@ -4532,6 +4568,23 @@ int gs_stream_read_probe(const void *buf, size_t bytes, float *sink, void *strea
     hipLaunchKernelGGL(k_stream_read, dim3((u32)grid), dim3(256), 0, (hipStream_t)stream,
                        static_cast<const float4 *>(buf), n4, sink);
     return launched("gs_stream_read_probe");
+}
+
+int gs_row_probe(const uint32_t *ids, uint32_t count, void *base, uint64_t n_rows, uint32_t row_bytes, int32_t write,
+                 float *sink, void *stream)
+{
+    if (!ids || !base || !sink || row_bytes == 0 || row_bytes > 1024 || (row_bytes % 16) != 0 || !aligned(base, 16))
+        return GS_EINVAL;
+    if (count == 0 || n_rows == 0) return GS_OK;
+    const int cu = cu_count();
+    const u32 grid = (u32)std::min<int64_t>(((int64_t)count + 15) / 16, (int64_t)(cu > 0 ? cu : 256) * 8);
+    if (write)
+        hipLaunchKernelGGL(k_row_probe<true>, dim3(grid), dim3(256), 0, (hipStream_t)stream, ids, count, (u64)n_rows,
+                           static_cast<float4 *>(base), row_bytes / 16, sink);
+    else
+        hipLaunchKernelGGL(k_row_probe<false>, dim3(grid), dim3(256), 0, (hipStream_t)stream, ids, count,
+                           (u64)n_rows, static_cast<float4 *>(base), row_bytes / 16, sink);
+    return launched("gs_row_probe");
 }
 
 int gs_step_advance(int32_t *step_dev, void *stream)

@@ -30,7 +30,7 @@ SYMBOLS = ("gs_lut_bytes", "gs_lut_build", "gs_lut_build_host", "gs_lut_build_sc
            "gs_cull_multi_autotune", "gs_grad_sum_multi", "gs_plan_image_split", "gs_lut_build_sgd_momentum",
            "gs_lut_build_sgd_momentum_host", "gs_lut_bytes_adamw", "gs_lut_build_adamw", "gs_lut_build_adamw_host",
            "gs_densify_workspace_bytes", "gs_densify_plan", "gs_densify_apply", "gs_cull_noalloc",
-           "gs_lut_seek", "gs_lut_seek_host", "gs_cull_summary_build", "gs_cull_table")
+           "gs_lut_seek", "gs_lut_seek_host", "gs_cull_summary_build", "gs_cull_table", "gs_row_probe")
 
 
 class GsCamera(C.Structure):
@@ -91,6 +91,7 @@ def _load():
         "gs_cull_noalloc": (C.c_int, [P(GsModel), P(GsCamera), i64, vp, vp, u32, vp]),
         "gs_cull_summary_build": (C.c_int, [P(GsModel), vp]),
         "gs_cull_table": (C.c_int, [P(GsModel), vp, i32, i64, vp, vp, u32, vp, sz, vp]),
+        "gs_row_probe": (C.c_int, [vp, u32, vp, u64, u32, i32, vp, vp]),
         "gs_gather": (C.c_int, [P(GsModel), i64, vp, vp, u32, vp, vp, vp]),
         "gs_scatter_grad": (C.c_int, [vp, vp, u32, i32, vp, vp, i32, vp]),
         "gs_adam_step_deferred": (C.c_int, [P(GsModel), i64, vp, vp, u32, vp, vp, vp, vp, vp, sz, vp]),
@@ -546,6 +547,13 @@ def densify(model: Model, step: int, grad_accum, grad_denom, max_radii2d=None, *
 
 def gs_step_advance(step_dev, stream=None):
     _check(lib.gs_step_advance(_ptr(step_dev), _stream(stream)), "gs_step_advance")
+
+
+def gs_row_probe(ids, count: int, rows, write: bool, sink, stream=None):
+    """Load (and with write, store back unchanged) rows ids[0..count) of the
+    2-D tensor `rows` (measurement helper)."""
+    _check(lib.gs_row_probe(_ptr(ids), int(count), _ptr(rows), rows.shape[0], rows.shape[1] * rows.element_size(),
+                            int(bool(write)), _ptr(sink), _stream(stream)), "gs_row_probe")
 
 
 def gs_stream_read_probe(buf, sink, stream=None):

@@ -370,3 +370,12 @@ def test_table_bound_covers_every_restore_coefficient(gsdp, kind, max_defer, sch
         assert v["Wf"][t & 1].max() <= wb, t
     # not vacuous, and within a modest factor of the largest coefficient held
     assert 0.0 < top <= wb < 4.0 * top
+
+
+def test_row_probe_checks_need_no_device(gsdp):
+    L = gsdp.lib
+    fake = C.c_void_p(1 << 20)
+    assert L.gs_row_probe(None, 10, fake, 100, 48, 1, fake, None) == gsdp.GS_EINVAL
+    assert L.gs_row_probe(fake, 10, fake, 100, 40, 1, fake, None) == gsdp.GS_EINVAL      # not a multiple of 16
+    assert L.gs_row_probe(fake, 10, fake, 100, 2048, 0, fake, None) == gsdp.GS_EINVAL    # more than 1024 bytes
+    assert L.gs_row_probe(fake, 0, fake, 100, 48, 0, fake, None) == gsdp.GS_OK          # nothing to do

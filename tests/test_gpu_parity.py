@@ -446,6 +446,20 @@ def test_band_cull_adversarial_deferred_rows(g, seed):
     assert got[(1, False)][1] < got[(0, False)][1] and got[(1, True)][1] < got[(0, False)][1]
 
 
+def test_row_probe_leaves_rows_unchanged(g):
+    """The row probe loads (and stores back) listed rows without changing a
+    byte; ids past the row count are skipped."""
+    rows = torch.randint(0, 255, (5000, 704), dtype=torch.uint8, device="cuda")
+    before = rows.clone()
+    ids = torch.tensor(sorted(set(np.random.default_rng(1).integers(0, 6000, 900).tolist())), dtype=torch.int32,
+                       device="cuda")
+    sink = torch.full((1,), 7.0, dtype=torch.float32, device="cuda")
+    for wr in (False, True):
+        g.gs_row_probe(ids, ids.numel(), rows, wr, sink)
+    torch.cuda.synchronize()
+    assert torch.equal(rows, before) and float(sink.item()) == 7.0
+
+
 def test_stream_read_probe(g):
     """The measurement helper reads and stores nothing; misaligned or ragged
     sizes are rejected."""
