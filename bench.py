@@ -20,6 +20,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -51,6 +52,12 @@ def parse():
     p.add_argument("--cull-mode", type=int, default=1)
     p.add_argument("--cull-summary", type=int, default=1, choices=[0, 1],
                    help="1: the band cull reads the 16-byte cull summaries; 0: the geometry rows")
+    p.add_argument("--cull-chunks", type=int, default=-1, choices=[-1, 0, 1],
+                   help="chunk records of the summaries (the cull skips chunks whose box is culled): 1 on, "
+                        "0 off, -1 on with rows in Morton order")
+    p.add_argument("--spatial-line", type=int, default=1, choices=[0, 1],
+                   help="with rows in generation order, also time the first state with rows in Morton order "
+                        "and chunk records (reported as spatial_order)")
     p.add_argument("--state", default="f32", choices=["f32", "bf16", "fp8"], help="Adam moment storage (both groups)")
     p.add_argument("--compare-state", default="bf16", choices=["", "f32", "bf16", "fp8"],
                    help="a second moment storage timed on the same scene and reported beside the first")
@@ -339,13 +346,18 @@ def run_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def chunks_on(args):
+    """Chunk records: as asked, or by default with rows in Morton order."""
+    return bool(args.cull_chunks) if args.cull_chunks >= 0 else args.order == "morton"
+
+
 def config_key(args, workload, state=None):
     """Names the launch configuration a counter summary was taken with."""
     st = state or args.state
     summ = args.cull_summary and args.cull_mode == 1 and args.geo_mode == 0
     return (f"{workload}/{st}/{args.geo_state or st}/{args.layout}/cull{args.cull_mode}"
             f"/geo{args.geo_mode}/K{args.max_defer}/tilt{args.tilt.replace(',', '-')}/{args.order}"
-            f"/sum{int(bool(summ))}")
+            f"/sum{int(bool(summ))}" + ("/chunks" if summ and chunks_on(args) else ""))
 
 
 def host_cpu():
@@ -365,20 +377,24 @@ def host_cpu():
     return model, nodes
 
 
-def step_bytes(n, M, R, geo_state, app_state, geo_mode, summary=0):
+def step_bytes(n, M, R, geo_state, app_state, geo_mode, summary=0, chunk_skip=None):
     """Algorithmic bytes of one step per call (sg / sa: bytes per stored moment
     of G / A): cull 44 per Gaussian (geometry row + last step) + 20 sg per
     restored row + 4 per visible id, or with cull summaries `summary` bytes per
     Gaussian (16, or 20 with the last step past 2^16 steps) + (4 + 40 + 20 sg)
     per restored row (last step, geometry row and moments; undecided rows that
-    need no restore are not counted) + 4 per visible id; gather id + last step
+    need no restore are not counted) + 4 per visible id; with chunk records
+    (chunk_skip: the fraction of chunks skipped) 32 per 1024-row chunk + the
+    summaries of the chunks not skipped; gather id + last step
     + G w, m, v + A w, m, v + the 236-byte output row; Adam id + last step
     read and write + per column w, g read, w written and m, v read and written
     (+ the 16-byte summary written)."""
     msz = {"f32": 4, "bf16": 2, "fp8": 1}
     sg, sa = msz[geo_state], msz[app_state]
     gcols = 0 if geo_mode else 10                       # G columns handled by the sparse kernels
-    if summary:
+    if summary and chunk_skip is not None:
+        cull = 32.0 * math.ceil(n / 1024) + float(summary) * n * (1.0 - chunk_skip) + (44.0 + 20.0 * sg) * R + 4.0 * M
+    elif summary:
         cull = float(summary) * n + (44.0 + 20.0 * sg) * R + 4.0 * M
     else:
         cull = 44.0 * n + 20.0 * sg * R + 4.0 * M
@@ -405,7 +421,8 @@ def run_single(args, w, geo0, app0, state, tilt, on_dev):
     model = gsdp.Model(geo_in, app0, lg, la, max_steps=2 * total_steps + 8, max_defer=args.max_defer,
                        cull_mode=args.cull_mode, app_layout=args.layout, geo_state=geo_state,
                        app_state=state, geo_mode=args.geo_mode, sr_seed=9,
-                       cull_summary=None if args.cull_summary else False)
+                       cull_summary=None if args.cull_summary else False,
+                       cull_chunks=chunks_on(args))
     summ = model.cull_sum is not None
     sum_bytes = (16 if model.max_steps <= 65536 else 20) if summ else 0
     del geo_in
@@ -457,6 +474,17 @@ def run_single(args, w, geo0, app0, state, tilt, on_dev):
     if h1["error"]:
         raise RuntimeError(f"cull reported an error flag: {h1}")
     ms_step = (t1 - t0) * 1e3 / args.steps
+    # the chunks the summary cull skipped at each timed step (decided again
+    # after the timed steps, from the records as they are then)
+    chunk_skip = None
+    if summ and model.cull_chunk is not None and args.max_defer == 0:
+        fl = torch.zeros(model.cull_chunk.shape[0], dtype=torch.uint8, device=dev)
+        fr = []
+        for k in range(args.steps):
+            t = args.warmup + 1 + k
+            gsdp.gs_cull_chunk_flags(model, cams[t - 1], t, fl, stream=stream)
+            fr.append(fl.float().mean())
+        chunk_skip = float(torch.stack(fr).mean().item())
 
     # the hardware's bandwidth for the last step's visible rows of the fused
     # state: loads, and loads with unchanged stores (gs_row_probe)
@@ -537,7 +565,7 @@ def run_single(args, w, geo0, app0, state, tilt, on_dev):
     M = vis_total / args.steps
     R = rest_total / args.steps
     f = M / n
-    by = step_bytes(n, M, R, geo_state, state, args.geo_mode, sum_bytes)
+    by = step_bytes(n, M, R, geo_state, state, args.geo_mode, sum_bytes, chunk_skip)
     kernels = {k: (float(ms), by[k]) for k, ms in (("cull", cull_ms), ("gather", gather_ms), ("adam", adam_ms))}
     dom = max(kernels, key=lambda k: kernels[k][0])
     sym = "cull_sum" if (dom == "cull" and summ) else dom   # the launches of the dominant call
@@ -556,7 +584,8 @@ def run_single(args, w, geo0, app0, state, tilt, on_dev):
                    "visible_fraction": f, "visible_per_step": M, "restored_per_step": R,
                    "state": state, "geo_state": geo_state, "app_layout": args.layout,
                    "max_defer": args.max_defer, "cull_mode": args.cull_mode, "geo_mode": args.geo_mode,
-                   "cull_summary": summ, "cull_bytes_per_row": sum_bytes or 44},
+                   "cull_summary": summ, "cull_bytes_per_row": sum_bytes or 44,
+                   "cull_chunks": model.cull_chunk is not None, "chunks_skipped": chunk_skip},
         "kernels_ms": {k: v[0] for k, v in kernels.items()},
         "graph_ms_per_step": graph_ms,
         "kernels_gbs": {k: v[1] / (v[0] * 1e-3) / 1e9 for k, v in kernels.items()},
@@ -650,6 +679,26 @@ def main():
     out["stream_probe"] = {"what": "streaming read of the [n][10] geometry array", "bytes": flat.numel() * 4,
                            "gbs": probe_gbs, "frac_of_peak": probe_gbs / HBM_PEAK_GBS}
     del gflat, flat
+    if args.spatial_line and args.order == "generated":
+        # the same scene with its rows sorted by the Morton code of their
+        # position, the first state, chunk records on
+        sp = argparse.Namespace(**vars(args))
+        sp.order, sp.cull_chunks = "morton", 1
+        perm = morton_order(torch.as_tensor(geo0)[:, :3], w.scene_box)
+        g_s = torch.as_tensor(geo0)[perm.to(torch.as_tensor(geo0).device)].contiguous()
+        a_s = torch.as_tensor(app0)[perm.to(torch.as_tensor(app0).device)].contiguous()
+        del perm
+        rec = run_single(sp, w, g_s, a_s, args.state, tilt, on_dev)
+        del g_s, a_s
+        keep = ("value", "ms_per_step", "step_ms", "value_p50", "kernels_ms", "kernels_gbs", "roofline",
+                "step_roofline")
+        out["spatial_order"] = {"what": "the same scene and cameras with the rows sorted by the Morton code of "
+                                        "their position (done before the timed steps) and chunk records on",
+                                **{k: rec[k] for k in keep},
+                                "config": {k: rec["config"][k] for k in ("row_order", "state", "cull_chunks",
+                                                                         "chunks_skipped", "visible_per_step",
+                                                                         "restored_per_step")}}
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, geo0, app0, args.cpu_sample, args.cpu_steps, *gi.lr_columns())
     print(json.dumps(out), flush=True)

@@ -105,6 +105,9 @@ typedef struct gs_model {
     int32_t reserved_;
     float *cull_sum;       /* optional device [n][4], 16-byte aligned: the cull summary of each
                               row (see gs_cull_summary_build), or NULL */
+    float *cull_chunk;     /* optional device [ceil(n / GS_CHUNK_ROWS)][8], 32-byte aligned:
+                              bounds of the summaries of each chunk of rows (see
+                              gs_cull_summary_build), or NULL; needs cull_sum */
 } gs_model;
 
 /* Optimizers.  GS_OPT_SGD_MOMENTUM is the momentum-optimizer extension the
@@ -237,7 +240,7 @@ int gs_cull(const gs_model *model, const gs_camera *cam, int64_t step, uint32_t 
  * memory of each GPU it runs on until the process ends, instead of `ws`.
  * Calls no allocating routine.
  *   - Limit: the model's workspace (gs_workspace_bytes with max_defer = 0)
- *     must fit the array, about 97M Gaussians; larger models get GS_ESPACE
+ *     must fit the array, about 95M Gaussians; larger models get GS_ESPACE
  *     (text in gs_last_hip_error).
  *   - max_defer > 0 and geo_mode = 1 return GS_EUNSUPPORTED: the update that
  *     follows those culls reads the cull's workspace, which the caller cannot
@@ -269,6 +272,31 @@ int gs_cull_noalloc(const gs_model *model, const gs_camera *cam, int64_t step, u
  * model->last_step.  Not available with geo_mode 1 (GS_EUNSUPPORTED from
  * every call).  GS_EINVAL when cull_sum is NULL. */
 int gs_cull_summary_build(const gs_model *model, void *stream);
+
+/* Chunk bounds of the summaries (a data layout of this library, not of the
+ * paper).  Rows i with i / GS_CHUNK_ROWS = c form chunk c.  When
+ * model->cull_chunk is also set, record c = cull_chunk[8c .. 8c+8) holds
+ * (lo_x, lo_y, lo_z, s_c, hi_x, hi_y, hi_z, 0): every summary centre of the
+ * chunk lies in the box [lo, hi], and every summary s of the chunk (the high
+ * 16 bits of w as an FP32 value) is at most s_c; s_c is a NaN when some row's
+ * summary is.  With max_defer = 0 the summary cull first tests a chunk's box,
+ * widened by the largest drift and footprint any of its rows can have at
+ * this step, against the camera, and skips the chunk's rows when the test
+ * shows that every one of them is culled (same visible list).  With rows in
+ * a spatial order (for instance sorted by the Morton code of their centre)
+ * most chunks of a camera that sees a small part of the scene are skipped.
+ * The calls that store summaries widen the records of the rows they write
+ * (records only grow); gs_cull_summary_build also recomputes every record
+ * tightly from the summaries. */
+#define GS_CHUNK_ROWS 1024
+
+/* The summary cull's chunk decisions for a camera (a diagnostic): flags[c] =
+ * 1 when gs_cull(model, cam, step, ...) skips chunk c (its record shows
+ * every row culled), else 0, for c < ceil(n / GS_CHUNK_ROWS); flags is
+ * device memory.  GS_EUNSUPPORTED unless the summary cull runs with chunk
+ * records: cull_mode = 1, eps > 0, Adam, geo_mode = 0, max_defer = 0,
+ * cull_sum and cull_chunk set. */
+int gs_cull_chunk_flags(const gs_model *model, const gs_camera *cam, int64_t step, uint8_t *flags, void *stream);
 
 /* gs_cull with the camera taken from device memory: record (t - 1) % n_cams
  * of `cams` (n_cams records from gs_camera_pack, uploaded by the caller,

@@ -49,6 +49,8 @@ using u64 = unsigned long long;
 using gsdp::kCullBlock;
 using gsdp::kCullIpt;
 using gsdp::kCullTile;
+using gsdp::kChunkRows;
+static_assert(kChunkRows == GS_CHUNK_ROWS, "chunk size of the public header");
 
 namespace {
 
@@ -625,13 +627,62 @@ __device__ __forceinline__ RowPre classify_pre_sum(const float4 &v, float wd, co
 // Store the summary of a row whose new geometric values sit in lanes 0..9 of
 // the wavefront (value x of this lane) and whose last step becomes `last`;
 // every lane of the wavefront takes part, lane 0 stores.
-__device__ __forceinline__ void cull_summary_store_wave(float4 *sum, u32 row, float x, int last)
+__device__ __forceinline__ float4 cull_summary_store_wave(float4 *sum, u32 row, float x, int last)
 {
     float g[10];
 #pragma unroll
     for (int j = 0; j < 10; ++j) g[j] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), j));
     const float4 v = cull_summary(g, last);
     if ((threadIdx.x & 63) == 0) sum[row] = v;
+    return v;
+}
+
+// Chunk records: rows [c * kChunkRows, (c + 1) * kChunkRows) share record c
+// of 8 floats (lo x, y, z, s, hi x, y, z, 0): the box of their summary
+// centres and the largest summary s (a NaN when some row's is).  Writers of
+// summaries widen records with float minima and maxima taken through integer
+// atomics: non-negative floats order as their bits read as signed integers,
+// negative ones in reverse as unsigned integers; a positive NaN (the
+// summaries' 0x7fc0 code) is above every float as a signed integer and below
+// every negative one as an unsigned integer, so a NaN s stays once stored.
+// -0 is stored as +0.
+__device__ __forceinline__ void fatomic_min(float *p, float v)
+{
+    v = v == 0.0f ? 0.0f : v;
+    if (v >= 0.0f) atomicMin(reinterpret_cast<int *>(p), __float_as_int(v));
+    else atomicMax(reinterpret_cast<unsigned int *>(p), __float_as_uint(v));
+}
+__device__ __forceinline__ void fatomic_max(float *p, float v)
+{
+    v = v == 0.0f ? 0.0f : v;
+    if (!(v < 0.0f)) atomicMax(reinterpret_cast<int *>(p), __float_as_int(v));
+    else atomicMin(reinterpret_cast<unsigned int *>(p), __float_as_uint(v));
+}
+
+// Element lane & 7 of the chunk record of `row` (every lane loads; lanes
+// past 7 repeat the first eight, so the wavefront reads one 32-byte record).
+__device__ __forceinline__ float chunk_rec_lane(const float *chunk, u32 row)
+{
+    return chunk[(size_t)(row / (u32)kChunkRows) * 8u + (threadIdx.x & 7u)];
+}
+
+// Widen the chunk record of `row` to hold its new summary v (uniform over the
+// wavefront); rec: this lane's element from chunk_rec_lane, loaded earlier in
+// the same launch (records only grow, so an older value is never too wide).
+// Lane j < 7 checks element j and widens it only when v lies outside.
+__device__ __forceinline__ void chunk_widen(float *chunk, u32 row, const float4 &v, float rec)
+{
+    const u32 lane = threadIdx.x & 63u;
+    const float sv = __uint_as_float(__float_as_uint(v.w) & 0xffff0000u);
+    const u32 e = lane < 3u ? lane : (lane < 4u ? 3u : lane - 4u);
+    const float x = lane == 3u ? sv : (e == 0u ? v.x : (e == 1u ? v.y : v.z));
+    const bool low = lane < 3u;
+    const bool need = lane < 7u && (low ? !(x >= rec) : !(x <= rec));
+    if (need) {
+        float *p = chunk + (size_t)(row / (u32)kChunkRows) * 8u + lane;
+        if (low) fatomic_min(p, x);
+        else fatomic_max(p, x);
+    }
 }
 
 // Bounds of a group of rows (a wavefront's) that classify_cam evaluates:
@@ -801,6 +852,8 @@ struct CullArgs {
     SideK side;                      // side_out constants (k_cull_sum)
     const CamPack *cams;             // camera table (k_cull_sum<..., true>): record (t - 1) % n_cams
     int32_t n_cams, pad9;
+    const float4 *chunk;             // [chunks][2] chunk records (k_chunk_scan), or null
+    u32 *chunk_flags;                // [chunks] k_chunk_scan's decisions (k_cull_sum), or null
 };
 
 // Seven blocks per CU (the LDS tiles allow seven): the register budget this
@@ -980,6 +1033,35 @@ __global__ __launch_bounds__(kCullBlock, 7) void k_cull(CullArgs a)
 // loads each one's geometry row, restores it when deferred and takes the
 // exact test.  Same outputs as k_cull, tile by tile.
 constexpr int kCullSumTiles = 2;      // tiles of a k_cull_sum block (of 1, 2, 4, 8 the fastest at 40M rows)
+static_assert(kCullSumTiles * kCullTile == kChunkRows, "a k_cull_sum block covers one chunk");
+
+// True only when every row of a chunk is culled: classify_box returns 0 for
+// each row with the RowPre of its summary at any defer count.  The record's
+// box holds each row's centre, so each |coordinate| is at most the box's mu;
+// each row's drift bound (kpos W + 1e-6 mu, W <= wbound) is at most the one
+// formed from wbound and the box's mu; each row's largest log-scale after the
+// restore (s + kscl W) is at most the record's s + kscl wbound, below 79 (so
+// no row is undecidable) and widened by 1e-4 before the exponential.
+// wave_sure_out then bounds what classify_box computes for each row.
+__device__ __forceinline__ bool chunk_sure_out(const float4 &c0, const float4 &c1, float wbound, const CamK &cam,
+                                               const BandK &band)
+{
+    const float smax = c0.w + band.kscl * wbound;
+    if (!(smax < 79.0f)) return false;
+    WaveBox w;
+    w.lo[0] = c0.x;
+    w.lo[1] = c0.y;
+    w.lo[2] = c0.z;
+    w.hi[0] = c1.x;
+    w.hi[1] = c1.y;
+    w.hi[2] = c1.z;
+    w.mu = fmaxf(fmaxf(fmaxf(fabsf(c0.x), fabsf(c1.x)), fmaxf(fabsf(c0.y), fabsf(c1.y))),
+                 fmaxf(fabsf(c0.z), fabsf(c1.z)));
+    w.dp = band.kpos * wbound + 1e-6f * w.mu;
+    const float sig = __expf(smax + 1e-4f) * 1.001f;
+    w.sig2 = sig * sig;
+    return wave_sure_out(w, cam, band);
+}
 // PACKED (steps up to 2^16): each row's defer count comes from the low 16
 // bits of its summary word, and the last-step array is not read.  CAMDEV:
 // the camera is record (t - 1) % n_cams of a device table (graph replay).
@@ -990,6 +1072,10 @@ __global__ __launch_bounds__(kCullBlock) void k_cull_sum(CullArgs a)
     static_assert(RPT <= 32, "row bits of a thread fit a word");
     __shared__ u32 sCntV[TPB][kCullIpt * 4], sCntS[TPB][kCullIpt * 4];
     __shared__ u32 sRestored[TPB];
+    // a chunk that k_chunk_scan skipped (it wrote the chunk's ballots and
+    // counts, and records a step error): nothing to do; tested first, so the
+    // rows' loads wait for one load only
+    if (a.chunk_flags && a.chunk_flags[blockIdx.x]) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t tile0 = (int64_t)blockIdx.x * TPB;
     const float *Wrow;
@@ -1172,6 +1258,118 @@ __global__ __launch_bounds__(256) void k_cull_summary_build(const float *gw, con
         }
         sum[r] = cull_summary(g, last[r]);
     }
+}
+
+// Chunk records of the summaries, tight: one block per chunk, four rows a
+// thread; the box of the centres and the largest s, a NaN s when any row's
+// summary s is a NaN (then its centre may be anything, and is left out).
+__global__ __launch_bounds__(256) void k_cull_chunk_build(const float4 *sum, int64_t n, float *chunk)
+{
+    __shared__ float sRed[4][8];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t r0 = (int64_t)blockIdx.x * kChunkRows;
+    const float inf = __builtin_huge_valf();
+    float lo[3] = {inf, inf, inf}, hi[3] = {-inf, -inf, -inf}, smax = -inf;
+    bool bad = false;
+#pragma unroll
+    for (int k = 0; k < kChunkRows / 256; ++k) {
+        const int64_t r = r0 + k * 256 + tid;
+        if (r < n) {
+            const float4 v = sum[r];
+            const float sv = __uint_as_float(__float_as_uint(v.w) & 0xffff0000u);
+            if (sv == sv) {
+                lo[0] = fminf(lo[0], v.x);
+                lo[1] = fminf(lo[1], v.y);
+                lo[2] = fminf(lo[2], v.z);
+                hi[0] = fmaxf(hi[0], v.x);
+                hi[1] = fmaxf(hi[1], v.y);
+                hi[2] = fmaxf(hi[2], v.z);
+                smax = fmaxf(smax, sv);
+            } else {
+                bad = true;
+            }
+        }
+    }
+    const bool any_bad = __ballot(bad) != 0ull;
+    float red[8];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        red[i] = wave_min(lo[i]);
+        red[4 + i] = wave_max(hi[i]);
+    }
+    red[3] = any_bad ? __builtin_nanf("") : wave_max(smax);
+    red[7] = 0.0f;
+    if (lane == 0)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) sRed[wave][i] = red[i];
+    __syncthreads();
+    if (tid < 8) {
+        float x = sRed[0][tid];
+#pragma unroll
+        for (int w = 1; w < 4; ++w) {
+            const float y = sRed[w][tid];
+            if (tid == 3) x = (x != x || y != y) ? __builtin_nanf("") : fmaxf(x, y);
+            else if (tid < 3) x = fminf(x, y);
+            else if (tid < 7) x = fmaxf(x, y);
+        }
+        chunk[blockIdx.x * 8ull + tid] = x;
+    }
+}
+
+// The summary cull's chunk decisions, one thread a chunk, launched before
+// k_cull_sum (with max_defer 0 and chunk records): flags[c] = 1 when chunk
+// c's record shows every row culled; this thread then writes the zero
+// ballots and counts of the chunk's tiles, and block c of k_cull_sum returns
+// at once.  (One launch over the chunks costs less than the test in every
+// k_cull_sum block, which would hold back the block's loads.)
+template <bool CAMDEV>
+__global__ __launch_bounds__(256) void k_chunk_scan(CullArgs a)
+{
+    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t chunks = (a.tiles + kCullSumTiles - 1) / kCullSumTiles;
+    const float *Wrow;
+    int dmax, step_err;
+    const int t = resolve_step(a.step, 0, &Wrow, &dmax, &step_err);
+    CamK cam;
+    BandK band;
+    if (CAMDEV) {
+        const CamPack &cp = a.cams[(t - 1) % a.n_cams];
+        cam = cp.cam;
+        band = cp.band;
+    } else {
+        cam = a.cam;
+        band = a.band;
+    }
+    const float wbound = a.step.hdr->wbound;
+    if (c >= chunks) return;
+    const bool skip = chunk_sure_out(a.chunk[2 * c], a.chunk[2 * c + 1], wbound, cam, band);
+    a.chunk_flags[c] = skip ? 1u : 0u;
+    // (the error is the same in every thread; k_cull_sum's skipped blocks do
+    // not record it)
+    if (c == 0) step_flag(a.step, step_err);
+    if (!skip) return;
+#pragma unroll
+    for (int j = 0; j < kCullSumTiles; ++j) {
+        const int64_t tile = c * kCullSumTiles + j;
+        if (tile < a.tiles) {
+            ulonglong2 *kb = reinterpret_cast<ulonglong2 *>(a.keep_bits + tile * gsdp::kWordsPerTile);
+#pragma unroll
+            for (int w = 0; w < gsdp::kWordsPerTile / 2; ++w) kb[w] = make_ulonglong2(0ull, 0ull);
+            a.tile_vs[tile] = 0ull;
+            a.tile_rest[tile] = 0u;
+        }
+    }
+}
+
+// flags[c] = 1 when the summary cull skips chunk c for this camera (the
+// decision k_chunk_scan takes), one thread a chunk.
+__global__ __launch_bounds__(256) void k_chunk_flags(const float4 *chunk, int64_t chunks,
+                                                     const gsdp::LutHeader *hdr, CamK cam, BandK band,
+                                                     uint8_t *flags)
+{
+    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (c >= chunks) return;
+    flags[c] = (uint8_t)chunk_sure_out(chunk[2 * c], chunk[2 * c + 1], hdr->wbound, cam, band);
 }
 
 // Block scans used by the one-block counter scans of the batched cull and of
@@ -1491,6 +1689,7 @@ struct RowArgs {
     u32 fz_s, fz_ogm, fz_ogv, fz_oam, fz_oav, pad8;
     LutAdv adv;                      // kAdam: the tables' advance to the next step
     float4 *cull_sum;                // [n] cull summaries kept current (or null)
+    float *cull_chunk;               // their chunk records, widened (or null)
 };
 
 // One wavefront per Gaussian row: lane c < 10 owns G column c, lane 10+c owns
@@ -1653,6 +1852,7 @@ __device__ __forceinline__ void rows_work(const RowArgs &a, const int t, const f
         // gradient rows of the iteration are consecutive, at constant offsets
         // from the first.
         gchar *rA[kRU], *rG[kRU];
+        float crec[kRU];                 // chunk record elements (summary writers)
         gchar *const cG = srow(a.g_geo, base, 40u), *const cA = srow(a.g_app, base, sAG);
 #pragma unroll
         for (int u = 0; u < kRU; ++u) {
@@ -1686,7 +1886,9 @@ __device__ __forceinline__ void rows_work(const RowArgs &a, const int t, const f
             // rows are deferred); the flush only those it catches up
             const bool ldm = MODE == kAdam || MODE == kAdamMax || MODE == kGather || d[u] > 0;
             const bool ldg = (MODE == kAdam || MODE == kAdamMax) && base + u < nvis;
+            crec[u] = 0.0f;
             if (!need) continue;
+            if ((MODE == kAdam || MODE == kFlush) && a.cull_chunk) crec[u] = chunk_rec_lane(a.cull_chunk, id[u]);
             // (with dense geometry the G moments are current: loading them is
             // harmless, and no lane mask is needed)
             if (FZ && ldm) {
@@ -1884,7 +2086,10 @@ __device__ __forceinline__ void rows_work(const RowArgs &a, const int t, const f
                     asm volatile("; A columns");
                 }
             }
-            if (a.cull_sum) cull_summary_store_wave(a.cull_sum, r, xs, t);
+            if (a.cull_sum) {
+                const float4 sv = cull_summary_store_wave(a.cull_sum, r, xs, t);
+                if (a.cull_chunk) chunk_widen(a.cull_chunk, r, sv, crec[u]);
+            }
             if (lane == 0) a.last[r] = t;
         }
         if (MODE == kAdamMax && lane == 0) {
@@ -1967,6 +2172,7 @@ struct FastArgs {
     u32 om, ov, pad0, pad1;          // byte offsets of the G m and G v runs in the fused row
     LutAdv adv;                      // kAdam: the tables' advance to the next step
     float4 *cull_sum;                // [n] cull summaries kept current (or null)
+    float *cull_chunk;               // their chunk records, widened (or null)
 };
 
 // Pointers into the global and the constant address space: global loads and
@@ -2060,8 +2266,11 @@ __device__ __forceinline__ void rows_fz_work(const FastArgs &a, const int t, con
         typename RawT<ST>::T mr[RU], vr[RU];
         gfloat *wa[RU];
         gchar *fb[RU];
+        float crec[RU];                  // chunk record elements (the update)
 #pragma unroll
         for (int u = 0; u < RU; ++u) {
+            crec[u] = 0.0f;
+            if (MODE == kAdam && a.cull_chunk) crec[u] = chunk_rec_lane(a.cull_chunk, id[u]);
             wa[u] = gptr(wb + (u64)id[u] * (u64)wst);
             fb[u] = srow(a.fz, id[u], a.fz_s);
             wr[u] = __float_as_uint(*wa[u]);
@@ -2108,7 +2317,10 @@ __device__ __forceinline__ void rows_fz_work(const FastArgs &a, const int t, con
                     mstore<ST>((char *)(fb[u] + lane_off(mo)), 0.0f, m1, rm, false);
                     mstore<ST>((char *)(fb[u] + lane_off(vo)), 0.0f, v1, rv, true);
                 }
-                if (a.cull_sum) cull_summary_store_wave(a.cull_sum, id[u], x, t);
+                if (a.cull_sum) {
+                    const float4 sv = cull_summary_store_wave(a.cull_sum, id[u], x, t);
+                    if (a.cull_chunk) chunk_widen(a.cull_chunk, id[u], sv, crec[u]);
+                }
                 if (lane == 0) a.last[id[u]] = t;
             }
         }
@@ -2439,6 +2651,7 @@ int check_model(const gs_model *m)
     // summaries stay current only where the row kernels store the geometry
     if (m->cull_sum && !aligned(m->cull_sum, 16)) return GS_EINVAL;
     if (m->cull_sum && m->geo_mode != 0) return GS_EUNSUPPORTED;
+    if (m->cull_chunk && (!m->cull_sum || !aligned(m->cull_chunk, 32))) return GS_EINVAL;
     return GS_OK;
 }
 
@@ -2595,6 +2808,7 @@ void fill_rows(RowArgs &a, const gs_model *m)
     a.last = m->last_step;
     a.n = m->n;
     a.cull_sum = reinterpret_cast<float4 *>(m->cull_sum);
+    a.cull_chunk = m->cull_sum ? m->cull_chunk : nullptr;
 }
 
 // The configuration of k_rows_fz: Adam, both groups' moments in FP32 or both
@@ -2628,6 +2842,7 @@ bool fill_fast(FastArgs &f, const gs_model *m)
     f.om = ogm;
     f.ov = ogv;
     f.cull_sum = reinterpret_cast<float4 *>(m->cull_sum);
+    f.cull_chunk = m->cull_sum ? m->cull_chunk : nullptr;
     return true;
 }
 
@@ -3885,6 +4100,28 @@ int gs_cull_table(const gs_model *model, const void *cams, int32_t n_cams, int64
                        cams, n_cams);
 }
 
+int gs_cull_chunk_flags(const gs_model *model, const gs_camera *cam, int64_t step, uint8_t *flags, void *stream)
+{
+    int rc = check_model(model);
+    if (rc) return rc;
+    if (!cam || (model->n > 0 && !flags)) return GS_EINVAL;
+    if (!step_ok(model, step)) return GS_EINVAL;
+    if (!(cam->fx > 0.0f && cam->fy > 0.0f) || cam->width <= 0 || cam->height <= 0) return GS_EINVAL;
+    const bool band = model->cull_mode == 1 && model->eps > 0.0 && std::isfinite(restore_bound(model->beta1, model->beta2));
+    if (!band || !model->cull_sum || !model->cull_chunk || model->geo_mode != 0 || model->optimizer != GS_OPT_ADAM ||
+        model->max_defer != 0)
+        return GS_EUNSUPPORTED;
+    if (model->n == 0) return GS_OK;
+    CamK ck;
+    BandK bk;
+    pack_camera(model, cam, ck, bk);
+    const int64_t chunks = (model->n + kChunkRows - 1) / kChunkRows;
+    hipLaunchKernelGGL(k_chunk_flags, dim3((unsigned)((chunks + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
+                       reinterpret_cast<const float4 *>(model->cull_chunk), chunks, step_k(model, step).hdr, ck, bk,
+                       flags);
+    return launched("gs_cull_chunk_flags");
+}
+
 int gs_cull_noalloc(const gs_model *model, const gs_camera *cam, int64_t step, uint32_t *ids, uint32_t *count_dev,
                     uint32_t capacity, void *stream)
 {
@@ -3918,7 +4155,12 @@ int gs_cull_summary_build(const gs_model *model, void *stream)
     const int64_t blocks = std::min<int64_t>((model->n + 255) / 256, (int64_t)(cu > 0 ? cu : 256) * 16);
     hipLaunchKernelGGL(k_cull_summary_build, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, model->geo.w,
                        model->last_step, reinterpret_cast<float4 *>(model->cull_sum), model->n);
-    return launched("gs_cull_summary_build");
+    rc = launched("gs_cull_summary_build");
+    if (rc || !model->cull_chunk) return rc;
+    const int64_t chunks = (model->n + kChunkRows - 1) / kChunkRows;
+    hipLaunchKernelGGL(k_cull_chunk_build, dim3((unsigned)chunks), dim3(256), 0, (hipStream_t)stream,
+                       reinterpret_cast<const float4 *>(model->cull_sum), model->n, model->cull_chunk);
+    return launched("gs_cull_summary_build (chunks)");
 }
 
 }  // extern "C"
@@ -3990,6 +4232,8 @@ int cull_launch(const gs_model *model, const gs_camera *cam, int64_t step, uint3
     a.sat_bits = model->max_defer > 0 ? reinterpret_cast<u64 *>(wsb + gsdp::ws_satbits_offset(n)) : nullptr;
     if (a.tiles > 0x7fffffff) return GS_EINVAL;
     a.sum = reinterpret_cast<const float4 *>(model->cull_sum);
+    a.chunk = (model->cull_sum && model->max_defer == 0) ? reinterpret_cast<const float4 *>(model->cull_chunk)
+                                                          : nullptr;
     if (a.cams && !(a.mode == 1 && a.sum && !a.geo_dense)) return GS_EUNSUPPORTED;
     if (a.tiles > 0) {
         if (a.mode == 1 && a.sum && !a.geo_dense) {
@@ -3997,6 +4241,12 @@ int cull_launch(const gs_model *model, const gs_camera *cam, int64_t step, uint3
             const unsigned blocks = (unsigned)((a.tiles + kCullSumTiles - 1) / kCullSumTiles);
             const bool packed = model->lut_max_steps <= 65536;
             const bool nt = (int64_t)n * (packed ? 16 : 20) > kLastLevelCacheBytes;
+            if (a.chunk) {
+                a.chunk_flags = reinterpret_cast<u32 *>(wsb + gsdp::ws_chunk_offset(n, model->max_defer));
+                const unsigned cb = (unsigned)((gsdp::cull_chunks(n) + 255) / 256);
+                if (a.cams) hipLaunchKernelGGL(k_chunk_scan<true>, dim3(cb), dim3(256), 0, st, a);
+                else hipLaunchKernelGGL(k_chunk_scan<false>, dim3(cb), dim3(256), 0, st, a);
+            }
             launch_cull_sum(nt, packed, a.cams != nullptr, blocks, st, a);
         } else if ((int64_t)n * 44 > kLastLevelCacheBytes) {
             // geometry and last step: 44 bytes a row

@@ -92,7 +92,8 @@ constexpr int kCullTile = kCullBlock * kCullIpt;
 // Workspace layout (bytes): header | tile counts (u64 visible<<32|saturated, then
 // u32 restored) | tile prefixes (u64) | group sums [groups][2] (u64) | keep ballots
 // [tiles][8] (u64) | saturated ballots [tiles][8] (u64, max_defer > 0) |
-// saturated ids [n] (u32, max_defer > 0) | FP8 block maxima and task list
+// saturated ids [n] (u32, max_defer > 0) | chunk decisions [chunks] (u32) |
+// FP8 block maxima and task list
 constexpr int64_t kWsHeader = 256;
 struct WsHeader {
     uint32_t vis_total;      // visible rows of the last cull
@@ -106,6 +107,8 @@ static_assert(sizeof(WsHeader) == 32, "workspace header layout");
 
 inline int64_t cull_tiles(int64_t n) { return (n + kCullTile - 1) / kCullTile; }
 constexpr int kWordsPerTile = kCullTile / 64;
+// rows of a chunk of the cull summaries' chunk records (GS_CHUNK_ROWS)
+constexpr int kChunkRows = 1024;
 inline int64_t ws_cnt_offset(int64_t) { return kWsHeader; }
 inline int64_t ws_off_offset(int64_t n) { return kWsHeader + 16 * cull_tiles(n); }
 // groups of kGroupTiles tiles: per-group sums of (visible, saturated) and restored
@@ -118,10 +121,17 @@ inline int64_t ws_sat_offset(int64_t n, int32_t K)
 {
     return ws_satbits_offset(n) + (K > 0 ? 8 * kWordsPerTile * cull_tiles(n) : 0);
 }
+// the summary cull's chunk decisions (u32 per chunk of kChunkRows rows)
+inline int64_t cull_chunks(int64_t n) { return (n + kChunkRows - 1) / kChunkRows; }
+inline int64_t ws_chunk_offset(int64_t n, int32_t K)
+{
+    const int64_t b = ws_sat_offset(n, K) + (K > 0 ? 4 * n : 0);
+    return (b + 15) / 16 * 16;
+}
 inline int64_t fp8_blocks(int64_t n) { return (n + 127) / 128; }
 inline int64_t ws_fp8_offset(int64_t n, int32_t K)
 {
-    const int64_t b = ws_sat_offset(n, K) + (K > 0 ? 4 * n : 0);
+    const int64_t b = ws_chunk_offset(n, K) + 4 * cull_chunks(n);
     return (b + 7) / 8 * 8;
 }
 // fp8: per-block max arrays for G m, G v, A m, A v (u32 each), the list of

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(PKG, "libgsdp.so")
 GS_OK, GS_EINVAL, GS_EHIP, GS_EUNSUPPORTED, GS_ESPACE = 0, -1, -2, -3, -4
 GS_F32, GS_BF16, GS_FP8E4M3 = 0, 1, 2
 GS_OPT_ADAM, GS_OPT_ADAMW, GS_OPT_SGD_MOMENTUM = 0, 1, 2
+GS_CHUNK_ROWS = 1024
 
 # exported C symbols (kept in sync with include/gsdp.h)
 SYMBOLS = ("gs_lut_bytes", "gs_lut_build", "gs_lut_build_host", "gs_lut_build_schedule",
@@ -30,7 +31,8 @@ SYMBOLS = ("gs_lut_bytes", "gs_lut_build", "gs_lut_build_host", "gs_lut_build_sc
            "gs_cull_multi_autotune", "gs_grad_sum_multi", "gs_plan_image_split", "gs_lut_build_sgd_momentum",
            "gs_lut_build_sgd_momentum_host", "gs_lut_bytes_adamw", "gs_lut_build_adamw", "gs_lut_build_adamw_host",
            "gs_densify_workspace_bytes", "gs_densify_plan", "gs_densify_apply", "gs_cull_noalloc",
-           "gs_lut_seek", "gs_lut_seek_host", "gs_cull_summary_build", "gs_cull_table", "gs_row_probe")
+           "gs_lut_seek", "gs_lut_seek_host", "gs_cull_summary_build", "gs_cull_table", "gs_row_probe",
+           "gs_cull_chunk_flags")
 
 
 class GsCamera(C.Structure):
@@ -52,7 +54,7 @@ class GsModel(C.Structure):
                 ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double),
                 ("cull_mode", C.c_int32), ("geo_mode", C.c_int32), ("sr_seed", C.c_uint64),
                 ("step_dev", C.c_void_p), ("optimizer", C.c_int32), ("reserved_", C.c_int32),
-                ("cull_sum", C.c_void_p)]
+                ("cull_sum", C.c_void_p), ("cull_chunk", C.c_void_p)]
 
 
 class GsMulti(C.Structure):
@@ -90,6 +92,7 @@ def _load():
         "gs_cull": (C.c_int, [P(GsModel), P(GsCamera), i64, vp, vp, u32, vp, sz, vp]),
         "gs_cull_noalloc": (C.c_int, [P(GsModel), P(GsCamera), i64, vp, vp, u32, vp]),
         "gs_cull_summary_build": (C.c_int, [P(GsModel), vp]),
+        "gs_cull_chunk_flags": (C.c_int, [P(GsModel), P(GsCamera), i64, vp, vp]),
         "gs_cull_table": (C.c_int, [P(GsModel), vp, i32, i64, vp, vp, u32, vp, sz, vp]),
         "gs_row_probe": (C.c_int, [vp, u32, vp, u64, u32, i32, vp, vp]),
         "gs_gather": (C.c_int, [P(GsModel), i64, vp, vp, u32, vp, vp, vp]),
@@ -243,13 +246,14 @@ class Model:
     def __init__(self, geo, app, lr_geo, lr_app, *, beta1=0.9, beta2=0.999, eps=1e-15, max_defer=0,
                  max_steps=1000, cull_mode=0, app_layout="separate", geo_state="f32", app_state="f32",
                  sr_seed=0, geo_mode=0, lr_scale=None, optimizer="adam", weight_decay=0.0, device=None,
-                 cull_summary=None):
+                 cull_summary=None, cull_chunks=False):
         device = device or torch.device("cuda")
         # constructor settings, reused by densify() for the resized model
         self._kw = dict(beta1=beta1, beta2=beta2, eps=eps, max_defer=max_defer, max_steps=max_steps,
                         cull_mode=cull_mode, app_layout=app_layout, geo_state=geo_state, app_state=app_state,
                         sr_seed=sr_seed, geo_mode=geo_mode, lr_scale=lr_scale, optimizer=optimizer,
-                        weight_decay=weight_decay, device=device, cull_summary=cull_summary)
+                        weight_decay=weight_decay, device=device, cull_summary=cull_summary,
+                        cull_chunks=cull_chunks)
         geo = torch.as_tensor(geo, dtype=torch.float32)
         app = torch.as_tensor(app, dtype=torch.float32)
         n, adim = geo.shape[0], app.shape[1]
@@ -370,14 +374,23 @@ class Model:
         if cull_summary:
             self.cull_sum = torch.empty((max(n, 1), 4), dtype=torch.float32, device=device)
             c.cull_sum = self.cull_sum.data_ptr()
+        # their chunk records (32 bytes per GS_CHUNK_ROWS rows): worth it when
+        # the rows are in a spatial order (the cull then skips most chunks);
+        # with rows in no order every chunk's box spans the scene
+        self.cull_chunk = None
+        if cull_chunks and self.cull_sum is not None:
+            self.cull_chunk = torch.empty((max((n + GS_CHUNK_ROWS - 1) // GS_CHUNK_ROWS, 1), 8),
+                                          dtype=torch.float32, device=device)
+            c.cull_chunk = self.cull_chunk.data_ptr()
         self.c = c
         self.ws = torch.zeros(gs_workspace_bytes(self) // 4, dtype=torch.int32, device=device)
         if self.cull_sum is not None:
             self.cull_summary_build()
 
     def cull_summary_build(self, stream=None):
-        """Recompute every row's cull summary from geo_w: needed after geo_w
-        is written other than by this library's calls (which keep them current)."""
+        """Recompute every row's cull summary from geo_w (and the chunk
+        records from the summaries): needed after geo_w is written other than
+        by this library's calls (which keep them current)."""
         _check(lib.gs_cull_summary_build(C.byref(self.c), _stream(stream)), "gs_cull_summary_build")
 
     @property
@@ -452,6 +465,14 @@ def gs_cull_noalloc(model: Model, cam, step: int, ids: torch.Tensor, count: torc
     camc = cam if isinstance(cam, GsCamera) else camera_struct(cam)
     _check(lib.gs_cull_noalloc(C.byref(model.c), C.byref(camc), int(step), _ptr(ids), _ptr(count), cap,
                                _stream(stream)), "gs_cull_noalloc")
+
+
+def gs_cull_chunk_flags(model: Model, cam, step: int, flags: torch.Tensor, stream=None):
+    """flags (uint8, one per chunk of GS_CHUNK_ROWS rows) = 1 where the summary
+    cull skips the chunk for this camera."""
+    camc = cam if isinstance(cam, GsCamera) else camera_struct(cam)
+    _check(lib.gs_cull_chunk_flags(C.byref(model.c), C.byref(camc), int(step), _ptr(flags), _stream(stream)),
+           "gs_cull_chunk_flags")
 
 
 def camera_table(model: Model, cams):

@@ -4,6 +4,8 @@ equal the oracle's independently computed FP32 tables bit for bit."""
 import ctypes as C
 import os
 import re
+import shutil
+import subprocess
 
 import numpy as np
 import pytest
@@ -43,6 +45,34 @@ def test_struct_layouts(gsdp):
     assert C.sizeof(gsdp.GsCamera) == 80
     assert C.sizeof(gsdp.GsGroup) == 3 * 8 + 6 * 4 + 2 * 8 + 64 * 4
     assert gsdp.GsModel.lut_max_steps.offset == 8 + 2 * C.sizeof(gsdp.GsGroup) + 16
+
+
+@pytest.mark.skipif(shutil.which("gcc") is None, reason="needs gcc")
+def test_struct_layouts_match_the_c_header(gsdp, tmp_path):
+    """Sizes and field offsets of the binding's structures equal those a C
+    compiler gives the header's."""
+    fields = {"gs_model": (gsdp.GsModel, ["n", "last_step", "lut", "lut_max_steps", "max_defer", "beta1",
+                                          "cull_mode", "sr_seed", "step_dev", "optimizer", "cull_sum",
+                                          "cull_chunk"]),
+              "gs_group": (gsdp.GsGroup, ["w", "lr"]),
+              "gs_camera": (gsdp.GsCamera, [])}
+    src = ["#include <stdio.h>", "#include <stddef.h>", '#include "gsdp.h"', "int main(void) {"]
+    for cname, (_, names) in fields.items():
+        src.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
+        for f in names:
+            src.append(f'printf("{cname}.{f} %zu\\n", offsetof({cname}, {f}));')
+    src.append('printf("GS_CHUNK_ROWS %d\\n", GS_CHUNK_ROWS); return 0; }')
+    c = tmp_path / "layout.c"
+    c.write_text("\n".join(src) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(c)], check=True)
+    got = dict(line.split() for line in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                           check=True).stdout.splitlines())
+    for cname, (cls, names) in fields.items():
+        assert int(got[cname]) == C.sizeof(cls), cname
+        for f in names:
+            assert int(got[f"{cname}.{f}"]) == getattr(cls, f).offset, f"{cname}.{f}"
+    assert int(got["GS_CHUNK_ROWS"]) == gsdp.GS_CHUNK_ROWS
 
 
 def test_status_strings(gsdp):
@@ -342,11 +372,37 @@ def test_cull_summary_checks_need_no_device(gsdp):
     m.cull_sum = 1 << 20
     m.geo_mode = 1
     assert L.gs_cull_summary_build(C.byref(m), None) == gsdp.GS_EUNSUPPORTED
+    m.geo_mode = 0
+    # chunk records need summaries and 32-byte alignment
+    m.cull_chunk = 1 << 21
+    m.cull_sum = None
+    assert L.gs_cull_summary_build(C.byref(m), None) == gsdp.GS_EINVAL
+    m.cull_sum = 1 << 20
+    m.cull_chunk = (1 << 21) + 16
+    assert L.gs_cull_summary_build(C.byref(m), None) == gsdp.GS_EINVAL
+    m.cull_chunk = None
+    m.geo_mode = 1
     cam = gsdp.GsCamera()
     cam.fx = cam.fy = 1000.0
     cam.width, cam.height = 64, 64
     ids = C.c_void_p(1 << 20)
     assert L.gs_cull_noalloc(C.byref(m), C.byref(cam), 1, ids, ids, 16, None) == gsdp.GS_EUNSUPPORTED
+    # chunk decisions: only where the summary cull runs with chunk records
+    # (cull_mode 0 here, then no records, then a deferral limit); missing
+    # camera or flags
+    m.geo_mode = 0
+    m.cull_chunk = 1 << 21
+    assert L.gs_cull_chunk_flags(C.byref(m), C.byref(cam), 1, ids, None) == gsdp.GS_EUNSUPPORTED
+    m.cull_mode = 1
+    m.cull_chunk = None
+    assert L.gs_cull_chunk_flags(C.byref(m), C.byref(cam), 1, ids, None) == gsdp.GS_EUNSUPPORTED
+    m.cull_chunk = 1 << 21
+    m.max_defer = 15
+    assert L.gs_cull_chunk_flags(C.byref(m), C.byref(cam), 1, ids, None) == gsdp.GS_EUNSUPPORTED
+    m.max_defer = 0
+    assert L.gs_cull_chunk_flags(C.byref(m), None, 1, ids, None) == gsdp.GS_EINVAL
+    assert L.gs_cull_chunk_flags(C.byref(m), C.byref(cam), 1, None, None) == gsdp.GS_EINVAL
+    assert L.gs_cull_chunk_flags(C.byref(m), C.byref(cam), 11, ids, None) == gsdp.GS_EINVAL
 
 
 @pytest.mark.parametrize("kind,max_defer,sched", [("adam", 0, False), ("adam", 15, False), ("adam", 0, True),
