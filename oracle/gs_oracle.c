@@ -1127,29 +1127,34 @@ void orc_lut_adamw_spec(double b1, double b2, double lam, double lr, int64_t t, 
     free(R);
 }
 
-/* FP64 deferred rows (paper order).  Wl, P: per column tables [dim][ldt]. */
+/* Model O2 with decoupled weight decay (AdamW): as orc_deferred_rows_f64,
+ * with the restore of d skipped steps w <- P[d] w - lr Wl[d] m / (sqrt(v) +
+ * eps) (per column tables [dim][ldt]) and the step of update t taken on the
+ * decayed value: w <- (1 - lr s_t lam) w - (lr s_t / (1-b1^t)) m / (sqrt(v) /
+ * sqrt(1-b2^t) + eps), m and v the new moments. */
 void orc_adamw_deferred_rows_f64(int dim, double *w, double *m, double *v, int64_t n_rows, const uint32_t *rows,
                                  const int64_t *d, const double *g, const double *lr, double b1, double b2,
                                  double eps, int64_t t, double s_t, double lam, const double *Wl, const double *P,
-                                 int64_t ldt, const double *mom_lut, const double *var_lut)
+                                 int64_t ldt, const double *m_dec, const double *v_dec)
 {
-    const double bias_correction = sqrt(1.0 - pow(b2, (double)t));
+    const double corr2 = sqrt(1.0 - pow(b2, (double)t));
+    const double corr1 = 1.0 - pow(b1, (double)t);
 #pragma omp parallel for schedule(static)
     for (int64_t j = 0; j < n_rows; ++j) {
-        int64_t id = rows[j];
-        int64_t dj = d[j];
+        const int64_t id = rows[j];
+        const int64_t dj = d[j];
         for (int k = 0; k < dim; ++k) {
-            int64_t e = id * dim + k;
-            double wk = w[e], mk = m[e], vk = v[e], gk = g ? g[j * dim + k] : 0.0;
-            if (dj > 0) wk = P[k * ldt + dj] * wk - (Wl[k * ldt + dj] * lr[k] * mk) / (sqrt(vk) + eps);
-            double m_new = mom_lut[dj] * mk + (1.0 - b1) * gk;
-            double v_new = var_lut[dj] * vk + (1.0 - b2) * gk * gk;
-            double lr_t = lr[k] * s_t;
-            double step_size = lr_t / (1.0 - pow(b1, (double)t));
-            wk = wk * (1.0 - lr_t * lam);
-            w[e] = wk - step_size * m_new / (sqrt(v_new) / bias_correction + eps);
-            m[e] = m_new;
-            v[e] = v_new;
+            const int64_t e = id * dim + k;
+            const double gk = g ? g[j * dim + k] : 0.0;
+            double wk = w[e];
+            if (dj > 0) wk = P[k * ldt + dj] * wk - (Wl[k * ldt + dj] * lr[k] * m[e]) / (sqrt(v[e]) + eps);
+            const double m1 = m_dec[dj] * m[e] + (1.0 - b1) * gk;
+            const double v1 = v_dec[dj] * v[e] + (1.0 - b2) * gk * gk;
+            const double rate = lr[k] * s_t;
+            wk = wk * (1.0 - rate * lam);
+            m[e] = m1;
+            v[e] = v1;
+            w[e] = wk - (rate / corr1) * m1 / (sqrt(v1) / corr2 + eps);
         }
     }
 }
