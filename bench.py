@@ -55,9 +55,9 @@ def parse():
     p.add_argument("--cull-chunks", type=int, default=-1, choices=[-1, 0, 1],
                    help="chunk records of the summaries (the cull skips chunks whose box is culled): 1 on, "
                         "0 off, -1 on with rows in Morton order")
-    p.add_argument("--spatial-line", type=int, default=1, choices=[0, 1],
-                   help="with rows in generation order, also time the first state with rows in Morton order "
-                        "and chunk records (reported as spatial_order)")
+    p.add_argument("--other-order", type=int, default=1, choices=[0, 1],
+                   help="also time the first state with the rows in the other order (reported as "
+                        "generation_order or spatial_order)")
     p.add_argument("--state", default="f32", choices=["f32", "bf16", "fp8"], help="Adam moment storage (both groups)")
     p.add_argument("--compare-state", default="bf16", choices=["", "f32", "bf16", "fp8"],
                    help="a second moment storage timed on the same scene and reported beside the first")
@@ -69,9 +69,10 @@ def parse():
     p.add_argument("--pool", type=int, default=4)
     p.add_argument("--device-scene", type=int, default=None,
                    help="1 = draw the scene on the device (default for more than 8M Gaussians)")
-    p.add_argument("--order", default="generated", choices=["generated", "morton"],
-                   help="row order of the scene: as generated (spatially random) or sorted by the Morton code "
-                        "of the position (visible rows then form contiguous runs)")
+    p.add_argument("--order", default="morton", choices=["generated", "morton"],
+                   help="row order of the scene: sorted by the Morton code of the position, as the scene is laid "
+                        "out at load (default; a camera's visible rows then form contiguous runs), or as generated "
+                        "(spatially random)")
     p.add_argument("--metrics-jsonl", default=None,
                    help="append one JSON record per timed step (HIP event times per call) to this file")
     p.add_argument("--no-cpu-baseline", action="store_true")
@@ -185,6 +186,20 @@ def measured_traffic(kernel, config_key):
     if not all(x in found for x in syms):
         return None
     return sum(found[x] for x in syms)
+
+
+def morton_sorted(geo, app, box, on_dev):
+    """The scene's rows sorted by the Morton code of their position (tensors
+    on the device, or numpy arrays for a host scene)."""
+    import torch
+    g_t = torch.as_tensor(geo)
+    perm = morton_order(g_t[:, :3], box)
+    g_s = g_t[perm].contiguous()
+    a_t = torch.as_tensor(app)
+    a_s = a_t[perm.to(a_t.device)].contiguous()
+    if not on_dev:
+        return g_s.numpy(), a_s.numpy()
+    return g_s, a_s
 
 
 def morton_order(pos, box):
@@ -640,13 +655,9 @@ def main():
     else:
         sc = gi.make_scene(w.n, seed=0, box=w.scene_box)
         geo0, app0 = sc.geo, sc.app
+    geo_gen, app_gen = geo0, app0
     if args.order == "morton":
-        g_t = torch.as_tensor(geo0)
-        perm = morton_order(g_t[:, :3], w.scene_box)
-        geo0 = g_t[perm].contiguous()
-        app0 = torch.as_tensor(app0)[perm.to(torch.as_tensor(app0).device)].contiguous()
-        if not on_dev:
-            geo0, app0 = geo0.numpy(), app0.numpy()
+        geo0, app0 = morton_sorted(geo0, app0, w.scene_box, on_dev)
     main_rec = run_single(args, w, geo0, app0, args.state, tilt, on_dev)
     second = None
     if args.compare_state and args.compare_state != args.state:
@@ -679,28 +690,29 @@ def main():
     out["stream_probe"] = {"what": "streaming read of the [n][10] geometry array", "bytes": flat.numel() * 4,
                            "gbs": probe_gbs, "frac_of_peak": probe_gbs / HBM_PEAK_GBS}
     del gflat, flat
-    if args.spatial_line and args.order == "generated":
-        # the same scene with its rows sorted by the Morton code of their
-        # position, the first state, chunk records on
-        sp = argparse.Namespace(**vars(args))
-        sp.order, sp.cull_chunks = "morton", 1
-        perm = morton_order(torch.as_tensor(geo0)[:, :3], w.scene_box)
-        g_s = torch.as_tensor(geo0)[perm.to(torch.as_tensor(geo0).device)].contiguous()
-        a_s = torch.as_tensor(app0)[perm.to(torch.as_tensor(app0).device)].contiguous()
-        del perm
-        rec = run_single(sp, w, g_s, a_s, args.state, tilt, on_dev)
-        del g_s, a_s
+    if args.other_order:
+        # the same scene and cameras, the first state, with the rows in the
+        # other order (chunk records with the Morton order only)
+        op = argparse.Namespace(**vars(args))
+        op.order = "generated" if args.order == "morton" else "morton"
+        op.cull_chunks = -1
+        if op.order == "morton":
+            g_o, a_o = morton_sorted(geo_gen, app_gen, w.scene_box, on_dev)
+        else:
+            g_o, a_o = geo_gen, app_gen
+        rec = run_single(op, w, g_o, a_o, args.state, tilt, on_dev)
+        del g_o, a_o
         keep = ("value", "ms_per_step", "step_ms", "value_p50", "kernels_ms", "kernels_gbs", "roofline",
                 "step_roofline")
-        out["spatial_order"] = {"what": "the same scene and cameras with the rows sorted by the Morton code of "
-                                        "their position (done before the timed steps) and chunk records on",
-                                **{k: rec[k] for k in keep},
-                                "config": {k: rec["config"][k] for k in ("row_order", "state", "cull_chunks",
-                                                                         "chunks_skipped", "visible_per_step",
-                                                                         "restored_per_step")}}
+        name = "spatial_order" if op.order == "morton" else "generation_order"
+        what = ("the rows sorted by the Morton code of their position, chunk records on" if op.order == "morton"
+                else "the rows in generation order (spatially random), no chunk records")
+        out[name] = {"what": "the same scene and cameras with " + what, **{k: rec[k] for k in keep},
+                     "config": {k: rec["config"][k] for k in ("row_order", "state", "cull_chunks", "chunks_skipped",
+                                                              "visible_per_step", "restored_per_step")}}
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, geo0, app0, args.cpu_sample, args.cpu_steps, *gi.lr_columns())
+        out["cpu_baseline"] = cpu_baseline(w, geo_gen, app_gen, args.cpu_sample, args.cpu_steps, *gi.lr_columns())
     print(json.dumps(out), flush=True)
 
 

@@ -1034,7 +1034,10 @@ __global__ __launch_bounds__(kCullBlock, 7) void k_cull(CullArgs a)
 // loads each one's geometry row, restores it when deferred and takes the
 // exact test.  Same outputs as k_cull, tile by tile.
 constexpr int kCullSumTiles = 2;      // tiles of a k_cull_sum block (of 1, 2, 4, 8 the fastest at 40M rows)
-static_assert(kCullSumTiles * kCullTile == kChunkRows, "a k_cull_sum block covers one chunk");
+// with chunk records (four tiles, two chunks, a block were slower: 21.2
+// against 19.4 us at 40M rows in Morton order)
+constexpr int kCullSumChunkTiles = 2;
+static_assert(kCullSumTiles * kCullTile == kChunkRows, "a chunk is the tiles of a k_cull_sum block");
 
 // True only when every row of a chunk is culled: classify_box returns 0 for
 // each row with the RowPre of its summary at any defer count.  The record's
@@ -1073,10 +1076,24 @@ __global__ __launch_bounds__(kCullBlock) void k_cull_sum(CullArgs a)
     static_assert(RPT <= 32, "row bits of a thread fit a word");
     __shared__ u32 sCntV[TPB][kCullIpt * 4], sCntS[TPB][kCullIpt * 4];
     __shared__ u32 sRestored[TPB];
-    // a chunk that k_chunk_scan skipped (it wrote the chunk's ballots and
-    // counts, and records a step error): nothing to do; tested first, so the
-    // rows' loads wait for one load only
-    if (a.chunk_flags && a.chunk_flags[blockIdx.x]) return;
+    // chunks that k_chunk_scan skipped (it wrote their ballots and counts,
+    // and records a step error) are neither loaded nor classified; a block
+    // whose chunks are all skipped has nothing to do.  Tested first, so the
+    // rows' loads wait for one load only.
+    constexpr int CT = kChunkRows / kCullTile;      // tiles of a chunk
+    static_assert(TPB % CT == 0, "a block covers whole chunks");
+    constexpr int CPB = TPB / CT;                   // chunks of a block
+    u32 live = (1u << CPB) - 1u;
+    if (a.chunk_flags) {
+        const int64_t nch = (a.tiles + CT - 1) / CT;
+        live = 0;
+#pragma unroll
+        for (int h = 0; h < CPB; ++h) {
+            const int64_t c = (int64_t)blockIdx.x * CPB + h;
+            if (c < nch && !a.chunk_flags[c]) live |= 1u << h;
+        }
+        if (!live) return;
+    }
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t tile0 = (int64_t)blockIdx.x * TPB;
     const float *Wrow;
@@ -1109,21 +1126,29 @@ __global__ __launch_bounds__(kCullBlock) void k_cull_sum(CullArgs a)
     const float4 *sb = a.sum + tile0 * kCullTile;
     const int32_t *lb = a.last + tile0 * kCullTile;
     if (full) {
-        valid = (RPT < 32 ? (1u << RPT) : 0u) - 1u;
 #pragma unroll
         for (int q = 0; q < RPT; ++q) {
             const int o = (q / kCullIpt) * kCullTile + (q % kCullIpt) * kCullBlock + tid;
-            if (!PACKED) lastv[q] = ld_sweep<NT>(lb + o);
-            sv[q] = ld_sweep<NT>(sb + o);
+            lastv[q] = 0;
+            sv[q] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            if ((live >> (q / kCullIpt / CT)) & 1u) {
+                valid |= 1u << q;
+                if (!PACKED) lastv[q] = ld_sweep<NT>(lb + o);
+                sv[q] = ld_sweep<NT>(sb + o);
+            }
         }
     } else {
 #pragma unroll
         for (int q = 0; q < RPT; ++q) {
             const int64_t row = row_of(q);
-            valid |= (u32)(row < a.n) << q;
-            const int64_t rc = row < a.n ? row : a.n - 1;
-            if (!PACKED) lastv[q] = ld_sweep<NT>(a.last + rc);
-            sv[q] = ld_sweep<NT>(a.sum + rc);
+            lastv[q] = 0;
+            sv[q] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            if ((live >> (q / kCullIpt / CT)) & 1u) {
+                valid |= (u32)(row < a.n) << q;
+                const int64_t rc = row < a.n ? row : a.n - 1;
+                if (!PACKED) lastv[q] = ld_sweep<NT>(a.last + rc);
+                sv[q] = ld_sweep<NT>(a.sum + rc);
+            }
         }
     }
     // A deferred row is classified with the tables' bound of every restore
@@ -1334,7 +1359,7 @@ template <bool CAMDEV>
 __global__ __launch_bounds__(256) void k_chunk_scan(CullArgs a)
 {
     const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int64_t chunks = (a.tiles + kCullSumTiles - 1) / kCullSumTiles;
+    const int64_t chunks = (a.n + kChunkRows - 1) / kChunkRows;
     const float *Wrow;
     int dmax, step_err;
     const int t = resolve_step(a.step, 0, &Wrow, &dmax, &step_err);
@@ -1362,8 +1387,8 @@ __global__ __launch_bounds__(256) void k_chunk_scan(CullArgs a)
     if (c == 0) step_flag(a.step, step_err);
     if (!skip) return;
 #pragma unroll
-    for (int j = 0; j < kCullSumTiles; ++j) {
-        const int64_t tile = c * kCullSumTiles + j;
+    for (int j = 0; j < kChunkRows / kCullTile; ++j) {
+        const int64_t tile = c * (kChunkRows / kCullTile) + j;
         if (tile < a.tiles) {
             ulonglong2 *kb = reinterpret_cast<ulonglong2 *>(a.keep_bits + tile * gsdp::kWordsPerTile);
 #pragma unroll
@@ -4212,19 +4237,28 @@ int gs_cull_summary_build(const gs_model *model, void *stream)
 
 namespace {
 
-template <bool NT, bool PACKED>
-void launch_cull_sum_c(bool camdev, unsigned blocks, hipStream_t st, const CullArgs &a)
+template <bool NT, bool PACKED, int TPB>
+void launch_cull_sum_c(bool camdev, hipStream_t st, const CullArgs &a)
 {
-    if (camdev) hipLaunchKernelGGL((k_cull_sum<NT, kCullSumTiles, PACKED, true>), dim3(blocks), dim3(kCullBlock), 0, st, a);
-    else hipLaunchKernelGGL((k_cull_sum<NT, kCullSumTiles, PACKED, false>), dim3(blocks), dim3(kCullBlock), 0, st, a);
+    const dim3 grid((unsigned)((a.tiles + TPB - 1) / TPB));
+    if (camdev) hipLaunchKernelGGL((k_cull_sum<NT, TPB, PACKED, true>), grid, dim3(kCullBlock), 0, st, a);
+    else hipLaunchKernelGGL((k_cull_sum<NT, TPB, PACKED, false>), grid, dim3(kCullBlock), 0, st, a);
 }
 
-void launch_cull_sum(bool nt, bool packed, bool camdev, unsigned blocks, hipStream_t st, const CullArgs &a)
+template <int TPB>
+void launch_cull_sum_t(bool nt, bool packed, bool camdev, hipStream_t st, const CullArgs &a)
 {
-    if (nt && packed) launch_cull_sum_c<true, true>(camdev, blocks, st, a);
-    else if (packed) launch_cull_sum_c<false, true>(camdev, blocks, st, a);
-    else if (nt) launch_cull_sum_c<true, false>(camdev, blocks, st, a);
-    else launch_cull_sum_c<false, false>(camdev, blocks, st, a);
+    if (nt && packed) launch_cull_sum_c<true, true, TPB>(camdev, st, a);
+    else if (packed) launch_cull_sum_c<false, true, TPB>(camdev, st, a);
+    else if (nt) launch_cull_sum_c<true, false, TPB>(camdev, st, a);
+    else launch_cull_sum_c<false, false, TPB>(camdev, st, a);
+}
+
+// the summary cull: two tiles a block, four with chunk decisions
+void launch_cull_sum(bool nt, bool packed, bool camdev, hipStream_t st, const CullArgs &a)
+{
+    if (a.chunk_flags) launch_cull_sum_t<kCullSumChunkTiles>(nt, packed, camdev, st, a);
+    else launch_cull_sum_t<kCullSumTiles>(nt, packed, camdev, st, a);
 }
 
 // The cull and ordered compaction of gs_cull on the workspace `wsb` (checked
@@ -4283,7 +4317,6 @@ int cull_launch(const gs_model *model, const gs_camera *cam, int64_t step, uint3
     if (a.tiles > 0) {
         if (a.mode == 1 && a.sum && !a.geo_dense) {
             // the summary (and the last step past 2^16 steps): 16 (20) bytes a row
-            const unsigned blocks = (unsigned)((a.tiles + kCullSumTiles - 1) / kCullSumTiles);
             const bool packed = model->lut_max_steps <= 65536;
             const bool nt = (int64_t)n * (packed ? 16 : 20) > kLastLevelCacheBytes;
             if (a.chunk) {
@@ -4296,7 +4329,7 @@ int cull_launch(const gs_model *model, const gs_camera *cam, int64_t step, uint3
                 if (a.cams) hipLaunchKernelGGL(k_chunk_scan<true>, dim3(cb), dim3(256), 0, st, a);
                 else hipLaunchKernelGGL(k_chunk_scan<false>, dim3(cb), dim3(256), 0, st, a);
             }
-            launch_cull_sum(nt, packed, a.cams != nullptr, blocks, st, a);
+            launch_cull_sum(nt, packed, a.cams != nullptr, st, a);
         } else if ((int64_t)n * 44 > kLastLevelCacheBytes) {
             // geometry and last step: 44 bytes a row
             hipLaunchKernelGGL(k_cull<true>, dim3((unsigned)a.tiles), dim3(kCullBlock), 0, st, a);
