@@ -150,9 +150,11 @@ def cpu_baseline(w, geo_all, app_all, sample, steps, lg, la):
 
 
 # the launches behind each timed call (the cull is three launches: tile cull,
-# group sums, prefixes + id scatter; the batched cull four)
+# group sums, prefixes + id scatter; with chunk records: chunk scan, tile
+# cull, prefixes + id scatter; the batched cull four)
 KERNEL_SYMBOLS = {"cull": ["k_cull", "k_tile_reduce", "k_tile_ids"],
-                  "cull_sum": ["k_cull_sum", "k_tile_reduce", "k_tile_ids"], "gather": ["k_rows_fz<0"],
+                  "cull_sum": ["k_cull_sum", "k_tile_reduce", "k_tile_ids"],
+                  "cull_chunks": ["k_chunk_scan", "k_cull_sum", "k_tile_ids"], "gather": ["k_rows_fz<0"],
                   "adam": ["k_rows_fz<1"], "cull_multi": ["k_cull_multi", "k_multi_reduce", "k_multi_gscan", "k_multi_offsets",
                                                       "k_multi_ids"],
                   "grad_sum": ["k_grad_sum"], "adam_bf16": ["k_rows_fz<1"]}
@@ -583,7 +585,8 @@ def run_single(args, w, geo0, app0, state, tilt, on_dev):
     by = step_bytes(n, M, R, geo_state, state, args.geo_mode, sum_bytes, chunk_skip)
     kernels = {k: (float(ms), by[k]) for k, ms in (("cull", cull_ms), ("gather", gather_ms), ("adam", adam_ms))}
     dom = max(kernels, key=lambda k: kernels[k][0])
-    sym = "cull_sum" if (dom == "cull" and summ) else dom   # the launches of the dominant call
+    # the launches of the dominant call
+    sym = dom if dom != "cull" or not summ else ("cull_chunks" if chunk_skip is not None else "cull_sum")
     dms, dbytes = kernels[dom]
     achieved = dbytes / (dms * 1e-3) / 1e9
     tot_bytes = sum(by.values())
