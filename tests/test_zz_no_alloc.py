@@ -1,6 +1,8 @@
 """gs_cull_noalloc (the cull whose workspace is the library's own per-GPU
 array) against gs_cull on the caller's workspace: ids and counts bit-exact on
-two calls in a row, the second on a smaller model (run with -m gpu)."""
+two calls in a row, the second on a smaller model; also with chunk records
+on rows in a spatial order, whose chunk scan writes into the array too (run
+with -m gpu)."""
 import sys
 
 import numpy as np
@@ -23,19 +25,25 @@ def g():
     return gsdp
 
 
-def _model(g, n, seed):
-    sc = gi.make_scene(n, seed=seed)
+def _model(g, n, seed, chunks):
     lg, la = gi.lr_columns()
+    if chunks:
+        from test_gpu_chunks import _scene
+        geo, app, _ = _scene(n, seed)
+        return g.Model(geo, app, lg, la, max_steps=8, cull_mode=1, cull_chunks=True)
+    sc = gi.make_scene(n, seed=seed)
     return g.Model(sc.geo, sc.app, lg, la, max_steps=8, cull_mode=1)
 
 
-@pytest.mark.parametrize("order", ["large_then_small", "small_again"])
+@pytest.mark.parametrize("order", ["large_then_small", "small_again", "chunks_large_then_small"])
 def test_cull_noalloc_matches_cull(g, order):
-    cams = gi.orbit_cameras(4, seed=3)
-    sizes = (300_007, 40_001) if order == "large_then_small" else (40_001, 12_345)
+    chunks = order.startswith("chunks")
+    cams = gi.aerial_cameras(4, 1000.0, 1000.0, seed=3) if chunks else gi.orbit_cameras(4, seed=3)
+    sizes = (300_007, 40_001) if order.endswith("large_then_small") else (40_001, 12_345)
     for call, n in enumerate(sizes):
         say(f"[noalloc] {order} call {call}: n={n}")
-        model = _model(g, n, seed=20 + call)
+        model = _model(g, n, 20 + call, chunks)
+        assert (model.cull_chunk is not None) == chunks
         # take one deferred step first so the cull restores rows (band classifier path)
         ids = torch.zeros(n, dtype=torch.int32, device="cuda")
         count = torch.zeros(1, dtype=torch.int32, device="cuda")
