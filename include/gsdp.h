@@ -259,11 +259,12 @@ int gs_cull_noalloc(const gs_model *model, const gs_camera *cam, int64_t step, u
  * step (with lut_max_steps > 65536 it also reads the last step), and loads
  * the row only where its conservative classification cannot decide; the
  * visible list is the same as without summaries.  cull_sum[i] = (x, y, z, w):
- * the centre of row i, and w whose high 16 bits are those of the FP32 value
- * s = (largest of the three log-scales) + 1e-6 (largest of their magnitudes)
- * rounded toward +infinity to 8 significand bits, or 0x7fc0 (a NaN) when a
- * geometric value is not finite, s >= 80, or the quaternion's squared norm is
- * below 1/4; the low 16 bits of w are last_step[i] modulo 2^16.
+ * the centre of row i, and w: bits 31..17 are those of the FP32 value s =
+ * (largest of the three log-scales) + 1e-6 (largest of their magnitudes)
+ * rounded toward +infinity to 7 significand bits, bit 16 is set when the
+ * quaternion's squared norm (evaluated in FP32) is at least 0.64, and the
+ * high 16 bits are 0x7fc0 (a NaN) instead when a geometric value is not
+ * finite or s >= 80; the low 16 bits of w are last_step[i] modulo 2^16.
  * Every call of this library that stores geometry or last steps
  * (gs_adam_step_deferred, gs_adam_flush, gs_densify_apply into dst) also
  * stores the summaries of the rows it writes; after geometry or last steps
@@ -277,8 +278,8 @@ int gs_cull_summary_build(const gs_model *model, void *stream);
  * paper).  Rows i with i / GS_CHUNK_ROWS = c form chunk c.  When
  * model->cull_chunk is also set, record c = cull_chunk[8c .. 8c+8) holds
  * (lo_x, lo_y, lo_z, s_c, hi_x, hi_y, hi_z, 0): every summary centre of the
- * chunk lies in the box [lo, hi], and every summary s of the chunk (the high
- * 16 bits of w as an FP32 value) is at most s_c; s_c is a NaN when some row's
+ * chunk lies in the box [lo, hi], and every summary s of the chunk (w &
+ * 0xfffe0000 as an FP32 value) is at most s_c; s_c is a NaN when some row's
  * summary is.  With max_defer = 0 the summary cull first tests a chunk's box,
  * widened by the largest drift and footprint any of its rows can have at
  * this step, against the camera, and skips the chunk's rows when the test

@@ -576,39 +576,53 @@ __device__ __forceinline__ int classify(const float *g, float wd, const CamK &c,
     return classify_cam(g, classify_pre(g, wd, b), c, b);
 }
 
+// The squared quaternion norm above which a row's summary allows a sure-in
+// decision.  A deferred row's quaternion may drift by up to 2 qd in norm (qd
+// = kq W, W up to the tables' bound of every restore coefficient, about 9 for
+// Adam), and the exact cull keeps a row only if its quaternion is not zero;
+// with |q|^2 >= 0.64 a sure-in decision holds while qd stays below about
+// 0.4 (rotation rates up to about 5.8e-3).
+constexpr float kSumQn2 = 0.64f;
+
 // Cull summary of one geometry row, 16 bytes: its centre (x, y, z) and one
-// word w.  The high 16 bits of w are those of s, the largest log-scale plus
-// the classifier's rounding slack, rounded up to 8 significand bits (so
-// s_up = w & 0xffff0000, read as a float, is >= s), or of a quiet NaN when
-// the band classifier must leave the row to the exact test: a non-finite
-// value, s of 80 or more, or a quaternion of squared norm below 1/4 (the
-// sure-in decision then needs the quaternion itself).  The low 16 bits hold
-// the row's last update step modulo 2^16, from which the cull recovers the
-// defer count while the steps fit 16 bits.  The band cull reads these 16
-// bytes instead of the 40-byte row and the last step; it loads the row only
-// for the rows the classifier leaves undecided.
+// word w.  Bits 31..17 of w are those of s, the largest log-scale plus the
+// classifier's rounding slack, rounded up to 7 significand bits (so s_up = w
+// & 0xfffe0000, read as a float, is >= s), or of a quiet NaN (0x7fc0 in the
+// high 16 bits) when the band classifier must leave the row to the exact
+// test: a non-finite value or s of 80 or more.  Bit 16 is set when the
+// quaternion's squared norm is at least kSumQn2: only then may the row be
+// classified as surely kept (a sure-out decision needs no quaternion).  The
+// low 16 bits hold the row's last update step modulo 2^16, from which the
+// cull recovers the defer count while the steps fit 16 bits.  The band cull
+// reads these 16 bytes instead of the 40-byte row and the last step; it
+// loads the row only for the rows the classifier leaves undecided.
+// (Rows whose quaternion is small are not sent to the exact test outright:
+// after long deferrals the catch-up of Adam's momentum moves quaternion
+// components by a tenth or more, and such rows would keep whole chunks from
+// being skipped.)
 __device__ __forceinline__ float4 cull_summary(const float *g, int last)
 {
     const float fsum = (((fabsf(g[0]) + fabsf(g[1])) + (fabsf(g[2]) + fabsf(g[3]))) +
                         ((fabsf(g[4]) + fabsf(g[5])) + (fabsf(g[6]) + fabsf(g[7])))) + (fabsf(g[8]) + fabsf(g[9]));
     const float sm = fmaxf(fmaxf(g[3], g[4]), g[5]) + 1e-6f * fmaxf(fmaxf(fabsf(g[3]), fabsf(g[4])), fabsf(g[5]));
     const float qn2 = fmaf(g[9], g[9], fmaf(g[8], g[8], fmaf(g[7], g[7], g[6] * g[6])));
-    const bool ok = __builtin_isfinite(fsum) && sm < 80.0f && qn2 >= 0.25f;
+    const bool ok = __builtin_isfinite(fsum) && sm < 80.0f;
     // round toward +infinity: a positive value's magnitude up, a negative one's down
     u32 b = __float_as_uint(sm);
-    if (b >> 31) b &= 0xffff0000u;
-    else if (b & 0xffffu) b = (b & 0xffff0000u) + 0x10000u;
-    const u32 hi = ok ? (b & 0xffff0000u) : 0x7fc00000u;
+    if (b >> 31) b &= 0xfffe0000u;
+    else if (b & 0x1ffffu) b = (b & 0xfffe0000u) + 0x20000u;
+    const u32 hi = ok ? ((b & 0xfffe0000u) | ((u32)(qn2 >= kSumQn2) << 16)) : 0x7fc00000u;
     return make_float4(g[0], g[1], g[2], __uint_as_float(hi | ((u32)last & 0xffffu)));
 }
 
 // classify_pre from a summary.  The bounds are those of classify_pre: the
 // centre is the row's, s already holds the slack that classify_pre adds after
 // the drift (the sum differs by at most an ulp, far inside the 0.1% margin
-// on sigma), a NaN s makes the row undecidable, and since the quaternion's
-// squared norm is at least 1/4 the sure-in condition on it holds whenever
-// 1.001 qmin^2 < 1/4.
-__device__ __forceinline__ RowPre classify_pre_sum(const float4 &v, float wd, const BandK &b)
+// on sigma), a NaN s makes the row undecidable, and with the summary's
+// quaternion bit (qok: squared norm at least kSumQn2) the sure-in condition
+// on the quaternion holds whenever 1.001 qmin^2 < kSumQn2; without it the row
+// can be decided out but not in.  v.w: s_up.
+__device__ __forceinline__ RowPre classify_pre_sum(const float4 &v, float wd, const BandK &b, u32 qok)
 {
     RowPre p;
     const float dpos = b.kpos * wd, dscl = b.kscl * wd, dq = b.kq * wd;
@@ -620,7 +634,7 @@ __device__ __forceinline__ RowPre classify_pre_sum(const float4 &v, float wd, co
     p.sig = sig;
     p.sig2 = sig * sig;
     const float qmin = 2.002f * dq + 1e-6f;
-    p.ok = smax < 80.0f ? (1.001f * (qmin * qmin) < 0.25f ? 3 : 1) : 0;
+    p.ok = smax < 80.0f ? ((qok != 0u && 1.001f * (qmin * qmin) < kSumQn2) ? 3 : 1) : 0;
     return p;
 }
 
@@ -673,7 +687,7 @@ __device__ __forceinline__ float chunk_rec_lane(const float *chunk, u32 row)
 __device__ __forceinline__ void chunk_widen(float *chunk, u32 row, const float4 &v, float rec)
 {
     const u32 lane = threadIdx.x & 63u;
-    const float sv = __uint_as_float(__float_as_uint(v.w) & 0xffff0000u);
+    const float sv = __uint_as_float(__float_as_uint(v.w) & 0xfffe0000u);
     const u32 e = lane < 3u ? lane : (lane < 4u ? 3u : lane - 4u);
     const float x = lane == 3u ? sv : (e == 0u ? v.x : (e == 1u ? v.y : v.z));
     const bool low = lane < 3u;
@@ -1157,6 +1171,7 @@ __global__ __launch_bounds__(kCullBlock) void k_cull_sum(CullArgs a)
     const float wbound = a.step.hdr->wbound;
     int dv[RPT];
     float wdv[RPT];
+    u32 qok = 0;                                          // the summaries' quaternion bits
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
         const u32 wb = __float_as_uint(sv[q].w);
@@ -1165,7 +1180,8 @@ __global__ __launch_bounds__(kCullBlock) void k_cull_sum(CullArgs a)
         d = d < 0 ? 0 : (d > dmax ? dmax : d);
         dv[q] = d;
         wdv[q] = d > 0 ? wbound : 0.0f;
-        sv[q].w = __uint_as_float(wb & 0xffff0000u);      // s rounded up (or NaN)
+        qok |= ((wb >> 16) & 1u) << q;
+        sv[q].w = __uint_as_float(wb & 0xfffe0000u);      // s rounded up (or NaN)
     }
     // classification: keep bits and undecided bits of this thread's rows.
     // side_out settles most rows; the full classification runs for a slot
@@ -1173,7 +1189,7 @@ __global__ __launch_bounds__(kCullBlock) void k_cull_sum(CullArgs a)
     u32 keepm = 0, und = 0;
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
-        const RowPre pre = classify_pre_sum(sv[q], wdv[q], band);
+        const RowPre pre = classify_pre_sum(sv[q], wdv[q], band, (qok >> q) & 1u);
         const bool left = !(pre.ok != 0 && side_out(sv[q], pre, cam, band, side)) && ((valid >> q) & 1u);
         if (__ballot(left) != 0ull) {
             const float c3[3] = {sv[q].x, sv[q].y, sv[q].z};
@@ -1309,7 +1325,7 @@ __global__ __launch_bounds__(256) void k_cull_chunk_build(const float4 *sum, int
         const int64_t r = r0 + k * 256 + tid;
         if (r < n) {
             const float4 v = sum[r];
-            const float sv = __uint_as_float(__float_as_uint(v.w) & 0xffff0000u);
+            const float sv = __uint_as_float(__float_as_uint(v.w) & 0xfffe0000u);
             if (sv == sv) {
                 lo[0] = fminf(lo[0], v.x);
                 lo[1] = fminf(lo[1], v.y);

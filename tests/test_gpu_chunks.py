@@ -40,7 +40,7 @@ def g():
 def _split(sumw):
     w = np.ascontiguousarray(sumw, np.float32).view(np.uint32).reshape(-1, 4)
     cen = w[:, :3].copy().view(np.float32)
-    s = (w[:, 3] & np.uint32(0xFFFF0000)).view(np.float32)
+    s = (w[:, 3] & np.uint32(0xFFFE0000)).view(np.float32)
     return cen, s
 
 
