@@ -9,6 +9,9 @@
   of the current geometry keeps; the summary cull with records lists exactly
   what the cull without them lists and what the oracle lists (also with the
   camera read from a device table); and the states stay bit-identical.
+- At 18M rows (the compaction's group sums filled by the summary cull), around
+  the 2^16-step boundary, and for empty, single-row and ragged models, the
+  cull with records lists what the oracle, or the cull without records, lists.
 """
 import sys
 
@@ -225,3 +228,142 @@ def test_chunk_records_after_densify(g):
     assert new.cull_chunk.shape[0] == (new.n + CH - 1) // CH
     assert same_records(new.cull_chunk.cpu().numpy(), host_chunks(new.cull_sum[:new.n].cpu().numpy()))
     check_contained(new, "after densify")
+
+
+def test_chunk_cull_grouped_aerial18m(g):
+    """18M Gaussians (more than 16384 tiles: the compaction takes the group
+    sums, which the chunk scan clears and the summary cull adds to, with no
+    separate reduction), rows in Morton order.  Step 1 bit-exact against the
+    oracle's cull; then, over updates that move positions 2 m a step, the cull
+    with chunk records equals the cull without them and the cull from a device
+    camera table, and no skipped chunk holds a kept row."""
+    w = gi.workload("aerial18m")
+    sc = gi.make_scene(w.n, seed=1, box=w.scene_box)
+    del sc.app
+    perm = _morton(sc.geo[:, :3].astype(np.float64))
+    geo = np.ascontiguousarray(sc.geo[perm])
+    del sc, perm
+    n, steps = w.n, 3
+    say(f"[chunks grouped] n={n}")
+    lg, la = gi.lr_columns()
+    lg = lg.copy()
+    lg[0:3] = 2.0
+    app = np.zeros((n, 1), np.float32)
+    kw = dict(max_steps=steps + 2, cull_mode=1, app_layout="fused")
+    a = g.Model(geo, app, lg, la, cull_chunks=True, **kw)
+    b = g.Model(geo, app, lg, la, **kw)
+    cams = [w.camera_for_step(t) for t in range(1, steps + 1)]
+    table = g.camera_table(a, cams)
+    ids = [torch.zeros(n, dtype=torch.int32, device="cuda") for _ in range(3)]
+    cnt = [torch.zeros(1, dtype=torch.int32, device="cuda") for _ in range(3)]
+    flags = torch.zeros(a.cull_chunk.shape[0], dtype=torch.uint8, device="cuda")
+    gg = torch.empty((n, 10), dtype=torch.float32, device="cuda")
+    ga = torch.empty((n, 1), dtype=torch.float32, device="cuda")
+    for t in range(1, steps + 1):
+        g.gs_cull(a, cams[t - 1], t, ids[0], cnt[0])
+        g.gs_cull(b, cams[t - 1], t, ids[1], cnt[1])
+        g.gs_cull_table(a, table, t, ids[2], cnt[2])
+        g.gs_cull_chunk_flags(a, cams[t - 1], t, flags)
+        torch.cuda.synchronize()
+        m = int(cnt[0].item())
+        for k in (1, 2):
+            assert int(cnt[k].item()) == m and torch.equal(ids[k][:m], ids[0][:m]), f"step {t}: path {k}"
+        kept = ids[0][:m].cpu().numpy().view(np.uint32)
+        f = flags.cpu().numpy().astype(bool)
+        assert not f[kept // CH].any(), f"step {t}: a skipped chunk holds a kept row"
+        if t == 1:
+            ref = orc.compact(orc.cull(geo, cams[0]))
+            assert m == ref.shape[0] and np.array_equal(kept, ref), "step 1: ids differ from the oracle's"
+        say(f"[chunks grouped] step {t}: M={m}, {f.mean():.3f} of the chunks skipped")
+        assert f.mean() > 0.5
+        g.gs_synth_grad(6, t, ids[0], cnt[0], gg, 0)
+        g.gs_synth_grad(6, t, ids[0], cnt[0], ga, 10)
+        for model in (a, b):
+            g.gs_adam_step_deferred(model, t, ids[0], cnt[0], gg, ga)
+    assert a.ws_header()["error"] == 0 and b.ws_header()["error"] == 0
+    check_contained(a, "after the updates")
+
+
+@pytest.mark.parametrize("T,t0", [(70_000, 65_530), (65_536, 65_524)])
+def test_chunk_cull_across_the_16_bit_step_boundary(g, T, t0):
+    """Past 2^16 steps the summary cull also reads the last-step array, with
+    chunk records too; around the boundary the cull with records lists what
+    the cull from the geometry rows lists, and the states stay equal."""
+    n = 60_000
+    geo, app, half = _scene(n, seed=31, half=300.0)
+    lg, la = gi.lr_columns()
+    lg = lg.copy()
+    lg[0:3] = 0.5
+    cams = gi.aerial_cameras(16, half, half, seed=31)
+    kw = dict(max_steps=T, cull_mode=1, app_layout="fused", sr_seed=2)
+    a = g.Model(geo, app, lg, la, cull_chunks=True, **kw)
+    b = g.Model(geo, app, lg, la, cull_summary=False, **kw)
+    for m in (a, b):
+        m.lut_seek(t0)
+    ids = [torch.zeros(n, dtype=torch.int32, device="cuda") for _ in range(2)]
+    cnt = [torch.zeros(1, dtype=torch.int32, device="cuda") for _ in range(2)]
+    flags = torch.zeros(a.cull_chunk.shape[0], dtype=torch.uint8, device="cuda")
+    gg = torch.empty((n, 10), dtype=torch.float32, device="cuda")
+    ga = torch.empty((n, 49), dtype=torch.float32, device="cuda")
+    skipped = 0.0
+    for t in range(t0, min(T, t0 + 12) + 1):
+        cam = cams[t % 16]
+        for k, m in enumerate((a, b)):
+            g.gs_cull(m, cam, t, ids[k], cnt[k])
+        g.gs_cull_chunk_flags(a, cam, t, flags)
+        torch.cuda.synchronize()
+        mm = int(cnt[0].item())
+        assert mm == int(cnt[1].item()) and torch.equal(ids[0][:mm], ids[1][:mm]), t
+        f = flags.cpu().numpy().astype(bool)
+        assert not f[ids[0][:mm].cpu().numpy() // CH].any(), t
+        skipped = max(skipped, f.mean())
+        g.gs_synth_grad(4, t, ids[0], cnt[0], gg, 0)
+        g.gs_synth_grad(4, t, ids[0], cnt[0], ga, 10)
+        for m in (a, b):
+            g.gs_adam_step_deferred(m, t, ids[0], cnt[0], gg, ga)
+    assert skipped > 0.3
+    check_contained(a, "after the updates")
+    sa, sb = a.state(), b.state()
+    for key in sa:
+        assert sa[key].tobytes() == sb[key].tobytes(), key
+    assert a.ws_header()["error"] == 0 and b.ws_header()["error"] == 0
+    say(f"[chunks 16-bit boundary] T={T}: steps {t0}..{min(T, t0 + 12)} equal, up to {skipped:.2f} skipped")
+
+
+@pytest.mark.parametrize("n", [0, 1, 5, 1023, 1024, 1025, 3007])
+def test_chunk_cull_small_and_ragged(g, n):
+    """Empty, single-row and ragged models (a last chunk of 1..1023 rows): the
+    cull with chunk records lists what the oracle's cull of the current
+    geometry lists, over updates that move positions 2 m a step."""
+    say(f"[chunks small] n={n}")
+    geo, app, half = _scene(max(n, 1), seed=40 + n, half=100.0)
+    geo, app = geo[:n], app[:n]
+    lg, la = gi.lr_columns()
+    lg = lg.copy()
+    lg[0:3] = 2.0
+    kw = dict(max_steps=6, cull_mode=1, app_layout="fused", sr_seed=3)
+    a = g.Model(geo, app, lg, la, cull_chunks=True, **kw)
+    # (an empty model keeps one unused record: the binding allocates nothing empty)
+    assert a.cull_chunk is not None and a.cull_chunk.shape[0] == max((n + CH - 1) // CH, 1)
+    o = orc.DeferredF32(geo, app, lg, la, sr_seed=3)
+    # two cameras over the middle (every tiny model has visible rows), two anywhere
+    near, far = gi.aerial_cameras(2, 5.0, 5.0, seed=n), gi.aerial_cameras(2, half, half, seed=n)
+    cams = [near[0], far[0], near[1], far[1]]
+    ids = torch.full((max(n, 1),), -1, dtype=torch.int32, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int32, device="cuda")
+    for t in range(1, 5):
+        g.gs_cull(a, cams[t - 1], t, ids, cnt)
+        torch.cuda.synchronize()
+        m = int(cnt.item())
+        valid = o.cull_current(t, cams[t - 1])
+        assert m == valid.shape[0] and np.array_equal(ids[:m].cpu().numpy().view(np.uint32), valid), t
+        gg, ga = gi.step_grads(0, t, valid)
+        # compact gradients of at least one row (an empty tensor has no address)
+        dg = torch.zeros((max(m, 1), 10), dtype=torch.float32, device="cuda")
+        da = torch.zeros((max(m, 1), 49), dtype=torch.float32, device="cuda")
+        dg[:m], da[:m] = torch.from_numpy(gg), torch.from_numpy(ga)
+        g.gs_adam_step_deferred(a, t, ids, cnt, dg, da, capacity=dg.shape[0])
+        o.step(t, valid, gg, ga)
+        if n:
+            check_contained(a, f"after update {t}")
+    assert a.ws_header()["error"] == 0
