@@ -73,7 +73,8 @@ def _rows(rng, n):
     geo[pick(), rng.integers(0, 10)] = np.nan
     geo[pick(), rng.integers(0, 10)] = np.inf
     geo[pick(), 3:6] = rng.choice([79.9999, 80.0, 85.0, 200.0, -200.0, 0.0, -0.0], (k, 3))
-    geo[pick(), 6:10] *= rng.choice([0.0, 0.3, 0.5, 0.7999, 0.8, 0.8001, 2.0], k)[:, None]
+    with np.errstate(invalid="ignore"):        # inf * 0 on rows that already hold an inf
+        geo[pick(), 6:10] *= rng.choice([0.0, 0.3, 0.5, 0.7999, 0.8, 0.8001, 2.0], k)[:, None]
     geo[pick(), :3] = rng.choice([3e38, -3e38, 1e30], (k, 3))
     return geo
 
