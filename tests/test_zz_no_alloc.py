@@ -1,7 +1,8 @@
 """gs_cull_noalloc (the cull whose workspace is the library's own per-GPU
 array) against gs_cull on the caller's workspace: ids and counts bit-exact on
 two calls in a row, the second on a smaller model; also with chunk records
-on rows in a spatial order, whose chunk scan writes into the array too (run
+on rows in a spatial order, whose chunk scan writes into the array too, at
+a size whose compaction reads group sums and then at one that does not (run
 with -m gpu)."""
 import sys
 
@@ -35,11 +36,16 @@ def _model(g, n, seed, chunks):
     return g.Model(sc.geo, sc.app, lg, la, max_steps=8, cull_mode=1)
 
 
-@pytest.mark.parametrize("order", ["large_then_small", "small_again", "chunks_large_then_small"])
+@pytest.mark.parametrize("order", ["large_then_small", "small_again", "chunks_large_then_small",
+                                   "chunks_grouped_then_small"])
 def test_cull_noalloc_matches_cull(g, order):
     chunks = order.startswith("chunks")
     cams = gi.aerial_cameras(4, 1000.0, 1000.0, seed=3) if chunks else gi.orbit_cameras(4, seed=3)
     sizes = (300_007, 40_001) if order.endswith("large_then_small") else (40_001, 12_345)
+    if order == "chunks_grouped_then_small":
+        # more than 16384 tiles: the group sums the summary cull adds to sit in
+        # the array too; then a model small enough to sum its tiles directly
+        sizes = (9_000_000, 300_007)
     for call, n in enumerate(sizes):
         say(f"[noalloc] {order} call {call}: n={n}")
         model = _model(g, n, 20 + call, chunks)
