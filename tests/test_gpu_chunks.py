@@ -8,7 +8,8 @@
   the flush; no chunk the summary cull skips holds a row the oracle's cull
   of the current geometry keeps; the summary cull with records lists exactly
   what the cull without them lists and what the oracle lists (also with the
-  camera read from a device table); and the states stay bit-identical.
+  camera read from a device table); and the states stay bit-identical (FP32,
+  BF16 and FP8 moments, whose two-pass update widens the records too).
 - At 18M rows (the compaction's group sums filled by the summary cull), around
   the 2^16-step boundary, and for empty, single-row and ragged models, the
   cull with records lists what the oracle, or the cull without records, lists.
@@ -21,6 +22,7 @@ import torch
 
 import gs_inputs as gi
 from oracle import oracle as orc
+from test_gpu_parity import _compare_state
 from test_gpu_summary import _rows
 
 pytestmark = pytest.mark.gpu
@@ -130,7 +132,7 @@ def test_chunk_records_need_summaries(g):
         g.gs_cull_chunk_flags(c, gi.orbit_cameras(1, seed=1)[0], 1, flags)
 
 
-@pytest.mark.parametrize("state,pos_lr", [("f32", 1.6e-4), ("f32", 2.0), ("bf16", 2.0)])
+@pytest.mark.parametrize("state,pos_lr", [("f32", 1.6e-4), ("f32", 2.0), ("bf16", 2.0), ("fp8", 2.0)])
 def test_chunk_cull_lockstep_vs_oracle(g, state, pos_lr):
     n, steps = 400_000, 12
     geo, app, half = _scene(n, seed=21)
@@ -185,10 +187,7 @@ def test_chunk_cull_lockstep_vs_oracle(g, state, pos_lr):
     sa, sb = a.state(), b.state()
     for k in sa:
         assert np.array_equal(np.asarray(sa[k]).view(np.uint8), np.asarray(sb[k]).view(np.uint8)), k
-    for k, name in ((0, "geo"), (1, "app")):
-        for part, ref in (("w", o.w[k]), ("m", o.m[k]), ("v", o.v[k])):
-            got = np.asarray(sa[f"{name}_{part}"])
-            assert np.array_equal(got.view(np.uint8), np.asarray(ref).view(np.uint8)), f"{name}_{part}"
+    _compare_state(a, o, "after the flush")
     # a rebuild gives tight records again, which hold every summary
     widened = a.cull_chunk.clone()
     a.cull_summary_build()
